@@ -1,0 +1,197 @@
+/*
+ * kmp.h -- C ABI of libkmp, a gfx950 (MI355X) implementation of the data-
+ * parallel hot path of deep multilevel graph partitioning (Gottesbueren,
+ * Heuer, Sanders, Schulz, Seemaier, "Deep Multilevel Graph Partitioning").
+ *
+ * Problem (paper Sec. 2, "Notation and Definitions"): given an undirected
+ * graph G = (V, E, c, w) with positive integer node weights c and edge
+ * weights w, split V into k blocks of weight at most
+ * L_k = (1 + eps) * ceil(c(V) / k) (the bound the paper's experiments check,
+ * Sec. 2 footnote and Sec. 6) while minimising the weight of cut edges.
+ *
+ * Method (paper Alg. 1 / Alg. 2, Sec. 4-5): coarsen by size-constrained label
+ * propagation (LP) and contraction until about 2C nodes remain (C = 160);
+ * bipartition the coarsest graph; while projecting back, bipartition blocks
+ * until level l has min(k, ceil2(n_l / C)) blocks; balance; refine with k-way
+ * LP.  The LP here is a deterministic "sub-round" reading of the paper's
+ * asynchronous LP, so results depend only on (graph, k, eps, seed).
+ *
+ * Conventions for every entry point:
+ *   - All array arguments are DEVICE (HBM) pointers on the current HIP device,
+ *     owned by the caller.  Inputs are read only; outputs are written fully.
+ *   - Graphs are symmetric CSR: xadj[n+1] row offsets (int32, xadj[0] = 0),
+ *     adjncy[m] neighbour ids (int32), m = xadj[n] = number of DIRECTED
+ *     entries (twice the number of edges).  vwgt[n] node weights and
+ *     adjwgt[m] edge weights may be NULL (all ones).  Neighbour order within a
+ *     row is free; self-loops and duplicates are not allowed.
+ *   - Sum of node weights and half the sum of edge weights must fit in int32.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     The library enqueues all work on it and synchronises it before return
+ *     (the scheduler reads per-level scalars).  Workspace comes from the
+ *     stream-ordered pool of the current device and is released before return.
+ *   - Calls on different streams may run concurrently from different threads.
+ *   - Return value: 0 = OK; 1 = KMP_IMBALANCED (output written, but some block
+ *     exceeds L_k; possible only with non-unit node weights); negative codes
+ *     below are errors and leave the output undefined.
+ */
+#ifndef KMP_H
+#define KMP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KMP_OK 0
+#define KMP_IMBALANCED 1
+#define KMP_EINVAL (-1)    /* n < 0, k < 1, eps < 0, eps > 1000 or NaN, NULL required pointer, m != xadj[n] */
+#define KMP_EGRAPH (-2)    /* invalid CSR (checked only when validation is requested) */
+#define KMP_EOVERFLOW (-3) /* sum(vwgt) or sum(adjwgt)/2 exceeds INT32_MAX */
+#define KMP_ENOMEM (-4)    /* device workspace allocation failed */
+#define KMP_EHIP (-5)      /* a HIP runtime call failed */
+
+#define KMP_MAX_LEVELS 64
+
+/* Options for kmp_partition_ex (all fields zero = defaults). */
+typedef struct kmp_options {
+    int32_t validate;       /* 1: check the CSR on the device first (KMP_EGRAPH on failure) */
+    int32_t reserved[7];
+} kmp_options;
+
+/* Statistics filled by kmp_partition_ex (host memory, may be NULL). */
+typedef struct kmp_stats {
+    int64_t cut;                            /* final edge cut (paper Sec. 2)            */
+    int64_t lk;                             /* L_k = floor(ceil(c(V)/k) (10^6 + e) / 10^6) */
+    int64_t max_block_weight;
+    int32_t levels;                         /* number of contractions L                  */
+    int32_t bipartitions;                   /* number of bipartitioned blocks (GGG calls) */
+    int32_t balance_rounds;
+    int32_t reserved0;
+    int32_t level_n[KMP_MAX_LEVELS + 1];    /* nodes per level                           */
+    int64_t level_m[KMP_MAX_LEVELS + 1];    /* directed entries per level                */
+    int64_t lp_cluster_moves;
+    int64_t lp_refine_moves;
+    int64_t lp_rated_edges;                 /* directed entries read by LP rating kernels */
+    int64_t contracted_edges;               /* sum of m_l over contracted levels          */
+    double ms_total;                        /* wall time of the call                      */
+    double ms_coarsen_lp;                   /* host-timed phases (stream synchronised)    */
+    double ms_contract;
+    double ms_initial;                      /* bipartitioning (extraction + GGG)          */
+    double ms_refine;                       /* balance + refinement + projection          */
+} kmp_stats;
+
+/*
+ * kmp_partition: partition (xadj, adjncy, vwgt, adjwgt) into k blocks with
+ * imbalance eps and tie-break seed `seed`; writes out_part[v] in [0, k).
+ * Paper: Alg. 1 (deep MGP driver), Alg. 2 (bipartitionBlocks), Sec. 5.
+ * Special cases: n = 0 -> OK, nothing written; k = 1 -> all zeros; k > n is
+ * allowed (some blocks stay empty).
+ */
+int kmp_partition(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                  int32_t n, int64_t m, int32_t k, double epsilon, uint64_t seed, int32_t* out_part,
+                  void* stream);
+
+/* As kmp_partition, with options (may be NULL) and statistics (may be NULL). */
+int kmp_partition_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                     int32_t n, int64_t m, int32_t k, double epsilon, uint64_t seed, int32_t* out_part,
+                     void* stream, const kmp_options* opt, kmp_stats* stats);
+
+/* Human-readable text for a status code (static storage). */
+const char* kmp_strerror(int code);
+
+/* Library version, "major.minor.patch" (static storage). */
+const char* kmp_version(void);
+
+/* ------------------------------------------------------------------------
+ * Step entry points.  Each runs one step of the pipeline on the device with
+ * the same semantics as inside kmp_partition, so a caller (or a test) can
+ * drive and check the steps one at a time.  Same conventions as above; all
+ * arrays are device pointers; every call synchronises `stream`.
+ * ------------------------------------------------------------------------ */
+
+/*
+ * kmp_lp_cluster: size-constrained LP clustering of one coarsening level
+ * (paper Sec. 2 "Size-Constrained Label Propagation", Sec. 5.1): start from
+ * singletons, at most 5 rounds of 4 hash-assigned sub-rounds, cluster weight
+ * bound U, tie-break hashes keyed by (seed, level).  Outputs label[n]
+ * (cluster ids in [0,n)), cw[n] cluster weights (int64, indexed by label),
+ * fav[n] favoured cluster (0xFFFFFFFF = none).  moves[5] (host pointer, may be
+ * NULL) receives moves per round.  Returns rounds run (>= 0) or an error.
+ */
+int kmp_lp_cluster(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                   int32_t n, int32_t level, int64_t U, uint64_t seed, int32_t* label, int64_t* cw,
+                   uint32_t* fav, int64_t* moves, void* stream);
+
+/*
+ * kmp_two_hop: two-hop merging of singleton clusters with the same favoured
+ * cluster (paper Sec. 5.1 "Two-hop Clustering") when fewer than half of the
+ * nodes were merged.  Updates label[n] and cw[n] in place.  Returns the number
+ * of merges (>= 0) or an error.
+ */
+int64_t kmp_two_hop(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                    int32_t n, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav, void* stream);
+
+/*
+ * kmp_contract: contract the clustering label[n] (paper Sec. 2 "Multilevel
+ * Graph Partitioning"): coarse id = rank of the label among non-empty labels,
+ * coarse node weight = member sum, parallel edges summed, intra-cluster edges
+ * dropped, coarse neighbours ascending.  Writes map[n]; *cn and *cm (host
+ * pointers) receive the coarse sizes.  The coarse arrays cxadj[n+1],
+ * cadjncy[m], cvwgt[n], cadjwgt[m] are caller buffers sized for the fine
+ * graph (upper bounds).
+ */
+int kmp_contract(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                 int32_t n, const int32_t* label, int32_t* map, int32_t* cn, int64_t* cm, int32_t* cxadj,
+                 int32_t* cadjncy, int32_t* cvwgt, int32_t* cadjwgt, void* stream);
+
+/*
+ * kmp_bipartition_round: one call of bipartitionBlocks (paper Alg. 2): every
+ * block b with final count fcount[b] >= 2 is split by multi-seed greedy graph
+ * growing into (first[b], floor(f/2)) and (first[b] + floor(f/2), ceil(f/2)),
+ * caps f0 * lk and f1 * lk; blocks are renumbered in ascending `first`.
+ * part[n] (device) is updated in place.  first/fcount are HOST arrays of
+ * capacity 2 * (*nblocks) updated in place; *nblocks (host) is updated.
+ */
+int kmp_bipartition_round(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
+                          const int32_t* adjwgt, int32_t n, int32_t level, int32_t* part, int32_t* nblocks,
+                          int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed, void* stream);
+
+/*
+ * kmp_balance: k-way balancing by relative gain (paper Sec. 5.3
+ * "Balancing") of part[n] over nb blocks with block weights wt[nb] (int64,
+ * updated) and caps cap[nb] (int64).  Returns the number of rounds run.
+ */
+int kmp_balance(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                int32_t n, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,
+                const int64_t* cap, void* stream);
+
+/*
+ * kmp_lp_refine: k-way LP refinement (paper Sec. 5.3 "Local Improvement")
+ * of part[n] over nb blocks, block weights wt[nb] (int64, updated), strict
+ * caps cap[nb] (int64).  moves[5] (host, may be NULL).  Returns rounds run.
+ */
+int kmp_lp_refine(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                  int32_t n, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,
+                  const int64_t* cap, int64_t* moves, void* stream);
+
+/*
+ * kmp_lp_subround: one sub-round (rate, admit, apply) of LP from an arbitrary
+ * state: nodes of sub-round class s that are active (active[n] bytes, NULL =
+ * all) are rated against the current labels; `tag` selects the tie-break
+ * family (2 = clustering, 3 = refinement); cap is cap_vec[nlab] if non-NULL
+ * else cap_scalar.  label[n], wt[nlab] (int64) updated; fav[n] (may be NULL)
+ * written for rated nodes; moved[n] bytes set for moved nodes.
+ * Returns the number of moves or an error.
+ */
+int64_t kmp_lp_subround(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
+                        const int32_t* adjwgt, int32_t n, int32_t level, int32_t round, int32_t s, uint32_t tag,
+                        uint64_t seed, int32_t* label, int64_t* wt, int32_t nlab, const int64_t* cap_vec,
+                        int64_t cap_scalar, const uint8_t* active, uint32_t* fav, uint8_t* moved,
+                        void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KMP_H */

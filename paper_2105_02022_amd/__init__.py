@@ -1,0 +1,248 @@
+"""Python binding of libkmp (gfx950 deep multilevel graph partitioning).
+
+Thin ctypes marshalling over the C ABI declared in ``include/kmp.h``: every
+function here has the name of the C entry point it calls and only converts
+arguments (torch device tensors -> device pointers, the current torch stream
+-> hipStream_t).  All computation runs in the HIP kernels of ``libkmp.so``;
+there is no fallback: if the library is missing, importing a function raises.
+
+Build the library with ``python -m paper_2105_02022_amd.build`` (or
+``__graft_entry__.build()``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, Optional, Sequence, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkmp.so")
+
+KMP_OK, KMP_IMBALANCED, KMP_EINVAL, KMP_EGRAPH, KMP_EOVERFLOW, KMP_ENOMEM, KMP_EHIP = 0, 1, -1, -2, -3, -4, -5
+MAX_LEVELS = 64
+
+
+class KmpOptions(ctypes.Structure):
+    _fields_ = [("validate", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
+class KmpStats(ctypes.Structure):
+    _fields_ = [("cut", ctypes.c_int64), ("lk", ctypes.c_int64), ("max_block_weight", ctypes.c_int64),
+                ("levels", ctypes.c_int32), ("bipartitions", ctypes.c_int32), ("balance_rounds", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("level_n", ctypes.c_int32 * (MAX_LEVELS + 1)),
+                ("level_m", ctypes.c_int64 * (MAX_LEVELS + 1)), ("lp_cluster_moves", ctypes.c_int64),
+                ("lp_refine_moves", ctypes.c_int64), ("lp_rated_edges", ctypes.c_int64),
+                ("contracted_edges", ctypes.c_int64), ("ms_total", ctypes.c_double),
+                ("ms_coarsen_lp", ctypes.c_double), ("ms_contract", ctypes.c_double),
+                ("ms_initial", ctypes.c_double), ("ms_refine", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_i32, _i64, _u32, _u64, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+_P32 = ctypes.POINTER(ctypes.c_int32)
+_P64 = ctypes.POINTER(ctypes.c_int64)
+
+SIGNATURES = {
+    "kmp_partition": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp]),
+    "kmp_partition_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp,
+                                        ctypes.POINTER(KmpOptions), ctypes.POINTER(KmpStats)]),
+    "kmp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "kmp_version": (ctypes.c_char_p, []),
+    "kmp_lp_cluster": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _i64, _u64, _vp, _vp, _vp, _P64, _vp]),
+    "kmp_two_hop": (_i64, [_vp, _vp, _vp, _vp, _i32, _i64, _vp, _vp, _vp, _vp]),
+    "kmp_contract": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _P32, _P64, _vp, _vp, _vp, _vp, _vp]),
+    "kmp_bipartition_round": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _vp, _P32, _P32, _P32, _i64, _u64,
+                                             _vp]),
+    "kmp_balance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _vp, _vp, _i32, _vp, _vp]),
+    "kmp_lp_refine": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _vp, _vp, _i32, _vp, _P64, _vp]),
+    "kmp_lp_subround": (_i64, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _u32, _u64, _vp, _vp, _i32, _vp, _i64,
+                               _vp, _vp, _vp, _vp]),
+}
+
+_lib = None
+
+
+def library() -> ctypes.CDLL:
+    """Load libkmp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libkmp.so not found at {LIB_PATH}; build it with "
+                              "`python -m paper_2105_02022_amd.build`")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libkmp takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_i32(*ts):
+    import torch
+    for t in ts:
+        if t is not None and t.dtype != torch.int32:
+            raise TypeError("graph arrays must be torch.int32")
+
+
+def kmp_strerror(code: int) -> str:
+    return library().kmp_strerror(code).decode()
+
+
+def kmp_version() -> str:
+    return library().kmp_version().decode()
+
+
+def kmp_partition(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
+                  stream=None) -> Tuple[int, "torch.Tensor"]:
+    """Returns (status, out_part).  Arrays are int32 device tensors."""
+    import torch
+    _check_i32(xadj, adjncy, vwgt, adjwgt)
+    n = xadj.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=xadj.device)
+    m = adjncy.numel()
+    rc = library().kmp_partition(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, m, k, epsilon,
+                                 seed & (2**64 - 1), _ptr(out), _stream(stream))
+    return rc, out
+
+
+def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
+                     stream=None, validate: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+    """Returns (status, out_part, stats dict)."""
+    import torch
+    _check_i32(xadj, adjncy, vwgt, adjwgt)
+    n = xadj.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=xadj.device)
+    opt = KmpOptions()
+    opt.validate = int(validate)
+    st = KmpStats()
+    rc = library().kmp_partition_ex(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
+                                    epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream), ctypes.byref(opt),
+                                    ctypes.byref(st))
+    L = st.levels
+    stats = {f[0]: getattr(st, f[0]) for f in KmpStats._fields_ if not f[0].startswith("reserved")}
+    stats["level_n"] = list(st.level_n[:L + 1])
+    stats["level_m"] = list(st.level_m[:L + 1])
+    return rc, out, stats
+
+
+def kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, level: int, U: int, seed: int, stream=None):
+    """Returns (rounds, label, cw, fav, moves[5])."""
+    import torch
+    _check_i32(xadj, adjncy, vwgt, adjwgt)
+    n = xadj.numel() - 1
+    dev = xadj.device
+    label = torch.empty(n, dtype=torch.int32, device=dev)
+    cw = torch.empty(n, dtype=torch.int64, device=dev)
+    fav = torch.empty(n, dtype=torch.int32, device=dev)
+    moves = (ctypes.c_int64 * 5)()
+    r = library().kmp_lp_cluster(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level, U,
+                                 seed & (2**64 - 1), _ptr(label), _ptr(cw), _ptr(fav),
+                                 ctypes.cast(moves, _P64), _stream(stream))
+    return r, label, cw, fav, list(moves)
+
+
+def kmp_two_hop(xadj, adjncy, vwgt, adjwgt, U: int, label, cw, fav, stream=None) -> int:
+    """In place on label (int32) and cw (int64); fav is int32 (bit pattern of uint32)."""
+    _check_i32(xadj, adjncy, vwgt, adjwgt, label, fav)
+    n = xadj.numel() - 1
+    return library().kmp_two_hop(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, U, _ptr(label), _ptr(cw),
+                                 _ptr(fav), _stream(stream))
+
+
+def kmp_contract(xadj, adjncy, vwgt, adjwgt, label, stream=None):
+    """Returns (status, map, cxadj, cadjncy, cvwgt, cadjwgt) trimmed to the coarse sizes."""
+    import torch
+    _check_i32(xadj, adjncy, vwgt, adjwgt, label)
+    n = xadj.numel() - 1
+    m = adjncy.numel()
+    dev = xadj.device
+    mp = torch.empty(n, dtype=torch.int32, device=dev)
+    cx = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    ca = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    cv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    cw = torch.empty(max(m, 1), dtype=torch.int32, device=dev)
+    cn = ctypes.c_int32(0)
+    cm = ctypes.c_int64(0)
+    rc = library().kmp_contract(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, _ptr(label), _ptr(mp),
+                                ctypes.byref(cn), ctypes.byref(cm), _ptr(cx), _ptr(ca), _ptr(cv), _ptr(cw),
+                                _stream(stream))
+    c_n, c_m = cn.value, cm.value
+    return rc, mp, cx[:c_n + 1], ca[:c_m], cv[:c_n], cw[:c_m]
+
+
+def kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, level: int, part, first: Sequence[int],
+                          fcount: Sequence[int], lk: int, seed: int, stream=None):
+    """part updated in place; returns (status, first, fcount) as lists."""
+    _check_i32(xadj, adjncy, vwgt, adjwgt, part)
+    n = xadj.numel() - 1
+    nb = len(first)
+    fa = (ctypes.c_int32 * (2 * nb + 1))(*first)
+    fc = (ctypes.c_int32 * (2 * nb + 1))(*fcount)
+    nbl = ctypes.c_int32(nb)
+    rc = library().kmp_bipartition_round(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level, _ptr(part),
+                                         ctypes.byref(nbl), ctypes.cast(fa, _P32), ctypes.cast(fc, _P32), lk,
+                                         seed & (2**64 - 1), _stream(stream))
+    q = nbl.value
+    return rc, list(fa[:q]), list(fc[:q])
+
+
+def kmp_balance(xadj, adjncy, vwgt, adjwgt, level: int, seed: int, part, wt, cap, stream=None) -> int:
+    _check_i32(xadj, adjncy, vwgt, adjwgt, part)
+    n = xadj.numel() - 1
+    return library().kmp_balance(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level, seed & (2**64 - 1),
+                                 _ptr(part), _ptr(wt), wt.numel(), _ptr(cap), _stream(stream))
+
+
+def kmp_lp_refine(xadj, adjncy, vwgt, adjwgt, level: int, seed: int, part, wt, cap, stream=None):
+    _check_i32(xadj, adjncy, vwgt, adjwgt, part)
+    n = xadj.numel() - 1
+    moves = (ctypes.c_int64 * 5)()
+    r = library().kmp_lp_refine(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level, seed & (2**64 - 1),
+                                _ptr(part), _ptr(wt), wt.numel(), _ptr(cap), ctypes.cast(moves, _P64),
+                                _stream(stream))
+    return r, list(moves)
+
+
+def kmp_lp_subround(xadj, adjncy, vwgt, adjwgt, level: int, round_: int, s: int, tag: int, seed: int, label, wt,
+                    cap_vec=None, cap_scalar: int = 0, active=None, fav=None, moved=None, stream=None) -> int:
+    _check_i32(xadj, adjncy, vwgt, adjwgt, label)
+    n = xadj.numel() - 1
+    return library().kmp_lp_subround(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level, round_, s, tag,
+                                     seed & (2**64 - 1), _ptr(label), _ptr(wt), wt.numel(), _ptr(cap_vec),
+                                     cap_scalar, _ptr(active), _ptr(fav), _ptr(moved), _stream(stream))
+
+
+def to_device(g, device="cuda"):
+    """Copy a generator Graph (numpy CSR) to int32 device tensors."""
+    import torch
+
+    def t(a):
+        return None if a is None else torch.from_numpy(a.astype("int32", copy=False)).to(device)
+    return t(g.xadj), t(g.adjncy), t(g.vwgt), t(g.adjwgt)
+
+
+def partition(g, k: int, epsilon: float = 0.03, seed: int = 1, device="cuda", validate: bool = False):
+    """Convenience: partition a generator Graph; returns (status, part numpy, stats)."""
+    xadj, adjncy, vwgt, adjwgt = to_device(g, device)
+    rc, out, stats = kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, epsilon, seed, validate=validate)
+    return rc, out.cpu().numpy(), stats

@@ -1,0 +1,278 @@
+// k-way balancer (paper Sec. 5.3 "Balancing"): move just enough nodes out of
+// every overloaded block, preferring high relative gain, into blocks that can
+// take them.
+//
+// Deterministic reading, per round:
+//   * target of a node v in an overloaded block b: the adjacent non-overloaded
+//     block with the largest connection that still fits (ties by hash, then
+//     index); otherwise the non-overloaded block with the most free capacity,
+//     if it fits;
+//   * d = conn(v, target) - conn(v, b); relative gain rg = d*c(v) if d >= 0,
+//     d/c(v) otherwise;
+//   * per overloaded block, candidates ordered by (rg desc, id asc); the
+//     shortest prefix whose weight covers the overload is selected;
+//   * selected moves into one target are admitted in ascending id while the
+//     target stays within its cap.
+// Sorting by rg is exact: d >= 0 sorts by the 62-bit integer d*c; d < 0 by
+// (floor(|d|/c), floor(2^62 (|d| mod c) / c)); two distinct fractions with
+// denominators below 2^31 differ by more than 2^-62, so the second word
+// separates them.
+#include "kmp_dev.h"
+
+namespace kmp {
+
+namespace {
+
+__global__ void k_bal_candidates(const int32_t* __restrict__ part, const uint8_t* __restrict__ over,
+                                 const int32_t* __restrict__ vwgt, int32_t n, int32_t tstar,
+                                 const int64_t* __restrict__ wt, const int64_t* __restrict__ cap,
+                                 int32_t* __restrict__ bal_t, const int64_t* __restrict__ bal_d,
+                                 int32_t* __restrict__ flag, uint32_t* __restrict__ kw0, uint32_t* __restrict__ kw1,
+                                 uint32_t* __restrict__ kw2, uint32_t* __restrict__ kcls)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t ok = 0;
+    const int32_t b = part[v];
+    if (over[b]) {
+        const int64_t c = vwgt ? vwgt[v] : 1;
+        int32_t t = bal_t[v];
+        int64_t d = bal_d[v];  // -conn(own) when there is no adjacent target
+        if (t < 0 && tstar >= 0 && wt[tstar] + c <= cap[tstar]) t = tstar;
+        bal_t[v] = t;
+        if (t >= 0) {
+            ok = 1;
+            uint32_t w0, w1, w2, cls;
+            if (d >= 0) {
+                const uint64_t key = ~((uint64_t)d * (uint64_t)c);  // descending d*c
+                cls = 0;
+                w0 = (uint32_t)(key >> 32);
+                w1 = (uint32_t)key;
+                w2 = 0;
+            } else {
+                const uint64_t ad = (uint64_t)(-d);
+                const uint64_t q = ad / (uint64_t)c, r = ad % (uint64_t)c;
+                const unsigned __int128 num = (unsigned __int128)r << 62;
+                const uint64_t frac = (uint64_t)(num / (unsigned __int128)(uint64_t)c);
+                cls = 1;
+                w0 = (uint32_t)q;
+                w1 = (uint32_t)(frac >> 32);
+                w2 = (uint32_t)frac;
+            }
+            kw0[v] = w0;
+            kw1[v] = w1;
+            kw2[v] = w2;
+            kcls[v] = cls;
+        }
+    }
+    flag[v] = ok;
+}
+
+__global__ void k_compact_ids(const int32_t* __restrict__ flag, const int32_t* __restrict__ pos, int32_t n,
+                              uint32_t* __restrict__ out)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && flag[v]) out[pos[v]] = (uint32_t)v;
+}
+
+__global__ void k_gather_key(const uint32_t* __restrict__ kw, const uint32_t* __restrict__ ids, int64_t nc,
+                             uint32_t* __restrict__ keys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) keys[i] = kw[ids[i]];
+}
+
+__global__ void k_gather_block(const int32_t* __restrict__ part, const uint32_t* __restrict__ ids, int64_t nc,
+                               uint32_t* __restrict__ keys)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) keys[i] = (uint32_t)part[ids[i]];
+}
+
+__global__ void k_gather_weight(const uint32_t* __restrict__ ids, const int32_t* __restrict__ vwgt, int64_t nc,
+                                int64_t* __restrict__ out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc) out[i] = vwgt ? vwgt[ids[i]] : 1;
+}
+
+// per block of the sorted list: weight before the element (exclusive)
+__global__ void k_seg_base(const uint32_t* __restrict__ blk, const int64_t* __restrict__ pre,
+                           const int64_t* __restrict__ cw, int64_t nc, int64_t* __restrict__ base)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nc && (i == 0 || blk[i] != blk[i - 1])) base[blk[i]] = pre[i] - cw[i];
+}
+
+__global__ void k_select(const uint32_t* __restrict__ ids, const uint32_t* __restrict__ blk,
+                         const int64_t* __restrict__ pre, const int64_t* __restrict__ cw,
+                         const int64_t* __restrict__ base, int64_t nc, const int64_t* __restrict__ wt,
+                         const int64_t* __restrict__ cap, uint8_t* __restrict__ sel)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nc) return;
+    const uint32_t b = blk[i];
+    const int64_t before = pre[i] - cw[i] - base[b];
+    sel[ids[i]] = before < wt[b] - cap[b];
+}
+
+__global__ void k_sel_flags(const uint8_t* __restrict__ sel, int32_t n, int32_t* __restrict__ flag)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) flag[v] = sel[v];
+}
+
+__global__ void k_sel_compact(const uint8_t* __restrict__ sel, const int32_t* __restrict__ pos, int32_t n,
+                              const int32_t* __restrict__ bal_t, uint32_t* __restrict__ keys,
+                              uint32_t* __restrict__ vals)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && sel[v]) {
+        keys[pos[v]] = (uint32_t)bal_t[v];
+        vals[pos[v]] = (uint32_t)v;
+    }
+}
+
+__global__ void k_admit_decide(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                               const int64_t* __restrict__ pre, const int64_t* __restrict__ base, int64_t ns,
+                               const int64_t* __restrict__ wt, const int64_t* __restrict__ cap,
+                               uint8_t* __restrict__ adm)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    const uint32_t t = keys[i];
+    adm[i] = wt[t] + (pre[i] - base[t]) <= cap[t];
+}
+
+__global__ void k_bal_apply(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                            const uint8_t* __restrict__ adm, int64_t ns, const int32_t* __restrict__ vwgt,
+                            int32_t* __restrict__ part, int64_t* __restrict__ wt, int64_t* counter)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns || !adm[i]) return;
+    const int32_t v = (int32_t)vals[i];
+    const int32_t t = (int32_t)keys[i];
+    const int64_t c = vwgt ? vwgt[v] : 1;
+    const int32_t b = part[v];
+    part[v] = t;
+    atomicAdd((unsigned long long*)&wt[t], (unsigned long long)c);
+    atomicAdd((unsigned long long*)&wt[b], (unsigned long long)(-c));
+    atomicAdd((unsigned long long*)counter, 1ull);
+}
+
+}  // namespace
+
+int32_t balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, int32_t* part,
+                int64_t* wt, int32_t nb, const int64_t* cap)
+{
+    const int32_t n = g.n;
+    if (n == 0 || nb == 0) return 0;
+    std::vector<int64_t> hcap(nb), hwt(nb);
+    c.read(hcap.data(), cap, sizeof(int64_t) * nb);
+    std::vector<uint8_t> hover(nb);
+    int32_t round = 0;
+    bool moved_prev = true;
+    DBuf<uint8_t> over, sel;
+    DBuf<int32_t> bal_t, flag;
+    DBuf<int64_t> bal_d;
+    DBuf<uint32_t> kw0, kw1, kw2, kcls;
+    for (;;) {
+        c.read(hwt.data(), wt, sizeof(int64_t) * nb);
+        bool any = false;
+        int32_t tstar = -1;
+        for (int32_t b = 0; b < nb; ++b) {
+            hover[b] = hwt[b] > hcap[b];
+            any |= hover[b] != 0;
+            if (!hover[b] && (tstar < 0 || hcap[b] - hwt[b] > hcap[tstar] - hwt[tstar])) tstar = b;
+        }
+        if (!any || !moved_prev) break;
+        if (!over.p) {
+            over = DBuf<uint8_t>(c, (size_t)nb);
+            sel = DBuf<uint8_t>(c, (size_t)n);
+            bal_t = DBuf<int32_t>(c, (size_t)n);
+            flag = DBuf<int32_t>(c, (size_t)n + 1);
+            bal_d = DBuf<int64_t>(c, (size_t)n);
+            kw0 = DBuf<uint32_t>(c, (size_t)n);
+            kw1 = DBuf<uint32_t>(c, (size_t)n);
+            kw2 = DBuf<uint32_t>(c, (size_t)n);
+            kcls = DBuf<uint32_t>(c, (size_t)n);
+        }
+        c.write(over.p, hover.data(), (size_t)nb);
+        fill_i32(c, bal_t.p, -1, n);
+        rate_for_balance(c, g, level, seed, round, sched, part, wt, cap, over.p, bal_t.p, bal_d.p);
+        hipLaunchKernelGGL(k_bal_candidates, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, over.p, g.vwgt, n,
+                           tstar, wt, cap, bal_t.p, bal_d.p, flag.p, kw0.p, kw1.p, kw2.p, kcls.p);
+        KMP_LAUNCH_CHECK();
+        DBuf<int32_t> pos(c, (size_t)n + 1);
+        scan_excl_i32(c, flag.p, pos.p, n, pos.p + n);
+        const int64_t ncand = c.read1(pos.p + n);
+        int64_t nmoved = 0;
+        if (ncand > 0) {
+            // candidate ids in ascending order
+            DBuf<uint32_t> ids(c, ncand), keys(c, ncand), k2(c, ncand), v2(c, ncand);
+            hipLaunchKernelGGL(k_compact_ids, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, flag.p, pos.p, n, ids.p);
+            KMP_LAUNCH_CHECK();
+            // LSD: least significant key word first, block last
+            const uint32_t* words[4] = {kw2.p, kw1.p, kw0.p, kcls.p};
+            const int wbits[4] = {32, 32, 32, 1};
+            for (int w = 0; w < 4; ++w) {
+                hipLaunchKernelGGL(k_gather_key, dim3(grid_for(ncand)), dim3(kBlock), 0, c.stream, words[w], ids.p,
+                                   ncand, keys.p);
+                KMP_LAUNCH_CHECK();
+                radix_sort_pairs(c, keys.p, ids.p, k2.p, v2.p, ncand, wbits[w]);
+            }
+            hipLaunchKernelGGL(k_gather_block, dim3(grid_for(ncand)), dim3(kBlock), 0, c.stream, part, ids.p, ncand,
+                               keys.p);
+            KMP_LAUNCH_CHECK();
+            radix_sort_pairs(c, keys.p, ids.p, k2.p, v2.p, ncand, bits_for((uint64_t)(nb - 1)));
+            // "just enough" prefix per overloaded block
+            DBuf<int64_t> cw(c, ncand), pre(c, ncand), base(c, (size_t)nb);
+            hipLaunchKernelGGL(k_gather_weight, dim3(grid_for(ncand)), dim3(kBlock), 0, c.stream, ids.p, g.vwgt,
+                               ncand, cw.p);
+            KMP_LAUNCH_CHECK();
+            scan_incl_i64(c, cw.p, pre.p, ncand);
+            hipLaunchKernelGGL(k_seg_base, dim3(grid_for(ncand)), dim3(kBlock), 0, c.stream, keys.p, pre.p, cw.p,
+                               ncand, base.p);
+            KMP_LAUNCH_CHECK();
+            c.zero(sel.p, (size_t)n);
+            hipLaunchKernelGGL(k_select, dim3(grid_for(ncand)), dim3(kBlock), 0, c.stream, ids.p, keys.p, pre.p, cw.p,
+                               base.p, ncand, wt, cap, sel.p);
+            KMP_LAUNCH_CHECK();
+            // admission per target in ascending id
+            hipLaunchKernelGGL(k_sel_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sel.p, n, flag.p);
+            KMP_LAUNCH_CHECK();
+            scan_excl_i32(c, flag.p, flag.p, n, flag.p + n);
+            const int64_t ns = c.read1(flag.p + n);
+            if (ns > 0) {
+                DBuf<uint32_t> tk(c, ns), tv(c, ns), tk2(c, ns), tv2(c, ns);
+                hipLaunchKernelGGL(k_sel_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sel.p, flag.p, n,
+                                   bal_t.p, tk.p, tv.p);
+                KMP_LAUNCH_CHECK();
+                radix_sort_pairs(c, tk.p, tv.p, tk2.p, tv2.p, ns, bits_for((uint64_t)(nb - 1)));
+                DBuf<int64_t> sc(c, ns), sp(c, ns), sb(c, (size_t)nb);
+                DBuf<uint8_t> adm(c, ns);
+                hipLaunchKernelGGL(k_gather_weight, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, tv.p, g.vwgt, ns,
+                                   sc.p);
+                KMP_LAUNCH_CHECK();
+                scan_incl_i64(c, sc.p, sp.p, ns);
+                hipLaunchKernelGGL(k_seg_base, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, tk.p, sp.p, sc.p, ns,
+                                   sb.p);
+                KMP_LAUNCH_CHECK();
+                hipLaunchKernelGGL(k_admit_decide, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, tk.p, tv.p, sp.p,
+                                   sb.p, ns, wt, cap, adm.p);
+                KMP_LAUNCH_CHECK();
+                int64_t* ctr = c.counters() + 11;
+                c.zero(ctr, sizeof(int64_t));
+                hipLaunchKernelGGL(k_bal_apply, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, tk.p, tv.p, adm.p, ns,
+                                   g.vwgt, part, wt, ctr);
+                KMP_LAUNCH_CHECK();
+                nmoved = c.read1(ctr);
+            }
+        }
+        moved_prev = nmoved > 0;
+        ++round;
+    }
+    return round;
+}
+
+}  // namespace kmp

@@ -1,0 +1,520 @@
+// Coarsening steps after label propagation: two-hop merging of singleton
+// clusters (paper Sec. 5.1 "Two-hop Clustering") and contraction (paper
+// Sec. 2 "Multilevel Graph Partitioning").
+//
+// Contraction layout: coarse id = rank of the label among non-empty labels
+// (prefix sum); members of every coarse node are bucketed; every coarse row
+// aggregates (map[u], w) over its members' edges, dropping intra-cluster
+// entries.  Rows whose members carry at most 4096 directed entries aggregate
+// in an LDS hash table and sort it in LDS (bitonic); heavier rows go through
+// an exact sort-reduce (stable radix by neighbour, then by row).
+#include "kmp_dev.h"
+
+namespace kmp {
+
+namespace {
+
+constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+
+// ---------------------------------------------------------------- two-hop
+__global__ void k_count_nonempty(const int64_t* __restrict__ cw, int32_t n, int64_t* out)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool f = i < n && cw[i] > 0;
+    uint64_t b = ballot64(f);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long*)out, (unsigned long long)__popcll(b));
+}
+
+__global__ void k_singleton_flags(const int32_t* __restrict__ label, const int64_t* __restrict__ cw,
+                                  const int32_t* __restrict__ vwgt, int32_t n, int32_t* __restrict__ flag)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int64_t c = vwgt ? vwgt[v] : 1;
+    flag[v] = cw[label[v]] == c;  // positive weights: the only member
+}
+
+__global__ void k_singleton_compact(const int32_t* __restrict__ flagpos, const int32_t* __restrict__ label,
+                                    const int64_t* __restrict__ cw, const int32_t* __restrict__ vwgt,
+                                    const uint32_t* __restrict__ fav, int32_t n, uint32_t* __restrict__ keys,
+                                    uint32_t* __restrict__ vals)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int64_t c = vwgt ? vwgt[v] : 1;
+    if (cw[label[v]] != c) return;
+    int32_t p = flagpos[v];
+    uint32_t f = fav[v];
+    keys[p] = f == kNone ? (uint32_t)n : f;  // isolated nodes form the last group
+    vals[p] = (uint32_t)v;
+}
+
+__global__ void k_group_heads(const uint32_t* __restrict__ keys, int64_t ns, int32_t* __restrict__ head)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    head[i] = (i == 0 || keys[i] != keys[i - 1]) ? (int32_t)i : 0;
+}
+
+__global__ void k_pair_eligible(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                const int32_t* __restrict__ gstart, int64_t ns, const int32_t* __restrict__ vwgt,
+                                int64_t U, int32_t* __restrict__ elig)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns) return;
+    int32_t e = 0;
+    if (((i - gstart[i]) & 1) == 0 && i + 1 < ns && keys[i + 1] == keys[i]) {
+        int64_t ca = vwgt ? vwgt[vals[i]] : 1;
+        int64_t cb = vwgt ? vwgt[vals[i + 1]] : 1;
+        e = ca + cb <= U;
+    }
+    elig[i] = e;
+}
+
+__global__ void k_pair_apply(const uint32_t* __restrict__ vals, const int32_t* __restrict__ elig,
+                             const int32_t* __restrict__ rank, int64_t ns, int64_t limit,
+                             const int32_t* __restrict__ vwgt, int32_t* __restrict__ label, int64_t* __restrict__ cw)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns || !elig[i] || rank[i] >= limit) return;
+    int32_t a = (int32_t)vals[i], b = (int32_t)vals[i + 1];
+    int32_t la = label[a], lb = label[b];
+    int64_t cb = vwgt ? vwgt[b] : 1;
+    label[b] = la;
+    atomicAdd((unsigned long long*)&cw[la], (unsigned long long)cb);
+    atomicAdd((unsigned long long*)&cw[lb], (unsigned long long)(-cb));
+}
+
+// ---------------------------------------------------------------- contraction
+__global__ void k_nonempty_flags(const int64_t* __restrict__ cw, int32_t n, int32_t* __restrict__ flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = cw[i] > 0;
+}
+
+__global__ void k_map_and_weights(const int32_t* __restrict__ label, const int32_t* __restrict__ cid,
+                                  const int64_t* __restrict__ cw, const int32_t* __restrict__ xadj, int32_t n,
+                                  int32_t* __restrict__ map, int32_t* __restrict__ cvwgt, int32_t* __restrict__ mcnt,
+                                  int32_t* __restrict__ dsum)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t c = cid[label[v]];
+    map[v] = c;
+    if (cw[v] > 0) cvwgt[cid[v]] = (int32_t)cw[v];  // v read as a label here
+    atomicAdd(&mcnt[c], 1);
+    atomicAdd(&dsum[c], xadj[v + 1] - xadj[v]);
+}
+
+__global__ void k_place_members(const int32_t* __restrict__ map, int32_t n, const int32_t* __restrict__ mstart,
+                                int32_t* __restrict__ cursor, int32_t* __restrict__ members)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t c = map[v];
+    int32_t p = atomicAdd(&cursor[c], 1);
+    members[mstart[c] + p] = (int32_t)v;
+}
+
+constexpr int R_T0 = 64, R_T1 = 512, R_T2 = 4096;
+
+__global__ void k_row_tiers(const int32_t* __restrict__ dsum, int32_t nc, uint32_t* __restrict__ key,
+                            uint32_t* __restrict__ val, int32_t* __restrict__ cnt4)
+{
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int32_t d = dsum[c];
+    uint32_t t = d <= R_T0 ? 0 : d <= R_T1 ? 1 : d <= R_T2 ? 2 : 3;
+    key[c] = t;
+    val[c] = (uint32_t)c;
+    atomicAdd(&cnt4[t], 1);
+}
+
+struct RowArgs {
+    const int32_t* xadj;
+    const int32_t* adjncy;
+    const int32_t* adjwgt;
+    const int32_t* map;
+    const int32_t* members;
+    const int32_t* mstart;   // [nc+1]
+    const int32_t* dstart;   // [nc+1] exclusive prefix of member degree sums
+    int32_t* tmp_adj;
+    int32_t* tmp_w;
+    int32_t* cdeg;
+};
+
+// G lanes per coarse row, 2^HB LDS slots per row.
+template <int G, int HB>
+__global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32_t* __restrict__ rows, int32_t count)
+{
+    constexpr int GPB = kBlock / G;
+    constexpr int HS = 1 << HB;
+    __shared__ uint32_t s_keys[GPB * HS];
+    __shared__ uint32_t s_vals[GPB * HS];
+    __shared__ uint32_t s_cnt[4];
+    const int tid = threadIdx.x, grp = tid / G, gl = tid % G;
+    uint32_t* keys = s_keys + grp * HS;
+    uint32_t* vals = s_vals + grp * HS;
+    for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
+        const int64_t i = base + grp;
+        const int32_t row = i < count ? rows[i] : -1;
+        for (int j = gl; j < HS; j += G) {
+            keys[j] = EMPTY;
+            vals[j] = 0;
+        }
+        __syncthreads();
+        if (row >= 0) {
+            for (int32_t mi = a.mstart[row]; mi < a.mstart[row + 1]; ++mi) {
+                const int32_t v = a.members[mi];
+                const int32_t e1 = a.xadj[v + 1];
+                for (int32_t e = a.xadj[v] + gl; e < e1; e += G) {
+                    const int32_t cu = a.map[a.adjncy[e]];
+                    if (cu == row) continue;
+                    const uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
+                    const uint32_t mask = HS - 1;
+                    uint32_t h = slot_of((uint32_t)cu, HB);
+                    while (true) {
+                        uint32_t old = atomicCAS(&keys[h], EMPTY, (uint32_t)cu);
+                        if (old == EMPTY || old == (uint32_t)cu) {
+                            atomicAdd(&vals[h], w);
+                            break;
+                        }
+                        h = (h + 1) & mask;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        // bitonic sort of every group's table, ascending key (EMPTY last)
+        for (int size = 2; size <= HS; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                for (int p = gl; p < HS / 2; p += G) {
+                    const int lo = 2 * stride * (p / stride) + (p % stride);
+                    const int hi = lo + stride;
+                    const bool up = (lo & size) == 0;
+                    const uint32_t kl = keys[lo], kh = keys[hi];
+                    if ((kl > kh) == up) {
+                        keys[lo] = kh;
+                        keys[hi] = kl;
+                        const uint32_t t = vals[lo];
+                        vals[lo] = vals[hi];
+                        vals[hi] = t;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // number of distinct neighbours = non-empty slots
+        uint32_t u = 0;
+        for (int j = gl; j < HS; j += G) u += keys[j] != EMPTY;
+        if (G <= 64) {
+#pragma unroll
+            for (int d = G / 2; d > 0; d >>= 1) u += __shfl_xor(u, d, G);
+        } else {
+            for (int d = 32; d > 0; d >>= 1) u += __shfl_xor(u, d, 64);
+            if ((tid & 63) == 0) s_cnt[tid >> 6] = u;
+            __syncthreads();
+            u = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        }
+        if (row >= 0) {
+            const int32_t o = a.dstart[row];
+            for (int j = gl; j < (int)u; j += G) {
+                a.tmp_adj[o + j] = (int32_t)keys[j];
+                a.tmp_w[o + j] = (int32_t)vals[j];
+            }
+            if (gl == 0) a.cdeg[row] = (int32_t)u;
+        }
+        __syncthreads();
+    }
+}
+
+// ---- heavy rows: expand, sort by (row, neighbour), reduce
+__global__ __launch_bounds__(kBlock) void k_heavy_expand(RowArgs a, const int32_t* __restrict__ rows, int32_t nrows,
+                                                         const int32_t* __restrict__ eoff, uint32_t nc,
+                                                         uint32_t* __restrict__ nbr, uint32_t* __restrict__ rowq,
+                                                         int32_t* __restrict__ w)
+{
+    for (int32_t q = blockIdx.x; q < nrows; q += gridDim.x) {
+        const int32_t row = rows[q];
+        int32_t pos = eoff[q];
+        for (int32_t mi = a.mstart[row]; mi < a.mstart[row + 1]; ++mi) {
+            const int32_t v = a.members[mi];
+            const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
+            for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
+                const int32_t cu = a.map[a.adjncy[e]];
+                const int32_t p = pos + (e - e0);
+                nbr[p] = cu == row ? nc : (uint32_t)cu;  // intra entries sort last in the row
+                rowq[p] = (uint32_t)q;
+                w[p] = a.adjwgt ? a.adjwgt[e] : 1;
+            }
+            pos += e1 - e0;
+        }
+    }
+}
+
+__global__ void k_heavy_deg(const int32_t* __restrict__ rows, int32_t nrows, const int32_t* __restrict__ dsum,
+                            int32_t* __restrict__ d)
+{
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < nrows) d[q] = dsum[rows[q]];
+}
+
+__global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* __restrict__ idx, int64_t n,
+                             uint32_t* __restrict__ dst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[idx[i]];
+}
+
+__global__ void k_heavy_heads(const uint32_t* __restrict__ rq, const uint32_t* __restrict__ nb,
+                              const uint32_t* __restrict__ perm, const int32_t* __restrict__ w, int64_t ne,
+                              int32_t* __restrict__ head, int64_t* __restrict__ wsorted)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    head[i] = (i == 0 || rq[i] != rq[i - 1] || nb[i] != nb[i - 1]);
+    wsorted[i] = w[perm[i]];
+}
+
+// Row start: remember the run id of the row's first entry.
+__global__ void k_heavy_rowfirst(const uint32_t* __restrict__ rq, const int32_t* __restrict__ head_excl, int64_t ne,
+                                 int32_t* __restrict__ rowfirst)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne && (i == 0 || rq[i] != rq[i - 1])) rowfirst[rq[i]] = head_excl[i];
+}
+
+__global__ void k_run_start(const int32_t* __restrict__ is_head, int64_t ne, int32_t* __restrict__ start_of_run,
+                            const int32_t* __restrict__ head_excl)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ne && is_head[i]) start_of_run[head_excl[i]] = (int32_t)i;
+}
+
+// The last entry of every run writes the run (sum of its weights); the last
+// entry of every row writes the row's distinct-neighbour count.  The intra-
+// cluster run (neighbour id nc) sorts last in its row and is dropped.
+__global__ void k_heavy_emit(const uint32_t* __restrict__ rq, const uint32_t* __restrict__ nb,
+                             const int32_t* __restrict__ head_excl, const int32_t* __restrict__ is_head,
+                             const int64_t* __restrict__ wpre, const int64_t* __restrict__ wsorted, int64_t ne,
+                             uint32_t nc, const int32_t* __restrict__ rows, const int32_t* __restrict__ dstart,
+                             const int32_t* __restrict__ start_of_run, const int32_t* __restrict__ rowfirst,
+                             int32_t* __restrict__ tmp_adj, int32_t* __restrict__ tmp_w, int32_t* __restrict__ cdeg)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ne) return;
+    const bool run_last = (i + 1 == ne) || is_head[i + 1];
+    if (!run_last) return;
+    const uint32_t q = rq[i];
+    const int32_t run = head_excl[i] + is_head[i] - 1;
+    const int32_t pos = run - rowfirst[q];
+    const int32_t row = rows[q];
+    const uint32_t nbr = nb[i];
+    if (nbr < nc) {
+        const int32_t s = start_of_run[run];
+        const int64_t sum = wpre[i] - wpre[s] + wsorted[s];
+        tmp_adj[dstart[row] + pos] = (int32_t)nbr;
+        tmp_w[dstart[row] + pos] = (int32_t)sum;
+    }
+    const bool row_last = (i + 1 == ne) || rq[i + 1] != q;
+    if (row_last) cdeg[row] = nbr < nc ? pos + 1 : pos;
+}
+
+__global__ void k_copy_rows(const int32_t* __restrict__ cxadj, const int32_t* __restrict__ dstart, int32_t nc,
+                            const int32_t* __restrict__ tmp_adj, const int32_t* __restrict__ tmp_w,
+                            int32_t* __restrict__ cadj, int32_t* __restrict__ cw)
+{
+    // 16 lanes per row
+    const int gl = threadIdx.x & 15;
+    int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int64_t stride = ((int64_t)gridDim.x * blockDim.x) >> 4;
+    for (; r < nc; r += stride) {
+        const int32_t o = cxadj[r], len = cxadj[r + 1] - o, s = dstart[r];
+        for (int32_t j = gl; j < len; j += 16) {
+            cadj[o + j] = tmp_adj[s + j];
+            cw[o + j] = tmp_w[s + j];
+        }
+    }
+}
+
+}  // namespace
+
+// ================================================================ host side
+
+int32_t count_nonempty(Ctx& c, const int64_t* cw, int32_t n)
+{
+    int64_t* ctr = c.counters();
+    c.zero(ctr + 8, sizeof(int64_t));
+    if (n > 0) {
+        hipLaunchKernelGGL(k_count_nonempty, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, cw, n, ctr + 8);
+        KMP_LAUNCH_CHECK();
+    }
+    return (int32_t)c.read1(ctr + 8);
+}
+
+int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav)
+{
+    const int32_t n = g.n;
+    const int32_t nc = count_nonempty(c, cw, n);
+    const int64_t half = n / 2;
+    if (nc <= half) return 0;
+    DBuf<int32_t> flag(c, (size_t)n + 1);
+    hipLaunchKernelGGL(k_singleton_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, label, cw, g.vwgt, n, flag.p);
+    KMP_LAUNCH_CHECK();
+    scan_excl_i32(c, flag.p, flag.p, n, flag.p + n);
+    const int32_t ns = c.read1(flag.p + n);
+    if (ns < 2) return 0;
+    DBuf<uint32_t> keys(c, ns), vals(c, ns), k2(c, ns), v2(c, ns);
+    hipLaunchKernelGGL(k_singleton_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, flag.p, label, cw, g.vwgt,
+                       fav, n, keys.p, vals.p);
+    KMP_LAUNCH_CHECK();
+    radix_sort_pairs(c, keys.p, vals.p, k2.p, v2.p, ns, bits_for((uint64_t)n));
+    DBuf<int32_t> gstart(c, ns), elig(c, (size_t)ns + 1);
+    hipLaunchKernelGGL(k_group_heads, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, keys.p, (int64_t)ns, gstart.p);
+    KMP_LAUNCH_CHECK();
+    scan_incl_max_i32(c, gstart.p, gstart.p, ns);
+    hipLaunchKernelGGL(k_pair_eligible, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, keys.p, vals.p, gstart.p,
+                       (int64_t)ns, g.vwgt, U, elig.p);
+    KMP_LAUNCH_CHECK();
+    DBuf<int32_t> rank(c, (size_t)ns + 1);
+    scan_excl_i32(c, elig.p, rank.p, ns, rank.p + ns);
+    const int64_t E = c.read1(rank.p + ns);
+    const int64_t limit = (int64_t)nc - half;
+    hipLaunchKernelGGL(k_pair_apply, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, vals.p, elig.p, rank.p,
+                       (int64_t)ns, limit, g.vwgt, label, cw);
+    KMP_LAUNCH_CHECK();
+    return E < limit ? E : limit;
+}
+
+void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
+              int32_t& cn, int64_t& cm)
+{
+    const int32_t n = g.n;
+    DBuf<int32_t> cid(c, (size_t)n + 1);
+    hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, cw, n, cid.p);
+    KMP_LAUNCH_CHECK();
+    scan_excl_i32(c, cid.p, cid.p, n, cid.p + n);
+    const int32_t nc = c.read1(cid.p + n);
+    cn = nc;
+    out.xadj = DBuf<int32_t>(c, (size_t)nc + 1);
+    out.vwgt = DBuf<int32_t>(c, (size_t)nc);
+    DBuf<int32_t> mstart(c, (size_t)nc + 1), dstart(c, (size_t)nc + 1), cursor(c, (size_t)nc);
+    c.zero(mstart.p, sizeof(int32_t) * ((size_t)nc + 1));
+    c.zero(dstart.p, sizeof(int32_t) * ((size_t)nc + 1));
+    c.zero(cursor.p, sizeof(int32_t) * (size_t)nc);
+    hipLaunchKernelGGL(k_map_and_weights, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, label, cid.p, cw, g.xadj, n,
+                       map, out.vwgt.p, mstart.p, dstart.p);
+    KMP_LAUNCH_CHECK();
+    // keep the per-row fine degree sums before turning them into offsets
+    DBuf<int32_t> dsum(c, (size_t)nc + 1);
+    KMP_HIP(hipMemcpyAsync(dsum.p, dstart.p, sizeof(int32_t) * (size_t)nc, hipMemcpyDeviceToDevice, c.stream));
+    scan_excl_i32(c, mstart.p, mstart.p, nc, mstart.p + nc);
+    scan_excl_i32(c, dstart.p, dstart.p, nc, dstart.p + nc);
+    DBuf<int32_t> members(c, (size_t)n);
+    hipLaunchKernelGGL(k_place_members, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, map, n, mstart.p, cursor.p,
+                       members.p);
+    KMP_LAUNCH_CHECK();
+    // rows by tier of their fine entry count
+    DBuf<uint32_t> rk(c, nc), rv(c, nc), rk2(c, nc), rv2(c, nc);
+    DBuf<int32_t> cnt4(c, 4);
+    c.zero(cnt4.p, 4 * sizeof(int32_t));
+    hipLaunchKernelGGL(k_row_tiers, dim3(grid_for(nc)), dim3(kBlock), 0, c.stream, dsum.p, nc, rk.p, rv.p, cnt4.p);
+    KMP_LAUNCH_CHECK();
+    radix_sort_pairs(c, rk.p, rv.p, rk2.p, rv2.p, nc, 2);
+    int32_t tc[4];
+    c.read(tc, cnt4.p, sizeof(tc));
+    const int32_t* rows = reinterpret_cast<const int32_t*>(rv.p);
+    DBuf<int32_t> tmp_adj(c, (size_t)(g.m > 0 ? g.m : 1)), tmp_w(c, (size_t)(g.m > 0 ? g.m : 1));
+    DBuf<int32_t> cdeg(c, (size_t)nc + 1);
+    RowArgs a;
+    a.xadj = g.xadj;
+    a.adjncy = g.adjncy;
+    a.adjwgt = g.adjwgt;
+    a.map = map;
+    a.members = members.p;
+    a.mstart = mstart.p;
+    a.dstart = dstart.p;
+    a.tmp_adj = tmp_adj.p;
+    a.tmp_w = tmp_w.p;
+    a.cdeg = cdeg.p;
+    int32_t off = 0;
+    if (tc[0] > 0) {
+        constexpr int G = 16;
+        hipLaunchKernelGGL((k_contract_rows<G, 7>), dim3(grid_for(tc[0], kBlock / G, 65536)), dim3(kBlock), 0,
+                           c.stream, a, rows + off, tc[0]);
+        KMP_LAUNCH_CHECK();
+    }
+    off += tc[0];
+    if (tc[1] > 0) {
+        constexpr int G = 64;
+        hipLaunchKernelGGL((k_contract_rows<G, 10>), dim3(grid_for(tc[1], kBlock / G, 65536)), dim3(kBlock), 0,
+                           c.stream, a, rows + off, tc[1]);
+        KMP_LAUNCH_CHECK();
+    }
+    off += tc[1];
+    if (tc[2] > 0) {
+        hipLaunchKernelGGL((k_contract_rows<256, 13>), dim3(grid_for(tc[2], 1, 65536)), dim3(kBlock), 0, c.stream, a,
+                           rows + off, tc[2]);
+        KMP_LAUNCH_CHECK();
+    }
+    off += tc[2];
+    if (tc[3] > 0) {
+        const int32_t nh = tc[3];
+        const int32_t* hrows = rows + off;
+        DBuf<int32_t> eoff(c, (size_t)nh + 1);
+        hipLaunchKernelGGL(k_heavy_deg, dim3(grid_for(nh)), dim3(kBlock), 0, c.stream, hrows, nh, dsum.p, eoff.p);
+        KMP_LAUNCH_CHECK();
+        scan_excl_i32(c, eoff.p, eoff.p, nh, eoff.p + nh);
+        const int64_t ne = c.read1(eoff.p + nh);
+        DBuf<uint32_t> nb(c, ne), rq(c, ne), perm(c, ne), t1(c, ne), t2(c, ne);
+        DBuf<int32_t> w(c, ne);
+        hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh, 1, 4096)), dim3(kBlock), 0, c.stream, a, hrows, nh,
+                           eoff.p, (uint32_t)nc, nb.p, rq.p, w.p);
+        KMP_LAUNCH_CHECK();
+        // sort entry ids by neighbour, then stably by row
+        iota_i32(c, reinterpret_cast<int32_t*>(perm.p), ne);
+        radix_sort_pairs(c, nb.p, perm.p, t1.p, t2.p, ne, bits_for((uint64_t)nc));
+        DBuf<uint32_t> rqs(c, ne);
+        hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, rq.p, perm.p, ne, rqs.p);
+        KMP_LAUNCH_CHECK();
+        // carry the neighbour along: sort (row, position) and gather both
+        DBuf<uint32_t> pos(c, ne);
+        iota_i32(c, reinterpret_cast<int32_t*>(pos.p), ne);
+        radix_sort_pairs(c, rqs.p, pos.p, t1.p, t2.p, ne, bits_for((uint64_t)(nh - 1)));
+        // final order: entry = perm[pos[i]]
+        DBuf<uint32_t> perm2(c, ne), nbs(c, ne);
+        hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, perm.p, pos.p, ne, perm2.p);
+        KMP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, nb.p, pos.p, ne, nbs.p);
+        KMP_LAUNCH_CHECK();
+        DBuf<int32_t> head(c, (size_t)ne + 1), hexcl(c, (size_t)ne + 1), runstart(c, (size_t)ne + 1);
+        DBuf<int64_t> ws(c, ne), wpre(c, ne);
+        hipLaunchKernelGGL(k_heavy_heads, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, rqs.p, nbs.p, perm2.p, w.p,
+                           ne, head.p, ws.p);
+        KMP_LAUNCH_CHECK();
+        scan_excl_i32(c, head.p, hexcl.p, ne, hexcl.p + ne);
+        scan_incl_i64(c, ws.p, wpre.p, ne);
+        hipLaunchKernelGGL(k_run_start, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, head.p, ne, runstart.p,
+                           hexcl.p);
+        KMP_LAUNCH_CHECK();
+        DBuf<int32_t> rowfirst(c, (size_t)nh);
+        hipLaunchKernelGGL(k_heavy_rowfirst, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, rqs.p, hexcl.p, ne,
+                           rowfirst.p);
+        KMP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_heavy_emit, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, rqs.p, nbs.p, hexcl.p, head.p,
+                           wpre.p, ws.p, ne, (uint32_t)nc, hrows, dstart.p, runstart.p, rowfirst.p, tmp_adj.p,
+                           tmp_w.p, cdeg.p);
+        KMP_LAUNCH_CHECK();
+    }
+    scan_excl_i32(c, cdeg.p, out.xadj.p, nc, out.xadj.p + nc);
+    cm = c.read1(out.xadj.p + nc);
+    out.adjncy = DBuf<int32_t>(c, (size_t)(cm > 0 ? cm : 1));
+    out.adjwgt = DBuf<int32_t>(c, (size_t)(cm > 0 ? cm : 1));
+    if (nc > 0) {
+        hipLaunchKernelGGL(k_copy_rows, dim3(grid_for((int64_t)nc * 16, kBlock, 16384)), dim3(kBlock), 0, c.stream,
+                           out.xadj.p, dstart.p, nc, tmp_adj.p, tmp_w.p, out.adjncy.p, out.adjwgt.p);
+        KMP_LAUNCH_CHECK();
+    }
+}
+
+}  // namespace kmp

@@ -1,0 +1,430 @@
+// Initial bipartitioning during uncoarsening (paper Alg. 2 "bipartitionBlocks",
+// Sec. 4 "Handling General k", Sec. 5.2), projection (Alg. 1) and block
+// statistics.
+//
+// Every block with final count f >= 2 is split by greedy graph growing (GGG,
+// Sec. 5.2): one workgroup per block builds the block's induced subgraph in
+// local ids (rank of the node id inside the block) and runs R = 8 growths,
+// one per wavefront; the growth with the lexicographically smallest
+// (infeasible?, overload, cut, seed index) is kept.  Growth j adds, while the
+// grown side weighs less than floor(c(B) f0 / f), the frontier node with the
+// largest gain (smallest local id on ties) that fits under f0 * L_k, or, when
+// no frontier node fits, the fitting unassigned node with the smallest hash
+// H(seed; 5, level, first, f, j, local id).
+#include "kmp_dev.h"
+
+namespace kmp {
+
+namespace {
+
+// ---------------------------------------------------------------- extraction
+__global__ void k_block_count(const int32_t* __restrict__ part, const int32_t* __restrict__ xadj, int32_t n,
+                              int32_t* __restrict__ bcnt, int32_t* __restrict__ bdeg, uint32_t* __restrict__ key,
+                              uint32_t* __restrict__ val)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    int32_t b = part[v];
+    atomicAdd(&bcnt[b], 1);
+    atomicAdd(&bdeg[b], xadj[v + 1] - xadj[v]);
+    key[v] = (uint32_t)b;
+    val[v] = (uint32_t)v;
+}
+
+__global__ void k_local_ids(const uint32_t* __restrict__ verts, const int32_t* __restrict__ part,
+                            const int32_t* __restrict__ bstart, int32_t n, int32_t* __restrict__ local)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t v = (int32_t)verts[i];
+    local[v] = (int32_t)i - bstart[part[v]];
+}
+
+// ---------------------------------------------------------------- GGG
+constexpr int GGG_THREADS = 64 * kSeeds;
+
+struct GGGJob {
+    int32_t b, first, f, nverts;
+    int32_t dsum;      // sum of degrees of the block's nodes (bound on internal entries)
+    int32_t pad;
+    int64_t scratch;   // byte offset into the global scratch (global variant)
+};
+
+struct GGGArgs {
+    const int32_t* xadj;
+    const int32_t* adjncy;
+    const int32_t* vwgt;
+    const int32_t* adjwgt;
+    const int32_t* part;
+    const uint32_t* verts;
+    const int32_t* bstart;
+    const int32_t* local;
+    const GGGJob* jobs;
+    int64_t lk;
+    uint32_t hpre;      // H prefix over (seed; T_GGG, level)
+    uint8_t* side;      // [n]
+    char* scratch;      // global variant
+};
+
+__host__ __device__ inline int64_t ggg_bytes(int64_t nv, int64_t d)
+{
+    // lxadj (nv+1) + lvw (nv) + ladj (d) + lw (d) + gain (R*nv) int32, state (R*nv) bytes
+    int64_t words = (nv + 1) + nv + 2 * d + (int64_t)kSeeds * nv;
+    int64_t bytes = words * 4 + (int64_t)kSeeds * nv;
+    return (bytes + 15) & ~(int64_t)15;
+}
+
+template <bool LDS>
+__device__ inline void fence_wave()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <bool LDS>
+__global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
+{
+    extern __shared__ __align__(16) char lds_raw[];
+    __shared__ int64_t s_red[GGG_THREADS / 64];
+    __shared__ int64_t s_cut[kSeeds], s_over[kSeeds];
+    __shared__ int32_t s_best;
+    __shared__ int32_t s_carry;
+
+    const GGGJob job = a.jobs[blockIdx.x];
+    const int32_t nv = job.nverts;
+    const int32_t b = job.b;
+    const uint32_t* vlist = a.verts + a.bstart[b];
+    char* base = LDS ? lds_raw : a.scratch + job.scratch;
+    int32_t* lxadj = reinterpret_cast<int32_t*>(base);
+    int32_t* lvw = lxadj + (nv + 1);
+    int32_t* ladj = lvw + nv;
+    int32_t* lw = ladj + job.dsum;
+    int32_t* gain_all = lw + job.dsum;
+    uint8_t* st_all = reinterpret_cast<uint8_t*>(gain_all + (int64_t)kSeeds * nv);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+    // ---- internal degrees and block weight
+    int64_t cacc = 0;
+    for (int32_t i = tid; i < nv; i += GGG_THREADS) {
+        const int32_t v = (int32_t)vlist[i];
+        int32_t cnt = 0;
+        for (int32_t e = a.xadj[v]; e < a.xadj[v + 1]; ++e) cnt += a.part[a.adjncy[e]] == b;
+        lxadj[i + 1] = cnt;
+        const int32_t c = a.vwgt ? a.vwgt[v] : 1;
+        lvw[i] = c;
+        cacc += c;
+    }
+    for (int d = 32; d > 0; d >>= 1) cacc += __shfl_xor(cacc, d, 64);
+    if (lane == 0) s_red[wv] = cacc;
+    if (tid == 0) {
+        lxadj[0] = 0;
+        s_carry = 0;
+    }
+    __syncthreads();
+    int64_t cB = 0;
+    for (int q = 0; q < GGG_THREADS / 64; ++q) cB += s_red[q];
+    // ---- prefix sum of internal degrees (chunks of GGG_THREADS, carry in LDS)
+    for (int32_t c0 = 0; c0 < nv; c0 += GGG_THREADS) {
+        const int32_t i = c0 + tid;
+        int32_t x = i < nv ? lxadj[i + 1] : 0;
+        // inclusive scan in the wave
+        for (int d = 1; d < 64; d <<= 1) {
+            int32_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        __syncthreads();
+        if (lane == 63) s_red[wv] = x;
+        __syncthreads();
+        int32_t pre = s_carry;
+        for (int q = 0; q < wv; ++q) pre += (int32_t)s_red[q];
+        if (i < nv) lxadj[i + 1] = pre + x;
+        __syncthreads();
+        if (tid == GGG_THREADS - 1) s_carry = pre + x;
+        __syncthreads();
+    }
+    // ---- local adjacency (ascending node id => ascending local id)
+    for (int32_t i = tid; i < nv; i += GGG_THREADS) {
+        const int32_t v = (int32_t)vlist[i];
+        int32_t pos = lxadj[i];
+        for (int32_t e = a.xadj[v]; e < a.xadj[v + 1]; ++e) {
+            const int32_t u = a.adjncy[e];
+            if (a.part[u] != b) continue;
+            ladj[pos] = a.local[u];
+            lw[pos] = a.adjwgt ? a.adjwgt[e] : 1;
+            ++pos;
+        }
+    }
+    __syncthreads();
+
+    // ---- one growth per wavefront
+    const int32_t f = job.f, f0 = f / 2, f1 = f - f0;
+    const int64_t t0 = cB * f0 / f;
+    const int64_t cap0 = (int64_t)f0 * a.lk, cap1 = (int64_t)f1 * a.lk;
+    const int j = wv;
+    int32_t* gain = gain_all + (int64_t)j * nv;
+    uint8_t* st = st_all + (int64_t)j * nv;  // 0 free, 1 frontier, 2 grown side
+    const uint32_t hj = hash_step(hash_step(hash_step(a.hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
+    for (int32_t i = lane; i < nv; i += 64) {
+        int32_t s = 0;
+        for (int32_t e = lxadj[i]; e < lxadj[i + 1]; ++e) s += lw[e];
+        gain[i] = -s;
+        st[i] = 0;
+    }
+    fence_wave<LDS>();
+    int64_t w0 = 0;
+    while (w0 < t0) {
+        uint64_t best = 0;  // (gain biased << 32) | ~id ; 0 = none
+        for (int32_t i = lane; i < nv; i += 64) {
+            if (st[i] != 1 || w0 + lvw[i] > cap0) continue;
+            const uint64_t k = ((uint64_t)((uint32_t)gain[i] ^ 0x80000000u) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
+            if (k > best) best = k;
+        }
+        for (int d = 32; d > 0; d >>= 1) {
+            const uint64_t o = shfl_xor_u64(best, d);
+            if (o > best) best = o;
+        }
+        int32_t pick;
+        if (best != 0) {
+            pick = (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFu));
+        } else {
+            uint64_t hb = ~0ull;  // (hash << 32) | id ; max = none
+            for (int32_t i = lane; i < nv; i += 64) {
+                if (st[i] == 2 || w0 + lvw[i] > cap0) continue;
+                const uint64_t k = ((uint64_t)hash_step(hj, (uint32_t)i, 6) << 32) | (uint32_t)i;
+                if (k < hb) hb = k;
+            }
+            for (int d = 32; d > 0; d >>= 1) {
+                const uint64_t o = shfl_xor_u64(hb, d);
+                if (o < hb) hb = o;
+            }
+            if (hb == ~0ull) break;
+            pick = (int32_t)(hb & 0xFFFFFFFFu);
+        }
+        if (lane == 0) st[pick] = 2;
+        w0 += lvw[pick];
+        fence_wave<LDS>();
+        for (int32_t e = lxadj[pick] + lane; e < lxadj[pick + 1]; e += 64) {
+            const int32_t u = ladj[e];
+            if (st[u] == 2) continue;
+            gain[u] += 2 * lw[e];
+            st[u] = 1;
+        }
+        fence_wave<LDS>();
+    }
+    int64_t cut = 0;
+    for (int32_t i = lane; i < nv; i += 64) {
+        if (st[i] != 2) continue;
+        for (int32_t e = lxadj[i]; e < lxadj[i + 1]; ++e)
+            if (st[ladj[e]] != 2) cut += lw[e];
+    }
+    for (int d = 32; d > 0; d >>= 1) cut += __shfl_xor(cut, d, 64);
+    if (lane == 0) {
+        s_cut[j] = cut;
+        s_over[j] = (w0 > cap0 ? w0 - cap0 : 0) + (cB - w0 > cap1 ? cB - w0 - cap1 : 0);
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int bj = 0;
+        for (int q = 1; q < kSeeds; ++q) {
+            const bool fq = s_over[q] > 0, fb = s_over[bj] > 0;
+            bool better;
+            if (fq != fb) better = !fq;
+            else if (s_over[q] != s_over[bj]) better = s_over[q] < s_over[bj];
+            else better = s_cut[q] < s_cut[bj];
+            if (better) bj = q;
+        }
+        s_best = bj;
+    }
+    __syncthreads();
+    const uint8_t* stb = st_all + (int64_t)s_best * nv;
+    for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = stb[i] == 2 ? 0 : 1;
+}
+
+__global__ void k_relabel(int32_t* __restrict__ part, const uint8_t* __restrict__ side,
+                          const int32_t* __restrict__ newidx, const uint8_t* __restrict__ split, int32_t n)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t b = part[v];
+    part[v] = newidx[b] + (split[b] ? side[v] : 0);
+}
+
+__global__ void k_project(const int32_t* __restrict__ cpart, const int32_t* __restrict__ map,
+                          int32_t* __restrict__ fpart, int32_t n)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) fpart[v] = cpart[map[v]];
+}
+
+__global__ void k_block_weights(const int32_t* __restrict__ part, const int32_t* __restrict__ vwgt, int32_t n,
+                                int64_t* __restrict__ wt)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n) atomicAdd((unsigned long long*)&wt[part[v]], (unsigned long long)(vwgt ? vwgt[v] : 1));
+}
+
+__global__ __launch_bounds__(kBlock) void k_cut(const int32_t* __restrict__ xadj, const int32_t* __restrict__ adjncy,
+                                                const int32_t* __restrict__ adjwgt, const int32_t* __restrict__ part,
+                                                int32_t n, int64_t* out)
+{
+    int64_t acc = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = part[v];
+        for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e)
+            if (part[adjncy[e]] != p) acc += adjwgt ? adjwgt[e] : 1;
+    }
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd((unsigned long long*)out, (unsigned long long)acc);
+}
+
+constexpr int64_t kLdsBudget = 64 * 1024;
+
+}  // namespace
+
+int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, std::vector<int32_t>& first,
+                          std::vector<int32_t>& fcount, int64_t lk, uint64_t seed)
+{
+    const int32_t n = g.n;
+    const int32_t nb = (int32_t)first.size();
+    std::vector<uint8_t> split(nb);
+    bool any = false;
+    for (int32_t bb = 0; bb < nb; ++bb) {
+        split[bb] = fcount[bb] >= 2;
+        any |= split[bb];
+    }
+    if (!any) return 0;
+    DBuf<uint8_t> side(c, (size_t)n);
+    int32_t calls = 0;
+    if (n > 0) {
+        DBuf<int32_t> bstart(c, (size_t)nb + 1), bdeg(c, (size_t)nb);
+        c.zero(bstart.p, sizeof(int32_t) * ((size_t)nb + 1));
+        c.zero(bdeg.p, sizeof(int32_t) * (size_t)nb);
+        DBuf<uint32_t> key(c, n), verts(c, n), k2(c, n), v2(c, n);
+        hipLaunchKernelGGL(k_block_count, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, g.xadj, n, bstart.p,
+                           bdeg.p, key.p, verts.p);
+        KMP_LAUNCH_CHECK();
+        radix_sort_pairs(c, key.p, verts.p, k2.p, v2.p, n, bits_for((uint64_t)(nb - 1)));
+        scan_excl_i32(c, bstart.p, bstart.p, nb, bstart.p + nb);
+        DBuf<int32_t> local(c, (size_t)n);
+        hipLaunchKernelGGL(k_local_ids, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, verts.p, part, bstart.p, n,
+                           local.p);
+        KMP_LAUNCH_CHECK();
+        std::vector<int32_t> hb(nb + 1), hd(nb);
+        c.read(hb.data(), bstart.p, sizeof(int32_t) * (nb + 1));
+        c.read(hd.data(), bdeg.p, sizeof(int32_t) * nb);
+        std::vector<GGGJob> lds_jobs, glob_jobs;
+        int64_t lds_max = 0, glob_total = 0;
+        for (int32_t bb = 0; bb < nb; ++bb) {
+            if (!split[bb]) continue;
+            GGGJob jb;
+            jb.b = bb;
+            jb.first = first[bb];
+            jb.f = fcount[bb];
+            jb.nverts = hb[bb + 1] - hb[bb];
+            jb.dsum = hd[bb];
+            jb.pad = 0;
+            jb.scratch = 0;
+            const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum);
+            if (bytes <= kLdsBudget) {
+                lds_jobs.push_back(jb);
+                if (bytes > lds_max) lds_max = bytes;
+            } else {
+                jb.scratch = glob_total;
+                glob_total += bytes;
+                glob_jobs.push_back(jb);
+            }
+            ++calls;
+        }
+        GGGArgs a;
+        a.xadj = g.xadj;
+        a.adjncy = g.adjncy;
+        a.vwgt = g.vwgt;
+        a.adjwgt = g.adjwgt;
+        a.part = part;
+        a.verts = verts.p;
+        a.bstart = bstart.p;
+        a.local = local.p;
+        a.lk = lk;
+        a.hpre = hash_prefix(seed, {TAG_GGG, (uint32_t)level});
+        a.side = side.p;
+        a.scratch = nullptr;
+        if (!lds_jobs.empty()) {
+            DBuf<GGGJob> jobs(c, lds_jobs.size());
+            c.write(jobs.p, lds_jobs.data(), sizeof(GGGJob) * lds_jobs.size());
+            a.jobs = jobs.p;
+            hipLaunchKernelGGL(k_ggg<true>, dim3((unsigned)lds_jobs.size()), dim3(GGG_THREADS), (size_t)lds_max,
+                               c.stream, a);
+            KMP_LAUNCH_CHECK();
+            c.sync();
+        }
+        if (!glob_jobs.empty()) {
+            DBuf<GGGJob> jobs(c, glob_jobs.size());
+            c.write(jobs.p, glob_jobs.data(), sizeof(GGGJob) * glob_jobs.size());
+            DBuf<char> scratch(c, (size_t)glob_total);
+            a.jobs = jobs.p;
+            a.scratch = scratch.p;
+            hipLaunchKernelGGL(k_ggg<false>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream, a);
+            KMP_LAUNCH_CHECK();
+            c.sync();
+        }
+    }
+    // renumber blocks in ascending `first`
+    std::vector<int32_t> newidx(nb), nf, nc;
+    nf.reserve(2 * nb);
+    nc.reserve(2 * nb);
+    for (int32_t bb = 0; bb < nb; ++bb) {
+        newidx[bb] = (int32_t)nf.size();
+        if (split[bb]) {
+            const int32_t f0 = fcount[bb] / 2;
+            nf.push_back(first[bb]);
+            nc.push_back(f0);
+            nf.push_back(first[bb] + f0);
+            nc.push_back(fcount[bb] - f0);
+        } else {
+            nf.push_back(first[bb]);
+            nc.push_back(fcount[bb]);
+        }
+    }
+    if (n > 0) {
+        DBuf<int32_t> dnew(c, (size_t)nb);
+        DBuf<uint8_t> dsplit(c, (size_t)nb);
+        c.write(dnew.p, newidx.data(), sizeof(int32_t) * nb);
+        c.write(dsplit.p, split.data(), (size_t)nb);
+        hipLaunchKernelGGL(k_relabel, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, side.p, dnew.p, dsplit.p,
+                           n);
+        KMP_LAUNCH_CHECK();
+        c.sync();
+    }
+    first.swap(nf);
+    fcount.swap(nc);
+    return calls;
+}
+
+void project(Ctx& c, const int32_t* coarse_part, const int32_t* map, int32_t* fine_part, int32_t n)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_project, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, coarse_part, map, fine_part, n);
+    KMP_LAUNCH_CHECK();
+}
+
+void block_weights(Ctx& c, const DGraph& g, const int32_t* part, int32_t nb, int64_t* wt)
+{
+    c.zero(wt, sizeof(int64_t) * (size_t)nb);
+    if (g.n <= 0) return;
+    hipLaunchKernelGGL(k_block_weights, dim3(grid_for(g.n)), dim3(kBlock), 0, c.stream, part, g.vwgt, g.n, wt);
+    KMP_LAUNCH_CHECK();
+}
+
+int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part)
+{
+    int64_t* ctr = c.counters();
+    c.zero(ctr + 9, sizeof(int64_t));
+    if (g.n > 0) {
+        hipLaunchKernelGGL(k_cut, dim3(grid_for(g.n, kBlock, 4096)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
+                           g.adjwgt, part, g.n, ctr + 9);
+        KMP_LAUNCH_CHECK();
+    }
+    return c.read1(ctr + 9) / 2;
+}
+
+}  // namespace kmp

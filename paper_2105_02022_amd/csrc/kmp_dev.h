@@ -1,0 +1,297 @@
+// Internal header of libkmp (gfx950).  Device helpers, the per-call context
+// and declarations of the building blocks shared by the .hip translation
+// units.  Nothing here is part of the public ABI (include/kmp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/kmp.h"
+
+namespace kmp {
+
+// ---------------------------------------------------------------- constants
+// Result-affecting constants of the deterministic reading (changing any of
+// them changes partitions).
+constexpr int kC = 160;              // contraction limit C (Alg. 1)
+constexpr int kRounds = 5;           // LP rounds (Sec. 5.1, Sec. 5.3)
+constexpr int kSub = 4;              // sub-rounds per LP round
+constexpr int kSeeds = 8;            // GGG runs per block (Alg. 2 "R bipartitions")
+constexpr int64_t kPPM = 1000000;    // epsilon fixed point
+constexpr int kMaxLevels = 64;
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kPhi = 0x9E3779B9u;
+enum : uint32_t { TAG_SUB = 1, TAG_CL = 2, TAG_REF = 3, TAG_BAL = 4, TAG_GGG = 5 };
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& what) : std::runtime_error(what), code(c) {}
+};
+
+#define KMP_HIP(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) {                                                                    \
+            if (e_ == hipErrorOutOfMemory) throw ::kmp::Error(KMP_ENOMEM, hipGetErrorString(e_)); \
+            throw ::kmp::Error(KMP_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));      \
+        }                                                                                          \
+    } while (0)
+
+#define KMP_LAUNCH_CHECK() KMP_HIP(hipGetLastError())
+
+// ---------------------------------------------------------------- hashing
+// Tie-break hash of the deterministic reading: fmix32 is MurmurHash3's 32-bit
+// finaliser; H(seed; a_1..a_t) folds fmix32 over the arguments, argument i
+// offset by i * 0x9E3779B9.  The host computes the fold over the leading,
+// call-invariant arguments ("prefix"); kernels finish it with hash_step.
+__host__ __device__ inline uint32_t fmix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+__host__ __device__ inline uint32_t hash_step(uint32_t h, uint32_t a, uint32_t i)
+{
+    return fmix32(h ^ (a + i * kPhi));
+}
+
+inline uint32_t hash_prefix(uint64_t seed, std::initializer_list<uint32_t> args)
+{
+    uint32_t h = fmix32((uint32_t)seed) ^ fmix32((uint32_t)(seed >> 32) + kPhi);
+    uint32_t i = 1;
+    for (uint32_t a : args) h = hash_step(h, a, i++);
+    return h;
+}
+
+// ---------------------------------------------------------------- device misc
+__device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
+
+__device__ inline int lane_id() { return __lane_id(); }
+
+template <typename T>
+__device__ inline T shfl_xor(T v, int mask, int width = 64)
+{
+    return __shfl_xor(v, mask, width);
+}
+
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask, int width = 64)
+{
+    uint32_t lo = __shfl_xor((uint32_t)v, mask, width);
+    uint32_t hi = __shfl_xor((uint32_t)(v >> 32), mask, width);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// LDS slot for a key in a table of 2^bits slots (multiplicative hashing).
+__device__ inline uint32_t slot_of(uint32_t key, int bits)
+{
+    return (key * 0x9E3779B1u) >> (32 - bits);
+}
+
+constexpr int kBlock = 256;
+
+inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 1u << 20)
+{
+    int64_t g = (items + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > (int64_t)cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------- context
+// One per library call: the stream, a pinned host buffer for scalar
+// read-backs and stream-ordered device allocations released on exit.
+class Ctx {
+  public:
+    explicit Ctx(hipStream_t s);
+    ~Ctx();
+    Ctx(const Ctx&) = delete;
+    Ctx& operator=(const Ctx&) = delete;
+
+    hipStream_t stream;
+
+    void* alloc_bytes(size_t bytes);
+    template <typename T>
+    T* alloc(size_t count)
+    {
+        return static_cast<T*>(alloc_bytes(sizeof(T) * (count > 0 ? count : 1)));
+    }
+    void free(void* p);
+    void zero(void* p, size_t bytes);
+    void sync();
+
+    // Copy `bytes` device bytes into pinned host memory and wait.
+    void read(void* host, const void* dev, size_t bytes);
+    void write(void* dev, const void* host, size_t bytes);
+    template <typename T>
+    T read1(const T* dev)
+    {
+        T v;
+        read(&v, dev, sizeof(T));
+        return v;
+    }
+    // A small device scratch of 64 x int64 counters (zeroed on request).
+    int64_t* counters();
+    void zero_counters();
+
+  private:
+    std::vector<void*> live_;
+    void* pinned_ = nullptr;
+    size_t pinned_bytes_ = 0;
+    int64_t* counters_ = nullptr;
+    void ensure_pinned(size_t bytes);
+};
+
+// RAII device buffer bound to a context.
+template <typename T>
+struct DBuf {
+    Ctx* ctx = nullptr;
+    T* p = nullptr;
+    size_t n = 0;
+    DBuf() = default;
+    DBuf(Ctx& c, size_t count) : ctx(&c), p(c.alloc<T>(count)), n(count) {}
+    DBuf(DBuf&& o) noexcept : ctx(o.ctx), p(o.p), n(o.n) { o.p = nullptr; }
+    DBuf& operator=(DBuf&& o) noexcept
+    {
+        reset();
+        ctx = o.ctx;
+        p = o.p;
+        n = o.n;
+        o.p = nullptr;
+        return *this;
+    }
+    ~DBuf() { reset(); }
+    void reset()
+    {
+        if (p && ctx) ctx->free(p);
+        p = nullptr;
+        n = 0;
+    }
+    T* get() const { return p; }
+    operator T*() const { return p; }
+};
+
+// ---------------------------------------------------------------- graph view
+struct DGraph {
+    int32_t n = 0;
+    int64_t m = 0;
+    const int32_t* xadj = nullptr;
+    const int32_t* adjncy = nullptr;
+    const int32_t* vwgt = nullptr;    // NULL = unit
+    const int32_t* adjwgt = nullptr;  // NULL = unit
+};
+
+// Owned coarse graph.
+struct OwnedGraph {
+    DBuf<int32_t> xadj, adjncy, vwgt, adjwgt;
+    DGraph view(int32_t n, int64_t m) const
+    {
+        DGraph g;
+        g.n = n;
+        g.m = m;
+        g.xadj = xadj.p;
+        g.adjncy = adjncy.p;
+        g.vwgt = vwgt.p;
+        g.adjwgt = adjwgt.p;
+        return g;
+    }
+};
+
+// ---------------------------------------------------------------- primitives
+// prims.hip
+// Exclusive prefix sum of n int32 values into out (may alias in); returns the
+// total through *total_dev (device, may be NULL).
+void scan_excl_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev);
+// Inclusive prefix sum of n int64 values.
+void scan_incl_i64(Ctx& c, const int64_t* in, int64_t* out, int64_t n);
+// Inclusive max-scan of n int32 values.
+void scan_incl_max_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n);
+// Stable LSD radix sort of (key, value) pairs by key, keys < 2^key_bits.
+// Results end in keys/vals (the alt buffers are scratch of the same size).
+void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                      int key_bits);
+void fill_i32(Ctx& c, int32_t* p, int32_t v, int64_t n);
+void fill_u8(Ctx& c, uint8_t* p, uint8_t v, int64_t n);
+void fill_i64(Ctx& c, int64_t* p, int64_t v, int64_t n);
+inline void set_i64(Ctx& c, int64_t* p, int64_t v) { fill_i64(c, p, v, 1); }
+void iota_i32(Ctx& c, int32_t* p, int64_t n);
+// Sum of node weights (int64) into *out_dev.
+void node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n, int64_t* out_dev);
+// Sum of edge weights (int64) into *out_dev.
+void edge_weight_sum(Ctx& c, const int32_t* adjwgt, int64_t m, int64_t* out_dev);
+int bits_for(uint64_t max_value);
+
+// ---------------------------------------------------------------- LP (lp.hip)
+struct LPState {
+    int32_t* label;     // [n]
+    int64_t* wt;        // [nlab]
+    int32_t nlab;
+    const int64_t* cap_vec;  // [nlab] or NULL
+    int64_t cap_scalar;
+    uint32_t* fav;      // [n] or NULL (clustering only)
+    uint32_t tag;
+};
+
+struct LPStats {
+    int64_t moves[kRounds] = {0, 0, 0, 0, 0};
+    int32_t rounds = 0;
+    int64_t rated_edges = 0;
+};
+
+// Per-level schedule: nodes grouped by (sub-round class, degree tier).
+struct LPSchedule {
+    DBuf<int32_t> order;              // node ids grouped by (tier, class)
+    int32_t off[kSub][4] = {};        // [class][tier] start of the segment in `order`
+    int32_t cnt[kSub][4] = {};        // [class][tier] segment size
+    int32_t hub_start = 0;            // hubs of all classes are contiguous from here
+    DBuf<int64_t> hub_slot_off;       // per hub: start of its global hash table
+    int64_t hub_slots_total = 0;
+    int64_t rated_deg[kSub] = {};     // total degree per class
+};
+
+void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched);
+LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st);
+int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32_t s, uint64_t seed,
+                    const LPSchedule& sched, LPState& st, const uint8_t* active, uint8_t* moved);
+
+// Balance-mode rating (same kernels): for every node of an overloaded block,
+// the adjacent non-overloaded block with the largest connection that fits
+// (bal_t, -1 if none) and d = conn(target) - conn(own block) (bal_d; -conn(own)
+// when there is no target).
+void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int32_t round,
+                      const LPSchedule& sched, const int32_t* part, const int64_t* wt, const int64_t* cap,
+                      const uint8_t* over, int32_t* bal_t, int64_t* bal_d);
+
+// ---------------------------------------------------------------- coarsening (coarsen.hip)
+int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav);
+int32_t count_nonempty(Ctx& c, const int64_t* cw, int32_t n);
+// Contract; returns coarse sizes; allocates the coarse graph in `out`.
+void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
+              int32_t& cn, int64_t& cm);
+
+// ---------------------------------------------------------------- IP (ip.hip)
+// One bipartitionBlocks round; first/fcount host vectors are updated.
+int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, std::vector<int32_t>& first,
+                          std::vector<int32_t>& fcount, int64_t lk, uint64_t seed);
+void project(Ctx& c, const int32_t* coarse_part, const int32_t* map, int32_t* fine_part, int32_t n);
+void block_weights(Ctx& c, const DGraph& g, const int32_t* part, int32_t nb, int64_t* wt);
+int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part);
+
+// ---------------------------------------------------------------- balance (balance.hip)
+int32_t balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, int32_t* part,
+                int64_t* wt, int32_t nb, const int64_t* cap);
+
+// ---------------------------------------------------------------- validation (kmp.hip)
+int validate_graph(Ctx& c, const DGraph& g);
+
+}  // namespace kmp

@@ -1,0 +1,432 @@
+// Data-parallel building blocks: per-call context, prefix scans, stable LSD
+// radix sort (wave-ballot ranking, 64-wide wavefronts), fills, reductions.
+#include "kmp_dev.h"
+
+namespace kmp {
+
+// ================================================================ context
+Ctx::Ctx(hipStream_t s) : stream(s) {}
+
+Ctx::~Ctx()
+{
+    for (void* p : live_) (void)hipFreeAsync(p, stream);
+    if (counters_) (void)hipFreeAsync(counters_, stream);
+    (void)hipStreamSynchronize(stream);
+    if (pinned_) (void)hipHostFree(pinned_);
+}
+
+void* Ctx::alloc_bytes(size_t bytes)
+{
+    void* p = nullptr;
+    if (bytes == 0) bytes = 8;
+    hipError_t e = hipMallocAsync(&p, bytes, stream);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        throw Error(KMP_ENOMEM, "device workspace allocation failed (" + std::to_string(bytes) + " bytes)");
+    }
+    live_.push_back(p);
+    return p;
+}
+
+void Ctx::free(void* p)
+{
+    if (!p) return;
+    for (size_t i = live_.size(); i-- > 0;)
+        if (live_[i] == p) {
+            live_[i] = live_.back();
+            live_.pop_back();
+            KMP_HIP(hipFreeAsync(p, stream));
+            return;
+        }
+}
+
+void Ctx::zero(void* p, size_t bytes)
+{
+    if (bytes) KMP_HIP(hipMemsetAsync(p, 0, bytes, stream));
+}
+
+void Ctx::sync() { KMP_HIP(hipStreamSynchronize(stream)); }
+
+void Ctx::ensure_pinned(size_t bytes)
+{
+    if (pinned_bytes_ >= bytes) return;
+    if (pinned_) KMP_HIP(hipHostFree(pinned_));
+    pinned_ = nullptr;
+    size_t sz = bytes < 4096 ? 4096 : bytes;
+    KMP_HIP(hipHostMalloc(&pinned_, sz, hipHostMallocDefault));
+    pinned_bytes_ = sz;
+}
+
+void Ctx::read(void* host, const void* dev, size_t bytes)
+{
+    if (!bytes) return;
+    ensure_pinned(bytes);
+    KMP_HIP(hipMemcpyAsync(pinned_, dev, bytes, hipMemcpyDeviceToHost, stream));
+    KMP_HIP(hipStreamSynchronize(stream));
+    memcpy(host, pinned_, bytes);
+}
+
+void Ctx::write(void* dev, const void* host, size_t bytes)
+{
+    if (!bytes) return;
+    // the staging buffer is reused: wait for any earlier copy out of it
+    KMP_HIP(hipStreamSynchronize(stream));
+    ensure_pinned(bytes);
+    memcpy(pinned_, host, bytes);
+    KMP_HIP(hipMemcpyAsync(dev, pinned_, bytes, hipMemcpyHostToDevice, stream));
+    KMP_HIP(hipStreamSynchronize(stream));
+}
+
+int64_t* Ctx::counters()
+{
+    if (!counters_) {
+        void* p = nullptr;
+        if (hipMallocAsync(&p, 64 * sizeof(int64_t), stream) != hipSuccess)
+            throw Error(KMP_ENOMEM, "counter allocation failed");
+        counters_ = static_cast<int64_t*>(p);
+        zero_counters();
+    }
+    return counters_;
+}
+
+void Ctx::zero_counters() { zero(counters(), 64 * sizeof(int64_t)); }
+
+int bits_for(uint64_t max_value)
+{
+    int b = 0;
+    while (b < 64 && (max_value >> b) != 0) ++b;
+    return b;
+}
+
+// ================================================================ scans
+namespace {
+
+constexpr int SCAN_IT = 8;
+constexpr int SCAN_TILE = kBlock * SCAN_IT;
+
+struct OpAdd {
+    template <typename T>
+    __device__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+    template <typename T>
+    __device__ T operator()(T a, T b) const { return a > b ? a : b; }
+};
+
+template <typename T>
+__device__ inline T shfl_up_t(T v, unsigned d) { return __shfl_up(v, d, 64); }
+
+// Inclusive scan of one value per thread across a 256-thread block.
+template <typename T, typename Op>
+__device__ T block_scan_incl(T v, Op op, T* lds_waves)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T y = shfl_up_t(v, d);
+        if (lane >= d) v = op(y, v);
+    }
+    if (lane == 63) lds_waves[w] = v;
+    __syncthreads();
+    if (w > 0) {
+        T pre = lds_waves[0];
+        for (int i = 1; i < w; ++i) pre = op(pre, lds_waves[i]);
+        v = op(pre, v);
+    }
+    __syncthreads();
+    return v;
+}
+
+// Per-tile reduction.
+template <typename T, typename Op>
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in, int64_t n, T* __restrict__ partial,
+                                                        T identity)
+{
+    __shared__ T lds[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IT;
+    Op op;
+    T acc = identity;
+#pragma unroll
+    for (int j = 0; j < SCAN_IT; ++j)
+        if (base + j < n) acc = op(acc, in[base + j]);
+    T tot = block_scan_incl<T, Op>(acc, op, lds);
+    if (threadIdx.x == kBlock - 1) partial[blockIdx.x] = tot;
+}
+
+// Scan tiles; tile t starts from carry partial_excl[t] (or identity when NULL).
+// A single block may also process all tiles sequentially (`tiles_per_block`).
+template <typename T, typename Op>
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const T* in, T* out, int64_t n, const T* __restrict__ partial_excl,
+                                                       int tiles_per_block, bool inclusive, T identity,
+                                                       T* total_out)
+{
+    __shared__ T lds[4];
+    __shared__ T carry_s;
+    Op op;
+    T carry = identity;
+    if (partial_excl) carry = partial_excl[blockIdx.x];
+    for (int t = 0; t < tiles_per_block; ++t) {
+        const int64_t tile = (int64_t)blockIdx.x * tiles_per_block + t;
+        const int64_t base = tile * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IT;
+        if (tile * SCAN_TILE >= n) break;
+        T v[SCAN_IT];
+        T acc = identity;
+#pragma unroll
+        for (int j = 0; j < SCAN_IT; ++j) {
+            v[j] = base + j < n ? in[base + j] : identity;
+            acc = op(acc, v[j]);
+        }
+        T incl = block_scan_incl<T, Op>(acc, op, lds);
+        // exclusive prefix of this thread = incl - own (recompute via op: prefix before thread)
+        T run = op(carry, incl);
+        // derive this thread's exclusive start: shift inclusive totals by one thread
+        T prev = __shfl_up(incl, 1, 64);
+        __shared__ T wave_last[4];
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        if (lane == 63) wave_last[w] = incl;
+        __syncthreads();
+        T start;
+        if (lane > 0) start = op(carry, prev);
+        else if (w > 0) start = op(carry, wave_last[w - 1]);
+        else start = carry;
+#pragma unroll
+        for (int j = 0; j < SCAN_IT; ++j) {
+            if (base + j < n) {
+                T nx = op(start, v[j]);
+                out[base + j] = inclusive ? nx : start;
+                start = nx;
+            } else {
+                start = op(start, v[j]);
+            }
+        }
+        if (threadIdx.x == kBlock - 1) carry_s = run;
+        __syncthreads();
+        carry = carry_s;
+        __syncthreads();
+    }
+    if (total_out && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total_out = carry;
+}
+
+template <typename T>
+__global__ void k_set_one(T* p, T v)
+{
+    if (threadIdx.x == 0) *p = v;
+}
+
+template <typename T, typename Op>
+void scan_impl(Ctx& c, const T* in, T* out, int64_t n, bool inclusive, T identity, T* total_dev)
+{
+    if (n <= 0) {
+        if (total_dev) {
+            hipLaunchKernelGGL(k_set_one<T>, dim3(1), dim3(64), 0, c.stream, total_dev, identity);
+            KMP_LAUNCH_CHECK();
+        }
+        return;
+    }
+    const int64_t tiles = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (tiles <= 8) {
+        hipLaunchKernelGGL((k_scan_tiles<T, Op>), dim3(1), dim3(kBlock), 0, c.stream, in, out, n, (const T*)nullptr,
+                           (int)tiles, inclusive, identity, total_dev);
+        KMP_LAUNCH_CHECK();
+        return;
+    }
+    DBuf<T> part(c, (size_t)tiles);
+    hipLaunchKernelGGL((k_scan_reduce<T, Op>), dim3((unsigned)tiles), dim3(kBlock), 0, c.stream, in, n, part.p,
+                       identity);
+    KMP_LAUNCH_CHECK();
+    // exclusive scan of the tile partials (recursive)
+    scan_impl<T, Op>(c, part.p, part.p, tiles, false, identity, nullptr);
+    hipLaunchKernelGGL((k_scan_tiles<T, Op>), dim3((unsigned)tiles), dim3(kBlock), 0, c.stream, in, out, n, part.p, 1,
+                       inclusive, identity, total_dev);
+    KMP_LAUNCH_CHECK();
+}
+
+}  // namespace
+
+void scan_excl_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n, int32_t* total_dev)
+{
+    scan_impl<int32_t, OpAdd>(c, in, out, n, false, 0, total_dev);
+}
+
+void scan_incl_i64(Ctx& c, const int64_t* in, int64_t* out, int64_t n)
+{
+    scan_impl<int64_t, OpAdd>(c, in, out, n, true, (int64_t)0, nullptr);
+}
+
+void scan_incl_max_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n)
+{
+    scan_impl<int32_t, OpMax>(c, in, out, n, true, INT32_MIN, nullptr);
+}
+
+// ================================================================ radix sort
+namespace {
+
+constexpr int RS_IT = 8;
+constexpr int RS_TILE = kBlock * RS_IT;
+
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t* __restrict__ keys, int64_t n, int shift,
+                                                    int32_t* __restrict__ hist, int nblk)
+{
+    __shared__ uint32_t cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll
+    for (int j = 0; j < RS_IT; ++j) {
+        int64_t idx = base + (int64_t)j * kBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = (int32_t)cnt[threadIdx.x];
+}
+
+// Stable scatter: element order inside a tile is (slot j, thread) = index order.
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+                                                       uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
+                                                       int64_t n, int shift, const int32_t* __restrict__ offs,
+                                                       int nblk)
+{
+    __shared__ uint32_t s_off[256];
+    __shared__ uint32_t s_cnt[4][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    s_off[tid] = (uint32_t)offs[(int64_t)tid * nblk + blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    const uint64_t lanes_below = (1ull << lane) - 1ull;
+    for (int j = 0; j < RS_IT; ++j) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) s_cnt[i][tid] = 0;
+        __syncthreads();
+        const int64_t idx = base + (int64_t)j * kBlock + tid;
+        const bool valid = idx < n;
+        uint32_t k = valid ? kin[idx] : 0u;
+        uint32_t v = valid ? vin[idx] : 0u;
+        uint32_t d = (k >> shift) & 255u;
+        uint64_t peers = ballot64(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bal = ballot64(bit);
+            peers &= bit ? bal : ~bal;
+        }
+        const int rank = __popcll(peers & lanes_below);
+        if (valid && rank == 0) s_cnt[w][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = s_off[d] + (uint32_t)rank;
+            for (int ww = 0; ww < w; ++ww) pos += s_cnt[ww][d];
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+        __syncthreads();
+        s_off[tid] += s_cnt[0][tid] + s_cnt[1][tid] + s_cnt[2][tid] + s_cnt[3][tid];
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                      int key_bits)
+{
+    if (n <= 1 || key_bits <= 0) return;
+    const int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
+    DBuf<int32_t> hist(c, (size_t)nblk * 256);
+    uint32_t *ks = keys, *vs = vals, *kd = keys_alt, *vd = vals_alt;
+    for (int shift = 0; shift < key_bits; shift += 8) {
+        hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(kBlock), 0, c.stream, ks, n, shift, hist.p, nblk);
+        KMP_LAUNCH_CHECK();
+        scan_excl_i32(c, hist.p, hist.p, (int64_t)nblk * 256, nullptr);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(kBlock), 0, c.stream, ks, vs, kd, vd, n, shift, hist.p,
+                           nblk);
+        KMP_LAUNCH_CHECK();
+        std::swap(ks, kd);
+        std::swap(vs, vd);
+    }
+    if (ks != keys) {
+        KMP_HIP(hipMemcpyAsync(keys, ks, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+        KMP_HIP(hipMemcpyAsync(vals, vs, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+    }
+}
+
+// ================================================================ fills, sums
+namespace {
+
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+__global__ void k_iota(int32_t* p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_i32(const int32_t* __restrict__ p, int64_t n, int64_t* out)
+{
+    int64_t acc = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc += p[i];
+    for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+    if ((threadIdx.x & 63) == 0 && acc) atomicAdd((unsigned long long*)out, (unsigned long long)acc);
+}
+
+}  // namespace
+
+void fill_i32(Ctx& c, int32_t* p, int32_t v, int64_t n)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<int32_t>, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, c.stream, p, v, n);
+    KMP_LAUNCH_CHECK();
+}
+void fill_u8(Ctx& c, uint8_t* p, uint8_t v, int64_t n)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<uint8_t>, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, c.stream, p, v, n);
+    KMP_LAUNCH_CHECK();
+}
+void fill_i64(Ctx& c, int64_t* p, int64_t v, int64_t n)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_fill<int64_t>, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, c.stream, p, v, n);
+    KMP_LAUNCH_CHECK();
+}
+void iota_i32(Ctx& c, int32_t* p, int64_t n)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_iota, dim3(grid_for(n, kBlock, 4096)), dim3(kBlock), 0, c.stream, p, n);
+    KMP_LAUNCH_CHECK();
+}
+
+void node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n, int64_t* out_dev)
+{
+    c.zero(out_dev, sizeof(int64_t));
+    if (!vwgt) {
+        int64_t v = n;
+        KMP_HIP(hipMemcpyAsync(out_dev, &v, sizeof(v), hipMemcpyHostToDevice, c.stream));
+        KMP_HIP(hipStreamSynchronize(c.stream));
+        return;
+    }
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_sum_i32, dim3(grid_for(n, kBlock, 2048)), dim3(kBlock), 0, c.stream, vwgt, (int64_t)n,
+                       out_dev);
+    KMP_LAUNCH_CHECK();
+}
+
+void edge_weight_sum(Ctx& c, const int32_t* adjwgt, int64_t m, int64_t* out_dev)
+{
+    c.zero(out_dev, sizeof(int64_t));
+    if (!adjwgt) {
+        int64_t v = m;
+        KMP_HIP(hipMemcpyAsync(out_dev, &v, sizeof(v), hipMemcpyHostToDevice, c.stream));
+        KMP_HIP(hipStreamSynchronize(c.stream));
+        return;
+    }
+    if (m <= 0) return;
+    hipLaunchKernelGGL(k_sum_i32, dim3(grid_for(m, kBlock, 2048)), dim3(kBlock), 0, c.stream, adjwgt, m, out_dev);
+    KMP_LAUNCH_CHECK();
+}
+
+}  // namespace kmp

@@ -1,0 +1,49 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+entry point declared in include/kmp.h, and reports argument errors."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2105_02022_amd as kmp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "kmp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kmp_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_present():
+    assert os.path.exists(kmp.LIB_PATH), "build libkmp.so first (__graft_entry__.build())"
+
+
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(kmp.LIB_PATH)
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(kmp.SIGNATURES)
+
+
+def test_strerror_and_version():
+    assert kmp.kmp_version().count(".") == 2
+    for code in (0, 1, -1, -2, -3, -4, -5):
+        assert kmp.kmp_strerror(code)
+    assert "unknown" in kmp.kmp_strerror(42)
+
+
+def test_argument_errors_before_any_device_work():
+    lib = kmp.library()
+    # k < 1, n < 0, negative / NaN eps: rejected before touching memory
+    assert lib.kmp_partition(None, None, None, None, 10, 0, 0, 0.03, 1, None, None) == kmp.KMP_EINVAL
+    assert lib.kmp_partition(None, None, None, None, -1, 0, 2, 0.03, 1, None, None) == kmp.KMP_EINVAL
+    assert lib.kmp_partition(None, None, None, None, 10, 0, 2, -1.0, 1, None, None) == kmp.KMP_EINVAL
+    assert lib.kmp_partition(None, None, None, None, 10, 0, 2, float("nan"), 1, None, None) == kmp.KMP_EINVAL
+    assert lib.kmp_partition(None, None, None, None, 10, 0, 2, 0.03, 1, None, None) == kmp.KMP_EINVAL  # NULL xadj
+    # empty graph: OK without device work
+    assert lib.kmp_partition(None, None, None, None, 0, 0, 4, 0.03, 1, None, None) == kmp.KMP_OK

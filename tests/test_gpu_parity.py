@@ -1,0 +1,301 @@
+"""GPU parity: every step of the HIP path through the C ABI against the CPU
+oracle on the same seeded inputs.  All arithmetic is integer, so the bar is
+bit-exact equality (labels, weights, favoured clusters, coarse CSR, block
+tables, partitions, cuts)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_02022_amd import gen
+from tests.helpers import csr_from_dense, node_w, two_cliques
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kmp():
+    import paper_2105_02022_amd as k
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    k.library()  # raises if libkmp.so is missing: no fallback
+    return k
+
+
+def dev(g):
+    import paper_2105_02022_amd as k
+    return k.to_device(g, "cuda")
+
+
+def t32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
+def t64(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int64)).cuda()
+
+
+def graphs_small():
+    return [
+        ("grid16", gen.grid(16, 16)),
+        ("rand_w", gen.random_graph(600, 6.0, 11, max_vw=5, max_ew=7)),
+        ("rand_iso", gen.random_graph(800, 3.0, 12, isolated_frac=0.2)),
+        ("rgg3000", gen.rgg(3000, 8.0, 5)),
+    ]
+
+
+# ------------------------------------------------------------------ LP sub-round
+@pytest.mark.parametrize("case", range(6))
+def test_lp_subround(kmp, case):
+    rng = np.random.default_rng(400 + case)
+    name, g = graphs_small()[case % 4]
+    n = g.n
+    c = node_w(g)
+    clustering = case < 3
+    if clustering:
+        nlab, tag = n, oracle.T_CL
+        label = rng.integers(0, n, n).astype(np.int32)
+        cap_scalar, capv = int(rng.integers(3, 20)), None
+    else:
+        nlab, tag = 6, oracle.T_REF
+        label = rng.integers(0, nlab, n).astype(np.int32)
+    wt = np.bincount(label, weights=c, minlength=nlab).astype(np.int64)
+    if not clustering:
+        capv = wt + rng.integers(0, 30, nlab)
+        cap_scalar = 0
+    active = (rng.random(n) < 0.7).astype(np.uint8) if case % 2 else None
+    level, r, s = int(rng.integers(0, 4)), int(rng.integers(0, 5)), int(rng.integers(0, 4))
+    seed = int(rng.integers(1, 2**40))
+    say(f"[lp_subround] {name} case={case} clustering={clustering} level={level} r={r} s={s}")
+    capo = capv if capv is not None else np.full(nlab, cap_scalar, np.int64)
+    fav0 = np.full(n, 0xFFFFFFFF, np.uint32)
+    exp_label, exp_wt, exp_fav, exp_moved, exp_nm = oracle.lp_subround(
+        g, level, r, s, tag, seed, label, wt, capv=capo, active=active, fav=fav0)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    d_label, d_wt = t32(label), t64(wt)
+    d_fav = t32(fav0.view(np.int32))
+    d_moved = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    d_act = None if active is None else torch.from_numpy(active).cuda()
+    d_cap = None if capv is None else t64(capv)
+    nm = kmp.kmp_lp_subround(xadj, adjncy, vwgt, adjwgt, level, r, s, tag, seed, d_label, d_wt, d_cap, cap_scalar,
+                             d_act, d_fav, d_moved)
+    assert nm == exp_nm
+    assert np.array_equal(d_label.cpu().numpy(), exp_label)
+    assert np.array_equal(d_wt.cpu().numpy(), exp_wt)
+    assert np.array_equal(d_moved.cpu().numpy(), exp_moved)
+    assert np.array_equal(d_fav.cpu().numpy().view(np.uint32), exp_fav)
+
+
+# ------------------------------------------------------------------ LP clustering
+@pytest.mark.parametrize("gi", range(4))
+def test_lp_cluster(kmp, gi):
+    name, g = graphs_small()[gi]
+    U, level, seed = 17, 1, 77
+    say(f"[lp_cluster] {name} n={g.n} m={g.m}")
+    exp_label, exp_cw, exp_fav, exp_moves, exp_rounds = oracle.lp_cluster(g, level, U, seed)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rounds, label, cw, fav, moves = kmp.kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, level, U, seed)
+    assert rounds == exp_rounds
+    assert moves == list(exp_moves)
+    assert np.array_equal(label.cpu().numpy(), exp_label)
+    assert np.array_equal(cw.cpu().numpy(), exp_cw)
+    assert np.array_equal(fav.cpu().numpy().view(np.uint32), exp_fav)
+
+
+def test_two_hop(kmp):
+    for name, g in graphs_small():
+        U, level, seed = 9, 0, 5
+        label, cw, fav, _, _ = oracle.lp_cluster(g, level, U, seed)
+        say(f"[two_hop] {name}")
+        exp_label, exp_cw, exp_merged = oracle.two_hop(g, U, label, cw, fav)
+        xadj, adjncy, vwgt, adjwgt = dev(g)
+        d_label, d_cw, d_fav = t32(label), t64(cw), t32(fav.view(np.int32))
+        merged = kmp.kmp_two_hop(xadj, adjncy, vwgt, adjwgt, U, d_label, d_cw, d_fav)
+        assert merged == exp_merged
+        assert np.array_equal(d_label.cpu().numpy(), exp_label)
+        assert np.array_equal(d_cw.cpu().numpy(), exp_cw)
+
+
+def _check_contract(kmp, g, label, name):
+    say(f"[contract] {name} n={g.n} m={g.m}")
+    exp_map, exp_cg = oracle.contract(g, label)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rc, mp, cx, ca, cv, cw = kmp.kmp_contract(xadj, adjncy, vwgt, adjwgt, t32(label))
+    assert rc == 0
+    assert np.array_equal(mp.cpu().numpy(), exp_map)
+    assert np.array_equal(cx.cpu().numpy(), exp_cg.xadj)
+    assert np.array_equal(ca.cpu().numpy(), exp_cg.adjncy)
+    assert np.array_equal(cv.cpu().numpy(), exp_cg.vwgt)
+    assert np.array_equal(cw.cpu().numpy(), exp_cg.adjwgt)
+
+
+def test_contract_small(kmp):
+    for name, g in graphs_small():
+        label, cw, fav, _, _ = oracle.lp_cluster(g, 0, 13, 3)
+        _check_contract(kmp, g, label, name)
+
+
+def test_contract_heavy_rows(kmp):
+    # clusters whose members carry > 4096 entries take the sort-reduce path;
+    # random labels into few clusters make every row heavy
+    rng = np.random.default_rng(3)
+    g = gen.rgg(40000, 8.0, 9)
+    _check_contract(kmp, g, rng.integers(0, 60, g.n).astype(np.int32), "rgg40000/60 clusters")
+    _check_contract(kmp, g, rng.integers(0, 4000, g.n).astype(np.int32), "rgg40000/4000 clusters")
+    gw = gen.random_graph(30000, 10.0, 4, max_vw=3, max_ew=9)
+    _check_contract(kmp, gw, rng.integers(0, 25, gw.n).astype(np.int32), "weighted/25 clusters")
+
+
+def test_hub_rating(kmp):
+    # star-heavy RMAT: degrees above 2048 use the global-hash tier
+    g = gen.rmat(14, 8 << 14, seed=3)
+    assert g.maxdeg > 2048
+    U, level, seed = 6, 0, 9
+    say(f"[lp_cluster hubs] rmat14 maxdeg={g.maxdeg}")
+    exp_label, exp_cw, exp_fav, exp_moves, exp_rounds = oracle.lp_cluster(g, level, U, seed)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rounds, label, cw, fav, moves = kmp.kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, level, U, seed)
+    assert rounds == exp_rounds and moves == list(exp_moves)
+    assert np.array_equal(label.cpu().numpy(), exp_label)
+    assert np.array_equal(fav.cpu().numpy().view(np.uint32), exp_fav)
+
+
+# ------------------------------------------------------------------ bipartition, balance, refine
+@pytest.mark.parametrize("k", [2, 5, 16])
+def test_bipartition_round(kmp, k):
+    g = gen.rgg(4000, 8.0, 21)
+    lk = oracle.lk(g.n, k, 0.03)
+    part = np.zeros(g.n, np.int32)
+    first, fcount = [0], [k]
+    d_part = t32(part)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    for rnd in range(4):
+        if max(fcount) < 2:
+            break
+        say(f"[bipartition_round] k={k} round={rnd} blocks={len(first)}")
+        part, ef, efc = oracle.bipartition_round(g, 0, part, first, fcount, lk, 3)
+        rc, first, fcount = kmp.kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, 0, d_part, first, fcount, lk, 3)
+        assert rc == 0
+        assert first == list(ef) and fcount == list(efc)
+        assert np.array_equal(d_part.cpu().numpy(), part)
+
+
+def test_bipartition_weighted_and_degenerate(kmp):
+    cases = [
+        ("weighted", gen.random_graph(900, 5.0, 31, max_vw=20, max_ew=5), 7),
+        ("cliques", csr_from_dense(two_cliques(40)), 2),
+        ("tiny", gen.grid(1, 3), 8),
+        ("isolated", gen.random_graph(500, 1.0, 32, isolated_frac=0.6), 4),
+    ]
+    for name, g, k in cases:
+        lk = oracle.lk(int(node_w(g).sum()), k, 0.03)
+        part = np.zeros(g.n, np.int32)
+        first, fcount = [0], [k]
+        d_part = t32(part)
+        xadj, adjncy, vwgt, adjwgt = dev(g)
+        while max(fcount) >= 2:
+            say(f"[bipartition] {name} blocks={len(first)}")
+            part, ef, efc = oracle.bipartition_round(g, 2, part, first, fcount, lk, 8)
+            rc, first, fcount = kmp.kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, 2, d_part, first, fcount,
+                                                          lk, 8)
+            assert rc == 0 and first == list(ef) and fcount == list(efc)
+            assert np.array_equal(d_part.cpu().numpy(), part)
+
+
+@pytest.mark.parametrize("case", range(4))
+def test_balance(kmp, case):
+    rng = np.random.default_rng(600 + case)
+    n, nb = 3000, 6
+    g = gen.random_graph(n, 5.0, 600 + case, max_vw=1 if case < 2 else 6, max_ew=4)
+    c = node_w(g)
+    part = rng.integers(0, nb, n).astype(np.int32)
+    part[: n // 3] = case % nb
+    wt = np.bincount(part, weights=c, minlength=nb).astype(np.int64)
+    cap = np.full(nb, int(c.sum()) // nb + 3, np.int64)
+    say(f"[balance] case={case} overload={int((wt - cap).clip(0).sum())}")
+    exp_part, exp_wt, exp_rounds = oracle.balance(g, 1, 44, part, wt, cap)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    d_part, d_wt = t32(part), t64(wt)
+    rounds = kmp.kmp_balance(xadj, adjncy, vwgt, adjwgt, 1, 44, d_part, d_wt, t64(cap))
+    assert rounds == exp_rounds
+    assert np.array_equal(d_part.cpu().numpy(), exp_part)
+    assert np.array_equal(d_wt.cpu().numpy(), exp_wt)
+
+
+@pytest.mark.parametrize("gi", range(4))
+def test_lp_refine(kmp, gi):
+    name, g = graphs_small()[gi]
+    rng = np.random.default_rng(700 + gi)
+    nb = 5
+    part = rng.integers(0, nb, g.n).astype(np.int32)
+    c = node_w(g)
+    wt = np.bincount(part, weights=c, minlength=nb).astype(np.int64)
+    cap = wt + 10
+    say(f"[lp_refine] {name}")
+    exp_part, exp_wt, _, exp_moves, exp_rounds = oracle.lp_generic(g, 2, oracle.T_REF, 6, part, wt, capv=cap)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    d_part, d_wt = t32(part), t64(wt)
+    rounds, moves = kmp.kmp_lp_refine(xadj, adjncy, vwgt, adjwgt, 2, 6, d_part, d_wt, t64(cap))
+    assert rounds == exp_rounds and moves == list(exp_moves)
+    assert np.array_equal(d_part.cpu().numpy(), exp_part)
+    assert np.array_equal(d_wt.cpu().numpy(), exp_wt)
+
+
+# ------------------------------------------------------------------ whole pipeline
+def _e2e(kmp, g, k, eps, seed, name):
+    say(f"[partition] {name} n={g.n} m={g.m} k={k} eps={eps} seed={seed}")
+    ref = oracle.partition(g, k, eps, seed)
+    rc, part, stats = kmp.partition(g, k, eps, seed)
+    assert rc == ref.status
+    assert np.array_equal(part, ref.part)
+    assert stats["cut"] == ref.stats["cut"]
+    assert stats["levels"] == ref.stats["levels"]
+    assert stats["level_n"] == ref.stats["level_n"]
+    assert stats["max_block_weight"] == ref.stats["max_block_weight"]
+    return stats
+
+
+@pytest.mark.parametrize("name,k,eps,seed", [
+    ("grid128", 8, 0.03, 1), ("grid64", 3, 0.0, 2), ("rgg20000", 12, 0.03, 4), ("rgg20000", 64, 0.03, 1),
+    ("rand_w", 7, 0.05, 9), ("rand_iso", 16, 0.03, 3), ("cliques", 2, 0.03, 1), ("grid16", 1, 0.03, 1),
+    ("tiny", 8, 0.03, 1),
+])
+def test_partition_small(kmp, name, k, eps, seed):
+    g = {
+        "grid128": lambda: gen.grid(128, 128), "grid64": lambda: gen.grid(64, 64),
+        "rgg20000": lambda: gen.rgg(20000, 8.0, 2),
+        "rand_w": lambda: gen.random_graph(5000, 5.0, 7, max_vw=4, max_ew=6),
+        "rand_iso": lambda: gen.random_graph(8000, 3.0, 8, isolated_frac=0.3),
+        "cliques": lambda: csr_from_dense(two_cliques(200)), "grid16": lambda: gen.grid(16, 16),
+        "tiny": lambda: gen.grid(2, 3),
+    }[name]()
+    _e2e(kmp, g, k, eps, seed, name)
+
+
+def test_partition_validation_errors(kmp):
+    g = gen.grid(8, 8)
+    bad = gen.Graph(g.xadj.copy(), g.adjncy.copy())
+    bad.adjncy[3] = 40   # breaks symmetry
+    xadj, adjncy, _, _ = dev(bad)
+    rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, None, None, 4, 0.03, 1, validate=True)
+    assert rc == kmp.KMP_EGRAPH
+    xadj, adjncy, _, _ = dev(g)
+    rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, None, None, 4, 0.03, 1, validate=True)
+    assert rc == kmp.KMP_OK
+    big = torch.full((g.n,), 2**28, dtype=torch.int32, device="cuda")
+    rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, big, None, 4, 0.03, 1)
+    assert rc == kmp.KMP_EOVERFLOW
+
+
+def test_partition_rgg_full(kmp):
+    """RGG 2^20, k = 64: the benchmark workload, end to end."""
+    g = gen.workload("rgg20")
+    stats = _e2e(kmp, g, 64, 0.03, 1, "rgg20 (n=2^20)")
+    say(f"  cut={stats['cut']} ms={stats['ms_total']:.1f}")
