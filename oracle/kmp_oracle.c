@@ -989,7 +989,11 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
     if (st) st->lk = lk;
     if (k == 1) {
         memset(out_part, 0, sizeof(int32_t) * (size_t)n);
-        if (st) st->max_block_weight = cV;
+        if (st) {
+            st->max_block_weight = cV;
+            st->level_n[0] = n;
+            st->level_m[0] = xadj[n];
+        }
         return cV > lk ? OR_IMBALANCED : OR_OK;
     }
 
