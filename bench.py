@@ -1,0 +1,159 @@
+#!/usr/bin/env python3
+"""Benchmark: deep multilevel graph partitioning hot path on one MI355X.
+
+A step is one whole kmp_partition call (LP clustering, two-hop, contraction,
+batched GGG, projection, balancing, LP refinement over all levels) on the
+random-geometric-graph workload: n = 2^20 points in the unit square, radius
+for average degree 8 (8,382,500 directed entries), k = 64, eps = 0.03,
+seed 1.  The CSR is resident in HBM before timing starts.
+
+value = (directed entries rated by LP + directed entries contracted) per
+second of whole-step wall time ("LP+contraction edges/s").
+
+roofline: the dominant kernel class (most summed HIP-event time among the
+classes with algorithmic byte counts), its algorithmic bytes per launch over
+its average launch duration, against 8 TB/s.  traffic: HBM bytes per launch
+from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if present.
+
+cpu_baseline: the CPU oracle (single thread) on the same workload.
+"""
+import argparse
+import json
+import os
+import re
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LP+contraction edges/s; batched graphs/s vs serial; p99 latency (exact cut)"
+HBM_PEAK_GBS = 8000.0
+WORKLOAD = dict(name="rgg20", k=64, eps=0.03, seed=1)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-runs", type=int, default=3)
+    return ap.parse_args()
+
+
+def traffic_from_profiles(kernel_symbol):
+    """HBM bytes per launch of `kernel_symbol` from the committed rocprofv3 PMC summary."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        e = d.get("kernels", {}).get(kernel_symbol)
+        if not e or d.get("source_hash") != _source_hash():
+            return None
+        return e["hbm_bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2105_02022_amd", "csrc"))):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(ROOT, "paper_2105_02022_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+KERNEL_OF_CLASS = {
+    "rate_t0": "k_rate_lds<8, 5>", "rate_t1": "k_rate_lds<64, 8>", "rate_t2": "k_rate_lds<256, 12>",
+    "rate_hub": "k_rate_hub", "contract_rows": "k_contract_rows",
+}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2105_02022_amd as kmp
+    from paper_2105_02022_amd import gen
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    kmp.library()
+    g = gen.workload(WORKLOAD["name"])
+    k, eps, seed = WORKLOAD["k"], WORKLOAD["eps"], WORKLOAD["seed"]
+    xadj, adjncy, vwgt, adjwgt = kmp.to_device(g, "cuda:0")
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    print(f"# graph n={g.n} m={g.m} maxdeg={g.maxdeg}; warmup {args.warmup}, steps {args.steps}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True)
+        assert rc == 0, kmp.kmp_strerror(rc)
+    torch.cuda.synchronize()
+    stats = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True)
+        stats.append(st)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step = elapsed * 1e3 / args.steps
+    print(f"# timed {args.steps} steps: {ms_step:.2f} ms/step", file=sys.stderr, flush=True)
+    st0 = stats[0]
+    edges = st0["lp_rated_edges"] + st0["contracted_edges"]
+    value = edges / (ms_step / 1e3)
+    part = out.cpu().numpy()
+    # roofline: dominant class with algorithmic bytes
+    classes = kmp.PROF_CLASSES
+    ms_c = {c: sum(s["prof"][c]["ms"] for s in stats) for c in classes}
+    by_c = {c: sum(s["prof"][c]["bytes"] for s in stats) for c in classes}
+    ln_c = {c: sum(s["prof"][c]["launches"] for s in stats) for c in classes}
+    dom = max((c for c in classes if by_c[c] > 0), key=lambda c: ms_c[c])
+    avg_ms = ms_c[dom] / ln_c[dom]
+    bytes_per_launch = by_c[dom] / ln_c[dom]
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles(KERNEL_OF_CLASS.get(dom, dom))
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": KERNEL_OF_CLASS.get(dom, dom), "class": dom,
+                "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": ln_c[dom] / args.steps,
+                "algorithmic_bytes_per_launch": round(bytes_per_launch),
+                "class_ms_per_step": {c: round(ms_c[c] / args.steps, 3) for c in classes if ln_c[c]}}
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        times = []
+        for r in range(args.cpu_runs):
+            t = time.perf_counter()
+            ref = oracle.partition(g, k, eps, seed, validate_input=False)
+            times.append(time.perf_counter() - t)
+            print(f"# oracle run {r}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
+        t_med = statistics.median(times)
+        parity = bool(np.array_equal(ref.part, part)) and ref.stats["cut"] == st0["cut"]
+        cpu = {"value": round(edges / t_med), "unit": "edges/s", "cores": 1, "kind": "oracle",
+               "sample": f"whole partition of the same workload, median of {args.cpu_runs} runs "
+                         f"({t_med:.2f} s each), single-threaded C oracle"}
+    line = {
+        "metric": METRIC, "value": round(value), "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+        "config": {"workload": "rgg20: 2D random geometric graph, n=2^20, avg degree 8, k=64, eps=0.03, seed 1",
+                   "n": g.n, "m_directed": g.m, "k": k, "eps": eps, "seed": seed, "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu,
+        "e2e_edges_per_s": round(g.m / (ms_step / 1e3)),
+        "lp_plus_contraction_edges_per_step": edges, "cut": st0["cut"], "levels": st0["levels"],
+        "parity_with_oracle": parity,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

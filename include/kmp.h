@@ -56,8 +56,30 @@ extern "C" {
 /* Options for kmp_partition_ex (all fields zero = defaults). */
 typedef struct kmp_options {
     int32_t validate;       /* 1: check the CSR on the device first (KMP_EGRAPH on failure) */
-    int32_t reserved[7];
+    int32_t profile;        /* 1: time kernel classes with HIP events (fills kmp_stats.prof_*) */
+    int32_t reserved[6];
 } kmp_options;
+
+/* Kernel classes reported when kmp_options.profile is set. */
+#define KMP_PROF_CLASSES 16
+enum {
+    KMP_PROF_RATE_T0 = 0,      /* LP rating, degree <= 16 (8 lanes per node)          */
+    KMP_PROF_RATE_T1 = 1,      /* LP rating, degree <= 128 (a wavefront per node)     */
+    KMP_PROF_RATE_T2 = 2,      /* LP rating, degree <= 2048 (a workgroup per node)    */
+    KMP_PROF_RATE_HUB = 3,     /* LP rating, hubs (global hash)                       */
+    KMP_PROF_ADMIT = 4,        /* admission of uncontended targets                    */
+    KMP_PROF_APPLY = 5,        /* apply admitted moves                                */
+    KMP_PROF_CONTENDED = 6,    /* sort + prefix admission of contended targets        */
+    KMP_PROF_ACTIVE = 7,       /* next-round active set                               */
+    KMP_PROF_CONTRACT_ROWS = 8,/* contraction: LDS aggregation of coarse rows         */
+    KMP_PROF_CONTRACT = 9,     /* contraction: relabel, bucketing, heavy rows, copy   */
+    KMP_PROF_TWO_HOP = 10,
+    KMP_PROF_GGG = 11,         /* batched greedy graph growing                        */
+    KMP_PROF_BALANCE = 12,
+    KMP_PROF_PROJECT = 13,     /* projection, relabel, block weights                  */
+    KMP_PROF_SCHEDULE = 14,    /* per-level sub-round class / degree-tier schedule    */
+    KMP_PROF_OTHER = 15
+};
 
 /* Statistics filled by kmp_partition_ex (host memory, may be NULL). */
 typedef struct kmp_stats {
@@ -79,6 +101,16 @@ typedef struct kmp_stats {
     double ms_contract;
     double ms_initial;                      /* bipartitioning (extraction + GGG)          */
     double ms_refine;                       /* balance + refinement + projection          */
+    /* filled when kmp_options.profile is set: per kernel class, the number of
+     * launches, the summed HIP-event duration of those launches and, for the
+     * LP rating and contraction-row classes, their algorithmic bytes (bytes
+     * the algorithm must move: rating 25 B per rated node + 12 B per rated
+     * directed entry, 8 B when edge weights are unit; contraction rows 12 B
+     * per fine entry + 12 B per member node + 8 B per coarse entry + 16 B per
+     * coarse row). */
+    int64_t prof_launches[KMP_PROF_CLASSES];
+    double prof_ms[KMP_PROF_CLASSES];
+    int64_t prof_bytes[KMP_PROF_CLASSES];
 } kmp_stats;
 
 /*

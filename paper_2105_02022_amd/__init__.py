@@ -22,8 +22,12 @@ KMP_OK, KMP_IMBALANCED, KMP_EINVAL, KMP_EGRAPH, KMP_EOVERFLOW, KMP_ENOMEM, KMP_E
 MAX_LEVELS = 64
 
 
+PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "contended", "active",
+                "contract_rows", "contract", "two_hop", "ggg", "balance", "project", "schedule", "other"]
+
+
 class KmpOptions(ctypes.Structure):
-    _fields_ = [("validate", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class KmpStats(ctypes.Structure):
@@ -34,7 +38,9 @@ class KmpStats(ctypes.Structure):
                 ("lp_refine_moves", ctypes.c_int64), ("lp_rated_edges", ctypes.c_int64),
                 ("contracted_edges", ctypes.c_int64), ("ms_total", ctypes.c_double),
                 ("ms_coarsen_lp", ctypes.c_double), ("ms_contract", ctypes.c_double),
-                ("ms_initial", ctypes.c_double), ("ms_refine", ctypes.c_double)]
+                ("ms_initial", ctypes.c_double), ("ms_refine", ctypes.c_double),
+                ("prof_launches", ctypes.c_int64 * 16), ("prof_ms", ctypes.c_double * 16),
+                ("prof_bytes", ctypes.c_int64 * 16)]
 
 
 _vp = ctypes.c_void_p
@@ -125,7 +131,7 @@ def kmp_partition(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, see
 
 
 def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
-                     stream=None, validate: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+                     stream=None, validate: bool = False, profile: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict)."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
@@ -134,14 +140,19 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
         out = torch.empty(max(n, 0), dtype=torch.int32, device=xadj.device)
     opt = KmpOptions()
     opt.validate = int(validate)
+    opt.profile = int(profile)
     st = KmpStats()
     rc = library().kmp_partition_ex(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
                                     epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream), ctypes.byref(opt),
                                     ctypes.byref(st))
     L = st.levels
-    stats = {f[0]: getattr(st, f[0]) for f in KmpStats._fields_ if not f[0].startswith("reserved")}
+    stats = {f[0]: getattr(st, f[0]) for f in KmpStats._fields_
+             if not f[0].startswith(("reserved", "prof_", "level_"))}
     stats["level_n"] = list(st.level_n[:L + 1])
     stats["level_m"] = list(st.level_m[:L + 1])
+    if profile:
+        stats["prof"] = {name: {"launches": st.prof_launches[i], "ms": st.prof_ms[i], "bytes": st.prof_bytes[i]}
+                         for i, name in enumerate(PROF_CLASSES)}
     return rc, out, stats
 
 

@@ -17,12 +17,17 @@ namespace {
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 
 // ---------------------------------------------------------------- two-hop
-__global__ void k_count_nonempty(const int64_t* __restrict__ cw, int32_t n, int64_t* out)
+__global__ __launch_bounds__(kBlock) void k_count_nonempty(const int64_t* __restrict__ cw, int32_t n, int64_t* out)
 {
+    __shared__ int32_t cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool f = i < n && cw[i] > 0;
     uint64_t b = ballot64(f);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long*)out, (unsigned long long)__popcll(b));
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&cnt, (int32_t)__popcll(b));
+    __syncthreads();
+    if (threadIdx.x == 0 && cnt) atomicAdd((unsigned long long*)out, (unsigned long long)cnt);
 }
 
 __global__ void k_singleton_flags(const int32_t* __restrict__ label, const int64_t* __restrict__ cw,
@@ -118,16 +123,23 @@ __global__ void k_place_members(const int32_t* __restrict__ map, int32_t n, cons
 
 constexpr int R_T0 = 64, R_T1 = 512, R_T2 = 4096;
 
-__global__ void k_row_tiers(const int32_t* __restrict__ dsum, int32_t nc, uint32_t* __restrict__ key,
-                            uint32_t* __restrict__ val, int32_t* __restrict__ cnt4)
+__global__ __launch_bounds__(kBlock) void k_row_tiers(const int32_t* __restrict__ dsum, int32_t nc,
+                                                      uint32_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                      int32_t* __restrict__ cnt4)
 {
+    __shared__ int32_t h[4];
+    if (threadIdx.x < 4) h[threadIdx.x] = 0;
+    __syncthreads();
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= nc) return;
-    int32_t d = dsum[c];
-    uint32_t t = d <= R_T0 ? 0 : d <= R_T1 ? 1 : d <= R_T2 ? 2 : 3;
-    key[c] = t;
-    val[c] = (uint32_t)c;
-    atomicAdd(&cnt4[t], 1);
+    if (c < nc) {
+        int32_t d = dsum[c];
+        uint32_t t = d <= R_T0 ? 0 : d <= R_T1 ? 1 : d <= R_T2 ? 2 : 3;
+        key[c] = t;
+        val[c] = (uint32_t)c;
+        atomicAdd(&h[t], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 4 && h[threadIdx.x]) atomicAdd(&cnt4[threadIdx.x], h[threadIdx.x]);
 }
 
 struct RowArgs {
@@ -141,6 +153,7 @@ struct RowArgs {
     int32_t* tmp_adj;
     int32_t* tmp_w;
     int32_t* cdeg;
+    int64_t* bytes_ctr;
 };
 
 // G lanes per coarse row, 2^HB LDS slots per row.
@@ -155,6 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
     const int tid = threadIdx.x, grp = tid / G, gl = tid % G;
     uint32_t* keys = s_keys + grp * HS;
     uint32_t* vals = s_vals + grp * HS;
+    int64_t bytes = 0;
     for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
         const int64_t i = base + grp;
         const int32_t row = i < count ? rows[i] : -1;
@@ -222,10 +236,17 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
                 a.tmp_adj[o + j] = (int32_t)keys[j];
                 a.tmp_w[o + j] = (int32_t)vals[j];
             }
-            if (gl == 0) a.cdeg[row] = (int32_t)u;
+            if (gl == 0) {
+                a.cdeg[row] = (int32_t)u;
+                const int64_t fine = a.dstart[row + 1] - a.dstart[row];
+                const int64_t mem = a.mstart[row + 1] - a.mstart[row];
+                bytes += 12 * fine + 12 * mem + 8 * (int64_t)u + 16;
+            }
         }
         __syncthreads();
     }
+    for (int d = 32; d > 0; d >>= 1) bytes += __shfl_xor(bytes, d, 64);
+    if ((tid & 63) == 0 && bytes) atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)bytes);
 }
 
 // ---- heavy rows: expand, sort by (row, neighbour), reduce
@@ -437,9 +458,11 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     a.tmp_adj = tmp_adj.p;
     a.tmp_w = tmp_w.p;
     a.cdeg = cdeg.p;
+    a.bytes_ctr = c.counters() + kBytesSlot + KMP_PROF_CONTRACT_ROWS;
     int32_t off = 0;
     if (tc[0] > 0) {
         constexpr int G = 16;
+        ProfScope ps(c, KMP_PROF_CONTRACT_ROWS);
         hipLaunchKernelGGL((k_contract_rows<G, 7>), dim3(grid_for(tc[0], kBlock / G, 65536)), dim3(kBlock), 0,
                            c.stream, a, rows + off, tc[0]);
         KMP_LAUNCH_CHECK();
@@ -447,12 +470,14 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     off += tc[0];
     if (tc[1] > 0) {
         constexpr int G = 64;
+        ProfScope ps(c, KMP_PROF_CONTRACT_ROWS);
         hipLaunchKernelGGL((k_contract_rows<G, 10>), dim3(grid_for(tc[1], kBlock / G, 65536)), dim3(kBlock), 0,
                            c.stream, a, rows + off, tc[1]);
         KMP_LAUNCH_CHECK();
     }
     off += tc[1];
     if (tc[2] > 0) {
+        ProfScope ps(c, KMP_PROF_CONTRACT_ROWS);
         hipLaunchKernelGGL((k_contract_rows<256, 13>), dim3(grid_for(tc[2], 1, 65536)), dim3(kBlock), 0, c.stream, a,
                            rows + off, tc[2]);
         KMP_LAUNCH_CHECK();

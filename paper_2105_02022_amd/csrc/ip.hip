@@ -18,17 +18,40 @@ namespace kmp {
 namespace {
 
 // ---------------------------------------------------------------- extraction
-__global__ void k_block_count(const int32_t* __restrict__ part, const int32_t* __restrict__ xadj, int32_t n,
-                              int32_t* __restrict__ bcnt, int32_t* __restrict__ bdeg, uint32_t* __restrict__ key,
-                              uint32_t* __restrict__ val)
+// Privatised in LDS when the block count is small (heavy contention otherwise).
+constexpr int kPrivBlocks = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_block_count(const int32_t* __restrict__ part,
+                                                        const int32_t* __restrict__ xadj, int32_t n, int32_t nb,
+                                                        int32_t* __restrict__ bcnt, int32_t* __restrict__ bdeg,
+                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ val)
 {
+    __shared__ int32_t hc[kPrivBlocks], hd[kPrivBlocks];
+    const bool priv = nb <= kPrivBlocks;
+    if (priv)
+        for (int i = threadIdx.x; i < nb; i += kBlock) hc[i] = hd[i] = 0;
+    __syncthreads();
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int32_t b = part[v];
-    atomicAdd(&bcnt[b], 1);
-    atomicAdd(&bdeg[b], xadj[v + 1] - xadj[v]);
-    key[v] = (uint32_t)b;
-    val[v] = (uint32_t)v;
+    if (v < n) {
+        int32_t b = part[v];
+        int32_t d = xadj[v + 1] - xadj[v];
+        if (priv) {
+            atomicAdd(&hc[b], 1);
+            atomicAdd(&hd[b], d);
+        } else {
+            atomicAdd(&bcnt[b], 1);
+            atomicAdd(&bdeg[b], d);
+        }
+        key[v] = (uint32_t)b;
+        val[v] = (uint32_t)v;
+    }
+    __syncthreads();
+    if (priv)
+        for (int i = threadIdx.x; i < nb; i += kBlock)
+            if (hc[i]) {
+                atomicAdd(&bcnt[i], hc[i]);
+                atomicAdd(&bdeg[i], hd[i]);
+            }
 }
 
 __global__ void k_local_ids(const uint32_t* __restrict__ verts, const int32_t* __restrict__ part,
@@ -206,7 +229,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
         for (int32_t e = lxadj[pick] + lane; e < lxadj[pick + 1]; e += 64) {
             const int32_t u = ladj[e];
             if (st[u] == 2) continue;
-            gain[u] += 2 * lw[e];
+            gain[u] = (int32_t)((int64_t)gain[u] + 2 * (int64_t)lw[e]);
             st[u] = 1;
         }
         fence_wave<LDS>();
@@ -256,11 +279,25 @@ __global__ void k_project(const int32_t* __restrict__ cpart, const int32_t* __re
     if (v < n) fpart[v] = cpart[map[v]];
 }
 
-__global__ void k_block_weights(const int32_t* __restrict__ part, const int32_t* __restrict__ vwgt, int32_t n,
-                                int64_t* __restrict__ wt)
+__global__ __launch_bounds__(kBlock) void k_block_weights(const int32_t* __restrict__ part,
+                                                          const int32_t* __restrict__ vwgt, int32_t n, int32_t nb,
+                                                          int64_t* __restrict__ wt)
 {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) atomicAdd((unsigned long long*)&wt[part[v]], (unsigned long long)(vwgt ? vwgt[v] : 1));
+    __shared__ unsigned long long h[kPrivBlocks];
+    const bool priv = nb <= kPrivBlocks;
+    if (priv)
+        for (int i = threadIdx.x; i < nb; i += kBlock) h[i] = 0;
+    __syncthreads();
+    // grid-stride: a few thousand blocks cover any n, each flushes nb counters once
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long c = (unsigned long long)(vwgt ? vwgt[v] : 1);
+        if (priv) atomicAdd(&h[part[v]], c);
+        else atomicAdd((unsigned long long*)&wt[part[v]], c);
+    }
+    __syncthreads();
+    if (priv)
+        for (int i = threadIdx.x; i < nb; i += kBlock)
+            if (h[i]) atomicAdd((unsigned long long*)&wt[i], h[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cut(const int32_t* __restrict__ xadj, const int32_t* __restrict__ adjncy,
@@ -300,8 +337,8 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         c.zero(bstart.p, sizeof(int32_t) * ((size_t)nb + 1));
         c.zero(bdeg.p, sizeof(int32_t) * (size_t)nb);
         DBuf<uint32_t> key(c, n), verts(c, n), k2(c, n), v2(c, n);
-        hipLaunchKernelGGL(k_block_count, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, g.xadj, n, bstart.p,
-                           bdeg.p, key.p, verts.p);
+        hipLaunchKernelGGL(k_block_count, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, g.xadj, n, nb,
+                           bstart.p, bdeg.p, key.p, verts.p);
         KMP_LAUNCH_CHECK();
         radix_sort_pairs(c, key.p, verts.p, k2.p, v2.p, n, bits_for((uint64_t)(nb - 1)));
         scan_excl_i32(c, bstart.p, bstart.p, nb, bstart.p + nb);
@@ -352,6 +389,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             DBuf<GGGJob> jobs(c, lds_jobs.size());
             c.write(jobs.p, lds_jobs.data(), sizeof(GGGJob) * lds_jobs.size());
             a.jobs = jobs.p;
+            ProfScope ps(c, KMP_PROF_GGG);
             hipLaunchKernelGGL(k_ggg<true>, dim3((unsigned)lds_jobs.size()), dim3(GGG_THREADS), (size_t)lds_max,
                                c.stream, a);
             KMP_LAUNCH_CHECK();
@@ -363,6 +401,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             DBuf<char> scratch(c, (size_t)glob_total);
             a.jobs = jobs.p;
             a.scratch = scratch.p;
+            ProfScope ps(c, KMP_PROF_GGG);
             hipLaunchKernelGGL(k_ggg<false>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream, a);
             KMP_LAUNCH_CHECK();
             c.sync();
@@ -411,7 +450,8 @@ void block_weights(Ctx& c, const DGraph& g, const int32_t* part, int32_t nb, int
 {
     c.zero(wt, sizeof(int64_t) * (size_t)nb);
     if (g.n <= 0) return;
-    hipLaunchKernelGGL(k_block_weights, dim3(grid_for(g.n)), dim3(kBlock), 0, c.stream, part, g.vwgt, g.n, wt);
+    hipLaunchKernelGGL(k_block_weights, dim3(grid_for(g.n, kBlock, 1024)), dim3(kBlock), 0, c.stream, part, g.vwgt,
+                       g.n, nb, wt);
     KMP_LAUNCH_CHECK();
 }
 

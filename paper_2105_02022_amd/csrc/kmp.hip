@@ -201,6 +201,11 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
     auto t_start = clk::now();
     init_pool_once();
     Ctx c(stream);
+    std::unique_ptr<Prof> prof;
+    if (opt && opt->profile) {
+        prof.reset(new Prof());
+        c.prof = prof.get();
+    }
     const int64_t cV = prepare(c, g0);
     if (opt && opt->validate) {
         int rc = validate_graph(c, g0);
@@ -341,7 +346,11 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
         st->ms_refine = ms_ref;
     }
     c.sync();
-    if (st) st->ms_total = ms_since(t_start);
+    if (st) {
+        st->ms_total = ms_since(t_start);
+        if (prof) c.prof_collect(st->prof_launches, st->prof_ms, st->prof_bytes);
+    }
+    c.prof = nullptr;
     return maxw > lk ? KMP_IMBALANCED : KMP_OK;
 }
 

@@ -108,6 +108,20 @@ inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 1
     return (unsigned)g;
 }
 
+// ---------------------------------------------------------------- profiling
+// HIP events around launches of selected kernel classes (when enabled).
+struct Prof {
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    ~Prof();
+};
+
+// Counter slots (Ctx::counters) receiving algorithmic bytes per class.
+constexpr int kBytesSlot = 16;
+
 // ---------------------------------------------------------------- context
 // One per library call: the stream, a pinned host buffer for scalar
 // read-backs and stream-ordered device allocations released on exit.
@@ -144,12 +158,26 @@ class Ctx {
     int64_t* counters();
     void zero_counters();
 
+    Prof* prof = nullptr;  // profiling enabled when non-null
+    int prof_begin(int cls);
+    void prof_end(int idx);
+    // Resolve the recorded events into per-class launches / ms and read the
+    // per-class algorithmic byte counters.
+    void prof_collect(int64_t* launches, double* ms, int64_t* bytes);
+
   private:
     std::vector<void*> live_;
     void* pinned_ = nullptr;
     size_t pinned_bytes_ = 0;
     int64_t* counters_ = nullptr;
     void ensure_pinned(size_t bytes);
+};
+
+struct ProfScope {
+    Ctx& c;
+    int idx;
+    ProfScope(Ctx& ctx, int cls) : c(ctx), idx(ctx.prof_begin(cls)) {}
+    ~ProfScope() { c.prof_end(idx); }
 };
 
 // RAII device buffer bound to a context.

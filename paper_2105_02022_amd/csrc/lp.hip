@@ -40,18 +40,25 @@ __device__ inline int32_t seg_index(const Seg4& s, int64_t i)
 }
 
 // ---------------------------------------------------------------- schedule
-__global__ void k_sched_keys(const int32_t* __restrict__ xadj, int32_t n, uint32_t hsub, uint32_t* __restrict__ key,
-                             uint32_t* __restrict__ val, int32_t* __restrict__ cnt16)
+__global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict__ xadj, int32_t n, uint32_t hsub,
+                                                       uint32_t* __restrict__ key, uint32_t* __restrict__ val,
+                                                       int32_t* __restrict__ cnt16)
 {
+    __shared__ int32_t h[16];
+    if (threadIdx.x < 16) h[threadIdx.x] = 0;
+    __syncthreads();
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    uint32_t s = hash_step(hsub, (uint32_t)v, 3) % kSub;
-    int32_t d = xadj[v + 1] - xadj[v];
-    uint32_t t = d <= T0_DEG ? 0 : d <= T1_DEG ? 1 : d <= T2_DEG ? 2 : 3;
-    uint32_t k = t * kSub + s;
-    key[v] = k;
-    val[v] = (uint32_t)v;
-    atomicAdd(&cnt16[k], 1);
+    if (v < n) {
+        uint32_t s = hash_step(hsub, (uint32_t)v, 3) % kSub;
+        int32_t d = xadj[v + 1] - xadj[v];
+        uint32_t t = d <= T0_DEG ? 0 : d <= T1_DEG ? 1 : d <= T2_DEG ? 2 : 3;
+        uint32_t k = t * kSub + s;
+        key[v] = k;
+        val[v] = (uint32_t)v;
+        atomicAdd(&h[k], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x < 16 && h[threadIdx.x]) atomicAdd(&cnt16[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void k_hub_slots(const int32_t* __restrict__ xadj, const int32_t* __restrict__ hubs, int32_t nh,
@@ -107,6 +114,7 @@ struct RateArgs {
     uint32_t* fav;          // [n] or NULL
     uint32_t* demand;       // [nlab]
     int64_t* counters;      // [0] rated edges
+    int64_t* bytes_ctr;     // algorithmic bytes of this launch's class
     // hubs (tier 3)
     uint32_t* hub_keys;
     uint32_t* hub_vals;
@@ -185,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
     const int grp = tid / G, gl = tid % G;
     uint32_t* keys = s_keys + grp * HS;
     uint32_t* vals = s_vals + grp * HS;
-    int64_t edges = 0;
+    int64_t edges = 0, nodes = 0;
     for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
         const int64_t i = base + grp;
         int32_t v = -1;
@@ -207,7 +215,10 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
                 uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
                 lds_insert(keys, vals, HB, K, w);
             }
-            if (gl == 0) edges += e1 - e0;
+            if (gl == 0) {
+                edges += e1 - e0;
+                nodes += 1;
+            }
         }
         __syncthreads();
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
@@ -248,9 +259,18 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
         if (v >= 0 && gl == 0) write_result(a, v, fav, adm, rown, cv);
         __syncthreads();
     }
-    // rated edge statistic (per wave leader)
-    for (int d = 32; d > 0; d >>= 1) edges += __shfl_xor(edges, d, 64);
-    if ((tid & 63) == 0 && edges) atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)edges);
+    // rated edge statistic and algorithmic bytes (per wave leader)
+    for (int d = 32; d > 0; d >>= 1) {
+        edges += __shfl_xor(edges, d, 64);
+        nodes += __shfl_xor(nodes, d, 64);
+    }
+    if ((tid & 63) == 0 && edges) {
+        atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)edges);
+        const int64_t bytes = 25 * nodes + (a.adjwgt ? 12 : 8) * edges;
+        atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)bytes);
+    } else if ((tid & 63) == 0 && nodes) {
+        atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)(25 * nodes));
+    }
 }
 
 // One workgroup per hub node, hash table in global memory.
@@ -318,6 +338,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a, const int32_t* 
             }
             write_result(a, v, fav, adm, rown, cv);
             atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)d);
+            atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)(25 + (a.adjwgt ? 12 : 8) * d));
         }
         __syncthreads();
     }
@@ -452,6 +473,7 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
     DBuf<int32_t> cnt(c, 16);
     c.zero(cnt.p, 16 * sizeof(int32_t));
     const uint32_t hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
+    ProfScope ps(c, KMP_PROF_SCHEDULE);
     hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, key.p, val.p,
                        cnt.p);
     KMP_LAUNCH_CHECK();
@@ -516,19 +538,26 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, uint32_
     for (int t = 0; t < 4; ++t) cnt[t] = sched.cnt[s][t];
     a.hub_keys = hub_keys;
     a.hub_vals = hub_vals;
+    int64_t* bytes = c.counters() + kBytesSlot;
     if (cnt[0] > 0) {
         constexpr int G = 8, GPB = kBlock / G;
+        ProfScope ps(c, KMP_PROF_RATE_T0);
+        a.bytes_ctr = bytes + KMP_PROF_RATE_T0;
         hipLaunchKernelGGL((k_rate_lds<G, 5>), dim3(grid_for(cnt[0], GPB, 65536)), dim3(kBlock), 0, c.stream, a,
                            order + sched.off[s][0], cnt[0]);
         KMP_LAUNCH_CHECK();
     }
     if (cnt[1] > 0) {
         constexpr int G = 64, GPB = kBlock / G;
+        ProfScope ps(c, KMP_PROF_RATE_T1);
+        a.bytes_ctr = bytes + KMP_PROF_RATE_T1;
         hipLaunchKernelGGL((k_rate_lds<G, 8>), dim3(grid_for(cnt[1], GPB, 65536)), dim3(kBlock), 0, c.stream, a,
                            order + sched.off[s][1], cnt[1]);
         KMP_LAUNCH_CHECK();
     }
     if (cnt[2] > 0) {
+        ProfScope ps(c, KMP_PROF_RATE_T2);
+        a.bytes_ctr = bytes + KMP_PROF_RATE_T2;
         hipLaunchKernelGGL((k_rate_lds<256, 12>), dim3(grid_for(cnt[2], 1, 65536)), dim3(kBlock), 0, c.stream, a,
                            order + sched.off[s][2], cnt[2]);
         KMP_LAUNCH_CHECK();
@@ -536,6 +565,8 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, uint32_
     if (cnt[3] > 0) {
         // hub tables are indexed by position in the hub range (all classes contiguous)
         a.hub_off = sched.hub_slot_off.p + (sched.off[s][3] - sched.hub_start);
+        ProfScope ps(c, KMP_PROF_RATE_HUB);
+        a.bytes_ctr = bytes + KMP_PROF_RATE_HUB;
         hipLaunchKernelGGL(k_rate_hub, dim3(grid_for(cnt[3], 1, 4096)), dim3(kBlock), 0, c.stream, a,
                            order + sched.off[s][3], cnt[3]);
         KMP_LAUNCH_CHECK();
@@ -583,9 +614,12 @@ int64_t subround_impl(Ctx& c, const DGraph& g, int32_t level, int32_t round, int
         total += cnt[t];
     }
     if (total == 0) return 0;
-    hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(total)), dim3(kBlock), 0, c.stream, seg, total, order, b.prop.p,
-                       b.demand.p, st.wt, st.cap_vec, st.cap_scalar, b.acc.p, ctr);
-    KMP_LAUNCH_CHECK();
+    {
+        ProfScope ps(c, KMP_PROF_ADMIT);
+        hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(total)), dim3(kBlock), 0, c.stream, seg, total, order, b.prop.p,
+                           b.demand.p, st.wt, st.cap_vec, st.cap_scalar, b.acc.p, ctr);
+        KMP_LAUNCH_CHECK();
+    }
     int64_t ncont = c.read1(ctr + 1);
     if (ncont > 0) {
         const int32_t n = g.n;
@@ -610,9 +644,12 @@ int64_t subround_impl(Ctx& c, const DGraph& g, int32_t level, int32_t round, int
                            ncont, st.wt, st.cap_vec, st.cap_scalar, b.acc.p);
         KMP_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_apply, dim3(grid_for(total)), dim3(kBlock), 0, c.stream, seg, total, order, b.prop.p,
-                       b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, moved, b.moved_list.p, ctr);
-    KMP_LAUNCH_CHECK();
+    {
+        ProfScope ps(c, KMP_PROF_APPLY);
+        hipLaunchKernelGGL(k_apply, dim3(grid_for(total)), dim3(kBlock), 0, c.stream, seg, total, order, b.prop.p,
+                           b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, moved, b.moved_list.p, ctr);
+        KMP_LAUNCH_CHECK();
+    }
     int64_t cursor = c.read1(ctr + 2);
     return cursor - moved_base;
 }
@@ -664,6 +701,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         if (nm == 0) break;
         if (r + 1 < kRounds) {
             c.zero(active.p, (size_t)g.n);
+            ProfScope ps(c, KMP_PROF_ACTIVE);
             hipLaunchKernelGGL(k_push_active, dim3(grid_for(nm * 64, kBlock, 8192)), dim3(kBlock), 0, c.stream,
                                b.moved_list.p, nm, g.xadj, g.adjncy, active.p);
             KMP_LAUNCH_CHECK();

@@ -1,5 +1,7 @@
 // Data-parallel building blocks: per-call context, prefix scans, stable LSD
 // radix sort (wave-ballot ranking, 64-wide wavefronts), fills, reductions.
+#include <mutex>
+
 #include "kmp_dev.h"
 
 namespace kmp {
@@ -90,6 +92,73 @@ int64_t* Ctx::counters()
 }
 
 void Ctx::zero_counters() { zero(counters(), 64 * sizeof(int64_t)); }
+
+// Events are recycled through a process-wide pool: creating an event costs far
+// more host time than recording one.
+namespace {
+std::mutex g_event_mu;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t take_event()
+{
+    {
+        std::lock_guard<std::mutex> lk(g_event_mu);
+        if (!g_event_pool.empty()) {
+            hipEvent_t e = g_event_pool.back();
+            g_event_pool.pop_back();
+            return e;
+        }
+    }
+    hipEvent_t e = nullptr;
+    KMP_HIP(hipEventCreate(&e));
+    return e;
+}
+}  // namespace
+
+Prof::~Prof()
+{
+    std::lock_guard<std::mutex> lk(g_event_mu);
+    for (auto& r : recs) {
+        if (r.a) g_event_pool.push_back(r.a);
+        if (r.b) g_event_pool.push_back(r.b);
+    }
+}
+
+int Ctx::prof_begin(int cls)
+{
+    if (!prof) return -1;
+    Prof::Rec r{cls, take_event(), nullptr};
+    KMP_HIP(hipEventRecord(r.a, stream));
+    prof->recs.push_back(r);
+    return (int)prof->recs.size() - 1;
+}
+
+void Ctx::prof_end(int idx)
+{
+    if (!prof || idx < 0) return;
+    hipEvent_t b = take_event();
+    KMP_HIP(hipEventRecord(b, stream));
+    prof->recs[idx].b = b;
+}
+
+void Ctx::prof_collect(int64_t* launches, double* ms, int64_t* bytes)
+{
+    for (int i = 0; i < KMP_PROF_CLASSES; ++i) {
+        launches[i] = 0;
+        ms[i] = 0;
+        bytes[i] = 0;
+    }
+    if (!prof) return;
+    sync();
+    for (auto& r : prof->recs) {
+        if (!r.b) continue;
+        float t = 0;
+        KMP_HIP(hipEventElapsedTime(&t, r.a, r.b));
+        launches[r.cls] += 1;
+        ms[r.cls] += t;
+    }
+    read(bytes, counters() + kBytesSlot, sizeof(int64_t) * KMP_PROF_CLASSES);
+}
 
 int bits_for(uint64_t max_value)
 {
