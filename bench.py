@@ -68,7 +68,7 @@ def _source_hash():
 
 
 KERNEL_OF_CLASS = {
-    "rate_t0": "k_rate_lds<8, 5>", "rate_t1": "k_rate_lds<64, 8>", "rate_t2": "k_rate_lds<256, 12>",
+    "rate_t0": "k_rate_lane", "rate_t1": "k_rate_lds<16, 7>", "rate_t2": "k_rate_lds<64, 10>",
     "rate_hub": "k_rate_hub", "contract_rows": "k_contract_rows",
 }
 

@@ -63,13 +63,13 @@ typedef struct kmp_options {
 /* Kernel classes reported when kmp_options.profile is set. */
 #define KMP_PROF_CLASSES 16
 enum {
-    KMP_PROF_RATE_T0 = 0,      /* LP rating, degree <= 16 (8 lanes per node)          */
-    KMP_PROF_RATE_T1 = 1,      /* LP rating, degree <= 128 (a wavefront per node)     */
-    KMP_PROF_RATE_T2 = 2,      /* LP rating, degree <= 2048 (a workgroup per node)    */
-    KMP_PROF_RATE_HUB = 3,     /* LP rating, hubs (global hash)                       */
+    KMP_PROF_RATE_T0 = 0,      /* LP rating, degree <= 16 (one lane per node)         */
+    KMP_PROF_RATE_T1 = 1,      /* LP rating, degree <= 64 (16 lanes per node)         */
+    KMP_PROF_RATE_T2 = 2,      /* LP rating, degree <= 4096 (wavefront / workgroup)   */
+    KMP_PROF_RATE_HUB = 3,     /* LP rating, degree > 4096 (global hash)              */
     KMP_PROF_ADMIT = 4,        /* admission of uncontended targets                    */
     KMP_PROF_APPLY = 5,        /* apply admitted moves                                */
-    KMP_PROF_CONTENDED = 6,    /* sort + prefix admission of contended targets        */
+    KMP_PROF_CONTENDED = 6,    /* in-LDS sort + prefix admission of contended targets */
     KMP_PROF_ACTIVE = 7,       /* next-round active set                               */
     KMP_PROF_CONTRACT_ROWS = 8,/* contraction: LDS aggregation of coarse rows         */
     KMP_PROF_CONTRACT = 9,     /* contraction: relabel, bucketing, heavy rows, copy   */

@@ -276,15 +276,25 @@ struct LPStats {
     int64_t rated_edges = 0;
 };
 
-// Per-level schedule: nodes grouped by (sub-round class, degree tier).
+// Per-level schedule: nodes grouped by (degree tier, sub-round class); the
+// segment of (tier t, class s) has index t * kSub + s.
+constexpr int kTiers = 5;
+constexpr int kSegs = kTiers * kSub;
+
 struct LPSchedule {
-    DBuf<int32_t> order;              // node ids grouped by (tier, class)
-    int32_t off[kSub][4] = {};        // [class][tier] start of the segment in `order`
-    int32_t cnt[kSub][4] = {};        // [class][tier] segment size
-    int32_t hub_start = 0;            // hubs of all classes are contiguous from here
+    DBuf<int32_t> order;              // node ids grouped by (tier, class), ascending id inside a segment
+    int32_t off[kSegs + 1] = {};      // segment start in `order`; off[kSegs] = n
+    int32_t cnt[kSegs] = {};          // segment size
+    DBuf<int32_t> segtab;             // device copy: [kSegs offsets][kSegs counts]
+    int32_t hub_start = 0;            // hubs (last tier) of all classes are contiguous from here
     DBuf<int64_t> hub_slot_off;       // per hub: start of its global hash table
     int64_t hub_slots_total = 0;
-    int64_t rated_deg[kSub] = {};     // total degree per class
+    int32_t class_size(int s) const
+    {
+        int32_t t = 0;
+        for (int q = 0; q < kTiers; ++q) t += cnt[q * kSub + s];
+        return t;
+    }
 };
 
 void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched);

@@ -3,62 +3,63 @@
 //
 // Deterministic sub-round reading: a round visits the nodes in S = 4 hash
 // classes; the nodes of one class are rated against the state at the start of
-// the sub-round (rate kernel), then proposals into one target are admitted in
+// the sub-round (rate kernels), then proposals into one target are admitted in
 // ascending node id while the running weight fits (admission), then applied.
+// After a round only nodes with a neighbour that moved stay active.
 //
 // Rate kernel tiers by degree (execution layout only; results identical):
-//   tier 0  deg <= 16    8 lanes per node, 32-slot LDS hash per node
-//   tier 1  deg <= 128   one wavefront per node, 256-slot LDS hash
-//   tier 2  deg <= 2048  one workgroup per node, 4096-slot LDS hash
-//   tier 3  deg >  2048  one workgroup per hub, global-memory hash table
+//   tier 0  deg <= 16    one lane per node, neighbour labels in registers
+//   tier 1  deg <= 64    16 lanes per node, 128-slot LDS hash per node
+//   tier 2  deg <= 512   one wavefront per node, 1024-slot LDS hash
+//   tier 3  deg <= 4096  one workgroup per node, 8192-slot LDS hash
+//   tier 4  deg >  4096  one workgroup per hub, global-memory hash table
+//
 // Admission: proposals add their weight to demand[K]; targets whose whole
-// demand fits are admitted at once; the rest ("contended") are sorted by
-// (target, id) and admitted by an inclusive prefix sum.
+// demand fits are admitted at once.  The others ("contended") are appended to
+// a list and resolved on the device by one workgroup that sorts the
+// (target, id) keys in LDS and admits by segmented prefix sums.  Sub-rounds
+// are enqueued speculatively: if the contended list of a sub-round exceeds
+// the LDS capacity, a device flag aborts the rest of the round and the host
+// finishes it on the exact path (sort in global memory), one sub-round at a
+// time.  Rounds after the first rate only the active nodes, compacted per
+// (tier, class) segment on the device.
 #include "kmp_dev.h"
 
 namespace kmp {
 
 namespace {
 
-constexpr int T0_DEG = 16, T1_DEG = 128, T2_DEG = 2048;
+constexpr int T0_DEG = 16, T1_DEG = 64, T2_DEG = 512, T3_DEG = 4096;
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
+constexpr int kSmallCap = 4096;     // contended entries resolved in LDS
+constexpr int kSmallThreads = 1024;
 
-struct Seg4 {
-    int32_t off[4];
-    int32_t cnt[4];
-};
+// ctl[] layout (int64, device): round control shared by the kernels
+enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_MOVED = 2, CTL_CONT = 3, CTL_N = 8 };
 
-__device__ inline int32_t seg_index(const Seg4& s, int64_t i)
+__device__ inline int tier_of(int32_t d)
 {
-    // map a flat index over the 4 segments to a position in `order`
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        if (i < s.cnt[t]) return s.off[t] + (int32_t)i;
-        i -= s.cnt[t];
-    }
-    return -1;
+    return d <= T0_DEG ? 0 : d <= T1_DEG ? 1 : d <= T2_DEG ? 2 : d <= T3_DEG ? 3 : 4;
 }
 
 // ---------------------------------------------------------------- schedule
 __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict__ xadj, int32_t n, uint32_t hsub,
                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ val,
-                                                       int32_t* __restrict__ cnt16)
+                                                       int32_t* __restrict__ cnt)
 {
-    __shared__ int32_t h[16];
-    if (threadIdx.x < 16) h[threadIdx.x] = 0;
+    __shared__ int32_t h[kSegs];
+    if (threadIdx.x < kSegs) h[threadIdx.x] = 0;
     __syncthreads();
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n) {
         uint32_t s = hash_step(hsub, (uint32_t)v, 3) % kSub;
-        int32_t d = xadj[v + 1] - xadj[v];
-        uint32_t t = d <= T0_DEG ? 0 : d <= T1_DEG ? 1 : d <= T2_DEG ? 2 : 3;
-        uint32_t k = t * kSub + s;
+        uint32_t k = (uint32_t)tier_of(xadj[v + 1] - xadj[v]) * kSub + s;
         key[v] = k;
         val[v] = (uint32_t)v;
         atomicAdd(&h[k], 1);
     }
     __syncthreads();
-    if (threadIdx.x < 16 && h[threadIdx.x]) atomicAdd(&cnt16[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < kSegs && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void k_hub_slots(const int32_t* __restrict__ xadj, const int32_t* __restrict__ hubs, int32_t nh,
@@ -71,6 +72,14 @@ __global__ void k_hub_slots(const int32_t* __restrict__ xadj, const int32_t* __r
     int64_t s = 1;
     while (s < 2 * d) s <<= 1;
     slots[i] = s;
+}
+
+// table offset of every hub, indexed by node id (lists of later rounds are compacted)
+__global__ void k_hub_scatter(const int32_t* __restrict__ hubs, const int64_t* __restrict__ slots,
+                              const int64_t* __restrict__ incl, int32_t nh, int64_t* __restrict__ off_by_node)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nh) off_by_node[hubs[i]] = incl[i] - slots[i];
 }
 
 // ---------------------------------------------------------------- rating
@@ -108,23 +117,31 @@ struct RateArgs {
     const int64_t* wt;
     const int64_t* cap_vec;
     int64_t cap_scalar;
-    const uint8_t* active;  // NULL = all
+    const uint8_t* active;  // NULL = every listed node is rated
     uint32_t hpre;          // H prefix over (seed; tag, level, round)
     int32_t* prop;          // [n], -1 = no proposal
     uint32_t* fav;          // [n] or NULL
     uint32_t* demand;       // [nlab]
     int64_t* counters;      // [0] rated edges
     int64_t* bytes_ctr;     // algorithmic bytes of this launch's class
-    // hubs (tier 3)
+    const int64_t* ctl;     // round control (abort flag) or NULL
+    const int32_t* list;    // node lists, segments described by segtab
+    const int32_t* segtab;  // [kSegs offsets][kSegs counts]
+    int seg;
+    // hubs
     uint32_t* hub_keys;
     uint32_t* hub_vals;
-    const int64_t* hub_off;
+    const int64_t* hub_off;  // by node id
     // balance mode (over != NULL): rate the nodes of overloaded blocks only,
-    // targets must be non-overloaded; write best target / gain / own rating
+    // targets must be non-overloaded; write best target / gain
     const uint8_t* over;
     int32_t* bal_t;
     int64_t* bal_d;
 };
+
+__device__ inline int64_t cap_of(const RateArgs& a, uint32_t K) { return a.cap_vec ? a.cap_vec[K] : a.cap_scalar; }
+
+__device__ inline bool aborted(const RateArgs& a) { return a.ctl && a.ctl[CTL_ABORT] != 0; }
 
 __device__ inline bool node_selected(const RateArgs& a, int32_t v)
 {
@@ -147,9 +164,7 @@ __device__ inline void write_result(const RateArgs& a, int32_t v, const Key3& fa
     }
 }
 
-__device__ inline int64_t cap_of(const RateArgs& a, uint32_t K) { return a.cap_vec ? a.cap_vec[K] : a.cap_scalar; }
-
-// Evaluate one table entry for the lane-local bests.
+// Evaluate one aggregated (label, rating) entry for the lane-local bests.
 __device__ inline void consider(const RateArgs& a, uint32_t key, uint32_t val, uint32_t own, int64_t cv, Key3& fav,
                                 Key3& adm, uint32_t& rown)
 {
@@ -163,6 +178,84 @@ __device__ inline void consider(const RateArgs& a, uint32_t key, uint32_t val, u
     if (better(c, adm)) {
         if (a.wt[key] + cv <= cap_of(a, key) && !(a.over && a.over[key])) adm = c;
     }
+}
+
+// per-wave statistic: rated entries and algorithmic bytes
+__device__ inline void flush_stats(const RateArgs& a, int64_t nodes, int64_t edges)
+{
+    for (int d = 32; d > 0; d >>= 1) {
+        edges += __shfl_xor(edges, d, 64);
+        nodes += __shfl_xor(nodes, d, 64);
+    }
+    if ((threadIdx.x & 63) == 0 && nodes) {
+        atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)edges);
+        const int64_t bytes = 25 * nodes + (a.adjwgt ? 12 : 8) * edges;
+        atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)bytes);
+    }
+}
+
+// Tier 0: one lane per node; labels and weights of the <= 16 neighbours live in
+// registers, duplicates are merged into their first occurrence, and the weight
+// (and cap) gathers of all candidates are issued together.
+__global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
+{
+    if (aborted(a)) return;
+    const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
+    int64_t edges = 0, nodes = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = a.list[off + i];
+        if (!node_selected(a, v)) continue;
+        const int32_t e0 = a.xadj[v];
+        const int32_t d = a.xadj[v + 1] - e0;
+        uint32_t lab[T0_DEG], w[T0_DEG];
+#pragma unroll
+        for (int j = 0; j < T0_DEG; ++j) {
+            if (j < d) {
+                lab[j] = (uint32_t)a.label[a.adjncy[e0 + j]];
+                w[j] = a.adjwgt ? (uint32_t)a.adjwgt[e0 + j] : 1u;
+            } else {
+                lab[j] = EMPTY;
+                w[j] = 0;
+            }
+        }
+#pragma unroll
+        for (int k = 1; k < T0_DEG; ++k) {
+            bool dup = false;
+#pragma unroll
+            for (int q = 0; q < k; ++q) {
+                const bool hit = !dup && lab[k] != EMPTY && lab[q] == lab[k];
+                w[q] += hit ? w[k] : 0u;
+                dup = dup || hit;
+            }
+            if (dup) lab[k] = EMPTY;
+        }
+        const uint32_t own = (uint32_t)a.label[v];
+        const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
+        bool fit[T0_DEG];
+#pragma unroll
+        for (int j = 0; j < T0_DEG; ++j) {
+            const bool cand = lab[j] != EMPTY && lab[j] != own;
+            fit[j] = cand && a.wt[lab[j]] + cv <= cap_of(a, lab[j]) && !(a.over && a.over[lab[j]]);
+        }
+        Key3 fav{0, 0, 0}, adm{0, 0, 0};
+        uint32_t rown = 0;
+#pragma unroll
+        for (int j = 0; j < T0_DEG; ++j) {
+            if (lab[j] == EMPTY) continue;
+            if (lab[j] == own) {
+                rown = w[j];
+                continue;
+            }
+            const Key3 c{w[j], hash_step(a.hpre, lab[j], 4), lab[j]};
+            if (better(c, fav)) fav = c;
+            if (fit[j] && better(c, adm)) adm = c;
+        }
+        write_result(a, v, fav, adm, rown, cv);
+        edges += d;
+        nodes += 1;
+    }
+    flush_stats(a, nodes, edges);
 }
 
 __device__ inline void lds_insert(uint32_t* keys, uint32_t* vals, int bits, uint32_t K, uint32_t w)
@@ -179,9 +272,9 @@ __device__ inline void lds_insert(uint32_t* keys, uint32_t* vals, int bits, uint
     }
 }
 
-// G lanes per node, 2^HB slots per node in LDS.  256 threads per block.
+// Tiers 1-3: G lanes per node, 2^HB slots per node in LDS, 256 threads.
 template <int G, int HB>
-__global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* __restrict__ order, int32_t count)
+__global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
 {
     constexpr int GPB = kBlock / G;
     constexpr int HS = 1 << HB;
@@ -189,6 +282,8 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
     __shared__ uint32_t s_vals[GPB * HS];
     __shared__ Key3 s_red[2][4];
     __shared__ uint32_t s_rown[4];
+    if (aborted(a)) return;
+    const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     const int tid = threadIdx.x;
     const int grp = tid / G, gl = tid % G;
     uint32_t* keys = s_keys + grp * HS;
@@ -198,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
         const int64_t i = base + grp;
         int32_t v = -1;
         if (i < count) {
-            v = order[i];
+            v = a.list[off + i];
             if (!node_selected(a, v)) v = -1;
         }
         for (int j = gl; j < HS; j += G) {
@@ -206,10 +301,8 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
             vals[j] = 0;
         }
         __syncthreads();
-        int32_t e0 = 0, e1 = 0;
         if (v >= 0) {
-            e0 = a.xadj[v];
-            e1 = a.xadj[v + 1];
+            const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
             for (int32_t e = e0 + gl; e < e1; e += G) {
                 uint32_t K = (uint32_t)a.label[a.adjncy[e]];
                 uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
@@ -223,10 +316,9 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
         __syncthreads();
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0;
-        uint32_t own = 0;
         int64_t cv = 0;
         if (v >= 0) {
-            own = (uint32_t)a.label[v];
+            const uint32_t own = (uint32_t)a.label[v];
             cv = a.vwgt ? a.vwgt[v] : 1;
             for (int j = gl; j < HS; j += G) consider(a, keys[j], vals[j], own, cv, fav, adm, rown);
         }
@@ -236,7 +328,6 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
 #pragma unroll
             for (int d = G / 2; d > 0; d >>= 1) rown += __shfl_xor(rown, d, G);
         } else {
-            // G == 256: wave reduce, then across the 4 waves through LDS
             fav = group_best<64>(fav);
             adm = group_best<64>(adm);
 #pragma unroll
@@ -259,41 +350,32 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a, const int32_t* 
         if (v >= 0 && gl == 0) write_result(a, v, fav, adm, rown, cv);
         __syncthreads();
     }
-    // rated edge statistic and algorithmic bytes (per wave leader)
-    for (int d = 32; d > 0; d >>= 1) {
-        edges += __shfl_xor(edges, d, 64);
-        nodes += __shfl_xor(nodes, d, 64);
-    }
-    if ((tid & 63) == 0 && edges) {
-        atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)edges);
-        const int64_t bytes = 25 * nodes + (a.adjwgt ? 12 : 8) * edges;
-        atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)bytes);
-    } else if ((tid & 63) == 0 && nodes) {
-        atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)(25 * nodes));
-    }
+    flush_stats(a, nodes, edges);
 }
 
-// One workgroup per hub node, hash table in global memory.
-__global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a, const int32_t* __restrict__ order, int32_t count)
+// Tier 4: one workgroup per hub node, hash table in global memory.
+__global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
 {
     __shared__ Key3 s_red[2][4];
     __shared__ uint32_t s_rown[4];
+    if (aborted(a)) return;
+    const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     const int tid = threadIdx.x;
+    int64_t edges = 0, nodes = 0;
     for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
-        int32_t v = order[i];
+        const int32_t v = a.list[off + i];
         if (!node_selected(a, v)) continue;  // uniform across the block
         const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
         const int64_t d = e1 - e0;
         int bits = 1;
         while ((1ll << bits) < 2 * d) ++bits;
         const int64_t hs = 1ll << bits;
-        uint32_t* keys = a.hub_keys + a.hub_off[i];
-        uint32_t* vals = a.hub_vals + a.hub_off[i];
+        uint32_t* keys = a.hub_keys + a.hub_off[v];
+        uint32_t* vals = a.hub_vals + a.hub_off[v];
         for (int64_t j = tid; j < hs; j += kBlock) {
             keys[j] = EMPTY;
             vals[j] = 0;
         }
-        __threadfence_block();
         __syncthreads();
         for (int32_t e = e0 + tid; e < e1; e += kBlock) {
             uint32_t K = (uint32_t)a.label[a.adjncy[e]];
@@ -309,7 +391,6 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a, const int32_t* 
                 h = (h + 1) & mask;
             }
         }
-        __threadfence_block();
         __syncthreads();
         const uint32_t own = (uint32_t)a.label[v];
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
@@ -337,39 +418,185 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a, const int32_t* 
                 rown += s_rown[q];
             }
             write_result(a, v, fav, adm, rown, cv);
-            atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)d);
-            atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)(25 + (a.adjwgt ? 12 : 8) * d));
+            edges += d;
+            nodes += 1;
         }
         __syncthreads();
     }
+    if (tid < 64) flush_stats(a, nodes, edges);
 }
 
 // ---------------------------------------------------------------- admission
-// acc[v]: 0 none, 1 admitted, 2 contended (decided by the exact path)
-__global__ void k_admit_fast(Seg4 seg, int64_t total, const int32_t* __restrict__ order,
-                             const int32_t* __restrict__ prop, const uint32_t* __restrict__ demand,
-                             const int64_t* __restrict__ wt, const int64_t* __restrict__ cap_vec, int64_t cap_scalar,
-                             uint8_t* __restrict__ acc, int64_t* counters)
+// The class-s nodes of the current lists: segments (t, s) for all tiers t.
+struct ClassSegs {
+    int32_t off[kTiers];
+    int32_t cnt[kTiers];
+    int32_t total;
+};
+
+__device__ inline ClassSegs class_segs(const int32_t* segtab, int s)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int contended = 0;
-    if (i < total) {
-        int32_t v = order[seg_index(seg, i)];
-        int32_t K = prop[v];
-        if (K >= 0) {
-            int64_t cap = cap_vec ? cap_vec[K] : cap_scalar;
-            if (wt[K] + (int64_t)demand[K] <= cap) {
-                acc[v] = 1;
-            } else {
-                acc[v] = 2;
-                contended = 1;
-            }
-        }
+    ClassSegs c;
+    c.total = 0;
+#pragma unroll
+    for (int t = 0; t < kTiers; ++t) {
+        c.off[t] = segtab[t * kSub + s];
+        c.cnt[t] = segtab[kSegs + t * kSub + s];
+        c.total += c.cnt[t];
     }
-    uint64_t b = ballot64(contended);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd((unsigned long long*)&counters[1], (unsigned long long)__popcll(b));
+    return c;
 }
 
+__device__ inline int32_t class_pos(const ClassSegs& c, int64_t i)
+{
+#pragma unroll
+    for (int t = 0; t < kTiers; ++t) {
+        if (i < c.cnt[t]) return c.off[t] + (int32_t)i;
+        i -= c.cnt[t];
+    }
+    return -1;
+}
+
+// Wave-aggregated reservation of one slot per requesting lane of a device cursor.
+__device__ inline int64_t reserve_slot(int64_t* cursor, bool want)
+{
+    const uint64_t b = ballot64(want);
+    if (!b) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)b) - 1;
+    int64_t base = 0;
+    if (lane == leader) base = (int64_t)atomicAdd((unsigned long long*)cursor, (unsigned long long)__popcll(b));
+    base = __shfl(base, leader, 64);
+    return want ? base + __popcll(b & ((1ull << lane) - 1ull)) : -1;
+}
+
+// acc[v]: 0 none, 1 admitted, 2 contended (decided by a contended path)
+__global__ __launch_bounds__(kBlock) void k_admit_fast(int64_t* ctl, const int32_t* __restrict__ list,
+                                                       const int32_t* __restrict__ segtab, int s,
+                                                       const int32_t* __restrict__ prop,
+                                                       const uint32_t* __restrict__ demand,
+                                                       const int64_t* __restrict__ wt,
+                                                       const int64_t* __restrict__ cap_vec, int64_t cap_scalar,
+                                                       uint8_t* __restrict__ acc, uint32_t* __restrict__ ckeys,
+                                                       uint32_t* __restrict__ cvals)
+{
+    if (ctl[CTL_ABORT]) return;
+    const ClassSegs cs = class_segs(segtab, s);
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < cs.total; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        bool cont = false;
+        int32_t v = -1, K = -1;
+        if (i < cs.total) {
+            v = list[class_pos(cs, i)];
+            K = prop[v];
+            if (K >= 0) {
+                const int64_t cap = cap_vec ? cap_vec[K] : cap_scalar;
+                if (wt[K] + (int64_t)demand[K] <= cap) {
+                    acc[v] = 1;
+                } else {
+                    acc[v] = 2;
+                    cont = true;
+                }
+            }
+        }
+        const int64_t slot = reserve_slot(&ctl[CTL_CONT], cont);
+        if (cont) {
+            ckeys[slot] = (uint32_t)K;
+            cvals[slot] = (uint32_t)v;
+        }
+    }
+}
+
+// One workgroup: sort the contended (target, id) keys in LDS, admit by
+// segmented prefix sums.  Raises the abort flag when the list is too long.
+__global__ __launch_bounds__(kSmallThreads) void k_contended_small(int64_t* ctl, int s, const uint32_t* __restrict__ ckeys,
+                                                                   const uint32_t* __restrict__ cvals,
+                                                                   const int32_t* __restrict__ vwgt,
+                                                                   const int64_t* __restrict__ wt,
+                                                                   const int64_t* __restrict__ cap_vec,
+                                                                   int64_t cap_scalar, int64_t* __restrict__ base,
+                                                                   uint8_t* __restrict__ acc)
+{
+    __shared__ uint64_t key[kSmallCap];
+    __shared__ int64_t pre[kSmallCap];
+    __shared__ int64_t wsum[kSmallThreads / 64];
+    __shared__ int64_t carry;
+    const int tid = threadIdx.x;
+    if (ctl[CTL_ABORT]) return;
+    const int64_t C = ctl[CTL_CONT];
+    if (C == 0) return;
+    if (C > kSmallCap) {
+        if (tid == 0) {
+            ctl[CTL_ABORT] = 1;
+            ctl[CTL_ABORT_SUB] = s;
+        }
+        return;
+    }
+    int P = 1;
+    while (P < C) P <<= 1;
+    for (int i = tid; i < P; i += kSmallThreads)
+        key[i] = i < C ? (((uint64_t)ckeys[i] << 32) | cvals[i]) : ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int p = tid; p < P / 2; p += kSmallThreads) {
+                const int lo = 2 * stride * (p / stride) + (p % stride);
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t x = key[lo], y = key[hi];
+                if ((x > y) == up) {
+                    key[lo] = y;
+                    key[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // inclusive prefix of node weights in sorted order (chunks of the block size)
+    if (tid == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < C; c0 += kSmallThreads) {
+        const int i = c0 + tid;
+        int64_t x = 0;
+        if (i < C) {
+            const uint32_t v = (uint32_t)key[i];
+            x = vwgt ? vwgt[v] : 1;
+        }
+        const int lane = tid & 63, wv = tid >> 6;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int64_t y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int64_t p = carry;
+        for (int q = 0; q < wv; ++q) p += wsum[q];
+        if (i < C) pre[i] = p + x;
+        __syncthreads();
+        if (tid == kSmallThreads - 1) carry = p + x;
+        __syncthreads();
+    }
+    // segment starts: weight before the first proposal of every target
+    for (int i = tid; i < C; i += kSmallThreads) {
+        const uint32_t K = (uint32_t)(key[i] >> 32);
+        if (i == 0 || (uint32_t)(key[i - 1] >> 32) != K) {
+            const uint32_t v = (uint32_t)key[i];
+            base[K] = pre[i] - (vwgt ? vwgt[v] : 1);
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    for (int i = tid; i < C; i += kSmallThreads) {
+        const uint32_t K = (uint32_t)(key[i] >> 32);
+        const uint32_t v = (uint32_t)key[i];
+        const int64_t cap = cap_vec ? cap_vec[K] : cap_scalar;
+        acc[v] = wt[K] + (pre[i] - base[K]) <= cap ? 1 : 0;
+    }
+    __syncthreads();
+    if (tid == 0) ctl[CTL_CONT] = 0;
+}
+
+// exact path (host synchronised): contended proposals in ascending id over all n
 __global__ void k_contended_flags(const uint8_t* __restrict__ acc, int32_t n, int32_t* __restrict__ flag)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -417,43 +644,87 @@ __global__ void k_decide(const uint32_t* __restrict__ keys, const uint32_t* __re
     acc[vals[i]] = wt[K] + (pre[i] - base[K]) <= cap ? 1 : 0;
 }
 
-__global__ void k_apply(Seg4 seg, int64_t total, const int32_t* __restrict__ order, int32_t* __restrict__ prop,
-                        uint8_t* __restrict__ acc, uint32_t* __restrict__ demand, int32_t* __restrict__ label,
-                        int64_t* __restrict__ wt, const int32_t* __restrict__ vwgt, uint8_t* __restrict__ moved,
-                        int32_t* __restrict__ moved_list, int64_t* counters)
+__global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* __restrict__ list,
+                                                  const int32_t* __restrict__ segtab, int s,
+                                                  int32_t* __restrict__ prop, uint8_t* __restrict__ acc,
+                                                  uint32_t* __restrict__ demand, int32_t* __restrict__ label,
+                                                  int64_t* __restrict__ wt, const int32_t* __restrict__ vwgt,
+                                                  uint8_t* __restrict__ moved, int32_t* __restrict__ moved_list)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    int32_t v = order[seg_index(seg, i)];
-    int32_t K = prop[v];
-    if (K < 0) return;
-    if (acc[v] == 1) {
-        int64_t c = vwgt ? vwgt[v] : 1;
-        int32_t old = label[v];
-        label[v] = K;
-        atomicAdd((unsigned long long*)&wt[K], (unsigned long long)c);
-        atomicAdd((unsigned long long*)&wt[old], (unsigned long long)(-c));
-        if (moved) moved[v] = 1;
-        unsigned long long slot = atomicAdd((unsigned long long*)&counters[2], 1ull);
-        if (moved_list) moved_list[slot] = v;
+    if (ctl[CTL_ABORT]) return;
+    const ClassSegs cs = class_segs(segtab, s);
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < cs.total; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        bool mv = false;
+        int32_t v = -1;
+        if (i < cs.total) {
+            v = list[class_pos(cs, i)];
+            const int32_t K = prop[v];
+            if (K >= 0) {
+                if (acc[v] == 1) {
+                    const int64_t c = vwgt ? vwgt[v] : 1;
+                    const int32_t old = label[v];
+                    label[v] = K;
+                    atomicAdd((unsigned long long*)&wt[K], (unsigned long long)c);
+                    atomicAdd((unsigned long long*)&wt[old], (unsigned long long)(-c));
+                    if (moved) moved[v] = 1;
+                    mv = true;
+                }
+                prop[v] = -1;
+                acc[v] = 0;
+                demand[K] = 0;
+            }
+        }
+        const int64_t slot = reserve_slot(&ctl[CTL_MOVED], mv);
+        if (mv) moved_list[slot] = v;
     }
-    prop[v] = -1;
-    acc[v] = 0;
-    demand[K] = 0;
 }
 
 // mark the neighbours of moved nodes active for the next round
 __global__ void k_push_active(const int32_t* __restrict__ moved_list, int64_t nm, const int32_t* __restrict__ xadj,
                               const int32_t* __restrict__ adjncy, uint8_t* __restrict__ active)
 {
-    // one wavefront per moved node
-    const int lane = threadIdx.x & 63;
-    int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    const int lane = threadIdx.x & 15;
+    int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 4;
     for (; w < nm; w += nw) {
         int32_t v = moved_list[w];
-        for (int32_t e = xadj[v] + lane; e < xadj[v + 1]; e += 64) active[adjncy[e]] = 1;
+        for (int32_t e = xadj[v] + lane; e < xadj[v + 1]; e += 16) active[adjncy[e]] = 1;
     }
+}
+
+// compact the active nodes of `order` segment by segment
+__global__ void k_active_flags(const int32_t* __restrict__ order, int32_t n, const uint8_t* __restrict__ active,
+                               int32_t* __restrict__ flag)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = active[order[i]];
+}
+
+__global__ void k_active_compact(const int32_t* __restrict__ order, const int32_t* __restrict__ flag,
+                                 const int32_t* __restrict__ pos, int32_t n, int32_t* __restrict__ alist)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) alist[pos[i]] = order[i];
+}
+
+struct SegBounds {
+    int32_t off[kSegs + 1];
+};
+
+__global__ void k_active_segtab(const int32_t* __restrict__ pos, SegBounds b, int32_t* __restrict__ segtab)
+{
+    const int j = threadIdx.x;
+    if (j < kSegs) {
+        const int32_t a = pos[b.off[j]], e = pos[b.off[j + 1]];
+        segtab[j] = a;
+        segtab[kSegs + j] = e - a;
+    }
+}
+
+__global__ void k_ctl_set(int64_t* ctl, int idx, int64_t v)
+{
+    if (threadIdx.x == 0) ctl[idx] = v;
 }
 
 }  // namespace
@@ -468,41 +739,51 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
     memset(sched.cnt, 0, sizeof(sched.cnt));
     sched.hub_slots_total = 0;
     sched.hub_start = n;
-    if (n == 0) return;
+    sched.segtab = DBuf<int32_t>(c, 2 * kSegs);
+    if (n == 0) {
+        c.zero(sched.segtab.p, sizeof(int32_t) * 2 * kSegs);
+        return;
+    }
     DBuf<uint32_t> key(c, n), val(c, n), key2(c, n), val2(c, n);
-    DBuf<int32_t> cnt(c, 16);
-    c.zero(cnt.p, 16 * sizeof(int32_t));
+    DBuf<int32_t> cnt(c, kSegs);
+    c.zero(cnt.p, kSegs * sizeof(int32_t));
     const uint32_t hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
-    ProfScope ps(c, KMP_PROF_SCHEDULE);
-    hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, key.p, val.p,
-                       cnt.p);
-    KMP_LAUNCH_CHECK();
-    radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, 4);
-    KMP_HIP(hipMemcpyAsync(sched.order.p, val.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
-    int32_t h[16];
-    c.read(h, cnt.p, sizeof(h));
-    // key = tier * 4 + class: the segments follow in that order
-    int32_t pos = 0;
-    int32_t segoff[4][4];
-    for (int t = 0; t < 4; ++t)
-        for (int s = 0; s < kSub; ++s) {
-            segoff[t][s] = pos;
-            sched.off[s][t] = pos;
-            sched.cnt[s][t] = h[t * kSub + s];
-            pos += h[t * kSub + s];
-        }
-    sched.hub_start = segoff[3][0];
-    // hub hash tables: hubs of all classes are contiguous from segoff[3][0]
-    int32_t nh = n - segoff[3][0];
-    if (nh > 0) {
-        sched.hub_slot_off = DBuf<int64_t>(c, (size_t)nh + 1);
-        DBuf<int64_t> slots(c, (size_t)nh);
-        hipLaunchKernelGGL(k_hub_slots, dim3(grid_for(nh)), dim3(kBlock), 0, c.stream, g.xadj,
-                           sched.order.p + segoff[3][0], nh, slots.p);
+    {
+        ProfScope ps(c, KMP_PROF_SCHEDULE);
+        hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, key.p,
+                           val.p, cnt.p);
         KMP_LAUNCH_CHECK();
-        scan_incl_i64(c, slots.p, sched.hub_slot_off.p + 1, nh);
-        c.zero(sched.hub_slot_off.p, sizeof(int64_t));
-        sched.hub_slots_total = c.read1(sched.hub_slot_off.p + nh);
+    }
+    radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, bits_for(kSegs - 1));
+    KMP_HIP(hipMemcpyAsync(sched.order.p, val.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+    int32_t h[kSegs];
+    c.read(h, cnt.p, sizeof(h));
+    int32_t pos = 0;
+    for (int j = 0; j < kSegs; ++j) {
+        sched.off[j] = pos;
+        sched.cnt[j] = h[j];
+        pos += h[j];
+    }
+    sched.off[kSegs] = n;
+    int32_t tab[2 * kSegs];
+    for (int j = 0; j < kSegs; ++j) {
+        tab[j] = sched.off[j];
+        tab[kSegs + j] = sched.cnt[j];
+    }
+    c.write(sched.segtab.p, tab, sizeof(tab));
+    sched.hub_start = sched.off[(kTiers - 1) * kSub];
+    const int32_t nh = n - sched.hub_start;
+    if (nh > 0) {
+        DBuf<int64_t> slots(c, (size_t)nh), incl(c, (size_t)nh);
+        const int32_t* hubs = sched.order.p + sched.hub_start;
+        hipLaunchKernelGGL(k_hub_slots, dim3(grid_for(nh)), dim3(kBlock), 0, c.stream, g.xadj, hubs, nh, slots.p);
+        KMP_LAUNCH_CHECK();
+        scan_incl_i64(c, slots.p, incl.p, nh);
+        sched.hub_slots_total = c.read1(incl.p + nh - 1);
+        sched.hub_slot_off = DBuf<int64_t>(c, (size_t)n);
+        hipLaunchKernelGGL(k_hub_scatter, dim3(grid_for(nh)), dim3(kBlock), 0, c.stream, hubs, slots.p, incl.p, nh,
+                           sched.hub_slot_off.p);
+        KMP_LAUNCH_CHECK();
     }
 }
 
@@ -514,6 +795,9 @@ struct LPBuffers {
     DBuf<uint32_t> demand;
     DBuf<uint32_t> hub_keys, hub_vals;
     DBuf<int32_t> moved_list;
+    DBuf<uint32_t> ckeys, cvals;   // contended (target, id), unordered
+    DBuf<int64_t> base;            // [nlab] weight before a target's first proposal
+    DBuf<int64_t> ctl;
 };
 
 void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t nlab, LPBuffers& b)
@@ -529,60 +813,17 @@ void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t nlab, 
         b.hub_vals = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
     }
     b.moved_list = DBuf<int32_t>(c, (size_t)g.n);
+    b.ckeys = DBuf<uint32_t>(c, (size_t)g.n);
+    b.cvals = DBuf<uint32_t>(c, (size_t)g.n);
+    b.base = DBuf<int64_t>(c, (size_t)nlab);
+    b.ctl = DBuf<int64_t>(c, CTL_N);
+    c.zero(b.ctl.p, sizeof(int64_t) * CTL_N);
 }
 
-void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, uint32_t* hub_keys, uint32_t* hub_vals)
+RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpre, LPBuffers* b)
 {
-    const int32_t* order = sched.order.p;
-    int32_t cnt[4];
-    for (int t = 0; t < 4; ++t) cnt[t] = sched.cnt[s][t];
-    a.hub_keys = hub_keys;
-    a.hub_vals = hub_vals;
-    int64_t* bytes = c.counters() + kBytesSlot;
-    if (cnt[0] > 0) {
-        constexpr int G = 8, GPB = kBlock / G;
-        ProfScope ps(c, KMP_PROF_RATE_T0);
-        a.bytes_ctr = bytes + KMP_PROF_RATE_T0;
-        hipLaunchKernelGGL((k_rate_lds<G, 5>), dim3(grid_for(cnt[0], GPB, 65536)), dim3(kBlock), 0, c.stream, a,
-                           order + sched.off[s][0], cnt[0]);
-        KMP_LAUNCH_CHECK();
-    }
-    if (cnt[1] > 0) {
-        constexpr int G = 64, GPB = kBlock / G;
-        ProfScope ps(c, KMP_PROF_RATE_T1);
-        a.bytes_ctr = bytes + KMP_PROF_RATE_T1;
-        hipLaunchKernelGGL((k_rate_lds<G, 8>), dim3(grid_for(cnt[1], GPB, 65536)), dim3(kBlock), 0, c.stream, a,
-                           order + sched.off[s][1], cnt[1]);
-        KMP_LAUNCH_CHECK();
-    }
-    if (cnt[2] > 0) {
-        ProfScope ps(c, KMP_PROF_RATE_T2);
-        a.bytes_ctr = bytes + KMP_PROF_RATE_T2;
-        hipLaunchKernelGGL((k_rate_lds<256, 12>), dim3(grid_for(cnt[2], 1, 65536)), dim3(kBlock), 0, c.stream, a,
-                           order + sched.off[s][2], cnt[2]);
-        KMP_LAUNCH_CHECK();
-    }
-    if (cnt[3] > 0) {
-        // hub tables are indexed by position in the hub range (all classes contiguous)
-        a.hub_off = sched.hub_slot_off.p + (sched.off[s][3] - sched.hub_start);
-        ProfScope ps(c, KMP_PROF_RATE_HUB);
-        a.bytes_ctr = bytes + KMP_PROF_RATE_HUB;
-        hipLaunchKernelGGL(k_rate_hub, dim3(grid_for(cnt[3], 1, 4096)), dim3(kBlock), 0, c.stream, a,
-                           order + sched.off[s][3], cnt[3]);
-        KMP_LAUNCH_CHECK();
-    }
-}
-
-// Returns moves of this sub-round; appends moved ids after `moved_base`.
-int64_t subround_impl(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32_t s, uint64_t seed,
-                      const LPSchedule& sched, LPState& st, const uint8_t* active, uint8_t* moved, LPBuffers& b,
-                      int64_t moved_base)
-{
-    int64_t* ctr = c.counters();
-    // counters[1] contended count; counters[2] = moved-list cursor
-    c.zero(ctr + 1, sizeof(int64_t));
-    set_i64(c, ctr + 2, moved_base);
     RateArgs a;
+    memset(&a, 0, sizeof(a));
     a.xadj = g.xadj;
     a.adjncy = g.adjncy;
     a.vwgt = g.vwgt;
@@ -591,67 +832,145 @@ int64_t subround_impl(Ctx& c, const DGraph& g, int32_t level, int32_t round, int
     a.wt = st.wt;
     a.cap_vec = st.cap_vec;
     a.cap_scalar = st.cap_scalar;
-    a.active = active;
-    a.hpre = hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)round});
-    a.prop = b.prop.p;
+    a.hpre = hpre;
     a.fav = st.fav;
-    a.demand = b.demand.p;
-    a.counters = ctr;
-    a.hub_off = nullptr;
-    a.over = nullptr;
-    a.bal_t = nullptr;
-    a.bal_d = nullptr;
+    a.counters = c.counters();
+    if (b) {
+        a.prop = b->prop.p;
+        a.demand = b->demand.p;
+        a.ctl = b->ctl.p;
+        a.hub_keys = b->hub_keys.p;
+        a.hub_vals = b->hub_vals.p;
+    }
+    return a;
+}
 
-    const int32_t* order = sched.order.p;
-    int32_t cnt[4];
-    for (int t = 0; t < 4; ++t) cnt[t] = sched.cnt[s][t];
-    launch_rate(c, a, sched, s, b.hub_keys.p, b.hub_vals.p);
-    Seg4 seg;
-    int64_t total = 0;
-    for (int t = 0; t < 4; ++t) {
-        seg.off[t] = sched.off[s][t];
-        seg.cnt[t] = cnt[t];
-        total += cnt[t];
-    }
-    if (total == 0) return 0;
-    {
-        ProfScope ps(c, KMP_PROF_ADMIT);
-        hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(total)), dim3(kBlock), 0, c.stream, seg, total, order, b.prop.p,
-                           b.demand.p, st.wt, st.cap_vec, st.cap_scalar, b.acc.p, ctr);
+// Launch the rating kernels of class s over the lists described by segtab;
+// grids are sized by the level's segment sizes (upper bounds of the lists).
+void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const int32_t* list, const int32_t* segtab)
+{
+    int64_t* bytes = c.counters() + kBytesSlot;
+    a.list = list;
+    a.segtab = segtab;
+    a.hub_off = sched.hub_slot_off.p;
+    for (int t = 0; t < kTiers; ++t) {
+        const int seg = t * kSub + s;
+        const int32_t ub = sched.cnt[seg];
+        if (ub == 0) continue;
+        a.seg = seg;
+        // LP launches count their algorithmic bytes per class (tier 3 joins tier 2)
+        if (!a.over) a.bytes_ctr = bytes + (t < 3 ? t : t == 3 ? KMP_PROF_RATE_T2 : KMP_PROF_RATE_HUB);
+        switch (t) {
+            case 0: {
+                ProfScope ps(c, KMP_PROF_RATE_T0);
+                hipLaunchKernelGGL(k_rate_lane, dim3(grid_for(ub, kBlock, 65536)), dim3(kBlock), 0, c.stream, a);
+                break;
+            }
+            case 1: {
+                constexpr int G = 16;
+                ProfScope ps(c, KMP_PROF_RATE_T1);
+                hipLaunchKernelGGL((k_rate_lds<G, 7>), dim3(grid_for(ub, kBlock / G, 65536)), dim3(kBlock), 0,
+                                   c.stream, a);
+                break;
+            }
+            case 2: {
+                constexpr int G = 64;
+                ProfScope ps(c, KMP_PROF_RATE_T2);
+                hipLaunchKernelGGL((k_rate_lds<G, 10>), dim3(grid_for(ub, kBlock / G, 65536)), dim3(kBlock), 0,
+                                   c.stream, a);
+                break;
+            }
+            case 3: {
+                ProfScope ps(c, KMP_PROF_RATE_T2);
+                hipLaunchKernelGGL((k_rate_lds<256, 13>), dim3(grid_for(ub, 1, 65536)), dim3(kBlock), 0, c.stream,
+                                   a);
+                break;
+            }
+            default: {
+                ProfScope ps(c, KMP_PROF_RATE_HUB);
+                hipLaunchKernelGGL(k_rate_hub, dim3(grid_for(ub, 1, 4096)), dim3(kBlock), 0, c.stream, a);
+                break;
+            }
+        }
         KMP_LAUNCH_CHECK();
     }
-    int64_t ncont = c.read1(ctr + 1);
-    if (ncont > 0) {
-        const int32_t n = g.n;
-        DBuf<int32_t> flag(c, (size_t)n + 1);
-        hipLaunchKernelGGL(k_contended_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, b.acc.p, n, flag.p);
-        KMP_LAUNCH_CHECK();
-        scan_excl_i32(c, flag.p, flag.p, n, nullptr);
-        DBuf<uint32_t> keys(c, ncont), vals(c, ncont), keys2(c, ncont), vals2(c, ncont);
-        hipLaunchKernelGGL(k_contended_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, b.acc.p, flag.p, n,
-                           b.prop.p, keys.p, vals.p);
-        KMP_LAUNCH_CHECK();
-        radix_sort_pairs(c, keys.p, vals.p, keys2.p, vals2.p, ncont, bits_for((uint64_t)(st.nlab - 1)));
-        DBuf<int64_t> pre(c, ncont), base(c, (size_t)st.nlab);
-        hipLaunchKernelGGL(k_gather_cw, dim3(grid_for(ncont)), dim3(kBlock), 0, c.stream, vals.p, ncont, g.vwgt,
-                           pre.p);
-        KMP_LAUNCH_CHECK();
-        scan_incl_i64(c, pre.p, pre.p, ncont);
-        hipLaunchKernelGGL(k_heads, dim3(grid_for(ncont)), dim3(kBlock), 0, c.stream, keys.p, pre.p, vals.p, g.vwgt,
-                           ncont, base.p);
-        KMP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_decide, dim3(grid_for(ncont)), dim3(kBlock), 0, c.stream, keys.p, vals.p, pre.p, base.p,
-                           ncont, st.wt, st.cap_vec, st.cap_scalar, b.acc.p);
-        KMP_LAUNCH_CHECK();
+}
+
+void launch_admit(Ctx& c, const LPSchedule& sched, int32_t s, const int32_t* list, const int32_t* segtab,
+                  LPState& st, LPBuffers& b)
+{
+    const int32_t ub = sched.class_size(s);
+    if (ub == 0) return;
+    ProfScope ps(c, KMP_PROF_ADMIT);
+    hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list,
+                       segtab, s, b.prop.p, b.demand.p, st.wt, st.cap_vec, st.cap_scalar, b.acc.p, b.ckeys.p,
+                       b.cvals.p);
+    KMP_LAUNCH_CHECK();
+}
+
+void launch_small(Ctx& c, int32_t s, const DGraph& g, LPState& st, LPBuffers& b)
+{
+    ProfScope ps(c, KMP_PROF_CONTENDED);
+    hipLaunchKernelGGL(k_contended_small, dim3(1), dim3(kSmallThreads), 0, c.stream, b.ctl.p, s, b.ckeys.p,
+                       b.cvals.p, g.vwgt, st.wt, st.cap_vec, st.cap_scalar, b.base.p, b.acc.p);
+    KMP_LAUNCH_CHECK();
+}
+
+void launch_apply(Ctx& c, const LPSchedule& sched, int32_t s, const int32_t* list, const int32_t* segtab,
+                  const DGraph& g, LPState& st, LPBuffers& b, uint8_t* moved)
+{
+    const int32_t ub = sched.class_size(s);
+    if (ub == 0) return;
+    ProfScope ps(c, KMP_PROF_APPLY);
+    hipLaunchKernelGGL(k_apply, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list, segtab,
+                       s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, moved, b.moved_list.p);
+    KMP_LAUNCH_CHECK();
+}
+
+void ctl_set(Ctx& c, LPBuffers& b, int idx, int64_t v)
+{
+    hipLaunchKernelGGL(k_ctl_set, dim3(1), dim3(64), 0, c.stream, b.ctl.p, idx, v);
+    KMP_LAUNCH_CHECK();
+}
+
+// Exact admission of the contended proposals (host synchronised).
+void resolve_exact(Ctx& c, const DGraph& g, LPState& st, LPBuffers& b)
+{
+    const int64_t ncont = c.read1(b.ctl.p + CTL_CONT);
+    if (ncont == 0) return;
+    const int32_t n = g.n;
+    DBuf<int32_t> flag(c, (size_t)n), pos(c, (size_t)n + 1);
+    hipLaunchKernelGGL(k_contended_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, b.acc.p, n, flag.p);
+    KMP_LAUNCH_CHECK();
+    scan_excl_i32(c, flag.p, pos.p, n, pos.p + n);
+    DBuf<uint32_t> keys(c, ncont), vals(c, ncont), keys2(c, ncont), vals2(c, ncont);
+    hipLaunchKernelGGL(k_contended_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, b.acc.p, pos.p, n, b.prop.p,
+                       keys.p, vals.p);
+    KMP_LAUNCH_CHECK();
+    radix_sort_pairs(c, keys.p, vals.p, keys2.p, vals2.p, ncont, bits_for((uint64_t)(st.nlab - 1)));
+    DBuf<int64_t> pre(c, ncont);
+    hipLaunchKernelGGL(k_gather_cw, dim3(grid_for(ncont)), dim3(kBlock), 0, c.stream, vals.p, ncont, g.vwgt, pre.p);
+    KMP_LAUNCH_CHECK();
+    scan_incl_i64(c, pre.p, pre.p, ncont);
+    hipLaunchKernelGGL(k_heads, dim3(grid_for(ncont)), dim3(kBlock), 0, c.stream, keys.p, pre.p, vals.p, g.vwgt, ncont,
+                       b.base.p);
+    KMP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_decide, dim3(grid_for(ncont)), dim3(kBlock), 0, c.stream, keys.p, vals.p, pre.p, b.base.p,
+                       ncont, st.wt, st.cap_vec, st.cap_scalar, b.acc.p);
+    KMP_LAUNCH_CHECK();
+    ctl_set(c, b, CTL_CONT, 0);
+}
+
+// One sub-round on the exact path (host synchronised after admission).
+void subround_exact(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t s, const int32_t* list,
+                    const int32_t* segtab, LPState& st, LPBuffers& b, const RateArgs& a, bool rate, uint8_t* moved)
+{
+    if (rate) {
+        launch_rate(c, a, sched, s, list, segtab);
+        launch_admit(c, sched, s, list, segtab, st, b);
     }
-    {
-        ProfScope ps(c, KMP_PROF_APPLY);
-        hipLaunchKernelGGL(k_apply, dim3(grid_for(total)), dim3(kBlock), 0, c.stream, seg, total, order, b.prop.p,
-                           b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, moved, b.moved_list.p, ctr);
-        KMP_LAUNCH_CHECK();
-    }
-    int64_t cursor = c.read1(ctr + 2);
-    return cursor - moved_base;
+    resolve_exact(c, g, st, b);
+    launch_apply(c, sched, s, list, segtab, g, st, b, moved);
 }
 
 }  // namespace
@@ -661,17 +980,10 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
                       const uint8_t* over, int32_t* bal_t, int64_t* bal_d)
 {
     if (g.n == 0) return;
-    RateArgs a;
-    memset(&a, 0, sizeof(a));
-    a.xadj = g.xadj;
-    a.adjncy = g.adjncy;
-    a.vwgt = g.vwgt;
-    a.adjwgt = g.adjwgt;
-    a.label = part;
-    a.wt = wt;
-    a.cap_vec = cap;
-    a.hpre = hash_prefix(seed, {TAG_BAL, (uint32_t)level, (uint32_t)round});
-    a.counters = c.counters() + 10;  // statistic slot not reported for balancing
+    LPState st{const_cast<int32_t*>(part), const_cast<int64_t*>(wt), 0, cap, 0, nullptr, TAG_BAL};
+    RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {TAG_BAL, (uint32_t)level, (uint32_t)round}), nullptr);
+    a.counters = c.counters() + 10;                          // not reported for balancing
+    a.bytes_ctr = c.counters() + kBytesSlot + KMP_PROF_OTHER;  // nor counted as LP bytes
     a.over = over;
     a.bal_t = bal_t;
     a.bal_d = bal_d;
@@ -680,30 +992,66 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
         hk = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
         hv = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
     }
-    for (int32_t s = 0; s < kSub; ++s) launch_rate(c, a, sched, s, hk.p, hv.p);
+    a.hub_keys = hk.p;
+    a.hub_vals = hv.p;
+    for (int32_t s = 0; s < kSub; ++s) launch_rate(c, a, sched, s, sched.order.p, sched.segtab.p);
 }
 
 LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st)
 {
     LPStats out;
-    if (g.n == 0) return out;
+    const int32_t n = g.n;
+    if (n == 0) return out;
     LPBuffers b;
     lp_buffers(c, g, sched, st.nlab, b);
-    DBuf<uint8_t> active(c, (size_t)g.n);
+    DBuf<uint8_t> active(c, (size_t)n);
+    DBuf<int32_t> alist(c, (size_t)n), flag(c, (size_t)n), pos(c, (size_t)n + 1), segtab_r(c, 2 * kSegs);
+    SegBounds bounds;
+    for (int j = 0; j <= kSegs; ++j) bounds.off[j] = sched.off[j];
     int64_t* ctr = c.counters();
     c.zero(ctr, sizeof(int64_t));  // rated edges
     for (int32_t r = 0; r < kRounds; ++r) {
         out.rounds = r + 1;
-        int64_t nm = 0;
-        for (int32_t s = 0; s < kSub; ++s)
-            nm += subround_impl(c, g, level, r, s, seed, sched, st, r == 0 ? nullptr : active.p, nullptr, b, nm);
+        const int32_t* list = r == 0 ? sched.order.p : alist.p;
+        const int32_t* segtab = r == 0 ? sched.segtab.p : segtab_r.p;
+        const RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
+        // speculative sub-rounds: no host synchronisation in between
+        for (int32_t s = 0; s < kSub; ++s) {
+            launch_rate(c, a, sched, s, list, segtab);
+            launch_admit(c, sched, s, list, segtab, st, b);
+            launch_small(c, s, g, st, b);
+            launch_apply(c, sched, s, list, segtab, g, st, b, nullptr);
+        }
+        int64_t h[CTL_N];
+        c.read(h, b.ctl.p, sizeof(h));
+        if (h[CTL_ABORT]) {
+            // finish the round on the exact path from the aborted sub-round on
+            const int32_t s0 = (int32_t)h[CTL_ABORT_SUB];
+            ctl_set(c, b, CTL_ABORT, 0);
+            subround_exact(c, g, sched, s0, list, segtab, st, b, a, false, nullptr);
+            for (int32_t s = s0 + 1; s < kSub; ++s) subround_exact(c, g, sched, s, list, segtab, st, b, a, true, nullptr);
+            c.read(h, b.ctl.p, sizeof(h));
+        }
+        const int64_t nm = h[CTL_MOVED];
         out.moves[r] = nm;
         if (nm == 0) break;
+        ctl_set(c, b, CTL_MOVED, 0);
         if (r + 1 < kRounds) {
-            c.zero(active.p, (size_t)g.n);
-            ProfScope ps(c, KMP_PROF_ACTIVE);
-            hipLaunchKernelGGL(k_push_active, dim3(grid_for(nm * 64, kBlock, 8192)), dim3(kBlock), 0, c.stream,
-                               b.moved_list.p, nm, g.xadj, g.adjncy, active.p);
+            c.zero(active.p, (size_t)n);
+            {
+                ProfScope ps(c, KMP_PROF_ACTIVE);
+                hipLaunchKernelGGL(k_push_active, dim3(grid_for(nm * 16, kBlock, 8192)), dim3(kBlock), 0, c.stream,
+                                   b.moved_list.p, nm, g.xadj, g.adjncy, active.p);
+                KMP_LAUNCH_CHECK();
+            }
+            hipLaunchKernelGGL(k_active_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sched.order.p, n,
+                               active.p, flag.p);
+            KMP_LAUNCH_CHECK();
+            scan_excl_i32(c, flag.p, pos.p, n, pos.p + n);
+            hipLaunchKernelGGL(k_active_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sched.order.p, flag.p,
+                               pos.p, n, alist.p);
+            KMP_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_active_segtab, dim3(1), dim3(64), 0, c.stream, pos.p, bounds, segtab_r.p);
             KMP_LAUNCH_CHECK();
         }
     }
@@ -717,7 +1065,10 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
     if (g.n == 0) return 0;
     LPBuffers b;
     lp_buffers(c, g, sched, st.nlab, b);
-    return subround_impl(c, g, level, round, s, seed, sched, st, active, moved, b, 0);
+    RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)round}), &b);
+    a.active = active;
+    subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, st, b, a, true, moved);
+    return c.read1(b.ctl.p + CTL_MOVED);
 }
 
 }  // namespace kmp
