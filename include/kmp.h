@@ -56,7 +56,8 @@ extern "C" {
 /* Options for kmp_partition_ex (all fields zero = defaults). */
 typedef struct kmp_options {
     int32_t validate;       /* 1: check the CSR on the device first (KMP_EGRAPH on failure) */
-    int32_t profile;        /* 1: time kernel classes with HIP events (fills kmp_stats.prof_*) */
+    int32_t profile;        /* 1: time kernel classes with HIP events (fills kmp_stats.prof_*);
+                               2: also synchronise at phase boundaries for the ms_* phase timers */
     int32_t reserved[6];
 } kmp_options;
 
@@ -97,7 +98,7 @@ typedef struct kmp_stats {
     int64_t lp_rated_edges;                 /* directed entries read by LP rating kernels */
     int64_t contracted_edges;               /* sum of m_l over contracted levels          */
     double ms_total;                        /* wall time of the call                      */
-    double ms_coarsen_lp;                   /* host-timed phases (stream synchronised)    */
+    double ms_coarsen_lp;                   /* host-timed phases (device-synchronised only with profile = 2) */
     double ms_contract;
     double ms_initial;                      /* bipartitioning (extraction + GGG)          */
     double ms_refine;                       /* balance + refinement + projection          */

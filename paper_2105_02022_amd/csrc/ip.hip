@@ -393,7 +393,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             hipLaunchKernelGGL(k_ggg<true>, dim3((unsigned)lds_jobs.size()), dim3(GGG_THREADS), (size_t)lds_max,
                                c.stream, a);
             KMP_LAUNCH_CHECK();
-            c.sync();
+
         }
         if (!glob_jobs.empty()) {
             DBuf<GGGJob> jobs(c, glob_jobs.size());
@@ -404,7 +404,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             ProfScope ps(c, KMP_PROF_GGG);
             hipLaunchKernelGGL(k_ggg<false>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream, a);
             KMP_LAUNCH_CHECK();
-            c.sync();
+
         }
     }
     // renumber blocks in ascending `first`
@@ -432,7 +432,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         hipLaunchKernelGGL(k_relabel, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, side.p, dnew.p, dsplit.p,
                            n);
         KMP_LAUNCH_CHECK();
-        c.sync();
+
     }
     first.swap(nf);
     fcount.swap(nc);

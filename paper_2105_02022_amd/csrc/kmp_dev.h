@@ -166,11 +166,21 @@ class Ctx {
     void prof_collect(int64_t* launches, double* ms, int64_t* bytes);
 
   private:
-    std::vector<void*> live_;
-    void* pinned_ = nullptr;
-    size_t pinned_bytes_ = 0;
+    // Device memory comes from a process-wide caching pool (per device):
+    // blocks freed during the call are reused by later allocations of the
+    // same call (stream order makes that safe) and return to the shared pool
+    // when the call ends, after the stream has drained.
+    int device_ = 0;
+    std::vector<std::pair<void*, size_t>> live_;   // (block, capacity) in use
+    std::vector<std::pair<void*, size_t>> freed_;  // freed during this call
+    // Pinned host staging: writes are enqueued without waiting; the chunks
+    // are recycled when the call ends.
+    std::vector<std::pair<void*, size_t>> pinned_chunks_;
+    size_t pinned_used_ = 0;
+    void* read_buf_ = nullptr;
+    size_t read_bytes_ = 0;
     int64_t* counters_ = nullptr;
-    void ensure_pinned(size_t bytes);
+    void* stage(size_t bytes);
 };
 
 struct ProfScope {

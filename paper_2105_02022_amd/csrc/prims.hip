@@ -1,5 +1,6 @@
 // Data-parallel building blocks: per-call context, prefix scans, stable LSD
 // radix sort (wave-ballot ranking, 64-wide wavefronts), fills, reductions.
+#include <map>
 #include <mutex>
 
 #include "kmp_dev.h"
@@ -7,26 +8,105 @@
 namespace kmp {
 
 // ================================================================ context
-Ctx::Ctx(hipStream_t s) : stream(s) {}
+namespace {
+
+// Process-wide cache of device blocks per device, keyed by capacity.
+struct DevicePool {
+    std::mutex mu;
+    std::multimap<size_t, void*> free_blocks[64];
+};
+DevicePool& device_pool()
+{
+    static DevicePool* p = new DevicePool();  // lives until process exit
+    return *p;
+}
+
+// Capacity class: multiples of 1/4 of the power of two below the request.
+size_t capacity_for(size_t bytes)
+{
+    if (bytes <= 256) return 256;
+    size_t p = 256;
+    while (p < bytes) p <<= 1;
+    const size_t half = p >> 1, step = half >> 2;
+    size_t c = half;
+    while (c < bytes) c += step;
+    return c;
+}
+
+// Take a cached block of capacity in [cap, 2 cap) from `m`, if any.
+void* take_block(std::multimap<size_t, void*>& m, size_t cap, size_t& got)
+{
+    auto it = m.lower_bound(cap);
+    if (it == m.end() || it->first >= 2 * cap) return nullptr;
+    void* p = it->second;
+    got = it->first;
+    m.erase(it);
+    return p;
+}
+
+std::mutex g_pinned_mu;
+std::vector<std::pair<void*, size_t>> g_pinned_free;
+
+}  // namespace
+
+Ctx::Ctx(hipStream_t s) : stream(s)
+{
+    if (hipGetDevice(&device_) != hipSuccess || device_ < 0 || device_ >= 64) device_ = 0;
+}
 
 Ctx::~Ctx()
 {
-    for (void* p : live_) (void)hipFreeAsync(p, stream);
-    if (counters_) (void)hipFreeAsync(counters_, stream);
     (void)hipStreamSynchronize(stream);
-    if (pinned_) (void)hipHostFree(pinned_);
+    DevicePool& dp = device_pool();
+    {
+        std::lock_guard<std::mutex> lk(dp.mu);
+        for (auto& b : live_) dp.free_blocks[device_].emplace(b.second, b.first);
+        for (auto& b : freed_) dp.free_blocks[device_].emplace(b.second, b.first);
+        if (counters_) dp.free_blocks[device_].emplace((size_t)512, (void*)counters_);
+    }
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    for (auto& c : pinned_chunks_) g_pinned_free.push_back(c);
+    if (read_buf_) g_pinned_free.emplace_back(read_buf_, read_bytes_);
 }
 
 void* Ctx::alloc_bytes(size_t bytes)
 {
-    void* p = nullptr;
-    if (bytes == 0) bytes = 8;
-    hipError_t e = hipMallocAsync(&p, bytes, stream);
-    if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        throw Error(KMP_ENOMEM, "device workspace allocation failed (" + std::to_string(bytes) + " bytes)");
+    const size_t cap = capacity_for(bytes);
+    size_t got = 0;
+    // blocks freed earlier in this call first (same stream), then the shared pool
+    for (size_t i = freed_.size(); i-- > 0;) {
+        if (freed_[i].second >= cap && freed_[i].second < 2 * cap) {
+            auto b = freed_[i];
+            freed_[i] = freed_.back();
+            freed_.pop_back();
+            live_.push_back(b);
+            return b.first;
+        }
     }
-    live_.push_back(p);
+    void* p = nullptr;
+    {
+        DevicePool& dp = device_pool();
+        std::lock_guard<std::mutex> lk(dp.mu);
+        p = take_block(dp.free_blocks[device_], cap, got);
+    }
+    if (!p) {
+        got = cap;
+        hipError_t e = hipMalloc(&p, cap);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            // release cached blocks and retry once
+            DevicePool& dp = device_pool();
+            std::lock_guard<std::mutex> lk(dp.mu);
+            for (auto& kv : dp.free_blocks[device_]) (void)hipFree(kv.second);
+            dp.free_blocks[device_].clear();
+            e = hipMalloc(&p, cap);
+            if (e != hipSuccess || !p) {
+                (void)hipGetLastError();
+                throw Error(KMP_ENOMEM, "device workspace allocation failed (" + std::to_string(bytes) + " bytes)");
+            }
+        }
+    }
+    live_.emplace_back(p, got);
     return p;
 }
 
@@ -34,10 +114,10 @@ void Ctx::free(void* p)
 {
     if (!p) return;
     for (size_t i = live_.size(); i-- > 0;)
-        if (live_[i] == p) {
+        if (live_[i].first == p) {
+            freed_.push_back(live_[i]);
             live_[i] = live_.back();
             live_.pop_back();
-            KMP_HIP(hipFreeAsync(p, stream));
             return;
         }
 }
@@ -49,42 +129,93 @@ void Ctx::zero(void* p, size_t bytes)
 
 void Ctx::sync() { KMP_HIP(hipStreamSynchronize(stream)); }
 
-void Ctx::ensure_pinned(size_t bytes)
+// Pinned staging for host-to-device copies: a bump arena over chunks that stay
+// untouched until the call ends (the copies may still be in flight).
+void* Ctx::stage(size_t bytes)
 {
-    if (pinned_bytes_ >= bytes) return;
-    if (pinned_) KMP_HIP(hipHostFree(pinned_));
-    pinned_ = nullptr;
-    size_t sz = bytes < 4096 ? 4096 : bytes;
-    KMP_HIP(hipHostMalloc(&pinned_, sz, hipHostMallocDefault));
-    pinned_bytes_ = sz;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (!pinned_chunks_.empty() && pinned_used_ + bytes <= pinned_chunks_.back().second) {
+        void* p = static_cast<char*>(pinned_chunks_.back().first) + pinned_used_;
+        pinned_used_ += bytes;
+        return p;
+    }
+    const size_t want = bytes < (1u << 20) ? (1u << 20) : bytes;
+    void* chunk = nullptr;
+    size_t got = 0;
+    {
+        std::lock_guard<std::mutex> lk(g_pinned_mu);
+        for (size_t i = 0; i < g_pinned_free.size(); ++i)
+            if (g_pinned_free[i].second >= want) {
+                chunk = g_pinned_free[i].first;
+                got = g_pinned_free[i].second;
+                g_pinned_free[i] = g_pinned_free.back();
+                g_pinned_free.pop_back();
+                break;
+            }
+    }
+    if (!chunk) {
+        KMP_HIP(hipHostMalloc(&chunk, want, hipHostMallocDefault));
+        got = want;
+    }
+    pinned_chunks_.emplace_back(chunk, got);
+    pinned_used_ = bytes;
+    return chunk;
 }
 
 void Ctx::read(void* host, const void* dev, size_t bytes)
 {
     if (!bytes) return;
-    ensure_pinned(bytes);
-    KMP_HIP(hipMemcpyAsync(pinned_, dev, bytes, hipMemcpyDeviceToHost, stream));
+    if (read_bytes_ < bytes) {
+        if (read_buf_) {
+            std::lock_guard<std::mutex> lk(g_pinned_mu);
+            g_pinned_free.emplace_back(read_buf_, read_bytes_);
+        }
+        read_buf_ = nullptr;
+        const size_t want = bytes < 4096 ? 4096 : bytes;
+        {
+            std::lock_guard<std::mutex> lk(g_pinned_mu);
+            for (size_t i = 0; i < g_pinned_free.size(); ++i)
+                if (g_pinned_free[i].second >= want) {
+                    read_buf_ = g_pinned_free[i].first;
+                    read_bytes_ = g_pinned_free[i].second;
+                    g_pinned_free[i] = g_pinned_free.back();
+                    g_pinned_free.pop_back();
+                    break;
+                }
+        }
+        if (!read_buf_) {
+            KMP_HIP(hipHostMalloc(&read_buf_, want, hipHostMallocDefault));
+            read_bytes_ = want;
+        }
+    }
+    KMP_HIP(hipMemcpyAsync(read_buf_, dev, bytes, hipMemcpyDeviceToHost, stream));
     KMP_HIP(hipStreamSynchronize(stream));
-    memcpy(host, pinned_, bytes);
+    memcpy(host, read_buf_, bytes);
 }
 
 void Ctx::write(void* dev, const void* host, size_t bytes)
 {
     if (!bytes) return;
-    // the staging buffer is reused: wait for any earlier copy out of it
-    KMP_HIP(hipStreamSynchronize(stream));
-    ensure_pinned(bytes);
-    memcpy(pinned_, host, bytes);
-    KMP_HIP(hipMemcpyAsync(dev, pinned_, bytes, hipMemcpyHostToDevice, stream));
-    KMP_HIP(hipStreamSynchronize(stream));
+    void* st = stage(bytes);
+    memcpy(st, host, bytes);
+    KMP_HIP(hipMemcpyAsync(dev, st, bytes, hipMemcpyHostToDevice, stream));
 }
 
 int64_t* Ctx::counters()
 {
     if (!counters_) {
+        size_t got = 0;
         void* p = nullptr;
-        if (hipMallocAsync(&p, 64 * sizeof(int64_t), stream) != hipSuccess)
-            throw Error(KMP_ENOMEM, "counter allocation failed");
+        {
+            DevicePool& dp = device_pool();
+            std::lock_guard<std::mutex> lk(dp.mu);
+            p = take_block(dp.free_blocks[device_], 512, got);
+            if (p && got != 512) {  // keep only exact 512-byte blocks for counters
+                dp.free_blocks[device_].emplace(got, p);
+                p = nullptr;
+            }
+        }
+        if (!p) KMP_HIP(hipMalloc(&p, 512));
         counters_ = static_cast<int64_t*>(p);
         zero_counters();
     }
