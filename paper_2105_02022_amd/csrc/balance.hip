@@ -157,7 +157,7 @@ __global__ void k_bal_apply(const uint32_t* __restrict__ keys, const uint32_t* _
     part[v] = t;
     atomicAdd((unsigned long long*)&wt[t], (unsigned long long)c);
     atomicAdd((unsigned long long*)&wt[b], (unsigned long long)(-c));
-    atomicAdd((unsigned long long*)counter, 1ull);
+    spread_add(counter, 1);
 }
 
 }  // namespace
@@ -261,12 +261,12 @@ int32_t balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPS
                 hipLaunchKernelGGL(k_admit_decide, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, tk.p, tv.p, sp.p,
                                    sb.p, ns, wt, cap, adm.p);
                 KMP_LAUNCH_CHECK();
-                int64_t* ctr = c.counters() + 11;
-                c.zero(ctr, sizeof(int64_t));
+                c.zero_spread(SP_BALMOVES);
+                int64_t* ctr = c.spread(SP_BALMOVES);
                 hipLaunchKernelGGL(k_bal_apply, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, tk.p, tv.p, adm.p, ns,
                                    g.vwgt, part, wt, ctr);
                 KMP_LAUNCH_CHECK();
-                nmoved = c.read1(ctr);
+                nmoved = c.read_spread(SP_BALMOVES);
             }
         }
         moved_prev = nmoved > 0;

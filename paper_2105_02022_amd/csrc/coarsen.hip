@@ -22,12 +22,13 @@ __global__ __launch_bounds__(kBlock) void k_count_nonempty(const int64_t* __rest
     __shared__ int32_t cnt;
     if (threadIdx.x == 0) cnt = 0;
     __syncthreads();
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool f = i < n && cw[i] > 0;
-    uint64_t b = ballot64(f);
-    if ((threadIdx.x & 63) == 0 && b) atomicAdd(&cnt, (int32_t)__popcll(b));
+    int32_t local = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        local += cw[i] > 0;
+    for (int d = 32; d > 0; d >>= 1) local += __shfl_xor(local, d, 64);
+    if ((threadIdx.x & 63) == 0 && local) atomicAdd(&cnt, local);
     __syncthreads();
-    if (threadIdx.x == 0 && cnt) atomicAdd((unsigned long long*)out, (unsigned long long)cnt);
+    if (threadIdx.x == 0 && cnt) spread_add(out, cnt);
 }
 
 __global__ void k_singleton_flags(const int32_t* __restrict__ label, const int64_t* __restrict__ cw,
@@ -130,8 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_row_tiers(const int32_t* __restrict_
     __shared__ int32_t h[4];
     if (threadIdx.x < 4) h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c < nc) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nc; c += (int64_t)gridDim.x * blockDim.x) {
         int32_t d = dsum[c];
         uint32_t t = d <= R_T0 ? 0 : d <= R_T1 ? 1 : d <= R_T2 ? 2 : 3;
         key[c] = t;
@@ -246,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
         __syncthreads();
     }
     for (int d = 32; d > 0; d >>= 1) bytes += __shfl_xor(bytes, d, 64);
-    if ((tid & 63) == 0 && bytes) atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)bytes);
+    if ((tid & 63) == 0 && bytes) spread_add(a.bytes_ctr, bytes);
 }
 
 // ---- heavy rows: expand, sort by (row, neighbour), reduce
@@ -364,13 +364,12 @@ __global__ void k_copy_rows(const int32_t* __restrict__ cxadj, const int32_t* __
 
 int32_t count_nonempty(Ctx& c, const int64_t* cw, int32_t n)
 {
-    int64_t* ctr = c.counters();
-    c.zero(ctr + 8, sizeof(int64_t));
-    if (n > 0) {
-        hipLaunchKernelGGL(k_count_nonempty, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, cw, n, ctr + 8);
-        KMP_LAUNCH_CHECK();
-    }
-    return (int32_t)c.read1(ctr + 8);
+    if (n <= 0) return 0;
+    c.zero_spread(SP_NONEMPTY);
+    hipLaunchKernelGGL(k_count_nonempty, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, cw, n,
+                       c.spread(SP_NONEMPTY));
+    KMP_LAUNCH_CHECK();
+    return (int32_t)c.read_spread(SP_NONEMPTY);
 }
 
 int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav)
@@ -439,7 +438,7 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     DBuf<uint32_t> rk(c, nc), rv(c, nc), rk2(c, nc), rv2(c, nc);
     DBuf<int32_t> cnt4(c, 4);
     c.zero(cnt4.p, 4 * sizeof(int32_t));
-    hipLaunchKernelGGL(k_row_tiers, dim3(grid_for(nc)), dim3(kBlock), 0, c.stream, dsum.p, nc, rk.p, rv.p, cnt4.p);
+    hipLaunchKernelGGL(k_row_tiers, dim3(grid_for(nc, kBlock, 256)), dim3(kBlock), 0, c.stream, dsum.p, nc, rk.p, rv.p, cnt4.p);
     KMP_LAUNCH_CHECK();
     radix_sort_pairs(c, rk.p, rv.p, rk2.p, rv2.p, nc, 2);
     int32_t tc[4];
@@ -458,7 +457,7 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     a.tmp_adj = tmp_adj.p;
     a.tmp_w = tmp_w.p;
     a.cdeg = cdeg.p;
-    a.bytes_ctr = c.counters() + kBytesSlot + KMP_PROF_CONTRACT_ROWS;
+    a.bytes_ctr = c.spread(SP_BYTES + KMP_PROF_CONTRACT_ROWS);
     int32_t off = 0;
     if (tc[0] > 0) {
         constexpr int G = 16;

@@ -31,8 +31,7 @@ __global__ __launch_bounds__(kBlock) void k_block_count(const int32_t* __restric
     if (priv)
         for (int i = threadIdx.x; i < nb; i += kBlock) hc[i] = hd[i] = 0;
     __syncthreads();
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) {
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         int32_t b = part[v];
         int32_t d = xadj[v + 1] - xadj[v];
         if (priv) {
@@ -304,6 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_cut(const int32_t* __restrict__ xadj
                                                 const int32_t* __restrict__ adjwgt, const int32_t* __restrict__ part,
                                                 int32_t n, int64_t* out)
 {
+    __shared__ int64_t ws[kBlock / 64];
     int64_t acc = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         const int32_t p = part[v];
@@ -311,7 +311,13 @@ __global__ __launch_bounds__(kBlock) void k_cut(const int32_t* __restrict__ xadj
             if (part[adjncy[e]] != p) acc += adjwgt ? adjwgt[e] : 1;
     }
     for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
-    if ((threadIdx.x & 63) == 0 && acc) atomicAdd((unsigned long long*)out, (unsigned long long)acc);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < kBlock / 64; ++q) t += ws[q];
+        if (t) spread_add(out, t);
+    }
 }
 
 constexpr int64_t kLdsBudget = 64 * 1024;
@@ -337,7 +343,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         c.zero(bstart.p, sizeof(int32_t) * ((size_t)nb + 1));
         c.zero(bdeg.p, sizeof(int32_t) * (size_t)nb);
         DBuf<uint32_t> key(c, n), verts(c, n), k2(c, n), v2(c, n);
-        hipLaunchKernelGGL(k_block_count, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, g.xadj, n, nb,
+        hipLaunchKernelGGL(k_block_count, dim3(grid_for(n, kBlock, 256)), dim3(kBlock), 0, c.stream, part, g.xadj, n, nb,
                            bstart.p, bdeg.p, key.p, verts.p);
         KMP_LAUNCH_CHECK();
         radix_sort_pairs(c, key.p, verts.p, k2.p, v2.p, n, bits_for((uint64_t)(nb - 1)));
@@ -450,21 +456,19 @@ void block_weights(Ctx& c, const DGraph& g, const int32_t* part, int32_t nb, int
 {
     c.zero(wt, sizeof(int64_t) * (size_t)nb);
     if (g.n <= 0) return;
-    hipLaunchKernelGGL(k_block_weights, dim3(grid_for(g.n, kBlock, 1024)), dim3(kBlock), 0, c.stream, part, g.vwgt,
+    hipLaunchKernelGGL(k_block_weights, dim3(grid_for(g.n, kBlock, 256)), dim3(kBlock), 0, c.stream, part, g.vwgt,
                        g.n, nb, wt);
     KMP_LAUNCH_CHECK();
 }
 
 int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part)
 {
-    int64_t* ctr = c.counters();
-    c.zero(ctr + 9, sizeof(int64_t));
-    if (g.n > 0) {
-        hipLaunchKernelGGL(k_cut, dim3(grid_for(g.n, kBlock, 4096)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
-                           g.adjwgt, part, g.n, ctr + 9);
-        KMP_LAUNCH_CHECK();
-    }
-    return c.read1(ctr + 9) / 2;
+    if (g.n <= 0) return 0;
+    c.zero_spread(SP_CUT);
+    hipLaunchKernelGGL(k_cut, dim3(grid_for(g.n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
+                       g.adjwgt, part, g.n, c.spread(SP_CUT));
+    KMP_LAUNCH_CHECK();
+    return c.read_spread(SP_CUT) / 2;
 }
 
 }  // namespace kmp

@@ -186,11 +186,7 @@ int64_t prepare(Ctx& c, const DGraph& g)
     c.read(&xn, g.xadj + g.n, sizeof(int32_t));
     if ((int64_t)xn != g.m) throw Error(KMP_EINVAL, "m != xadj[n]");
     if (g.m > 0 && !g.adjncy) throw Error(KMP_EINVAL, "adjncy is NULL");
-    int64_t* ctr = c.counters();
-    node_weight_sum(c, g.vwgt, g.n, ctr + 13);
-    edge_weight_sum(c, g.adjwgt, g.m, ctr + 14);
-    int64_t sums[2];
-    c.read(sums, ctr + 13, sizeof(sums));
+    int64_t sums[2] = {node_weight_sum(c, g.vwgt, g.n), edge_weight_sum(c, g.adjwgt, g.m)};
     if (sums[0] > INT32_MAX || sums[1] / 2 > INT32_MAX) throw Error(KMP_EOVERFLOW, "weight sum exceeds int32");
     return sums[0];
 }

@@ -119,8 +119,25 @@ struct Prof {
     ~Prof();
 };
 
-// Counter slots (Ctx::counters) receiving algorithmic bytes per class.
-constexpr int kBytesSlot = 16;
+// Spread counters: every logical counter owns 64 slots; a block adds to slot
+// (blockIdx.x & 63) and the host sums the slots.  Atomics on one address from
+// thousands of wavefronts serialise (about 11 ns each), so no hot counter is
+// a single word.
+constexpr int kSpreadSlots = 64;
+enum SpreadCounter {
+    SP_RATED = 0,           // LP rated directed entries
+    SP_BYTES = 1,           // + class: algorithmic bytes per profiling class (16)
+    SP_NONEMPTY = 17,
+    SP_CUT = 18,
+    SP_VSUM = 19,
+    SP_ESUM = 20,
+    SP_BALMOVES = 21,
+    SP_COUNT = 24
+};
+__device__ inline void spread_add(int64_t* base, int64_t v)
+{
+    atomicAdd((unsigned long long*)&base[blockIdx.x & (kSpreadSlots - 1)], (unsigned long long)v);
+}
 
 // ---------------------------------------------------------------- context
 // One per library call: the stream, a pinned host buffer for scalar
@@ -157,6 +174,10 @@ class Ctx {
     // A small device scratch of 64 x int64 counters (zeroed on request).
     int64_t* counters();
     void zero_counters();
+    // Spread counters (zeroed when first used in a call).
+    int64_t* spread(int idx);
+    void zero_spread(int idx);
+    int64_t read_spread(int idx);
 
     Prof* prof = nullptr;  // profiling enabled when non-null
     int prof_begin(int cls);
@@ -180,6 +201,7 @@ class Ctx {
     void* read_buf_ = nullptr;
     size_t read_bytes_ = 0;
     int64_t* counters_ = nullptr;
+    int64_t* spread_ = nullptr;
     void* stage(size_t bytes);
 };
 
@@ -263,10 +285,9 @@ void fill_u8(Ctx& c, uint8_t* p, uint8_t v, int64_t n);
 void fill_i64(Ctx& c, int64_t* p, int64_t v, int64_t n);
 inline void set_i64(Ctx& c, int64_t* p, int64_t v) { fill_i64(c, p, v, 1); }
 void iota_i32(Ctx& c, int32_t* p, int64_t n);
-// Sum of node weights (int64) into *out_dev.
-void node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n, int64_t* out_dev);
-// Sum of edge weights (int64) into *out_dev.
-void edge_weight_sum(Ctx& c, const int32_t* adjwgt, int64_t m, int64_t* out_dev);
+// Sum of node / edge weights (int64; NULL weights count 1 each).
+int64_t node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n);
+int64_t edge_weight_sum(Ctx& c, const int32_t* adjwgt, int64_t m);
 int bits_for(uint64_t max_value);
 
 // ---------------------------------------------------------------- LP (lp.hip)

@@ -34,8 +34,11 @@ constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 constexpr int kSmallCap = 4096;     // contended entries resolved in LDS
 constexpr int kSmallThreads = 1024;
 
-// ctl[] layout (int64, device): round control shared by the kernels
-enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_MOVED = 2, CTL_CONT = 3, CTL_N = 8 };
+// ctl[] layout (int64, device): round control shared by the kernels, then
+// kSpreadSlots per-block move counts (CTL_MS), then the compacted-list segment
+// tables of the next round (read back together once per round)
+enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_CONT = 3, CTL_N = 8, CTL_MS = CTL_N };
+constexpr int kCtlWords = CTL_N + kSpreadSlots + 2 * kSegs;  // int64 words
 
 __device__ inline int tier_of(int32_t d)
 {
@@ -122,7 +125,7 @@ struct RateArgs {
     int32_t* prop;          // [n], -1 = no proposal
     uint32_t* fav;          // [n] or NULL
     uint32_t* demand;       // [nlab]
-    int64_t* counters;      // [0] rated edges
+    int64_t* counters;      // spread counter: rated edges
     int64_t* bytes_ctr;     // algorithmic bytes of this launch's class
     const int64_t* ctl;     // round control (abort flag) or NULL
     const int32_t* list;    // node lists, segments described by segtab
@@ -188,9 +191,8 @@ __device__ inline void flush_stats(const RateArgs& a, int64_t nodes, int64_t edg
         nodes += __shfl_xor(nodes, d, 64);
     }
     if ((threadIdx.x & 63) == 0 && nodes) {
-        atomicAdd((unsigned long long*)&a.counters[0], (unsigned long long)edges);
-        const int64_t bytes = 25 * nodes + (a.adjwgt ? 12 : 8) * edges;
-        atomicAdd((unsigned long long*)a.bytes_ctr, (unsigned long long)bytes);
+        spread_add(a.counters, edges);
+        spread_add(a.bytes_ctr, 25 * nodes + (a.adjwgt ? 12 : 8) * edges);
     }
 }
 
@@ -644,52 +646,61 @@ __global__ void k_decide(const uint32_t* __restrict__ keys, const uint32_t* __re
     acc[vals[i]] = wt[K] + (pre[i] - base[K]) <= cap ? 1 : 0;
 }
 
+// Apply admitted moves.  Moved nodes get mflag[v] = stamp (the round number + 1
+// inside lp_run, so flags never need clearing); per-block move counts go to the
+// spread slots ctl[CTL_MS + (block & 63)].
 __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* __restrict__ list,
                                                   const int32_t* __restrict__ segtab, int s,
                                                   int32_t* __restrict__ prop, uint8_t* __restrict__ acc,
                                                   uint32_t* __restrict__ demand, int32_t* __restrict__ label,
                                                   int64_t* __restrict__ wt, const int32_t* __restrict__ vwgt,
-                                                  uint8_t* __restrict__ moved, int32_t* __restrict__ moved_list)
+                                                  uint8_t* __restrict__ mflag, uint8_t stamp)
 {
+    __shared__ int32_t bm;
     if (ctl[CTL_ABORT]) return;
+    if (threadIdx.x == 0) bm = 0;
+    __syncthreads();
     const ClassSegs cs = class_segs(segtab, s);
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < cs.total; i0 += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = i0 + threadIdx.x;
-        bool mv = false;
-        int32_t v = -1;
-        if (i < cs.total) {
-            v = list[class_pos(cs, i)];
-            const int32_t K = prop[v];
-            if (K >= 0) {
-                if (acc[v] == 1) {
-                    const int64_t c = vwgt ? vwgt[v] : 1;
-                    const int32_t old = label[v];
-                    label[v] = K;
-                    atomicAdd((unsigned long long*)&wt[K], (unsigned long long)c);
-                    atomicAdd((unsigned long long*)&wt[old], (unsigned long long)(-c));
-                    if (moved) moved[v] = 1;
-                    mv = true;
-                }
-                prop[v] = -1;
-                acc[v] = 0;
-                demand[K] = 0;
-            }
+    int32_t mine = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cs.total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = list[class_pos(cs, i)];
+        const int32_t K = prop[v];
+        if (K < 0) continue;
+        if (acc[v] == 1) {
+            const int64_t c = vwgt ? vwgt[v] : 1;
+            const int32_t old = label[v];
+            label[v] = K;
+            atomicAdd((unsigned long long*)&wt[K], (unsigned long long)c);
+            atomicAdd((unsigned long long*)&wt[old], (unsigned long long)(-c));
+            mflag[v] = stamp;
+            ++mine;
         }
-        const int64_t slot = reserve_slot(&ctl[CTL_MOVED], mv);
-        if (mv) moved_list[slot] = v;
+        prop[v] = -1;
+        acc[v] = 0;
+        demand[K] = 0;
     }
+    for (int d = 32; d > 0; d >>= 1) mine += __shfl_xor(mine, d, 64);
+    if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&bm, mine);
+    __syncthreads();
+    if (threadIdx.x == 0 && bm) atomicAdd((unsigned long long*)&ctl[CTL_MS + (blockIdx.x & (kSpreadSlots - 1))], (unsigned long long)bm);
 }
 
-// mark the neighbours of moved nodes active for the next round
-__global__ void k_push_active(const int32_t* __restrict__ moved_list, int64_t nm, const int32_t* __restrict__ xadj,
-                              const int32_t* __restrict__ adjncy, uint8_t* __restrict__ active)
+// mark the neighbours of the nodes moved in this round active for the next one;
+// blockIdx.y selects the segment of the round's lists
+__global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restrict__ list,
+                                                        const int32_t* __restrict__ segtab,
+                                                        const uint8_t* __restrict__ mflag, uint8_t stamp,
+                                                        const int32_t* __restrict__ xadj,
+                                                        const int32_t* __restrict__ adjncy,
+                                                        uint8_t* __restrict__ active)
 {
-    const int lane = threadIdx.x & 15;
-    int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
-    const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 4;
-    for (; w < nm; w += nw) {
-        int32_t v = moved_list[w];
-        for (int32_t e = xadj[v] + lane; e < xadj[v + 1]; e += 16) active[adjncy[e]] = 1;
+    const int seg = blockIdx.y;
+    const int32_t off = segtab[seg], cnt = segtab[kSegs + seg];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t v = list[off + i];
+        if (mflag[v] != stamp) continue;
+        for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e) active[adjncy[e]] = 1;
     }
 }
 
@@ -794,7 +805,7 @@ struct LPBuffers {
     DBuf<uint8_t> acc;
     DBuf<uint32_t> demand;
     DBuf<uint32_t> hub_keys, hub_vals;
-    DBuf<int32_t> moved_list;
+    DBuf<uint8_t> mflag;           // round stamp of the last move of every node
     DBuf<uint32_t> ckeys, cvals;   // contended (target, id), unordered
     DBuf<int64_t> base;            // [nlab] weight before a target's first proposal
     DBuf<int64_t> ctl;
@@ -812,12 +823,13 @@ void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t nlab, 
         b.hub_keys = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
         b.hub_vals = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
     }
-    b.moved_list = DBuf<int32_t>(c, (size_t)g.n);
+    b.mflag = DBuf<uint8_t>(c, (size_t)g.n);
+    c.zero(b.mflag.p, (size_t)g.n);
     b.ckeys = DBuf<uint32_t>(c, (size_t)g.n);
     b.cvals = DBuf<uint32_t>(c, (size_t)g.n);
     b.base = DBuf<int64_t>(c, (size_t)nlab);
-    b.ctl = DBuf<int64_t>(c, CTL_N);
-    c.zero(b.ctl.p, sizeof(int64_t) * CTL_N);
+    b.ctl = DBuf<int64_t>(c, kCtlWords);
+    c.zero(b.ctl.p, sizeof(int64_t) * kCtlWords);
 }
 
 RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpre, LPBuffers* b)
@@ -834,7 +846,7 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
     a.cap_scalar = st.cap_scalar;
     a.hpre = hpre;
     a.fav = st.fav;
-    a.counters = c.counters();
+    a.counters = c.spread(SP_RATED);
     if (b) {
         a.prop = b->prop.p;
         a.demand = b->demand.p;
@@ -847,19 +859,20 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
 
 // Launch the rating kernels of class s over the lists described by segtab;
 // grids are sized by the level's segment sizes (upper bounds of the lists).
-void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const int32_t* list, const int32_t* segtab)
+void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const int32_t* list, const int32_t* segtab,
+                 const int32_t* ubs)
 {
-    int64_t* bytes = c.counters() + kBytesSlot;
+    int64_t* bytes = c.spread(SP_BYTES);
     a.list = list;
     a.segtab = segtab;
     a.hub_off = sched.hub_slot_off.p;
     for (int t = 0; t < kTiers; ++t) {
         const int seg = t * kSub + s;
-        const int32_t ub = sched.cnt[seg];
+        const int32_t ub = ubs[seg];
         if (ub == 0) continue;
         a.seg = seg;
         // LP launches count their algorithmic bytes per class (tier 3 joins tier 2)
-        if (!a.over) a.bytes_ctr = bytes + (t < 3 ? t : t == 3 ? KMP_PROF_RATE_T2 : KMP_PROF_RATE_HUB);
+        if (!a.over) a.bytes_ctr = bytes + kSpreadSlots * (t < 3 ? t : t == 3 ? KMP_PROF_RATE_T2 : KMP_PROF_RATE_HUB);
         switch (t) {
             case 0: {
                 ProfScope ps(c, KMP_PROF_RATE_T0);
@@ -896,10 +909,17 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
     }
 }
 
-void launch_admit(Ctx& c, const LPSchedule& sched, int32_t s, const int32_t* list, const int32_t* segtab,
-                  LPState& st, LPBuffers& b)
+int32_t class_ub(const int32_t* ubs, int32_t s)
 {
-    const int32_t ub = sched.class_size(s);
+    int32_t t = 0;
+    for (int q = 0; q < kTiers; ++q) t += ubs[q * kSub + s];
+    return t;
+}
+
+void launch_admit(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, const int32_t* segtab, LPState& st,
+                  LPBuffers& b)
+{
+    const int32_t ub = class_ub(ubs, s);
     if (ub == 0) return;
     ProfScope ps(c, KMP_PROF_ADMIT);
     hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list,
@@ -916,14 +936,14 @@ void launch_small(Ctx& c, int32_t s, const DGraph& g, LPState& st, LPBuffers& b)
     KMP_LAUNCH_CHECK();
 }
 
-void launch_apply(Ctx& c, const LPSchedule& sched, int32_t s, const int32_t* list, const int32_t* segtab,
-                  const DGraph& g, LPState& st, LPBuffers& b, uint8_t* moved)
+void launch_apply(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, const int32_t* segtab,
+                  const DGraph& g, LPState& st, LPBuffers& b, uint8_t* mflag, uint8_t stamp)
 {
-    const int32_t ub = sched.class_size(s);
+    const int32_t ub = class_ub(ubs, s);
     if (ub == 0) return;
     ProfScope ps(c, KMP_PROF_APPLY);
     hipLaunchKernelGGL(k_apply, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list, segtab,
-                       s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, moved, b.moved_list.p);
+                       s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, mflag, stamp);
     KMP_LAUNCH_CHECK();
 }
 
@@ -963,14 +983,15 @@ void resolve_exact(Ctx& c, const DGraph& g, LPState& st, LPBuffers& b)
 
 // One sub-round on the exact path (host synchronised after admission).
 void subround_exact(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t s, const int32_t* list,
-                    const int32_t* segtab, LPState& st, LPBuffers& b, const RateArgs& a, bool rate, uint8_t* moved)
+                    const int32_t* segtab, const int32_t* ubs, LPState& st, LPBuffers& b, const RateArgs& a,
+                    bool rate, uint8_t* mflag, uint8_t stamp)
 {
     if (rate) {
-        launch_rate(c, a, sched, s, list, segtab);
-        launch_admit(c, sched, s, list, segtab, st, b);
+        launch_rate(c, a, sched, s, list, segtab, ubs);
+        launch_admit(c, ubs, s, list, segtab, st, b);
     }
     resolve_exact(c, g, st, b);
-    launch_apply(c, sched, s, list, segtab, g, st, b, moved);
+    launch_apply(c, ubs, s, list, segtab, g, st, b, mflag, stamp);
 }
 
 }  // namespace
@@ -982,8 +1003,8 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
     if (g.n == 0) return;
     LPState st{const_cast<int32_t*>(part), const_cast<int64_t*>(wt), 0, cap, 0, nullptr, TAG_BAL};
     RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {TAG_BAL, (uint32_t)level, (uint32_t)round}), nullptr);
-    a.counters = c.counters() + 10;                          // not reported for balancing
-    a.bytes_ctr = c.counters() + kBytesSlot + KMP_PROF_OTHER;  // nor counted as LP bytes
+    a.counters = c.spread(SP_BYTES + KMP_PROF_OTHER);  // balancing reports no rated edges
+    a.bytes_ctr = c.spread(SP_BYTES + KMP_PROF_OTHER);  // nor LP bytes
     a.over = over;
     a.bal_t = bal_t;
     a.bal_d = bal_d;
@@ -994,7 +1015,7 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
     }
     a.hub_keys = hk.p;
     a.hub_vals = hv.p;
-    for (int32_t s = 0; s < kSub; ++s) launch_rate(c, a, sched, s, sched.order.p, sched.segtab.p);
+    for (int32_t s = 0; s < kSub; ++s) launch_rate(c, a, sched, s, sched.order.p, sched.segtab.p, sched.cnt);
 }
 
 LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st)
@@ -1005,57 +1026,80 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     LPBuffers b;
     lp_buffers(c, g, sched, st.nlab, b);
     DBuf<uint8_t> active(c, (size_t)n);
-    DBuf<int32_t> alist(c, (size_t)n), flag(c, (size_t)n), pos(c, (size_t)n + 1), segtab_r(c, 2 * kSegs);
+    DBuf<int32_t> alist0(c, (size_t)n), alist1(c, (size_t)n), flag(c, (size_t)n), pos(c, (size_t)n + 1);
+    int32_t* alist[2] = {alist0.p, alist1.p};
+    int32_t* segtab_r[2] = {reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kSpreadSlots),
+                            reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kSpreadSlots) + 2 * kSegs};
     SegBounds bounds;
     for (int j = 0; j <= kSegs; ++j) bounds.off[j] = sched.off[j];
-    int64_t* ctr = c.counters();
-    c.zero(ctr, sizeof(int64_t));  // rated edges
+    c.zero_spread(SP_RATED);
+    int32_t ub[kSegs];
+    memcpy(ub, sched.cnt, sizeof(ub));
+    // enqueue: next-round active set (neighbours of nodes moved in round r) and
+    // its compaction into list buffer q
+    auto enqueue_next_lists = [&](int32_t r, const int32_t* list, const int32_t* segtab, int q) {
+        c.zero(active.p, (size_t)n);
+        int32_t mx = 1;
+        for (int j = 0; j < kSegs; ++j) mx = std::max(mx, ub[j]);
+        {
+            ProfScope ps(c, KMP_PROF_ACTIVE);
+            hipLaunchKernelGGL(k_push_active, dim3(grid_for(mx, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream, list,
+                               segtab, b.mflag.p, (uint8_t)(r + 1), g.xadj, g.adjncy, active.p);
+            KMP_LAUNCH_CHECK();
+        }
+        hipLaunchKernelGGL(k_active_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sched.order.p, n, active.p,
+                           flag.p);
+        KMP_LAUNCH_CHECK();
+        scan_excl_i32(c, flag.p, pos.p, n, pos.p + n);
+        hipLaunchKernelGGL(k_active_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sched.order.p, flag.p,
+                           pos.p, n, alist[q]);
+        KMP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_active_segtab, dim3(1), dim3(64), 0, c.stream, pos.p, bounds, segtab_r[q]);
+        KMP_LAUNCH_CHECK();
+    };
+    struct {
+        int64_t ctl[CTL_N];
+        int64_t moved[kSpreadSlots];
+        int32_t seg[2][2 * kSegs];
+    } h;
+    static_assert(sizeof(h) == sizeof(int64_t) * kCtlWords, "control block layout");
     for (int32_t r = 0; r < kRounds; ++r) {
         out.rounds = r + 1;
-        const int32_t* list = r == 0 ? sched.order.p : alist.p;
-        const int32_t* segtab = r == 0 ? sched.segtab.p : segtab_r.p;
+        const int cur = r & 1, nxt = cur ^ 1;
+        const uint8_t stamp = (uint8_t)(r + 1);
+        const int32_t* list = r == 0 ? sched.order.p : alist[cur];
+        const int32_t* segtab = r == 0 ? sched.segtab.p : segtab_r[cur];
         const RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
         // speculative sub-rounds: no host synchronisation in between
         for (int32_t s = 0; s < kSub; ++s) {
-            launch_rate(c, a, sched, s, list, segtab);
-            launch_admit(c, sched, s, list, segtab, st, b);
+            launch_rate(c, a, sched, s, list, segtab, ub);
+            launch_admit(c, ub, s, list, segtab, st, b);
             launch_small(c, s, g, st, b);
-            launch_apply(c, sched, s, list, segtab, g, st, b, nullptr);
+            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, stamp);
         }
-        int64_t h[CTL_N];
-        c.read(h, b.ctl.p, sizeof(h));
-        if (h[CTL_ABORT]) {
+        const bool more = r + 1 < kRounds;
+        if (more) enqueue_next_lists(r, list, segtab, nxt);
+        c.read(&h, b.ctl.p, sizeof(h));
+        if (h.ctl[CTL_ABORT]) {
             // finish the round on the exact path from the aborted sub-round on
-            const int32_t s0 = (int32_t)h[CTL_ABORT_SUB];
+            // (the current lists are untouched: the next round writes the other buffer)
+            const int32_t s0 = (int32_t)h.ctl[CTL_ABORT_SUB];
             ctl_set(c, b, CTL_ABORT, 0);
-            subround_exact(c, g, sched, s0, list, segtab, st, b, a, false, nullptr);
-            for (int32_t s = s0 + 1; s < kSub; ++s) subround_exact(c, g, sched, s, list, segtab, st, b, a, true, nullptr);
-            c.read(h, b.ctl.p, sizeof(h));
+            subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp);
+            for (int32_t s = s0 + 1; s < kSub; ++s)
+                subround_exact(c, g, sched, s, list, segtab, ub, st, b, a, true, b.mflag.p, stamp);
+            if (more) enqueue_next_lists(r, list, segtab, nxt);
+            c.read(&h, b.ctl.p, sizeof(h));
         }
-        const int64_t nm = h[CTL_MOVED];
+        int64_t nm = 0;
+        for (int q = 0; q < kSpreadSlots; ++q) nm += h.moved[q];
         out.moves[r] = nm;
-        if (nm == 0) break;
-        ctl_set(c, b, CTL_MOVED, 0);
-        if (r + 1 < kRounds) {
-            c.zero(active.p, (size_t)n);
-            {
-                ProfScope ps(c, KMP_PROF_ACTIVE);
-                hipLaunchKernelGGL(k_push_active, dim3(grid_for(nm * 16, kBlock, 8192)), dim3(kBlock), 0, c.stream,
-                                   b.moved_list.p, nm, g.xadj, g.adjncy, active.p);
-                KMP_LAUNCH_CHECK();
-            }
-            hipLaunchKernelGGL(k_active_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sched.order.p, n,
-                               active.p, flag.p);
-            KMP_LAUNCH_CHECK();
-            scan_excl_i32(c, flag.p, pos.p, n, pos.p + n);
-            hipLaunchKernelGGL(k_active_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sched.order.p, flag.p,
-                               pos.p, n, alist.p);
-            KMP_LAUNCH_CHECK();
-            hipLaunchKernelGGL(k_active_segtab, dim3(1), dim3(64), 0, c.stream, pos.p, bounds, segtab_r.p);
-            KMP_LAUNCH_CHECK();
-        }
+        if (nm == 0 || !more) break;
+        c.zero(b.ctl.p + CTL_MS, sizeof(int64_t) * kSpreadSlots);
+        // the next round's lists are exactly sized
+        for (int j = 0; j < kSegs; ++j) ub[j] = h.seg[nxt][kSegs + j];
     }
-    out.rated_edges = c.read1(ctr);
+    out.rated_edges = c.read_spread(SP_RATED);
     return out;
 }
 
@@ -1067,8 +1111,12 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
     lp_buffers(c, g, sched, st.nlab, b);
     RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)round}), &b);
     a.active = active;
-    subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, st, b, a, true, moved);
-    return c.read1(b.ctl.p + CTL_MOVED);
+    subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, sched.cnt, st, b, a, true, moved, 1);
+    int64_t slots[kSpreadSlots];
+    c.read(slots, b.ctl.p + CTL_MS, sizeof(slots));
+    int64_t nm = 0;
+    for (int q = 0; q < kSpreadSlots; ++q) nm += slots[q];
+    return nm;
 }
 
 }  // namespace kmp

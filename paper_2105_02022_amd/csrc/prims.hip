@@ -63,6 +63,7 @@ Ctx::~Ctx()
         for (auto& b : live_) dp.free_blocks[device_].emplace(b.second, b.first);
         for (auto& b : freed_) dp.free_blocks[device_].emplace(b.second, b.first);
         if (counters_) dp.free_blocks[device_].emplace((size_t)512, (void*)counters_);
+        if (spread_) dp.free_blocks[device_].emplace((size_t)SP_COUNT * kSpreadSlots * 8, (void*)spread_);
     }
     std::lock_guard<std::mutex> lk(g_pinned_mu);
     for (auto& c : pinned_chunks_) g_pinned_free.push_back(c);
@@ -224,6 +225,39 @@ int64_t* Ctx::counters()
 
 void Ctx::zero_counters() { zero(counters(), 64 * sizeof(int64_t)); }
 
+int64_t* Ctx::spread(int idx)
+{
+    if (!spread_) {
+        const size_t bytes = (size_t)SP_COUNT * kSpreadSlots * sizeof(int64_t);
+        size_t got = 0;
+        void* p = nullptr;
+        {
+            DevicePool& dp = device_pool();
+            std::lock_guard<std::mutex> lk(dp.mu);
+            p = take_block(dp.free_blocks[device_], bytes, got);
+            if (p && got != bytes) {
+                dp.free_blocks[device_].emplace(got, p);
+                p = nullptr;
+            }
+        }
+        if (!p) KMP_HIP(hipMalloc(&p, bytes));
+        spread_ = static_cast<int64_t*>(p);
+        zero(spread_, bytes);
+    }
+    return spread_ + (size_t)idx * kSpreadSlots;
+}
+
+void Ctx::zero_spread(int idx) { zero(spread(idx), kSpreadSlots * sizeof(int64_t)); }
+
+int64_t Ctx::read_spread(int idx)
+{
+    int64_t v[kSpreadSlots];
+    read(v, spread(idx), sizeof(v));
+    int64_t s = 0;
+    for (int i = 0; i < kSpreadSlots; ++i) s += v[i];
+    return s;
+}
+
 // Events are recycled through a process-wide pool: creating an event costs far
 // more host time than recording one.
 namespace {
@@ -288,7 +322,7 @@ void Ctx::prof_collect(int64_t* launches, double* ms, int64_t* bytes)
         launches[r.cls] += 1;
         ms[r.cls] += t;
     }
-    read(bytes, counters() + kBytesSlot, sizeof(int64_t) * KMP_PROF_CLASSES);
+    for (int i = 0; i < KMP_PROF_CLASSES; ++i) bytes[i] = read_spread(SP_BYTES + i);
 }
 
 int bits_for(uint64_t max_value)
@@ -566,11 +600,18 @@ __global__ void k_iota(int32_t* p, int64_t n)
 
 __global__ __launch_bounds__(kBlock) void k_sum_i32(const int32_t* __restrict__ p, int64_t n, int64_t* out)
 {
+    __shared__ int64_t ws[kBlock / 64];
     int64_t acc = 0;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         acc += p[i];
     for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
-    if ((threadIdx.x & 63) == 0 && acc) atomicAdd((unsigned long long*)out, (unsigned long long)acc);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int q = 0; q < kBlock / 64; ++q) t += ws[q];
+        if (t) spread_add(out, t);
+    }
 }
 
 }  // namespace
@@ -600,33 +641,26 @@ void iota_i32(Ctx& c, int32_t* p, int64_t n)
     KMP_LAUNCH_CHECK();
 }
 
-void node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n, int64_t* out_dev)
+int64_t node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n)
 {
-    c.zero(out_dev, sizeof(int64_t));
-    if (!vwgt) {
-        int64_t v = n;
-        KMP_HIP(hipMemcpyAsync(out_dev, &v, sizeof(v), hipMemcpyHostToDevice, c.stream));
-        KMP_HIP(hipStreamSynchronize(c.stream));
-        return;
-    }
-    if (n <= 0) return;
-    hipLaunchKernelGGL(k_sum_i32, dim3(grid_for(n, kBlock, 2048)), dim3(kBlock), 0, c.stream, vwgt, (int64_t)n,
-                       out_dev);
+    if (!vwgt) return n;
+    if (n <= 0) return 0;
+    c.zero_spread(SP_VSUM);
+    hipLaunchKernelGGL(k_sum_i32, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, vwgt, (int64_t)n,
+                       c.spread(SP_VSUM));
     KMP_LAUNCH_CHECK();
+    return c.read_spread(SP_VSUM);
 }
 
-void edge_weight_sum(Ctx& c, const int32_t* adjwgt, int64_t m, int64_t* out_dev)
+int64_t edge_weight_sum(Ctx& c, const int32_t* adjwgt, int64_t m)
 {
-    c.zero(out_dev, sizeof(int64_t));
-    if (!adjwgt) {
-        int64_t v = m;
-        KMP_HIP(hipMemcpyAsync(out_dev, &v, sizeof(v), hipMemcpyHostToDevice, c.stream));
-        KMP_HIP(hipStreamSynchronize(c.stream));
-        return;
-    }
-    if (m <= 0) return;
-    hipLaunchKernelGGL(k_sum_i32, dim3(grid_for(m, kBlock, 2048)), dim3(kBlock), 0, c.stream, adjwgt, m, out_dev);
+    if (!adjwgt) return m;
+    if (m <= 0) return 0;
+    c.zero_spread(SP_ESUM);
+    hipLaunchKernelGGL(k_sum_i32, dim3(grid_for(m, kBlock, 1024)), dim3(kBlock), 0, c.stream, adjwgt, m,
+                       c.spread(SP_ESUM));
     KMP_LAUNCH_CHECK();
+    return c.read_spread(SP_ESUM);
 }
 
 }  // namespace kmp
