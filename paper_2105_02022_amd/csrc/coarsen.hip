@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
     uint32_t* keys = s_keys + grp * HS;
     uint32_t* vals = s_vals + grp * HS;
     int64_t bytes = 0;
-    for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
+    for (int64_t base = (int64_t)xcd_block() * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
         const int64_t i = base + grp;
         const int32_t row = i < count ? rows[i] : -1;
         for (int j = gl; j < HS; j += G) {

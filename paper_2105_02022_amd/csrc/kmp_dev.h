@@ -100,6 +100,20 @@ __device__ inline uint32_t slot_of(uint32_t key, int bits)
 
 constexpr int kBlock = 256;
 
+// XCD-aware work mapping.  Workgroups are dispatched round-robin over the 8
+// XCDs of the chip (physical block b runs on XCD b % 8) and every XCD has its
+// own L2.  Renumbering so that XCD x owns one contiguous range of logical
+// blocks keeps neighbouring nodes (which share label / weight cache lines) on
+// one L2.  Bijective on [0, gridDim.x).
+constexpr uint32_t kXcds = 8;
+__device__ inline uint32_t xcd_block()
+{
+    const uint32_t b = blockIdx.x, G = gridDim.x;
+    const uint32_t q = G / kXcds, r = G % kXcds;
+    const uint32_t x = b % kXcds, k = b / kXcds;
+    return x * q + (x < r ? x : r) + k;
+}
+
 inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 1u << 20)
 {
     int64_t g = (items + per_block - 1) / per_block;

@@ -197,26 +197,46 @@ __device__ inline void flush_stats(const RateArgs& a, int64_t nodes, int64_t edg
 }
 
 // Tier 0: one lane per node; labels and weights of the <= 16 neighbours live in
-// registers, duplicates are merged into their first occurrence, and the weight
-// (and cap) gathers of all candidates are issued together.
+// registers.  Loads use clamped indices so that they are unconditional and the
+// compiler issues each batch (neighbour ids, labels, candidate weights) back to
+// back with a single wait; duplicates are merged into their first occurrence
+// with selects.  EW: edge weights present; CAPV: per-label caps; BAL: balance
+// mode.
+template <bool EW, bool CAPV, bool BAL>
 __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
 {
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     int64_t edges = 0, nodes = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+    for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = a.list[off + i];
-        if (!node_selected(a, v)) continue;
+        const uint32_t own = (uint32_t)a.label[v];
+        if (BAL) {
+            if (!a.over[own]) continue;
+        } else if (a.active && !a.active[v]) {
+            continue;
+        }
         const int32_t e0 = a.xadj[v];
         const int32_t d = a.xadj[v + 1] - e0;
+        const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
         uint32_t lab[T0_DEG], w[T0_DEG];
+        if (d > 0) {
+            int32_t u[T0_DEG];
 #pragma unroll
-        for (int j = 0; j < T0_DEG; ++j) {
-            if (j < d) {
-                lab[j] = (uint32_t)a.label[a.adjncy[e0 + j]];
-                w[j] = a.adjwgt ? (uint32_t)a.adjwgt[e0 + j] : 1u;
-            } else {
+            for (int j = 0; j < T0_DEG; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
+#pragma unroll
+            for (int j = 0; j < T0_DEG; ++j) lab[j] = (uint32_t)a.label[u[j]];
+#pragma unroll
+            for (int j = 0; j < T0_DEG; ++j) w[j] = EW ? (uint32_t)a.adjwgt[e0 + (j < d ? j : d - 1)] : 1u;
+#pragma unroll
+            for (int j = 0; j < T0_DEG; ++j) {
+                lab[j] = j < d ? lab[j] : EMPTY;
+                w[j] = j < d ? w[j] : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < T0_DEG; ++j) {
                 lab[j] = EMPTY;
                 w[j] = 0;
             }
@@ -230,28 +250,28 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
                 w[q] += hit ? w[k] : 0u;
                 dup = dup || hit;
             }
-            if (dup) lab[k] = EMPTY;
+            lab[k] = dup ? EMPTY : lab[k];
         }
-        const uint32_t own = (uint32_t)a.label[v];
-        const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
-        bool fit[T0_DEG];
+        // weight (and cap / overload flag) of every candidate, one batch of loads
+        int64_t wk[T0_DEG];
 #pragma unroll
-        for (int j = 0; j < T0_DEG; ++j) {
-            const bool cand = lab[j] != EMPTY && lab[j] != own;
-            fit[j] = cand && a.wt[lab[j]] + cv <= cap_of(a, lab[j]) && !(a.over && a.over[lab[j]]);
-        }
+        for (int j = 0; j < T0_DEG; ++j) wk[j] = a.wt[lab[j] != EMPTY ? lab[j] : own];
+        int64_t ck[T0_DEG];
+#pragma unroll
+        for (int j = 0; j < T0_DEG; ++j) ck[j] = CAPV ? a.cap_vec[lab[j] != EMPTY ? lab[j] : own] : a.cap_scalar;
+        bool ov[T0_DEG];
+#pragma unroll
+        for (int j = 0; j < T0_DEG; ++j) ov[j] = BAL ? a.over[lab[j] != EMPTY ? lab[j] : own] != 0 : false;
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0;
 #pragma unroll
         for (int j = 0; j < T0_DEG; ++j) {
-            if (lab[j] == EMPTY) continue;
-            if (lab[j] == own) {
-                rown = w[j];
-                continue;
-            }
+            const bool is_own = lab[j] == own;
+            rown = is_own ? w[j] : rown;
+            const bool cand = lab[j] != EMPTY && !is_own;
             const Key3 c{w[j], hash_step(a.hpre, lab[j], 4), lab[j]};
-            if (better(c, fav)) fav = c;
-            if (fit[j] && better(c, adm)) adm = c;
+            if (cand && better(c, fav)) fav = c;
+            if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
         }
         write_result(a, v, fav, adm, rown, cv);
         edges += d;
@@ -291,7 +311,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
     uint32_t* keys = s_keys + grp * HS;
     uint32_t* vals = s_vals + grp * HS;
     int64_t edges = 0, nodes = 0;
-    for (int64_t base = (int64_t)blockIdx.x * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
+    for (int64_t base = (int64_t)xcd_block() * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
         const int64_t i = base + grp;
         int32_t v = -1;
         if (i < count) {
@@ -364,7 +384,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     const int tid = threadIdx.x;
     int64_t edges = 0, nodes = 0;
-    for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+    for (int64_t i = xcd_block(); i < count; i += gridDim.x) {
         const int32_t v = a.list[off + i];
         if (!node_selected(a, v)) continue;  // uniform across the block
         const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
@@ -484,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void k_admit_fast(int64_t* ctl, const int32
 {
     if (ctl[CTL_ABORT]) return;
     const ClassSegs cs = class_segs(segtab, s);
-    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < cs.total; i0 += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i0 = (int64_t)xcd_block() * blockDim.x; i0 < cs.total; i0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = i0 + threadIdx.x;
         bool cont = false;
         int32_t v = -1, K = -1;
@@ -662,7 +682,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
     __syncthreads();
     const ClassSegs cs = class_segs(segtab, s);
     int32_t mine = 0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cs.total;
+    for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < cs.total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = list[class_pos(cs, i)];
         const int32_t K = prop[v];
@@ -697,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restric
 {
     const int seg = blockIdx.y;
     const int32_t off = segtab[seg], cnt = segtab[kSegs + seg];
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = list[off + i];
         if (mflag[v] != stamp) continue;
         for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e) active[adjncy[e]] = 1;
@@ -876,7 +896,18 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
         switch (t) {
             case 0: {
                 ProfScope ps(c, KMP_PROF_RATE_T0);
-                hipLaunchKernelGGL(k_rate_lane, dim3(grid_for(ub, kBlock, 65536)), dim3(kBlock), 0, c.stream, a);
+                const dim3 grid(grid_for(ub, kBlock, 65536));
+                const bool ew = a.adjwgt != nullptr;
+                if (a.over) {
+                    if (ew) hipLaunchKernelGGL((k_rate_lane<true, true, true>), grid, dim3(kBlock), 0, c.stream, a);
+                    else hipLaunchKernelGGL((k_rate_lane<false, true, true>), grid, dim3(kBlock), 0, c.stream, a);
+                } else if (a.cap_vec) {
+                    if (ew) hipLaunchKernelGGL((k_rate_lane<true, true, false>), grid, dim3(kBlock), 0, c.stream, a);
+                    else hipLaunchKernelGGL((k_rate_lane<false, true, false>), grid, dim3(kBlock), 0, c.stream, a);
+                } else {
+                    if (ew) hipLaunchKernelGGL((k_rate_lane<true, false, false>), grid, dim3(kBlock), 0, c.stream, a);
+                    else hipLaunchKernelGGL((k_rate_lane<false, false, false>), grid, dim3(kBlock), 0, c.stream, a);
+                }
                 break;
             }
             case 1: {
