@@ -11,8 +11,10 @@ value = (directed entries rated by LP + directed entries contracted) per
 second of whole-step wall time ("LP+contraction edges/s").
 
 roofline: the dominant kernel class (most summed HIP-event time among the
-classes with algorithmic byte counts), its algorithmic bytes per launch over
-its average launch duration, against 8 TB/s.  traffic: HBM bytes per launch
+classes with algorithmic byte counts, events recorded around those launches
+during the timed steps), its algorithmic bytes per launch over its average
+launch duration, against 8 TB/s.  class_ms_per_step comes from one extra
+untimed step with every class timed.  traffic: HBM bytes per launch
 from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if present.
 
 cpu_baseline: the CPU oracle (single thread) on the same workload.
@@ -43,34 +45,29 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_from_profiles(kernel_symbol):
-    """HBM bytes per launch of `kernel_symbol` from the committed rocprofv3 PMC summary."""
-    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
-    if not os.path.exists(path):
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_rgg20.md")
+
+# kernel classes whose launches count algorithmic bytes (LP rating tiers, contraction rows)
+BYTE_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "contract_rows"]
+
+# profiling class -> kernel family, where every launch of the class is a launch of that family
+KERNEL_OF_CLASS = {"rate_t0": "k_rate_lane", "rate_hub": "k_rate_hub", "contract_rows": "k_contract_rows"}
+
+
+def traffic_from_profiles(family):
+    """HBM bytes per launch of a kernel family from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary (the JSON block at its end), or None if absent or taken on other kernel sources."""
+    from paper_2105_02022_amd.profsum import source_hash
+    if family is None or not os.path.exists(TRAFFIC_SUMMARY):
         return None
-    try:
-        d = json.load(open(path))
-        e = d.get("kernels", {}).get(kernel_symbol)
-        if not e or d.get("source_hash") != _source_hash():
-            return None
-        return e["hbm_bytes_per_launch"]
-    except Exception:
+    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_SUMMARY).read(), re.S)
+    if not m:
         return None
-
-
-def _source_hash():
-    import hashlib
-    h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2105_02022_amd", "csrc"))):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(ROOT, "paper_2105_02022_amd", "csrc", f), "rb").read())
-    return h.hexdigest()[:16]
-
-
-KERNEL_OF_CLASS = {
-    "rate_t0": "k_rate_lane", "rate_t1": "k_rate_lds<16, 7>", "rate_t2": "k_rate_lds<64, 10>",
-    "rate_hub": "k_rate_hub", "contract_rows": "k_contract_rows",
-}
+    d = json.loads(m.group(1))
+    e = d.get("kernels", {}).get(family)
+    if not e or d.get("source_hash") != source_hash():
+        return None
+    return e["hbm_bytes_per_launch"]
 
 
 def main():
@@ -94,13 +91,17 @@ def main():
     print(f"# graph n={g.n} m={g.m} maxdeg={g.maxdeg}; warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     for _ in range(args.warmup):
-        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True)
+        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out)
         assert rc == 0, kmp.kmp_strerror(rc)
+    # one untimed step with every kernel class timed: the per-class breakdown
+    _, _, st_all = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True)
     torch.cuda.synchronize()
+    # timed steps: HIP events only around the launches of the classes that count algorithmic bytes
     stats = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True)
+        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True,
+                                         profile_classes=BYTE_CLASSES)
         stats.append(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -115,17 +116,18 @@ def main():
     ms_c = {c: sum(s["prof"][c]["ms"] for s in stats) for c in classes}
     by_c = {c: sum(s["prof"][c]["bytes"] for s in stats) for c in classes}
     ln_c = {c: sum(s["prof"][c]["launches"] for s in stats) for c in classes}
-    dom = max((c for c in classes if by_c[c] > 0), key=lambda c: ms_c[c])
+    dom = max((c for c in BYTE_CLASSES if by_c[c] > 0), key=lambda c: ms_c[c])
     avg_ms = ms_c[dom] / ln_c[dom]
     bytes_per_launch = by_c[dom] / ln_c[dom]
     achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(KERNEL_OF_CLASS.get(dom, dom))
+    traffic = traffic_from_profiles(KERNEL_OF_CLASS.get(dom))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": KERNEL_OF_CLASS.get(dom, dom), "class": dom,
                 "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": ln_c[dom] / args.steps,
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                "class_ms_per_step": {c: round(ms_c[c] / args.steps, 3) for c in classes if ln_c[c]}}
+                "class_ms_per_step": {c: round(st_all["prof"][c]["ms"], 3) for c in classes
+                                      if st_all["prof"][c]["launches"]}}
     cpu = None
     parity = None
     if not args.no_cpu_baseline:

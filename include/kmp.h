@@ -58,7 +58,8 @@ typedef struct kmp_options {
     int32_t validate;       /* 1: check the CSR on the device first (KMP_EGRAPH on failure) */
     int32_t profile;        /* 1: time kernel classes with HIP events (fills kmp_stats.prof_*);
                                2: also synchronise at phase boundaries for the ms_* phase timers */
-    int32_t reserved[6];
+    uint32_t profile_classes; /* bit i set: time class i only (fewer event records); 0: all classes */
+    int32_t reserved[5];
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */

@@ -27,7 +27,8 @@ PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "
 
 
 class KmpOptions(ctypes.Structure):
-    _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+    _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
+                ("reserved", ctypes.c_int32 * 5)]
 
 
 class KmpStats(ctypes.Structure):
@@ -131,8 +132,10 @@ def kmp_partition(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, see
 
 
 def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
-                     stream=None, validate: bool = False, profile: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
-    """Returns (status, out_part, stats dict)."""
+                     stream=None, validate: bool = False, profile: bool = False,
+                     profile_classes=None) -> Tuple[int, "torch.Tensor", Dict]:
+    """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
+    (None: all)."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -141,6 +144,8 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt = KmpOptions()
     opt.validate = int(validate)
     opt.profile = int(profile)
+    if profile_classes:
+        opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
     rc = library().kmp_partition_ex(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
                                     epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream), ctypes.byref(opt),

@@ -201,6 +201,7 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
     const bool phase_sync = opt && opt->profile >= 2;  // phase timers wait for the device (profile = 2)
     if (opt && opt->profile) {
         prof.reset(new Prof());
+        prof->mask = opt->profile_classes;
         c.prof = prof.get();
     }
     const int64_t cV = prepare(c, g0);

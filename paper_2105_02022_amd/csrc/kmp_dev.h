@@ -130,6 +130,7 @@ struct Prof {
         hipEvent_t a, b;
     };
     std::vector<Rec> recs;
+    uint32_t mask = 0;  // classes to time (0: all)
     ~Prof();
 };
 

@@ -398,6 +398,9 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
             keys[j] = EMPTY;
             vals[j] = 0;
         }
+        // the table lives in global memory: make the clears (and below, the
+        // atomics) complete at device scope before other waves use the slots
+        __threadfence();
         __syncthreads();
         for (int32_t e = e0 + tid; e < e1; e += kBlock) {
             uint32_t K = (uint32_t)a.label[a.adjncy[e]];
@@ -413,6 +416,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
                 h = (h + 1) & mask;
             }
         }
+        __threadfence();
         __syncthreads();
         const uint32_t own = (uint32_t)a.label[v];
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
@@ -891,11 +895,12 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
         const int32_t ub = ubs[seg];
         if (ub == 0) continue;
         a.seg = seg;
-        // LP launches count their algorithmic bytes per class (tier 3 joins tier 2)
+        // LP launches count their algorithmic bytes per class (tier 3 joins tier 2); the
+        // balancer's rating launches are timed under the balance class and count no LP bytes
         if (!a.over) a.bytes_ctr = bytes + kSpreadSlots * (t < 3 ? t : t == 3 ? KMP_PROF_RATE_T2 : KMP_PROF_RATE_HUB);
         switch (t) {
             case 0: {
-                ProfScope ps(c, KMP_PROF_RATE_T0);
+                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_T0);
                 const dim3 grid(grid_for(ub, kBlock, 65536));
                 const bool ew = a.adjwgt != nullptr;
                 if (a.over) {
@@ -912,26 +917,26 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
             }
             case 1: {
                 constexpr int G = 16;
-                ProfScope ps(c, KMP_PROF_RATE_T1);
+                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_T1);
                 hipLaunchKernelGGL((k_rate_lds<G, 7>), dim3(grid_for(ub, kBlock / G, 65536)), dim3(kBlock), 0,
                                    c.stream, a);
                 break;
             }
             case 2: {
                 constexpr int G = 64;
-                ProfScope ps(c, KMP_PROF_RATE_T2);
+                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_T2);
                 hipLaunchKernelGGL((k_rate_lds<G, 10>), dim3(grid_for(ub, kBlock / G, 65536)), dim3(kBlock), 0,
                                    c.stream, a);
                 break;
             }
             case 3: {
-                ProfScope ps(c, KMP_PROF_RATE_T2);
+                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_T2);
                 hipLaunchKernelGGL((k_rate_lds<256, 13>), dim3(grid_for(ub, 1, 65536)), dim3(kBlock), 0, c.stream,
                                    a);
                 break;
             }
             default: {
-                ProfScope ps(c, KMP_PROF_RATE_HUB);
+                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_HUB);
                 hipLaunchKernelGGL(k_rate_hub, dim3(grid_for(ub, 1, 4096)), dim3(kBlock), 0, c.stream, a);
                 break;
             }

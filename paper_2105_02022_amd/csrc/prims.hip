@@ -291,7 +291,7 @@ Prof::~Prof()
 
 int Ctx::prof_begin(int cls)
 {
-    if (!prof) return -1;
+    if (!prof || (prof->mask && !((prof->mask >> cls) & 1u))) return -1;
     Prof::Rec r{cls, take_event(), nullptr};
     KMP_HIP(hipEventRecord(r.a, stream));
     prof->recs.push_back(r);

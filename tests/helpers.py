@@ -82,3 +82,29 @@ def path(n):
     for i in range(n - 1):
         A[i, i + 1] = A[i + 1, i] = 1
     return A
+
+
+def with_hubs(g, degrees, seed):
+    """`g` plus one new vertex per entry of `degrees`, each joined to that many
+    distinct random vertices of `g` (unit weights; symmetric; sorted rows)."""
+    from paper_2105_02022_amd.gen import Graph
+    assert g.vwgt is None and g.adjwgt is None
+    rng = np.random.default_rng(seed)
+    n0 = g.n
+    src = np.repeat(np.arange(n0, dtype=np.int64), np.diff(g.xadj))
+    dst = np.asarray(g.adjncy, np.int64)
+    us, vs = [src], [dst]
+    for h, d in enumerate(degrees):
+        nb = rng.choice(n0, size=d, replace=False).astype(np.int64)
+        hub = np.full(d, n0 + h, np.int64)
+        us += [hub, nb]
+        vs += [nb, hub]
+    u = np.concatenate(us)
+    v = np.concatenate(vs)
+    n = n0 + len(degrees)
+    key = np.unique(u * n + v)
+    u, v = key // n, key % n
+    xadj = np.zeros(n + 1, np.int64)
+    np.add.at(xadj, u + 1, 1)
+    return Graph(np.cumsum(xadj).astype(np.int32), v.astype(np.int32), None, None, "hubs",
+                 int(np.diff(np.cumsum(xadj)).max()))

@@ -2,6 +2,9 @@
 oracle on the same seeded inputs.  All arithmetic is integer, so the bar is
 bit-exact equality (labels, weights, favoured clusters, coarse CSR, block
 tables, partitions, cuts)."""
+import hashlib
+import json
+import os
 import sys
 
 import numpy as np
@@ -9,7 +12,7 @@ import pytest
 
 import oracle
 from paper_2105_02022_amd import gen
-from tests.helpers import csr_from_dense, node_w, two_cliques
+from tests.helpers import csr_from_dense, node_w, two_cliques, with_hubs
 
 pytestmark = pytest.mark.gpu
 
@@ -153,18 +156,25 @@ def test_contract_heavy_rows(kmp):
     _check_contract(kmp, gw, rng.integers(0, 25, gw.n).astype(np.int32), "weighted/25 clusters")
 
 
-def test_hub_rating(kmp):
-    # star-heavy RMAT: degrees above 2048 use the global-hash tier
-    g = gen.rmat(14, 8 << 14, seed=3)
-    assert g.maxdeg > 2048
-    U, level, seed = 6, 0, 9
-    say(f"[lp_cluster hubs] rmat14 maxdeg={g.maxdeg}")
-    exp_label, exp_cw, exp_fav, exp_moves, exp_rounds = oracle.lp_cluster(g, level, U, seed)
-    xadj, adjncy, vwgt, adjwgt = dev(g)
-    rounds, label, cw, fav, moves = kmp.kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, level, U, seed)
-    assert rounds == exp_rounds and moves == list(exp_moves)
-    assert np.array_equal(label.cpu().numpy(), exp_label)
-    assert np.array_equal(fav.cpu().numpy().view(np.uint32), exp_fav)
+def hub_graphs():
+    # degrees above 4096 take the one-workgroup-per-node tier with a global hash
+    return [("rgg20000+hubs", with_hubs(gen.rgg(20000, 8.0, 5), [4097, 6000, 15000], seed=2)),
+            ("rmat16", gen.rmat(16, 8 << 16, seed=3))]
+
+
+@pytest.mark.parametrize("gi", range(2))
+def test_hub_rating(kmp, gi):
+    name, g = hub_graphs()[gi]
+    assert int(np.diff(g.xadj).max()) > 4096
+    for U, level, seed in ((6, 0, 9), (40, 2, 4)):
+        say(f"[lp_cluster hubs] {name} maxdeg={int(np.diff(g.xadj).max())} U={U}")
+        exp_label, exp_cw, exp_fav, exp_moves, exp_rounds = oracle.lp_cluster(g, level, U, seed)
+        xadj, adjncy, vwgt, adjwgt = dev(g)
+        rounds, label, cw, fav, moves = kmp.kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, level, U, seed)
+        assert rounds == exp_rounds and moves == list(exp_moves)
+        assert np.array_equal(label.cpu().numpy(), exp_label)
+        assert np.array_equal(fav.cpu().numpy().view(np.uint32), exp_fav)
+        _check_contract(kmp, g, exp_label, name)
 
 
 # ------------------------------------------------------------------ bipartition, balance, refine
@@ -298,4 +308,41 @@ def test_partition_rgg_full(kmp):
     """RGG 2^20, k = 64: the benchmark workload, end to end."""
     g = gen.workload("rgg20")
     stats = _e2e(kmp, g, 64, 0.03, 1, "rgg20 (n=2^20)")
+    say(f"  cut={stats['cut']} ms={stats['ms_total']:.1f}")
+
+
+@pytest.mark.parametrize("gi,k", [(0, 8), (0, 64), (1, 16)])
+def test_partition_hubs(kmp, gi, k):
+    name, g = hub_graphs()[gi]
+    _e2e(kmp, g, k, 0.03, 5, name)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _sha(a):
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+@pytest.mark.parametrize("case", sorted(f[:-5] for f in os.listdir(GOLDEN) if f.endswith(".json")))
+def test_partition_golden(kmp, case):
+    """Full-size workloads against stored oracle results (tests/golden/make_golden.py)."""
+    exp = json.load(open(os.path.join(GOLDEN, case + ".json")))
+    g = gen.workload(exp["workload"])
+    gx = exp["graph"]
+    assert (g.n, g.m) == (gx["n"], gx["m"])
+    assert _sha(np.asarray(g.xadj, np.int32)) == gx["xadj_sha256"]
+    assert _sha(np.asarray(g.adjncy, np.int32)) == gx["adjncy_sha256"]
+    k = exp["k"]
+    say(f"[golden] {case}: n={g.n} m={g.m} k={k}")
+    rc, part, stats = kmp.partition(g, k, exp["eps"], exp["seed"])
+    assert rc == exp["status"]
+    bw = np.bincount(part, minlength=k).astype(np.int64)
+    assert stats["cut"] == exp["stats"]["cut"]
+    assert stats["levels"] == exp["stats"]["levels"]
+    assert stats["level_n"] == exp["stats"]["level_n"]
+    assert stats["level_m"] == exp["stats"]["level_m"]
+    assert stats["max_block_weight"] == exp["stats"]["max_block_weight"]
+    assert _sha(bw) == exp["block_weights_sha256"]
+    assert _sha(np.asarray(part, np.int32)) == exp["part_sha256"]
     say(f"  cut={stats['cut']} ms={stats['ms_total']:.1f}")
