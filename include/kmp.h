@@ -131,6 +131,47 @@ int kmp_partition_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* 
                      int32_t n, int64_t m, int32_t k, double epsilon, uint64_t seed, int32_t* out_part,
                      void* stream, const kmp_options* opt, kmp_stats* stats);
 
+/* One job of a batch: a graph in the layout above plus its own k, eps, seed
+ * and output array (all device pointers owned by the caller). */
+typedef struct kmp_graph_desc {
+    const int32_t* xadj;
+    const int32_t* adjncy;
+    const int32_t* vwgt;    /* NULL = unit */
+    const int32_t* adjwgt;  /* NULL = unit */
+    int32_t n;
+    int32_t k;
+    int64_t m;              /* = xadj[n] */
+    double epsilon;
+    uint64_t seed;
+    int32_t* out_part;      /* [n], values in [0, k) */
+} kmp_graph_desc;
+
+/* Per-job result of kmp_partition_batch (host memory). */
+typedef struct kmp_job_result {
+    int32_t status;                       /* KMP_OK, KMP_IMBALANCED or a negative code for this job */
+    int32_t levels;                       /* number of contractions                          */
+    int64_t cut;
+    int64_t max_block_weight;
+    int64_t lk;
+    int32_t level_n[KMP_MAX_LEVELS + 1];  /* nodes per level                                 */
+} kmp_job_result;
+
+/*
+ * kmp_partition_batch: partition `count` independent graphs in one pass of
+ * the hot path.  The jobs run level by level as one disjoint union of their
+ * level graphs (the paper's algorithm per job, Alg. 1 / Alg. 2, Sec. 5), so
+ * one kernel launch serves every job that is at that step; each job's output
+ * equals what kmp_partition returns for it alone (same graph, k, eps, seed).
+ * A job with invalid arguments gets its error code in results[i].status and
+ * does not stop the others.  results may be NULL; opt / stats as for
+ * kmp_partition_ex (stats: counters summed over the batch, cut = sum of cuts).
+ * The call synchronises `stream` before returning.  Returns KMP_OK once every
+ * job has its status, or a negative code for the call itself (count < 0,
+ * graphs == NULL with count > 0, HIP errors, device memory exhausted).
+ */
+int kmp_partition_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_result* results, void* stream,
+                        const kmp_options* opt, kmp_stats* stats);
+
 /* Human-readable text for a status code (static storage). */
 const char* kmp_strerror(int code);
 

@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Dict, Optional, Sequence, Tuple
+from typing import Dict, List, Optional, Sequence, Tuple
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkmp.so")
@@ -49,10 +49,24 @@ _i32, _i64, _u32, _u64, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, 
 _P32 = ctypes.POINTER(ctypes.c_int32)
 _P64 = ctypes.POINTER(ctypes.c_int64)
 
+class KmpGraphDesc(ctypes.Structure):
+    _fields_ = [("xadj", ctypes.c_void_p), ("adjncy", ctypes.c_void_p), ("vwgt", ctypes.c_void_p),
+                ("adjwgt", ctypes.c_void_p), ("n", ctypes.c_int32), ("k", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("epsilon", ctypes.c_double), ("seed", ctypes.c_uint64), ("out_part", ctypes.c_void_p)]
+
+
+class KmpJobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("levels", ctypes.c_int32), ("cut", ctypes.c_int64),
+                ("max_block_weight", ctypes.c_int64), ("lk", ctypes.c_int64),
+                ("level_n", ctypes.c_int32 * (MAX_LEVELS + 1))]
+
+
 SIGNATURES = {
     "kmp_partition": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp]),
     "kmp_partition_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp,
                                         ctypes.POINTER(KmpOptions), ctypes.POINTER(KmpStats)]),
+    "kmp_partition_batch": (ctypes.c_int, [ctypes.POINTER(KmpGraphDesc), _i32, ctypes.POINTER(KmpJobResult), _vp,
+                                           ctypes.POINTER(KmpOptions), ctypes.POINTER(KmpStats)]),
     "kmp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kmp_version": (ctypes.c_char_p, []),
     "kmp_lp_cluster": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _i64, _u64, _vp, _vp, _vp, _P64, _vp]),
@@ -150,6 +164,11 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     rc = library().kmp_partition_ex(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
                                     epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream), ctypes.byref(opt),
                                     ctypes.byref(st))
+    stats = _stats_dict(st, profile)
+    return rc, out, stats
+
+
+def _stats_dict(st: "KmpStats", profile: bool) -> Dict:
     L = st.levels
     stats = {f[0]: getattr(st, f[0]) for f in KmpStats._fields_
              if not f[0].startswith(("reserved", "prof_", "level_"))}
@@ -158,7 +177,40 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     if profile:
         stats["prof"] = {name: {"launches": st.prof_launches[i], "ms": st.prof_ms[i], "bytes": st.prof_bytes[i]}
                          for i, name in enumerate(PROF_CLASSES)}
-    return rc, out, stats
+    return stats
+
+
+def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool = False,
+                        profile_classes=None) -> Tuple[int, List[Dict], Dict]:
+    """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
+    xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
+    Returns (call status, per-job result dicts, aggregate stats)."""
+    _check_i32(*[j.get(f) for j in jobs for f in ("xadj", "adjncy", "vwgt", "adjwgt", "out")])
+    descs = (KmpGraphDesc * max(len(jobs), 1))()
+    for i, j in enumerate(jobs):
+        d = descs[i]
+        d.xadj, d.adjncy = _ptr(j["xadj"]), _ptr(j["adjncy"])
+        d.vwgt, d.adjwgt = _ptr(j.get("vwgt")), _ptr(j.get("adjwgt"))
+        d.n = j["xadj"].numel() - 1
+        d.m = j["adjncy"].numel()
+        d.k = int(j["k"])
+        d.epsilon = float(j.get("epsilon", 0.03))
+        d.seed = int(j.get("seed", 1)) & (2**64 - 1)
+        d.out_part = _ptr(j["out"])
+    res = (KmpJobResult * max(len(jobs), 1))()
+    opt = KmpOptions()
+    opt.validate = int(validate)
+    opt.profile = int(profile)
+    if profile_classes:
+        opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
+    st = KmpStats()
+    rc = library().kmp_partition_batch(descs, len(jobs), res, _stream(stream), ctypes.byref(opt), ctypes.byref(st))
+    out = []
+    for i in range(len(jobs)):
+        r = res[i]
+        out.append({"status": r.status, "levels": r.levels, "cut": r.cut, "max_block_weight": r.max_block_weight,
+                    "lk": r.lk, "level_n": list(r.level_n[:r.levels + 1])})
+    return rc, out, _stats_dict(st, profile)
 
 
 def kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, level: int, U: int, seed: int, stream=None):

@@ -23,8 +23,10 @@ namespace kmp {
 
 namespace {
 
+// tstar: fallback block (one graph); batches: gtstar[bjob[b]] per job
 __global__ void k_bal_candidates(const int32_t* __restrict__ part, const uint8_t* __restrict__ over,
                                  const int32_t* __restrict__ vwgt, int32_t n, int32_t tstar,
+                                 const int32_t* __restrict__ bjob, const int32_t* __restrict__ gtstar,
                                  const int64_t* __restrict__ wt, const int64_t* __restrict__ cap,
                                  int32_t* __restrict__ bal_t, const int64_t* __restrict__ bal_d,
                                  int32_t* __restrict__ flag, uint32_t* __restrict__ kw0, uint32_t* __restrict__ kw1,
@@ -38,7 +40,8 @@ __global__ void k_bal_candidates(const int32_t* __restrict__ part, const uint8_t
         const int64_t c = vwgt ? vwgt[v] : 1;
         int32_t t = bal_t[v];
         int64_t d = bal_d[v];  // -conn(own) when there is no adjacent target
-        if (t < 0 && tstar >= 0 && wt[tstar] + c <= cap[tstar]) t = tstar;
+        const int32_t ts = bjob ? gtstar[bjob[b]] : tstar;
+        if (t < 0 && ts >= 0 && wt[ts] + c <= cap[ts]) t = ts;
         bal_t[v] = t;
         if (t >= 0) {
             ok = 1;
@@ -144,48 +147,78 @@ __global__ void k_admit_decide(const uint32_t* __restrict__ keys, const uint32_t
     adm[i] = wt[t] + (pre[i] - base[t]) <= cap[t];
 }
 
-__global__ void k_bal_apply(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
-                            const uint8_t* __restrict__ adm, int64_t ns, const int32_t* __restrict__ vwgt,
-                            int32_t* __restrict__ part, int64_t* __restrict__ wt, int64_t* counter)
+// moves are counted per block-of-threads into spread slots (one graph) or per
+// job (batches: bjob != NULL)
+__global__ __launch_bounds__(kBlock) void k_bal_apply(const uint32_t* __restrict__ keys,
+                                                      const uint32_t* __restrict__ vals,
+                                                      const uint8_t* __restrict__ adm, int64_t ns,
+                                                      const int32_t* __restrict__ vwgt, int32_t* __restrict__ part,
+                                                      int64_t* __restrict__ wt, const int32_t* __restrict__ bjob,
+                                                      int64_t* counter)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ns || !adm[i]) return;
-    const int32_t v = (int32_t)vals[i];
-    const int32_t t = (int32_t)keys[i];
-    const int64_t c = vwgt ? vwgt[v] : 1;
-    const int32_t b = part[v];
-    part[v] = t;
-    atomicAdd((unsigned long long*)&wt[t], (unsigned long long)c);
-    atomicAdd((unsigned long long*)&wt[b], (unsigned long long)(-c));
-    spread_add(counter, 1);
+    __shared__ int32_t bm;
+    if (threadIdx.x == 0) bm = 0;
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t j = -1;
+    if (i < ns && adm[i]) {
+        const int32_t v = (int32_t)vals[i];
+        const int32_t t = (int32_t)keys[i];
+        const int64_t c = vwgt ? vwgt[v] : 1;
+        const int32_t b = part[v];
+        part[v] = t;
+        atomicAdd((unsigned long long*)&wt[t], (unsigned long long)c);
+        atomicAdd((unsigned long long*)&wt[b], (unsigned long long)(-c));
+        j = bjob ? bjob[t] : 0;
+        if (!bjob) atomicAdd(&bm, 1);
+    }
+    if (bjob) {
+        job_add(counter, j, 1);
+    } else {
+        __syncthreads();
+        if (threadIdx.x == 0 && bm) spread_add(counter, bm);
+    }
 }
 
 }  // namespace
 
-int32_t balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, int32_t* part,
-                int64_t* wt, int32_t nb, const int64_t* cap)
+int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64_t>& seeds,
+                const LPSchedule& sched, int32_t* part, int64_t* wt, const BlockTab& bt, const int64_t* cap,
+                const JobTabs& jt, const int32_t* boff)
 {
     const int32_t n = g.n;
+    const int32_t nb = bt.size();
+    const int32_t njobs = (int32_t)seeds.size();
+    const bool batch = jt.gid != nullptr;
     if (n == 0 || nb == 0) return 0;
     std::vector<int64_t> hcap(nb), hwt(nb);
     c.read(hcap.data(), cap, sizeof(int64_t) * nb);
-    std::vector<uint8_t> hover(nb);
+    std::vector<uint8_t> hover(nb), active(njobs, 1), any(njobs);
+    std::vector<int32_t> tstar(njobs);
+    std::vector<int64_t> moved(njobs);
     int32_t round = 0;
-    bool moved_prev = true;
     DBuf<uint8_t> over, sel;
-    DBuf<int32_t> bal_t, flag;
-    DBuf<int64_t> bal_d;
+    DBuf<int32_t> bal_t, flag, dbjob, dtstar;
+    DBuf<int64_t> bal_d, dmoved;
     DBuf<uint32_t> kw0, kw1, kw2, kcls;
     for (;;) {
         c.read(hwt.data(), wt, sizeof(int64_t) * nb);
-        bool any = false;
-        int32_t tstar = -1;
+        // per job: overloaded blocks, fallback block (most free capacity, smallest index)
+        std::fill(any.begin(), any.end(), 0);
+        std::fill(tstar.begin(), tstar.end(), -1);
         for (int32_t b = 0; b < nb; ++b) {
-            hover[b] = hwt[b] > hcap[b];
-            any |= hover[b] != 0;
-            if (!hover[b] && (tstar < 0 || hcap[b] - hwt[b] > hcap[tstar] - hwt[tstar])) tstar = b;
+            const int32_t j = batch ? bt.job[b] : 0;
+            const bool ov = hwt[b] > hcap[b];
+            any[j] |= ov;
+            if (!ov && (tstar[j] < 0 || hcap[b] - hwt[b] > hcap[tstar[j]] - hwt[tstar[j]])) tstar[j] = b;
         }
-        if (!any || !moved_prev) break;
+        bool go = false;
+        for (int32_t j = 0; j < njobs; ++j) {
+            active[j] = active[j] && any[j];  // a job stops for good: no overload, or no move last round
+            go |= active[j] != 0;
+        }
+        if (!go) break;
+        for (int32_t b = 0; b < nb; ++b) hover[b] = hwt[b] > hcap[b] && active[batch ? bt.job[b] : 0];
         if (!over.p) {
             over = DBuf<uint8_t>(c, (size_t)nb);
             sel = DBuf<uint8_t>(c, (size_t)n);
@@ -196,17 +229,24 @@ int32_t balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPS
             kw1 = DBuf<uint32_t>(c, (size_t)n);
             kw2 = DBuf<uint32_t>(c, (size_t)n);
             kcls = DBuf<uint32_t>(c, (size_t)n);
+            if (batch) {
+                dbjob = DBuf<int32_t>(c, (size_t)nb);
+                c.write(dbjob.p, bt.job.data(), sizeof(int32_t) * nb);
+                dtstar = DBuf<int32_t>(c, (size_t)njobs);
+                dmoved = DBuf<int64_t>(c, (size_t)njobs);
+            }
         }
         c.write(over.p, hover.data(), (size_t)nb);
+        if (batch) c.write(dtstar.p, tstar.data(), sizeof(int32_t) * njobs);
         fill_i32(c, bal_t.p, -1, n);
-        rate_for_balance(c, g, level, seed, round, sched, part, wt, cap, over.p, bal_t.p, bal_d.p);
+        rate_for_balance(c, g, level, seeds[0], round, sched, part, wt, cap, over.p, bal_t.p, bal_d.p, jt, boff);
         hipLaunchKernelGGL(k_bal_candidates, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, over.p, g.vwgt, n,
-                           tstar, wt, cap, bal_t.p, bal_d.p, flag.p, kw0.p, kw1.p, kw2.p, kcls.p);
+                           tstar[0], dbjob.p, dtstar.p, wt, cap, bal_t.p, bal_d.p, flag.p, kw0.p, kw1.p, kw2.p, kcls.p);
         KMP_LAUNCH_CHECK();
         DBuf<int32_t> pos(c, (size_t)n + 1);
         scan_excl_i32(c, flag.p, pos.p, n, pos.p + n);
         const int64_t ncand = c.read1(pos.p + n);
-        int64_t nmoved = 0;
+        std::fill(moved.begin(), moved.end(), 0);
         if (ncand > 0) {
             // candidate ids in ascending order
             DBuf<uint32_t> ids(c, ncand), keys(c, ncand), k2(c, ncand), v2(c, ncand);
@@ -261,15 +301,22 @@ int32_t balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPS
                 hipLaunchKernelGGL(k_admit_decide, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, tk.p, tv.p, sp.p,
                                    sb.p, ns, wt, cap, adm.p);
                 KMP_LAUNCH_CHECK();
-                c.zero_spread(SP_BALMOVES);
-                int64_t* ctr = c.spread(SP_BALMOVES);
+                int64_t* ctr;
+                if (batch) {
+                    c.zero(dmoved.p, sizeof(int64_t) * njobs);
+                    ctr = dmoved.p;
+                } else {
+                    c.zero_spread(SP_BALMOVES);
+                    ctr = c.spread(SP_BALMOVES);
+                }
                 hipLaunchKernelGGL(k_bal_apply, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, tk.p, tv.p, adm.p, ns,
-                                   g.vwgt, part, wt, ctr);
+                                   g.vwgt, part, wt, dbjob.p, ctr);
                 KMP_LAUNCH_CHECK();
-                nmoved = c.read_spread(SP_BALMOVES);
+                if (batch) c.read(moved.data(), dmoved.p, sizeof(int64_t) * njobs);
+                else moved[0] = c.read_spread(SP_BALMOVES);
             }
         }
-        moved_prev = nmoved > 0;
+        for (int32_t j = 0; j < njobs; ++j) active[j] = active[j] && moved[j] > 0;
         ++round;
     }
     return round;

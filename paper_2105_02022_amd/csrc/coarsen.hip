@@ -31,27 +31,31 @@ __global__ __launch_bounds__(kBlock) void k_count_nonempty(const int64_t* __rest
     if (threadIdx.x == 0 && cnt) spread_add(out, cnt);
 }
 
+// Batches: only jobs with glimit[job] > 0 take part.
 __global__ void k_singleton_flags(const int32_t* __restrict__ label, const int64_t* __restrict__ cw,
-                                  const int32_t* __restrict__ vwgt, int32_t n, int32_t* __restrict__ flag)
+                                  const int32_t* __restrict__ vwgt, int32_t n, const int32_t* __restrict__ gid,
+                                  const int64_t* __restrict__ glimit, int32_t* __restrict__ flag)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     int64_t c = vwgt ? vwgt[v] : 1;
-    flag[v] = cw[label[v]] == c;  // positive weights: the only member
+    const bool takes_part = !gid || glimit[gid[v]] > 0;
+    flag[v] = takes_part && cw[label[v]] == c;  // positive weights: the only member
 }
 
-__global__ void k_singleton_compact(const int32_t* __restrict__ flagpos, const int32_t* __restrict__ label,
-                                    const int64_t* __restrict__ cw, const int32_t* __restrict__ vwgt,
-                                    const uint32_t* __restrict__ fav, int32_t n, uint32_t* __restrict__ keys,
+// Group key 2 * fav; isolated nodes (fav NONE) form the last group of their
+// job: key 2 * (end of the job's node range) - 1.
+__global__ void k_singleton_compact(const int32_t* __restrict__ flag, const int32_t* __restrict__ flagpos,
+                                    const uint32_t* __restrict__ fav, int32_t n, const int32_t* __restrict__ gid,
+                                    const int32_t* __restrict__ gend, uint32_t* __restrict__ keys,
                                     uint32_t* __restrict__ vals)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= n) return;
-    int64_t c = vwgt ? vwgt[v] : 1;
-    if (cw[label[v]] != c) return;
+    if (v >= n || !flag[v]) return;
     int32_t p = flagpos[v];
     uint32_t f = fav[v];
-    keys[p] = f == kNone ? (uint32_t)n : f;  // isolated nodes form the last group
+    const uint32_t end = gid ? (uint32_t)gend[gid[v]] : (uint32_t)n;
+    keys[p] = f == kNone ? 2u * end - 1u : 2u * f;
     vals[p] = (uint32_t)v;
 }
 
@@ -64,7 +68,8 @@ __global__ void k_group_heads(const uint32_t* __restrict__ keys, int64_t ns, int
 
 __global__ void k_pair_eligible(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                                 const int32_t* __restrict__ gstart, int64_t ns, const int32_t* __restrict__ vwgt,
-                                int64_t U, int32_t* __restrict__ elig)
+                                int64_t U, const int32_t* __restrict__ gid, const int64_t* __restrict__ gU,
+                                int32_t* __restrict__ elig)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ns) return;
@@ -72,17 +77,35 @@ __global__ void k_pair_eligible(const uint32_t* __restrict__ keys, const uint32_
     if (((i - gstart[i]) & 1) == 0 && i + 1 < ns && keys[i + 1] == keys[i]) {
         int64_t ca = vwgt ? vwgt[vals[i]] : 1;
         int64_t cb = vwgt ? vwgt[vals[i + 1]] : 1;
-        e = ca + cb <= U;
+        e = ca + cb <= (gid ? gU[gid[vals[i]]] : U);
     }
     elig[i] = e;
 }
 
-__global__ void k_pair_apply(const uint32_t* __restrict__ vals, const int32_t* __restrict__ elig,
-                             const int32_t* __restrict__ rank, int64_t ns, int64_t limit,
-                             const int32_t* __restrict__ vwgt, int32_t* __restrict__ label, int64_t* __restrict__ cw)
+// batches: eligible-pair rank at the first singleton of every job
+__global__ void k_job_rank0(const uint32_t* __restrict__ vals, const int32_t* __restrict__ gid,
+                            const int32_t* __restrict__ rank, int64_t ns, int32_t* __restrict__ grank0)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= ns || !elig[i] || rank[i] >= limit) return;
+    if (i >= ns) return;
+    const int32_t j = gid[vals[i]];
+    if (i == 0 || gid[vals[i - 1]] != j) grank0[j] = rank[i];
+}
+
+__global__ void k_pair_apply(const uint32_t* __restrict__ vals, const int32_t* __restrict__ elig,
+                             const int32_t* __restrict__ rank, int64_t ns, int64_t limit,
+                             const int32_t* __restrict__ gid, const int64_t* __restrict__ glimit,
+                             const int32_t* __restrict__ grank0, const int32_t* __restrict__ vwgt,
+                             int32_t* __restrict__ label, int64_t* __restrict__ cw)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ns || !elig[i]) return;
+    if (gid) {
+        const int32_t j = gid[vals[i]];
+        if (rank[i] - grank0[j] >= glimit[j]) return;
+    } else if (rank[i] >= limit) {
+        return;
+    }
     int32_t a = (int32_t)vals[i], b = (int32_t)vals[i + 1];
     int32_t la = label[a], lb = label[b];
     int64_t cb = vwgt ? vwgt[b] : 1;
@@ -91,20 +114,43 @@ __global__ void k_pair_apply(const uint32_t* __restrict__ vals, const int32_t* _
     atomicAdd((unsigned long long*)&cw[lb], (unsigned long long)(-cb));
 }
 
+// Per-job non-empty labels (label K of job j is node K of job j).
+__global__ __launch_bounds__(kBlock) void k_count_nonempty_jobs(const int64_t* __restrict__ cw, int32_t n,
+                                                                const int32_t* __restrict__ gid, int64_t* out)
+{
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + threadIdx.x;
+        int32_t j = -1;
+        int64_t x = 0;
+        if (i < n) {
+            j = gid[i];
+            x = cw[i] > 0;
+        }
+        job_add(out, j, x);
+    }
+}
+
 // ---------------------------------------------------------------- contraction
-__global__ void k_nonempty_flags(const int64_t* __restrict__ cw, int32_t n, int32_t* __restrict__ flag)
+// Batches: labels of jobs with gkeep[job] == 0 are not contracted.
+__global__ void k_nonempty_flags(const int64_t* __restrict__ cw, int32_t n, const int32_t* __restrict__ gid,
+                                 const uint8_t* __restrict__ gkeep, int32_t* __restrict__ flag)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flag[i] = cw[i] > 0;
+    if (i < n) flag[i] = cw[i] > 0 && (!gkeep || gkeep[gid[i]]);
 }
 
 __global__ void k_map_and_weights(const int32_t* __restrict__ label, const int32_t* __restrict__ cid,
                                   const int64_t* __restrict__ cw, const int32_t* __restrict__ xadj, int32_t n,
+                                  const int32_t* __restrict__ gid, const uint8_t* __restrict__ gkeep,
                                   int32_t* __restrict__ map, int32_t* __restrict__ cvwgt, int32_t* __restrict__ mcnt,
                                   int32_t* __restrict__ dsum)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
+    if (gkeep && !gkeep[gid[v]]) {
+        map[v] = -1;
+        return;
+    }
     int32_t c = cid[label[v]];
     map[v] = c;
     if (cw[v] > 0) cvwgt[cid[v]] = (int32_t)cw[v];  // v read as a label here
@@ -118,6 +164,7 @@ __global__ void k_place_members(const int32_t* __restrict__ map, int32_t n, cons
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= n) return;
     int32_t c = map[v];
+    if (c < 0) return;
     int32_t p = atomicAdd(&cursor[c], 1);
     members[mstart[c] + p] = (int32_t)v;
 }
@@ -372,46 +419,94 @@ int32_t count_nonempty(Ctx& c, const int64_t* cw, int32_t n)
     return (int32_t)c.read_spread(SP_NONEMPTY);
 }
 
-int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav)
+void count_nonempty_jobs(Ctx& c, const int64_t* cw, int32_t n, const JobTabs& jt, int32_t njobs,
+                         std::vector<int64_t>& out)
+{
+    out.assign(njobs, 0);
+    if (n <= 0) return;
+    if (!jt.gid) {
+        out[0] = count_nonempty(c, cw, n);
+        return;
+    }
+    DBuf<int64_t> d(c, (size_t)njobs);
+    c.zero(d.p, sizeof(int64_t) * njobs);
+    hipLaunchKernelGGL(k_count_nonempty_jobs, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, cw, n,
+                       jt.gid, d.p);
+    KMP_LAUNCH_CHECK();
+    c.read(out.data(), d.p, sizeof(int64_t) * njobs);
+}
+
+namespace {
+
+// Two-hop merging of singletons (Sec. 5.1): singletons sorted by (favoured
+// cluster, id), paired (0,1), (2,3), ... inside a group; the first `limit`
+// eligible pairs (c(a) + c(b) <= U) of every job merge.  One graph: scalar U
+// and limit; batches: gU / glimit / gend by job.
+int64_t two_hop_core(Ctx& c, const DGraph& g, const JobTabs& jt, int64_t U, int64_t limit, const int64_t* gU,
+                     const int64_t* glimit, const int32_t* gend, int32_t njobs, int32_t* label, int64_t* cw,
+                     const uint32_t* fav, bool count)
 {
     const int32_t n = g.n;
-    const int32_t nc = count_nonempty(c, cw, n);
-    const int64_t half = n / 2;
-    if (nc <= half) return 0;
-    DBuf<int32_t> flag(c, (size_t)n + 1);
-    hipLaunchKernelGGL(k_singleton_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, label, cw, g.vwgt, n, flag.p);
+    ProfScope ps(c, KMP_PROF_TWO_HOP);
+    DBuf<int32_t> flag(c, (size_t)n), pos(c, (size_t)n + 1);
+    hipLaunchKernelGGL(k_singleton_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, label, cw, g.vwgt, n, jt.gid,
+                       glimit, flag.p);
     KMP_LAUNCH_CHECK();
-    scan_excl_i32(c, flag.p, flag.p, n, flag.p + n);
-    const int32_t ns = c.read1(flag.p + n);
+    scan_excl_i32(c, flag.p, pos.p, n, pos.p + n);
+    const int32_t ns = c.read1(pos.p + n);
     if (ns < 2) return 0;
     DBuf<uint32_t> keys(c, ns), vals(c, ns), k2(c, ns), v2(c, ns);
-    hipLaunchKernelGGL(k_singleton_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, flag.p, label, cw, g.vwgt,
-                       fav, n, keys.p, vals.p);
+    hipLaunchKernelGGL(k_singleton_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, flag.p, pos.p, fav, n,
+                       jt.gid, gend, keys.p, vals.p);
     KMP_LAUNCH_CHECK();
-    radix_sort_pairs(c, keys.p, vals.p, k2.p, v2.p, ns, bits_for((uint64_t)n));
+    radix_sort_pairs(c, keys.p, vals.p, k2.p, v2.p, ns, bits_for(2 * (uint64_t)n));
     DBuf<int32_t> gstart(c, ns), elig(c, (size_t)ns + 1);
     hipLaunchKernelGGL(k_group_heads, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, keys.p, (int64_t)ns, gstart.p);
     KMP_LAUNCH_CHECK();
     scan_incl_max_i32(c, gstart.p, gstart.p, ns);
     hipLaunchKernelGGL(k_pair_eligible, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, keys.p, vals.p, gstart.p,
-                       (int64_t)ns, g.vwgt, U, elig.p);
+                       (int64_t)ns, g.vwgt, U, jt.gid, gU, elig.p);
     KMP_LAUNCH_CHECK();
     DBuf<int32_t> rank(c, (size_t)ns + 1);
     scan_excl_i32(c, elig.p, rank.p, ns, rank.p + ns);
-    const int64_t E = c.read1(rank.p + ns);
-    const int64_t limit = (int64_t)nc - half;
+    DBuf<int32_t> grank0;
+    if (jt.gid) {
+        grank0 = DBuf<int32_t>(c, (size_t)njobs);
+        hipLaunchKernelGGL(k_job_rank0, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, vals.p, jt.gid, rank.p,
+                           (int64_t)ns, grank0.p);
+        KMP_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(k_pair_apply, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, vals.p, elig.p, rank.p,
-                       (int64_t)ns, limit, g.vwgt, label, cw);
+                       (int64_t)ns, limit, jt.gid, glimit, grank0.p, g.vwgt, label, cw);
     KMP_LAUNCH_CHECK();
+    return count ? (int64_t)c.read1(rank.p + ns) : 0;
+}
+
+}  // namespace
+
+int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav, bool count)
+{
+    const int32_t n = g.n;
+    const int32_t nc = count_nonempty(c, cw, n);
+    const int64_t half = n / 2;
+    if (nc <= half) return 0;
+    const int64_t limit = (int64_t)nc - half;
+    const int64_t E = two_hop_core(c, g, JobTabs{}, U, limit, nullptr, nullptr, nullptr, 1, label, cw, fav, count);
     return E < limit ? E : limit;
 }
 
+void two_hop_jobs(Ctx& c, const DGraph& g, const JobTabs& jt, const int64_t* gU, const int64_t* glimit,
+                  const int32_t* gend, int32_t njobs, int32_t* label, int64_t* cw, const uint32_t* fav)
+{
+    two_hop_core(c, g, jt, 0, 0, gU, glimit, gend, njobs, label, cw, fav, false);
+}
+
 void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
-              int32_t& cn, int64_t& cm)
+              int32_t& cn, int64_t& cm, const JobTabs& jt, const uint8_t* gkeep)
 {
     const int32_t n = g.n;
     DBuf<int32_t> cid(c, (size_t)n + 1);
-    hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, cw, n, cid.p);
+    hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, cw, n, jt.gid, gkeep, cid.p);
     KMP_LAUNCH_CHECK();
     scan_excl_i32(c, cid.p, cid.p, n, cid.p + n);
     const int32_t nc = c.read1(cid.p + n);
@@ -423,7 +518,7 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     c.zero(dstart.p, sizeof(int32_t) * ((size_t)nc + 1));
     c.zero(cursor.p, sizeof(int32_t) * (size_t)nc);
     hipLaunchKernelGGL(k_map_and_weights, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, label, cid.p, cw, g.xadj, n,
-                       map, out.vwgt.p, mstart.p, dstart.p);
+                       jt.gid, gkeep, map, out.vwgt.p, mstart.p, dstart.p);
     KMP_LAUNCH_CHECK();
     // keep the per-row fine degree sums before turning them into offsets
     DBuf<int32_t> dsum(c, (size_t)nc + 1);

@@ -68,8 +68,9 @@ constexpr int GGG_THREADS = 64 * kSeeds;
 struct GGGJob {
     int32_t b, first, f, nverts;
     int32_t dsum;      // sum of degrees of the block's nodes (bound on internal entries)
-    int32_t pad;
+    uint32_t hpre;     // H prefix over (seed; T_GGG, level) of the block's job
     int64_t scratch;   // byte offset into the global scratch (global variant)
+    int64_t lk;        // L_k of the block's job
 };
 
 struct GGGArgs {
@@ -82,8 +83,6 @@ struct GGGArgs {
     const int32_t* bstart;
     const int32_t* local;
     const GGGJob* jobs;
-    int64_t lk;
-    uint32_t hpre;      // H prefix over (seed; T_GGG, level)
     uint8_t* side;      // [n]
     char* scratch;      // global variant
 };
@@ -181,11 +180,11 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     // ---- one growth per wavefront
     const int32_t f = job.f, f0 = f / 2, f1 = f - f0;
     const int64_t t0 = cB * f0 / f;
-    const int64_t cap0 = (int64_t)f0 * a.lk, cap1 = (int64_t)f1 * a.lk;
+    const int64_t cap0 = (int64_t)f0 * job.lk, cap1 = (int64_t)f1 * job.lk;
     const int j = wv;
     int32_t* gain = gain_all + (int64_t)j * nv;
     uint8_t* st = st_all + (int64_t)j * nv;  // 0 free, 1 frontier, 2 grown side
-    const uint32_t hj = hash_step(hash_step(hash_step(a.hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
+    const uint32_t hj = hash_step(hash_step(hash_step(job.hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
     for (int32_t i = lane; i < nv; i += 64) {
         int32_t s = 0;
         for (int32_t e = lxadj[i]; e < lxadj[i + 1]; ++e) s += lw[e];
@@ -278,6 +277,18 @@ __global__ void k_project(const int32_t* __restrict__ cpart, const int32_t* __re
     if (v < n) fpart[v] = cpart[map[v]];
 }
 
+// batches: projected nodes take the renumbered coarse block; nodes of jobs
+// whose coarsest level is this one (map < 0) start in their job's block
+__global__ void k_project_jobs(const int32_t* __restrict__ cpart, const int32_t* __restrict__ map,
+                               const int32_t* __restrict__ remap, const int32_t* __restrict__ gid,
+                               const int32_t* __restrict__ start_block, int32_t* __restrict__ fpart, int32_t n)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    const int32_t c = map ? map[v] : -1;
+    fpart[v] = c >= 0 ? remap[cpart[c]] : start_block[gid[v]];
+}
+
 __global__ __launch_bounds__(kBlock) void k_block_weights(const int32_t* __restrict__ part,
                                                           const int32_t* __restrict__ vwgt, int32_t n, int32_t nb,
                                                           int64_t* __restrict__ wt)
@@ -320,21 +331,39 @@ __global__ __launch_bounds__(kBlock) void k_cut(const int32_t* __restrict__ xadj
     }
 }
 
+// cut entries of every job (each cut edge counted from both ends)
+__global__ __launch_bounds__(kBlock) void k_cut_jobs(const int32_t* __restrict__ xadj,
+                                                     const int32_t* __restrict__ adjncy,
+                                                     const int32_t* __restrict__ adjwgt,
+                                                     const int32_t* __restrict__ part, const int32_t* __restrict__ gid,
+                                                     int32_t n, int64_t* out)
+{
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = base + threadIdx.x;
+        int64_t acc = 0;
+        int32_t j = -1;
+        if (v < n) {
+            j = gid[v];
+            const int32_t p = part[v];
+            for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e)
+                if (part[adjncy[e]] != p) acc += adjwgt ? adjwgt[e] : 1;
+        }
+        job_add(out, j, acc);
+    }
+}
+
 constexpr int64_t kLdsBudget = 64 * 1024;
 
 }  // namespace
 
-int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, std::vector<int32_t>& first,
-                          std::vector<int32_t>& fcount, int64_t lk, uint64_t seed)
+int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, BlockTab& bt,
+                          const std::vector<uint8_t>& split, const std::vector<int64_t>& lk,
+                          const std::vector<uint32_t>& hseed)
 {
     const int32_t n = g.n;
-    const int32_t nb = (int32_t)first.size();
-    std::vector<uint8_t> split(nb);
+    const int32_t nb = bt.size();
     bool any = false;
-    for (int32_t bb = 0; bb < nb; ++bb) {
-        split[bb] = fcount[bb] >= 2;
-        any |= split[bb];
-    }
+    for (int32_t bb = 0; bb < nb; ++bb) any |= split[bb] != 0;
     if (!any) return 0;
     DBuf<uint8_t> side(c, (size_t)n);
     int32_t calls = 0;
@@ -359,14 +388,16 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         int64_t lds_max = 0, glob_total = 0;
         for (int32_t bb = 0; bb < nb; ++bb) {
             if (!split[bb]) continue;
+            const int32_t jb_job = bt.job.empty() ? 0 : bt.job[bb];
             GGGJob jb;
             jb.b = bb;
-            jb.first = first[bb];
-            jb.f = fcount[bb];
+            jb.first = bt.first[bb];
+            jb.f = bt.f[bb];
             jb.nverts = hb[bb + 1] - hb[bb];
             jb.dsum = hd[bb];
-            jb.pad = 0;
+            jb.hpre = hash_step(hash_step(hseed[jb_job], TAG_GGG, 1), (uint32_t)level, 2);
             jb.scratch = 0;
+            jb.lk = lk[jb_job];
             const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum);
             if (bytes <= kLdsBudget) {
                 lds_jobs.push_back(jb);
@@ -387,8 +418,6 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         a.verts = verts.p;
         a.bstart = bstart.p;
         a.local = local.p;
-        a.lk = lk;
-        a.hpre = hash_prefix(seed, {TAG_GGG, (uint32_t)level});
         a.side = side.p;
         a.scratch = nullptr;
         if (!lds_jobs.empty()) {
@@ -399,7 +428,6 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             hipLaunchKernelGGL(k_ggg<true>, dim3((unsigned)lds_jobs.size()), dim3(GGG_THREADS), (size_t)lds_max,
                                c.stream, a);
             KMP_LAUNCH_CHECK();
-
         }
         if (!glob_jobs.empty()) {
             DBuf<GGGJob> jobs(c, glob_jobs.size());
@@ -410,24 +438,29 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             ProfScope ps(c, KMP_PROF_GGG);
             hipLaunchKernelGGL(k_ggg<false>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream, a);
             KMP_LAUNCH_CHECK();
-
         }
     }
-    // renumber blocks in ascending `first`
-    std::vector<int32_t> newidx(nb), nf, nc;
-    nf.reserve(2 * nb);
-    nc.reserve(2 * nb);
+    // renumber blocks: split blocks become (first, f0) and (first + f0, f - f0)
+    std::vector<int32_t> newidx(nb);
+    BlockTab nt;
+    nt.first.reserve(2 * nb);
+    nt.f.reserve(2 * nb);
+    nt.job.reserve(2 * nb);
     for (int32_t bb = 0; bb < nb; ++bb) {
-        newidx[bb] = (int32_t)nf.size();
+        const int32_t jb_job = bt.job.empty() ? 0 : bt.job[bb];
+        newidx[bb] = nt.size();
         if (split[bb]) {
-            const int32_t f0 = fcount[bb] / 2;
-            nf.push_back(first[bb]);
-            nc.push_back(f0);
-            nf.push_back(first[bb] + f0);
-            nc.push_back(fcount[bb] - f0);
+            const int32_t f0 = bt.f[bb] / 2;
+            nt.first.push_back(bt.first[bb]);
+            nt.f.push_back(f0);
+            nt.job.push_back(jb_job);
+            nt.first.push_back(bt.first[bb] + f0);
+            nt.f.push_back(bt.f[bb] - f0);
+            nt.job.push_back(jb_job);
         } else {
-            nf.push_back(first[bb]);
-            nc.push_back(fcount[bb]);
+            nt.first.push_back(bt.first[bb]);
+            nt.f.push_back(bt.f[bb]);
+            nt.job.push_back(jb_job);
         }
     }
     if (n > 0) {
@@ -438,17 +471,26 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         hipLaunchKernelGGL(k_relabel, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, side.p, dnew.p, dsplit.p,
                            n);
         KMP_LAUNCH_CHECK();
-
     }
-    first.swap(nf);
-    fcount.swap(nc);
+    bt = std::move(nt);
     return calls;
 }
 
 void project(Ctx& c, const int32_t* coarse_part, const int32_t* map, int32_t* fine_part, int32_t n)
 {
     if (n <= 0) return;
+    ProfScope ps(c, KMP_PROF_PROJECT);
     hipLaunchKernelGGL(k_project, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, coarse_part, map, fine_part, n);
+    KMP_LAUNCH_CHECK();
+}
+
+void project_jobs(Ctx& c, const int32_t* coarse_part, const int32_t* map, const int32_t* remap, const int32_t* gid,
+                  const int32_t* start_block, int32_t* fine_part, int32_t n)
+{
+    if (n <= 0) return;
+    ProfScope ps(c, KMP_PROF_PROJECT);
+    hipLaunchKernelGGL(k_project_jobs, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, coarse_part, map, remap, gid,
+                       start_block, fine_part, n);
     KMP_LAUNCH_CHECK();
 }
 
@@ -469,6 +511,20 @@ int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part)
                        g.adjwgt, part, g.n, c.spread(SP_CUT));
     KMP_LAUNCH_CHECK();
     return c.read_spread(SP_CUT) / 2;
+}
+
+void edge_cut_jobs(Ctx& c, const DGraph& g, const int32_t* part, const int32_t* gid, int32_t njobs,
+                   std::vector<int64_t>& out)
+{
+    out.assign(njobs, 0);
+    if (g.n <= 0) return;
+    DBuf<int64_t> d(c, (size_t)njobs);
+    c.zero(d.p, sizeof(int64_t) * njobs);
+    hipLaunchKernelGGL(k_cut_jobs, dim3(grid_for(g.n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
+                       g.adjwgt, part, gid, g.n, d.p);
+    KMP_LAUNCH_CHECK();
+    c.read(out.data(), d.p, sizeof(int64_t) * njobs);
+    for (auto& x : out) x /= 2;
 }
 
 }  // namespace kmp

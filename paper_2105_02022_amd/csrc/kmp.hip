@@ -144,13 +144,108 @@ __global__ void k_final_ids(const int32_t* __restrict__ part, const int32_t* __r
     if (v < n) out[v] = first[part[v]];
 }
 
-struct Level {
-    DGraph g;
-    OwnedGraph own;      // storage for coarse levels
-    DBuf<int32_t> map;   // to the next coarser level
-    std::unique_ptr<LPSchedule> sched;
+// ---------------------------------------------------------------- batches: union of the jobs' graphs
+struct JobPtrs {
+    const int32_t* xadj;
+    const int32_t* adjncy;
+    const int32_t* vwgt;
+    const int32_t* adjwgt;
+    int32_t* out;
 };
 
+// largest i in [0, cnt) with off[i] <= x (off nondecreasing, off[0] = 0 <= x)
+__device__ inline int32_t find_member(const int64_t* __restrict__ off, int32_t cnt, int64_t x)
+{
+    int32_t lo = 0, hi = cnt - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= x) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// xadj[n] of every member job (compared with the m it was given)
+__global__ void k_job_tails(const JobPtrs* __restrict__ P, const int32_t* __restrict__ mjob,
+                            const int64_t* __restrict__ moff, int32_t cnt, int32_t* __restrict__ out)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) out[i] = P[mjob[i]].xadj[moff[i + 1] - moff[i]];
+}
+
+// per-job sums of node weights (jobs with vwgt) and edge weights (jobs with
+// adjwgt), read from the inputs at their position in the union
+__global__ __launch_bounds__(kBlock) void k_job_sums(const JobPtrs* __restrict__ P, const int32_t* __restrict__ mjob,
+                                                     const int64_t* __restrict__ off, int32_t cnt, int64_t total,
+                                                     bool nodes, int64_t* out)
+{
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < total; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t x = base + threadIdx.x;
+        int32_t j = -1;
+        int64_t w = 0;
+        if (x < total) {
+            const int32_t i = find_member(off, cnt, x);
+            j = mjob[i];
+            const int32_t* a = nodes ? P[j].vwgt : P[j].adjwgt;
+            w = a ? a[x - off[i]] : 1;
+        }
+        job_add(out, j, w);
+    }
+}
+
+__global__ void k_union_nodes(const JobPtrs* __restrict__ P, const int32_t* __restrict__ mjob,
+                              const int64_t* __restrict__ moff, const int64_t* __restrict__ meoff, int32_t cnt,
+                              int32_t N, int32_t* __restrict__ xadj, int32_t* __restrict__ vwgt,
+                              int32_t* __restrict__ gid)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    const int32_t i = find_member(moff, cnt, v);
+    const int32_t j = mjob[i];
+    const int64_t l = v - moff[i];
+    xadj[v] = (int32_t)(meoff[i] + P[j].xadj[l]);
+    if (vwgt) vwgt[v] = P[j].vwgt ? P[j].vwgt[l] : 1;
+    gid[v] = j;
+}
+
+__global__ void k_union_entries(const JobPtrs* __restrict__ P, const int32_t* __restrict__ mjob,
+                                const int64_t* __restrict__ moff, const int64_t* __restrict__ meoff, int32_t cnt,
+                                int64_t M, int32_t* __restrict__ adjncy, int32_t* __restrict__ adjwgt)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= M) return;
+    const int32_t i = find_member(meoff, cnt, e);
+    const int32_t j = mjob[i];
+    const int64_t l = e - meoff[i];
+    adjncy[e] = (int32_t)(moff[i] + P[j].adjncy[l]);
+    if (adjwgt) adjwgt[e] = P[j].adjwgt ? P[j].adjwgt[l] : 1;
+}
+
+__global__ void k_fill_gid(const int32_t* __restrict__ mjob, const int64_t* __restrict__ moff, int32_t cnt, int32_t N,
+                           int32_t* __restrict__ gid)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < N) gid[v] = mjob[find_member(moff, cnt, v)];
+}
+
+__global__ void k_gather_at(const int32_t* __restrict__ a, const int64_t* __restrict__ idx, int32_t cnt,
+                            int64_t* __restrict__ out)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < cnt) out[i] = a[idx[i]];
+}
+
+__global__ void k_final_ids_jobs(const int32_t* __restrict__ part, const int32_t* __restrict__ first,
+                                 const int32_t* __restrict__ gid, const int32_t* __restrict__ noff,
+                                 const JobPtrs* __restrict__ P, int32_t N)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    const int32_t j = gid[v];
+    P[j].out[v - noff[j]] = first[part[v]];
+}
+
+// ---------------------------------------------------------------- scheduler
 int64_t eps_ppm(double eps) { return (int64_t)std::llround(eps * (double)kPPM); }
 
 int64_t level_U(int32_t n_l, int32_t& kc, int64_t cV, int64_t e)
@@ -165,12 +260,6 @@ int32_t ceil2_div_C(int32_t n_l)
     while (p * kC < n_l) p *= 2;
     return p > INT32_MAX ? INT32_MAX : (int32_t)p;
 }
-
-struct Common {
-    int64_t cV = 0;
-    int64_t e = 0;
-    int64_t lk = 0;
-};
 
 int check_args(const int32_t* xadj, int32_t n, int64_t m, int32_t k, double eps, const int32_t* out)
 {
@@ -191,6 +280,526 @@ int64_t prepare(Ctx& c, const DGraph& g)
     return sums[0];
 }
 
+// One job of a pass: its input, parameters and results.
+struct JobRun {
+    DGraph g;
+    int32_t k = 1;
+    double eps = 0;
+    uint64_t seed = 0;
+    int32_t* out = nullptr;
+    int status = KMP_OK;
+    bool run = false;         // takes part in the multilevel pass
+    int64_t cV = 0, e = 0, lk = 0;
+    int32_t kc = 0;           // k' of the coarsening bound (Sec. 5.1)
+    int32_t L = -1;           // coarsest level
+    int64_t cut = 0, maxw = 0;
+    std::vector<int32_t> level_n;
+    std::vector<int64_t> level_m;
+};
+
+// A level of the pass: the member jobs' level graphs (one graph, or their
+// disjoint union in job order).
+struct Level {
+    DGraph g;
+    OwnedGraph own;               // storage for unions and coarse levels
+    DBuf<int32_t> map;            // to the next coarser level (-1: the job's coarsest level is this one)
+    std::unique_ptr<LPSchedule> sched;
+    bool sched_full = false;      // the schedule holds every node (refinement can reuse it)
+    std::vector<int32_t> mem;     // member jobs, ascending
+    std::vector<int64_t> moff;    // by member: first node; moff[mem.size()] = n
+    std::vector<int32_t> nn;      // by job: nodes at this level
+    std::vector<int64_t> mm;      // by job: directed entries at this level
+    DBuf<int32_t> gid;            // batches: job of every node
+    DBuf<int32_t> dnoff, dgend;   // batches: by job, first node / end of the job's node range
+    DBuf<int32_t> dmjob;          // batches: by member
+    DBuf<int64_t> dmoff;
+};
+
+struct Totals {
+    int64_t moves_cl = 0, moves_ref = 0, rated = 0, contracted = 0;
+    int32_t bip = 0, brounds = 0;
+    double ms_lp = 0, ms_con = 0, ms_ip = 0, ms_ref = 0;
+};
+
+template <typename T>
+DBuf<T> upload(Ctx& c, const std::vector<T>& v)
+{
+    DBuf<T> d(c, v.size());
+    if (!v.empty()) c.write(d.p, v.data(), sizeof(T) * v.size());
+    return d;
+}
+
+// Per-job device tables of a batch level (gid, per-job node offsets / range
+// ends, member lists) from its member list and per-job node counts.
+void set_level_tables(Ctx& c, Level& L, int32_t nj)
+{
+    const int32_t cnt = (int32_t)L.mem.size();
+    std::vector<int32_t> noff(nj, 0), gend(nj, 0);
+    for (int32_t i = 0; i < cnt; ++i) {
+        noff[L.mem[i]] = (int32_t)L.moff[i];
+        gend[L.mem[i]] = (int32_t)L.moff[i + 1];
+    }
+    L.dnoff = upload(c, noff);
+    L.dgend = upload(c, gend);
+    L.dmjob = upload(c, L.mem);
+    L.dmoff = upload(c, L.moff);
+    if (!L.gid.p) {
+        L.gid = DBuf<int32_t>(c, (size_t)std::max(L.g.n, 1));
+        if (L.g.n > 0) {
+            hipLaunchKernelGGL(k_fill_gid, dim3(grid_for(L.g.n)), dim3(kBlock), 0, c.stream, L.dmjob.p, L.dmoff.p,
+                               cnt, L.g.n, L.gid.p);
+            KMP_LAUNCH_CHECK();
+        }
+    }
+}
+
+JobTabs tabs_of(const Level& L, const DBuf<uint32_t>& ghash)
+{
+    JobTabs t;
+    t.gid = L.gid.p;
+    t.ghash = ghash.p;
+    t.noff = L.dnoff.p;
+    return t;
+}
+
+// Jobs with run = true in job order, with their node / entry offsets in the union.
+void batch_members(const std::vector<JobRun>& jobs, std::vector<int32_t>& mem, std::vector<int64_t>& moff,
+                   std::vector<int64_t>& meoff)
+{
+    mem.clear();
+    moff.assign(1, 0);
+    meoff.assign(1, 0);
+    for (int32_t j = 0; j < (int32_t)jobs.size(); ++j)
+        if (jobs[j].run) {
+            mem.push_back(j);
+            moff.push_back(moff.back() + jobs[j].g.n);
+            meoff.push_back(meoff.back() + jobs[j].g.m);
+        }
+}
+
+// Checks every job of a batch on the device at once: m == xadj[n] and the
+// int32 bounds of the weight sums (failing jobs leave the pass with their
+// code); computes c(V).  Uploads the per-job pointer table.
+void check_batch(Ctx& c, std::vector<JobRun>& jobs, DBuf<JobPtrs>& dptr)
+{
+    const int32_t nj = (int32_t)jobs.size();
+    std::vector<JobPtrs> ptr(nj);
+    for (int32_t j = 0; j < nj; ++j)
+        ptr[j] = JobPtrs{jobs[j].g.xadj, jobs[j].g.adjncy, jobs[j].g.vwgt, jobs[j].g.adjwgt, jobs[j].out};
+    dptr = upload(c, ptr);
+    auto members = [&](std::vector<int32_t>& mem, std::vector<int64_t>& moff, std::vector<int64_t>& meoff) {
+        batch_members(jobs, mem, moff, meoff);
+    };
+    std::vector<int32_t> mem;
+    std::vector<int64_t> moff, meoff;
+    members(mem, moff, meoff);
+    int32_t cnt = (int32_t)mem.size();
+    if (cnt == 0) return;
+    {   // m == xadj[n]
+        DBuf<int32_t> dm = upload(c, mem);
+        DBuf<int64_t> dmo = upload(c, moff);
+        DBuf<int32_t> tails(c, (size_t)cnt);
+        hipLaunchKernelGGL(k_job_tails, dim3(grid_for(cnt)), dim3(kBlock), 0, c.stream, dptr.p, dm.p, dmo.p, cnt,
+                           tails.p);
+        KMP_LAUNCH_CHECK();
+        std::vector<int32_t> ht(cnt);
+        c.read(ht.data(), tails.p, sizeof(int32_t) * cnt);
+        for (int32_t i = 0; i < cnt; ++i)
+            if ((int64_t)ht[i] != jobs[mem[i]].g.m || (jobs[mem[i]].g.m > 0 && !jobs[mem[i]].g.adjncy)) {
+                jobs[mem[i]].status = KMP_EINVAL;
+                jobs[mem[i]].run = false;
+            }
+    }
+    members(mem, moff, meoff);
+    cnt = (int32_t)mem.size();
+    if (cnt == 0) return;
+    {   // weight sums (int64), only for jobs that carry weights
+        bool any_vw = false, any_ew = false;
+        for (int32_t j : mem) {
+            any_vw |= jobs[j].g.vwgt != nullptr;
+            any_ew |= jobs[j].g.adjwgt != nullptr;
+        }
+        std::vector<int64_t> vs(nj, 0), es(nj, 0);
+        DBuf<int32_t> dm = upload(c, mem);
+        DBuf<int64_t> dmo = upload(c, moff), dme = upload(c, meoff);
+        DBuf<int64_t> acc(c, (size_t)nj);
+        if (any_vw) {
+            c.zero(acc.p, sizeof(int64_t) * nj);
+            hipLaunchKernelGGL(k_job_sums, dim3(grid_for(moff[cnt], kBlock, 1024)), dim3(kBlock), 0, c.stream, dptr.p,
+                               dm.p, dmo.p, cnt, moff[cnt], true, acc.p);
+            KMP_LAUNCH_CHECK();
+            c.read(vs.data(), acc.p, sizeof(int64_t) * nj);
+        }
+        if (any_ew && meoff[cnt] > 0) {
+            c.zero(acc.p, sizeof(int64_t) * nj);
+            hipLaunchKernelGGL(k_job_sums, dim3(grid_for(meoff[cnt], kBlock, 1024)), dim3(kBlock), 0, c.stream,
+                               dptr.p, dm.p, dme.p, cnt, meoff[cnt], false, acc.p);
+            KMP_LAUNCH_CHECK();
+            c.read(es.data(), acc.p, sizeof(int64_t) * nj);
+        }
+        for (int32_t j : mem) {
+            const int64_t cV = jobs[j].g.vwgt ? vs[j] : jobs[j].g.n;
+            const int64_t ew = jobs[j].g.adjwgt ? es[j] : jobs[j].g.m;
+            if (cV > INT32_MAX || ew / 2 > INT32_MAX) {
+                jobs[j].status = KMP_EOVERFLOW;
+                jobs[j].run = false;
+            }
+            jobs[j].cV = cV;
+        }
+    }
+}
+
+// Level 0 of a batch: the jobs with run = true concatenated in job order.
+void build_union(Ctx& c, const std::vector<JobRun>& jobs, const DBuf<JobPtrs>& dptr, Level& L0)
+{
+    const int32_t nj = (int32_t)jobs.size();
+    std::vector<int32_t> mem;
+    std::vector<int64_t> moff, meoff;
+    batch_members(jobs, mem, moff, meoff);
+    const int32_t cnt = (int32_t)mem.size();
+    if (cnt == 0) return;
+    const int64_t N = moff[cnt], M = meoff[cnt];
+    if (N >= INT32_MAX || M > INT32_MAX) throw Error(KMP_EINVAL, "batch exceeds int32 node or entry range");
+    bool any_vw = false, any_ew = false;
+    for (int32_t j : mem) {
+        any_vw |= jobs[j].g.vwgt != nullptr;
+        any_ew |= jobs[j].g.adjwgt != nullptr;
+    }
+    L0.mem = mem;
+    L0.moff = moff;
+    L0.nn.assign(nj, 0);
+    L0.mm.assign(nj, 0);
+    for (int32_t j : mem) {
+        L0.nn[j] = jobs[j].g.n;
+        L0.mm[j] = jobs[j].g.m;
+    }
+    L0.own.xadj = DBuf<int32_t>(c, (size_t)N + 1);
+    L0.own.adjncy = DBuf<int32_t>(c, (size_t)std::max<int64_t>(M, 1));
+    if (any_vw) L0.own.vwgt = DBuf<int32_t>(c, (size_t)N);
+    if (any_ew) L0.own.adjwgt = DBuf<int32_t>(c, (size_t)std::max<int64_t>(M, 1));
+    L0.gid = DBuf<int32_t>(c, (size_t)N);
+    set_level_tables(c, L0, nj);  // gid is filled below
+    DBuf<int64_t> dme = upload(c, meoff);
+    hipLaunchKernelGGL(k_union_nodes, dim3(grid_for(N)), dim3(kBlock), 0, c.stream, dptr.p, L0.dmjob.p, L0.dmoff.p,
+                       dme.p, cnt, (int32_t)N, L0.own.xadj.p, L0.own.vwgt.p, L0.gid.p);
+    KMP_LAUNCH_CHECK();
+    fill_i32(c, L0.own.xadj.p + N, (int32_t)M, 1);
+    if (M > 0) {
+        hipLaunchKernelGGL(k_union_entries, dim3(grid_for(M)), dim3(kBlock), 0, c.stream, dptr.p, L0.dmjob.p,
+                           L0.dmoff.p, dme.p, cnt, M, L0.own.adjncy.p, L0.own.adjwgt.p);
+        KMP_LAUNCH_CHECK();
+    }
+    L0.g = L0.own.view((int32_t)N, M);
+}
+
+// The deep-MGP pass (Alg. 1 unrolled) over the jobs with run = true.  One
+// job works on its own graph; several run level by level on the union of
+// their level graphs, each job with its own parameters and stopping points.
+void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>& dptr, const kmp_options* opt,
+              Totals& t)
+{
+    const int32_t nj = (int32_t)jobs.size();
+    const bool phase_sync = opt && opt->profile >= 2;
+    std::vector<std::unique_ptr<Level>> lv;
+    lv.emplace_back(new Level());
+    if (batch) {
+        build_union(c, jobs, dptr, *lv[0]);
+        if (lv[0]->mem.empty()) return;
+    } else {
+        Level& L0 = *lv[0];
+        L0.g = jobs[0].g;
+        L0.mem = {0};
+        L0.moff = {0, jobs[0].g.n};
+        L0.nn = {jobs[0].g.n};
+        L0.mm = {jobs[0].g.m};
+    }
+    std::vector<uint32_t> hseed(nj);
+    std::vector<uint64_t> seeds(nj);
+    std::vector<int64_t> lkv(nj);
+    for (int32_t j = 0; j < nj; ++j) {
+        hseed[j] = seed_hash(jobs[j].seed);
+        seeds[j] = jobs[j].seed;
+        lkv[j] = jobs[j].lk;
+    }
+    DBuf<uint32_t> dghash;
+    if (batch) dghash = upload(c, hseed);
+    const uint64_t seed0 = jobs[lv[0]->mem[0]].seed;  // scalar hash prefixes (one job)
+
+    // ---------------- coarsening
+    for (int32_t l = 0;; ++l) {
+        Level& L = *lv[l];
+        const DGraph& g = L.g;
+        for (int32_t j : L.mem) {
+            jobs[j].level_n.push_back(L.nn[j]);
+            jobs[j].level_m.push_back(L.mm[j]);
+        }
+        auto t0 = clk::now();
+        std::vector<uint8_t> takes(nj, 0);
+        std::vector<int64_t> U(nj, 0);
+        int32_t ntake = 0;
+        for (int32_t j : L.mem) {
+            if (L.nn[j] > 2 * kC && l < kMaxLevels) {
+                takes[j] = 1;
+                U[j] = level_U(L.nn[j], jobs[j].kc, jobs[j].cV, jobs[j].e);
+                ++ntake;
+            } else {
+                jobs[j].L = l;
+            }
+        }
+        if (ntake == 0) break;
+        const bool full = ntake == (int32_t)L.mem.size();
+        const JobTabs jt = tabs_of(L, dghash);
+        DBuf<uint8_t> dtakes;
+        DBuf<int64_t> dU;
+        if (batch) {
+            dU = upload(c, U);
+            if (!full) dtakes = upload(c, takes);
+        }
+        L.sched.reset(new LPSchedule());
+        lp_build_schedule(c, g, l, seed0, *L.sched, jt, dtakes.p);
+        L.sched_full = full;
+        DBuf<int32_t> label(c, (size_t)g.n);
+        DBuf<int64_t> cw(c, (size_t)g.n);
+        DBuf<uint32_t> fav(c, (size_t)g.n);
+        hipLaunchKernelGGL(k_iota_weights, dim3(grid_for(g.n)), dim3(kBlock), 0, c.stream, g.vwgt, g.n, label.p, cw.p,
+                           fav.p);
+        KMP_LAUNCH_CHECK();
+        LPState ls{label.p, cw.p, g.n, nullptr, batch ? 0 : U[0], fav.p, TAG_CL, jt,
+                   batch ? L.dnoff.p : nullptr, batch ? dU.p : nullptr};
+        LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
+        for (int r = 0; r < kRounds; ++r) t.moves_cl += lps.moves[r];
+        t.rated += lps.rated_edges;
+        std::vector<int64_t> nc;
+        if (!batch) {
+            two_hop(c, g, U[0], label.p, cw.p, fav.p, false);
+        } else {
+            count_nonempty_jobs(c, cw.p, g.n, jt, nj, nc);
+            std::vector<int64_t> lim(nj, 0);
+            bool any = false;
+            for (int32_t j : L.mem)
+                if (takes[j] && nc[j] > L.nn[j] / 2) {
+                    lim[j] = nc[j] - L.nn[j] / 2;
+                    any = true;
+                }
+            if (any) {
+                DBuf<int64_t> dlim = upload(c, lim);
+                two_hop_jobs(c, g, jt, dU.p, dlim.p, L.dgend.p, nj, label.p, cw.p, fav.p);
+            }
+        }
+        count_nonempty_jobs(c, cw.p, g.n, jt, batch ? nj : 1, nc);
+        t.ms_lp += ms_since(t0);
+        std::vector<uint8_t> keep(nj, 0);
+        int32_t nkeep = 0;
+        for (int32_t j : L.mem) {
+            if (!takes[j]) continue;
+            if (20LL * nc[j] > 19LL * L.nn[j]) {
+                jobs[j].L = l;  // converged: this level is the job's coarsest
+            } else {
+                keep[j] = 1;
+                ++nkeep;
+            }
+        }
+        if (nkeep == 0) break;
+        auto t1 = clk::now();
+        std::unique_ptr<Level> next(new Level());
+        L.map = DBuf<int32_t>(c, (size_t)g.n);
+        int32_t cn = 0;
+        int64_t cm = 0;
+        DBuf<uint8_t> dkeep;
+        if (batch) dkeep = upload(c, keep);
+        contract(c, g, label.p, cw.p, L.map.p, next->own, cn, cm, jt, dkeep.p);
+        next->g = next->own.view(cn, cm);
+        next->nn.assign(nj, 0);
+        next->mm.assign(nj, 0);
+        next->moff.assign(1, 0);
+        for (int32_t j : L.mem)
+            if (keep[j]) {
+                next->mem.push_back(j);
+                next->nn[j] = (int32_t)nc[j];
+                next->moff.push_back(next->moff.back() + nc[j]);
+                t.contracted += L.mm[j];
+            }
+        if (!batch) {
+            next->mm[0] = cm;
+        } else {
+            set_level_tables(c, *next, nj);
+            const int32_t cnt = (int32_t)next->mem.size();
+            DBuf<int64_t> ends(c, (size_t)cnt + 1);
+            hipLaunchKernelGGL(k_gather_at, dim3(grid_for(cnt + 1)), dim3(kBlock), 0, c.stream, next->own.xadj.p,
+                               next->dmoff.p, cnt + 1, ends.p);
+            KMP_LAUNCH_CHECK();
+            std::vector<int64_t> he(cnt + 1);
+            c.read(he.data(), ends.p, sizeof(int64_t) * (cnt + 1));
+            for (int32_t i = 0; i < cnt; ++i) next->mm[next->mem[i]] = he[i + 1] - he[i];
+        }
+        if (phase_sync) c.sync();
+        t.ms_con += ms_since(t1);
+        lv.push_back(std::move(next));
+    }
+    int32_t Lmax = 0;
+    for (int32_t j : lv[0]->mem) Lmax = std::max(Lmax, jobs[j].L);
+
+    // ---------------- uncoarsening
+    BlockTab bt;
+    DBuf<int32_t> part;
+    DBuf<int64_t> wt, cap;
+    for (int32_t l = Lmax; l >= 0; --l) {
+        Level& L = *lv[l];
+        const DGraph& g = L.g;
+        const JobTabs jt = tabs_of(L, dghash);
+        auto t0 = clk::now();
+        // block table: projected jobs keep their blocks; a job whose coarsest
+        // level is this one starts with the single block (0, k)
+        BlockTab nt;
+        std::vector<int32_t> remap(std::max(bt.size(), 1)), start(nj, -1);
+        int32_t ob = 0;
+        for (int32_t j : L.mem) {
+            if (jobs[j].L == l) {
+                start[j] = nt.size();
+                nt.first.push_back(0);
+                nt.f.push_back(jobs[j].k);
+                nt.job.push_back(j);
+            } else {
+                while (ob < bt.size() && bt.job[ob] == j) {
+                    remap[ob] = nt.size();
+                    nt.first.push_back(bt.first[ob]);
+                    nt.f.push_back(bt.f[ob]);
+                    nt.job.push_back(j);
+                    ++ob;
+                }
+            }
+        }
+        DBuf<int32_t> fine(c, (size_t)std::max(g.n, 1));
+        if (!batch) {
+            if (l == Lmax) c.zero(fine.p, sizeof(int32_t) * (size_t)g.n);
+            else project(c, part.p, L.map.p, fine.p, g.n);
+        } else {
+            DBuf<int32_t> dremap = upload(c, remap), dstart = upload(c, start);
+            project_jobs(c, l == Lmax ? nullptr : part.p, l == Lmax ? nullptr : L.map.p, dremap.p, L.gid.p,
+                         dstart.p, fine.p, g.n);
+        }
+        part = std::move(fine);
+        bt = std::move(nt);
+        // bipartition blocks until every job has k'_l blocks (Alg. 1, Sec. 4)
+        std::vector<int32_t> kp(nj, 0);
+        for (int32_t j : L.mem) {
+            kp[j] = (l == 0) ? jobs[j].k : std::min(jobs[j].k, ceil2_div_C(L.nn[j]));
+            kp[j] = std::max(kp[j], 2);
+        }
+        auto t1 = clk::now();
+        for (;;) {
+            std::vector<int32_t> nbj(nj, 0);
+            for (int32_t b = 0; b < bt.size(); ++b) ++nbj[bt.job[b]];
+            std::vector<uint8_t> split(bt.size());
+            bool any = false;
+            for (int32_t b = 0; b < bt.size(); ++b) {
+                split[b] = bt.f[b] >= 2 && nbj[bt.job[b]] < kp[bt.job[b]];
+                any |= split[b] != 0;
+            }
+            if (!any) break;
+            t.bip += bipartition_round(c, g, l, part.p, bt, split, lkv, hseed);
+        }
+        if (phase_sync) c.sync();
+        t.ms_ip += ms_since(t1);
+        auto t2 = clk::now();
+        const int32_t nb = bt.size();
+        wt = DBuf<int64_t>(c, (size_t)nb);
+        cap = DBuf<int64_t>(c, (size_t)nb);
+        block_weights(c, g, part.p, nb, wt.p);
+        std::vector<int64_t> hcap(nb);
+        std::vector<int32_t> boff(nj, 0);
+        for (int32_t b = nb - 1; b >= 0; --b) {
+            hcap[b] = (int64_t)bt.f[b] * jobs[bt.job[b]].lk;
+            boff[bt.job[b]] = b;
+        }
+        c.write(cap.p, hcap.data(), sizeof(int64_t) * nb);
+        DBuf<int32_t> dboff;
+        if (batch) dboff = upload(c, boff);
+        if (!L.sched || !L.sched_full) {
+            L.sched.reset(new LPSchedule());
+            lp_build_schedule(c, g, l, seed0, *L.sched, jt, nullptr);
+            L.sched_full = true;
+        }
+        t.brounds += balance(c, g, l, batch ? seeds : std::vector<uint64_t>{seed0}, *L.sched, part.p, wt.p, bt, cap.p,
+                             jt, dboff.p);
+        LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF, jt, dboff.p, nullptr};
+        LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
+        for (int r = 0; r < kRounds; ++r) t.moves_ref += lps.moves[r];
+        t.rated += lps.rated_edges;
+        if (phase_sync) c.sync();
+        t.ms_ref += ms_since(t2) + (ms_since(t0) - ms_since(t1));
+        // the coarser level is no longer needed
+        if (l < Lmax) lv[l + 1].reset();
+    }
+    // ---------------- final block ids, cuts and statuses
+    Level& L0 = *lv[0];
+    const int32_t nb = bt.size();
+    DBuf<int32_t> dfirst = upload(c, bt.first);
+    if (!batch) {
+        hipLaunchKernelGGL(k_final_ids, dim3(grid_for(L0.g.n)), dim3(kBlock), 0, c.stream, part.p, dfirst.p, L0.g.n,
+                           jobs[0].out);
+        KMP_LAUNCH_CHECK();
+    } else {
+        hipLaunchKernelGGL(k_final_ids_jobs, dim3(grid_for(L0.g.n)), dim3(kBlock), 0, c.stream, part.p, dfirst.p,
+                           L0.gid.p, L0.dnoff.p, dptr.p, L0.g.n);
+        KMP_LAUNCH_CHECK();
+    }
+    std::vector<int64_t> hw(nb);
+    c.read(hw.data(), wt.p, sizeof(int64_t) * nb);
+    for (int32_t b = 0; b < nb; ++b) jobs[bt.job[b]].maxw = std::max(jobs[bt.job[b]].maxw, hw[b]);
+    if (!batch) {
+        jobs[0].cut = edge_cut(c, L0.g, part.p);
+    } else {
+        std::vector<int64_t> cuts;
+        edge_cut_jobs(c, L0.g, part.p, L0.gid.p, nj, cuts);
+        for (int32_t j : L0.mem) jobs[j].cut = cuts[j];
+    }
+    for (int32_t j : L0.mem) jobs[j].status = jobs[j].maxw > jobs[j].lk ? KMP_IMBALANCED : KMP_OK;
+    c.sync();
+}
+
+// Derived integers of a job (Sec. 2 balance constraint, Sec. 5.1); k = 1 and
+// n = 0 jobs are finished here.
+void setup_job(Ctx& c, JobRun& jb)
+{
+    jb.e = eps_ppm(jb.eps);
+    const int64_t W = (jb.cV + jb.k - 1) / jb.k;
+    jb.lk = W * (kPPM + jb.e) / kPPM;
+    jb.kc = (int32_t)std::min<int64_t>(jb.k, jb.g.n / kC);
+    jb.run = jb.g.n > 0 && jb.k > 1;
+    if (jb.g.n > 0 && jb.k == 1) {
+        fill_i32(c, jb.out, 0, jb.g.n);
+        jb.maxw = jb.cV;
+        jb.level_n = {jb.g.n};
+        jb.level_m = {jb.g.m};
+        jb.L = 0;
+        jb.status = jb.cV > jb.lk ? KMP_IMBALANCED : KMP_OK;
+    }
+    if (jb.g.n == 0) jb.status = KMP_OK;
+}
+
+void fill_stats(kmp_stats* st, const JobRun& jb, const Totals& t)
+{
+    st->cut = jb.cut;
+    st->lk = jb.lk;
+    st->max_block_weight = jb.maxw;
+    st->levels = std::max(jb.L, 0);
+    for (size_t l = 0; l < jb.level_n.size() && l <= (size_t)kMaxLevels; ++l) {
+        st->level_n[l] = jb.level_n[l];
+        st->level_m[l] = jb.level_m[l];
+    }
+    st->bipartitions = t.bip;
+    st->balance_rounds = t.brounds;
+    st->lp_cluster_moves = t.moves_cl;
+    st->lp_refine_moves = t.moves_ref;
+    st->lp_rated_edges = t.rated;
+    st->contracted_edges = t.contracted;
+    st->ms_coarsen_lp = t.ms_lp;
+    st->ms_contract = t.ms_con;
+    st->ms_initial = t.ms_ip;
+    st->ms_refine = t.ms_ref;
+}
+
 int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32_t* out_part, hipStream_t stream,
                    const kmp_options* opt, kmp_stats* st)
 {
@@ -198,158 +807,103 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
     init_pool_once();
     Ctx c(stream);
     std::unique_ptr<Prof> prof;
-    const bool phase_sync = opt && opt->profile >= 2;  // phase timers wait for the device (profile = 2)
     if (opt && opt->profile) {
         prof.reset(new Prof());
         prof->mask = opt->profile_classes;
         c.prof = prof.get();
     }
-    const int64_t cV = prepare(c, g0);
+    std::vector<JobRun> jobs(1);
+    JobRun& jb = jobs[0];
+    jb.g = g0;
+    jb.k = k;
+    jb.eps = eps;
+    jb.seed = seed;
+    jb.out = out_part;
+    jb.cV = prepare(c, g0);
     if (opt && opt->validate) {
         int rc = validate_graph(c, g0);
         if (rc != KMP_OK) return rc;
     }
-    const int64_t e = eps_ppm(eps);
-    const int64_t W = (cV + k - 1) / k;
-    const int64_t lk = W * (kPPM + e) / kPPM;
-    if (st) st->lk = lk;
-    const int32_t n = g0.n;
-    if (k == 1) {
-        fill_i32(c, out_part, 0, n);
-        c.sync();
-        if (st) {
-            st->max_block_weight = cV;
-            st->level_n[0] = n;
-            st->level_m[0] = g0.m;
-            st->ms_total = ms_since(t_start);
-        }
-        return cV > lk ? KMP_IMBALANCED : KMP_OK;
-    }
-
-    // ---------------- coarsening
-    std::vector<std::unique_ptr<Level>> lv;
-    lv.emplace_back(new Level());
-    lv[0]->g = g0;
-    int32_t kc = std::min<int64_t>(k, n / kC);
-    double ms_lp = 0, ms_con = 0, ms_ip = 0, ms_ref = 0;
-    int64_t moves_cl = 0, moves_ref = 0, rated = 0, contracted = 0;
-    while (lv.back()->g.n > 2 * kC && (int)lv.size() - 1 < kMaxLevels) {
-        Level& L = *lv.back();
-        const DGraph& g = L.g;
-        const int32_t level = (int32_t)lv.size() - 1;
-        auto t0 = clk::now();
-        const int64_t U = level_U(g.n, kc, cV, e);
-        L.sched.reset(new LPSchedule());
-        lp_build_schedule(c, g, level, seed, *L.sched);
-        DBuf<int32_t> label(c, (size_t)g.n);
-        DBuf<int64_t> cw(c, (size_t)g.n);
-        DBuf<uint32_t> fav(c, (size_t)g.n);
-        hipLaunchKernelGGL(k_iota_weights, dim3(grid_for(g.n)), dim3(kBlock), 0, c.stream, g.vwgt, g.n, label.p, cw.p,
-                           fav.p);
-        KMP_LAUNCH_CHECK();
-        LPState ls{label.p, cw.p, g.n, nullptr, U, fav.p, TAG_CL};
-        LPStats lps = lp_run(c, g, level, seed, *L.sched, ls);
-        for (int r = 0; r < kRounds; ++r) moves_cl += lps.moves[r];
-        rated += lps.rated_edges;
-        two_hop(c, g, U, label.p, cw.p, fav.p);
-        const int32_t nc = count_nonempty(c, cw.p, g.n);
-        ms_lp += ms_since(t0);
-        if (20LL * nc > 19LL * g.n) break;  // converged: keep this level as the coarsest
-        auto t1 = clk::now();
-        std::unique_ptr<Level> next(new Level());
-        L.map = DBuf<int32_t>(c, (size_t)g.n);
-        int32_t cn = 0;
-        int64_t cm = 0;
-        contract(c, g, label.p, cw.p, L.map.p, next->own, cn, cm);
-        next->g = next->own.view(cn, cm);
-        contracted += g.m;
-        if (phase_sync) c.sync();
-        ms_con += ms_since(t1);
-        lv.push_back(std::move(next));
-    }
-    const int32_t Lc = (int32_t)lv.size() - 1;
-    if (st) {
-        st->levels = Lc;
-        for (int32_t l = 0; l <= Lc; ++l) {
-            st->level_n[l] = lv[l]->g.n;
-            st->level_m[l] = lv[l]->g.m;
-        }
-    }
-
-    // ---------------- uncoarsening
-    std::vector<int32_t> first{0}, fcount{k};
-    DBuf<int32_t> part(c, (size_t)lv[Lc]->g.n);
-    c.zero(part.p, sizeof(int32_t) * (size_t)lv[Lc]->g.n);
-    int32_t bip = 0, brounds = 0;
-    DBuf<int64_t> wt, cap;
-    for (int32_t l = Lc; l >= 0; --l) {
-        Level& L = *lv[l];
-        const DGraph& g = L.g;
-        auto t0 = clk::now();
-        if (l < Lc) {
-            DBuf<int32_t> fine(c, (size_t)g.n);
-            project(c, part.p, L.map.p, fine.p, g.n);
-            part = std::move(fine);
-        }
-        int32_t kp = (l == 0) ? k : std::min(k, ceil2_div_C(g.n));
-        kp = std::max(kp, 2);
-        auto t1 = clk::now();
-        while ((int32_t)first.size() < kp) bip += bipartition_round(c, g, l, part.p, first, fcount, lk, seed);
-        if (phase_sync) c.sync();
-        ms_ip += ms_since(t1);
-        auto t2 = clk::now();
-        const int32_t nb = (int32_t)first.size();
-        wt = DBuf<int64_t>(c, (size_t)nb);
-        cap = DBuf<int64_t>(c, (size_t)nb);
-        block_weights(c, g, part.p, nb, wt.p);
-        std::vector<int64_t> hcap(nb);
-        for (int32_t b = 0; b < nb; ++b) hcap[b] = (int64_t)fcount[b] * lk;
-        c.write(cap.p, hcap.data(), sizeof(int64_t) * nb);
-        if (!L.sched) {
-            L.sched.reset(new LPSchedule());
-            lp_build_schedule(c, g, l, seed, *L.sched);
-        }
-        brounds += balance(c, g, l, seed, *L.sched, part.p, wt.p, nb, cap.p);
-        LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF};
-        LPStats lps = lp_run(c, g, l, seed, *L.sched, ls);
-        for (int r = 0; r < kRounds; ++r) moves_ref += lps.moves[r];
-        rated += lps.rated_edges;
-        if (phase_sync) c.sync();
-        ms_ref += ms_since(t2) + (ms_since(t0) - ms_since(t1));
-        // the finer level no longer needs this level's storage
-        if (l < Lc) lv[l + 1].reset();
-    }
-    // ---------------- final block ids and status
-    const int32_t nb = (int32_t)first.size();
-    DBuf<int32_t> dfirst(c, (size_t)nb);
-    c.write(dfirst.p, first.data(), sizeof(int32_t) * nb);
-    hipLaunchKernelGGL(k_final_ids, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part.p, dfirst.p, n, out_part);
-    KMP_LAUNCH_CHECK();
-    std::vector<int64_t> hw(nb);
-    c.read(hw.data(), wt.p, sizeof(int64_t) * nb);
-    int64_t maxw = 0;
-    for (int64_t x : hw) maxw = std::max(maxw, x);
-    if (st) {
-        st->cut = edge_cut(c, g0, part.p);
-        st->max_block_weight = maxw;
-        st->bipartitions = bip;
-        st->balance_rounds = brounds;
-        st->lp_cluster_moves = moves_cl;
-        st->lp_refine_moves = moves_ref;
-        st->lp_rated_edges = rated;
-        st->contracted_edges = contracted;
-        st->ms_coarsen_lp = ms_lp;
-        st->ms_contract = ms_con;
-        st->ms_initial = ms_ip;
-        st->ms_refine = ms_ref;
-    }
+    setup_job(c, jb);
+    Totals t;
+    if (jb.run) run_jobs(c, jobs, false, DBuf<JobPtrs>(), opt, t);
     c.sync();
     if (st) {
+        fill_stats(st, jb, t);
         st->ms_total = ms_since(t_start);
         if (prof) c.prof_collect(st->prof_launches, st->prof_ms, st->prof_bytes);
     }
     c.prof = nullptr;
-    return maxw > lk ? KMP_IMBALANCED : KMP_OK;
+    return jb.status;
+}
+
+int partition_batch_impl(const kmp_graph_desc* gd, int32_t count, kmp_job_result* res, hipStream_t stream,
+                         const kmp_options* opt, kmp_stats* st)
+{
+    auto t_start = clk::now();
+    init_pool_once();
+    Ctx c(stream);
+    std::unique_ptr<Prof> prof;
+    if (opt && opt->profile) {
+        prof.reset(new Prof());
+        prof->mask = opt->profile_classes;
+        c.prof = prof.get();
+    }
+    std::vector<JobRun> jobs(count);
+    for (int32_t i = 0; i < count; ++i) {
+        JobRun& jb = jobs[i];
+        const kmp_graph_desc& d = gd[i];
+        jb.g.n = d.n;
+        jb.g.m = d.m;
+        jb.g.xadj = d.xadj;
+        jb.g.adjncy = d.adjncy;
+        jb.g.vwgt = d.vwgt;
+        jb.g.adjwgt = d.adjwgt;
+        jb.k = d.k;
+        jb.eps = d.epsilon;
+        jb.seed = d.seed;
+        jb.out = d.out_part;
+        jb.status = check_args(d.xadj, d.n, d.m, d.k, d.epsilon, d.out_part);
+        if (jb.status == KMP_OK && d.n == 0 && d.m != 0) jb.status = KMP_EINVAL;
+        jb.run = jb.status == KMP_OK && d.n > 0;
+    }
+    if (opt && opt->validate)
+        for (auto& jb : jobs)
+            if (jb.run) {
+                jb.status = validate_graph(c, jb.g);
+                jb.run = jb.status == KMP_OK;
+            }
+    // m == xadj[n] and the weight sums, for the whole batch at once
+    Totals t;
+    DBuf<JobPtrs> dptr;
+    check_batch(c, jobs, dptr);
+    for (auto& jb : jobs)
+        if (jb.run) setup_job(c, jb);
+    bool any = false;
+    for (auto& jb : jobs) any |= jb.run;
+    if (any) run_jobs(c, jobs, true, dptr, opt, t);
+    c.sync();
+    if (res)
+        for (int32_t i = 0; i < count; ++i) {
+            kmp_job_result& r = res[i];
+            memset(&r, 0, sizeof(r));
+            r.status = jobs[i].status;
+            r.levels = std::max(jobs[i].L, 0);
+            r.cut = jobs[i].cut;
+            r.max_block_weight = jobs[i].maxw;
+            r.lk = jobs[i].lk;
+            for (size_t l = 0; l < jobs[i].level_n.size() && l <= (size_t)kMaxLevels; ++l)
+                r.level_n[l] = jobs[i].level_n[l];
+        }
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        fill_stats(st, JobRun(), t);
+        for (auto& jb : jobs) st->cut += jb.cut;
+        st->ms_total = ms_since(t_start);
+        if (prof) c.prof_collect(st->prof_launches, st->prof_ms, st->prof_bytes);
+    }
+    c.prof = nullptr;
+    return KMP_OK;
 }
 
 DGraph make_graph(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt, int32_t n,
@@ -405,6 +959,17 @@ int kmp_partition(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwg
                   int64_t m, int32_t k, double epsilon, uint64_t seed, int32_t* out_part, void* stream)
 {
     return kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, n, m, k, epsilon, seed, out_part, stream, nullptr, nullptr);
+}
+
+int kmp_partition_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_result* results, void* stream,
+                        const kmp_options* opt, kmp_stats* stats)
+{
+    if (stats) memset(stats, 0, sizeof(*stats));
+    if (count < 0 || (count > 0 && !graphs)) return KMP_EINVAL;
+    if (count == 0) return KMP_OK;
+    return (int)guarded([&]() -> int64_t {
+        return partition_batch_impl(graphs, count, results, (hipStream_t)stream, opt, stats);
+    });
 }
 
 const char* kmp_strerror(int code)
@@ -517,14 +1082,20 @@ int kmp_bipartition_round(const int32_t* xadj, const int32_t* adjncy, const int3
         int32_t m32 = 0;
         if (n > 0) c.read(&m32, xadj + n, sizeof(int32_t));
         DGraph g = make_graph(xadj, adjncy, vwgt, adjwgt, n, m32);
-        std::vector<int32_t> f(first, first + *nblocks), fc(fcount, fcount + *nblocks);
-        bipartition_round(c, g, level, part, f, fc, lk, seed);
+        BlockTab bt;
+        bt.first.assign(first, first + *nblocks);
+        bt.f.assign(fcount, fcount + *nblocks);
+        bt.job.assign(*nblocks, 0);
+        std::vector<uint8_t> split(*nblocks);
+        for (int32_t b = 0; b < *nblocks; ++b) split[b] = bt.f[b] >= 2;
+        bipartition_round(c, g, level, part, bt, split, std::vector<int64_t>{lk},
+                          std::vector<uint32_t>{seed_hash(seed)});
         c.sync();
-        for (size_t i = 0; i < f.size(); ++i) {
-            first[i] = f[i];
-            fcount[i] = fc[i];
+        for (int32_t i = 0; i < bt.size(); ++i) {
+            first[i] = bt.first[i];
+            fcount[i] = bt.f[i];
         }
-        *nblocks = (int32_t)f.size();
+        *nblocks = bt.size();
         return KMP_OK;
     });
 }
@@ -543,7 +1114,11 @@ int kmp_balance(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
         DGraph g = make_graph(xadj, adjncy, vwgt, adjwgt, n, m32);
         LPSchedule sched;
         lp_build_schedule(c, g, level, seed, sched);
-        int32_t r = balance(c, g, level, seed, sched, part, wt, nb, cap);
+        BlockTab bt;
+        bt.first.assign(nb, 0);
+        bt.f.assign(nb, 1);
+        bt.job.assign(nb, 0);
+        int32_t r = balance(c, g, level, std::vector<uint64_t>{seed}, sched, part, wt, bt, cap);
         c.sync();
         return r;
     });

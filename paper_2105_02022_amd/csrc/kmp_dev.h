@@ -74,6 +74,15 @@ inline uint32_t hash_prefix(uint64_t seed, std::initializer_list<uint32_t> args)
     return h;
 }
 
+// H over (seed; a1, a2, a3) from the seed part of the prefix (kernels of a
+// batch finish per-job prefixes themselves).
+__host__ __device__ inline uint32_t hash3(uint32_t hseed, uint32_t a1, uint32_t a2, uint32_t a3)
+{
+    return hash_step(hash_step(hash_step(hseed, a1, 1), a2, 2), a3, 3);
+}
+
+inline uint32_t seed_hash(uint64_t seed) { return hash_prefix(seed, {}); }
+
 // ---------------------------------------------------------------- device misc
 __device__ inline uint64_t ballot64(bool p) { return __ballot(p); }
 
@@ -152,6 +161,25 @@ enum SpreadCounter {
 __device__ inline void spread_add(int64_t* base, int64_t v)
 {
     atomicAdd((unsigned long long*)&base[blockIdx.x & (kSpreadSlots - 1)], (unsigned long long)v);
+}
+
+// out[j] += x for every lane with job j >= 0.  Node ids are grouped by job, so
+// a wavefront mostly holds one job: then one lane adds the wave's sum.  Every
+// lane of the wavefront must call this.
+__device__ inline void job_add(int64_t* out, int32_t j, int64_t x)
+{
+    const uint64_t valid = __ballot(j >= 0);
+    if (!valid) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((unsigned long long)valid) - 1;
+    const int32_t jl = __shfl(j, leader, 64);
+    if (__ballot(j >= 0 && j != jl) == 0) {
+        int64_t sum = j >= 0 ? x : 0;
+        for (int d = 32; d > 0; d >>= 1) sum += __shfl_xor(sum, d, 64);
+        if (lane == leader && sum) atomicAdd((unsigned long long*)&out[jl], (unsigned long long)sum);
+    } else if (j >= 0 && x) {
+        atomicAdd((unsigned long long*)&out[j], (unsigned long long)x);
+    }
 }
 
 // ---------------------------------------------------------------- context
@@ -305,6 +333,18 @@ int64_t node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n);
 int64_t edge_weight_sum(Ctx& c, const int32_t* adjwgt, int64_t m);
 int bits_for(uint64_t max_value);
 
+// ---------------------------------------------------------------- batches
+// The jobs of a batch run level by level as one disjoint union of their level
+// graphs, concatenated in job order.  gid[v] is the job of node v; per-job
+// tables are indexed by job.  Hashes take job-local arguments (a node or label
+// minus its job's offset, each job's own seed), so every job's result is the
+// one it gets alone.  One graph: gid = NULL (every node is job 0, offset 0).
+struct JobTabs {
+    const int32_t* gid = nullptr;     // [n] job of every node
+    const uint32_t* ghash = nullptr;  // [jobs] seed_hash of every job's seed
+    const int32_t* noff = nullptr;    // [jobs] first node of every job at this level
+};
+
 // ---------------------------------------------------------------- LP (lp.hip)
 struct LPState {
     int32_t* label;     // [n]
@@ -314,6 +354,11 @@ struct LPState {
     int64_t cap_scalar;
     uint32_t* fav;      // [n] or NULL (clustering only)
     uint32_t tag;
+    // batches: label offset of every job (node offset for clustering, block
+    // offset for refinement) and per-job scalar caps (clustering) or NULL
+    JobTabs jt = {};
+    const int32_t* loff = nullptr;
+    const int64_t* gcap = nullptr;
 };
 
 struct LPStats {
@@ -329,7 +374,7 @@ constexpr int kSegs = kTiers * kSub;
 
 struct LPSchedule {
     DBuf<int32_t> order;              // node ids grouped by (tier, class), ascending id inside a segment
-    int32_t off[kSegs + 1] = {};      // segment start in `order`; off[kSegs] = n
+    int32_t off[kSegs + 1] = {};      // segment start in `order`; off[kSegs] = scheduled nodes
     int32_t cnt[kSegs] = {};          // segment size
     DBuf<int32_t> segtab;             // device copy: [kSegs offsets][kSegs counts]
     int32_t hub_start = 0;            // hubs (last tier) of all classes are contiguous from here
@@ -343,7 +388,10 @@ struct LPSchedule {
     }
 };
 
-void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched);
+// Schedule of the nodes of one level.  Batches: per-job seeds through jt, and
+// only the nodes of jobs with gpart[job] != 0 are scheduled (gpart NULL: all).
+void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched,
+                       const JobTabs& jt = {}, const uint8_t* gpart = nullptr);
 LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st);
 int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32_t s, uint64_t seed,
                     const LPSchedule& sched, LPState& st, const uint8_t* active, uint8_t* moved);
@@ -352,28 +400,60 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
 // the adjacent non-overloaded block with the largest connection that fits
 // (bal_t, -1 if none) and d = conn(target) - conn(own block) (bal_d; -conn(own)
 // when there is no target).
+// Batches: jt and the per-job block offsets boff make the hash job-local.
 void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int32_t round,
                       const LPSchedule& sched, const int32_t* part, const int64_t* wt, const int64_t* cap,
-                      const uint8_t* over, int32_t* bal_t, int64_t* bal_d);
+                      const uint8_t* over, int32_t* bal_t, int64_t* bal_d, const JobTabs& jt = {},
+                      const int32_t* boff = nullptr);
 
 // ---------------------------------------------------------------- coarsening (coarsen.hip)
-int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav);
+// Two-hop of one graph; returns the number of merges when `count` is set
+// (one more read-back), else 0.
+int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav,
+                bool count = true);
+// Two-hop of a batch: per-job bounds gU, merge limits glimit and node range
+// ends gend (device, by job; jobs with limit 0 do not take part).
+void two_hop_jobs(Ctx& c, const DGraph& g, const JobTabs& jt, const int64_t* gU, const int64_t* glimit,
+                  const int32_t* gend, int32_t njobs, int32_t* label, int64_t* cw, const uint32_t* fav);
 int32_t count_nonempty(Ctx& c, const int64_t* cw, int32_t n);
+// Non-empty labels of every job (labels of job j are its node ids).
+void count_nonempty_jobs(Ctx& c, const int64_t* cw, int32_t n, const JobTabs& jt, int32_t njobs,
+                         std::vector<int64_t>& out);
 // Contract; returns coarse sizes; allocates the coarse graph in `out`.
+// Batches: only nodes of jobs with gkeep[job] != 0 are contracted (the others
+// get map = -1); coarse ids stay grouped by job.
 void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
-              int32_t& cn, int64_t& cm);
+              int32_t& cn, int64_t& cm, const JobTabs& jt = {}, const uint8_t* gkeep = nullptr);
 
 // ---------------------------------------------------------------- IP (ip.hip)
-// One bipartitionBlocks round; first/fcount host vectors are updated.
-int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, std::vector<int32_t>& first,
-                          std::vector<int32_t>& fcount, int64_t lk, uint64_t seed);
+// Block table of a level: blocks in job order, ascending `first` inside a job.
+struct BlockTab {
+    std::vector<int32_t> first, f, job;
+    int32_t size() const { return (int32_t)first.size(); }
+};
+// One bipartitionBlocks round over the blocks with split[b] != 0 (f >= 2);
+// the table is updated.  Per job: L_k (lk) and the seed part of the hash.
+int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, BlockTab& bt,
+                          const std::vector<uint8_t>& split, const std::vector<int64_t>& lk,
+                          const std::vector<uint32_t>& hseed);
 void project(Ctx& c, const int32_t* coarse_part, const int32_t* map, int32_t* fine_part, int32_t n);
+// Batches: nodes with map >= 0 take remap[coarse block]; the others start in
+// their job's single block start_block[job].
+void project_jobs(Ctx& c, const int32_t* coarse_part, const int32_t* map, const int32_t* remap,
+                  const int32_t* gid, const int32_t* start_block, int32_t* fine_part, int32_t n);
 void block_weights(Ctx& c, const DGraph& g, const int32_t* part, int32_t nb, int64_t* wt);
 int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part);
+// Cut of every job (gid by node).
+void edge_cut_jobs(Ctx& c, const DGraph& g, const int32_t* part, const int32_t* gid, int32_t njobs,
+                   std::vector<int64_t>& out);
 
 // ---------------------------------------------------------------- balance (balance.hip)
-int32_t balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, int32_t* part,
-                int64_t* wt, int32_t nb, const int64_t* cap);
+// Balancer rounds.  Batches: bt.job gives every block's job, jt/boff make the
+// hashes job-local and each job stops on its own (no overload, or a round
+// without moves).
+int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64_t>& seeds,
+                const LPSchedule& sched, int32_t* part, int64_t* wt, const BlockTab& bt, const int64_t* cap,
+                const JobTabs& jt = {}, const int32_t* boff = nullptr);
 
 // ---------------------------------------------------------------- validation (kmp.hip)
 int validate_graph(Ctx& c, const DGraph& g);

@@ -46,23 +46,34 @@ __device__ inline int tier_of(int32_t d)
 }
 
 // ---------------------------------------------------------------- schedule
+// key = tier * S + class; nodes of jobs that do not take part get key kSegs
+// (sorted behind every segment)
 __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict__ xadj, int32_t n, uint32_t hsub,
+                                                       JobTabs jt, const uint8_t* __restrict__ gpart, uint32_t level,
                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ val,
                                                        int32_t* __restrict__ cnt)
 {
-    __shared__ int32_t h[kSegs];
-    if (threadIdx.x < kSegs) h[threadIdx.x] = 0;
+    __shared__ int32_t h[kSegs + 1];
+    if (threadIdx.x <= kSegs) h[threadIdx.x] = 0;
     __syncthreads();
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v < n) {
-        uint32_t s = hash_step(hsub, (uint32_t)v, 3) % kSub;
-        uint32_t k = (uint32_t)tier_of(xadj[v + 1] - xadj[v]) * kSub + s;
+        uint32_t hs = hsub, vl = (uint32_t)v;
+        bool takes_part = true;
+        if (jt.gid) {
+            const int32_t j = jt.gid[v];
+            hs = hash_step(hash_step(jt.ghash[j], TAG_SUB, 1), level, 2);
+            vl = (uint32_t)(v - jt.noff[j]);
+            takes_part = !gpart || gpart[j];
+        }
+        const uint32_t s = hash_step(hs, vl, 3) % kSub;
+        const uint32_t k = takes_part ? (uint32_t)tier_of(xadj[v + 1] - xadj[v]) * kSub + s : (uint32_t)kSegs;
         key[v] = k;
         val[v] = (uint32_t)v;
         atomicAdd(&h[k], 1);
     }
     __syncthreads();
-    if (threadIdx.x < kSegs && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x <= kSegs && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void k_hub_slots(const int32_t* __restrict__ xadj, const int32_t* __restrict__ hubs, int32_t nh,
@@ -140,9 +151,28 @@ struct RateArgs {
     const uint8_t* over;
     int32_t* bal_t;
     int64_t* bal_d;
+    // batches (gid != NULL): per-job seed hash, label offset and scalar cap;
+    // the per-node prefix is H(seed_job; tag, level, round)
+    const int32_t* gid;
+    const uint32_t* ghash;
+    const int32_t* loff;
+    const int64_t* gcap;
+    uint32_t tag, level, round;
 };
 
-__device__ inline int64_t cap_of(const RateArgs& a, uint32_t K) { return a.cap_vec ? a.cap_vec[K] : a.cap_scalar; }
+// Per-node part of the rating key: hash prefix, label offset, scalar cap.
+struct NodeKey {
+    uint32_t hp, lo;
+    int64_t cap;
+};
+
+__device__ inline NodeKey node_key(const RateArgs& a, int32_t v)
+{
+    if (!a.gid) return NodeKey{a.hpre, 0u, a.cap_scalar};
+    const int32_t j = a.gid[v];
+    return NodeKey{hash3(a.ghash[j], a.tag, a.level, a.round), (uint32_t)a.loff[j],
+                   a.gcap ? a.gcap[j] : a.cap_scalar};
+}
 
 __device__ inline bool aborted(const RateArgs& a) { return a.ctl && a.ctl[CTL_ABORT] != 0; }
 
@@ -168,18 +198,19 @@ __device__ inline void write_result(const RateArgs& a, int32_t v, const Key3& fa
 }
 
 // Evaluate one aggregated (label, rating) entry for the lane-local bests.
-__device__ inline void consider(const RateArgs& a, uint32_t key, uint32_t val, uint32_t own, int64_t cv, Key3& fav,
-                                Key3& adm, uint32_t& rown)
+__device__ inline void consider(const RateArgs& a, const NodeKey& nk, uint32_t key, uint32_t val, uint32_t own,
+                                int64_t cv, Key3& fav, Key3& adm, uint32_t& rown)
 {
     if (key == EMPTY) return;
     if (key == own) {
         rown = val;
         return;
     }
-    Key3 c{val, hash_step(a.hpre, key, 4), key};
+    Key3 c{val, hash_step(nk.hp, key - nk.lo, 4), key};
     if (better(c, fav)) fav = c;
     if (better(c, adm)) {
-        if (a.wt[key] + cv <= cap_of(a, key) && !(a.over && a.over[key])) adm = c;
+        const int64_t cap = a.cap_vec ? a.cap_vec[key] : nk.cap;
+        if (a.wt[key] + cv <= cap && !(a.over && a.over[key])) adm = c;
     }
 }
 
@@ -220,6 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
         const int32_t e0 = a.xadj[v];
         const int32_t d = a.xadj[v + 1] - e0;
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
+        const NodeKey nk = node_key(a, v);
         uint32_t lab[T0_DEG], w[T0_DEG];
         if (d > 0) {
             int32_t u[T0_DEG];
@@ -258,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
         for (int j = 0; j < T0_DEG; ++j) wk[j] = a.wt[lab[j] != EMPTY ? lab[j] : own];
         int64_t ck[T0_DEG];
 #pragma unroll
-        for (int j = 0; j < T0_DEG; ++j) ck[j] = CAPV ? a.cap_vec[lab[j] != EMPTY ? lab[j] : own] : a.cap_scalar;
+        for (int j = 0; j < T0_DEG; ++j) ck[j] = CAPV ? a.cap_vec[lab[j] != EMPTY ? lab[j] : own] : nk.cap;
         bool ov[T0_DEG];
 #pragma unroll
         for (int j = 0; j < T0_DEG; ++j) ov[j] = BAL ? a.over[lab[j] != EMPTY ? lab[j] : own] != 0 : false;
@@ -269,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
             const bool is_own = lab[j] == own;
             rown = is_own ? w[j] : rown;
             const bool cand = lab[j] != EMPTY && !is_own;
-            const Key3 c{w[j], hash_step(a.hpre, lab[j], 4), lab[j]};
+            const Key3 c{w[j], hash_step(nk.hp, lab[j] - nk.lo, 4), lab[j]};
             if (cand && better(c, fav)) fav = c;
             if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
         }
@@ -341,8 +373,9 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
         int64_t cv = 0;
         if (v >= 0) {
             const uint32_t own = (uint32_t)a.label[v];
+            const NodeKey nk = node_key(a, v);
             cv = a.vwgt ? a.vwgt[v] : 1;
-            for (int j = gl; j < HS; j += G) consider(a, keys[j], vals[j], own, cv, fav, adm, rown);
+            for (int j = gl; j < HS; j += G) consider(a, nk, keys[j], vals[j], own, cv, fav, adm, rown);
         }
         if (G <= 64) {
             fav = group_best<G>(fav);
@@ -420,12 +453,13 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
         __syncthreads();
         const uint32_t own = (uint32_t)a.label[v];
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
+        const NodeKey nk = node_key(a, v);
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0;
         for (int64_t j = tid; j < hs; j += kBlock) {
             uint32_t key = __hip_atomic_load(&keys[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             uint32_t val = __hip_atomic_load(&vals[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            consider(a, key, val, own, cv, fav, adm, rown);
+            consider(a, nk, key, val, own, cv, fav, adm, rown);
         }
         fav = group_best<64>(fav);
         adm = group_best<64>(adm);
@@ -496,13 +530,27 @@ __device__ inline int64_t reserve_slot(int64_t* cursor, bool want)
     return want ? base + __popcll(b & ((1ull << lane) - 1ull)) : -1;
 }
 
+// Cap of target K for a proposal of node v (v and K belong to one job).
+struct CapArgs {
+    const int64_t* vec;   // [nlab] or NULL
+    int64_t scalar;
+    const int32_t* gid;   // batches: per-job scalar caps
+    const int64_t* gcap;
+};
+
+__device__ inline int64_t cap_for(const CapArgs& c, uint32_t K, uint32_t v)
+{
+    if (c.vec) return c.vec[K];
+    if (c.gcap) return c.gcap[c.gid[v]];
+    return c.scalar;
+}
+
 // acc[v]: 0 none, 1 admitted, 2 contended (decided by a contended path)
 __global__ __launch_bounds__(kBlock) void k_admit_fast(int64_t* ctl, const int32_t* __restrict__ list,
                                                        const int32_t* __restrict__ segtab, int s,
                                                        const int32_t* __restrict__ prop,
                                                        const uint32_t* __restrict__ demand,
-                                                       const int64_t* __restrict__ wt,
-                                                       const int64_t* __restrict__ cap_vec, int64_t cap_scalar,
+                                                       const int64_t* __restrict__ wt, CapArgs caps,
                                                        uint8_t* __restrict__ acc, uint32_t* __restrict__ ckeys,
                                                        uint32_t* __restrict__ cvals)
 {
@@ -516,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_admit_fast(int64_t* ctl, const int32
             v = list[class_pos(cs, i)];
             K = prop[v];
             if (K >= 0) {
-                const int64_t cap = cap_vec ? cap_vec[K] : cap_scalar;
+                const int64_t cap = cap_for(caps, (uint32_t)K, (uint32_t)v);
                 if (wt[K] + (int64_t)demand[K] <= cap) {
                     acc[v] = 1;
                 } else {
@@ -538,9 +586,8 @@ __global__ __launch_bounds__(kBlock) void k_admit_fast(int64_t* ctl, const int32
 __global__ __launch_bounds__(kSmallThreads) void k_contended_small(int64_t* ctl, int s, const uint32_t* __restrict__ ckeys,
                                                                    const uint32_t* __restrict__ cvals,
                                                                    const int32_t* __restrict__ vwgt,
-                                                                   const int64_t* __restrict__ wt,
-                                                                   const int64_t* __restrict__ cap_vec,
-                                                                   int64_t cap_scalar, int64_t* __restrict__ base,
+                                                                   const int64_t* __restrict__ wt, CapArgs caps,
+                                                                   int64_t* __restrict__ base,
                                                                    uint8_t* __restrict__ acc)
 {
     __shared__ uint64_t key[kSmallCap];
@@ -615,7 +662,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_contended_small(int64_t* ctl,
     for (int i = tid; i < C; i += kSmallThreads) {
         const uint32_t K = (uint32_t)(key[i] >> 32);
         const uint32_t v = (uint32_t)key[i];
-        const int64_t cap = cap_vec ? cap_vec[K] : cap_scalar;
+        const int64_t cap = cap_for(caps, K, v);
         acc[v] = wt[K] + (pre[i] - base[K]) <= cap ? 1 : 0;
     }
     __syncthreads();
@@ -660,13 +707,12 @@ __global__ void k_heads(const uint32_t* __restrict__ keys, const int64_t* __rest
 
 __global__ void k_decide(const uint32_t* __restrict__ keys, const uint32_t* __restrict__ vals,
                          const int64_t* __restrict__ pre, const int64_t* __restrict__ base, int64_t np,
-                         const int64_t* __restrict__ wt, const int64_t* __restrict__ cap_vec, int64_t cap_scalar,
-                         uint8_t* __restrict__ acc)
+                         const int64_t* __restrict__ wt, CapArgs caps, uint8_t* __restrict__ acc)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= np) return;
     uint32_t K = keys[i];
-    int64_t cap = cap_vec ? cap_vec[K] : cap_scalar;
+    int64_t cap = cap_for(caps, K, vals[i]);
     acc[vals[i]] = wt[K] + (pre[i] - base[K]) <= cap ? 1 : 0;
 }
 
@@ -766,7 +812,8 @@ __global__ void k_ctl_set(int64_t* ctl, int idx, int64_t v)
 
 // ================================================================ host side
 
-void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched)
+void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched, const JobTabs& jt,
+                       const uint8_t* gpart)
 {
     const int32_t n = g.n;
     sched.order = DBuf<int32_t>(c, (size_t)n);
@@ -780,18 +827,18 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
         return;
     }
     DBuf<uint32_t> key(c, n), val(c, n), key2(c, n), val2(c, n);
-    DBuf<int32_t> cnt(c, kSegs);
-    c.zero(cnt.p, kSegs * sizeof(int32_t));
+    DBuf<int32_t> cnt(c, kSegs + 1);
+    c.zero(cnt.p, (kSegs + 1) * sizeof(int32_t));
     const uint32_t hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
     {
         ProfScope ps(c, KMP_PROF_SCHEDULE);
-        hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, key.p,
-                           val.p, cnt.p);
+        hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, jt, gpart,
+                           (uint32_t)level, key.p, val.p, cnt.p);
         KMP_LAUNCH_CHECK();
     }
-    radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, bits_for(kSegs - 1));
+    radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, bits_for(kSegs));
     KMP_HIP(hipMemcpyAsync(sched.order.p, val.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
-    int32_t h[kSegs];
+    int32_t h[kSegs + 1];
     c.read(h, cnt.p, sizeof(h));
     int32_t pos = 0;
     for (int j = 0; j < kSegs; ++j) {
@@ -799,7 +846,7 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
         sched.cnt[j] = h[j];
         pos += h[j];
     }
-    sched.off[kSegs] = n;
+    sched.off[kSegs] = pos;  // nodes of jobs that do not take part follow
     int32_t tab[2 * kSegs];
     for (int j = 0; j < kSegs; ++j) {
         tab[j] = sched.off[j];
@@ -807,7 +854,7 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
     }
     c.write(sched.segtab.p, tab, sizeof(tab));
     sched.hub_start = sched.off[(kTiers - 1) * kSub];
-    const int32_t nh = n - sched.hub_start;
+    const int32_t nh = sched.off[kSegs] - sched.hub_start;
     if (nh > 0) {
         DBuf<int64_t> slots(c, (size_t)nh), incl(c, (size_t)nh);
         const int32_t* hubs = sched.order.p + sched.hub_start;
@@ -871,6 +918,11 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
     a.hpre = hpre;
     a.fav = st.fav;
     a.counters = c.spread(SP_RATED);
+    a.gid = st.jt.gid;
+    a.ghash = st.jt.ghash;
+    a.loff = st.loff;
+    a.gcap = st.gcap;
+    a.tag = st.tag;
     if (b) {
         a.prop = b->prop.p;
         a.demand = b->demand.p;
@@ -952,6 +1004,11 @@ int32_t class_ub(const int32_t* ubs, int32_t s)
     return t;
 }
 
+CapArgs cap_args(const LPState& st)
+{
+    return CapArgs{st.cap_vec, st.cap_scalar, st.jt.gid, st.gcap};
+}
+
 void launch_admit(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, const int32_t* segtab, LPState& st,
                   LPBuffers& b)
 {
@@ -959,8 +1016,7 @@ void launch_admit(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, co
     if (ub == 0) return;
     ProfScope ps(c, KMP_PROF_ADMIT);
     hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list,
-                       segtab, s, b.prop.p, b.demand.p, st.wt, st.cap_vec, st.cap_scalar, b.acc.p, b.ckeys.p,
-                       b.cvals.p);
+                       segtab, s, b.prop.p, b.demand.p, st.wt, cap_args(st), b.acc.p, b.ckeys.p, b.cvals.p);
     KMP_LAUNCH_CHECK();
 }
 
@@ -968,7 +1024,7 @@ void launch_small(Ctx& c, int32_t s, const DGraph& g, LPState& st, LPBuffers& b)
 {
     ProfScope ps(c, KMP_PROF_CONTENDED);
     hipLaunchKernelGGL(k_contended_small, dim3(1), dim3(kSmallThreads), 0, c.stream, b.ctl.p, s, b.ckeys.p,
-                       b.cvals.p, g.vwgt, st.wt, st.cap_vec, st.cap_scalar, b.base.p, b.acc.p);
+                       b.cvals.p, g.vwgt, st.wt, cap_args(st), b.base.p, b.acc.p);
     KMP_LAUNCH_CHECK();
 }
 
@@ -1012,7 +1068,7 @@ void resolve_exact(Ctx& c, const DGraph& g, LPState& st, LPBuffers& b)
                        b.base.p);
     KMP_LAUNCH_CHECK();
     hipLaunchKernelGGL(k_decide, dim3(grid_for(ncont)), dim3(kBlock), 0, c.stream, keys.p, vals.p, pre.p, b.base.p,
-                       ncont, st.wt, st.cap_vec, st.cap_scalar, b.acc.p);
+                       ncont, st.wt, cap_args(st), b.acc.p);
     KMP_LAUNCH_CHECK();
     ctl_set(c, b, CTL_CONT, 0);
 }
@@ -1034,11 +1090,13 @@ void subround_exact(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t s,
 
 void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int32_t round,
                       const LPSchedule& sched, const int32_t* part, const int64_t* wt, const int64_t* cap,
-                      const uint8_t* over, int32_t* bal_t, int64_t* bal_d)
+                      const uint8_t* over, int32_t* bal_t, int64_t* bal_d, const JobTabs& jt, const int32_t* boff)
 {
     if (g.n == 0) return;
-    LPState st{const_cast<int32_t*>(part), const_cast<int64_t*>(wt), 0, cap, 0, nullptr, TAG_BAL};
+    LPState st{const_cast<int32_t*>(part), const_cast<int64_t*>(wt), 0, cap, 0, nullptr, TAG_BAL, jt, boff};
     RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {TAG_BAL, (uint32_t)level, (uint32_t)round}), nullptr);
+    a.level = (uint32_t)level;
+    a.round = (uint32_t)round;
     a.counters = c.spread(SP_BYTES + KMP_PROF_OTHER);  // balancing reports no rated edges
     a.bytes_ctr = c.spread(SP_BYTES + KMP_PROF_OTHER);  // nor LP bytes
     a.over = over;
@@ -1105,7 +1163,9 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         const uint8_t stamp = (uint8_t)(r + 1);
         const int32_t* list = r == 0 ? sched.order.p : alist[cur];
         const int32_t* segtab = r == 0 ? sched.segtab.p : segtab_r[cur];
-        const RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
+        RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
+        a.level = (uint32_t)level;
+        a.round = (uint32_t)r;
         // speculative sub-rounds: no host synchronisation in between
         for (int32_t s = 0; s < kSub; ++s) {
             launch_rate(c, a, sched, s, list, segtab, ub);
@@ -1146,6 +1206,8 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
     LPBuffers b;
     lp_buffers(c, g, sched, st.nlab, b);
     RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)round}), &b);
+    a.level = (uint32_t)level;
+    a.round = (uint32_t)round;
     a.active = active;
     subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, sched.cnt, st, b, a, true, moved, 1);
     int64_t slots[kSpreadSlots];

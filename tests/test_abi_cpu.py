@@ -47,3 +47,35 @@ def test_argument_errors_before_any_device_work():
     assert lib.kmp_partition(None, None, None, None, 10, 0, 2, 0.03, 1, None, None) == kmp.KMP_EINVAL  # NULL xadj
     # empty graph: OK without device work
     assert lib.kmp_partition(None, None, None, None, 0, 0, 4, 0.03, 1, None, None) == kmp.KMP_OK
+
+
+def test_batch_argument_errors_before_any_device_work():
+    lib = kmp.library()
+    assert lib.kmp_partition_batch(None, -1, None, None, None, None) == kmp.KMP_EINVAL
+    assert lib.kmp_partition_batch(None, 3, None, None, None, None) == kmp.KMP_EINVAL
+    assert lib.kmp_partition_batch(None, 0, None, None, None, None) == kmp.KMP_OK
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """ctypes mirrors of the public structs have the sizes and offsets gcc gives the header's."""
+    import subprocess
+    fields = {"kmp_graph_desc": (kmp.KmpGraphDesc, ["n", "m", "seed", "out_part"]),
+              "kmp_job_result": (kmp.KmpJobResult, ["cut", "lk", "level_n"]),
+              "kmp_options": (kmp.KmpOptions, ["profile_classes"]),
+              "kmp_stats": (kmp.KmpStats, ["level_n", "level_m", "ms_total", "prof_bytes"])}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kmp.h"', "int main(void) {"]
+    for st, (_, fs) in fields.items():
+        lines.append(f'printf("%zu\\n", sizeof({st}));')
+        for f in fs:
+            lines.append(f'printf("%zu\\n", offsetof({st}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    exp = []
+    for st, (cls, fs) in fields.items():
+        exp.append(ctypes.sizeof(cls))
+        exp += [getattr(cls, f).offset for f in fs]
+    assert got == exp

@@ -346,3 +346,94 @@ def test_partition_golden(kmp, case):
     assert _sha(bw) == exp["block_weights_sha256"]
     assert _sha(np.asarray(part, np.int32)) == exp["part_sha256"]
     say(f"  cut={stats['cut']} ms={stats['ms_total']:.1f}")
+
+
+# ------------------------------------------------------------------ batches
+def _batch_jobs(specs):
+    jobs = []
+    for name, g, k, eps, seed in specs:
+        xadj, adjncy, vwgt, adjwgt = dev(g)
+        out = torch.full((max(g.n, 1),), -7, dtype=torch.int32, device="cuda")[:g.n]
+        jobs.append(dict(name=name, g=g, xadj=xadj, adjncy=adjncy, vwgt=vwgt, adjwgt=adjwgt, out=out, k=k,
+                         epsilon=eps, seed=seed))
+    return jobs
+
+
+def _check_batch_against_oracle(kmp, jobs, skip=()):
+    rc, res, _ = kmp.kmp_partition_batch(jobs)
+    assert rc == kmp.KMP_OK
+    for j, r in zip(jobs, res):
+        if j["name"] in skip:
+            continue
+        ref = oracle.partition(j["g"], j["k"], j["epsilon"], j["seed"])
+        say(f"  [batch job] {j['name']} n={j['g'].n} k={j['k']}: status {r['status']} cut {r['cut']}")
+        assert r["status"] == ref.status, j["name"]
+        assert np.array_equal(j["out"].cpu().numpy(), ref.part), j["name"]
+        assert r["cut"] == ref.stats["cut"], j["name"]
+        assert r["max_block_weight"] == ref.stats["max_block_weight"], j["name"]
+        assert r["levels"] == ref.stats["levels"], j["name"]
+        assert r["level_n"] == ref.stats["level_n"], j["name"]
+    return res
+
+
+def test_batch_mixed_jobs(kmp):
+    """Jobs of different shapes, k, eps and seeds in one pass: each equals the oracle run alone."""
+    specs = [
+        ("grid64x40", gen.grid(64, 40), 8, 0.03, 3),
+        ("rgg5000", gen.rgg(5000, 8.0, 7), 16, 0.03, 0),
+        ("rand_w", gen.random_graph(3000, 5.0, 5, max_vw=4, max_ew=6), 5, 0.05, 9),
+        ("rand_iso", gen.random_graph(4000, 3.0, 8, isolated_frac=0.3), 16, 0.03, 2),
+        ("tiny", gen.grid(2, 3), 8, 0.03, 1),
+        ("k1", gen.grid(16, 16), 1, 0.03, 4),
+        ("grid128", gen.grid(128, 128), 8, 0.03, 1),
+        ("rgg20000", gen.rgg(20000, 8.0, 2), 64, 0.03, 1),
+        ("hubs", with_hubs(gen.rgg(20000, 8.0, 5), [4097, 6000, 15000], seed=2), 8, 0.03, 5),
+        ("cliques", csr_from_dense(two_cliques(100)), 2, 0.03, 1),
+        ("rgg700_eps0", gen.rgg(700, 8.0, 3), 4, 0.0, 6),
+    ]
+    say(f"[batch] {len(specs)} mixed jobs")
+    _check_batch_against_oracle(kmp, _batch_jobs(specs))
+
+
+def test_batch_errors_and_empty_jobs(kmp):
+    """Bad jobs get their own status and do not disturb the others."""
+    good = gen.grid(20, 20)
+    specs = [("good0", good, 4, 0.03, 1), ("empty", gen.Graph(np.zeros(1, np.int32), np.zeros(0, np.int32)), 4,
+                                                                0.03, 1),
+             ("good1", gen.rgg(3000, 8.0, 1), 8, 0.03, 2)]
+    jobs = _batch_jobs(specs)
+    bad = _batch_jobs([("bad_m", good, 4, 0.03, 1)])[0]
+    bad["adjncy"] = torch.cat([bad["adjncy"], bad["adjncy"][:1]])  # m != xadj[n]
+    bad_k = _batch_jobs([("bad_k", good, 0, 0.03, 1)])[0]
+    heavy = gen.grid(8, 8)
+    over = _batch_jobs([("overflow", gen.Graph(heavy.xadj, heavy.adjncy, np.full(64, 2**28, np.int32)), 4, 0.03,
+                         1)])[0]
+    jobs = [jobs[0], bad, jobs[1], bad_k, over, jobs[2]]
+    rc, res, _ = kmp.kmp_partition_batch(jobs)
+    assert rc == kmp.KMP_OK
+    assert [r["status"] for r in res] == [0, kmp.KMP_EINVAL, 0, kmp.KMP_EINVAL, kmp.KMP_EOVERFLOW, 0]
+    for j in (jobs[0], jobs[5]):
+        ref = oracle.partition(j["g"], j["k"], j["epsilon"], j["seed"])
+        assert np.array_equal(j["out"].cpu().numpy(), ref.part)
+
+
+def test_batch_workload_sample(kmp):
+    """32 graphs of the batched recipe (grids and RGGs, n log-uniform in [2^10, 2^13]), k = 16."""
+    sizes = gen.batch_sizes(32, lo=10, span=3)
+    specs = [(f"b{i}", gen.batch_graph(i, n), 16, 0.03, i) for i, n in enumerate(sizes)]
+    say(f"[batch] recipe sample, sum n = {sum(sizes)}")
+    _check_batch_against_oracle(kmp, _batch_jobs(specs))
+
+
+def test_batch_equals_single_calls(kmp):
+    """The same job alone (kmp_partition_ex) and inside a batch gives the same partition."""
+    specs = [(f"r{i}", gen.rgg(2000 + 700 * i, 8.0, 40 + i), 8 + i, 0.03, 100 + i) for i in range(6)]
+    jobs = _batch_jobs(specs)
+    rc, res, _ = kmp.kmp_partition_batch(jobs)
+    assert rc == 0
+    for j, r in zip(jobs, res):
+        rc1, out1, st1 = kmp.kmp_partition_ex(j["xadj"], j["adjncy"], j["vwgt"], j["adjwgt"], j["k"], j["epsilon"],
+                                              j["seed"])
+        assert rc1 == r["status"]
+        assert torch.equal(out1, j["out"])
+        assert st1["cut"] == r["cut"]
