@@ -42,7 +42,56 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-runs", type=int, default=3)
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-reps", type=int, default=3)
     return ap.parse_args()
+
+
+def batched_comparison(kmp, gen, torch, count, reps):
+    """Batched workload: `count` graphs (even i: grid, odd i: RGG of average degree 8), n log-uniform in
+    [2^10, 2^16], k = 16, eps = 0.03, seed i; one kmp_partition_batch call against `count` serial
+    kmp_partition calls on the same stream, outputs compared element by element."""
+    sizes = gen.batch_sizes(count)
+    jobs, outs_serial = [], []
+    for i, n in enumerate(sizes):
+        g = gen.batch_graph(i, n)
+        xadj, adjncy, vwgt, adjwgt = kmp.to_device(g, "cuda:0")
+        jobs.append(dict(xadj=xadj, adjncy=adjncy, vwgt=vwgt, adjwgt=adjwgt, k=16, epsilon=0.03, seed=i,
+                         out=torch.empty(g.n, dtype=torch.int32, device="cuda:0")))
+        outs_serial.append(torch.empty(g.n, dtype=torch.int32, device="cuda:0"))
+    sum_n = sum(sizes)
+    sum_m = sum(int(j["adjncy"].numel()) for j in jobs)
+    torch.cuda.synchronize()
+
+    def serial():
+        cuts = []
+        for j, o in zip(jobs, outs_serial):
+            rc, _, st = kmp.kmp_partition_ex(j["xadj"], j["adjncy"], j["vwgt"], j["adjwgt"], j["k"], j["epsilon"],
+                                             j["seed"], out=o)
+            assert rc == 0
+            cuts.append(st["cut"])
+        return cuts
+
+    rc, res, _ = kmp.kmp_partition_batch(jobs)  # warmup
+    assert rc == 0
+    serial()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        rc, res, _ = kmp.kmp_partition_batch(jobs)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t) / reps
+    t = time.perf_counter()
+    cuts = serial()
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t
+    identical = all(torch.equal(j["out"], o) for j, o in zip(jobs, outs_serial)) and \
+        [r["cut"] for r in res] == cuts and all(r["status"] == 0 for r in res)
+    return {"graphs": count, "sum_n": sum_n, "sum_m_directed": sum_m, "k": 16,
+            "batch_ms": round(t_batch * 1e3, 2), "serial_ms": round(t_serial * 1e3, 2),
+            "graphs_per_s": round(count / t_batch, 1), "serial_graphs_per_s": round(count / t_serial, 1),
+            "speedup_vs_serial": round(t_serial / t_batch, 2), "identical_to_serial": bool(identical)}
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_rgg20.md")
@@ -128,6 +177,10 @@ def main():
                 "algorithmic_bytes_per_launch": round(bytes_per_launch),
                 "class_ms_per_step": {c: round(st_all["prof"][c]["ms"], 3) for c in classes
                                       if st_all["prof"][c]["launches"]}}
+    batched = None
+    if not args.no_batched:
+        batched = batched_comparison(kmp, gen, torch, args.batch_count, args.batch_reps)
+        print(f"# batched: {batched}", file=sys.stderr, flush=True)
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -152,7 +205,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "e2e_edges_per_s": round(g.m / (ms_step / 1e3)),
         "lp_plus_contraction_edges_per_step": edges, "cut": st0["cut"], "levels": st0["levels"],
-        "parity_with_oracle": parity,
+        "parity_with_oracle": parity, "batched": batched,
     }
     print(json.dumps(line), flush=True)
 
