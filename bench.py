@@ -45,7 +45,87 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serving-jobs", type=int, default=400)
+    ap.add_argument("--serving-loads", type=str, default="0.7",
+                    help="offered loads as fractions of the measured capacity, comma separated")
+    ap.add_argument("--serving-workers", type=int, default=2)
+    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     return ap.parse_args()
+
+
+def serving_run(kmp, gen, torch, count, loads, workers, budget_gib):
+    """Serving workload: `count` jobs (type uniform over grid / RGG / RMAT with edge factor 8, n log-uniform
+    in [2^12, 2^21], k uniform over {2, 8, 64, 512, 4096}, eps 0.03, seed j), each on a graph of a shared
+    pool of generated graphs (the job's type at the nearest pool size), CSRs resident in HBM before the run.
+    Capacity: every job submitted at once.  Then Poisson arrivals at each offered load (fraction of the
+    capacity).  Latency = completion - submission, from the server's own clock."""
+    import numpy as np
+    specs = gen.serving_jobs(count)
+    keys = sorted(set(gen.serving_pool_key(t, n) for t, n, _, _ in specs))
+    t_gen = time.perf_counter()
+    pool = {}
+    for key in keys:
+        g = gen.pool_graph(key)
+        pool[key] = (g, kmp.to_device(g, "cuda:0"))
+    print(f"# serving pool: {len(keys)} graphs in {time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    jobs = []
+    for typ, n, k, seed in specs:
+        g, (xadj, adjncy, vwgt, adjwgt) = pool[gen.serving_pool_key(typ, n)]
+        jobs.append(dict(xadj=xadj, adjncy=adjncy, vwgt=vwgt, adjwgt=adjwgt, k=k, epsilon=0.03, seed=seed,
+                         out=torch.empty(g.n, dtype=torch.int32, device="cuda:0")))
+    torch.cuda.synchronize()
+    budget = int(budget_gib * (1 << 30))
+
+    def run(rate):
+        rng = np.random.default_rng(12345)
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count)) if rate else None
+        with kmp.Server(budget, workers) as srv:
+            t0 = time.perf_counter()
+            ids = []
+            for j, job in enumerate(jobs):
+                if arrivals is not None:
+                    dt = t0 + arrivals[j] - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                ids.append(srv.submit(job))
+            res = []
+            for q, i in enumerate(ids):
+                res.append(srv.wait(i))
+                if (q + 1) % max(1, count // 8) == 0:
+                    print(f"#   {q + 1}/{count} done after {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                          flush=True)
+            t_end = time.perf_counter()
+            st = srv.stats()
+        lat = np.array([r["latency_ms"] for r in res])
+        return {"graphs_per_s": round(count / (t_end - t0), 1), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2), "batches": st["batches"],
+                "max_batch_jobs": st["max_batch_jobs"], "all_ok": all(r["status"] in (0, 1) for r in res),
+                "seconds": round(t_end - t0, 2)}, res
+
+    print("# serving: warmup run", file=sys.stderr, flush=True)
+    run(None)  # warmup: pools, events, code objects
+    print("# serving: capacity run (every job submitted at once)", file=sys.stderr, flush=True)
+    cap, _ = run(None)
+    capacity = cap["graphs_per_s"]
+    print(f"# serving capacity: {cap}", file=sys.stderr, flush=True)
+    runs = []
+    for frac in loads:
+        r, res = run(frac * capacity)
+        r = dict(offered_load=frac, arrival_rate_per_s=round(frac * capacity, 1), **r)
+        runs.append(r)
+        print(f"# serving load {frac}: {r}", file=sys.stderr, flush=True)
+    # each result is the same alone and in the mix
+    sample = list(range(0, count, max(1, count // 24)))
+    same = True
+    for j in sample:
+        job = jobs[j]
+        rc, alone, st = kmp.kmp_partition_ex(job["xadj"], job["adjncy"], job["vwgt"], job["adjwgt"], job["k"],
+                                             job["epsilon"], job["seed"])
+        same &= bool(torch.equal(alone, job["out"])) and rc in (0, 1)
+    return {"jobs": count, "pool_graphs": len(keys), "workers": workers, "hbm_budget_gib": budget_gib,
+            "saturated": cap, "capacity_graphs_per_s": capacity, "poisson": runs,
+            "alone_equals_mix_sample": len(sample), "alone_equals_mix": bool(same)}
 
 
 def batched_comparison(kmp, gen, torch, count, reps):
@@ -181,6 +261,11 @@ def main():
     if not args.no_batched:
         batched = batched_comparison(kmp, gen, torch, args.batch_count, args.batch_reps)
         print(f"# batched: {batched}", file=sys.stderr, flush=True)
+    serving = None
+    if not args.no_serving:
+        loads = [float(x) for x in args.serving_loads.split(",") if x]
+        serving = serving_run(kmp, gen, torch, args.serving_jobs, loads, args.serving_workers,
+                              args.serving_budget_gib)
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -205,7 +290,7 @@ def main():
         "roofline": roofline, "cpu_baseline": cpu,
         "e2e_edges_per_s": round(g.m / (ms_step / 1e3)),
         "lp_plus_contraction_edges_per_step": edges, "cut": st0["cut"], "levels": st0["levels"],
-        "parity_with_oracle": parity, "batched": batched,
+        "parity_with_oracle": parity, "batched": batched, "serving": serving,
     }
     print(json.dumps(line), flush=True)
 

@@ -37,6 +37,7 @@
 #ifndef KMP_H
 #define KMP_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -171,6 +172,48 @@ typedef struct kmp_job_result {
  */
 int kmp_partition_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_result* results, void* stream,
                         const kmp_options* opt, kmp_stats* stats);
+
+/*
+ * Serving loop with continuous batching (jobs arriving over time).
+ *
+ * kmp_server_create starts `workers` (1..16) host threads on the current
+ * device, each with its own non-blocking HIP stream.  Submitted jobs wait in
+ * arrival order; a free worker takes the longest run of waiting jobs from the
+ * front whose estimated device footprint (160 B per node + 96 B per directed
+ * entry + 1 MiB) fits in what is left of hbm_budget_bytes, and runs them as
+ * one batch (as kmp_partition_batch).  A job larger than the whole budget runs
+ * alone once nothing else is running.  Jobs that arrive while batches run are
+ * admitted by the next free worker, so their work overlaps on the device.
+ * Each job's output equals kmp_partition's for it alone.  Returns NULL on
+ * invalid arguments or when no stream / thread can be created.
+ *
+ * kmp_server_submit copies the descriptor and returns at once with a job id;
+ * the job's device arrays must stay valid and untouched until its result has
+ * been taken.  kmp_server_poll returns 0 while the job is pending and 1 once
+ * it is done, filling `result` and `latency_ms` (completion minus submission,
+ * host steady clock; both may be NULL) and forgetting the job;
+ * kmp_server_wait blocks until then.  Unknown ids give KMP_EINVAL.
+ * kmp_server_destroy finishes every submitted job, then stops the workers.
+ */
+typedef struct kmp_server kmp_server;
+
+typedef struct kmp_server_stats {
+    int64_t jobs_submitted;
+    int64_t jobs_done;
+    int64_t batches;          /* batches run so far          */
+    int64_t max_batch_jobs;   /* largest batch               */
+    int64_t queued;           /* jobs waiting now            */
+    int64_t hbm_in_use;       /* footprint of running batches */
+    int32_t running_batches;
+    int32_t reserved;
+} kmp_server_stats;
+
+kmp_server* kmp_server_create(size_t hbm_budget_bytes, int32_t workers);
+int kmp_server_submit(kmp_server* server, const kmp_graph_desc* job, uint64_t* job_id);
+int kmp_server_poll(kmp_server* server, uint64_t job_id, kmp_job_result* result, double* latency_ms);
+int kmp_server_wait(kmp_server* server, uint64_t job_id, kmp_job_result* result, double* latency_ms);
+int kmp_server_stats_get(kmp_server* server, kmp_server_stats* stats);
+void kmp_server_destroy(kmp_server* server);
 
 /* Human-readable text for a status code (static storage). */
 const char* kmp_strerror(int code);

@@ -61,12 +61,26 @@ class KmpJobResult(ctypes.Structure):
                 ("level_n", ctypes.c_int32 * (MAX_LEVELS + 1))]
 
 
+class KmpServerStats(ctypes.Structure):
+    _fields_ = [("jobs_submitted", ctypes.c_int64), ("jobs_done", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("max_batch_jobs", ctypes.c_int64), ("queued", ctypes.c_int64), ("hbm_in_use", ctypes.c_int64),
+                ("running_batches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 SIGNATURES = {
     "kmp_partition": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp]),
     "kmp_partition_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp,
                                         ctypes.POINTER(KmpOptions), ctypes.POINTER(KmpStats)]),
     "kmp_partition_batch": (ctypes.c_int, [ctypes.POINTER(KmpGraphDesc), _i32, ctypes.POINTER(KmpJobResult), _vp,
                                            ctypes.POINTER(KmpOptions), ctypes.POINTER(KmpStats)]),
+    "kmp_server_create": (_vp, [ctypes.c_size_t, _i32]),
+    "kmp_server_submit": (ctypes.c_int, [_vp, ctypes.POINTER(KmpGraphDesc), ctypes.POINTER(ctypes.c_uint64)]),
+    "kmp_server_poll": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(KmpJobResult),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "kmp_server_wait": (ctypes.c_int, [_vp, ctypes.c_uint64, ctypes.POINTER(KmpJobResult),
+                                       ctypes.POINTER(ctypes.c_double)]),
+    "kmp_server_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(KmpServerStats)]),
+    "kmp_server_destroy": (None, [_vp]),
     "kmp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kmp_version": (ctypes.c_char_p, []),
     "kmp_lp_cluster": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _i64, _u64, _vp, _vp, _vp, _P64, _vp]),
@@ -185,18 +199,9 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
-    _check_i32(*[j.get(f) for j in jobs for f in ("xadj", "adjncy", "vwgt", "adjwgt", "out")])
     descs = (KmpGraphDesc * max(len(jobs), 1))()
     for i, j in enumerate(jobs):
-        d = descs[i]
-        d.xadj, d.adjncy = _ptr(j["xadj"]), _ptr(j["adjncy"])
-        d.vwgt, d.adjwgt = _ptr(j.get("vwgt")), _ptr(j.get("adjwgt"))
-        d.n = j["xadj"].numel() - 1
-        d.m = j["adjncy"].numel()
-        d.k = int(j["k"])
-        d.epsilon = float(j.get("epsilon", 0.03))
-        d.seed = int(j.get("seed", 1)) & (2**64 - 1)
-        d.out_part = _ptr(j["out"])
+        _fill_desc(descs[i], j)
     res = (KmpJobResult * max(len(jobs), 1))()
     opt = KmpOptions()
     opt.validate = int(validate)
@@ -205,12 +210,82 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
     rc = library().kmp_partition_batch(descs, len(jobs), res, _stream(stream), ctypes.byref(opt), ctypes.byref(st))
-    out = []
-    for i in range(len(jobs)):
-        r = res[i]
-        out.append({"status": r.status, "levels": r.levels, "cut": r.cut, "max_block_weight": r.max_block_weight,
-                    "lk": r.lk, "level_n": list(r.level_n[:r.levels + 1])})
-    return rc, out, _stats_dict(st, profile)
+    return rc, [_result_dict(res[i]) for i in range(len(jobs))], _stats_dict(st, profile)
+
+
+def _fill_desc(d: "KmpGraphDesc", j: Dict):
+    _check_i32(*[j.get(f) for f in ("xadj", "adjncy", "vwgt", "adjwgt", "out")])
+    d.xadj, d.adjncy = _ptr(j["xadj"]), _ptr(j["adjncy"])
+    d.vwgt, d.adjwgt = _ptr(j.get("vwgt")), _ptr(j.get("adjwgt"))
+    d.n = j["xadj"].numel() - 1
+    d.m = j["adjncy"].numel()
+    d.k = int(j["k"])
+    d.epsilon = float(j.get("epsilon", 0.03))
+    d.seed = int(j.get("seed", 1)) & (2**64 - 1)
+    d.out_part = _ptr(j["out"])
+
+
+def _result_dict(r: "KmpJobResult") -> Dict:
+    return {"status": r.status, "levels": r.levels, "cut": r.cut, "max_block_weight": r.max_block_weight,
+            "lk": r.lk, "level_n": list(r.level_n[:max(r.levels, 0) + 1])}
+
+
+class Server:
+    """kmp_server_*: jobs submitted over time, partitioned in continuous batches by `workers` threads
+    (one HIP stream each) under an HBM footprint budget.  A job is a dict as for kmp_partition_batch;
+    its tensors are kept referenced here until its result is taken."""
+
+    def __init__(self, hbm_budget_bytes: int, workers: int = 2):
+        self._h = library().kmp_server_create(int(hbm_budget_bytes), int(workers))
+        if not self._h:
+            raise RuntimeError("kmp_server_create failed")
+        self._live = {}
+
+    def submit(self, job: Dict) -> int:
+        d = KmpGraphDesc()
+        _fill_desc(d, job)
+        jid = ctypes.c_uint64(0)
+        rc = library().kmp_server_submit(self._h, ctypes.byref(d), ctypes.byref(jid))
+        if rc != KMP_OK:
+            raise RuntimeError(f"kmp_server_submit: {kmp_strerror(rc)}")
+        self._live[jid.value] = job
+        return jid.value
+
+    def _take(self, fn, jid: int):
+        r = KmpJobResult()
+        lat = ctypes.c_double(0.0)
+        rc = fn(self._h, jid, ctypes.byref(r), ctypes.byref(lat))
+        if rc < 0:
+            raise KeyError(jid)
+        if rc == 0:
+            return None
+        self._live.pop(jid, None)
+        out = _result_dict(r)
+        out["latency_ms"] = lat.value
+        return out
+
+    def poll(self, jid: int) -> Optional[Dict]:
+        return self._take(library().kmp_server_poll, jid)
+
+    def wait(self, jid: int) -> Dict:
+        return self._take(library().kmp_server_wait, jid)
+
+    def stats(self) -> Dict:
+        st = KmpServerStats()
+        library().kmp_server_stats_get(self._h, ctypes.byref(st))
+        return {f[0]: getattr(st, f[0]) for f in KmpServerStats._fields_ if f[0] != "reserved"}
+
+    def close(self):
+        if self._h:
+            library().kmp_server_destroy(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, level: int, U: int, seed: int, stream=None):

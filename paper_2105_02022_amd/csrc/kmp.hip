@@ -11,6 +11,7 @@
 #include <chrono>
 #include <cmath>
 #include <memory>
+#include <mutex>
 
 #include "kmp_dev.h"
 
@@ -23,17 +24,17 @@ double ms_since(clk::time_point t) { return std::chrono::duration<double, std::m
 
 void init_pool_once()
 {
-    static bool done = false;
-    if (done) return;
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-        hipMemPool_t pool;
-        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-            uint64_t thr = UINT64_MAX;
-            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipMemPool_t pool;
+            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+                uint64_t thr = UINT64_MAX;
+                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+            }
         }
-    }
-    done = true;
+    });
 }
 
 // ---------------------------------------------------------------- validation
@@ -935,6 +936,14 @@ int64_t guarded(F&& f)
 
 }  // namespace
 
+int run_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_result* results, hipStream_t stream,
+              const kmp_options* opt, kmp_stats* stats)
+{
+    return (int)guarded([&]() -> int64_t {
+        return partition_batch_impl(graphs, count, results, stream, opt, stats);
+    });
+}
+
 }  // namespace kmp
 
 using namespace kmp;
@@ -967,9 +976,7 @@ int kmp_partition_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_res
     if (stats) memset(stats, 0, sizeof(*stats));
     if (count < 0 || (count > 0 && !graphs)) return KMP_EINVAL;
     if (count == 0) return KMP_OK;
-    return (int)guarded([&]() -> int64_t {
-        return partition_batch_impl(graphs, count, results, (hipStream_t)stream, opt, stats);
-    });
+    return run_batch(graphs, count, results, (hipStream_t)stream, opt, stats);
 }
 
 const char* kmp_strerror(int code)

@@ -123,7 +123,11 @@ __device__ inline uint32_t xcd_block()
     return x * q + (x < r ? x : r) + k;
 }
 
-inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 1u << 20)
+// Blocks for `items` work items at `per_block` items per block.  The default
+// cap only keeps the grid inside HIP's limits: kernels written as one item per
+// thread (no grid-stride loop) rely on covering every item, and batches reach
+// 2^31 entries.  Pass a small cap only to kernels with grid-stride loops.
+inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 0x7FFFFFFFu)
 {
     int64_t g = (items + per_block - 1) / per_block;
     if (g < 1) g = 1;
@@ -455,7 +459,10 @@ int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64
                 const LPSchedule& sched, int32_t* part, int64_t* wt, const BlockTab& bt, const int64_t* cap,
                 const JobTabs& jt = {}, const int32_t* boff = nullptr);
 
-// ---------------------------------------------------------------- validation (kmp.hip)
+// ---------------------------------------------------------------- validation, batches (kmp.hip)
 int validate_graph(Ctx& c, const DGraph& g);
+// kmp_partition_batch on `stream` with errors mapped to status codes.
+int run_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_result* results, hipStream_t stream,
+              const kmp_options* opt, kmp_stats* stats);
 
 }  // namespace kmp

@@ -56,8 +56,8 @@ __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict
     __shared__ int32_t h[kSegs + 1];
     if (threadIdx.x <= kSegs) h[threadIdx.x] = 0;
     __syncthreads();
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v < n) {
+    // grid-stride over a capped grid: each block adds its kSegs + 1 counts once
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
         uint32_t hs = hsub, vl = (uint32_t)v;
         bool takes_part = true;
         if (jt.gid) {
@@ -757,7 +757,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
 }
 
 // mark the neighbours of the nodes moved in this round active for the next one;
-// blockIdx.y selects the segment of the round's lists
+// blockIdx.y selects the segment of the round's lists.  The segment's degree
+// tier picks the width that walks a node's neighbours: one lane (degree <= 64),
+// one wavefront (<= 4096) or the whole workgroup (hubs).
 __global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ segtab,
                                                         const uint8_t* __restrict__ mflag, uint8_t stamp,
@@ -766,11 +768,27 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restric
                                                         uint8_t* __restrict__ active)
 {
     const int seg = blockIdx.y;
+    const int tier = seg / kSub;
     const int32_t off = segtab[seg], cnt = segtab[kSegs + seg];
-    for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * blockDim.x) {
+    if (tier <= 1) {
+        for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < cnt;
+             i += (int64_t)gridDim.x * blockDim.x) {
+            const int32_t v = list[off + i];
+            if (mflag[v] != stamp) continue;
+            for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e) active[adjncy[e]] = 1;
+        }
+        return;
+    }
+    // W lanes per node: a wavefront (tiers 2, 3) or the workgroup (hubs); the
+    // loop bounds are uniform across the W lanes of a node
+    const int W = tier == 4 ? kBlock : 64;
+    const int per_block = kBlock / W;
+    const int grp = threadIdx.x / W, gl = threadIdx.x % W;
+    for (int64_t i = (int64_t)xcd_block() * per_block + grp; i < cnt; i += (int64_t)gridDim.x * per_block) {
         const int32_t v = list[off + i];
         if (mflag[v] != stamp) continue;
-        for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e) active[adjncy[e]] = 1;
+        const int32_t e1 = xadj[v + 1];
+        for (int32_t e = xadj[v] + gl; e < e1; e += W) active[adjncy[e]] = 1;
     }
 }
 
@@ -832,7 +850,7 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
     const uint32_t hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
     {
         ProfScope ps(c, KMP_PROF_SCHEDULE);
-        hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, jt, gpart,
+        hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, jt, gpart,
                            (uint32_t)level, key.p, val.p, cnt.p);
         KMP_LAUNCH_CHECK();
     }

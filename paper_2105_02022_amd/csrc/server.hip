@@ -1,0 +1,216 @@
+// Serving loop: partition jobs that arrive over time, with continuous batching.
+//
+// Submitted jobs wait in arrival order.  Each worker thread owns a HIP stream;
+// when a worker is free it takes the longest run of waiting jobs, from the
+// front, whose estimated device footprint fits the free part of the HBM
+// budget (at most kMaxBatchJobs), and partitions them as one batch (the
+// level-by-level union pass of kmp_partition_batch).  Jobs that arrive while
+// other batches run are admitted by the next free worker, so their work
+// overlaps on the device with the batches already running.  Every job's
+// result is the one kmp_partition gives for it alone.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+
+#include "kmp_dev.h"
+
+struct kmp_server {
+    using clk = std::chrono::steady_clock;
+    struct Job {
+        kmp_graph_desc d;
+        size_t foot = 0;
+        int state = 0;  // 0 waiting, 1 running, 2 done
+        kmp_job_result res;
+        clk::time_point t_submit, t_start, t_done;
+    };
+    int device = 0;
+    size_t budget = 0, in_use = 0;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> streams;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, Job> jobs;
+    uint64_t next_id = 1;
+    int running = 0;
+    bool stop = false;
+    kmp_server_stats st = {};
+};
+
+namespace kmp {
+namespace {
+
+constexpr int kMaxBatchJobs = 256;
+
+// Device bytes a job may hold at its peak: the union copy of its CSR, LP and
+// contraction work arrays, and the coarse levels (which can stay close to the
+// input size on skewed graphs, where coarsening is slow).
+size_t footprint(const kmp_graph_desc& d)
+{
+    const double n = (double)(d.n > 0 ? d.n : 0), m = (double)(d.m > 0 ? d.m : 0);
+    return (size_t)(160.0 * n + 96.0 * m) + ((size_t)1 << 20);
+}
+
+void worker_main(kmp_server* s, int w)
+{
+    (void)hipSetDevice(s->device);
+    hipStream_t stream = s->streams[w];
+    std::vector<uint64_t> ids;
+    std::vector<kmp_graph_desc> descs;
+    std::vector<kmp_job_result> res;
+    for (;;) {
+        size_t reserved = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            // the front job fits, or nothing else is running (a job larger than
+            // the whole budget then runs alone)
+            s->cv_work.wait(lk, [&] {
+                if (s->stop && s->queue.empty()) return true;
+                if (s->queue.empty()) return false;
+                const size_t f = s->jobs[s->queue.front()].foot;
+                return s->in_use + f <= s->budget || s->in_use == 0;
+            });
+            if (s->queue.empty()) return;  // stopping and drained
+            ids.clear();
+            while (!s->queue.empty() && (int)ids.size() < kMaxBatchJobs) {
+                kmp_server::Job& jb = s->jobs[s->queue.front()];
+                const bool fits = s->in_use + reserved + jb.foot <= s->budget;
+                if (!fits && !(ids.empty() && s->in_use == 0)) break;
+                reserved += jb.foot;
+                jb.state = 1;
+                jb.t_start = kmp_server::clk::now();
+                ids.push_back(s->queue.front());
+                s->queue.pop_front();
+            }
+            s->in_use += reserved;
+            ++s->running;
+            descs.resize(ids.size());
+            for (size_t i = 0; i < ids.size(); ++i) descs[i] = s->jobs[ids[i]].d;
+        }
+        res.assign(ids.size(), kmp_job_result{});
+        const int rc = run_batch(descs.data(), (int32_t)ids.size(), res.data(), stream, nullptr, nullptr);
+        const auto t_done = kmp_server::clk::now();
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (size_t i = 0; i < ids.size(); ++i) {
+                kmp_server::Job& jb = s->jobs[ids[i]];
+                jb.res = res[i];
+                if (rc < 0) jb.res.status = rc;  // the whole batch failed
+                jb.state = 2;
+                jb.t_done = t_done;
+            }
+            s->in_use -= reserved;
+            --s->running;
+            s->st.batches += 1;
+            s->st.jobs_done += (int64_t)ids.size();
+            if ((int64_t)ids.size() > s->st.max_batch_jobs) s->st.max_batch_jobs = (int64_t)ids.size();
+        }
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
+    }
+}
+
+int take_result(kmp_server* s, uint64_t id, kmp_job_result* result, double* latency_ms, bool block)
+{
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->jobs.find(id) == s->jobs.end()) return KMP_EINVAL;
+    // look the job up again after every wake-up: submissions may rehash the map
+    if (block) s->cv_done.wait(lk, [&] { return s->jobs.find(id)->second.state == 2; });
+    auto it = s->jobs.find(id);
+    if (it->second.state != 2) return 0;
+    if (result) *result = it->second.res;
+    if (latency_ms)
+        *latency_ms = std::chrono::duration<double, std::milli>(it->second.t_done - it->second.t_submit).count();
+    s->jobs.erase(it);
+    return 1;
+}
+
+}  // namespace
+}  // namespace kmp
+
+using namespace kmp;
+
+extern "C" {
+
+kmp_server* kmp_server_create(size_t hbm_budget_bytes, int32_t workers)
+{
+    if (workers < 1 || workers > 16 || hbm_budget_bytes == 0) return nullptr;
+    kmp_server* s = new (std::nothrow) kmp_server();
+    if (!s) return nullptr;
+    bool ok = hipGetDevice(&s->device) == hipSuccess;
+    s->budget = hbm_budget_bytes;
+    for (int w = 0; ok && w < workers; ++w) {
+        hipStream_t st = nullptr;
+        ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
+        if (ok) s->streams.push_back(st);
+    }
+    try {
+        for (int w = 0; ok && w < workers; ++w) s->workers.emplace_back(worker_main, s, w);
+    } catch (...) {
+        ok = false;
+    }
+    if (!ok) {
+        kmp_server_destroy(s);  // joins the workers that did start (nothing is queued)
+        return nullptr;
+    }
+    return s;
+}
+
+int kmp_server_submit(kmp_server* s, const kmp_graph_desc* job, uint64_t* job_id)
+{
+    if (!s || !job || !job_id) return KMP_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) return KMP_EINVAL;
+    const uint64_t id = s->next_id++;
+    kmp_server::Job& jb = s->jobs[id];
+    jb.d = *job;
+    jb.foot = footprint(*job);
+    jb.t_submit = kmp_server::clk::now();
+    s->queue.push_back(id);
+    s->st.jobs_submitted += 1;
+    *job_id = id;
+    s->cv_work.notify_one();
+    return KMP_OK;
+}
+
+int kmp_server_poll(kmp_server* s, uint64_t job_id, kmp_job_result* result, double* latency_ms)
+{
+    if (!s) return KMP_EINVAL;
+    return take_result(s, job_id, result, latency_ms, false);
+}
+
+int kmp_server_wait(kmp_server* s, uint64_t job_id, kmp_job_result* result, double* latency_ms)
+{
+    if (!s) return KMP_EINVAL;
+    return take_result(s, job_id, result, latency_ms, true);
+}
+
+int kmp_server_stats_get(kmp_server* s, kmp_server_stats* out)
+{
+    if (!s || !out) return KMP_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->st;
+    out->queued = (int64_t)s->queue.size();
+    out->running_batches = s->running;
+    out->hbm_in_use = (int64_t)s->in_use;
+    return KMP_OK;
+}
+
+void kmp_server_destroy(kmp_server* s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->workers) t.join();
+    for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+    delete s;
+}
+
+}  // extern "C"

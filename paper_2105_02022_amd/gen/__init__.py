@@ -184,6 +184,42 @@ def batch_graph(i: int, n_i: int) -> Graph:
     return rgg(n_i, 8.0, seed=i)
 
 
+SERVING_KS = (2, 8, 64, 512, 4096)
+
+
+def serving_jobs(count: int = 2000, seed: int = 0x5E2F_1CE5, lo: int = 12, hi: int = 21):
+    """Jobs of the serving workload: job j has type uniform over (grid, rgg, rmat), n log-uniform in
+    [2^lo, 2^hi], k uniform over SERVING_KS, eps 0.03 and seed j (draws from SplitMix64)."""
+    out = []
+    for j in range(count):
+        typ = ("grid", "rgg", "rmat")[sm64(seed, 3 * j) % 3]
+        u = (sm64(seed, 3 * j + 1) >> 11) * (1.0 / (1 << 53))
+        n = int(math.floor(2.0 ** (lo + (hi - lo) * u)))
+        k = SERVING_KS[sm64(seed, 3 * j + 2) % len(SERVING_KS)]
+        out.append((typ, n, k, j))
+    return out
+
+
+def serving_pool_key(typ: str, n: int, buckets: int = 12, lo: int = 12, hi: int = 21):
+    """Graph of the shared pool that serves a job of this type and size: RMAT at scale round(log2 n),
+    grids and RGGs at the nearest of `buckets` log-spaced sizes in [2^lo, 2^hi]."""
+    if typ == "rmat":
+        return ("rmat", min(hi, max(lo, int(round(math.log2(n))))))
+    b = min(buckets - 1, max(0, int((math.log2(n) - lo) / (hi - lo) * buckets)))
+    return (typ, int(math.floor(2.0 ** (lo + (hi - lo) * (b + 0.5) / buckets))))
+
+
+def pool_graph(key) -> Graph:
+    """RMAT: scale s with 8 * 2^s generated edges (edge factor 8); grid: floor(sqrt n) rows; RGG: degree 8."""
+    typ, x = key
+    if typ == "rmat":
+        return rmat(x, 8 << x, seed=x)
+    if typ == "grid":
+        a = max(1, int(math.isqrt(x)))
+        return grid(a, x // a)
+    return rgg(x, 8.0, seed=x)
+
+
 WORKLOADS = {
     "grid128": dict(k=8, eps=0.03, seed=1),
     "rgg20": dict(k=64, eps=0.03, seed=1),

@@ -62,7 +62,8 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {"kmp_graph_desc": (kmp.KmpGraphDesc, ["n", "m", "seed", "out_part"]),
               "kmp_job_result": (kmp.KmpJobResult, ["cut", "lk", "level_n"]),
               "kmp_options": (kmp.KmpOptions, ["profile_classes"]),
-              "kmp_stats": (kmp.KmpStats, ["level_n", "level_m", "ms_total", "prof_bytes"])}
+              "kmp_stats": (kmp.KmpStats, ["level_n", "level_m", "ms_total", "prof_bytes"]),
+              "kmp_server_stats": (kmp.KmpServerStats, ["hbm_in_use", "running_batches"])}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kmp.h"', "int main(void) {"]
     for st, (_, fs) in fields.items():
         lines.append(f'printf("%zu\\n", sizeof({st}));')
@@ -79,3 +80,16 @@ def test_struct_layouts_match_header(tmp_path):
         exp.append(ctypes.sizeof(cls))
         exp += [getattr(cls, f).offset for f in fs]
     assert got == exp
+
+
+def test_server_argument_errors_before_any_device_work():
+    lib = kmp.library()
+    assert not lib.kmp_server_create(1 << 30, 0)
+    assert not lib.kmp_server_create(1 << 30, 17)
+    assert not lib.kmp_server_create(0, 2)
+    jid = ctypes.c_uint64(0)
+    assert lib.kmp_server_submit(None, None, ctypes.byref(jid)) == kmp.KMP_EINVAL
+    assert lib.kmp_server_poll(None, 1, None, None) == kmp.KMP_EINVAL
+    assert lib.kmp_server_wait(None, 1, None, None) == kmp.KMP_EINVAL
+    assert lib.kmp_server_stats_get(None, None) == kmp.KMP_EINVAL
+    lib.kmp_server_destroy(None)

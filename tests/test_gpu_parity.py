@@ -437,3 +437,24 @@ def test_batch_equals_single_calls(kmp):
         assert rc1 == r["status"]
         assert torch.equal(out1, j["out"])
         assert st1["cut"] == r["cut"]
+
+
+def test_batch_beyond_2_28_entries(kmp):
+    """A batch whose union holds more than 2^28 directed entries (more threads than a 2^20-block grid
+    covers): every job equals its single kmp_partition_ex call, which the golden tests pin to the oracle."""
+    rm = gen.rmat(21, 8 << 21, seed=21)
+    rg = gen.rgg(1 << 20, 8.0, seed=1)
+    specs = [(f"rmat21_{i}", rm, (2, 64, 512, 4096)[i % 4], 0.03, 50 + i) for i in range(9)]
+    specs += [("rgg20_a", rg, 64, 0.03, 1), ("rgg20_b", rg, 8, 0.03, 2)]
+    total = sum(g.m for _, g, _, _, _ in specs)
+    assert total > (1 << 28)
+    say(f"[batch] {len(specs)} jobs, sum m = {total}")
+    jobs = _batch_jobs(specs)
+    rc, res, _ = kmp.kmp_partition_batch(jobs)
+    assert rc == kmp.KMP_OK
+    for j, r in zip(jobs, res):
+        rc1, out1, st1 = kmp.kmp_partition_ex(j["xadj"], j["adjncy"], j["vwgt"], j["adjwgt"], j["k"], j["epsilon"],
+                                              j["seed"])
+        assert rc1 == r["status"], j["name"]
+        assert st1["cut"] == r["cut"], j["name"]
+        assert torch.equal(out1, j["out"]), j["name"]
