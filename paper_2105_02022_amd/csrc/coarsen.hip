@@ -203,15 +203,20 @@ struct RowArgs {
     int64_t* bytes_ctr;
 };
 
-// G lanes per coarse row, 2^HB LDS slots per row.
+// G lanes per coarse row, 2^HB LDS slots per row; rows carry at most 2^(HB-1)
+// fine entries.  After aggregation the occupied slots are compacted to the
+// front of the table (through registers) and only the next power of two above
+// their count is sorted (bitonic).
 template <int G, int HB>
 __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32_t* __restrict__ rows, int32_t count)
 {
     constexpr int GPB = kBlock / G;
     constexpr int HS = 1 << HB;
+    constexpr int PER = HS / G;  // slots per lane
     __shared__ uint32_t s_keys[GPB * HS];
     __shared__ uint32_t s_vals[GPB * HS];
-    __shared__ uint32_t s_cnt[4];
+    __shared__ uint32_t s_u[GPB];
+    __shared__ uint32_t s_pmax;
     const int tid = threadIdx.x, grp = tid / G, gl = tid % G;
     uint32_t* keys = s_keys + grp * HS;
     uint32_t* vals = s_vals + grp * HS;
@@ -223,6 +228,8 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
             keys[j] = EMPTY;
             vals[j] = 0;
         }
+        if (tid < GPB) s_u[tid] = 0;
+        if (tid == 0) s_pmax = 2;
         __syncthreads();
         if (row >= 0) {
             for (int32_t mi = a.mstart[row]; mi < a.mstart[row + 1]; ++mi) {
@@ -246,40 +253,55 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
             }
         }
         __syncthreads();
-        // bitonic sort of every group's table, ascending key (EMPTY last)
-        for (int size = 2; size <= HS; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                for (int p = gl; p < HS / 2; p += G) {
-                    const int lo = 2 * stride * (p / stride) + (p % stride);
-                    const int hi = lo + stride;
-                    const bool up = (lo & size) == 0;
-                    const uint32_t kl = keys[lo], kh = keys[hi];
-                    if ((kl > kh) == up) {
-                        keys[lo] = kh;
-                        keys[hi] = kl;
-                        const uint32_t t = vals[lo];
-                        vals[lo] = vals[hi];
-                        vals[hi] = t;
+        // compact the occupied slots (at most 2^(HB-1): one per fine entry)
+        uint32_t rk[PER], rv[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            rk[q] = keys[q * G + gl];
+            rv[q] = vals[q * G + gl];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (rk[q] != EMPTY) {
+                const uint32_t p = atomicAdd(&s_u[grp], 1u);
+                keys[p] = rk[q];
+                vals[p] = rv[q];
+            }
+        }
+        __syncthreads();
+        const uint32_t u = s_u[grp];
+        uint32_t P = 2;
+        while (P < u) P <<= 1;
+        for (uint32_t j = u + gl; j < P; j += G) keys[j] = EMPTY;
+        if (gl == 0) atomicMax(&s_pmax, P);
+        __syncthreads();
+        // bitonic sort of the first P entries, ascending key (padding last);
+        // every group runs the block's largest P so the barriers stay uniform
+        const uint32_t PM = s_pmax;
+        for (uint32_t size = 2; size <= PM; size <<= 1) {
+            for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+                if (size <= P) {
+                    for (uint32_t p = gl; p < P / 2; p += G) {
+                        const uint32_t lo = 2 * stride * (p / stride) + (p % stride);
+                        const uint32_t hi = lo + stride;
+                        const bool up = (lo & size) == 0;
+                        const uint32_t kl = keys[lo], kh = keys[hi];
+                        if ((kl > kh) == up) {
+                            keys[lo] = kh;
+                            keys[hi] = kl;
+                            const uint32_t t = vals[lo];
+                            vals[lo] = vals[hi];
+                            vals[hi] = t;
+                        }
                     }
                 }
                 __syncthreads();
             }
         }
-        // number of distinct neighbours = non-empty slots
-        uint32_t u = 0;
-        for (int j = gl; j < HS; j += G) u += keys[j] != EMPTY;
-        if (G <= 64) {
-#pragma unroll
-            for (int d = G / 2; d > 0; d >>= 1) u += __shfl_xor(u, d, G);
-        } else {
-            for (int d = 32; d > 0; d >>= 1) u += __shfl_xor(u, d, 64);
-            if ((tid & 63) == 0) s_cnt[tid >> 6] = u;
-            __syncthreads();
-            u = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
-        }
         if (row >= 0) {
             const int32_t o = a.dstart[row];
-            for (int j = gl; j < (int)u; j += G) {
+            for (uint32_t j = gl; j < u; j += G) {
                 a.tmp_adj[o + j] = (int32_t)keys[j];
                 a.tmp_w[o + j] = (int32_t)vals[j];
             }

@@ -34,11 +34,12 @@ constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 constexpr int kSmallCap = 4096;     // contended entries resolved in LDS
 constexpr int kSmallThreads = 1024;
 
-// ctl[] layout (int64, device): round control shared by the kernels, then
-// kSpreadSlots per-block move counts (CTL_MS), then the compacted-list segment
-// tables of the next round (read back together once per round)
+// ctl[] layout (int64, device): round control shared by the kernels, then two
+// sets of kSpreadSlots per-block move counts (CTL_MS, used by alternate rounds
+// so that each round clears the next one's set on the device), then the two
+// segment tables of the compacted lists (read back together once per round)
 enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_CONT = 3, CTL_N = 8, CTL_MS = CTL_N };
-constexpr int kCtlWords = CTL_N + kSpreadSlots + 2 * kSegs;  // int64 words
+constexpr int kCtlWords = CTL_N + 2 * kSpreadSlots + 2 * kSegs;  // int64 words
 
 __device__ inline int tier_of(int32_t d)
 {
@@ -718,13 +719,13 @@ __global__ void k_decide(const uint32_t* __restrict__ keys, const uint32_t* __re
 
 // Apply admitted moves.  Moved nodes get mflag[v] = stamp (the round number + 1
 // inside lp_run, so flags never need clearing); per-block move counts go to the
-// spread slots ctl[CTL_MS + (block & 63)].
+// spread slots ctl[ms + (block & 63)].
 __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* __restrict__ list,
                                                   const int32_t* __restrict__ segtab, int s,
                                                   int32_t* __restrict__ prop, uint8_t* __restrict__ acc,
                                                   uint32_t* __restrict__ demand, int32_t* __restrict__ label,
                                                   int64_t* __restrict__ wt, const int32_t* __restrict__ vwgt,
-                                                  uint8_t* __restrict__ mflag, uint8_t stamp)
+                                                  uint8_t* __restrict__ mflag, uint8_t stamp, int ms)
 {
     __shared__ int32_t bm;
     if (ctl[CTL_ABORT]) return;
@@ -753,21 +754,37 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
     for (int d = 32; d > 0; d >>= 1) mine += __shfl_xor(mine, d, 64);
     if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&bm, mine);
     __syncthreads();
-    if (threadIdx.x == 0 && bm) atomicAdd((unsigned long long*)&ctl[CTL_MS + (blockIdx.x & (kSpreadSlots - 1))], (unsigned long long)bm);
+    if (threadIdx.x == 0 && bm)
+        atomicAdd((unsigned long long*)&ctl[ms + (blockIdx.x & (kSpreadSlots - 1))], (unsigned long long)bm);
 }
 
-// mark the neighbours of the nodes moved in this round active for the next one;
-// blockIdx.y selects the segment of the round's lists.  The segment's degree
-// tier picks the width that walks a node's neighbours: one lane (degree <= 64),
-// one wavefront (<= 4096) or the whole workgroup (hubs).
+struct SegBounds {
+    int32_t off[kSegs + 1];
+};
+
+// Mark the neighbours of the nodes moved in this round active for the next one
+// (active[u] = stamp, so the array never needs clearing); blockIdx.y selects
+// the segment of the round's lists.  The segment's degree tier picks the width
+// that walks a node's neighbours: one lane (degree <= 64), one wavefront
+// (<= 4096) or the whole workgroup (hubs).  Block (0, 0) also resets the next
+// round's segment table (offsets = the schedule's, counts 0) and move-count set.
 __global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ segtab,
                                                         const uint8_t* __restrict__ mflag, uint8_t stamp,
                                                         const int32_t* __restrict__ xadj,
                                                         const int32_t* __restrict__ adjncy,
-                                                        uint8_t* __restrict__ active)
+                                                        uint8_t* __restrict__ active, SegBounds b,
+                                                        int32_t* __restrict__ next_segtab,
+                                                        int64_t* __restrict__ next_moves)
 {
     const int seg = blockIdx.y;
+    if (blockIdx.x == 0 && seg == 0) {
+        if (threadIdx.x < kSegs) {
+            next_segtab[threadIdx.x] = b.off[threadIdx.x];
+            next_segtab[kSegs + threadIdx.x] = 0;
+        }
+        if (threadIdx.x < kSpreadSlots) next_moves[threadIdx.x] = 0;
+    }
     const int tier = seg / kSub;
     const int32_t off = segtab[seg], cnt = segtab[kSegs + seg];
     if (tier <= 1) {
@@ -775,7 +792,7 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restric
              i += (int64_t)gridDim.x * blockDim.x) {
             const int32_t v = list[off + i];
             if (mflag[v] != stamp) continue;
-            for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e) active[adjncy[e]] = 1;
+            for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e) active[adjncy[e]] = stamp;
         }
         return;
     }
@@ -788,36 +805,36 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restric
         const int32_t v = list[off + i];
         if (mflag[v] != stamp) continue;
         const int32_t e1 = xadj[v + 1];
-        for (int32_t e = xadj[v] + gl; e < e1; e += W) active[adjncy[e]] = 1;
+        for (int32_t e = xadj[v] + gl; e < e1; e += W) active[adjncy[e]] = stamp;
     }
 }
 
-// compact the active nodes of `order` segment by segment
-__global__ void k_active_flags(const int32_t* __restrict__ order, int32_t n, const uint8_t* __restrict__ active,
-                               int32_t* __restrict__ flag)
+// Append the nodes of `order` segment blockIdx.y with active == stamp to the
+// same segment region of `alist`; counts go to next_segtab[kSegs + seg].  The
+// order inside a segment is free (results do not depend on it), so each block
+// reserves its slots with one atomic.
+__global__ __launch_bounds__(kBlock) void k_active_append(const int32_t* __restrict__ order, SegBounds b,
+                                                          const uint8_t* __restrict__ active, uint8_t stamp,
+                                                          int32_t* __restrict__ alist,
+                                                          int32_t* __restrict__ next_segtab)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) flag[i] = active[order[i]];
-}
-
-__global__ void k_active_compact(const int32_t* __restrict__ order, const int32_t* __restrict__ flag,
-                                 const int32_t* __restrict__ pos, int32_t n, int32_t* __restrict__ alist)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n && flag[i]) alist[pos[i]] = order[i];
-}
-
-struct SegBounds {
-    int32_t off[kSegs + 1];
-};
-
-__global__ void k_active_segtab(const int32_t* __restrict__ pos, SegBounds b, int32_t* __restrict__ segtab)
-{
-    const int j = threadIdx.x;
-    if (j < kSegs) {
-        const int32_t a = pos[b.off[j]], e = pos[b.off[j + 1]];
-        segtab[j] = a;
-        segtab[kSegs + j] = e - a;
+    __shared__ int32_t s_cnt, s_base;
+    const int seg = blockIdx.y;
+    const int32_t lo = b.off[seg], hi = b.off[seg + 1];
+    for (int64_t i0 = lo + (int64_t)xcd_block() * kBlock; i0 < hi; i0 += (int64_t)gridDim.x * kBlock) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        const int64_t i = i0 + threadIdx.x;
+        int32_t v = -1, slot = -1;
+        if (i < hi) {
+            v = order[i];
+            if (active[v] == stamp) slot = atomicAdd(&s_cnt, 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(&next_segtab[kSegs + seg], s_cnt);
+        __syncthreads();
+        if (slot >= 0) alist[lo + s_base + slot] = v;
+        __syncthreads();
     }
 }
 
@@ -1047,13 +1064,13 @@ void launch_small(Ctx& c, int32_t s, const DGraph& g, LPState& st, LPBuffers& b)
 }
 
 void launch_apply(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, const int32_t* segtab,
-                  const DGraph& g, LPState& st, LPBuffers& b, uint8_t* mflag, uint8_t stamp)
+                  const DGraph& g, LPState& st, LPBuffers& b, uint8_t* mflag, uint8_t stamp, int ms)
 {
     const int32_t ub = class_ub(ubs, s);
     if (ub == 0) return;
     ProfScope ps(c, KMP_PROF_APPLY);
     hipLaunchKernelGGL(k_apply, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list, segtab,
-                       s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, mflag, stamp);
+                       s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, mflag, stamp, ms);
     KMP_LAUNCH_CHECK();
 }
 
@@ -1094,14 +1111,14 @@ void resolve_exact(Ctx& c, const DGraph& g, LPState& st, LPBuffers& b)
 // One sub-round on the exact path (host synchronised after admission).
 void subround_exact(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t s, const int32_t* list,
                     const int32_t* segtab, const int32_t* ubs, LPState& st, LPBuffers& b, const RateArgs& a,
-                    bool rate, uint8_t* mflag, uint8_t stamp)
+                    bool rate, uint8_t* mflag, uint8_t stamp, int ms)
 {
     if (rate) {
         launch_rate(c, a, sched, s, list, segtab, ubs);
         launch_admit(c, ubs, s, list, segtab, st, b);
     }
     resolve_exact(c, g, st, b);
-    launch_apply(c, ubs, s, list, segtab, g, st, b, mflag, stamp);
+    launch_apply(c, ubs, s, list, segtab, g, st, b, mflag, stamp, ms);
 }
 
 }  // namespace
@@ -1138,40 +1155,37 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     LPBuffers b;
     lp_buffers(c, g, sched, st.nlab, b);
     DBuf<uint8_t> active(c, (size_t)n);
-    DBuf<int32_t> alist0(c, (size_t)n), alist1(c, (size_t)n), flag(c, (size_t)n), pos(c, (size_t)n + 1);
+    c.zero(active.p, (size_t)n);
+    DBuf<int32_t> alist0(c, (size_t)n), alist1(c, (size_t)n);
     int32_t* alist[2] = {alist0.p, alist1.p};
-    int32_t* segtab_r[2] = {reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kSpreadSlots),
-                            reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kSpreadSlots) + 2 * kSegs};
+    int32_t* segtab_r[2] = {reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + 2 * kSpreadSlots),
+                            reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + 2 * kSpreadSlots) + 2 * kSegs};
     SegBounds bounds;
     for (int j = 0; j <= kSegs; ++j) bounds.off[j] = sched.off[j];
     c.zero_spread(SP_RATED);
     int32_t ub[kSegs];
     memcpy(ub, sched.cnt, sizeof(ub));
-    // enqueue: next-round active set (neighbours of nodes moved in round r) and
-    // its compaction into list buffer q
+    // enqueue: next-round active set (neighbours of nodes moved in round r),
+    // appended segment by segment to list buffer q
     auto enqueue_next_lists = [&](int32_t r, const int32_t* list, const int32_t* segtab, int q) {
-        c.zero(active.p, (size_t)n);
-        int32_t mx = 1;
-        for (int j = 0; j < kSegs; ++j) mx = std::max(mx, ub[j]);
-        {
-            ProfScope ps(c, KMP_PROF_ACTIVE);
-            hipLaunchKernelGGL(k_push_active, dim3(grid_for(mx, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream, list,
-                               segtab, b.mflag.p, (uint8_t)(r + 1), g.xadj, g.adjncy, active.p);
-            KMP_LAUNCH_CHECK();
+        int32_t mx = 1, mseg = 1;
+        for (int j = 0; j < kSegs; ++j) {
+            mx = std::max(mx, ub[j]);
+            mseg = std::max(mseg, sched.cnt[j]);
         }
-        hipLaunchKernelGGL(k_active_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sched.order.p, n, active.p,
-                           flag.p);
+        const uint8_t stamp = (uint8_t)(r + 1);
+        ProfScope ps(c, KMP_PROF_ACTIVE);
+        hipLaunchKernelGGL(k_push_active, dim3(grid_for(mx, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream, list,
+                           segtab, b.mflag.p, stamp, g.xadj, g.adjncy, active.p, bounds, segtab_r[q],
+                           b.ctl.p + CTL_MS + ((r + 1) & 1) * kSpreadSlots);
         KMP_LAUNCH_CHECK();
-        scan_excl_i32(c, flag.p, pos.p, n, pos.p + n);
-        hipLaunchKernelGGL(k_active_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, sched.order.p, flag.p,
-                           pos.p, n, alist[q]);
-        KMP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_active_segtab, dim3(1), dim3(64), 0, c.stream, pos.p, bounds, segtab_r[q]);
+        hipLaunchKernelGGL(k_active_append, dim3(grid_for(mseg, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream,
+                           sched.order.p, bounds, active.p, stamp, alist[q], segtab_r[q]);
         KMP_LAUNCH_CHECK();
     };
     struct {
         int64_t ctl[CTL_N];
-        int64_t moved[kSpreadSlots];
+        int64_t moved[2][kSpreadSlots];
         int32_t seg[2][2 * kSegs];
     } h;
     static_assert(sizeof(h) == sizeof(int64_t) * kCtlWords, "control block layout");
@@ -1179,6 +1193,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         out.rounds = r + 1;
         const int cur = r & 1, nxt = cur ^ 1;
         const uint8_t stamp = (uint8_t)(r + 1);
+        const int ms = CTL_MS + cur * kSpreadSlots;  // this round's move-count set (cleared by the previous round)
         const int32_t* list = r == 0 ? sched.order.p : alist[cur];
         const int32_t* segtab = r == 0 ? sched.segtab.p : segtab_r[cur];
         RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
@@ -1189,7 +1204,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
             launch_rate(c, a, sched, s, list, segtab, ub);
             launch_admit(c, ub, s, list, segtab, st, b);
             launch_small(c, s, g, st, b);
-            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, stamp);
+            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, stamp, ms);
         }
         const bool more = r + 1 < kRounds;
         if (more) enqueue_next_lists(r, list, segtab, nxt);
@@ -1199,17 +1214,16 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
             // (the current lists are untouched: the next round writes the other buffer)
             const int32_t s0 = (int32_t)h.ctl[CTL_ABORT_SUB];
             ctl_set(c, b, CTL_ABORT, 0);
-            subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp);
+            subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp, ms);
             for (int32_t s = s0 + 1; s < kSub; ++s)
-                subround_exact(c, g, sched, s, list, segtab, ub, st, b, a, true, b.mflag.p, stamp);
+                subround_exact(c, g, sched, s, list, segtab, ub, st, b, a, true, b.mflag.p, stamp, ms);
             if (more) enqueue_next_lists(r, list, segtab, nxt);
             c.read(&h, b.ctl.p, sizeof(h));
         }
         int64_t nm = 0;
-        for (int q = 0; q < kSpreadSlots; ++q) nm += h.moved[q];
+        for (int q = 0; q < kSpreadSlots; ++q) nm += h.moved[cur][q];
         out.moves[r] = nm;
         if (nm == 0 || !more) break;
-        c.zero(b.ctl.p + CTL_MS, sizeof(int64_t) * kSpreadSlots);
         // the next round's lists are exactly sized
         for (int j = 0; j < kSegs; ++j) ub[j] = h.seg[nxt][kSegs + j];
     }
@@ -1227,7 +1241,7 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
     a.level = (uint32_t)level;
     a.round = (uint32_t)round;
     a.active = active;
-    subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, sched.cnt, st, b, a, true, moved, 1);
+    subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, sched.cnt, st, b, a, true, moved, 1, CTL_MS);
     int64_t slots[kSpreadSlots];
     c.read(slots, b.ctl.p + CTL_MS, sizeof(slots));
     int64_t nm = 0;
