@@ -184,15 +184,20 @@ __global__ __launch_bounds__(kBlock) void k_bal_apply(const uint32_t* __restrict
 
 int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64_t>& seeds,
                 const LPSchedule& sched, int32_t* part, int64_t* wt, const BlockTab& bt, const int64_t* cap,
-                const JobTabs& jt, const int32_t* boff)
+                const JobTabs& jt, const int32_t* boff, const std::vector<int64_t>* hcap_in)
 {
     const int32_t n = g.n;
     const int32_t nb = bt.size();
     const int32_t njobs = (int32_t)seeds.size();
     const bool batch = jt.gid != nullptr;
     if (n == 0 || nb == 0) return 0;
-    std::vector<int64_t> hcap(nb), hwt(nb);
-    c.read(hcap.data(), cap, sizeof(int64_t) * nb);
+    std::vector<int64_t> hcap, hwt(nb);
+    if (hcap_in) {
+        hcap = *hcap_in;
+    } else {
+        hcap.resize(nb);
+        c.read(hcap.data(), cap, sizeof(int64_t) * nb);
+    }
     std::vector<uint8_t> hover(nb), active(njobs, 1), any(njobs);
     std::vector<int32_t> tstar(njobs);
     std::vector<int64_t> moved(njobs);

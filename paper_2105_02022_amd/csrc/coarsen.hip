@@ -536,9 +536,11 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     out.xadj = DBuf<int32_t>(c, (size_t)nc + 1);
     out.vwgt = DBuf<int32_t>(c, (size_t)nc);
     DBuf<int32_t> mstart(c, (size_t)nc + 1), dstart(c, (size_t)nc + 1), cursor(c, (size_t)nc);
-    c.zero(mstart.p, sizeof(int32_t) * ((size_t)nc + 1));
-    c.zero(dstart.p, sizeof(int32_t) * ((size_t)nc + 1));
-    c.zero(cursor.p, sizeof(int32_t) * (size_t)nc);
+    DBuf<int32_t> cnt4(c, 4);
+    fill_bytes_many(c, {{mstart.p, 4 * ((int64_t)nc + 1), 0},
+                        {dstart.p, 4 * ((int64_t)nc + 1), 0},
+                        {cursor.p, 4 * (int64_t)nc, 0},
+                        {cnt4.p, 16, 0}});
     hipLaunchKernelGGL(k_map_and_weights, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, label, cid.p, cw, g.xadj, n,
                        jt.gid, gkeep, map, out.vwgt.p, mstart.p, dstart.p);
     KMP_LAUNCH_CHECK();
@@ -553,8 +555,6 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     KMP_LAUNCH_CHECK();
     // rows by tier of their fine entry count
     DBuf<uint32_t> rk(c, nc), rv(c, nc), rk2(c, nc), rv2(c, nc);
-    DBuf<int32_t> cnt4(c, 4);
-    c.zero(cnt4.p, 4 * sizeof(int32_t));
     hipLaunchKernelGGL(k_row_tiers, dim3(grid_for(nc, kBlock, 256)), dim3(kBlock), 0, c.stream, dsum.p, nc, rk.p, rv.p, cnt4.p);
     KMP_LAUNCH_CHECK();
     radix_sort_pairs(c, rk.p, rv.p, rk2.p, rv2.p, nc, 2);

@@ -369,8 +369,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
     int32_t calls = 0;
     if (n > 0) {
         DBuf<int32_t> bstart(c, (size_t)nb + 1), bdeg(c, (size_t)nb);
-        c.zero(bstart.p, sizeof(int32_t) * ((size_t)nb + 1));
-        c.zero(bdeg.p, sizeof(int32_t) * (size_t)nb);
+        fill_bytes_many(c, {{bstart.p, 4 * ((int64_t)nb + 1), 0}, {bdeg.p, 4 * (int64_t)nb, 0}});
         DBuf<uint32_t> key(c, n), verts(c, n), k2(c, n), v2(c, n);
         hipLaunchKernelGGL(k_block_count, dim3(grid_for(n, kBlock, 256)), dim3(kBlock), 0, c.stream, part, g.xadj, n, nb,
                            bstart.p, bdeg.p, key.p, verts.p);

@@ -569,7 +569,6 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
                    batch ? L.dnoff.p : nullptr, batch ? dU.p : nullptr};
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_cl += lps.moves[r];
-        t.rated += lps.rated_edges;
         std::vector<int64_t> nc;
         if (!batch) {
             two_hop(c, g, U[0], label.p, cw.p, fav.p, false);
@@ -722,11 +721,10 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
             L.sched_full = true;
         }
         t.brounds += balance(c, g, l, batch ? seeds : std::vector<uint64_t>{seed0}, *L.sched, part.p, wt.p, bt, cap.p,
-                             jt, dboff.p);
+                             jt, dboff.p, &hcap);
         LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF, jt, dboff.p, nullptr};
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_ref += lps.moves[r];
-        t.rated += lps.rated_edges;
         if (phase_sync) c.sync();
         t.ms_ref += ms_since(t2) + (ms_since(t0) - ms_since(t1));
         // the coarser level is no longer needed
@@ -756,7 +754,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         for (int32_t j : L0.mem) jobs[j].cut = cuts[j];
     }
     for (int32_t j : L0.mem) jobs[j].status = jobs[j].maxw > jobs[j].lk ? KMP_IMBALANCED : KMP_OK;
-    c.sync();
+    t.rated = c.read_spread(SP_RATED);
 }
 
 // Derived integers of a job (Sec. 2 balance constraint, Sec. 5.1); k = 1 and

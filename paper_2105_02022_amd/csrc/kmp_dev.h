@@ -327,6 +327,14 @@ void scan_incl_max_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n);
 // Results end in keys/vals (the alt buffers are scratch of the same size).
 void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
                       int key_bits);
+// Several byte fills in one launch (at most kMaxFills buffers).
+constexpr int kMaxFills = 8;
+struct ByteFill {
+    void* p;
+    int64_t bytes;
+    uint8_t byte;
+};
+void fill_bytes_many(Ctx& c, std::initializer_list<ByteFill> fills);
 void fill_i32(Ctx& c, int32_t* p, int32_t v, int64_t n);
 void fill_u8(Ctx& c, uint8_t* p, uint8_t v, int64_t n);
 void fill_i64(Ctx& c, int64_t* p, int64_t v, int64_t n);
@@ -368,7 +376,6 @@ struct LPState {
 struct LPStats {
     int64_t moves[kRounds] = {0, 0, 0, 0, 0};
     int32_t rounds = 0;
-    int64_t rated_edges = 0;
 };
 
 // Per-level schedule: nodes grouped by (degree tier, sub-round class); the
@@ -396,6 +403,7 @@ struct LPSchedule {
 // only the nodes of jobs with gpart[job] != 0 are scheduled (gpart NULL: all).
 void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched,
                        const JobTabs& jt = {}, const uint8_t* gpart = nullptr);
+// Rated entries accumulate in the context's SP_RATED spread counter.
 LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st);
 int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32_t s, uint64_t seed,
                     const LPSchedule& sched, LPState& st, const uint8_t* active, uint8_t* moved);
@@ -455,9 +463,10 @@ void edge_cut_jobs(Ctx& c, const DGraph& g, const int32_t* part, const int32_t* 
 // Balancer rounds.  Batches: bt.job gives every block's job, jt/boff make the
 // hashes job-local and each job stops on its own (no overload, or a round
 // without moves).
+// hcap: the caps on the host when the caller has them (else they are read).
 int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64_t>& seeds,
                 const LPSchedule& sched, int32_t* part, int64_t* wt, const BlockTab& bt, const int64_t* cap,
-                const JobTabs& jt = {}, const int32_t* boff = nullptr);
+                const JobTabs& jt = {}, const int32_t* boff = nullptr, const std::vector<int64_t>* hcap = nullptr);
 
 // ---------------------------------------------------------------- validation, batches (kmp.hip)
 int validate_graph(Ctx& c, const DGraph& g);

@@ -432,9 +432,10 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
             keys[j] = EMPTY;
             vals[j] = 0;
         }
-        // the table lives in global memory: make the clears (and below, the
-        // atomics) complete at device scope before other waves use the slots
-        __threadfence();
+        // the table is global memory used by this workgroup only (one CU, one
+        // L2): a workgroup-scope fence orders the clears (and below, the
+        // atomics) before the other waves use the slots
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __syncthreads();
         for (int32_t e = e0 + tid; e < e1; e += kBlock) {
             uint32_t K = (uint32_t)a.label[a.adjncy[e]];
@@ -450,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
                 h = (h + 1) & mask;
             }
         }
-        __threadfence();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
         __syncthreads();
         const uint32_t own = (uint32_t)a.label[v];
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
@@ -915,27 +916,31 @@ struct LPBuffers {
     DBuf<uint32_t> ckeys, cvals;   // contended (target, id), unordered
     DBuf<int64_t> base;            // [nlab] weight before a target's first proposal
     DBuf<int64_t> ctl;
+    DBuf<uint8_t> active;          // round stamp of the active set (lp_run)
 };
 
 void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t nlab, LPBuffers& b)
 {
     b.prop = DBuf<int32_t>(c, (size_t)g.n);
-    fill_i32(c, b.prop.p, -1, g.n);
     b.acc = DBuf<uint8_t>(c, (size_t)g.n);
-    c.zero(b.acc.p, (size_t)g.n);
     b.demand = DBuf<uint32_t>(c, (size_t)nlab);
-    c.zero(b.demand.p, sizeof(uint32_t) * (size_t)nlab);
     if (sched.hub_slots_total > 0) {
         b.hub_keys = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
         b.hub_vals = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
     }
     b.mflag = DBuf<uint8_t>(c, (size_t)g.n);
-    c.zero(b.mflag.p, (size_t)g.n);
     b.ckeys = DBuf<uint32_t>(c, (size_t)g.n);
     b.cvals = DBuf<uint32_t>(c, (size_t)g.n);
     b.base = DBuf<int64_t>(c, (size_t)nlab);
     b.ctl = DBuf<int64_t>(c, kCtlWords);
-    c.zero(b.ctl.p, sizeof(int64_t) * kCtlWords);
+    b.active = DBuf<uint8_t>(c, (size_t)g.n);
+    // prop = -1, everything else 0, in one launch
+    fill_bytes_many(c, {{b.prop.p, 4 * (int64_t)g.n, 0xFF},
+                        {b.acc.p, (int64_t)g.n, 0},
+                        {b.demand.p, 4 * (int64_t)nlab, 0},
+                        {b.mflag.p, (int64_t)g.n, 0},
+                        {b.ctl.p, (int64_t)sizeof(int64_t) * kCtlWords, 0},
+                        {b.active.p, (int64_t)g.n, 0}});
 }
 
 RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpre, LPBuffers* b)
@@ -1154,15 +1159,13 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     if (n == 0) return out;
     LPBuffers b;
     lp_buffers(c, g, sched, st.nlab, b);
-    DBuf<uint8_t> active(c, (size_t)n);
-    c.zero(active.p, (size_t)n);
+    DBuf<uint8_t>& active = b.active;
     DBuf<int32_t> alist0(c, (size_t)n), alist1(c, (size_t)n);
     int32_t* alist[2] = {alist0.p, alist1.p};
     int32_t* segtab_r[2] = {reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + 2 * kSpreadSlots),
                             reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + 2 * kSpreadSlots) + 2 * kSegs};
     SegBounds bounds;
     for (int j = 0; j <= kSegs; ++j) bounds.off[j] = sched.off[j];
-    c.zero_spread(SP_RATED);
     int32_t ub[kSegs];
     memcpy(ub, sched.cnt, sizeof(ub));
     // enqueue: next-round active set (neighbours of nodes moved in round r),
@@ -1227,7 +1230,6 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         // the next round's lists are exactly sized
         for (int j = 0; j < kSegs; ++j) ub[j] = h.seg[nxt][kSegs + j];
     }
-    out.rated_edges = c.read_spread(SP_RATED);
     return out;
 }
 

@@ -616,6 +616,52 @@ __global__ __launch_bounds__(kBlock) void k_sum_i32(const int32_t* __restrict__ 
 
 }  // namespace
 
+namespace {
+struct FillList {
+    unsigned char* p[kMaxFills];
+    int64_t bytes[kMaxFills];
+    uint32_t word[kMaxFills];  // the byte repeated four times
+};
+
+// blockIdx.y = buffer; 4-byte stores over the aligned body, bytes at the ends
+__global__ __launch_bounds__(kBlock) void k_fill_many(FillList L)
+{
+    const int q = blockIdx.y;
+    unsigned char* p = L.p[q];
+    const int64_t nb = L.bytes[q];
+    const uint64_t a = (uint64_t)p;
+    const int64_t head = (int64_t)((4 - (a & 3)) & 3) < nb ? (int64_t)((4 - (a & 3)) & 3) : nb;
+    const int64_t words = (nb - head) >> 2;
+    uint32_t* w = reinterpret_cast<uint32_t*>(p + head);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int64_t i = t; i < words; i += stride) w[i] = L.word[q];
+    const unsigned char b = (unsigned char)L.word[q];
+    if (t < head) p[t] = b;
+    const int64_t tail0 = head + (words << 2);
+    if (t < nb - tail0) p[tail0 + t] = b;
+}
+}  // namespace
+
+void fill_bytes_many(Ctx& c, std::initializer_list<ByteFill> fills)
+{
+    FillList L;
+    int nf = 0;
+    int64_t mx = 0;
+    for (const ByteFill& f : fills) {
+        if (!f.p || f.bytes <= 0) continue;
+        if (nf == kMaxFills) throw Error(KMP_EINVAL, "too many buffers in one fill");
+        L.p[nf] = static_cast<unsigned char*>(f.p);
+        L.bytes[nf] = f.bytes;
+        L.word[nf] = 0x01010101u * f.byte;
+        mx = std::max<int64_t>(mx, f.bytes / 4 + 4);
+        ++nf;
+    }
+    if (nf == 0) return;
+    hipLaunchKernelGGL(k_fill_many, dim3(grid_for(mx, kBlock, 4096), nf), dim3(kBlock), 0, c.stream, L);
+    KMP_LAUNCH_CHECK();
+}
+
 void fill_i32(Ctx& c, int32_t* p, int32_t v, int64_t n)
 {
     if (n <= 0) return;
