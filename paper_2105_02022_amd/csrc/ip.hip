@@ -193,17 +193,32 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     }
     fence_wave<LDS>();
     int64_t w0 = 0;
+    // Each step's loads are unconditional and issued together (state, weight
+    // and gain of up to four nodes per lane; adjacency entry and weight, then
+    // the neighbour's state and gain), so a step waits on a few LDS round
+    // trips instead of one per predicated load.
+    const int32_t last = nv - 1;
     while (w0 < t0) {
         uint64_t best = 0;  // (gain biased << 32) | ~id ; 0 = none
-        for (int32_t i = lane; i < nv; i += 64) {
-            if (st[i] != 1 || w0 + lvw[i] > cap0) continue;
-            const uint64_t k = ((uint64_t)((uint32_t)gain[i] ^ 0x80000000u) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)i);
-            if (k > best) best = k;
+        for (int32_t i0 = lane; i0 < nv; i0 += 256) {
+            uint8_t sv[4];
+            int32_t wv[4], gv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int32_t i = i0 + 64 * j <= last ? i0 + 64 * j : last;
+                sv[j] = st[i];
+                wv[j] = lvw[i];
+                gv[j] = gain[i];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint32_t i = (uint32_t)(i0 + 64 * j);
+                const uint64_t k = ((uint64_t)((uint32_t)gv[j] ^ 0x80000000u) << 32) | (uint64_t)(0xFFFFFFFFu - i);
+                const bool ok = (int32_t)i <= last && sv[j] == 1 && w0 + wv[j] <= cap0;
+                best = ok && k > best ? k : best;
+            }
         }
-        for (int d = 32; d > 0; d >>= 1) {
-            const uint64_t o = shfl_xor_u64(best, d);
-            if (o > best) best = o;
-        }
+        best = wave_max_u64(best);
         int32_t pick;
         if (best != 0) {
             pick = (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFu));
@@ -214,20 +229,21 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
                 const uint64_t k = ((uint64_t)hash_step(hj, (uint32_t)i, 6) << 32) | (uint32_t)i;
                 if (k < hb) hb = k;
             }
-            for (int d = 32; d > 0; d >>= 1) {
-                const uint64_t o = shfl_xor_u64(hb, d);
-                if (o < hb) hb = o;
-            }
+            hb = wave_min_u64(hb);
             if (hb == ~0ull) break;
             pick = (int32_t)(hb & 0xFFFFFFFFu);
         }
+        const int32_t pw = lvw[pick], pe0 = lxadj[pick], pe1 = lxadj[pick + 1];
         if (lane == 0) st[pick] = 2;
-        w0 += lvw[pick];
+        w0 += pw;
         fence_wave<LDS>();
-        for (int32_t e = lxadj[pick] + lane; e < lxadj[pick + 1]; e += 64) {
+        for (int32_t e = pe0 + lane; e < pe1; e += 64) {
             const int32_t u = ladj[e];
-            if (st[u] == 2) continue;
-            gain[u] = (int32_t)((int64_t)gain[u] + 2 * (int64_t)lw[e]);
+            const int32_t we = lw[e];
+            const uint8_t su = st[u];
+            const int32_t gu = gain[u];
+            if (su == 2) continue;
+            gain[u] = (int32_t)((int64_t)gu + 2 * (int64_t)we);
             st[u] = 1;
         }
         fence_wave<LDS>();

@@ -101,6 +101,46 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int mask, int width = 64)
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Wavefront max / min of a 64-bit key without LDS traffic: DPP moves within
+// each row of 16 lanes (quad swaps, half-row and row mirrors), then the four
+// row results through readlane.  Every lane of the wavefront must be active;
+// the result is uniform.
+template <int CTRL>
+__device__ inline uint64_t dpp_u64(uint64_t v)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t wave_max_u64(uint64_t v)
+{
+    uint64_t o;
+    o = dpp_u64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v = o > v ? o : v;
+    o = dpp_u64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v = o > v ? o : v;
+    o = dpp_u64<0x141>(v);  // row_half_mirror
+    v = o > v ? o : v;
+    o = dpp_u64<0x140>(v);  // row_mirror
+    v = o > v ? o : v;
+    const uint64_t a = readlane_u64(v, 0), b = readlane_u64(v, 16), c = readlane_u64(v, 32), d = readlane_u64(v, 48);
+    const uint64_t ab = a > b ? a : b, cd = c > d ? c : d;
+    return ab > cd ? ab : cd;
+}
+
+__device__ inline uint64_t wave_min_u64(uint64_t v)
+{
+    return ~wave_max_u64(~v);
+}
+
 // LDS slot for a key in a table of 2^bits slots (multiplicative hashing).
 __device__ inline uint32_t slot_of(uint32_t key, int bits)
 {
