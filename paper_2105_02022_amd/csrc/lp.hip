@@ -16,12 +16,13 @@
 //
 // Admission: proposals add their weight to demand[K]; targets whose whole
 // demand fits are admitted at once.  The others ("contended") are appended to
-// a list and resolved on the device by one workgroup that sorts the
-// (target, id) keys in LDS and admits by segmented prefix sums.  Sub-rounds
-// are enqueued speculatively: if the contended list of a sub-round exceeds
-// the LDS capacity, a device flag aborts the rest of the round and the host
-// finishes it on the exact path (sort in global memory), one sub-round at a
-// time.  Rounds after the first rate only the active nodes, compacted per
+// a list (with the target's weight at the start of the sub-round); the apply
+// kernel decides each contended proposal by summing the weights of the
+// proposals into its target with smaller ids, read from the list through LDS.
+// Sub-rounds are enqueued speculatively: if the contended list of a sub-round
+// is longer than kSmallCap, a device flag aborts the rest of the round and the
+// host finishes it on the exact path (sort in global memory), one sub-round at
+// a time.  Rounds after the first rate only the active nodes, compacted per
 // (tier, class) segment on the device.
 #include "kmp_dev.h"
 
@@ -31,10 +32,12 @@ namespace {
 
 constexpr int T0_DEG = 16, T1_DEG = 64, T2_DEG = 512, T3_DEG = 4096;
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
-constexpr int kSmallCap = 4096;     // contended entries resolved in LDS
-constexpr int kSmallThreads = 1024;
+constexpr int kSmallCap = 4096;     // contended entries resolved on the device
+constexpr int kCandChunk = 1024;    // contended entries staged in LDS per pass
 
-// ctl[] layout (int64, device): round control shared by the kernels, then two
+// ctl[] layout (int64, device): round control shared by the kernels (the
+// contended-list length alternates between CTL_CONT and CTL_CONT + 1 by
+// sub-round parity, so that each apply clears the next one's), then two
 // sets of kSpreadSlots per-block move counts (CTL_MS, used by alternate rounds
 // so that each round clears the next one's set on the device), then the two
 // segment tables of the compacted lists (read back together once per round)
@@ -554,7 +557,8 @@ __global__ __launch_bounds__(kBlock) void k_admit_fast(int64_t* ctl, const int32
                                                        const uint32_t* __restrict__ demand,
                                                        const int64_t* __restrict__ wt, CapArgs caps,
                                                        uint8_t* __restrict__ acc, uint32_t* __restrict__ ckeys,
-                                                       uint32_t* __restrict__ cvals)
+                                                       uint32_t* __restrict__ cvals, int64_t* __restrict__ wsnap,
+                                                       int cont_idx)
 {
     if (ctl[CTL_ABORT]) return;
     const ClassSegs cs = class_segs(segtab, s);
@@ -567,108 +571,22 @@ __global__ __launch_bounds__(kBlock) void k_admit_fast(int64_t* ctl, const int32
             K = prop[v];
             if (K >= 0) {
                 const int64_t cap = cap_for(caps, (uint32_t)K, (uint32_t)v);
-                if (wt[K] + (int64_t)demand[K] <= cap) {
+                const int64_t w = wt[K];
+                if (w + (int64_t)demand[K] <= cap) {
                     acc[v] = 1;
                 } else {
                     acc[v] = 2;
+                    wsnap[K] = w;  // every proposal into K writes the same value
                     cont = true;
                 }
             }
         }
-        const int64_t slot = reserve_slot(&ctl[CTL_CONT], cont);
+        const int64_t slot = reserve_slot(&ctl[cont_idx], cont);
         if (cont) {
             ckeys[slot] = (uint32_t)K;
             cvals[slot] = (uint32_t)v;
         }
     }
-}
-
-// One workgroup: sort the contended (target, id) keys in LDS, admit by
-// segmented prefix sums.  Raises the abort flag when the list is too long.
-__global__ __launch_bounds__(kSmallThreads) void k_contended_small(int64_t* ctl, int s, const uint32_t* __restrict__ ckeys,
-                                                                   const uint32_t* __restrict__ cvals,
-                                                                   const int32_t* __restrict__ vwgt,
-                                                                   const int64_t* __restrict__ wt, CapArgs caps,
-                                                                   int64_t* __restrict__ base,
-                                                                   uint8_t* __restrict__ acc)
-{
-    __shared__ uint64_t key[kSmallCap];
-    __shared__ int64_t pre[kSmallCap];
-    __shared__ int64_t wsum[kSmallThreads / 64];
-    __shared__ int64_t carry;
-    const int tid = threadIdx.x;
-    if (ctl[CTL_ABORT]) return;
-    const int64_t C = ctl[CTL_CONT];
-    if (C == 0) return;
-    if (C > kSmallCap) {
-        if (tid == 0) {
-            ctl[CTL_ABORT] = 1;
-            ctl[CTL_ABORT_SUB] = s;
-        }
-        return;
-    }
-    int P = 1;
-    while (P < C) P <<= 1;
-    for (int i = tid; i < P; i += kSmallThreads)
-        key[i] = i < C ? (((uint64_t)ckeys[i] << 32) | cvals[i]) : ~0ull;
-    __syncthreads();
-    for (int size = 2; size <= P; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int p = tid; p < P / 2; p += kSmallThreads) {
-                const int lo = 2 * stride * (p / stride) + (p % stride);
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint64_t x = key[lo], y = key[hi];
-                if ((x > y) == up) {
-                    key[lo] = y;
-                    key[hi] = x;
-                }
-            }
-            __syncthreads();
-        }
-    }
-    // inclusive prefix of node weights in sorted order (chunks of the block size)
-    if (tid == 0) carry = 0;
-    __syncthreads();
-    for (int c0 = 0; c0 < C; c0 += kSmallThreads) {
-        const int i = c0 + tid;
-        int64_t x = 0;
-        if (i < C) {
-            const uint32_t v = (uint32_t)key[i];
-            x = vwgt ? vwgt[v] : 1;
-        }
-        const int lane = tid & 63, wv = tid >> 6;
-        for (int d = 1; d < 64; d <<= 1) {
-            const int64_t y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
-        }
-        if (lane == 63) wsum[wv] = x;
-        __syncthreads();
-        int64_t p = carry;
-        for (int q = 0; q < wv; ++q) p += wsum[q];
-        if (i < C) pre[i] = p + x;
-        __syncthreads();
-        if (tid == kSmallThreads - 1) carry = p + x;
-        __syncthreads();
-    }
-    // segment starts: weight before the first proposal of every target
-    for (int i = tid; i < C; i += kSmallThreads) {
-        const uint32_t K = (uint32_t)(key[i] >> 32);
-        if (i == 0 || (uint32_t)(key[i - 1] >> 32) != K) {
-            const uint32_t v = (uint32_t)key[i];
-            base[K] = pre[i] - (vwgt ? vwgt[v] : 1);
-        }
-    }
-    __threadfence_block();
-    __syncthreads();
-    for (int i = tid; i < C; i += kSmallThreads) {
-        const uint32_t K = (uint32_t)(key[i] >> 32);
-        const uint32_t v = (uint32_t)key[i];
-        const int64_t cap = cap_for(caps, K, v);
-        acc[v] = wt[K] + (pre[i] - base[K]) <= cap ? 1 : 0;
-    }
-    __syncthreads();
-    if (tid == 0) ctl[CTL_CONT] = 0;
 }
 
 // exact path (host synchronised): contended proposals in ascending id over all n
@@ -718,28 +636,79 @@ __global__ void k_decide(const uint32_t* __restrict__ keys, const uint32_t* __re
     acc[vals[i]] = wt[K] + (pre[i] - base[K]) <= cap ? 1 : 0;
 }
 
-// Apply admitted moves.  Moved nodes get mflag[v] = stamp (the round number + 1
+// Apply the sub-round's moves.  Contended proposals (acc = 2) are decided
+// here: v is admitted iff the weight of its target at the sub-round start plus
+// the weights of all proposals into the target with id <= v fits the cap (the
+// contended list is staged through LDS in chunks by the blocks that hold
+// contended nodes).  A list longer than kSmallCap aborts the sub-round before
+// any move is applied.  Moved nodes get mflag[v] = stamp (the round number + 1
 // inside lp_run, so flags never need clearing); per-block move counts go to the
-// spread slots ctl[ms + (block & 63)].
+// spread slots ctl[ms + (block & 63)].  Block 0 clears the next sub-round's
+// contended-list length.
 __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* __restrict__ list,
                                                   const int32_t* __restrict__ segtab, int s,
                                                   int32_t* __restrict__ prop, uint8_t* __restrict__ acc,
                                                   uint32_t* __restrict__ demand, int32_t* __restrict__ label,
                                                   int64_t* __restrict__ wt, const int32_t* __restrict__ vwgt,
-                                                  uint8_t* __restrict__ mflag, uint8_t stamp, int ms)
+                                                  uint8_t* __restrict__ mflag, uint8_t stamp, int ms,
+                                                  const uint32_t* __restrict__ ckeys,
+                                                  const uint32_t* __restrict__ cvals,
+                                                  const int64_t* __restrict__ wsnap, CapArgs caps, int cont_idx)
 {
     __shared__ int32_t bm;
+    __shared__ uint64_t s_kv[kCandChunk];  // (target << 32) | id
+    __shared__ int32_t s_w[kCandChunk];
     if (ctl[CTL_ABORT]) return;
+    const int64_t C = ctl[cont_idx];
+    if (C > kSmallCap) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            ctl[CTL_ABORT] = 1;
+            ctl[CTL_ABORT_SUB] = s;
+        }
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) ctl[CTL_CONT + ((cont_idx - CTL_CONT) ^ 1)] = 0;
     if (threadIdx.x == 0) bm = 0;
     __syncthreads();
     const ClassSegs cs = class_segs(segtab, s);
     int32_t mine = 0;
-    for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < cs.total;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t v = list[class_pos(cs, i)];
-        const int32_t K = prop[v];
+    for (int64_t i0 = (int64_t)xcd_block() * blockDim.x; i0 < cs.total; i0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = i0 + threadIdx.x;
+        int32_t v = -1, K = -1;
+        uint8_t a = 0;
+        if (i < cs.total) {
+            v = list[class_pos(cs, i)];
+            K = prop[v];
+            if (K >= 0) a = acc[v];
+        }
+        const bool contended = a == 2;
+        if (__syncthreads_or(contended)) {
+            int64_t pre = 0;
+            for (int64_t c0 = 0; c0 < C; c0 += kCandChunk) {
+                const int len = (int)(C - c0 < kCandChunk ? C - c0 : kCandChunk);
+                for (int j = threadIdx.x; j < len; j += blockDim.x) {
+                    const uint32_t u = cvals[c0 + j];
+                    s_kv[j] = ((uint64_t)ckeys[c0 + j] << 32) | u;
+                    if (vwgt) s_w[j] = vwgt[u];
+                }
+                __syncthreads();
+                if (contended) {
+                    // entries of target K with id <= v: keys in [K << 32, (K << 32) | v]
+                    const uint64_t lo = (uint64_t)(uint32_t)K << 32, hi = lo | (uint32_t)v;
+                    if (vwgt) {
+#pragma unroll 8
+                        for (int j = 0; j < len; ++j) pre += (s_kv[j] >= lo && s_kv[j] <= hi) ? s_w[j] : 0;
+                    } else {
+#pragma unroll 8
+                        for (int j = 0; j < len; ++j) pre += (s_kv[j] >= lo && s_kv[j] <= hi) ? 1 : 0;
+                    }
+                }
+                __syncthreads();
+            }
+            if (contended) a = wsnap[K] + pre <= cap_for(caps, (uint32_t)K, (uint32_t)v) ? 1 : 0;
+        }
         if (K < 0) continue;
-        if (acc[v] == 1) {
+        if (a == 1) {
             const int64_t c = vwgt ? vwgt[v] : 1;
             const int32_t old = label[v];
             label[v] = K;
@@ -1056,15 +1025,8 @@ void launch_admit(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, co
     if (ub == 0) return;
     ProfScope ps(c, KMP_PROF_ADMIT);
     hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list,
-                       segtab, s, b.prop.p, b.demand.p, st.wt, cap_args(st), b.acc.p, b.ckeys.p, b.cvals.p);
-    KMP_LAUNCH_CHECK();
-}
-
-void launch_small(Ctx& c, int32_t s, const DGraph& g, LPState& st, LPBuffers& b)
-{
-    ProfScope ps(c, KMP_PROF_CONTENDED);
-    hipLaunchKernelGGL(k_contended_small, dim3(1), dim3(kSmallThreads), 0, c.stream, b.ctl.p, s, b.ckeys.p,
-                       b.cvals.p, g.vwgt, st.wt, cap_args(st), b.base.p, b.acc.p);
+                       segtab, s, b.prop.p, b.demand.p, st.wt, cap_args(st), b.acc.p, b.ckeys.p, b.cvals.p,
+                       b.base.p, CTL_CONT + (s & 1));
     KMP_LAUNCH_CHECK();
 }
 
@@ -1075,7 +1037,8 @@ void launch_apply(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, co
     if (ub == 0) return;
     ProfScope ps(c, KMP_PROF_APPLY);
     hipLaunchKernelGGL(k_apply, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list, segtab,
-                       s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, mflag, stamp, ms);
+                       s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, mflag, stamp, ms, b.ckeys.p,
+                       b.cvals.p, b.base.p, cap_args(st), CTL_CONT + (s & 1));
     KMP_LAUNCH_CHECK();
 }
 
@@ -1085,10 +1048,11 @@ void ctl_set(Ctx& c, LPBuffers& b, int idx, int64_t v)
     KMP_LAUNCH_CHECK();
 }
 
-// Exact admission of the contended proposals (host synchronised).
-void resolve_exact(Ctx& c, const DGraph& g, LPState& st, LPBuffers& b)
+// Exact admission of the contended proposals of sub-round s (host synchronised).
+void resolve_exact(Ctx& c, const DGraph& g, LPState& st, LPBuffers& b, int32_t s)
 {
-    const int64_t ncont = c.read1(b.ctl.p + CTL_CONT);
+    const int cont_idx = CTL_CONT + (s & 1);
+    const int64_t ncont = c.read1(b.ctl.p + cont_idx);
     if (ncont == 0) return;
     const int32_t n = g.n;
     DBuf<int32_t> flag(c, (size_t)n), pos(c, (size_t)n + 1);
@@ -1110,7 +1074,7 @@ void resolve_exact(Ctx& c, const DGraph& g, LPState& st, LPBuffers& b)
     hipLaunchKernelGGL(k_decide, dim3(grid_for(ncont)), dim3(kBlock), 0, c.stream, keys.p, vals.p, pre.p, b.base.p,
                        ncont, st.wt, cap_args(st), b.acc.p);
     KMP_LAUNCH_CHECK();
-    ctl_set(c, b, CTL_CONT, 0);
+    ctl_set(c, b, cont_idx, 0);
 }
 
 // One sub-round on the exact path (host synchronised after admission).
@@ -1122,7 +1086,7 @@ void subround_exact(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t s,
         launch_rate(c, a, sched, s, list, segtab, ubs);
         launch_admit(c, ubs, s, list, segtab, st, b);
     }
-    resolve_exact(c, g, st, b);
+    resolve_exact(c, g, st, b, s);
     launch_apply(c, ubs, s, list, segtab, g, st, b, mflag, stamp, ms);
 }
 
@@ -1206,7 +1170,6 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         for (int32_t s = 0; s < kSub; ++s) {
             launch_rate(c, a, sched, s, list, segtab, ub);
             launch_admit(c, ub, s, list, segtab, st, b);
-            launch_small(c, s, g, st, b);
             launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, stamp, ms);
         }
         const bool more = r + 1 < kRounds;
