@@ -576,28 +576,17 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     a.cdeg = cdeg.p;
     a.bytes_ctr = c.spread(SP_BYTES + KMP_PROF_CONTRACT_ROWS);
     int32_t off = 0;
-    if (tc[0] > 0) {
-        constexpr int G = 16;
-        ProfScope ps(c, KMP_PROF_CONTRACT_ROWS);
-        hipLaunchKernelGGL((k_contract_rows<G, 7>), dim3(grid_for(tc[0], kBlock / G, 65536)), dim3(kBlock), 0,
-                           c.stream, a, rows + off, tc[0]);
-        KMP_LAUNCH_CHECK();
-    }
+    if (tc[0] > 0)
+        KMP_LAUNCH_TIMED(c, KMP_PROF_CONTRACT_ROWS, (k_contract_rows<16, 7>), dim3(grid_for(tc[0], kBlock / 16, 65536)),
+                         dim3(kBlock), 0, a, rows + off, tc[0]);
     off += tc[0];
-    if (tc[1] > 0) {
-        constexpr int G = 64;
-        ProfScope ps(c, KMP_PROF_CONTRACT_ROWS);
-        hipLaunchKernelGGL((k_contract_rows<G, 10>), dim3(grid_for(tc[1], kBlock / G, 65536)), dim3(kBlock), 0,
-                           c.stream, a, rows + off, tc[1]);
-        KMP_LAUNCH_CHECK();
-    }
+    if (tc[1] > 0)
+        KMP_LAUNCH_TIMED(c, KMP_PROF_CONTRACT_ROWS, (k_contract_rows<64, 10>),
+                         dim3(grid_for(tc[1], kBlock / 64, 65536)), dim3(kBlock), 0, a, rows + off, tc[1]);
     off += tc[1];
-    if (tc[2] > 0) {
-        ProfScope ps(c, KMP_PROF_CONTRACT_ROWS);
-        hipLaunchKernelGGL((k_contract_rows<256, 13>), dim3(grid_for(tc[2], 1, 65536)), dim3(kBlock), 0, c.stream, a,
-                           rows + off, tc[2]);
-        KMP_LAUNCH_CHECK();
-    }
+    if (tc[2] > 0)
+        KMP_LAUNCH_TIMED(c, KMP_PROF_CONTRACT_ROWS, (k_contract_rows<256, 13>), dim3(grid_for(tc[2], 1, 65536)),
+                         dim3(kBlock), 0, a, rows + off, tc[2]);
     off += tc[2];
     if (tc[3] > 0) {
         const int32_t nh = tc[3];

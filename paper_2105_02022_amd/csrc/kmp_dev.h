@@ -3,6 +3,7 @@
 // units.  Nothing here is part of the public ABI (include/kmp.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -269,6 +270,10 @@ class Ctx {
     Prof* prof = nullptr;  // profiling enabled when non-null
     int prof_begin(int cls);
     void prof_end(int idx);
+    // Events for one launch of class cls (false: not timed).  The caller
+    // passes them to hipExtLaunchKernelGGL, which stamps the kernel's own start
+    // and end (the duration a profiler reports for the dispatch).
+    bool prof_pair(int cls, hipEvent_t& a, hipEvent_t& b);
     // Resolve the recorded events into per-class launches / ms and read the
     // per-class algorithmic byte counters.
     void prof_collect(int64_t* launches, double* ms, int64_t* bytes);
@@ -298,6 +303,18 @@ struct ProfScope {
     ProfScope(Ctx& ctx, int cls) : c(ctx), idx(ctx.prof_begin(cls)) {}
     ~ProfScope() { c.prof_end(idx); }
 };
+
+// Launch on c.stream; when class cls is being timed, the kernel's own start
+// and end are stamped into the class's events (hipExtLaunchKernelGGL).
+#define KMP_LAUNCH_TIMED(c, cls, kernel, grid, block, shmem, ...)                                          \
+    do {                                                                                                   \
+        hipEvent_t ea_, eb_;                                                                               \
+        if ((c).prof_pair((cls), ea_, eb_))                                                                \
+            hipExtLaunchKernelGGL(kernel, grid, block, shmem, (c).stream, ea_, eb_, 0, __VA_ARGS__);        \
+        else                                                                                               \
+            hipLaunchKernelGGL(kernel, grid, block, shmem, (c).stream, __VA_ARGS__);                        \
+        KMP_LAUNCH_CHECK();                                                                                \
+    } while (0)
 
 // RAII device buffer bound to a context.
 template <typename T>

@@ -959,50 +959,42 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
         // LP launches count their algorithmic bytes per class (tier 3 joins tier 2); the
         // balancer's rating launches are timed under the balance class and count no LP bytes
         if (!a.over) a.bytes_ctr = bytes + kSpreadSlots * (t < 3 ? t : t == 3 ? KMP_PROF_RATE_T2 : KMP_PROF_RATE_HUB);
+        const int cls = a.over ? KMP_PROF_BALANCE
+                               : t == 0 ? KMP_PROF_RATE_T0
+                               : t == 1 ? KMP_PROF_RATE_T1
+                               : t <= 3 ? KMP_PROF_RATE_T2
+                                        : KMP_PROF_RATE_HUB;
         switch (t) {
             case 0: {
-                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_T0);
                 const dim3 grid(grid_for(ub, kBlock, 65536));
                 const bool ew = a.adjwgt != nullptr;
                 if (a.over) {
-                    if (ew) hipLaunchKernelGGL((k_rate_lane<true, true, true>), grid, dim3(kBlock), 0, c.stream, a);
-                    else hipLaunchKernelGGL((k_rate_lane<false, true, true>), grid, dim3(kBlock), 0, c.stream, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, true>), grid, dim3(kBlock), 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, true>), grid, dim3(kBlock), 0, a);
                 } else if (a.cap_vec) {
-                    if (ew) hipLaunchKernelGGL((k_rate_lane<true, true, false>), grid, dim3(kBlock), 0, c.stream, a);
-                    else hipLaunchKernelGGL((k_rate_lane<false, true, false>), grid, dim3(kBlock), 0, c.stream, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, false>), grid, dim3(kBlock), 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, false>), grid, dim3(kBlock), 0, a);
                 } else {
-                    if (ew) hipLaunchKernelGGL((k_rate_lane<true, false, false>), grid, dim3(kBlock), 0, c.stream, a);
-                    else hipLaunchKernelGGL((k_rate_lane<false, false, false>), grid, dim3(kBlock), 0, c.stream, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, false, false>), grid, dim3(kBlock), 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, false, false>), grid, dim3(kBlock), 0, a);
                 }
                 break;
             }
-            case 1: {
-                constexpr int G = 16;
-                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_T1);
-                hipLaunchKernelGGL((k_rate_lds<G, 7>), dim3(grid_for(ub, kBlock / G, 65536)), dim3(kBlock), 0,
-                                   c.stream, a);
+            case 1:
+                KMP_LAUNCH_TIMED(c, cls, (k_rate_lds<16, 7>), dim3(grid_for(ub, kBlock / 16, 65536)), dim3(kBlock), 0,
+                                 a);
                 break;
-            }
-            case 2: {
-                constexpr int G = 64;
-                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_T2);
-                hipLaunchKernelGGL((k_rate_lds<G, 10>), dim3(grid_for(ub, kBlock / G, 65536)), dim3(kBlock), 0,
-                                   c.stream, a);
+            case 2:
+                KMP_LAUNCH_TIMED(c, cls, (k_rate_lds<64, 10>), dim3(grid_for(ub, kBlock / 64, 65536)), dim3(kBlock),
+                                 0, a);
                 break;
-            }
-            case 3: {
-                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_T2);
-                hipLaunchKernelGGL((k_rate_lds<256, 13>), dim3(grid_for(ub, 1, 65536)), dim3(kBlock), 0, c.stream,
-                                   a);
+            case 3:
+                KMP_LAUNCH_TIMED(c, cls, (k_rate_lds<256, 13>), dim3(grid_for(ub, 1, 65536)), dim3(kBlock), 0, a);
                 break;
-            }
-            default: {
-                ProfScope ps(c, a.over ? KMP_PROF_BALANCE : KMP_PROF_RATE_HUB);
-                hipLaunchKernelGGL(k_rate_hub, dim3(grid_for(ub, 1, 4096)), dim3(kBlock), 0, c.stream, a);
+            default:
+                KMP_LAUNCH_TIMED(c, cls, k_rate_hub, dim3(grid_for(ub, 1, 4096)), dim3(kBlock), 0, a);
                 break;
-            }
         }
-        KMP_LAUNCH_CHECK();
     }
 }
 

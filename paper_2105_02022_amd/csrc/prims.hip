@@ -298,6 +298,15 @@ int Ctx::prof_begin(int cls)
     return (int)prof->recs.size() - 1;
 }
 
+bool Ctx::prof_pair(int cls, hipEvent_t& a, hipEvent_t& b)
+{
+    if (!prof || (prof->mask && !((prof->mask >> cls) & 1u))) return false;
+    a = take_event();
+    b = take_event();
+    prof->recs.push_back(Prof::Rec{cls, a, b});
+    return true;
+}
+
 void Ctx::prof_end(int idx)
 {
     if (!prof || idx < 0) return;
