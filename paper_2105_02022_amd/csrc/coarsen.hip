@@ -523,15 +523,29 @@ void two_hop_jobs(Ctx& c, const DGraph& g, const JobTabs& jt, const int64_t* gU,
     two_hop_core(c, g, jt, 0, 0, gU, glimit, gend, njobs, label, cw, fav, false);
 }
 
-void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
-              int32_t& cn, int64_t& cm, const JobTabs& jt, const uint8_t* gkeep)
+int32_t contract_ids(Ctx& c, const DGraph& g, const int64_t* cw, DBuf<int32_t>& cid, const JobTabs& jt,
+                     const uint8_t* gkeep)
 {
     const int32_t n = g.n;
-    DBuf<int32_t> cid(c, (size_t)n + 1);
+    cid = DBuf<int32_t>(c, (size_t)n + 1);
     hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, cw, n, jt.gid, gkeep, cid.p);
     KMP_LAUNCH_CHECK();
     scan_excl_i32(c, cid.p, cid.p, n, cid.p + n);
-    const int32_t nc = c.read1(cid.p + n);
+    return c.read1(cid.p + n);
+}
+
+void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
+              int32_t& cn, int64_t& cm, const JobTabs& jt, const uint8_t* gkeep, DBuf<int32_t>* cid_in, int32_t nc_in)
+{
+    const int32_t n = g.n;
+    DBuf<int32_t> cid_own;
+    int32_t nc;
+    if (cid_in) {
+        nc = nc_in;
+    } else {
+        nc = contract_ids(c, g, cw, cid_own, jt, gkeep);
+    }
+    DBuf<int32_t>& cid = cid_in ? *cid_in : cid_own;
     cn = nc;
     out.xadj = DBuf<int32_t>(c, (size_t)nc + 1);
     out.vwgt = DBuf<int32_t>(c, (size_t)nc);

@@ -384,21 +384,25 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
     DBuf<uint8_t> side(c, (size_t)n);
     int32_t calls = 0;
     if (n > 0) {
-        DBuf<int32_t> bstart(c, (size_t)nb + 1), bdeg(c, (size_t)nb);
-        fill_bytes_many(c, {{bstart.p, 4 * ((int64_t)nb + 1), 0}, {bdeg.p, 4 * (int64_t)nb, 0}});
+        // block starts (nb + 1) and degree sums (nb) in one buffer: one read-back
+        DBuf<int32_t> bsd(c, 2 * (size_t)nb + 1);
+        int32_t* bstart_p = bsd.p;
+        int32_t* bdeg_p = bsd.p + nb + 1;
+        fill_bytes_many(c, {{bsd.p, 4 * (2 * (int64_t)nb + 1), 0}});
         DBuf<uint32_t> key(c, n), verts(c, n), k2(c, n), v2(c, n);
         hipLaunchKernelGGL(k_block_count, dim3(grid_for(n, kBlock, 256)), dim3(kBlock), 0, c.stream, part, g.xadj, n, nb,
-                           bstart.p, bdeg.p, key.p, verts.p);
+                           bstart_p, bdeg_p, key.p, verts.p);
         KMP_LAUNCH_CHECK();
         radix_sort_pairs(c, key.p, verts.p, k2.p, v2.p, n, bits_for((uint64_t)(nb - 1)));
-        scan_excl_i32(c, bstart.p, bstart.p, nb, bstart.p + nb);
+        scan_excl_i32(c, bstart_p, bstart_p, nb, bstart_p + nb);
         DBuf<int32_t> local(c, (size_t)n);
-        hipLaunchKernelGGL(k_local_ids, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, verts.p, part, bstart.p, n,
+        hipLaunchKernelGGL(k_local_ids, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, verts.p, part, bstart_p, n,
                            local.p);
         KMP_LAUNCH_CHECK();
-        std::vector<int32_t> hb(nb + 1), hd(nb);
-        c.read(hb.data(), bstart.p, sizeof(int32_t) * (nb + 1));
-        c.read(hd.data(), bdeg.p, sizeof(int32_t) * nb);
+        std::vector<int32_t> hbd(2 * (size_t)nb + 1);
+        c.read(hbd.data(), bsd.p, sizeof(int32_t) * hbd.size());
+        const int32_t* hb = hbd.data();
+        const int32_t* hd = hbd.data() + nb + 1;
         std::vector<GGGJob> lds_jobs, glob_jobs;
         int64_t lds_max = 0, glob_total = 0;
         for (int32_t bb = 0; bb < nb; ++bb) {
@@ -431,7 +435,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         a.adjwgt = g.adjwgt;
         a.part = part;
         a.verts = verts.p;
-        a.bstart = bstart.p;
+        a.bstart = bstart_p;
         a.local = local.p;
         a.side = side.p;
         a.scratch = nullptr;

@@ -570,8 +570,10 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_cl += lps.moves[r];
         std::vector<int64_t> nc;
+        DBuf<int32_t> cid;  // one graph: the coarse ids, computed once for the test and the contraction
         if (!batch) {
             two_hop(c, g, U[0], label.p, cw.p, fav.p, false);
+            nc.assign(1, contract_ids(c, g, cw.p, cid));
         } else {
             count_nonempty_jobs(c, cw.p, g.n, jt, nj, nc);
             std::vector<int64_t> lim(nj, 0);
@@ -584,9 +586,9 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
             if (any) {
                 DBuf<int64_t> dlim = upload(c, lim);
                 two_hop_jobs(c, g, jt, dU.p, dlim.p, L.dgend.p, nj, label.p, cw.p, fav.p);
+                count_nonempty_jobs(c, cw.p, g.n, jt, nj, nc);
             }
         }
-        count_nonempty_jobs(c, cw.p, g.n, jt, batch ? nj : 1, nc);
         t.ms_lp += ms_since(t0);
         std::vector<uint8_t> keep(nj, 0);
         int32_t nkeep = 0;
@@ -607,7 +609,8 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         int64_t cm = 0;
         DBuf<uint8_t> dkeep;
         if (batch) dkeep = upload(c, keep);
-        contract(c, g, label.p, cw.p, L.map.p, next->own, cn, cm, jt, dkeep.p);
+        if (batch) contract(c, g, label.p, cw.p, L.map.p, next->own, cn, cm, jt, dkeep.p);
+        else contract(c, g, label.p, cw.p, L.map.p, next->own, cn, cm, jt, nullptr, &cid, (int32_t)nc[0]);
         next->g = next->own.view(cn, cm);
         next->nn.assign(nj, 0);
         next->mm.assign(nj, 0);

@@ -491,8 +491,15 @@ void count_nonempty_jobs(Ctx& c, const int64_t* cw, int32_t n, const JobTabs& jt
 // Contract; returns coarse sizes; allocates the coarse graph in `out`.
 // Batches: only nodes of jobs with gkeep[job] != 0 are contracted (the others
 // get map = -1); coarse ids stay grouped by job.
+// cid_in / nc_in: coarse ids and count from contract_ids, when the caller
+// already computed them (its convergence test needs the count first).
 void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
-              int32_t& cn, int64_t& cm, const JobTabs& jt = {}, const uint8_t* gkeep = nullptr);
+              int32_t& cn, int64_t& cm, const JobTabs& jt = {}, const uint8_t* gkeep = nullptr,
+              DBuf<int32_t>* cid_in = nullptr, int32_t nc_in = 0);
+// Coarse id of every non-empty label (exclusive prefix of the non-empty
+// flags, jobs with gkeep[job] == 0 excluded); returns their number.
+int32_t contract_ids(Ctx& c, const DGraph& g, const int64_t* cw, DBuf<int32_t>& cid, const JobTabs& jt = {},
+                     const uint8_t* gkeep = nullptr);
 
 // ---------------------------------------------------------------- IP (ip.hip)
 // Block table of a level: blocks in job order, ascending `first` inside a job.
