@@ -176,6 +176,15 @@ inline unsigned grid_for(int64_t items, int per_block = kBlock, unsigned cap = 0
     return (unsigned)g;
 }
 
+// Workgroup size for a launch of `items` one-per-lane gathers.  A gather-heavy
+// wave is limited by the L1 request rate of its compute unit, so launches of
+// fewer than 64 Ki items use narrower workgroups: their waves then spread over
+// all 256 compute units instead of stacking four to a unit on a few of them.
+inline int spread_block(int64_t items)
+{
+    return items >= 256 * 256 ? 256 : items >= 256 * 128 ? 128 : 64;
+}
+
 // ---------------------------------------------------------------- profiling
 // HIP events around launches of selected kernel classes (when enabled).
 struct Prof {

@@ -31,6 +31,7 @@ namespace kmp {
 namespace {
 
 constexpr int T0_DEG = 16, T1_DEG = 64, T2_DEG = 512, T3_DEG = 4096;
+constexpr int T0_NARROW = 8;  // tier-0 nodes of at most this degree are listed first
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 constexpr int kSmallCap = 4096;     // contended entries resolved on the device
 constexpr int kCandChunk = 1024;    // contended entries staged in LDS per pass
@@ -50,8 +51,9 @@ __device__ inline int tier_of(int32_t d)
 }
 
 // ---------------------------------------------------------------- schedule
-// key = tier * S + class; nodes of jobs that do not take part get key kSegs
-// (sorted behind every segment)
+// segment = tier * S + class; nodes of jobs that do not take part get segment
+// kSegs (sorted behind every segment).  The sort key is 2 * segment + (tier-0
+// node of degree > T0_NARROW).
 __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict__ xadj, int32_t n, uint32_t hsub,
                                                        JobTabs jt, const uint8_t* __restrict__ gpart, uint32_t level,
                                                        uint32_t* __restrict__ key, uint32_t* __restrict__ val,
@@ -71,8 +73,10 @@ __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict
             takes_part = !gpart || gpart[j];
         }
         const uint32_t s = hash_step(hs, vl, 3) % kSub;
-        const uint32_t k = takes_part ? (uint32_t)tier_of(xadj[v + 1] - xadj[v]) * kSub + s : (uint32_t)kSegs;
-        key[v] = k;
+        const int32_t d = xadj[v + 1] - xadj[v];
+        const uint32_t t = (uint32_t)tier_of(d);
+        const uint32_t k = takes_part ? t * kSub + s : (uint32_t)kSegs;
+        key[v] = 2 * k + (t == 0 && d > T0_NARROW ? 1u : 0u);  // narrow tier-0 nodes first in their segment
         val[v] = (uint32_t)v;
         atomicAdd(&h[k], 1);
     }
@@ -231,12 +235,74 @@ __device__ inline void flush_stats(const RateArgs& a, int64_t nodes, int64_t edg
     }
 }
 
-// Tier 0: one lane per node; labels and weights of the <= 16 neighbours live in
+// Tier 0: one lane per node; labels and weights of the <= DEG neighbours live in
 // registers.  Loads use clamped indices so that they are unconditional and the
 // compiler issues each batch (neighbour ids, labels, candidate weights) back to
 // back with a single wait; duplicates are merged into their first occurrence
 // with selects.  EW: edge weights present; CAPV: per-label caps; BAL: balance
 // mode.
+template <int DEG, bool EW, bool CAPV, bool BAL>
+__device__ inline void rate_lane_node(const RateArgs& a, int32_t v, uint32_t own, int32_t e0, int32_t d, int64_t cv,
+                                      const NodeKey& nk)
+{
+    uint32_t lab[DEG], w[DEG];
+    if (d > 0) {
+        int32_t u[DEG];
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) lab[j] = (uint32_t)a.label[u[j]];
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) w[j] = EW ? (uint32_t)a.adjwgt[e0 + (j < d ? j : d - 1)] : 1u;
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) {
+            lab[j] = j < d ? lab[j] : EMPTY;
+            w[j] = j < d ? w[j] : 0u;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) {
+            lab[j] = EMPTY;
+            w[j] = 0;
+        }
+    }
+#pragma unroll
+    for (int k = 1; k < DEG; ++k) {
+        bool dup = false;
+#pragma unroll
+        for (int q = 0; q < k; ++q) {
+            const bool hit = !dup && lab[k] != EMPTY && lab[q] == lab[k];
+            w[q] += hit ? w[k] : 0u;
+            dup = dup || hit;
+        }
+        lab[k] = dup ? EMPTY : lab[k];
+    }
+    // weight (and cap / overload flag) of every candidate, one batch of loads
+    int64_t wk[DEG];
+#pragma unroll
+    for (int j = 0; j < DEG; ++j) wk[j] = a.wt[lab[j] != EMPTY ? lab[j] : own];
+    int64_t ck[DEG];
+#pragma unroll
+    for (int j = 0; j < DEG; ++j) ck[j] = CAPV ? a.cap_vec[lab[j] != EMPTY ? lab[j] : own] : nk.cap;
+    bool ov[DEG];
+#pragma unroll
+    for (int j = 0; j < DEG; ++j) ov[j] = BAL ? a.over[lab[j] != EMPTY ? lab[j] : own] != 0 : false;
+    Key3 fav{0, 0, 0}, adm{0, 0, 0};
+    uint32_t rown = 0;
+#pragma unroll
+    for (int j = 0; j < DEG; ++j) {
+        const bool is_own = lab[j] == own;
+        rown = is_own ? w[j] : rown;
+        const bool cand = lab[j] != EMPTY && !is_own;
+        const Key3 c{w[j], hash_step(nk.hp, lab[j] - nk.lo, 4), lab[j]};
+        if (cand && better(c, fav)) fav = c;
+        if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
+    }
+    write_result(a, v, fav, adm, rown, cv);
+}
+
+// A tier-0 segment lists its nodes of degree <= T0_NARROW first, so most
+// wavefronts take the half-width body as a whole (a wave-uniform branch).
 template <bool EW, bool CAPV, bool BAL>
 __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
 {
@@ -256,60 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
         const int32_t d = a.xadj[v + 1] - e0;
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
         const NodeKey nk = node_key(a, v);
-        uint32_t lab[T0_DEG], w[T0_DEG];
-        if (d > 0) {
-            int32_t u[T0_DEG];
-#pragma unroll
-            for (int j = 0; j < T0_DEG; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
-#pragma unroll
-            for (int j = 0; j < T0_DEG; ++j) lab[j] = (uint32_t)a.label[u[j]];
-#pragma unroll
-            for (int j = 0; j < T0_DEG; ++j) w[j] = EW ? (uint32_t)a.adjwgt[e0 + (j < d ? j : d - 1)] : 1u;
-#pragma unroll
-            for (int j = 0; j < T0_DEG; ++j) {
-                lab[j] = j < d ? lab[j] : EMPTY;
-                w[j] = j < d ? w[j] : 0u;
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < T0_DEG; ++j) {
-                lab[j] = EMPTY;
-                w[j] = 0;
-            }
-        }
-#pragma unroll
-        for (int k = 1; k < T0_DEG; ++k) {
-            bool dup = false;
-#pragma unroll
-            for (int q = 0; q < k; ++q) {
-                const bool hit = !dup && lab[k] != EMPTY && lab[q] == lab[k];
-                w[q] += hit ? w[k] : 0u;
-                dup = dup || hit;
-            }
-            lab[k] = dup ? EMPTY : lab[k];
-        }
-        // weight (and cap / overload flag) of every candidate, one batch of loads
-        int64_t wk[T0_DEG];
-#pragma unroll
-        for (int j = 0; j < T0_DEG; ++j) wk[j] = a.wt[lab[j] != EMPTY ? lab[j] : own];
-        int64_t ck[T0_DEG];
-#pragma unroll
-        for (int j = 0; j < T0_DEG; ++j) ck[j] = CAPV ? a.cap_vec[lab[j] != EMPTY ? lab[j] : own] : nk.cap;
-        bool ov[T0_DEG];
-#pragma unroll
-        for (int j = 0; j < T0_DEG; ++j) ov[j] = BAL ? a.over[lab[j] != EMPTY ? lab[j] : own] != 0 : false;
-        Key3 fav{0, 0, 0}, adm{0, 0, 0};
-        uint32_t rown = 0;
-#pragma unroll
-        for (int j = 0; j < T0_DEG; ++j) {
-            const bool is_own = lab[j] == own;
-            rown = is_own ? w[j] : rown;
-            const bool cand = lab[j] != EMPTY && !is_own;
-            const Key3 c{w[j], hash_step(nk.hp, lab[j] - nk.lo, 4), lab[j]};
-            if (cand && better(c, fav)) fav = c;
-            if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
-        }
-        write_result(a, v, fav, adm, rown, cv);
+        if (ballot64(d > T0_NARROW)) rate_lane_node<T0_DEG, EW, CAPV, BAL>(a, v, own, e0, d, cv, nk);
+        else rate_lane_node<T0_NARROW, EW, CAPV, BAL>(a, v, own, e0, d, cv, nk);
         edges += d;
         nodes += 1;
     }
@@ -841,7 +855,7 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
                            (uint32_t)level, key.p, val.p, cnt.p);
         KMP_LAUNCH_CHECK();
     }
-    radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, bits_for(kSegs));
+    radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, bits_for(2 * kSegs + 1));
     KMP_HIP(hipMemcpyAsync(sched.order.p, val.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
     int32_t h[kSegs + 1];
     c.read(h, cnt.p, sizeof(h));
@@ -966,17 +980,18 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
                                         : KMP_PROF_RATE_HUB;
         switch (t) {
             case 0: {
-                const dim3 grid(grid_for(ub, kBlock, 65536));
+                const int bs = spread_block(ub);
+                const dim3 grid(grid_for(ub, bs, 65536)), block(bs);
                 const bool ew = a.adjwgt != nullptr;
                 if (a.over) {
-                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, true>), grid, dim3(kBlock), 0, a);
-                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, true>), grid, dim3(kBlock), 0, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, true>), grid, block, 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, true>), grid, block, 0, a);
                 } else if (a.cap_vec) {
-                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, false>), grid, dim3(kBlock), 0, a);
-                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, false>), grid, dim3(kBlock), 0, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, false>), grid, block, 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, false>), grid, block, 0, a);
                 } else {
-                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, false, false>), grid, dim3(kBlock), 0, a);
-                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, false, false>), grid, dim3(kBlock), 0, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, false, false>), grid, block, 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, false, false>), grid, block, 0, a);
                 }
                 break;
             }
@@ -1016,7 +1031,8 @@ void launch_admit(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, co
     const int32_t ub = class_ub(ubs, s);
     if (ub == 0) return;
     ProfScope ps(c, KMP_PROF_ADMIT);
-    hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list,
+    const int bs = spread_block(ub);
+    hipLaunchKernelGGL(k_admit_fast, dim3(grid_for(ub, bs, 8192)), dim3(bs), 0, c.stream, b.ctl.p, list,
                        segtab, s, b.prop.p, b.demand.p, st.wt, cap_args(st), b.acc.p, b.ckeys.p, b.cvals.p,
                        b.base.p, CTL_CONT + (s & 1));
     KMP_LAUNCH_CHECK();
@@ -1028,7 +1044,8 @@ void launch_apply(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, co
     const int32_t ub = class_ub(ubs, s);
     if (ub == 0) return;
     ProfScope ps(c, KMP_PROF_APPLY);
-    hipLaunchKernelGGL(k_apply, dim3(grid_for(ub, kBlock, 8192)), dim3(kBlock), 0, c.stream, b.ctl.p, list, segtab,
+    const int bs = spread_block(ub);
+    hipLaunchKernelGGL(k_apply, dim3(grid_for(ub, bs, 8192)), dim3(bs), 0, c.stream, b.ctl.p, list, segtab,
                        s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, mflag, stamp, ms, b.ckeys.p,
                        b.cvals.p, b.base.p, cap_args(st), CTL_CONT + (s & 1));
     KMP_LAUNCH_CHECK();
