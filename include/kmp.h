@@ -60,7 +60,10 @@ typedef struct kmp_options {
     int32_t profile;        /* 1: time kernel classes with HIP events (fills kmp_stats.prof_*);
                                2: also synchronise at phase boundaries for the ms_* phase timers */
     uint32_t profile_classes; /* bit i set: time class i only (fewer event records); 0: all classes */
-    int32_t reserved[5];
+    int32_t force_exact;    /* 1: every LP sub-round with a contended proposal takes the host-synchronised
+                               exact admission path (by default only sub-rounds with more than 4096
+                               contended proposals do).  The output does not depend on it. */
+    int32_t reserved[4];
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */
@@ -92,7 +95,7 @@ typedef struct kmp_stats {
     int32_t levels;                         /* number of contractions L                  */
     int32_t bipartitions;                   /* number of bipartitioned blocks (GGG calls) */
     int32_t balance_rounds;
-    int32_t reserved0;
+    int32_t lp_exact_subrounds;             /* LP sub-rounds finished on the exact admission path */
     int32_t level_n[KMP_MAX_LEVELS + 1];    /* nodes per level                           */
     int64_t level_m[KMP_MAX_LEVELS + 1];    /* directed entries per level                */
     int64_t lp_cluster_moves;

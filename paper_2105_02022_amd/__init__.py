@@ -28,13 +28,13 @@ PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "
 
 class KmpOptions(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
-                ("reserved", ctypes.c_int32 * 5)]
+                ("force_exact", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class KmpStats(ctypes.Structure):
     _fields_ = [("cut", ctypes.c_int64), ("lk", ctypes.c_int64), ("max_block_weight", ctypes.c_int64),
                 ("levels", ctypes.c_int32), ("bipartitions", ctypes.c_int32), ("balance_rounds", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32), ("level_n", ctypes.c_int32 * (MAX_LEVELS + 1)),
+                ("lp_exact_subrounds", ctypes.c_int32), ("level_n", ctypes.c_int32 * (MAX_LEVELS + 1)),
                 ("level_m", ctypes.c_int64 * (MAX_LEVELS + 1)), ("lp_cluster_moves", ctypes.c_int64),
                 ("lp_refine_moves", ctypes.c_int64), ("lp_rated_edges", ctypes.c_int64),
                 ("contracted_edges", ctypes.c_int64), ("ms_total", ctypes.c_double),
@@ -161,9 +161,9 @@ def kmp_partition(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, see
 
 def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
                      stream=None, validate: bool = False, profile: bool = False,
-                     profile_classes=None) -> Tuple[int, "torch.Tensor", Dict]:
+                     profile_classes=None, force_exact: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
-    (None: all)."""
+    (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -172,6 +172,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt = KmpOptions()
     opt.validate = int(validate)
     opt.profile = int(profile)
+    opt.force_exact = int(force_exact)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -195,7 +196,7 @@ def _stats_dict(st: "KmpStats", profile: bool) -> Dict:
 
 
 def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool = False,
-                        profile_classes=None) -> Tuple[int, List[Dict], Dict]:
+                        profile_classes=None, force_exact: bool = False) -> Tuple[int, List[Dict], Dict]:
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
@@ -206,6 +207,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     opt = KmpOptions()
     opt.validate = int(validate)
     opt.profile = int(profile)
+    opt.force_exact = int(force_exact)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()

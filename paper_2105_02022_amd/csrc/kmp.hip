@@ -318,7 +318,7 @@ struct Level {
 
 struct Totals {
     int64_t moves_cl = 0, moves_ref = 0, rated = 0, contracted = 0;
-    int32_t bip = 0, brounds = 0;
+    int32_t bip = 0, brounds = 0, exact = 0;
     double ms_lp = 0, ms_con = 0, ms_ip = 0, ms_ref = 0;
 };
 
@@ -569,6 +569,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
                    batch ? L.dnoff.p : nullptr, batch ? dU.p : nullptr};
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_cl += lps.moves[r];
+        t.exact += lps.exact_subrounds;
         std::vector<int64_t> nc;
         DBuf<int32_t> cid;  // one graph: the coarse ids, computed once for the test and the contraction
         if (!batch) {
@@ -728,6 +729,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF, jt, dboff.p, nullptr};
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_ref += lps.moves[r];
+        t.exact += lps.exact_subrounds;
         if (phase_sync) c.sync();
         t.ms_ref += ms_since(t2) + (ms_since(t0) - ms_since(t1));
         // the coarser level is no longer needed
@@ -792,6 +794,7 @@ void fill_stats(kmp_stats* st, const JobRun& jb, const Totals& t)
     }
     st->bipartitions = t.bip;
     st->balance_rounds = t.brounds;
+    st->lp_exact_subrounds = t.exact;
     st->lp_cluster_moves = t.moves_cl;
     st->lp_refine_moves = t.moves_ref;
     st->lp_rated_edges = t.rated;
@@ -814,6 +817,7 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
         prof->mask = opt->profile_classes;
         c.prof = prof.get();
     }
+    c.force_exact = opt && opt->force_exact;
     std::vector<JobRun> jobs(1);
     JobRun& jb = jobs[0];
     jb.g = g0;
@@ -851,6 +855,7 @@ int partition_batch_impl(const kmp_graph_desc* gd, int32_t count, kmp_job_result
         prof->mask = opt->profile_classes;
         c.prof = prof.get();
     }
+    c.force_exact = opt && opt->force_exact;
     std::vector<JobRun> jobs(count);
     for (int32_t i = 0; i < count; ++i) {
         JobRun& jb = jobs[i];

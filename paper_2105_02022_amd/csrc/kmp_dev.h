@@ -277,6 +277,7 @@ class Ctx {
     int64_t read_spread(int idx);
 
     Prof* prof = nullptr;  // profiling enabled when non-null
+    bool force_exact = false;  // LP: contended sub-rounds take the exact path
     int prof_begin(int cls);
     void prof_end(int idx);
     // Events for one launch of class cls (false: not timed).  The caller
@@ -441,6 +442,7 @@ struct LPState {
 
 struct LPStats {
     int64_t moves[kRounds] = {0, 0, 0, 0, 0};
+    int32_t exact_subrounds = 0;  // sub-rounds finished on the exact admission path
     int32_t rounds = 0;
 };
 

@@ -38,12 +38,12 @@ constexpr int kCandChunk = 1024;    // contended entries staged in LDS per pass
 
 // ctl[] layout (int64, device): round control shared by the kernels (the
 // contended-list length alternates between CTL_CONT and CTL_CONT + 1 by
-// sub-round parity, so that each apply clears the next one's), then two
-// sets of kSpreadSlots per-block move counts (CTL_MS, used by alternate rounds
-// so that each round clears the next one's set on the device), then the two
-// segment tables of the compacted lists (read back together once per round)
-enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_CONT = 3, CTL_N = 8, CTL_MS = CTL_N };
-constexpr int kCtlWords = CTL_N + 2 * kSpreadSlots + 2 * kSegs;  // int64 words
+// sub-round parity, so that each apply clears the next one's; an abort records
+// its round stamp and sub-round), then one set of kSpreadSlots per-block move
+// counts per round (CTL_MS + r * kSpreadSlots), then the two segment tables of
+// the compacted lists (used by alternate rounds)
+enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_ABORT_STAMP = 2, CTL_CONT = 3, CTL_N = 8, CTL_MS = CTL_N };
+constexpr int kCtlWords = CTL_N + kRounds * kSpreadSlots + 2 * kSegs;  // int64 words
 
 __device__ inline int tier_of(int32_t d)
 {
@@ -667,17 +667,19 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
                                                   uint8_t* __restrict__ mflag, uint8_t stamp, int ms,
                                                   const uint32_t* __restrict__ ckeys,
                                                   const uint32_t* __restrict__ cvals,
-                                                  const int64_t* __restrict__ wsnap, CapArgs caps, int cont_idx)
+                                                  const int64_t* __restrict__ wsnap, CapArgs caps, int cont_idx,
+                                                  int64_t small_cap)
 {
     __shared__ int32_t bm;
     __shared__ uint64_t s_kv[kCandChunk];  // (target << 32) | id
     __shared__ int32_t s_w[kCandChunk];
     if (ctl[CTL_ABORT]) return;
     const int64_t C = ctl[cont_idx];
-    if (C > kSmallCap) {
+    if (C > small_cap) {
         if (blockIdx.x == 0 && threadIdx.x == 0) {
             ctl[CTL_ABORT] = 1;
             ctl[CTL_ABORT_SUB] = s;
+            ctl[CTL_ABORT_STAMP] = stamp;
         }
         return;
     }
@@ -751,23 +753,22 @@ struct SegBounds {
 // the segment of the round's lists.  The segment's degree tier picks the width
 // that walks a node's neighbours: one lane (degree <= 64), one wavefront
 // (<= 4096) or the whole workgroup (hubs).  Block (0, 0) also resets the next
-// round's segment table (offsets = the schedule's, counts 0) and move-count set.
-__global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restrict__ list,
+// round's segment table (offsets = the schedule's, counts 0).  Nothing happens
+// after an abort (the host redoes this step once the round is finished).
+__global__ __launch_bounds__(kBlock) void k_push_active(const int64_t* __restrict__ ctl,
+                                                        const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ segtab,
                                                         const uint8_t* __restrict__ mflag, uint8_t stamp,
                                                         const int32_t* __restrict__ xadj,
                                                         const int32_t* __restrict__ adjncy,
                                                         uint8_t* __restrict__ active, SegBounds b,
-                                                        int32_t* __restrict__ next_segtab,
-                                                        int64_t* __restrict__ next_moves)
+                                                        int32_t* __restrict__ next_segtab)
 {
+    if (ctl[CTL_ABORT]) return;
     const int seg = blockIdx.y;
-    if (blockIdx.x == 0 && seg == 0) {
-        if (threadIdx.x < kSegs) {
-            next_segtab[threadIdx.x] = b.off[threadIdx.x];
-            next_segtab[kSegs + threadIdx.x] = 0;
-        }
-        if (threadIdx.x < kSpreadSlots) next_moves[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && seg == 0 && threadIdx.x < kSegs) {
+        next_segtab[threadIdx.x] = b.off[threadIdx.x];
+        next_segtab[kSegs + threadIdx.x] = 0;
     }
     const int tier = seg / kSub;
     const int32_t off = segtab[seg], cnt = segtab[kSegs + seg];
@@ -797,12 +798,14 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int32_t* __restric
 // same segment region of `alist`; counts go to next_segtab[kSegs + seg].  The
 // order inside a segment is free (results do not depend on it), so each block
 // reserves its slots with one atomic.
-__global__ __launch_bounds__(kBlock) void k_active_append(const int32_t* __restrict__ order, SegBounds b,
+__global__ __launch_bounds__(kBlock) void k_active_append(const int64_t* __restrict__ ctl,
+                                                          const int32_t* __restrict__ order, SegBounds b,
                                                           const uint8_t* __restrict__ active, uint8_t stamp,
                                                           int32_t* __restrict__ alist,
                                                           int32_t* __restrict__ next_segtab)
 {
     __shared__ int32_t s_cnt, s_base;
+    if (ctl[CTL_ABORT]) return;
     const int seg = blockIdx.y;
     const int32_t lo = b.off[seg], hi = b.off[seg + 1];
     for (int64_t i0 = lo + (int64_t)xcd_block() * kBlock; i0 < hi; i0 += (int64_t)gridDim.x * kBlock) {
@@ -1047,7 +1050,8 @@ void launch_apply(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, co
     const int bs = spread_block(ub);
     hipLaunchKernelGGL(k_apply, dim3(grid_for(ub, bs, 8192)), dim3(bs), 0, c.stream, b.ctl.p, list, segtab,
                        s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, mflag, stamp, ms, b.ckeys.p,
-                       b.cvals.p, b.base.p, cap_args(st), CTL_CONT + (s & 1));
+                       b.cvals.p, b.base.p, cap_args(st), CTL_CONT + (s & 1),
+                       (int64_t)(c.force_exact ? 0 : kSmallCap));
     KMP_LAUNCH_CHECK();
 }
 
@@ -1135,8 +1139,8 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     DBuf<uint8_t>& active = b.active;
     DBuf<int32_t> alist0(c, (size_t)n), alist1(c, (size_t)n);
     int32_t* alist[2] = {alist0.p, alist1.p};
-    int32_t* segtab_r[2] = {reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + 2 * kSpreadSlots),
-                            reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + 2 * kSpreadSlots) + 2 * kSegs};
+    int32_t* segtab_r[2] = {reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kRounds * kSpreadSlots),
+                            reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kRounds * kSpreadSlots) + 2 * kSegs};
     SegBounds bounds;
     for (int j = 0; j <= kSegs; ++j) bounds.off[j] = sched.off[j];
     int32_t ub[kSegs];
@@ -1151,17 +1155,16 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         }
         const uint8_t stamp = (uint8_t)(r + 1);
         ProfScope ps(c, KMP_PROF_ACTIVE);
-        hipLaunchKernelGGL(k_push_active, dim3(grid_for(mx, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream, list,
-                           segtab, b.mflag.p, stamp, g.xadj, g.adjncy, active.p, bounds, segtab_r[q],
-                           b.ctl.p + CTL_MS + ((r + 1) & 1) * kSpreadSlots);
+        hipLaunchKernelGGL(k_push_active, dim3(grid_for(mx, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream, b.ctl.p,
+                           list, segtab, b.mflag.p, stamp, g.xadj, g.adjncy, active.p, bounds, segtab_r[q]);
         KMP_LAUNCH_CHECK();
         hipLaunchKernelGGL(k_active_append, dim3(grid_for(mseg, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream,
-                           sched.order.p, bounds, active.p, stamp, alist[q], segtab_r[q]);
+                           b.ctl.p, sched.order.p, bounds, active.p, stamp, alist[q], segtab_r[q]);
         KMP_LAUNCH_CHECK();
     };
     struct {
         int64_t ctl[CTL_N];
-        int64_t moved[2][kSpreadSlots];
+        int64_t moved[kRounds][kSpreadSlots];
         int32_t seg[2][2 * kSegs];
     } h;
     static_assert(sizeof(h) == sizeof(int64_t) * kCtlWords, "control block layout");
@@ -1169,7 +1172,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         out.rounds = r + 1;
         const int cur = r & 1, nxt = cur ^ 1;
         const uint8_t stamp = (uint8_t)(r + 1);
-        const int ms = CTL_MS + cur * kSpreadSlots;  // this round's move-count set (cleared by the previous round)
+        const int ms = CTL_MS + r * kSpreadSlots;  // this round's move-count set
         const int32_t* list = r == 0 ? sched.order.p : alist[cur];
         const int32_t* segtab = r == 0 ? sched.segtab.p : segtab_r[cur];
         RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
@@ -1186,17 +1189,20 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         c.read(&h, b.ctl.p, sizeof(h));
         if (h.ctl[CTL_ABORT]) {
             // finish the round on the exact path from the aborted sub-round on
-            // (the current lists are untouched: the next round writes the other buffer)
+            // (the next round's list building did nothing; the current lists are
+            // untouched: the next round writes the other buffer)
             const int32_t s0 = (int32_t)h.ctl[CTL_ABORT_SUB];
+            if (h.ctl[CTL_ABORT_STAMP] != stamp) throw Error(KMP_EHIP, "LP abort recorded for an unexpected round");
             ctl_set(c, b, CTL_ABORT, 0);
             subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp, ms);
             for (int32_t s = s0 + 1; s < kSub; ++s)
                 subround_exact(c, g, sched, s, list, segtab, ub, st, b, a, true, b.mflag.p, stamp, ms);
             if (more) enqueue_next_lists(r, list, segtab, nxt);
             c.read(&h, b.ctl.p, sizeof(h));
+            out.exact_subrounds += kSub - s0;
         }
         int64_t nm = 0;
-        for (int q = 0; q < kSpreadSlots; ++q) nm += h.moved[cur][q];
+        for (int q = 0; q < kSpreadSlots; ++q) nm += h.moved[r][q];
         out.moves[r] = nm;
         if (nm == 0 || !more) break;
         // the next round's lists are exactly sized

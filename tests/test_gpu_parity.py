@@ -317,6 +317,29 @@ def test_partition_hubs(kmp, gi, k):
     _e2e(kmp, g, k, 0.03, 5, name)
 
 
+@pytest.mark.parametrize("name,k,seed", [("grid128", 8, 1), ("rgg20000", 64, 1), ("rand_w", 7, 9), ("hubs", 8, 5)])
+def test_partition_forced_exact_path(kmp, name, k, seed):
+    """Every LP sub-round with a contended proposal stops on the device and is finished on the
+    host-synchronised exact path (while the next round is already queued); the output must not
+    change."""
+    g = {"grid128": lambda: gen.grid(128, 128), "rgg20000": lambda: gen.rgg(20000, 8.0, 2),
+         "rand_w": lambda: gen.random_graph(5000, 5.0, 7, max_vw=4, max_ew=6),
+         "hubs": lambda: hub_graphs()[0][1]}[name]()
+    say(f"[partition, exact path forced] {name} n={g.n} k={k} seed={seed}")
+    ref = oracle.partition(g, k, 0.03, seed)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, seed, force_exact=True)
+    say(f"  exact sub-rounds: {stats['lp_exact_subrounds']}")
+    assert rc == ref.status
+    assert np.array_equal(part.cpu().numpy(), ref.part)
+    assert stats["cut"] == ref.stats["cut"] and stats["level_n"] == ref.stats["level_n"]
+    assert stats["lp_cluster_moves"] == ref.stats["lp_cluster_moves"]
+    assert stats["lp_refine_moves"] == ref.stats["lp_refine_moves"]
+    assert stats["lp_exact_subrounds"] > 0
+    _, _, plain = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, seed)
+    assert plain["lp_exact_subrounds"] < stats["lp_exact_subrounds"]
+
+
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
@@ -359,8 +382,8 @@ def _batch_jobs(specs):
     return jobs
 
 
-def _check_batch_against_oracle(kmp, jobs, skip=()):
-    rc, res, _ = kmp.kmp_partition_batch(jobs)
+def _check_batch_against_oracle(kmp, jobs, skip=(), **kw):
+    rc, res, _ = kmp.kmp_partition_batch(jobs, **kw)
     assert rc == kmp.KMP_OK
     for j, r in zip(jobs, res):
         if j["name"] in skip:
@@ -393,6 +416,18 @@ def test_batch_mixed_jobs(kmp):
     ]
     say(f"[batch] {len(specs)} mixed jobs")
     _check_batch_against_oracle(kmp, _batch_jobs(specs))
+
+
+def test_batch_forced_exact_path(kmp):
+    """The batch pass with the exact admission path forced for every contended sub-round."""
+    specs = [
+        ("grid64x40", gen.grid(64, 40), 8, 0.03, 3),
+        ("rgg5000", gen.rgg(5000, 8.0, 7), 16, 0.03, 0),
+        ("rand_w", gen.random_graph(3000, 5.0, 5, max_vw=4, max_ew=6), 5, 0.05, 9),
+        ("tiny", gen.grid(2, 3), 8, 0.03, 1),
+    ]
+    say(f"[batch, exact path forced] {len(specs)} jobs")
+    _check_batch_against_oracle(kmp, _batch_jobs(specs), force_exact=True)
 
 
 def test_batch_errors_and_empty_jobs(kmp):
