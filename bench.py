@@ -178,10 +178,11 @@ def batched_comparison(kmp, gen, torch, count, reps):
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_rgg20.md")
 
 # kernel classes whose launches count algorithmic bytes (LP rating tiers, contraction rows)
-BYTE_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "contract_rows"]
+BYTE_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "lp_small", "contract_rows"]
 
 # profiling class -> kernel family, where every launch of the class is a launch of that family
-KERNEL_OF_CLASS = {"rate_t0": "k_rate_lane", "rate_hub": "k_rate_hub", "contract_rows": "k_contract_rows"}
+KERNEL_OF_CLASS = {"rate_t0": "k_rate_lane", "rate_hub": "k_rate_hub", "lp_small": "k_lp_small",
+                   "contract_rows": "k_contract_rows"}
 
 
 def traffic_from_profiles(family):

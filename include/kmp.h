@@ -62,8 +62,12 @@ typedef struct kmp_options {
     uint32_t profile_classes; /* bit i set: time class i only (fewer event records); 0: all classes */
     int32_t force_exact;    /* 1: every LP sub-round with a contended proposal takes the host-synchronised
                                exact admission path (by default only sub-rounds with more than 4096
-                               contended proposals do).  The output does not depend on it. */
-    int32_t reserved[4];
+                               contended proposals do); implies small_level_n = -1.  The output does not
+                               depend on it. */
+    int32_t small_level_n;  /* LP calls on levels of at most this many nodes (and no node of degree > 64)
+                               run in one workgroup launch: 0 = default (8192), -1 = never.  The output
+                               does not depend on it. */
+    int32_t reserved[3];
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */
@@ -75,7 +79,7 @@ enum {
     KMP_PROF_RATE_HUB = 3,     /* LP rating, degree > 4096 (global hash)              */
     KMP_PROF_ADMIT = 4,        /* admission of uncontended targets                    */
     KMP_PROF_APPLY = 5,        /* apply admitted moves                                */
-    KMP_PROF_CONTENDED = 6,    /* in-LDS sort + prefix admission of contended targets */
+    KMP_PROF_LP_SMALL = 6,     /* whole LP call of a small level in one workgroup     */
     KMP_PROF_ACTIVE = 7,       /* next-round active set                               */
     KMP_PROF_CONTRACT_ROWS = 8,/* contraction: LDS aggregation of coarse rows         */
     KMP_PROF_CONTRACT = 9,     /* contraction: relabel, bucketing, heavy rows, copy   */
@@ -109,9 +113,10 @@ typedef struct kmp_stats {
     double ms_refine;                       /* balance + refinement + projection          */
     /* filled when kmp_options.profile is set: per kernel class, the number of
      * launches, the summed HIP-event duration of those launches and, for the
-     * LP rating and contraction-row classes, their algorithmic bytes (bytes
-     * the algorithm must move: rating 25 B per rated node + 12 B per rated
-     * directed entry, 8 B when edge weights are unit; contraction rows 12 B
+     * LP rating, one-workgroup LP and contraction-row classes, their
+     * algorithmic bytes (bytes the algorithm must move: rating 25 B per rated
+     * node + 12 B per rated directed entry, 8 B when edge weights are unit;
+     * the one-workgroup LP counts its rating bytes only; contraction rows 12 B
      * per fine entry + 12 B per member node + 8 B per coarse entry + 16 B per
      * coarse row). */
     int64_t prof_launches[KMP_PROF_CLASSES];

@@ -22,13 +22,13 @@ KMP_OK, KMP_IMBALANCED, KMP_EINVAL, KMP_EGRAPH, KMP_EOVERFLOW, KMP_ENOMEM, KMP_E
 MAX_LEVELS = 64
 
 
-PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "contended", "active",
+PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "lp_small", "active",
                 "contract_rows", "contract", "two_hop", "ggg", "balance", "project", "schedule", "other"]
 
 
 class KmpOptions(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
-                ("force_exact", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("force_exact", ctypes.c_int32), ("small_level_n", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class KmpStats(ctypes.Structure):
@@ -161,9 +161,11 @@ def kmp_partition(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, see
 
 def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
                      stream=None, validate: bool = False, profile: bool = False,
-                     profile_classes=None, force_exact: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+                     profile_classes=None, force_exact: bool = False,
+                     small_level_n: int = 0) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
-    (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path."""
+    (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path.
+    `small_level_n`: largest level run by the one-workgroup LP (0 default, -1 never)."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -173,6 +175,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt.validate = int(validate)
     opt.profile = int(profile)
     opt.force_exact = int(force_exact)
+    opt.small_level_n = int(small_level_n)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -196,7 +199,8 @@ def _stats_dict(st: "KmpStats", profile: bool) -> Dict:
 
 
 def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool = False,
-                        profile_classes=None, force_exact: bool = False) -> Tuple[int, List[Dict], Dict]:
+                        profile_classes=None, force_exact: bool = False,
+                        small_level_n: int = 0) -> Tuple[int, List[Dict], Dict]:
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
@@ -208,6 +212,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     opt.validate = int(validate)
     opt.profile = int(profile)
     opt.force_exact = int(force_exact)
+    opt.small_level_n = int(small_level_n)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()

@@ -277,7 +277,8 @@ class Ctx {
     int64_t read_spread(int idx);
 
     Prof* prof = nullptr;  // profiling enabled when non-null
-    bool force_exact = false;  // LP: contended sub-rounds take the exact path
+    bool force_exact = false;    // LP: contended sub-rounds take the exact path
+    int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0 default, < 0 never)
     int prof_begin(int cls);
     void prof_end(int idx);
     // Events for one launch of class cls (false: not timed).  The caller
@@ -452,7 +453,8 @@ constexpr int kTiers = 5;
 constexpr int kSegs = kTiers * kSub;
 
 struct LPSchedule {
-    DBuf<int32_t> order;              // node ids grouped by (tier, class), ascending id inside a segment
+    DBuf<int32_t> order;              // node ids grouped by (tier, class); ascending id inside a segment,
+                                      // except that tier-0 segments list degrees <= 8 first
     int32_t off[kSegs + 1] = {};      // segment start in `order`; off[kSegs] = scheduled nodes
     int32_t cnt[kSegs] = {};          // segment size
     DBuf<int32_t> segtab;             // device copy: [kSegs offsets][kSegs counts]

@@ -830,6 +830,189 @@ __global__ void k_ctl_set(int64_t* ctl, int idx, int64_t v)
     if (threadIdx.x == 0) ctl[idx] = v;
 }
 
+// ---------------------------------------------------------------- small levels
+// Every round and sub-round of one LP call on a small level in a single
+// workgroup.  The steps of a sub-round (rate, admit at the sub-round start
+// weights, decide contended targets, apply) are separated by workgroup
+// barriers instead of kernel launches, so the whole call costs one launch and
+// one read-back.  The next round's active set is marked while moves are
+// applied, in the stamp array of the next round's parity (the marks never hide
+// a node's stamp for the current round).  Levels run here only if every node
+// has degree <= T1_DEG: tier-0 nodes are rated one per lane as in k_rate_lane,
+// tier-1 nodes one per wavefront with a 2^7-slot LDS table.  All global
+// accesses stay inside one workgroup, which the workgroup-scope fences of the
+// barriers order.
+constexpr int kSmallBlock = 1024;
+constexpr int32_t kSmallLevelN = 8192;  // default largest level (nodes) run in one workgroup
+
+struct SmallLP {
+    RateArgs a;               // graph, caps, prop, demand, fav, counters; hpre / round set per round
+    int32_t* label;           // [n]
+    int64_t* wt;              // [nlab]
+    const int32_t* order;     // schedule: node ids by segment
+    int32_t off[2 * kSub];    // tier t (0, 1), class s: segment start order[off[t * S + s]]
+    int32_t cnt[2 * kSub];
+    uint32_t hpre[kRounds];   // H prefix over (seed; tag, level, round) of every round
+    uint8_t* act[2];          // active stamps by round parity (zeroed)
+    uint8_t* acc;             // [n] zeroed
+    uint32_t* ckeys;          // [n] contended (target, id)
+    uint32_t* cvals;
+    int64_t* wsnap;           // [nlab] start weight of contended targets
+    CapArgs caps;
+    int64_t* out;             // [kRounds] moves per round, [kRounds] rounds run (zeroed)
+};
+
+template <bool EW, bool CAPV>
+__global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
+{
+    constexpr int HB = 7, HS = 1 << HB, NW = kSmallBlock / 64;
+    __shared__ uint32_t s_keys[NW * HS];
+    __shared__ uint32_t s_vals[NW * HS];
+    __shared__ uint64_t s_kv[kCandChunk];  // (target << 32) | id
+    __shared__ int32_t s_w[kCandChunk];
+    __shared__ int32_t s_cont, s_moves;
+    RateArgs a = p.a;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint32_t* keys = s_keys + wv * HS;
+    uint32_t* vals = s_vals + wv * HS;
+    int64_t edges = 0, nodes = 0;
+    int32_t rounds = kRounds;
+    for (int32_t r = 0; r < kRounds; ++r) {
+        a.hpre = p.hpre[r];
+        a.round = (uint32_t)r;
+        const uint8_t* act = p.act[r & 1];
+        uint8_t* act_next = p.act[(r + 1) & 1];
+        const uint8_t stamp = (uint8_t)(r + 1), stamp_next = (uint8_t)(r + 2);
+        if (tid == 0) s_moves = 0;
+        for (int s = 0; s < kSub; ++s) {
+            const int32_t o0 = p.off[s], c0 = p.cnt[s], o1 = p.off[kSub + s], c1 = p.cnt[kSub + s];
+            // rate, tier 0: one lane per node
+            for (int32_t i = tid; i < c0; i += kSmallBlock) {
+                const int32_t v = p.order[o0 + i];
+                if (r > 0 && act[v] != stamp) continue;
+                const uint32_t own = (uint32_t)p.label[v];
+                const int32_t e0 = a.xadj[v];
+                const int32_t d = a.xadj[v + 1] - e0;
+                const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
+                const NodeKey nk = node_key(a, v);
+                if (ballot64(d > T0_NARROW)) rate_lane_node<T0_DEG, EW, CAPV, false>(a, v, own, e0, d, cv, nk);
+                else rate_lane_node<T0_NARROW, EW, CAPV, false>(a, v, own, e0, d, cv, nk);
+                edges += d;
+                nodes += 1;
+            }
+            // rate, tier 1: one wavefront per node (the loop is uniform in the wave)
+            for (int32_t i = wv; i < c1; i += NW) {
+                const int32_t v = p.order[o1 + i];
+                if (r > 0 && act[v] != stamp) continue;
+                for (int j = lane; j < HS; j += 64) {
+                    keys[j] = EMPTY;
+                    vals[j] = 0;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
+                for (int32_t e = e0 + lane; e < e1; e += 64)
+                    lds_insert(keys, vals, HB, (uint32_t)p.label[a.adjncy[e]], EW ? (uint32_t)a.adjwgt[e] : 1u);
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                const uint32_t own = (uint32_t)p.label[v];
+                const NodeKey nk = node_key(a, v);
+                const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
+                Key3 fav{0, 0, 0}, adm{0, 0, 0};
+                uint32_t rown = 0;
+                for (int j = lane; j < HS; j += 64) consider(a, nk, keys[j], vals[j], own, cv, fav, adm, rown);
+                fav = group_best<64>(fav);
+                adm = group_best<64>(adm);
+#pragma unroll
+                for (int dd = 32; dd > 0; dd >>= 1) rown += __shfl_xor(rown, dd, 64);
+                if (lane == 0) {
+                    write_result(a, v, fav, adm, rown, cv);
+                    edges += e1 - e0;
+                    nodes += 1;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                __builtin_amdgcn_wave_barrier();  // the table is cleared for the next node only after every read
+            }
+            if (tid == 0) s_cont = 0;
+            __syncthreads();
+            // admission at the sub-round start weights (no weight changes until the apply step)
+            const int32_t total = c0 + c1;
+            for (int32_t i = tid; i < total; i += kSmallBlock) {
+                const int32_t v = p.order[i < c0 ? o0 + i : o1 + (i - c0)];
+                const int32_t K = a.prop[v];
+                if (K < 0) continue;
+                const int64_t wK = p.wt[K];
+                if (wK + (int64_t)a.demand[K] <= cap_for(p.caps, (uint32_t)K, (uint32_t)v)) {
+                    p.acc[v] = 1;
+                } else {
+                    p.acc[v] = 2;
+                    p.wsnap[K] = wK;  // every proposal into K writes the same value
+                    const int32_t slot = atomicAdd(&s_cont, 1);
+                    p.ckeys[slot] = (uint32_t)K;
+                    p.cvals[slot] = (uint32_t)v;
+                }
+            }
+            __syncthreads();
+            const int32_t C = s_cont;
+            // contended targets: the longest prefix in id order that fits; then apply
+            // the admitted moves and mark the neighbours of moved nodes for round r + 1
+            for (int32_t i0 = 0; i0 < total; i0 += kSmallBlock) {
+                const int32_t i = i0 + tid;
+                int32_t v = -1, K = -1;
+                uint8_t ac = 0;
+                if (i < total) {
+                    v = p.order[i < c0 ? o0 + i : o1 + (i - c0)];
+                    K = a.prop[v];
+                    if (K >= 0) ac = p.acc[v];
+                }
+                const bool contended = ac == 2;
+                if (C > 0 && __syncthreads_or(contended)) {
+                    int64_t pre = 0;
+                    for (int32_t q0 = 0; q0 < C; q0 += kCandChunk) {
+                        const int len = C - q0 < kCandChunk ? C - q0 : kCandChunk;
+                        for (int j = tid; j < len; j += kSmallBlock) {
+                            const uint32_t u = p.cvals[q0 + j];
+                            s_kv[j] = ((uint64_t)p.ckeys[q0 + j] << 32) | u;
+                            s_w[j] = a.vwgt ? a.vwgt[u] : 1;
+                        }
+                        __syncthreads();
+                        if (contended) {
+                            const uint64_t lo = (uint64_t)(uint32_t)K << 32, hi = lo | (uint32_t)v;
+                            for (int j = 0; j < len; ++j) pre += (s_kv[j] >= lo && s_kv[j] <= hi) ? s_w[j] : 0;
+                        }
+                        __syncthreads();
+                    }
+                    if (contended) ac = p.wsnap[K] + pre <= cap_for(p.caps, (uint32_t)K, (uint32_t)v) ? 1 : 0;
+                }
+                if (K < 0) continue;
+                if (ac == 1) {
+                    const int64_t c = a.vwgt ? a.vwgt[v] : 1;
+                    const int32_t old = p.label[v];
+                    p.label[v] = K;
+                    atomicAdd((unsigned long long*)&p.wt[K], (unsigned long long)c);
+                    atomicAdd((unsigned long long*)&p.wt[old], (unsigned long long)(-c));
+                    if (r + 1 < kRounds)
+                        for (int32_t e = a.xadj[v]; e < a.xadj[v + 1]; ++e) act_next[a.adjncy[e]] = stamp_next;
+                    atomicAdd(&s_moves, 1);
+                }
+                a.prop[v] = -1;
+                p.acc[v] = 0;
+                a.demand[K] = 0;
+            }
+            __syncthreads();
+        }
+        const int32_t moved = s_moves;
+        if (tid == 0) p.out[r] = moved;
+        __syncthreads();  // every thread has read s_moves before the next round clears it
+        if (moved == 0) {
+            rounds = r + 1;
+            break;
+        }
+    }
+    if (tid == 0) p.out[kRounds] = rounds;
+    flush_stats(a, nodes, edges);
+}
+
 }  // namespace
 
 // ================================================================ host side
@@ -1129,6 +1312,60 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
     for (int32_t s = 0; s < kSub; ++s) launch_rate(c, a, sched, s, sched.order.p, sched.segtab.p, sched.cnt);
 }
 
+namespace {
+
+// A level runs the single-workgroup LP when it is small and has no node of
+// degree above T1_DEG (and the exact admission path is not forced).
+bool small_level(const Ctx& c, const DGraph& g, const LPSchedule& sched)
+{
+    const int32_t limit = c.small_level_n == 0 ? kSmallLevelN : c.small_level_n;
+    if (c.force_exact || limit < 0 || g.n > limit) return false;
+    for (int j = 2 * kSub; j < kSegs; ++j)
+        if (sched.cnt[j]) return false;
+    return true;
+}
+
+LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st,
+                     LPBuffers& b)
+{
+    SmallLP p;
+    memset(&p, 0, sizeof(p));
+    p.a = make_rate_args(c, g, st, 0, &b);
+    p.a.level = (uint32_t)level;
+    p.a.ctl = nullptr;
+    p.a.bytes_ctr = c.spread(SP_BYTES + KMP_PROF_LP_SMALL);
+    p.label = st.label;
+    p.wt = st.wt;
+    p.order = sched.order.p;
+    for (int j = 0; j < 2 * kSub; ++j) {
+        p.off[j] = sched.off[j];
+        p.cnt[j] = sched.cnt[j];
+    }
+    for (int r = 0; r < kRounds; ++r) p.hpre[r] = hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r});
+    p.act[0] = b.active.p;
+    p.act[1] = b.mflag.p;
+    p.acc = b.acc.p;
+    p.ckeys = b.ckeys.p;
+    p.cvals = b.cvals.p;
+    p.wsnap = b.base.p;
+    p.caps = cap_args(st);
+    p.out = b.ctl.p;
+    const bool ew = g.adjwgt != nullptr, capv = st.cap_vec != nullptr;
+    const dim3 grid(1), block(kSmallBlock);
+    if (ew && capv) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<true, true>), grid, block, 0, p);
+    else if (ew) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<true, false>), grid, block, 0, p);
+    else if (capv) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<false, true>), grid, block, 0, p);
+    else KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<false, false>), grid, block, 0, p);
+    int64_t h[kRounds + 1];
+    c.read(h, b.ctl.p, sizeof(h));
+    LPStats out;
+    out.rounds = (int32_t)h[kRounds];
+    for (int r = 0; r < kRounds; ++r) out.moves[r] = h[r];
+    return out;
+}
+
+}  // namespace
+
 LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st)
 {
     LPStats out;
@@ -1136,6 +1373,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     if (n == 0) return out;
     LPBuffers b;
     lp_buffers(c, g, sched, st.nlab, b);
+    if (small_level(c, g, sched)) return lp_run_small(c, g, level, seed, sched, st, b);
     DBuf<uint8_t>& active = b.active;
     DBuf<int32_t> alist0(c, (size_t)n), alist1(c, (size_t)n);
     int32_t* alist[2] = {alist0.p, alist1.p};

@@ -340,6 +340,27 @@ def test_partition_forced_exact_path(kmp, name, k, seed):
     assert plain["lp_exact_subrounds"] < stats["lp_exact_subrounds"]
 
 
+@pytest.mark.parametrize("name,k,seed,small", [("grid128", 8, 1, -1), ("rgg20000", 64, 1, -1),
+                                               ("rgg20000", 12, 4, 1 << 22), ("rand_w", 7, 9, 1 << 22),
+                                               ("hubs", 8, 5, 1 << 22), ("rand_iso", 16, 3, 1 << 22)])
+def test_partition_lp_paths(kmp, name, k, seed, small):
+    """LP calls on every level through the multi-launch path (small = -1), or on every level without
+    a node of degree > 64 through the one-workgroup kernel (small = 2^22): the output is the oracle's."""
+    g = {"grid128": lambda: gen.grid(128, 128), "rgg20000": lambda: gen.rgg(20000, 8.0, 2),
+         "rand_w": lambda: gen.random_graph(5000, 5.0, 7, max_vw=4, max_ew=6),
+         "rand_iso": lambda: gen.random_graph(8000, 3.0, 8, isolated_frac=0.3),
+         "hubs": lambda: hub_graphs()[0][1]}[name]()
+    say(f"[partition, small_level_n={small}] {name} n={g.n} k={k} seed={seed}")
+    ref = oracle.partition(g, k, 0.03, seed)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, seed, small_level_n=small)
+    assert rc == ref.status
+    assert np.array_equal(part.cpu().numpy(), ref.part)
+    assert stats["cut"] == ref.stats["cut"] and stats["level_n"] == ref.stats["level_n"]
+    assert stats["lp_cluster_moves"] == ref.stats["lp_cluster_moves"]
+    assert stats["lp_refine_moves"] == ref.stats["lp_refine_moves"]
+
+
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
@@ -428,6 +449,21 @@ def test_batch_forced_exact_path(kmp):
     ]
     say(f"[batch, exact path forced] {len(specs)} jobs")
     _check_batch_against_oracle(kmp, _batch_jobs(specs), force_exact=True)
+
+
+@pytest.mark.parametrize("small", [-1, 1 << 22])
+def test_batch_lp_paths(kmp, small):
+    """The batch pass with every LP call on the multi-launch path, or on the one-workgroup kernel
+    wherever the union level qualifies."""
+    specs = [
+        ("grid64x40", gen.grid(64, 40), 8, 0.03, 3),
+        ("rgg5000", gen.rgg(5000, 8.0, 7), 16, 0.03, 0),
+        ("rand_w", gen.random_graph(3000, 5.0, 5, max_vw=4, max_ew=6), 5, 0.05, 9),
+        ("rand_iso", gen.random_graph(4000, 3.0, 8, isolated_frac=0.3), 16, 0.03, 2),
+        ("tiny", gen.grid(2, 3), 8, 0.03, 1),
+    ]
+    say(f"[batch, small_level_n={small}] {len(specs)} jobs")
+    _check_batch_against_oracle(kmp, _batch_jobs(specs), small_level_n=small)
 
 
 def test_batch_errors_and_empty_jobs(kmp):
