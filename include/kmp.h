@@ -223,6 +223,56 @@ int kmp_server_wait(kmp_server* server, uint64_t job_id, kmp_job_result* result,
 int kmp_server_stats_get(kmp_server* server, kmp_server_stats* stats);
 void kmp_server_destroy(kmp_server* server);
 
+/* ------------------------------------------------------------------------
+ * Tuning.  Launch choices that change how the path runs on the device but
+ * never its output (the partition depends only on graph, k, epsilon and seed).
+ * They are process-wide: every call reads them once when it starts.  The
+ * rating tiers follow the degree ranges of the rating kernels: degree <=
+ * tier0_deg one lane per node; <= tier1_deg 16 lanes with a 128-slot LDS
+ * table; <= tier2_deg a wavefront with a 1024-slot table; <= tier3_deg a
+ * workgroup with an 8192-slot table; above, a workgroup with a global table
+ * (each table has at least twice as many slots as the largest degree it may
+ * hold, which bounds the ranges).
+ * ------------------------------------------------------------------------ */
+typedef struct kmp_tuning {
+    int32_t small_level_n;  /* LP calls on levels of at most this many nodes with no node of degree > 64
+                               run in one workgroup launch; -1 = never (range -1 .. 2^30; default 8192) */
+    int32_t tier0_deg;      /* 1 .. 16, default 16     */
+    int32_t tier1_deg;      /* tier0_deg .. 64, default 64      */
+    int32_t tier2_deg;      /* tier1_deg .. 512, default 512    */
+    int32_t tier3_deg;      /* tier2_deg .. 4096, default 4096  */
+    int32_t reserved[3];    /* 0 */
+} kmp_tuning;
+
+/* Set the process-wide tuning (NULL: the defaults).  KMP_EINVAL, and no
+ * change, if a value is outside its range. */
+int kmp_set_tuning(const kmp_tuning* tuning);
+/* Current process-wide tuning.  KMP_EINVAL if tuning is NULL. */
+int kmp_get_tuning(kmp_tuning* tuning);
+
+typedef struct kmp_autotune_report {
+    int32_t configs;        /* settings timed                                  */
+    int32_t reps;           /* timed calls per setting (median taken)          */
+    double ms_start;        /* median ms of kmp_partition with the start setting */
+    double ms_best;         /* median ms with the chosen setting               */
+} kmp_autotune_report;
+
+/*
+ * kmp_autotune: time kmp_partition on the given job (device arrays, as for
+ * kmp_partition_batch; graph->out_part receives the partition) under a set
+ * of candidate tunings and keep the fastest.  Coordinate search from the
+ * current setting: small_level_n over {-1, 2048, 4096, 8192, 16384, 32768},
+ * then each tier cut-off over {its default, half of it}; a candidate replaces
+ * the current value only if its median time over `reps` calls (1..50, after
+ * one untimed call) is at least 2% lower.  Every candidate's partition must equal the
+ * first one's bit for bit: a difference returns KMP_EHIP (a defect, since
+ * tuning never changes the output).  On success the chosen tuning is set
+ * process-wide and copied to *chosen (may be NULL); report may be NULL.
+ * Calls in other threads meanwhile run under whichever setting is current.
+ */
+int kmp_autotune(const kmp_graph_desc* graph, int32_t reps, void* stream, kmp_tuning* chosen,
+                 kmp_autotune_report* report);
+
 /* Human-readable text for a status code (static storage). */
 const char* kmp_strerror(int code);
 

@@ -67,6 +67,19 @@ class KmpServerStats(ctypes.Structure):
                 ("running_batches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class KmpTuning(ctypes.Structure):
+    _fields_ = [("small_level_n", ctypes.c_int32), ("tier0_deg", ctypes.c_int32), ("tier1_deg", ctypes.c_int32),
+                ("tier2_deg", ctypes.c_int32), ("tier3_deg", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+
+class KmpAutotuneReport(ctypes.Structure):
+    _fields_ = [("configs", ctypes.c_int32), ("reps", ctypes.c_int32), ("ms_start", ctypes.c_double),
+                ("ms_best", ctypes.c_double)]
+
+
+TUNING_FIELDS = ("small_level_n", "tier0_deg", "tier1_deg", "tier2_deg", "tier3_deg")
+
+
 SIGNATURES = {
     "kmp_partition": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp]),
     "kmp_partition_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp,
@@ -81,6 +94,10 @@ SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_double)]),
     "kmp_server_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(KmpServerStats)]),
     "kmp_server_destroy": (None, [_vp]),
+    "kmp_set_tuning": (ctypes.c_int, [ctypes.POINTER(KmpTuning)]),
+    "kmp_get_tuning": (ctypes.c_int, [ctypes.POINTER(KmpTuning)]),
+    "kmp_autotune": (ctypes.c_int, [ctypes.POINTER(KmpGraphDesc), _i32, _vp, ctypes.POINTER(KmpTuning),
+                                    ctypes.POINTER(KmpAutotuneReport)]),
     "kmp_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "kmp_version": (ctypes.c_char_p, []),
     "kmp_lp_cluster": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _i64, _u64, _vp, _vp, _vp, _P64, _vp]),
@@ -157,6 +174,41 @@ def kmp_partition(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, see
     rc = library().kmp_partition(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, m, k, epsilon,
                                  seed & (2**64 - 1), _ptr(out), _stream(stream))
     return rc, out
+
+
+def kmp_get_tuning() -> Dict:
+    """The process-wide tuning (launch choices that never change the output)."""
+    t = KmpTuning()
+    rc = library().kmp_get_tuning(ctypes.byref(t))
+    if rc != KMP_OK:
+        raise RuntimeError(kmp_strerror(rc))
+    return {f: getattr(t, f) for f in TUNING_FIELDS}
+
+
+def kmp_set_tuning(tuning: Optional[Dict] = None) -> int:
+    """Set the process-wide tuning from a dict with the TUNING_FIELDS (None: the defaults)."""
+    if tuning is None:
+        return library().kmp_set_tuning(None)
+    t = KmpTuning()
+    for f in TUNING_FIELDS:
+        setattr(t, f, int(tuning[f]))
+    return library().kmp_set_tuning(ctypes.byref(t))
+
+
+def kmp_autotune(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
+                 reps: int = 3, stream=None) -> Tuple[int, Dict, Dict]:
+    """Time kmp_partition on this job under candidate tunings and keep the fastest (process-wide).
+    Returns (status, chosen tuning, report)."""
+    import torch
+    n = xadj.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=xadj.device)
+    d = KmpGraphDesc()
+    _fill_desc(d, dict(xadj=xadj, adjncy=adjncy, vwgt=vwgt, adjwgt=adjwgt, out=out, k=k, epsilon=epsilon,
+                       seed=seed))
+    t, r = KmpTuning(), KmpAutotuneReport()
+    rc = library().kmp_autotune(ctypes.byref(d), int(reps), _stream(stream), ctypes.byref(t), ctypes.byref(r))
+    return rc, {f: getattr(t, f) for f in TUNING_FIELDS}, {f[0]: getattr(r, f[0]) for f in r._fields_}
 
 
 def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,

@@ -8,6 +8,7 @@
 //             at least 2), balance, refine with k-way LP.
 // Host code only orchestrates; every data-parallel step runs in the kernels
 // of prims/lp/coarsen/ip/balance.hip.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <memory>
@@ -942,6 +943,90 @@ int64_t guarded(F&& f)
     }
 }
 
+// Coordinate search over output-invariant launch choices: time kmp_partition
+// under each candidate (median of `reps` calls after an untimed one), keep a
+// candidate only if it is at least 2% faster, and require every partition to
+// equal the first one.
+int64_t autotune_impl(const kmp_graph_desc& d, int32_t reps, hipStream_t stream, kmp_tuning* chosen,
+                      kmp_autotune_report* report)
+{
+    const Tuning start = tuning_get();
+    Tuning cur = start;
+    std::vector<int32_t> ref((size_t)std::max(d.n, 1)), got((size_t)std::max(d.n, 1));
+    int32_t configs = 0;
+    bool have_ref = false;
+    auto run = [&](const Tuning& t) -> double {
+        tuning_set(t);
+        std::vector<double> ms;
+        for (int32_t r = 0; r <= reps; ++r) {
+            const auto t0 = clk::now();
+            const int rc = kmp_partition(d.xadj, d.adjncy, d.vwgt, d.adjwgt, d.n, d.m, d.k, d.epsilon, d.seed,
+                                         d.out_part, stream);
+            if (rc < 0) throw Error(rc, "partition failed while tuning");
+            if (r > 0) ms.push_back(ms_since(t0));
+        }
+        if (d.n > 0) {
+            KMP_HIP(hipMemcpyAsync(got.data(), d.out_part, sizeof(int32_t) * (size_t)d.n, hipMemcpyDeviceToHost,
+                                   stream));
+            KMP_HIP(hipStreamSynchronize(stream));
+        }
+        if (!have_ref) {
+            ref = got;
+            have_ref = true;
+        } else if (ref != got) {
+            throw Error(KMP_EHIP, "a tuning changed the partition");
+        }
+        ++configs;
+        std::sort(ms.begin(), ms.end());
+        return ms[ms.size() / 2];
+    };
+    try {
+        const double ms_start = run(cur);
+        double best = ms_start;
+        auto consider = [&](const Tuning& t) {
+            if (!tuning_valid(t)) return;
+            const double ms = run(t);
+            if (ms < 0.98 * best) {  // a clear gain, not timing noise
+                best = ms;
+                cur = t;
+            }
+        };
+        for (int32_t v : {-1, 2048, 4096, 8192, 16384, 32768}) {
+            if (v == cur.small_level_n) continue;
+            Tuning t = cur;
+            t.small_level_n = v;
+            consider(t);
+        }
+        const Tuning dflt;
+        for (int i = 0; i < 4; ++i)
+            for (int32_t v : {dflt.cut[i], dflt.cut[i] / 2}) {
+                if (v == cur.cut[i]) continue;
+                Tuning t = cur;
+                t.cut[i] = v;
+                consider(t);
+            }
+        tuning_set(cur);
+        if (report) {
+            report->configs = configs;
+            report->reps = reps;
+            report->ms_start = ms_start;
+            report->ms_best = best;
+        }
+    } catch (...) {
+        tuning_set(start);
+        throw;
+    }
+    if (chosen) {
+        memset(chosen, 0, sizeof(*chosen));
+        chosen->small_level_n = cur.small_level_n;
+        chosen->tier0_deg = cur.cut[0];
+        chosen->tier1_deg = cur.cut[1];
+        chosen->tier2_deg = cur.cut[2];
+        chosen->tier3_deg = cur.cut[3];
+    }
+    return KMP_OK;
+}
+
 }  // namespace
 
 int run_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_result* results, hipStream_t stream,
@@ -985,6 +1070,45 @@ int kmp_partition_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_res
     if (count < 0 || (count > 0 && !graphs)) return KMP_EINVAL;
     if (count == 0) return KMP_OK;
     return run_batch(graphs, count, results, (hipStream_t)stream, opt, stats);
+}
+
+int kmp_set_tuning(const kmp_tuning* t)
+{
+    Tuning u;
+    if (t) {
+        u.small_level_n = t->small_level_n;
+        u.cut[0] = t->tier0_deg;
+        u.cut[1] = t->tier1_deg;
+        u.cut[2] = t->tier2_deg;
+        u.cut[3] = t->tier3_deg;
+        if (!tuning_valid(u)) return KMP_EINVAL;
+    }
+    tuning_set(u);
+    return KMP_OK;
+}
+
+int kmp_get_tuning(kmp_tuning* t)
+{
+    if (!t) return KMP_EINVAL;
+    const Tuning u = tuning_get();
+    memset(t, 0, sizeof(*t));
+    t->small_level_n = u.small_level_n;
+    t->tier0_deg = u.cut[0];
+    t->tier1_deg = u.cut[1];
+    t->tier2_deg = u.cut[2];
+    t->tier3_deg = u.cut[3];
+    return KMP_OK;
+}
+
+int kmp_autotune(const kmp_graph_desc* graph, int32_t reps, void* stream, kmp_tuning* chosen,
+                 kmp_autotune_report* report)
+{
+    if (report) memset(report, 0, sizeof(*report));
+    if (!graph || reps < 1 || reps > 50) return KMP_EINVAL;
+    const int rc = check_args(graph->xadj, graph->n, graph->m, graph->k, graph->epsilon, graph->out_part);
+    if (rc != KMP_OK) return rc;
+    if (graph->n == 0) return KMP_EINVAL;
+    return (int)guarded([&]() -> int64_t { return autotune_impl(*graph, reps, (hipStream_t)stream, chosen, report); });
 }
 
 const char* kmp_strerror(int code)

@@ -236,6 +236,16 @@ __device__ inline void job_add(int64_t* out, int32_t j, int64_t x)
     }
 }
 
+// ---------------------------------------------------------------- tuning
+// Output-invariant launch choices (kmp_tuning), process-wide.
+struct Tuning {
+    int32_t small_level_n = 8192;  // one-workgroup LP up to this many nodes (-1 never)
+    int32_t cut[4] = {16, 64, 512, 4096};  // rating tiers: largest degree of tiers 0..3
+};
+bool tuning_valid(const Tuning& t);
+Tuning tuning_get();
+void tuning_set(const Tuning& t);
+
 // ---------------------------------------------------------------- context
 // One per library call: the stream, a pinned host buffer for scalar
 // read-backs and stream-ordered device allocations released on exit.
@@ -278,7 +288,8 @@ class Ctx {
 
     Prof* prof = nullptr;  // profiling enabled when non-null
     bool force_exact = false;    // LP: contended sub-rounds take the exact path
-    int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0 default, < 0 never)
+    int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0: tune's, < 0 never)
+    Tuning tune;                 // the process-wide tuning when the call started
     int prof_begin(int cls);
     void prof_end(int idx);
     // Events for one launch of class cls (false: not timed).  The caller

@@ -45,9 +45,14 @@ constexpr int kCandChunk = 1024;    // contended entries staged in LDS per pass
 enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_ABORT_STAMP = 2, CTL_CONT = 3, CTL_N = 8, CTL_MS = CTL_N };
 constexpr int kCtlWords = CTL_N + kRounds * kSpreadSlots + 2 * kSegs;  // int64 words
 
-__device__ inline int tier_of(int32_t d)
+// Largest degree of tiers 0..3 (a tuning choice bounded by T0_DEG .. T3_DEG).
+struct TierCuts {
+    int32_t c[4];
+};
+
+__device__ inline int tier_of(int32_t d, const TierCuts& tc)
 {
-    return d <= T0_DEG ? 0 : d <= T1_DEG ? 1 : d <= T2_DEG ? 2 : d <= T3_DEG ? 3 : 4;
+    return d <= tc.c[0] ? 0 : d <= tc.c[1] ? 1 : d <= tc.c[2] ? 2 : d <= tc.c[3] ? 3 : 4;
 }
 
 // ---------------------------------------------------------------- schedule
@@ -56,8 +61,8 @@ __device__ inline int tier_of(int32_t d)
 // node of degree > T0_NARROW).
 __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict__ xadj, int32_t n, uint32_t hsub,
                                                        JobTabs jt, const uint8_t* __restrict__ gpart, uint32_t level,
-                                                       uint32_t* __restrict__ key, uint32_t* __restrict__ val,
-                                                       int32_t* __restrict__ cnt)
+                                                       TierCuts tc, uint32_t* __restrict__ key,
+                                                       uint32_t* __restrict__ val, int32_t* __restrict__ cnt)
 {
     __shared__ int32_t h[kSegs + 1];
     if (threadIdx.x <= kSegs) h[threadIdx.x] = 0;
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict
         }
         const uint32_t s = hash_step(hs, vl, 3) % kSub;
         const int32_t d = xadj[v + 1] - xadj[v];
-        const uint32_t t = (uint32_t)tier_of(d);
+        const uint32_t t = (uint32_t)tier_of(d, tc);
         const uint32_t k = takes_part ? t * kSub + s : (uint32_t)kSegs;
         key[v] = 2 * k + (t == 0 && d > T0_NARROW ? 1u : 0u);  // narrow tier-0 nodes first in their segment
         val[v] = (uint32_t)v;
@@ -838,12 +843,11 @@ __global__ void k_ctl_set(int64_t* ctl, int idx, int64_t v)
 // one read-back.  The next round's active set is marked while moves are
 // applied, in the stamp array of the next round's parity (the marks never hide
 // a node's stamp for the current round).  Levels run here only if every node
-// has degree <= T1_DEG: tier-0 nodes are rated one per lane as in k_rate_lane,
+// sits in rating tiers 0 and 1 (degree <= T1_DEG): tier-0 nodes are rated one per lane as in k_rate_lane,
 // tier-1 nodes one per wavefront with a 2^7-slot LDS table.  All global
 // accesses stay inside one workgroup, which the workgroup-scope fences of the
 // barriers order.
 constexpr int kSmallBlock = 1024;
-constexpr int32_t kSmallLevelN = 8192;  // default largest level (nodes) run in one workgroup
 
 struct SmallLP {
     RateArgs a;               // graph, caps, prop, demand, fav, counters; hpre / round set per round
@@ -1037,8 +1041,9 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
     const uint32_t hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
     {
         ProfScope ps(c, KMP_PROF_SCHEDULE);
+        const TierCuts tc{{c.tune.cut[0], c.tune.cut[1], c.tune.cut[2], c.tune.cut[3]}};
         hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, jt, gpart,
-                           (uint32_t)level, key.p, val.p, cnt.p);
+                           (uint32_t)level, tc, key.p, val.p, cnt.p);
         KMP_LAUNCH_CHECK();
     }
     radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, bits_for(2 * kSegs + 1));
@@ -1314,11 +1319,12 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
 
 namespace {
 
-// A level runs the single-workgroup LP when it is small and has no node of
-// degree above T1_DEG (and the exact admission path is not forced).
+// A level runs the single-workgroup LP when it is small and its nodes all sit
+// in rating tiers 0 and 1 (degree <= T1_DEG), unless the exact admission path
+// is forced.
 bool small_level(const Ctx& c, const DGraph& g, const LPSchedule& sched)
 {
-    const int32_t limit = c.small_level_n == 0 ? kSmallLevelN : c.small_level_n;
+    const int32_t limit = c.small_level_n == 0 ? c.tune.small_level_n : c.small_level_n;
     if (c.force_exact || limit < 0 || g.n > limit) return false;
     for (int j = 2 * kSub; j < kSegs; ++j)
         if (sched.cnt[j]) return false;

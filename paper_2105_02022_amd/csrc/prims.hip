@@ -49,7 +49,36 @@ std::vector<std::pair<void*, size_t>> g_pinned_free;
 
 }  // namespace
 
-Ctx::Ctx(hipStream_t s) : stream(s)
+namespace {
+std::mutex g_tune_mu;
+Tuning g_tune;
+}  // namespace
+
+bool tuning_valid(const Tuning& t)
+{
+    if (t.small_level_n < -1 || t.small_level_n > (1 << 30)) return false;
+    const int32_t hi[4] = {16, 64, 512, 4096};
+    int32_t lo = 1;
+    for (int i = 0; i < 4; ++i) {
+        if (t.cut[i] < lo || t.cut[i] > hi[i]) return false;
+        lo = t.cut[i];
+    }
+    return true;
+}
+
+Tuning tuning_get()
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    return g_tune;
+}
+
+void tuning_set(const Tuning& t)
+{
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune = t;
+}
+
+Ctx::Ctx(hipStream_t s) : stream(s), tune(tuning_get())
 {
     if (hipGetDevice(&device_) != hipSuccess || device_ < 0 || device_ >= 64) device_ = 0;
 }

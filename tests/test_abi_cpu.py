@@ -63,7 +63,9 @@ def test_struct_layouts_match_header(tmp_path):
               "kmp_job_result": (kmp.KmpJobResult, ["cut", "lk", "level_n"]),
               "kmp_options": (kmp.KmpOptions, ["profile_classes", "force_exact", "small_level_n"]),
               "kmp_stats": (kmp.KmpStats, ["lp_exact_subrounds", "level_n", "level_m", "ms_total", "prof_bytes"]),
-              "kmp_server_stats": (kmp.KmpServerStats, ["hbm_in_use", "running_batches"])}
+              "kmp_server_stats": (kmp.KmpServerStats, ["hbm_in_use", "running_batches"]),
+              "kmp_tuning": (kmp.KmpTuning, ["tier3_deg", "reserved"]),
+              "kmp_autotune_report": (kmp.KmpAutotuneReport, ["ms_start", "ms_best"])}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kmp.h"', "int main(void) {"]
     for st, (_, fs) in fields.items():
         lines.append(f'printf("%zu\\n", sizeof({st}));')
@@ -93,3 +95,33 @@ def test_server_argument_errors_before_any_device_work():
     assert lib.kmp_server_wait(None, 1, None, None) == kmp.KMP_EINVAL
     assert lib.kmp_server_stats_get(None, None) == kmp.KMP_EINVAL
     lib.kmp_server_destroy(None)
+
+
+def test_tuning_validation_without_device_work():
+    """kmp_set_tuning keeps the setting on a bad value; NULL restores the defaults."""
+    lib = kmp.library()
+    assert kmp.kmp_set_tuning(None) == kmp.KMP_OK
+    dflt = kmp.kmp_get_tuning()
+    assert dflt == {"small_level_n": 8192, "tier0_deg": 16, "tier1_deg": 64, "tier2_deg": 512, "tier3_deg": 4096}
+    bad = [dict(dflt, tier0_deg=17), dict(dflt, tier0_deg=0), dict(dflt, tier1_deg=8, tier0_deg=16),
+           dict(dflt, tier2_deg=513), dict(dflt, tier3_deg=256), dict(dflt, small_level_n=-2),
+           dict(dflt, small_level_n=(1 << 30) + 1)]
+    for b in bad:
+        assert kmp.kmp_set_tuning(b) == kmp.KMP_EINVAL, b
+        assert kmp.kmp_get_tuning() == dflt
+    good = dict(small_level_n=-1, tier0_deg=8, tier1_deg=32, tier2_deg=256, tier3_deg=2048)
+    assert kmp.kmp_set_tuning(good) == kmp.KMP_OK
+    assert kmp.kmp_get_tuning() == good
+    assert kmp.kmp_set_tuning(None) == kmp.KMP_OK
+    assert kmp.kmp_get_tuning() == dflt
+    assert lib.kmp_get_tuning(None) == kmp.KMP_EINVAL
+
+
+def test_autotune_argument_errors_before_any_device_work():
+    lib = kmp.library()
+    assert lib.kmp_autotune(None, 3, None, None, None) == kmp.KMP_EINVAL
+    d = kmp.KmpGraphDesc()
+    d.n, d.k, d.m, d.epsilon = 10, 2, 0, 0.03
+    assert lib.kmp_autotune(ctypes.byref(d), 0, None, None, None) == kmp.KMP_EINVAL   # reps
+    assert lib.kmp_autotune(ctypes.byref(d), 51, None, None, None) == kmp.KMP_EINVAL  # reps
+    assert lib.kmp_autotune(ctypes.byref(d), 3, None, None, None) == kmp.KMP_EINVAL   # NULL arrays

@@ -361,6 +361,43 @@ def test_partition_lp_paths(kmp, name, k, seed, small):
     assert stats["lp_refine_moves"] == ref.stats["lp_refine_moves"]
 
 
+@pytest.mark.parametrize("name,k", [("hubs", 8), ("rgg20000", 64)])
+def test_partition_under_other_tunings(kmp, name, k):
+    """Halved rating-tier cut-offs (more nodes in the wider tiers) and the one-workgroup LP off or on for
+    every level: the output is the oracle's."""
+    g = {"rgg20000": lambda: gen.rgg(20000, 8.0, 2), "hubs": lambda: hub_graphs()[0][1]}[name]()
+    ref = oracle.partition(g, k, 0.03, 5)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    try:
+        for small in (-1, 1 << 20):
+            t = dict(small_level_n=small, tier0_deg=8, tier1_deg=32, tier2_deg=256, tier3_deg=2048)
+            assert kmp.kmp_set_tuning(t) == kmp.KMP_OK
+            say(f"[partition, tuning {t}] {name} n={g.n} k={k}")
+            rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, 5)
+            assert rc == ref.status
+            assert np.array_equal(part.cpu().numpy(), ref.part)
+            assert stats["cut"] == ref.stats["cut"]
+    finally:
+        kmp.kmp_set_tuning(None)
+
+
+def test_autotune_picks_a_setting_and_keeps_the_output(kmp):
+    g = gen.rgg(20000, 8.0, 2)
+    ref = oracle.partition(g, 16, 0.03, 3)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    try:
+        rc, chosen, report = kmp.kmp_autotune(xadj, adjncy, vwgt, adjwgt, 16, 0.03, 3, reps=2)
+        say(f"[autotune] chosen {chosen} report {report}")
+        assert rc == kmp.KMP_OK
+        assert kmp.kmp_get_tuning() == chosen
+        assert report["configs"] >= 10 and report["reps"] == 2
+        assert 0 < report["ms_best"] <= report["ms_start"]
+        rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, 16, 0.03, 3)
+        assert rc == ref.status and np.array_equal(part.cpu().numpy(), ref.part)
+    finally:
+        kmp.kmp_set_tuning(None)
+
+
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
