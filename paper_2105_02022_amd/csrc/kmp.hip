@@ -497,6 +497,25 @@ void build_union(Ctx& c, const std::vector<JobRun>& jobs, const DBuf<JobPtrs>& d
 // The deep-MGP pass (Alg. 1 unrolled) over the jobs with run = true.  One
 // job works on its own graph; several run level by level on the union of
 // their level graphs, each job with its own parameters and stopping points.
+// Batches: the jobs of level L whose LP runs in the one-workgroup kernel (small
+// enough, no node of degree above the tier-1 cut-off); `part` (may be NULL)
+// marks the jobs that take part.
+void pick_small_jobs(const Ctx& c, const Level& L, const std::vector<uint8_t>* part, int32_t nj, LPState& ls)
+{
+    ls.njobs = nj;
+    const int32_t limit = small_limit(c);
+    if (limit < 0) return;
+    for (size_t mi = 0; mi < L.mem.size(); ++mi) {
+        const int32_t j = L.mem[mi];
+        if (part && !(*part)[j]) continue;
+        if (L.nn[j] > 0 && L.nn[j] <= limit && L.sched->job_maxdeg[j] <= c.tune.cut[1]) {
+            ls.small_jobs.push_back(j);
+            ls.small_start.push_back((int32_t)L.moff[mi]);
+            ls.small_count.push_back(L.nn[j]);
+        }
+    }
+}
+
 void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>& dptr, const kmp_options* opt,
               Totals& t)
 {
@@ -558,7 +577,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
             if (!full) dtakes = upload(c, takes);
         }
         L.sched.reset(new LPSchedule());
-        lp_build_schedule(c, g, l, seed0, *L.sched, jt, dtakes.p);
+        lp_build_schedule(c, g, l, seed0, *L.sched, jt, dtakes.p, nj);
         L.sched_full = full;
         DBuf<int32_t> label(c, (size_t)g.n);
         DBuf<int64_t> cw(c, (size_t)g.n);
@@ -568,6 +587,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         KMP_LAUNCH_CHECK();
         LPState ls{label.p, cw.p, g.n, nullptr, batch ? 0 : U[0], fav.p, TAG_CL, jt,
                    batch ? L.dnoff.p : nullptr, batch ? dU.p : nullptr};
+        if (batch) pick_small_jobs(c, L, &takes, nj, ls);
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_cl += lps.moves[r];
         t.exact += lps.exact_subrounds;
@@ -722,12 +742,13 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         if (batch) dboff = upload(c, boff);
         if (!L.sched || !L.sched_full) {
             L.sched.reset(new LPSchedule());
-            lp_build_schedule(c, g, l, seed0, *L.sched, jt, nullptr);
+            lp_build_schedule(c, g, l, seed0, *L.sched, jt, nullptr, nj);
             L.sched_full = true;
         }
         t.brounds += balance(c, g, l, batch ? seeds : std::vector<uint64_t>{seed0}, *L.sched, part.p, wt.p, bt, cap.p,
                              jt, dboff.p, &hcap);
         LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF, jt, dboff.p, nullptr};
+        if (batch) pick_small_jobs(c, L, nullptr, nj, ls);
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_ref += lps.moves[r];
         t.exact += lps.exact_subrounds;

@@ -450,7 +450,14 @@ struct LPState {
     JobTabs jt = {};
     const int32_t* loff = nullptr;
     const int64_t* gcap = nullptr;
+    // batches: jobs whose LP runs in the one-workgroup kernel (one workgroup
+    // each), with their first node and node count at this level
+    int32_t njobs = 0;
+    std::vector<int32_t> small_jobs, small_start, small_count;
 };
+
+// Largest level (nodes) of the one-workgroup LP for this call; -1: never.
+int32_t small_limit(const Ctx& c);
 
 struct LPStats {
     int64_t moves[kRounds] = {0, 0, 0, 0, 0};
@@ -472,6 +479,7 @@ struct LPSchedule {
     int32_t hub_start = 0;            // hubs (last tier) of all classes are contiguous from here
     DBuf<int64_t> hub_slot_off;       // per hub: start of its global hash table
     int64_t hub_slots_total = 0;
+    std::vector<int32_t> job_maxdeg;  // batches: largest degree of every job's scheduled nodes (0: none)
     int32_t class_size(int s) const
     {
         int32_t t = 0;
@@ -483,7 +491,7 @@ struct LPSchedule {
 // Schedule of the nodes of one level.  Batches: per-job seeds through jt, and
 // only the nodes of jobs with gpart[job] != 0 are scheduled (gpart NULL: all).
 void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched,
-                       const JobTabs& jt = {}, const uint8_t* gpart = nullptr);
+                       const JobTabs& jt = {}, const uint8_t* gpart = nullptr, int32_t njobs = 0);
 // Rated entries accumulate in the context's SP_RATED spread counter.
 LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st);
 int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32_t s, uint64_t seed,

@@ -59,31 +59,55 @@ __device__ inline int tier_of(int32_t d, const TierCuts& tc)
 // segment = tier * S + class; nodes of jobs that do not take part get segment
 // kSegs (sorted behind every segment).  The sort key is 2 * segment + (tier-0
 // node of degree > T0_NARROW).
+// For batches, jmax[j] receives the largest degree among job j's scheduled
+// nodes (one atomic per wavefront when the wavefront's nodes share a job).
 __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict__ xadj, int32_t n, uint32_t hsub,
                                                        JobTabs jt, const uint8_t* __restrict__ gpart, uint32_t level,
                                                        TierCuts tc, uint32_t* __restrict__ key,
-                                                       uint32_t* __restrict__ val, int32_t* __restrict__ cnt)
+                                                       uint32_t* __restrict__ val, int32_t* __restrict__ cnt,
+                                                       int32_t* __restrict__ jmax)
 {
     __shared__ int32_t h[kSegs + 1];
     if (threadIdx.x <= kSegs) h[threadIdx.x] = 0;
     __syncthreads();
-    // grid-stride over a capped grid: each block adds its kSegs + 1 counts once
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        uint32_t hs = hsub, vl = (uint32_t)v;
-        bool takes_part = true;
-        if (jt.gid) {
-            const int32_t j = jt.gid[v];
-            hs = hash_step(hash_step(jt.ghash[j], TAG_SUB, 1), level, 2);
-            vl = (uint32_t)(v - jt.noff[j]);
-            takes_part = !gpart || gpart[j];
+    // grid-stride over a capped grid (uniform trip count: every lane reaches the
+    // wavefront reductions); each block adds its kSegs + 1 counts once
+    for (int64_t v0 = (int64_t)blockIdx.x * blockDim.x; v0 < n; v0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t v = v0 + threadIdx.x;
+        const bool in = v < n;
+        int32_t j = -1, d = 0;
+        if (in) {
+            uint32_t hs = hsub, vl = (uint32_t)v;
+            bool takes_part = true;
+            if (jt.gid) {
+                j = jt.gid[v];
+                hs = hash_step(hash_step(jt.ghash[j], TAG_SUB, 1), level, 2);
+                vl = (uint32_t)(v - jt.noff[j]);
+                takes_part = !gpart || gpart[j];
+            }
+            const uint32_t s = hash_step(hs, vl, 3) % kSub;
+            d = xadj[v + 1] - xadj[v];
+            const uint32_t t = (uint32_t)tier_of(d, tc);
+            const uint32_t k = takes_part ? t * kSub + s : (uint32_t)kSegs;
+            key[v] = 2 * k + (t == 0 && d > T0_NARROW ? 1u : 0u);  // narrow tier-0 nodes first in their segment
+            val[v] = (uint32_t)v;
+            atomicAdd(&h[k], 1);
+            if (!takes_part) j = -1;
         }
-        const uint32_t s = hash_step(hs, vl, 3) % kSub;
-        const int32_t d = xadj[v + 1] - xadj[v];
-        const uint32_t t = (uint32_t)tier_of(d, tc);
-        const uint32_t k = takes_part ? t * kSub + s : (uint32_t)kSegs;
-        key[v] = 2 * k + (t == 0 && d > T0_NARROW ? 1u : 0u);  // narrow tier-0 nodes first in their segment
-        val[v] = (uint32_t)v;
-        atomicAdd(&h[k], 1);
+        if (jmax) {
+            // lanes without a scheduled node carry j = -1
+            const uint64_t live = ballot64(j >= 0);
+            if (live) {
+                const int32_t j0 = __shfl(j, __ffsll((unsigned long long)live) - 1, 64);
+                if (ballot64(j >= 0 && j != j0) == 0) {
+                    int32_t m = j >= 0 ? d : 0;
+                    for (int q = 32; q > 0; q >>= 1) m = max(m, __shfl_xor(m, q, 64));
+                    if ((threadIdx.x & 63) == 0) atomicMax(&jmax[j0], m);
+                } else if (j >= 0) {
+                    atomicMax(&jmax[j], d);
+                }
+            }
+        }
     }
     __syncthreads();
     if (threadIdx.x <= kSegs && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
@@ -830,6 +854,36 @@ __global__ __launch_bounds__(kBlock) void k_active_append(const int64_t* __restr
     }
 }
 
+// Round-0 lists without the nodes of skipped jobs: the nodes of `order`
+// segment blockIdx.y whose job is not skipped, appended to the same segment
+// region of `alist`; counts go to segtab[kSegs + seg] (zero before), the
+// segment's start to segtab[seg].
+__global__ __launch_bounds__(kBlock) void k_order_skip_jobs(const int32_t* __restrict__ order, SegBounds b,
+                                                            const int32_t* __restrict__ gid,
+                                                            const uint8_t* __restrict__ skip,
+                                                            int32_t* __restrict__ alist, int32_t* __restrict__ segtab)
+{
+    __shared__ int32_t s_cnt, s_base;
+    const int seg = blockIdx.y;
+    const int32_t lo = b.off[seg], hi = b.off[seg + 1];
+    if (blockIdx.x == 0 && threadIdx.x == 0) segtab[seg] = lo;
+    for (int64_t i0 = lo + (int64_t)xcd_block() * kBlock; i0 < hi; i0 += (int64_t)gridDim.x * kBlock) {
+        if (threadIdx.x == 0) s_cnt = 0;
+        __syncthreads();
+        const int64_t i = i0 + threadIdx.x;
+        int32_t v = -1, slot = -1;
+        if (i < hi) {
+            v = order[i];
+            if (!skip[gid[v]]) slot = atomicAdd(&s_cnt, 1);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(&segtab[kSegs + seg], s_cnt);
+        __syncthreads();
+        if (slot >= 0) alist[lo + s_base + slot] = v;
+        __syncthreads();
+    }
+}
+
 __global__ void k_ctl_set(int64_t* ctl, int idx, int64_t v)
 {
     if (threadIdx.x == 0) ctl[idx] = v;
@@ -850,20 +904,22 @@ __global__ void k_ctl_set(int64_t* ctl, int idx, int64_t v)
 constexpr int kSmallBlock = 1024;
 
 struct SmallLP {
-    RateArgs a;               // graph, caps, prop, demand, fav, counters; hpre / round set per round
+    RateArgs a;               // graph, caps, prop, demand, fav, counters, job tables; hpre / round set per round
     int32_t* label;           // [n]
     int64_t* wt;              // [nlab]
-    const int32_t* order;     // schedule: node ids by segment
-    int32_t off[2 * kSub];    // tier t (0, 1), class s: segment start order[off[t * S + s]]
-    int32_t cnt[2 * kSub];
-    uint32_t hpre[kRounds];   // H prefix over (seed; tag, level, round) of every round
-    uint8_t* act[2];          // active stamps by round parity (zeroed)
+    const int32_t* jstart;    // by workgroup: the job's first node and node count
+    const int32_t* jcount;
+    uint32_t hsub;            // one graph: H prefix over (seed; T_SUB, level) of the sub-round classes
+    uint32_t hpre[kRounds];   // one graph: H prefix over (seed; tag, level, round) of every round
+    int32_t cut0;             // largest degree rated one per lane (tier 0)
+    int32_t* lists;           // [n] scratch: each job's class lists inside its own node range
+    uint8_t* act[2];          // [n] active stamps by round parity (zeroed)
     uint8_t* acc;             // [n] zeroed
-    uint32_t* ckeys;          // [n] contended (target, id)
+    uint32_t* ckeys;          // [n] contended (target, id), inside each job's node range
     uint32_t* cvals;
     int64_t* wsnap;           // [nlab] start weight of contended targets
     CapArgs caps;
-    int64_t* out;             // [kRounds] moves per round, [kRounds] rounds run (zeroed)
+    int64_t* out;             // [kRounds] moves per round (summed over jobs), [kRounds] largest round count
 };
 
 template <bool EW, bool CAPV>
@@ -875,24 +931,57 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
     __shared__ uint64_t s_kv[kCandChunk];  // (target << 32) | id
     __shared__ int32_t s_w[kCandChunk];
     __shared__ int32_t s_cont, s_moves;
+    __shared__ int32_t s_cnt[3 * kSub], s_off[3 * kSub];
     RateArgs a = p.a;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t* keys = s_keys + wv * HS;
     uint32_t* vals = s_vals + wv * HS;
+    const int32_t start = p.jstart[blockIdx.x], nj = p.jcount[blockIdx.x];
+    uint32_t hs = p.hsub;
+    if (a.gid) hs = hash_step(hash_step(a.ghash[a.gid[start]], TAG_SUB, 1), a.level, 2);
+    // The job's class lists, inside its node range: for class s, tier-0 nodes of
+    // degree <= T0_NARROW, the other tier-0 nodes, then tier-1 nodes (list
+    // 3 s + 0, 1, 2).  The order inside a list does not matter.
+    auto list_of = [&](int32_t i) -> int {
+        const int32_t d = a.xadj[start + i + 1] - a.xadj[start + i];
+        const int t = d > p.cut0 ? 2 : d <= T0_NARROW ? 0 : 1;
+        return 3 * (int)(hash_step(hs, (uint32_t)i, 3) % kSub) + t;
+    };
+    if (tid < 3 * kSub) s_cnt[tid] = 0;
+    __syncthreads();
+    for (int32_t i = tid; i < nj; i += kSmallBlock) atomicAdd(&s_cnt[list_of(i)], 1);
+    __syncthreads();
+    if (tid == 0) {
+        int32_t o = 0;
+        for (int q = 0; q < 3 * kSub; ++q) {
+            s_off[q] = o;
+            o += s_cnt[q];
+            s_cnt[q] = 0;
+        }
+    }
+    __syncthreads();
+    for (int32_t i = tid; i < nj; i += kSmallBlock) {
+        const int q = list_of(i);
+        p.lists[start + s_off[q] + atomicAdd(&s_cnt[q], 1)] = start + i;
+    }
+    __syncthreads();
+    const int32_t* order = p.lists + start;
     int64_t edges = 0, nodes = 0;
     int32_t rounds = kRounds;
     for (int32_t r = 0; r < kRounds; ++r) {
-        a.hpre = p.hpre[r];
+        a.hpre = p.hpre[r];  // batches: node_key derives each job's prefix instead
+
         a.round = (uint32_t)r;
         const uint8_t* act = p.act[r & 1];
         uint8_t* act_next = p.act[(r + 1) & 1];
         const uint8_t stamp = (uint8_t)(r + 1), stamp_next = (uint8_t)(r + 2);
         if (tid == 0) s_moves = 0;
         for (int s = 0; s < kSub; ++s) {
-            const int32_t o0 = p.off[s], c0 = p.cnt[s], o1 = p.off[kSub + s], c1 = p.cnt[kSub + s];
+            const int32_t o0 = s_off[3 * s], c0 = s_cnt[3 * s] + s_cnt[3 * s + 1], o1 = s_off[3 * s + 2],
+                          c1 = s_cnt[3 * s + 2];
             // rate, tier 0: one lane per node
             for (int32_t i = tid; i < c0; i += kSmallBlock) {
-                const int32_t v = p.order[o0 + i];
+                const int32_t v = order[o0 + i];
                 if (r > 0 && act[v] != stamp) continue;
                 const uint32_t own = (uint32_t)p.label[v];
                 const int32_t e0 = a.xadj[v];
@@ -906,7 +995,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             }
             // rate, tier 1: one wavefront per node (the loop is uniform in the wave)
             for (int32_t i = wv; i < c1; i += NW) {
-                const int32_t v = p.order[o1 + i];
+                const int32_t v = order[o1 + i];
                 if (r > 0 && act[v] != stamp) continue;
                 for (int j = lane; j < HS; j += 64) {
                     keys[j] = EMPTY;
@@ -942,7 +1031,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             // admission at the sub-round start weights (no weight changes until the apply step)
             const int32_t total = c0 + c1;
             for (int32_t i = tid; i < total; i += kSmallBlock) {
-                const int32_t v = p.order[i < c0 ? o0 + i : o1 + (i - c0)];
+                const int32_t v = order[i < c0 ? o0 + i : o1 + (i - c0)];
                 const int32_t K = a.prop[v];
                 if (K < 0) continue;
                 const int64_t wK = p.wt[K];
@@ -951,7 +1040,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 } else {
                     p.acc[v] = 2;
                     p.wsnap[K] = wK;  // every proposal into K writes the same value
-                    const int32_t slot = atomicAdd(&s_cont, 1);
+                    const int32_t slot = start + atomicAdd(&s_cont, 1);
                     p.ckeys[slot] = (uint32_t)K;
                     p.cvals[slot] = (uint32_t)v;
                 }
@@ -965,7 +1054,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 int32_t v = -1, K = -1;
                 uint8_t ac = 0;
                 if (i < total) {
-                    v = p.order[i < c0 ? o0 + i : o1 + (i - c0)];
+                    v = order[i < c0 ? o0 + i : o1 + (i - c0)];
                     K = a.prop[v];
                     if (K >= 0) ac = p.acc[v];
                 }
@@ -975,8 +1064,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                     for (int32_t q0 = 0; q0 < C; q0 += kCandChunk) {
                         const int len = C - q0 < kCandChunk ? C - q0 : kCandChunk;
                         for (int j = tid; j < len; j += kSmallBlock) {
-                            const uint32_t u = p.cvals[q0 + j];
-                            s_kv[j] = ((uint64_t)p.ckeys[q0 + j] << 32) | u;
+                            const uint32_t u = p.cvals[start + q0 + j];
+                            s_kv[j] = ((uint64_t)p.ckeys[start + q0 + j] << 32) | u;
                             s_w[j] = a.vwgt ? a.vwgt[u] : 1;
                         }
                         __syncthreads();
@@ -1006,14 +1095,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             __syncthreads();
         }
         const int32_t moved = s_moves;
-        if (tid == 0) p.out[r] = moved;
+        if (tid == 0 && moved) atomicAdd((unsigned long long*)&p.out[r], (unsigned long long)moved);
         __syncthreads();  // every thread has read s_moves before the next round clears it
         if (moved == 0) {
             rounds = r + 1;
             break;
         }
     }
-    if (tid == 0) p.out[kRounds] = rounds;
+    if (tid == 0) atomicMax((unsigned long long*)&p.out[kRounds], (unsigned long long)rounds);
     flush_stats(a, nodes, edges);
 }
 
@@ -1022,7 +1111,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
 // ================================================================ host side
 
 void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched, const JobTabs& jt,
-                       const uint8_t* gpart)
+                       const uint8_t* gpart, int32_t njobs)
 {
     const int32_t n = g.n;
     sched.order = DBuf<int32_t>(c, (size_t)n);
@@ -1036,20 +1125,23 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
         return;
     }
     DBuf<uint32_t> key(c, n), val(c, n), key2(c, n), val2(c, n);
-    DBuf<int32_t> cnt(c, kSegs + 1);
-    c.zero(cnt.p, (kSegs + 1) * sizeof(int32_t));
+    const int32_t nj = jt.gid ? njobs : 0;
+    DBuf<int32_t> cnt(c, (size_t)(kSegs + 1 + nj));  // segment sizes, then the jobs' largest degrees
+    c.zero(cnt.p, (kSegs + 1 + nj) * sizeof(int32_t));
     const uint32_t hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
     {
         ProfScope ps(c, KMP_PROF_SCHEDULE);
         const TierCuts tc{{c.tune.cut[0], c.tune.cut[1], c.tune.cut[2], c.tune.cut[3]}};
         hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, jt, gpart,
-                           (uint32_t)level, tc, key.p, val.p, cnt.p);
+                           (uint32_t)level, tc, key.p, val.p, cnt.p, nj ? cnt.p + kSegs + 1 : nullptr);
         KMP_LAUNCH_CHECK();
     }
     radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, bits_for(2 * kSegs + 1));
     KMP_HIP(hipMemcpyAsync(sched.order.p, val.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
-    int32_t h[kSegs + 1];
-    c.read(h, cnt.p, sizeof(h));
+    std::vector<int32_t> hv((size_t)(kSegs + 1 + nj));
+    c.read(hv.data(), cnt.p, sizeof(int32_t) * hv.size());
+    const int32_t* h = hv.data();
+    sched.job_maxdeg.assign(hv.begin() + kSegs + 1, hv.end());
     int32_t pos = 0;
     for (int j = 0; j < kSegs; ++j) {
         sched.off[j] = pos;
@@ -1091,6 +1183,7 @@ struct LPBuffers {
     DBuf<int64_t> base;            // [nlab] weight before a target's first proposal
     DBuf<int64_t> ctl;
     DBuf<uint8_t> active;          // round stamp of the active set (lp_run)
+    DBuf<int64_t> sout;            // one-workgroup LP: moves per round, round count
 };
 
 void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t nlab, LPBuffers& b)
@@ -1108,13 +1201,15 @@ void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t nlab, 
     b.base = DBuf<int64_t>(c, (size_t)nlab);
     b.ctl = DBuf<int64_t>(c, kCtlWords);
     b.active = DBuf<uint8_t>(c, (size_t)g.n);
+    b.sout = DBuf<int64_t>(c, kRounds + 1);
     // prop = -1, everything else 0, in one launch
     fill_bytes_many(c, {{b.prop.p, 4 * (int64_t)g.n, 0xFF},
                         {b.acc.p, (int64_t)g.n, 0},
                         {b.demand.p, 4 * (int64_t)nlab, 0},
                         {b.mflag.p, (int64_t)g.n, 0},
                         {b.ctl.p, (int64_t)sizeof(int64_t) * kCtlWords, 0},
-                        {b.active.p, (int64_t)g.n, 0}});
+                        {b.active.p, (int64_t)g.n, 0},
+                        {b.sout.p, (int64_t)sizeof(int64_t) * (kRounds + 1), 0}});
 }
 
 RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpre, LPBuffers* b)
@@ -1319,20 +1414,22 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
 
 namespace {
 
-// A level runs the single-workgroup LP when it is small and its nodes all sit
-// in rating tiers 0 and 1 (degree <= T1_DEG), unless the exact admission path
-// is forced.
+// A graph's level runs the one-workgroup LP when it is small and its nodes all
+// sit in rating tiers 0 and 1 (degree <= T1_DEG), unless the exact admission
+// path is forced.
 bool small_level(const Ctx& c, const DGraph& g, const LPSchedule& sched)
 {
-    const int32_t limit = c.small_level_n == 0 ? c.tune.small_level_n : c.small_level_n;
-    if (c.force_exact || limit < 0 || g.n > limit) return false;
+    const int32_t limit = small_limit(c);
+    if (limit < 0 || g.n > limit) return false;
     for (int j = 2 * kSub; j < kSegs; ++j)
         if (sched.cnt[j]) return false;
     return true;
 }
 
-LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st,
-                     LPBuffers& b)
+// The LP of the given jobs (node ranges), one workgroup each.
+LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPState& st, LPBuffers& b,
+                     const std::vector<int32_t>& start, const std::vector<int32_t>& count, uint8_t* act0,
+                     uint8_t* act1)
 {
     SmallLP p;
     memset(&p, 0, sizeof(p));
@@ -1342,28 +1439,33 @@ LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, cons
     p.a.bytes_ctr = c.spread(SP_BYTES + KMP_PROF_LP_SMALL);
     p.label = st.label;
     p.wt = st.wt;
-    p.order = sched.order.p;
-    for (int j = 0; j < 2 * kSub; ++j) {
-        p.off[j] = sched.off[j];
-        p.cnt[j] = sched.cnt[j];
-    }
+    std::vector<int32_t> ranges(start);
+    ranges.insert(ranges.end(), count.begin(), count.end());
+    DBuf<int32_t> dr(c, ranges.size());
+    c.write(dr.p, ranges.data(), sizeof(int32_t) * ranges.size());
+    p.jstart = dr.p;
+    p.jcount = dr.p + start.size();
+    p.hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
     for (int r = 0; r < kRounds; ++r) p.hpre[r] = hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r});
-    p.act[0] = b.active.p;
-    p.act[1] = b.mflag.p;
+    p.cut0 = c.tune.cut[0];
+    DBuf<int32_t> lists(c, (size_t)g.n);
+    p.lists = lists.p;
+    p.act[0] = act0;
+    p.act[1] = act1;
     p.acc = b.acc.p;
     p.ckeys = b.ckeys.p;
     p.cvals = b.cvals.p;
     p.wsnap = b.base.p;
     p.caps = cap_args(st);
-    p.out = b.ctl.p;
+    p.out = b.sout.p;
     const bool ew = g.adjwgt != nullptr, capv = st.cap_vec != nullptr;
-    const dim3 grid(1), block(kSmallBlock);
+    const dim3 grid((unsigned)start.size()), block(kSmallBlock);
     if (ew && capv) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<true, true>), grid, block, 0, p);
     else if (ew) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<true, false>), grid, block, 0, p);
     else if (capv) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<false, true>), grid, block, 0, p);
     else KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<false, false>), grid, block, 0, p);
     int64_t h[kRounds + 1];
-    c.read(h, b.ctl.p, sizeof(h));
+    c.read(h, b.sout.p, sizeof(h));
     LPStats out;
     out.rounds = (int32_t)h[kRounds];
     for (int r = 0; r < kRounds; ++r) out.moves[r] = h[r];
@@ -1372,14 +1474,22 @@ LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, cons
 
 }  // namespace
 
-LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st)
+int32_t small_limit(const Ctx& c)
+{
+    if (c.force_exact) return -1;
+    return c.small_level_n != 0 ? c.small_level_n : c.tune.small_level_n;
+}
+
+namespace {
+
+// The launch-per-step LP: kSub sub-rounds of rate / admit / apply launches per
+// round, one read-back per round.  Nodes of the jobs in `skip` (already done
+// by the one-workgroup LP) are left out of round 0 and are never activated.
+LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st,
+                  LPBuffers& b, const std::vector<int32_t>& skip)
 {
     LPStats out;
     const int32_t n = g.n;
-    if (n == 0) return out;
-    LPBuffers b;
-    lp_buffers(c, g, sched, st.nlab, b);
-    if (small_level(c, g, sched)) return lp_run_small(c, g, level, seed, sched, st, b);
     DBuf<uint8_t>& active = b.active;
     DBuf<int32_t> alist0(c, (size_t)n), alist1(c, (size_t)n);
     int32_t* alist[2] = {alist0.p, alist1.p};
@@ -1412,13 +1522,32 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         int32_t seg[2][2 * kSegs];
     } h;
     static_assert(sizeof(h) == sizeof(int64_t) * kCtlWords, "control block layout");
+    const int32_t* list0 = sched.order.p;
+    const int32_t* segtab0 = sched.segtab.p;
+    if (!skip.empty()) {
+        // round 0 lists without the skipped jobs' nodes
+        std::vector<uint8_t> flag((size_t)st.njobs, 0);
+        for (int32_t j : skip) flag[j] = 1;
+        DBuf<uint8_t> dflag(c, flag.size());
+        c.write(dflag.p, flag.data(), flag.size());
+        int32_t mseg = 1;
+        for (int j = 0; j < kSegs; ++j) mseg = std::max(mseg, sched.cnt[j]);
+        hipLaunchKernelGGL(k_order_skip_jobs, dim3(grid_for(mseg, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream,
+                           sched.order.p, bounds, st.jt.gid, dflag.p, alist[0], segtab_r[0]);
+        KMP_LAUNCH_CHECK();
+        int32_t tab[2 * kSegs];
+        c.read(tab, segtab_r[0], sizeof(tab));
+        for (int j = 0; j < kSegs; ++j) ub[j] = tab[kSegs + j];
+        list0 = alist[0];
+        segtab0 = segtab_r[0];
+    }
     for (int32_t r = 0; r < kRounds; ++r) {
         out.rounds = r + 1;
         const int cur = r & 1, nxt = cur ^ 1;
         const uint8_t stamp = (uint8_t)(r + 1);
         const int ms = CTL_MS + r * kSpreadSlots;  // this round's move-count set
-        const int32_t* list = r == 0 ? sched.order.p : alist[cur];
-        const int32_t* segtab = r == 0 ? sched.segtab.p : segtab_r[cur];
+        const int32_t* list = r == 0 ? list0 : alist[cur];
+        const int32_t* segtab = r == 0 ? segtab0 : segtab_r[cur];
         RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
         a.level = (uint32_t)level;
         a.round = (uint32_t)r;
@@ -1452,6 +1581,48 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
         // the next round's lists are exactly sized
         for (int j = 0; j < kSegs; ++j) ub[j] = h.seg[nxt][kSegs + j];
     }
+    return out;
+}
+
+}  // namespace
+
+LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st)
+{
+    const int32_t n = g.n;
+    if (n == 0) return LPStats();
+    // jobs that run the one-workgroup LP; the others take the launch-per-step path
+    std::vector<int32_t> ss, sc;
+    if (!st.jt.gid) {
+        if (small_level(c, g, sched)) {
+            ss.assign(1, 0);
+            sc.assign(1, n);
+        }
+    } else {
+        ss = st.small_start;
+        sc = st.small_count;
+    }
+    int64_t small_nodes = 0;
+    for (int32_t x : sc) small_nodes += x;
+    const bool all_small = !ss.empty() && small_nodes == sched.off[kSegs];
+    LPBuffers b;
+    lp_buffers(c, g, sched, st.nlab, b);
+    LPStats small;
+    if (!ss.empty()) {
+        uint8_t* act0 = b.active.p;
+        uint8_t* act1 = b.mflag.p;
+        DBuf<uint8_t> sact;
+        if (!all_small) {  // the other jobs' rounds use active / mflag
+            sact = DBuf<uint8_t>(c, 2 * (size_t)n);
+            c.zero(sact.p, 2 * (size_t)n);
+            act0 = sact.p;
+            act1 = sact.p + n;
+        }
+        small = lp_run_small(c, g, level, seed, st, b, ss, sc, act0, act1);
+        if (all_small) return small;
+    }
+    LPStats out = lp_rounds(c, g, level, seed, sched, st, b, st.small_jobs);
+    for (int r = 0; r < kRounds; ++r) out.moves[r] += small.moves[r];
+    out.rounds = std::max(out.rounds, small.rounds);
     return out;
 }
 
