@@ -500,18 +500,22 @@ void build_union(Ctx& c, const std::vector<JobRun>& jobs, const DBuf<JobPtrs>& d
 // Batches: the jobs of level L whose LP runs in the one-workgroup kernel (small
 // enough, no node of degree above the tier-1 cut-off); `part` (may be NULL)
 // marks the jobs that take part.
-void pick_small_jobs(const Ctx& c, const Level& L, const std::vector<uint8_t>* part, int32_t nj, LPState& ls)
+// Labels of job j: clustering, its nodes (lfirst / lcount NULL); refinement,
+// its blocks.
+void pick_small_jobs(const Ctx& c, const Level& L, const std::vector<uint8_t>* part, int32_t nj, LPState& ls,
+                     const std::vector<int32_t>* lfirst = nullptr, const std::vector<int32_t>* lcount = nullptr)
 {
     ls.njobs = nj;
-    const int32_t limit = small_limit(c);
-    if (limit < 0) return;
     for (size_t mi = 0; mi < L.mem.size(); ++mi) {
         const int32_t j = L.mem[mi];
         if (part && !(*part)[j]) continue;
-        if (L.nn[j] > 0 && L.nn[j] <= limit && L.sched->job_maxdeg[j] <= c.tune.cut[1]) {
+        const int32_t nl = lcount ? (*lcount)[j] : L.nn[j];
+        if (small_job_fits(c, L.nn[j], nl) && L.sched->job_maxdeg[j] <= c.tune.cut[1]) {
             ls.small_jobs.push_back(j);
             ls.small_start.push_back((int32_t)L.moff[mi]);
             ls.small_count.push_back(L.nn[j]);
+            ls.small_loff.push_back(lfirst ? (*lfirst)[j] : (int32_t)L.moff[mi]);
+            ls.small_nlab.push_back(nl);
         }
     }
 }
@@ -748,7 +752,11 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         t.brounds += balance(c, g, l, batch ? seeds : std::vector<uint64_t>{seed0}, *L.sched, part.p, wt.p, bt, cap.p,
                              jt, dboff.p, &hcap);
         LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF, jt, dboff.p, nullptr};
-        if (batch) pick_small_jobs(c, L, nullptr, nj, ls);
+        if (batch) {
+            std::vector<int32_t> nbk(nj, 0);
+            for (int32_t b = 0; b < nb; ++b) ++nbk[bt.job[b]];
+            pick_small_jobs(c, L, nullptr, nj, ls, &boff, &nbk);
+        }
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_ref += lps.moves[r];
         t.exact += lps.exact_subrounds;

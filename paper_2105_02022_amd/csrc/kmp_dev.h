@@ -453,11 +453,14 @@ struct LPState {
     // batches: jobs whose LP runs in the one-workgroup kernel (one workgroup
     // each), with their first node and node count at this level
     int32_t njobs = 0;
-    std::vector<int32_t> small_jobs, small_start, small_count;
+    std::vector<int32_t> small_jobs, small_start, small_count, small_loff, small_nlab;
 };
 
 // Largest level (nodes) of the one-workgroup LP for this call; -1: never.
 int32_t small_limit(const Ctx& c);
+// A job of `nodes` nodes and `labels` labels may run the one-workgroup LP
+// (within the cut-off, and its state fits in LDS).
+bool small_job_fits(const Ctx& c, int32_t nodes, int32_t labels);
 
 struct LPStats {
     int64_t moves[kRounds] = {0, 0, 0, 0, 0};

@@ -24,6 +24,8 @@
 // host finishes it on the exact path (sort in global memory), one sub-round at
 // a time.  Rounds after the first rate only the active nodes, compacted per
 // (tier, class) segment on the device.
+#include <mutex>
+
 #include "kmp_dev.h"
 
 namespace kmp {
@@ -890,37 +892,96 @@ __global__ void k_ctl_set(int64_t* ctl, int idx, int64_t v)
 }
 
 // ---------------------------------------------------------------- small levels
-// Every round and sub-round of one LP call on a small level in a single
-// workgroup.  The steps of a sub-round (rate, admit at the sub-round start
-// weights, decide contended targets, apply) are separated by workgroup
-// barriers instead of kernel launches, so the whole call costs one launch and
-// one read-back.  The next round's active set is marked while moves are
-// applied, in the stamp array of the next round's parity (the marks never hide
-// a node's stamp for the current round).  Levels run here only if every node
-// sits in rating tiers 0 and 1 (degree <= T1_DEG): tier-0 nodes are rated one per lane as in k_rate_lane,
-// tier-1 nodes one per wavefront with a 2^7-slot LDS table.  All global
-// accesses stay inside one workgroup, which the workgroup-scope fences of the
-// barriers order.
+// Every round and sub-round of one LP call of a small job in a single
+// workgroup (one workgroup per job).  The steps of a sub-round (rate, admit
+// at the sub-round start weights, decide contended targets, apply) are
+// separated by workgroup barriers instead of kernel launches, so the whole
+// call costs one launch and one read-back.  The job's mutable state lives in
+// LDS for the whole call (labels, proposals, admission flags, active stamps as
+// local ids; label weights and demands as int32, which hold any weight since
+// c(V) < 2^31); only the graph, the caps and the favoured clusters are in
+// global memory, and labels and weights are written back at the end.  The
+// next round's active set is marked while moves are applied, in the stamp
+// array of the next round's parity (the marks never hide a node's stamp for
+// the current round).  A job runs here only if every node sits in rating
+// tiers 0 and 1 (degree <= T1_DEG): tier-0 nodes are rated one per lane,
+// tier-1 nodes one per wavefront with a 2^7-slot LDS table.
 constexpr int kSmallBlock = 1024;
+// dynamic LDS of a job: 3 int32 per label (weight, demand, start weight of a
+// contended target) + 3 int16 and 3 bytes per node (list, label, proposal;
+// admission flag, two stamp arrays), within what the static tables leave
+__host__ __device__ inline int64_t small_lds_bytes(int64_t nodes, int64_t labels)
+{
+    return (12 * labels + 9 * nodes + 15) & ~(int64_t)15;
+}
+constexpr int64_t kSmallLdsBudget = 128 * 1024;
 
 struct SmallLP {
-    RateArgs a;               // graph, caps, prop, demand, fav, counters, job tables; hpre / round set per round
-    int32_t* label;           // [n]
-    int64_t* wt;              // [nlab]
-    const int32_t* jstart;    // by workgroup: the job's first node and node count
+    RateArgs a;               // graph, caps, fav, counters, job tables; hpre / round set per round
+    int32_t* label;           // [n] global labels (read at the start, written at the end)
+    int64_t* wt;              // [nlab] global label weights (same)
+    const int32_t* jstart;    // by workgroup: the job's first node, node count, first label, label count
     const int32_t* jcount;
+    const int32_t* jloff;
+    const int32_t* jnlab;
     uint32_t hsub;            // one graph: H prefix over (seed; T_SUB, level) of the sub-round classes
     uint32_t hpre[kRounds];   // one graph: H prefix over (seed; tag, level, round) of every round
     int32_t cut0;             // largest degree rated one per lane (tier 0)
-    int32_t* lists;           // [n] scratch: each job's class lists inside its own node range
-    uint8_t* act[2];          // [n] active stamps by round parity (zeroed)
-    uint8_t* acc;             // [n] zeroed
-    uint32_t* ckeys;          // [n] contended (target, id), inside each job's node range
-    uint32_t* cvals;
-    int64_t* wsnap;           // [nlab] start weight of contended targets
-    CapArgs caps;
+    uint32_t* cont;           // [n] contended (target << 16 | node), local ids, inside each job's node range
     int64_t* out;             // [kRounds] moves per round (summed over jobs), [kRounds] largest round count
 };
+
+// Tier-0 rating of local node li (global id v) against the LDS labels and
+// weights; labels are local (global label - lo), which is also what the
+// tie-break hash takes.
+template <int DEG, bool EW, bool CAPV>
+__device__ inline void rate_lane_local(const RateArgs& a, int32_t v, int32_t start, int32_t lo, uint32_t own,
+                                       int32_t e0, int32_t d, int64_t cv, const NodeKey& nk,
+                                       const int16_t* s_lab, const int32_t* s_wt, Key3& fav, Key3& adm,
+                                       uint32_t& rown)
+{
+    uint32_t lab[DEG], w[DEG];
+    if (d > 0) {
+        int32_t u[DEG];
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) w[j] = EW ? (uint32_t)a.adjwgt[e0 + (j < d ? j : d - 1)] : 1u;
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) lab[j] = j < d ? (uint32_t)s_lab[u[j] - start] : EMPTY;
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) w[j] = j < d ? w[j] : 0u;
+    } else {
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) {
+            lab[j] = EMPTY;
+            w[j] = 0;
+        }
+    }
+#pragma unroll
+    for (int k = 1; k < DEG; ++k) {
+        bool dup = false;
+#pragma unroll
+        for (int q = 0; q < k; ++q) {
+            const bool hit = !dup && lab[k] != EMPTY && lab[q] == lab[k];
+            w[q] += hit ? w[k] : 0u;
+            dup = dup || hit;
+        }
+        lab[k] = dup ? EMPTY : lab[k];
+    }
+#pragma unroll
+    for (int j = 0; j < DEG; ++j) {
+        const bool is_own = lab[j] == own;
+        rown = is_own ? w[j] : rown;
+        const bool cand = lab[j] != EMPTY && !is_own;
+        const uint32_t l = cand ? lab[j] : own;
+        const int64_t wk = s_wt[l];
+        const int64_t ck = CAPV ? a.cap_vec[lo + l] : nk.cap;
+        const Key3 c{w[j], hash_step(nk.hp, lab[j], 4), lab[j]};
+        if (cand && better(c, fav)) fav = c;
+        if (cand && wk + cv <= ck && better(c, adm)) adm = c;
+    }
+}
 
 template <bool EW, bool CAPV>
 __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
@@ -928,20 +989,41 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
     constexpr int HB = 7, HS = 1 << HB, NW = kSmallBlock / 64;
     __shared__ uint32_t s_keys[NW * HS];
     __shared__ uint32_t s_vals[NW * HS];
-    __shared__ uint64_t s_kv[kCandChunk];  // (target << 32) | id
+    __shared__ uint32_t s_kv[kCandChunk];  // (target << 16) | node, local ids
     __shared__ int32_t s_w[kCandChunk];
     __shared__ int32_t s_cont, s_moves;
     __shared__ int32_t s_cnt[3 * kSub], s_off[3 * kSub];
+    extern __shared__ __align__(16) char s_dyn[];
     RateArgs a = p.a;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t* keys = s_keys + wv * HS;
     uint32_t* vals = s_vals + wv * HS;
     const int32_t start = p.jstart[blockIdx.x], nj = p.jcount[blockIdx.x];
+    const int32_t lo = p.jloff[blockIdx.x], nl = p.jnlab[blockIdx.x];
+    int32_t* s_wt = reinterpret_cast<int32_t*>(s_dyn);
+    int32_t* s_dem = s_wt + nl;
+    int32_t* s_ws = s_dem + nl;
+    int16_t* s_ord = reinterpret_cast<int16_t*>(s_ws + nl);
+    int16_t* s_lab = s_ord + nj;
+    int16_t* s_prop = s_lab + nj;
+    uint8_t* s_acc = reinterpret_cast<uint8_t*>(s_prop + nj);
+    uint8_t* s_act[2] = {s_acc + nj, s_acc + 2 * nj};
+    for (int32_t i = tid; i < nj; i += kSmallBlock) {
+        s_lab[i] = (int16_t)(p.label[start + i] - lo);
+        s_prop[i] = -1;
+        s_acc[i] = 0;
+        s_act[0][i] = 0;
+        s_act[1][i] = 0;
+    }
+    for (int32_t k = tid; k < nl; k += kSmallBlock) {
+        s_wt[k] = (int32_t)p.wt[lo + k];
+        s_dem[k] = 0;
+    }
     uint32_t hs = p.hsub;
     if (a.gid) hs = hash_step(hash_step(a.ghash[a.gid[start]], TAG_SUB, 1), a.level, 2);
-    // The job's class lists, inside its node range: for class s, tier-0 nodes of
-    // degree <= T0_NARROW, the other tier-0 nodes, then tier-1 nodes (list
-    // 3 s + 0, 1, 2).  The order inside a list does not matter.
+    // The job's class lists (local ids): for class s, tier-0 nodes of degree <=
+    // T0_NARROW, the other tier-0 nodes, then tier-1 nodes (list 3 s + 0, 1, 2).
+    // The order inside a list does not matter.
     auto list_of = [&](int32_t i) -> int {
         const int32_t d = a.xadj[start + i + 1] - a.xadj[start + i];
         const int t = d > p.cut0 ? 2 : d <= T0_NARROW ? 0 : 1;
@@ -962,18 +1044,17 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
     __syncthreads();
     for (int32_t i = tid; i < nj; i += kSmallBlock) {
         const int q = list_of(i);
-        p.lists[start + s_off[q] + atomicAdd(&s_cnt[q], 1)] = start + i;
+        s_ord[s_off[q] + atomicAdd(&s_cnt[q], 1)] = (int16_t)i;
     }
     __syncthreads();
-    const int32_t* order = p.lists + start;
     int64_t edges = 0, nodes = 0;
     int32_t rounds = kRounds;
     for (int32_t r = 0; r < kRounds; ++r) {
         a.hpre = p.hpre[r];  // batches: node_key derives each job's prefix instead
-
         a.round = (uint32_t)r;
-        const uint8_t* act = p.act[r & 1];
-        uint8_t* act_next = p.act[(r + 1) & 1];
+        const NodeKey nk = node_key(a, start);  // the same for every node of the job
+        const uint8_t* act = s_act[r & 1];
+        uint8_t* act_next = s_act[(r + 1) & 1];
         const uint8_t stamp = (uint8_t)(r + 1), stamp_next = (uint8_t)(r + 2);
         if (tid == 0) s_moves = 0;
         for (int s = 0; s < kSub; ++s) {
@@ -981,22 +1062,34 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                           c1 = s_cnt[3 * s + 2];
             // rate, tier 0: one lane per node
             for (int32_t i = tid; i < c0; i += kSmallBlock) {
-                const int32_t v = order[o0 + i];
-                if (r > 0 && act[v] != stamp) continue;
-                const uint32_t own = (uint32_t)p.label[v];
+                const int32_t li = s_ord[o0 + i];
+                if (r > 0 && act[li] != stamp) continue;
+                const int32_t v = start + li;
+                const uint32_t own = (uint32_t)s_lab[li];
                 const int32_t e0 = a.xadj[v];
                 const int32_t d = a.xadj[v + 1] - e0;
                 const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
-                const NodeKey nk = node_key(a, v);
-                if (ballot64(d > T0_NARROW)) rate_lane_node<T0_DEG, EW, CAPV, false>(a, v, own, e0, d, cv, nk);
-                else rate_lane_node<T0_NARROW, EW, CAPV, false>(a, v, own, e0, d, cv, nk);
+                Key3 fav{0, 0, 0}, adm{0, 0, 0};
+                uint32_t rown = 0;
+                if (ballot64(d > T0_NARROW))
+                    rate_lane_local<T0_DEG, EW, CAPV>(a, v, start, lo, own, e0, d, cv, nk, s_lab, s_wt, fav, adm,
+                                                      rown);
+                else
+                    rate_lane_local<T0_NARROW, EW, CAPV>(a, v, start, lo, own, e0, d, cv, nk, s_lab, s_wt, fav,
+                                                         adm, rown);
+                if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
+                if (adm.r > rown) {
+                    s_prop[li] = (int16_t)adm.k;
+                    atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                }
                 edges += d;
                 nodes += 1;
             }
             // rate, tier 1: one wavefront per node (the loop is uniform in the wave)
             for (int32_t i = wv; i < c1; i += NW) {
-                const int32_t v = order[o1 + i];
-                if (r > 0 && act[v] != stamp) continue;
+                const int32_t li = s_ord[o1 + i];
+                if (r > 0 && act[li] != stamp) continue;
+                const int32_t v = start + li;
                 for (int j = lane; j < HS; j += 64) {
                     keys[j] = EMPTY;
                     vals[j] = 0;
@@ -1005,21 +1098,37 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 __builtin_amdgcn_wave_barrier();
                 const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
                 for (int32_t e = e0 + lane; e < e1; e += 64)
-                    lds_insert(keys, vals, HB, (uint32_t)p.label[a.adjncy[e]], EW ? (uint32_t)a.adjwgt[e] : 1u);
+                    lds_insert(keys, vals, HB, (uint32_t)s_lab[a.adjncy[e] - start], EW ? (uint32_t)a.adjwgt[e] : 1u);
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();
-                const uint32_t own = (uint32_t)p.label[v];
-                const NodeKey nk = node_key(a, v);
+                const uint32_t own = (uint32_t)s_lab[li];
                 const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
                 Key3 fav{0, 0, 0}, adm{0, 0, 0};
                 uint32_t rown = 0;
-                for (int j = lane; j < HS; j += 64) consider(a, nk, keys[j], vals[j], own, cv, fav, adm, rown);
+                for (int j = lane; j < HS; j += 64) {
+                    const uint32_t key = keys[j], val = vals[j];
+                    if (key == EMPTY) continue;
+                    if (key == own) {
+                        rown = val;
+                        continue;
+                    }
+                    const Key3 c{val, hash_step(nk.hp, key, 4), key};
+                    if (better(c, fav)) fav = c;
+                    if (better(c, adm)) {
+                        const int64_t ck = CAPV ? a.cap_vec[lo + key] : nk.cap;
+                        if (s_wt[key] + cv <= ck) adm = c;
+                    }
+                }
                 fav = group_best<64>(fav);
                 adm = group_best<64>(adm);
 #pragma unroll
                 for (int dd = 32; dd > 0; dd >>= 1) rown += __shfl_xor(rown, dd, 64);
                 if (lane == 0) {
-                    write_result(a, v, fav, adm, rown, cv);
+                    if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
+                    if (adm.r > rown) {
+                        s_prop[li] = (int16_t)adm.k;
+                        atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                    }
                     edges += e1 - e0;
                     nodes += 1;
                 }
@@ -1031,18 +1140,17 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             // admission at the sub-round start weights (no weight changes until the apply step)
             const int32_t total = c0 + c1;
             for (int32_t i = tid; i < total; i += kSmallBlock) {
-                const int32_t v = order[i < c0 ? o0 + i : o1 + (i - c0)];
-                const int32_t K = a.prop[v];
+                const int32_t li = s_ord[i < c0 ? o0 + i : o1 + (i - c0)];
+                const int32_t K = s_prop[li];
                 if (K < 0) continue;
-                const int64_t wK = p.wt[K];
-                if (wK + (int64_t)a.demand[K] <= cap_for(p.caps, (uint32_t)K, (uint32_t)v)) {
-                    p.acc[v] = 1;
+                const int64_t wK = s_wt[K];
+                const int64_t cap = CAPV ? a.cap_vec[lo + K] : nk.cap;
+                if (wK + (int64_t)s_dem[K] <= cap) {
+                    s_acc[li] = 1;
                 } else {
-                    p.acc[v] = 2;
-                    p.wsnap[K] = wK;  // every proposal into K writes the same value
-                    const int32_t slot = start + atomicAdd(&s_cont, 1);
-                    p.ckeys[slot] = (uint32_t)K;
-                    p.cvals[slot] = (uint32_t)v;
+                    s_acc[li] = 2;
+                    s_ws[K] = (int32_t)wK;  // every proposal into K writes the same value
+                    p.cont[start + atomicAdd(&s_cont, 1)] = ((uint32_t)K << 16) | (uint32_t)li;
                 }
             }
             __syncthreads();
@@ -1051,12 +1159,12 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             // the admitted moves and mark the neighbours of moved nodes for round r + 1
             for (int32_t i0 = 0; i0 < total; i0 += kSmallBlock) {
                 const int32_t i = i0 + tid;
-                int32_t v = -1, K = -1;
+                int32_t li = -1, K = -1;
                 uint8_t ac = 0;
                 if (i < total) {
-                    v = order[i < c0 ? o0 + i : o1 + (i - c0)];
-                    K = a.prop[v];
-                    if (K >= 0) ac = p.acc[v];
+                    li = s_ord[i < c0 ? o0 + i : o1 + (i - c0)];
+                    K = s_prop[li];
+                    if (K >= 0) ac = s_acc[li];
                 }
                 const bool contended = ac == 2;
                 if (C > 0 && __syncthreads_or(contended)) {
@@ -1064,33 +1172,38 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                     for (int32_t q0 = 0; q0 < C; q0 += kCandChunk) {
                         const int len = C - q0 < kCandChunk ? C - q0 : kCandChunk;
                         for (int j = tid; j < len; j += kSmallBlock) {
-                            const uint32_t u = p.cvals[start + q0 + j];
-                            s_kv[j] = ((uint64_t)p.ckeys[start + q0 + j] << 32) | u;
-                            s_w[j] = a.vwgt ? a.vwgt[u] : 1;
+                            const uint32_t kv = p.cont[start + q0 + j];
+                            s_kv[j] = kv;
+                            s_w[j] = a.vwgt ? a.vwgt[start + (int32_t)(kv & 0xFFFFu)] : 1;
                         }
                         __syncthreads();
                         if (contended) {
-                            const uint64_t lo = (uint64_t)(uint32_t)K << 32, hi = lo | (uint32_t)v;
-                            for (int j = 0; j < len; ++j) pre += (s_kv[j] >= lo && s_kv[j] <= hi) ? s_w[j] : 0;
+                            // entries of target K with local id <= li
+                            const uint32_t klo = (uint32_t)K << 16, khi = klo | (uint32_t)li;
+                            for (int j = 0; j < len; ++j) pre += (s_kv[j] >= klo && s_kv[j] <= khi) ? s_w[j] : 0;
                         }
                         __syncthreads();
                     }
-                    if (contended) ac = p.wsnap[K] + pre <= cap_for(p.caps, (uint32_t)K, (uint32_t)v) ? 1 : 0;
+                    if (contended) {
+                        const int64_t cap = CAPV ? a.cap_vec[lo + K] : nk.cap;
+                        ac = (int64_t)s_ws[K] + pre <= cap ? 1 : 0;
+                    }
                 }
                 if (K < 0) continue;
                 if (ac == 1) {
-                    const int64_t c = a.vwgt ? a.vwgt[v] : 1;
-                    const int32_t old = p.label[v];
-                    p.label[v] = K;
-                    atomicAdd((unsigned long long*)&p.wt[K], (unsigned long long)c);
-                    atomicAdd((unsigned long long*)&p.wt[old], (unsigned long long)(-c));
+                    const int32_t v = start + li;
+                    const int32_t c = a.vwgt ? a.vwgt[v] : 1;
+                    const int32_t old = s_lab[li];
+                    s_lab[li] = (int16_t)K;
+                    atomicAdd(&s_wt[K], c);
+                    atomicAdd(&s_wt[old], -c);
                     if (r + 1 < kRounds)
-                        for (int32_t e = a.xadj[v]; e < a.xadj[v + 1]; ++e) act_next[a.adjncy[e]] = stamp_next;
+                        for (int32_t e = a.xadj[v]; e < a.xadj[v + 1]; ++e) act_next[a.adjncy[e] - start] = stamp_next;
                     atomicAdd(&s_moves, 1);
                 }
-                a.prop[v] = -1;
-                p.acc[v] = 0;
-                a.demand[K] = 0;
+                s_prop[li] = -1;
+                s_acc[li] = 0;
+                s_dem[K] = 0;
             }
             __syncthreads();
         }
@@ -1102,6 +1215,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             break;
         }
     }
+    for (int32_t i = tid; i < nj; i += kSmallBlock) p.label[start + i] = lo + s_lab[i];
+    for (int32_t k = tid; k < nl; k += kSmallBlock) p.wt[lo + k] = s_wt[k];
     if (tid == 0) atomicMax((unsigned long long*)&p.out[kRounds], (unsigned long long)rounds);
     flush_stats(a, nodes, edges);
 }
@@ -1414,22 +1529,32 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
 
 namespace {
 
-// A graph's level runs the one-workgroup LP when it is small and its nodes all
-// sit in rating tiers 0 and 1 (degree <= T1_DEG), unless the exact admission
-// path is forced.
-bool small_level(const Ctx& c, const DGraph& g, const LPSchedule& sched)
+// A graph's level runs the one-workgroup LP when it is small, its state fits in
+// LDS and its nodes all sit in rating tiers 0 and 1 (degree <= T1_DEG), unless
+// the exact admission path is forced.
+bool small_level(const Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t nlab)
 {
-    const int32_t limit = small_limit(c);
-    if (limit < 0 || g.n > limit) return false;
+    if (!small_job_fits(c, g.n, nlab)) return false;
     for (int j = 2 * kSub; j < kSegs; ++j)
         if (sched.cnt[j]) return false;
     return true;
 }
 
-// The LP of the given jobs (node ranges), one workgroup each.
+template <bool EW, bool CAPV>
+void launch_small(Ctx& c, unsigned jobs, size_t lds, const SmallLP& p)
+{
+    static std::once_flag once;  // LDS beyond the 64 KiB default, once per instantiation
+    std::call_once(once, [] {
+        (void)hipFuncSetAttribute((const void*)k_lp_small<EW, CAPV>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)kSmallLdsBudget);
+    });
+    KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<EW, CAPV>), dim3(jobs), dim3(kSmallBlock), lds, p);
+}
+
+// The LP of the given jobs (node ranges and label ranges), one workgroup each.
 LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPState& st, LPBuffers& b,
-                     const std::vector<int32_t>& start, const std::vector<int32_t>& count, uint8_t* act0,
-                     uint8_t* act1)
+                     const std::vector<int32_t>& start, const std::vector<int32_t>& count,
+                     const std::vector<int32_t>& loff, const std::vector<int32_t>& nlab)
 {
     SmallLP p;
     memset(&p, 0, sizeof(p));
@@ -1439,31 +1564,31 @@ LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSt
     p.a.bytes_ctr = c.spread(SP_BYTES + KMP_PROF_LP_SMALL);
     p.label = st.label;
     p.wt = st.wt;
-    std::vector<int32_t> ranges(start);
-    ranges.insert(ranges.end(), count.begin(), count.end());
-    DBuf<int32_t> dr(c, ranges.size());
-    c.write(dr.p, ranges.data(), sizeof(int32_t) * ranges.size());
-    p.jstart = dr.p;
-    p.jcount = dr.p + start.size();
+    const size_t nj = start.size();
+    std::vector<int32_t> tab;
+    tab.reserve(4 * nj);
+    tab.insert(tab.end(), start.begin(), start.end());
+    tab.insert(tab.end(), count.begin(), count.end());
+    tab.insert(tab.end(), loff.begin(), loff.end());
+    tab.insert(tab.end(), nlab.begin(), nlab.end());
+    DBuf<int32_t> dt(c, tab.size());
+    c.write(dt.p, tab.data(), sizeof(int32_t) * tab.size());
+    p.jstart = dt.p;
+    p.jcount = dt.p + nj;
+    p.jloff = dt.p + 2 * nj;
+    p.jnlab = dt.p + 3 * nj;
     p.hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
     for (int r = 0; r < kRounds; ++r) p.hpre[r] = hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r});
     p.cut0 = c.tune.cut[0];
-    DBuf<int32_t> lists(c, (size_t)g.n);
-    p.lists = lists.p;
-    p.act[0] = act0;
-    p.act[1] = act1;
-    p.acc = b.acc.p;
-    p.ckeys = b.ckeys.p;
-    p.cvals = b.cvals.p;
-    p.wsnap = b.base.p;
-    p.caps = cap_args(st);
+    p.cont = b.ckeys.p;
     p.out = b.sout.p;
+    int64_t lds = 0;
+    for (size_t q = 0; q < nj; ++q) lds = std::max(lds, small_lds_bytes(count[q], nlab[q]));
     const bool ew = g.adjwgt != nullptr, capv = st.cap_vec != nullptr;
-    const dim3 grid((unsigned)start.size()), block(kSmallBlock);
-    if (ew && capv) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<true, true>), grid, block, 0, p);
-    else if (ew) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<true, false>), grid, block, 0, p);
-    else if (capv) KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<false, true>), grid, block, 0, p);
-    else KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<false, false>), grid, block, 0, p);
+    if (ew && capv) launch_small<true, true>(c, (unsigned)nj, (size_t)lds, p);
+    else if (ew) launch_small<true, false>(c, (unsigned)nj, (size_t)lds, p);
+    else if (capv) launch_small<false, true>(c, (unsigned)nj, (size_t)lds, p);
+    else launch_small<false, false>(c, (unsigned)nj, (size_t)lds, p);
     int64_t h[kRounds + 1];
     c.read(h, b.sout.p, sizeof(h));
     LPStats out;
@@ -1478,6 +1603,12 @@ int32_t small_limit(const Ctx& c)
 {
     if (c.force_exact) return -1;
     return c.small_level_n != 0 ? c.small_level_n : c.tune.small_level_n;
+}
+
+bool small_job_fits(const Ctx& c, int32_t nodes, int32_t labels)
+{
+    const int32_t limit = small_limit(c);
+    return limit >= 0 && nodes > 0 && nodes <= limit && small_lds_bytes(nodes, labels) <= kSmallLdsBudget;
 }
 
 namespace {
@@ -1591,15 +1722,19 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     const int32_t n = g.n;
     if (n == 0) return LPStats();
     // jobs that run the one-workgroup LP; the others take the launch-per-step path
-    std::vector<int32_t> ss, sc;
+    std::vector<int32_t> ss, sc, sl, sn;
     if (!st.jt.gid) {
-        if (small_level(c, g, sched)) {
+        if (small_level(c, g, sched, st.nlab)) {
             ss.assign(1, 0);
             sc.assign(1, n);
+            sl.assign(1, 0);
+            sn.assign(1, st.nlab);
         }
     } else {
         ss = st.small_start;
         sc = st.small_count;
+        sl = st.small_loff;
+        sn = st.small_nlab;
     }
     int64_t small_nodes = 0;
     for (int32_t x : sc) small_nodes += x;
@@ -1608,16 +1743,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     lp_buffers(c, g, sched, st.nlab, b);
     LPStats small;
     if (!ss.empty()) {
-        uint8_t* act0 = b.active.p;
-        uint8_t* act1 = b.mflag.p;
-        DBuf<uint8_t> sact;
-        if (!all_small) {  // the other jobs' rounds use active / mflag
-            sact = DBuf<uint8_t>(c, 2 * (size_t)n);
-            c.zero(sact.p, 2 * (size_t)n);
-            act0 = sact.p;
-            act1 = sact.p + n;
-        }
-        small = lp_run_small(c, g, level, seed, st, b, ss, sc, act0, act1);
+        small = lp_run_small(c, g, level, seed, st, b, ss, sc, sl, sn);
         if (all_small) return small;
     }
     LPStats out = lp_rounds(c, g, level, seed, sched, st, b, st.small_jobs);
