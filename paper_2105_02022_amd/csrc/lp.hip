@@ -808,7 +808,14 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int64_t* __restric
              i += (int64_t)gridDim.x * blockDim.x) {
             const int32_t v = list[off + i];
             if (mflag[v] != stamp) continue;
-            for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e) active[adjncy[e]] = stamp;
+            const int32_t e0 = xadj[v], e1 = xadj[v + 1];
+            for (int32_t eb = e0; eb < e1; eb += 8) {  // 8 neighbour ids per batch of loads
+                int32_t u[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) u[q] = adjncy[eb + q < e1 ? eb + q : e1 - 1];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) active[u[q]] = stamp;
+            }
         }
         return;
     }
@@ -1057,6 +1064,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
         uint8_t* act_next = s_act[(r + 1) & 1];
         const uint8_t stamp = (uint8_t)(r + 1), stamp_next = (uint8_t)(r + 2);
         if (tid == 0) s_moves = 0;
+        int32_t mine = 0;  // moves applied by this thread in round r
         for (int s = 0; s < kSub; ++s) {
             const int32_t o0 = s_off[3 * s], c0 = s_cnt[3 * s] + s_cnt[3 * s + 1], o1 = s_off[3 * s + 2],
                           c1 = s_cnt[3 * s + 2];
@@ -1137,7 +1145,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             }
             if (tid == 0) s_cont = 0;
             __syncthreads();
-            // admission at the sub-round start weights (no weight changes until the apply step)
+            // admission at the sub-round start weights (no weight changes until the apply step);
+            // contended proposals are listed (target << 16 | node, local ids) with their weights
             const int32_t total = c0 + c1;
             for (int32_t i = tid; i < total; i += kSmallBlock) {
                 const int32_t li = s_ord[i < c0 ? o0 + i : o1 + (i - c0)];
@@ -1150,13 +1159,35 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 } else {
                     s_acc[li] = 2;
                     s_ws[K] = (int32_t)wK;  // every proposal into K writes the same value
-                    p.cont[start + atomicAdd(&s_cont, 1)] = ((uint32_t)K << 16) | (uint32_t)li;
+                    const int32_t slot = atomicAdd(&s_cont, 1);
+                    const uint32_t kv = ((uint32_t)K << 16) | (uint32_t)li;
+                    const int32_t w = a.vwgt ? a.vwgt[start + li] : 1;
+                    if (slot < kCandChunk) {
+                        s_kv[slot] = kv;
+                        s_w[slot] = w;
+                    }
+                    p.cont[start + slot] = kv;
                 }
             }
             __syncthreads();
             const int32_t C = s_cont;
-            // contended targets: the longest prefix in id order that fits; then apply
-            // the admitted moves and mark the neighbours of moved nodes for round r + 1
+            // contended targets: the longest prefix in id order that fits.  Up to
+            // kCandChunk entries, every entry finds its prefix in the LDS list;
+            // longer lists are staged through LDS in chunks per node.
+            if (C > 0 && C <= kCandChunk) {
+                for (int32_t t = tid; t < C; t += kSmallBlock) {
+                    const uint32_t kv = s_kv[t];
+                    const uint32_t klo = kv & 0xFFFF0000u;
+                    int64_t pre = 0;
+#pragma unroll 8
+                    for (int j = 0; j < C; ++j) pre += (s_kv[j] >= klo && s_kv[j] <= kv) ? s_w[j] : 0;
+                    const int32_t K = (int32_t)(kv >> 16);
+                    const int64_t cap = CAPV ? a.cap_vec[lo + K] : nk.cap;
+                    s_acc[kv & 0xFFFFu] = (int64_t)s_ws[K] + pre <= cap ? 1 : 0;
+                }
+                __syncthreads();
+            }
+            // apply the admitted moves and mark the neighbours of moved nodes for round r + 1
             for (int32_t i0 = 0; i0 < total; i0 += kSmallBlock) {
                 const int32_t i = i0 + tid;
                 int32_t li = -1, K = -1;
@@ -1166,8 +1197,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                     K = s_prop[li];
                     if (K >= 0) ac = s_acc[li];
                 }
-                const bool contended = ac == 2;
-                if (C > 0 && __syncthreads_or(contended)) {
+                const bool contended = ac == 2;  // only when C > kCandChunk
+                if (C > kCandChunk && __syncthreads_or(contended)) {
                     int64_t pre = 0;
                     for (int32_t q0 = 0; q0 < C; q0 += kCandChunk) {
                         const int len = C - q0 < kCandChunk ? C - q0 : kCandChunk;
@@ -1180,6 +1211,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                         if (contended) {
                             // entries of target K with local id <= li
                             const uint32_t klo = (uint32_t)K << 16, khi = klo | (uint32_t)li;
+#pragma unroll 8
                             for (int j = 0; j < len; ++j) pre += (s_kv[j] >= klo && s_kv[j] <= khi) ? s_w[j] : 0;
                         }
                         __syncthreads();
@@ -1197,9 +1229,18 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                     s_lab[li] = (int16_t)K;
                     atomicAdd(&s_wt[K], c);
                     atomicAdd(&s_wt[old], -c);
-                    if (r + 1 < kRounds)
-                        for (int32_t e = a.xadj[v]; e < a.xadj[v + 1]; ++e) act_next[a.adjncy[e] - start] = stamp_next;
-                    atomicAdd(&s_moves, 1);
+                    if (r + 1 < kRounds) {
+                        // neighbour ids in batches of 8 loads issued together
+                        const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
+                        for (int32_t eb = e0; eb < e1; eb += 8) {
+                            int32_t u[8];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) u[q] = a.adjncy[eb + q < e1 ? eb + q : e1 - 1];
+#pragma unroll
+                            for (int q = 0; q < 8; ++q) act_next[u[q] - start] = stamp_next;
+                        }
+                    }
+                    ++mine;
                 }
                 s_prop[li] = -1;
                 s_acc[li] = 0;
@@ -1207,6 +1248,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             }
             __syncthreads();
         }
+        for (int dd = 32; dd > 0; dd >>= 1) mine += __shfl_xor(mine, dd, 64);
+        if (lane == 0 && mine) atomicAdd(&s_moves, mine);
+        __syncthreads();
         const int32_t moved = s_moves;
         if (tid == 0 && moved) atomicAdd((unsigned long long*)&p.out[r], (unsigned long long)moved);
         __syncthreads();  // every thread has read s_moves before the next round clears it
