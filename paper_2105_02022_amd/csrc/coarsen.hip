@@ -481,12 +481,13 @@ int64_t two_hop_core(Ctx& c, const DGraph& g, const JobTabs& jt, int64_t U, int6
     hipLaunchKernelGGL(k_singleton_compact, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, flag.p, pos.p, fav, n,
                        jt.gid, gend, keys.p, vals.p);
     KMP_LAUNCH_CHECK();
-    radix_sort_pairs(c, keys.p, vals.p, k2.p, v2.p, ns, bits_for(2 * (uint64_t)n));
+    uint32_t *skeys = nullptr, *svals = nullptr;  // the sorted pairs (first or alternate buffers)
+    radix_sort_pairs(c, keys.p, vals.p, k2.p, v2.p, ns, bits_for(2 * (uint64_t)n), &skeys, &svals);
     DBuf<int32_t> gstart(c, ns), elig(c, (size_t)ns + 1);
-    hipLaunchKernelGGL(k_group_heads, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, keys.p, (int64_t)ns, gstart.p);
+    hipLaunchKernelGGL(k_group_heads, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, skeys, (int64_t)ns, gstart.p);
     KMP_LAUNCH_CHECK();
     scan_incl_max_i32(c, gstart.p, gstart.p, ns);
-    hipLaunchKernelGGL(k_pair_eligible, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, keys.p, vals.p, gstart.p,
+    hipLaunchKernelGGL(k_pair_eligible, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, skeys, svals, gstart.p,
                        (int64_t)ns, g.vwgt, U, jt.gid, gU, elig.p);
     KMP_LAUNCH_CHECK();
     DBuf<int32_t> rank(c, (size_t)ns + 1);
@@ -494,11 +495,11 @@ int64_t two_hop_core(Ctx& c, const DGraph& g, const JobTabs& jt, int64_t U, int6
     DBuf<int32_t> grank0;
     if (jt.gid) {
         grank0 = DBuf<int32_t>(c, (size_t)njobs);
-        hipLaunchKernelGGL(k_job_rank0, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, vals.p, jt.gid, rank.p,
+        hipLaunchKernelGGL(k_job_rank0, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, svals, jt.gid, rank.p,
                            (int64_t)ns, grank0.p);
         KMP_LAUNCH_CHECK();
     }
-    hipLaunchKernelGGL(k_pair_apply, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, vals.p, elig.p, rank.p,
+    hipLaunchKernelGGL(k_pair_apply, dim3(grid_for(ns)), dim3(kBlock), 0, c.stream, svals, elig.p, rank.p,
                        (int64_t)ns, limit, jt.gid, glimit, grank0.p, g.vwgt, label, cw);
     KMP_LAUNCH_CHECK();
     return count ? (int64_t)c.read1(rank.p + ns) : 0;
@@ -558,11 +559,11 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     hipLaunchKernelGGL(k_map_and_weights, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, label, cid.p, cw, g.xadj, n,
                        jt.gid, gkeep, map, out.vwgt.p, mstart.p, dstart.p);
     KMP_LAUNCH_CHECK();
-    // keep the per-row fine degree sums before turning them into offsets
-    DBuf<int32_t> dsum(c, (size_t)nc + 1);
-    KMP_HIP(hipMemcpyAsync(dsum.p, dstart.p, sizeof(int32_t) * (size_t)nc, hipMemcpyDeviceToDevice, c.stream));
+    // dsum keeps the per-row fine degree sums; dstart receives their offsets
+    DBuf<int32_t> dsum = std::move(dstart);
+    dstart = DBuf<int32_t>(c, (size_t)nc + 1);
     scan_excl_i32(c, mstart.p, mstart.p, nc, mstart.p + nc);
-    scan_excl_i32(c, dstart.p, dstart.p, nc, dstart.p + nc);
+    scan_excl_i32(c, dsum.p, dstart.p, nc, dstart.p + nc);
     DBuf<int32_t> members(c, (size_t)n);
     hipLaunchKernelGGL(k_place_members, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, map, n, mstart.p, cursor.p,
                        members.p);
@@ -571,10 +572,11 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     DBuf<uint32_t> rk(c, nc), rv(c, nc), rk2(c, nc), rv2(c, nc);
     hipLaunchKernelGGL(k_row_tiers, dim3(grid_for(nc, kBlock, 256)), dim3(kBlock), 0, c.stream, dsum.p, nc, rk.p, rv.p, cnt4.p);
     KMP_LAUNCH_CHECK();
-    radix_sort_pairs(c, rk.p, rv.p, rk2.p, rv2.p, nc, 2);
+    uint32_t* rsorted = nullptr;
+    radix_sort_pairs(c, rk.p, rv.p, rk2.p, rv2.p, nc, 2, nullptr, &rsorted);
     int32_t tc[4];
     c.read(tc, cnt4.p, sizeof(tc));
-    const int32_t* rows = reinterpret_cast<const int32_t*>(rv.p);
+    const int32_t* rows = reinterpret_cast<const int32_t*>(rsorted);
     DBuf<int32_t> tmp_adj(c, (size_t)(g.m > 0 ? g.m : 1)), tmp_w(c, (size_t)(g.m > 0 ? g.m : 1));
     DBuf<int32_t> cdeg(c, (size_t)nc + 1);
     RowArgs a;

@@ -393,10 +393,11 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         hipLaunchKernelGGL(k_block_count, dim3(grid_for(n, kBlock, 256)), dim3(kBlock), 0, c.stream, part, g.xadj, n, nb,
                            bstart_p, bdeg_p, key.p, verts.p);
         KMP_LAUNCH_CHECK();
-        radix_sort_pairs(c, key.p, verts.p, k2.p, v2.p, n, bits_for((uint64_t)(nb - 1)));
+        uint32_t* vsorted = nullptr;  // the block-sorted vertices (verts or v2)
+        radix_sort_pairs(c, key.p, verts.p, k2.p, v2.p, n, bits_for((uint64_t)(nb - 1)), nullptr, &vsorted);
         scan_excl_i32(c, bstart_p, bstart_p, nb, bstart_p + nb);
         DBuf<int32_t> local(c, (size_t)n);
-        hipLaunchKernelGGL(k_local_ids, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, verts.p, part, bstart_p, n,
+        hipLaunchKernelGGL(k_local_ids, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, vsorted, part, bstart_p, n,
                            local.p);
         KMP_LAUNCH_CHECK();
         std::vector<int32_t> hbd(2 * (size_t)nb + 1);
@@ -434,7 +435,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         a.vwgt = g.vwgt;
         a.adjwgt = g.adjwgt;
         a.part = part;
-        a.verts = verts.p;
+        a.verts = vsorted;
         a.bstart = bstart_p;
         a.local = local.p;
         a.side = side.p;

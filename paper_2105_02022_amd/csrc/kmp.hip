@@ -525,6 +525,9 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
 {
     const int32_t nj = (int32_t)jobs.size();
     const bool phase_sync = opt && opt->profile >= 2;
+    // moves of the one-workgroup LP calls (clustering, refinement), read once at the end
+    DBuf<int64_t> dmoves(c, 2 * (kRounds + 1));
+    c.zero(dmoves.p, sizeof(int64_t) * 2 * (kRounds + 1));
     std::vector<std::unique_ptr<Level>> lv;
     lv.emplace_back(new Level());
     if (batch) {
@@ -592,6 +595,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         LPState ls{label.p, cw.p, g.n, nullptr, batch ? 0 : U[0], fav.p, TAG_CL, jt,
                    batch ? L.dnoff.p : nullptr, batch ? dU.p : nullptr};
         if (batch) pick_small_jobs(c, L, &takes, nj, ls);
+        ls.moves_out = dmoves.p;
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_cl += lps.moves[r];
         t.exact += lps.exact_subrounds;
@@ -757,6 +761,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
             for (int32_t b = 0; b < nb; ++b) ++nbk[bt.job[b]];
             pick_small_jobs(c, L, nullptr, nj, ls, &boff, &nbk);
         }
+        ls.moves_out = dmoves.p + kRounds + 1;
         LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_ref += lps.moves[r];
         t.exact += lps.exact_subrounds;
@@ -790,6 +795,12 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
     }
     for (int32_t j : L0.mem) jobs[j].status = jobs[j].maxw > jobs[j].lk ? KMP_IMBALANCED : KMP_OK;
     t.rated = c.read_spread(SP_RATED);
+    int64_t hm[2 * (kRounds + 1)];
+    c.read(hm, dmoves.p, sizeof(hm));
+    for (int r = 0; r < kRounds; ++r) {
+        t.moves_cl += hm[r];
+        t.moves_ref += hm[kRounds + 1 + r];
+    }
 }
 
 // Derived integers of a job (Sec. 2 balance constraint, Sec. 5.1); k = 1 and

@@ -402,10 +402,12 @@ void scan_excl_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n, int32_t* 
 void scan_incl_i64(Ctx& c, const int64_t* in, int64_t* out, int64_t n);
 // Inclusive max-scan of n int32 values.
 void scan_incl_max_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n);
-// Stable LSD radix sort of (key, value) pairs by key, keys < 2^key_bits.
-// Results end in keys/vals (the alt buffers are scratch of the same size).
+// Stable LSD radix sort of (key, value) pairs by key, keys < 2^key_bits (the
+// alt buffers are scratch of the same size).  With out_keys / out_vals NULL
+// the result ends in keys / vals; otherwise they receive the buffers that hold
+// it (the alt ones after an odd number of passes) and nothing is copied.
 void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                      int key_bits);
+                      int key_bits, uint32_t** out_keys = nullptr, uint32_t** out_vals = nullptr);
 // Several byte fills in one launch (at most kMaxFills buffers).
 constexpr int kMaxFills = 8;
 struct ByteFill {
@@ -454,6 +456,9 @@ struct LPState {
     // each), with their first node and node count at this level
     int32_t njobs = 0;
     std::vector<int32_t> small_jobs, small_start, small_count, small_loff, small_nlab;
+    // when set, the one-workgroup LP adds its moves per round (and the largest
+    // round count) here instead of returning them: no read-back per call
+    int64_t* moves_out = nullptr;  // [kRounds + 1], zeroed by the caller
 };
 
 // Largest level (nodes) of the one-workgroup LP for this call; -1: never.

@@ -928,9 +928,10 @@ struct SmallLP {
     int32_t* label;           // [n] global labels (read at the start, written at the end)
     int64_t* wt;              // [nlab] global label weights (same)
     const int32_t* jstart;    // by workgroup: the job's first node, node count, first label, label count
-    const int32_t* jcount;
+    const int32_t* jcount;    // (all NULL for one job: then `one` holds the four values)
     const int32_t* jloff;
     const int32_t* jnlab;
+    int32_t one[4];
     uint32_t hsub;            // one graph: H prefix over (seed; T_SUB, level) of the sub-round classes
     uint32_t hpre[kRounds];   // one graph: H prefix over (seed; tag, level, round) of every round
     int32_t cut0;             // largest degree rated one per lane (tier 0)
@@ -1005,8 +1006,10 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     uint32_t* keys = s_keys + wv * HS;
     uint32_t* vals = s_vals + wv * HS;
-    const int32_t start = p.jstart[blockIdx.x], nj = p.jcount[blockIdx.x];
-    const int32_t lo = p.jloff[blockIdx.x], nl = p.jnlab[blockIdx.x];
+    const int32_t start = p.jstart ? p.jstart[blockIdx.x] : p.one[0];
+    const int32_t nj = p.jstart ? p.jcount[blockIdx.x] : p.one[1];
+    const int32_t lo = p.jstart ? p.jloff[blockIdx.x] : p.one[2];
+    const int32_t nl = p.jstart ? p.jnlab[blockIdx.x] : p.one[3];
     int32_t* s_wt = reinterpret_cast<int32_t*>(s_dyn);
     int32_t* s_dem = s_wt + nl;
     int32_t* s_ws = s_dem + nl;
@@ -1283,7 +1286,8 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
         c.zero(sched.segtab.p, sizeof(int32_t) * 2 * kSegs);
         return;
     }
-    DBuf<uint32_t> key(c, n), val(c, n), key2(c, n), val2(c, n);
+    DBuf<uint32_t> key(c, n), key2(c, n);
+    DBuf<int32_t> val(c, n), val2(c, n);
     const int32_t nj = jt.gid ? njobs : 0;
     DBuf<int32_t> cnt(c, (size_t)(kSegs + 1 + nj));  // segment sizes, then the jobs' largest degrees
     c.zero(cnt.p, (kSegs + 1 + nj) * sizeof(int32_t));
@@ -1292,11 +1296,14 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
         ProfScope ps(c, KMP_PROF_SCHEDULE);
         const TierCuts tc{{c.tune.cut[0], c.tune.cut[1], c.tune.cut[2], c.tune.cut[3]}};
         hipLaunchKernelGGL(k_sched_keys, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub, jt, gpart,
-                           (uint32_t)level, tc, key.p, val.p, cnt.p, nj ? cnt.p + kSegs + 1 : nullptr);
+                           (uint32_t)level, tc, key.p, reinterpret_cast<uint32_t*>(val.p), cnt.p,
+                           nj ? cnt.p + kSegs + 1 : nullptr);
         KMP_LAUNCH_CHECK();
     }
-    radix_sort_pairs(c, key.p, val.p, key2.p, val2.p, n, bits_for(2 * kSegs + 1));
-    KMP_HIP(hipMemcpyAsync(sched.order.p, val.p, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, c.stream));
+    uint32_t* sorted = nullptr;
+    radix_sort_pairs(c, key.p, reinterpret_cast<uint32_t*>(val.p), key2.p, reinterpret_cast<uint32_t*>(val2.p), n,
+                     bits_for(2 * kSegs + 1), nullptr, &sorted);
+    sched.order = reinterpret_cast<int32_t*>(sorted) == val.p ? std::move(val) : std::move(val2);
     std::vector<int32_t> hv((size_t)(kSegs + 1 + nj));
     c.read(hv.data(), cnt.p, sizeof(int32_t) * hv.size());
     const int32_t* h = hv.data();
@@ -1609,23 +1616,31 @@ LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSt
     p.label = st.label;
     p.wt = st.wt;
     const size_t nj = start.size();
-    std::vector<int32_t> tab;
-    tab.reserve(4 * nj);
-    tab.insert(tab.end(), start.begin(), start.end());
-    tab.insert(tab.end(), count.begin(), count.end());
-    tab.insert(tab.end(), loff.begin(), loff.end());
-    tab.insert(tab.end(), nlab.begin(), nlab.end());
-    DBuf<int32_t> dt(c, tab.size());
-    c.write(dt.p, tab.data(), sizeof(int32_t) * tab.size());
-    p.jstart = dt.p;
-    p.jcount = dt.p + nj;
-    p.jloff = dt.p + 2 * nj;
-    p.jnlab = dt.p + 3 * nj;
+    DBuf<int32_t> dt;
+    if (nj == 1) {
+        p.one[0] = start[0];
+        p.one[1] = count[0];
+        p.one[2] = loff[0];
+        p.one[3] = nlab[0];
+    } else {
+        std::vector<int32_t> tab;
+        tab.reserve(4 * nj);
+        tab.insert(tab.end(), start.begin(), start.end());
+        tab.insert(tab.end(), count.begin(), count.end());
+        tab.insert(tab.end(), loff.begin(), loff.end());
+        tab.insert(tab.end(), nlab.begin(), nlab.end());
+        dt = DBuf<int32_t>(c, tab.size());
+        c.write(dt.p, tab.data(), sizeof(int32_t) * tab.size());
+        p.jstart = dt.p;
+        p.jcount = dt.p + nj;
+        p.jloff = dt.p + 2 * nj;
+        p.jnlab = dt.p + 3 * nj;
+    }
     p.hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
     for (int r = 0; r < kRounds; ++r) p.hpre[r] = hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r});
     p.cut0 = c.tune.cut[0];
     p.cont = b.ckeys.p;
-    p.out = b.sout.p;
+    p.out = st.moves_out ? st.moves_out : b.sout.p;
     int64_t lds = 0;
     for (size_t q = 0; q < nj; ++q) lds = std::max(lds, small_lds_bytes(count[q], nlab[q]));
     const bool ew = g.adjwgt != nullptr, capv = st.cap_vec != nullptr;
@@ -1633,9 +1648,10 @@ LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSt
     else if (ew) launch_small<true, false>(c, (unsigned)nj, (size_t)lds, p);
     else if (capv) launch_small<false, true>(c, (unsigned)nj, (size_t)lds, p);
     else launch_small<false, false>(c, (unsigned)nj, (size_t)lds, p);
+    LPStats out;
+    if (st.moves_out) return out;  // the caller reads the accumulated counts later
     int64_t h[kRounds + 1];
     c.read(h, b.sout.p, sizeof(h));
-    LPStats out;
     out.rounds = (int32_t)h[kRounds];
     for (int r = 0; r < kRounds; ++r) out.moves[r] = h[r];
     return out;

@@ -598,8 +598,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
 }  // namespace
 
 void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
-                      int key_bits)
+                      int key_bits, uint32_t** out_keys, uint32_t** out_vals)
 {
+    if (out_keys) *out_keys = keys;
+    if (out_vals) *out_vals = vals;
     if (n <= 1 || key_bits <= 0) return;
     const int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
     DBuf<int32_t> hist(c, (size_t)nblk * 256);
@@ -613,6 +615,11 @@ void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt
         KMP_LAUNCH_CHECK();
         std::swap(ks, kd);
         std::swap(vs, vd);
+    }
+    if (out_keys || out_vals) {
+        if (out_keys) *out_keys = ks;
+        if (out_vals) *out_vals = vs;
+        return;
     }
     if (ks != keys) {
         KMP_HIP(hipMemcpyAsync(keys, ks, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, c.stream));
