@@ -183,8 +183,8 @@ __global__ __launch_bounds__(kBlock) void k_bal_apply(const uint32_t* __restrict
 }  // namespace
 
 int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64_t>& seeds,
-                const LPSchedule& sched, int32_t* part, int64_t* wt, const BlockTab& bt, const int64_t* cap,
-                const JobTabs& jt, const int32_t* boff, const std::vector<int64_t>* hcap_in)
+                const std::function<const LPSchedule&()>& sched, int32_t* part, int64_t* wt, const BlockTab& bt,
+                const int64_t* cap, const JobTabs& jt, const int32_t* boff, const std::vector<int64_t>* hcap_in)
 {
     const int32_t n = g.n;
     const int32_t nb = bt.size();
@@ -244,7 +244,7 @@ int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64
         c.write(over.p, hover.data(), (size_t)nb);
         if (batch) c.write(dtstar.p, tstar.data(), sizeof(int32_t) * njobs);
         fill_i32(c, bal_t.p, -1, n);
-        rate_for_balance(c, g, level, seeds[0], round, sched, part, wt, cap, over.p, bal_t.p, bal_d.p, jt, boff);
+        rate_for_balance(c, g, level, seeds[0], round, sched(), part, wt, cap, over.p, bal_t.p, bal_d.p, jt, boff);
         hipLaunchKernelGGL(k_bal_candidates, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, part, over.p, g.vwgt, n,
                            tstar[0], dbjob.p, dtstar.p, wt, cap, bal_t.p, bal_d.p, flag.p, kw0.p, kw1.p, kw2.p, kcls.p);
         KMP_LAUNCH_CHECK();

@@ -536,7 +536,8 @@ int32_t contract_ids(Ctx& c, const DGraph& g, const int64_t* cw, DBuf<int32_t>& 
 }
 
 void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
-              int32_t& cn, int64_t& cm, const JobTabs& jt, const uint8_t* gkeep, DBuf<int32_t>* cid_in, int32_t nc_in)
+              int32_t& cn, int64_t& cm, const JobTabs& jt, const uint8_t* gkeep, DBuf<int32_t>* cid_in, int32_t nc_in,
+              int32_t* maxdeg)
 {
     const int32_t n = g.n;
     DBuf<int32_t> cid_own;
@@ -551,11 +552,11 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
     out.xadj = DBuf<int32_t>(c, (size_t)nc + 1);
     out.vwgt = DBuf<int32_t>(c, (size_t)nc);
     DBuf<int32_t> mstart(c, (size_t)nc + 1), dstart(c, (size_t)nc + 1), cursor(c, (size_t)nc);
-    DBuf<int32_t> cnt4(c, 4);
+    DBuf<int32_t> cnt4(c, 6);  // row tier counts; then the coarse entry count and largest degree
     fill_bytes_many(c, {{mstart.p, 4 * ((int64_t)nc + 1), 0},
                         {dstart.p, 4 * ((int64_t)nc + 1), 0},
                         {cursor.p, 4 * (int64_t)nc, 0},
-                        {cnt4.p, 16, 0}});
+                        {cnt4.p, 24, 0}});
     hipLaunchKernelGGL(k_map_and_weights, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, label, cid.p, cw, g.xadj, n,
                        jt.gid, gkeep, map, out.vwgt.p, mstart.p, dstart.p);
     KMP_LAUNCH_CHECK();
@@ -653,7 +654,9 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
         KMP_LAUNCH_CHECK();
     }
     scan_excl_i32(c, cdeg.p, out.xadj.p, nc, out.xadj.p + nc);
-    cm = c.read1(out.xadj.p + nc);
+    int32_t md = 0;
+    entries_and_max_degree(c, out.xadj.p, nc, cm, md, cnt4.p + 4);
+    if (maxdeg) *maxdeg = md;
     out.adjncy = DBuf<int32_t>(c, (size_t)(cm > 0 ? cm : 1));
     out.adjwgt = DBuf<int32_t>(c, (size_t)(cm > 0 ? cm : 1));
     if (nc > 0) {

@@ -270,12 +270,13 @@ int check_args(const int32_t* xadj, int32_t n, int64_t m, int32_t k, double eps,
     return KMP_OK;
 }
 
-// Checks m == xadj[n] and the int32 bounds of the weight sums; returns c(V).
-int64_t prepare(Ctx& c, const DGraph& g)
+// Checks m == xadj[n] and the int32 bounds of the weight sums; returns c(V)
+// and the largest degree.
+int64_t prepare(Ctx& c, const DGraph& g, int32_t& maxdeg)
 {
-    int32_t xn = 0;
-    c.read(&xn, g.xadj + g.n, sizeof(int32_t));
-    if ((int64_t)xn != g.m) throw Error(KMP_EINVAL, "m != xadj[n]");
+    int64_t xn = 0;
+    entries_and_max_degree(c, g.xadj, g.n, xn, maxdeg);
+    if (xn != g.m) throw Error(KMP_EINVAL, "m != xadj[n]");
     if (g.m > 0 && !g.adjncy) throw Error(KMP_EINVAL, "adjncy is NULL");
     int64_t sums[2] = {node_weight_sum(c, g.vwgt, g.n), edge_weight_sum(c, g.adjwgt, g.m)};
     if (sums[0] > INT32_MAX || sums[1] / 2 > INT32_MAX) throw Error(KMP_EOVERFLOW, "weight sum exceeds int32");
@@ -295,6 +296,7 @@ struct JobRun {
     int32_t kc = 0;           // k' of the coarsening bound (Sec. 5.1)
     int32_t L = -1;           // coarsest level
     int64_t cut = 0, maxw = 0;
+    int32_t maxdeg = -1;      // largest degree of the input (one graph)
     std::vector<int32_t> level_n;
     std::vector<int64_t> level_m;
 };
@@ -315,6 +317,7 @@ struct Level {
     DBuf<int32_t> dnoff, dgend;   // batches: by job, first node / end of the job's node range
     DBuf<int32_t> dmjob;          // batches: by member
     DBuf<int64_t> dmoff;
+    int32_t maxdeg = -1;          // one graph: largest degree (-1: not known)
 };
 
 struct Totals {
@@ -540,6 +543,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         L0.moff = {0, jobs[0].g.n};
         L0.nn = {jobs[0].g.n};
         L0.mm = {jobs[0].g.m};
+        L0.maxdeg = jobs[0].maxdeg;
     }
     std::vector<uint32_t> hseed(nj);
     std::vector<uint64_t> seeds(nj);
@@ -583,9 +587,13 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
             dU = upload(c, U);
             if (!full) dtakes = upload(c, takes);
         }
-        L.sched.reset(new LPSchedule());
-        lp_build_schedule(c, g, l, seed0, *L.sched, jt, dtakes.p, nj);
-        L.sched_full = full;
+        // a small single graph skips the schedule: its LP builds its own class lists
+        const bool small_lp = !batch && L.maxdeg >= 0 && L.maxdeg <= c.tune.cut[1] && small_job_fits(c, g.n, g.n);
+        if (!small_lp) {
+            L.sched.reset(new LPSchedule());
+            lp_build_schedule(c, g, l, seed0, *L.sched, jt, dtakes.p, nj);
+            L.sched_full = full;
+        }
         DBuf<int32_t> label(c, (size_t)g.n);
         DBuf<int64_t> cw(c, (size_t)g.n);
         DBuf<uint32_t> fav(c, (size_t)g.n);
@@ -596,7 +604,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
                    batch ? L.dnoff.p : nullptr, batch ? dU.p : nullptr};
         if (batch) pick_small_jobs(c, L, &takes, nj, ls);
         ls.moves_out = dmoves.p;
-        LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
+        LPStats lps = lp_run(c, g, l, seed0, small_lp ? nullptr : L.sched.get(), ls);
         for (int r = 0; r < kRounds; ++r) t.moves_cl += lps.moves[r];
         t.exact += lps.exact_subrounds;
         std::vector<int64_t> nc;
@@ -640,7 +648,9 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         DBuf<uint8_t> dkeep;
         if (batch) dkeep = upload(c, keep);
         if (batch) contract(c, g, label.p, cw.p, L.map.p, next->own, cn, cm, jt, dkeep.p);
-        else contract(c, g, label.p, cw.p, L.map.p, next->own, cn, cm, jt, nullptr, &cid, (int32_t)nc[0]);
+        else
+            contract(c, g, label.p, cw.p, L.map.p, next->own, cn, cm, jt, nullptr, &cid, (int32_t)nc[0],
+                     &next->maxdeg);
         next->g = next->own.view(cn, cm);
         next->nn.assign(nj, 0);
         next->mm.assign(nj, 0);
@@ -748,13 +758,18 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         c.write(cap.p, hcap.data(), sizeof(int64_t) * nb);
         DBuf<int32_t> dboff;
         if (batch) dboff = upload(c, boff);
-        if (!L.sched || !L.sched_full) {
-            L.sched.reset(new LPSchedule());
-            lp_build_schedule(c, g, l, seed0, *L.sched, jt, nullptr, nj);
-            L.sched_full = true;
-        }
-        t.brounds += balance(c, g, l, batch ? seeds : std::vector<uint64_t>{seed0}, *L.sched, part.p, wt.p, bt, cap.p,
-                             jt, dboff.p, &hcap);
+        auto level_sched = [&]() -> const LPSchedule& {
+            if (!L.sched || !L.sched_full) {
+                L.sched.reset(new LPSchedule());
+                lp_build_schedule(c, g, l, seed0, *L.sched, jt, nullptr, nj);
+                L.sched_full = true;
+            }
+            return *L.sched;
+        };
+        const bool small_lp = !batch && L.maxdeg >= 0 && L.maxdeg <= c.tune.cut[1] && small_job_fits(c, g.n, nb);
+        if (!small_lp) level_sched();
+        t.brounds += balance(c, g, l, batch ? seeds : std::vector<uint64_t>{seed0}, level_sched, part.p, wt.p, bt,
+                             cap.p, jt, dboff.p, &hcap);
         LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF, jt, dboff.p, nullptr};
         if (batch) {
             std::vector<int32_t> nbk(nj, 0);
@@ -762,7 +777,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
             pick_small_jobs(c, L, nullptr, nj, ls, &boff, &nbk);
         }
         ls.moves_out = dmoves.p + kRounds + 1;
-        LPStats lps = lp_run(c, g, l, seed0, *L.sched, ls);
+        LPStats lps = lp_run(c, g, l, seed0, small_lp ? nullptr : &level_sched(), ls);
         for (int r = 0; r < kRounds; ++r) t.moves_ref += lps.moves[r];
         t.exact += lps.exact_subrounds;
         if (phase_sync) c.sync();
@@ -867,7 +882,7 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
     jb.eps = eps;
     jb.seed = seed;
     jb.out = out_part;
-    jb.cV = prepare(c, g0);
+    jb.cV = prepare(c, g0, jb.maxdeg);
     if (opt && opt->validate) {
         int rc = validate_graph(c, g0);
         if (rc != KMP_OK) return rc;
@@ -1188,7 +1203,7 @@ int kmp_lp_cluster(const int32_t* xadj, const int32_t* adjncy, const int32_t* vw
         hipLaunchKernelGGL(k_iota_weights, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, vwgt, n, label, cw, fav);
         KMP_LAUNCH_CHECK();
         LPState ls{label, cw, n, nullptr, U, fav, TAG_CL};
-        LPStats r = lp_run(c, g, level, seed, sched, ls);
+        LPStats r = lp_run(c, g, level, seed, &sched, ls);
         c.sync();
         if (moves)
             for (int q = 0; q < kRounds; ++q) moves[q] = r.moves[q];
@@ -1297,7 +1312,8 @@ int kmp_balance(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
         bt.first.assign(nb, 0);
         bt.f.assign(nb, 1);
         bt.job.assign(nb, 0);
-        int32_t r = balance(c, g, level, std::vector<uint64_t>{seed}, sched, part, wt, bt, cap);
+        int32_t r = balance(c, g, level, std::vector<uint64_t>{seed}, [&]() -> const LPSchedule& { return sched; },
+                            part, wt, bt, cap);
         c.sync();
         return r;
     });
@@ -1320,7 +1336,7 @@ int kmp_lp_refine(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwg
         LPSchedule sched;
         lp_build_schedule(c, g, level, seed, sched);
         LPState ls{part, wt, nb, cap, 0, nullptr, TAG_REF};
-        LPStats r = lp_run(c, g, level, seed, sched, ls);
+        LPStats r = lp_run(c, g, level, seed, &sched, ls);
         c.sync();
         if (moves)
             for (int q = 0; q < kRounds; ++q) moves[q] = r.moves[q];

@@ -9,6 +9,7 @@
 
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -408,6 +409,10 @@ void scan_incl_max_i32(Ctx& c, const int32_t* in, int32_t* out, int64_t n);
 // it (the alt ones after an odd number of passes) and nothing is copied.
 void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
                       int key_bits, uint32_t** out_keys = nullptr, uint32_t** out_vals = nullptr);
+// m = xadj[n] and the largest degree of a CSR, in one read-back (zeroed2: two
+// zeroed int32 of scratch, or NULL to allocate and clear them here).
+void entries_and_max_degree(Ctx& c, const int32_t* xadj, int32_t n, int64_t& m, int32_t& maxdeg,
+                            int32_t* zeroed2 = nullptr);
 // Several byte fills in one launch (at most kMaxFills buffers).
 constexpr int kMaxFills = 8;
 struct ByteFill {
@@ -501,7 +506,9 @@ struct LPSchedule {
 void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched,
                        const JobTabs& jt = {}, const uint8_t* gpart = nullptr, int32_t njobs = 0);
 // Rated entries accumulate in the context's SP_RATED spread counter.
-LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st);
+// sched NULL: a single graph whose level the caller found small (at most the
+// one-workgroup cut-off, no degree above the tier-1 cut-off, state fits LDS).
+LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule* sched, LPState& st);
 int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32_t s, uint64_t seed,
                     const LPSchedule& sched, LPState& st, const uint8_t* active, uint8_t* moved);
 
@@ -533,9 +540,10 @@ void count_nonempty_jobs(Ctx& c, const int64_t* cw, int32_t n, const JobTabs& jt
 // get map = -1); coarse ids stay grouped by job.
 // cid_in / nc_in: coarse ids and count from contract_ids, when the caller
 // already computed them (its convergence test needs the count first).
+// maxdeg (may be NULL) receives the coarse graph's largest degree.
 void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,
               int32_t& cn, int64_t& cm, const JobTabs& jt = {}, const uint8_t* gkeep = nullptr,
-              DBuf<int32_t>* cid_in = nullptr, int32_t nc_in = 0);
+              DBuf<int32_t>* cid_in = nullptr, int32_t nc_in = 0, int32_t* maxdeg = nullptr);
 // Coarse id of every non-empty label (exclusive prefix of the non-empty
 // flags, jobs with gkeep[job] == 0 excluded); returns their number.
 int32_t contract_ids(Ctx& c, const DGraph& g, const int64_t* cw, DBuf<int32_t>& cid, const JobTabs& jt = {},
@@ -568,9 +576,12 @@ void edge_cut_jobs(Ctx& c, const DGraph& g, const int32_t* part, const int32_t* 
 // hashes job-local and each job stops on its own (no overload, or a round
 // without moves).
 // hcap: the caps on the host when the caller has them (else they are read).
+// sched builds (or returns) the level's schedule; it is called only when some
+// block is overloaded.
 int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64_t>& seeds,
-                const LPSchedule& sched, int32_t* part, int64_t* wt, const BlockTab& bt, const int64_t* cap,
-                const JobTabs& jt = {}, const int32_t* boff = nullptr, const std::vector<int64_t>* hcap = nullptr);
+                const std::function<const LPSchedule&()>& sched, int32_t* part, int64_t* wt, const BlockTab& bt,
+                const int64_t* cap, const JobTabs& jt = {}, const int32_t* boff = nullptr,
+                const std::vector<int64_t>* hcap = nullptr);
 
 // ---------------------------------------------------------------- validation, batches (kmp.hip)
 int validate_graph(Ctx& c, const DGraph& g);

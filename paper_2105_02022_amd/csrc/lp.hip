@@ -1352,14 +1352,14 @@ struct LPBuffers {
     DBuf<int64_t> sout;            // one-workgroup LP: moves per round, round count
 };
 
-void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t nlab, LPBuffers& b)
+void lp_buffers(Ctx& c, const DGraph& g, int64_t hub_slots, int32_t nlab, LPBuffers& b)
 {
     b.prop = DBuf<int32_t>(c, (size_t)g.n);
     b.acc = DBuf<uint8_t>(c, (size_t)g.n);
     b.demand = DBuf<uint32_t>(c, (size_t)nlab);
-    if (sched.hub_slots_total > 0) {
-        b.hub_keys = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
-        b.hub_vals = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
+    if (hub_slots > 0) {
+        b.hub_keys = DBuf<uint32_t>(c, (size_t)hub_slots);
+        b.hub_vals = DBuf<uint32_t>(c, (size_t)hub_slots);
     }
     b.mflag = DBuf<uint8_t>(c, (size_t)g.n);
     b.ckeys = DBuf<uint32_t>(c, (size_t)g.n);
@@ -1777,10 +1777,16 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
 
 }  // namespace
 
-LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st)
+LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule* sched_p, LPState& st)
 {
     const int32_t n = g.n;
     if (n == 0) return LPStats();
+    if (!sched_p) {  // a small single graph: no schedule needed
+        LPBuffers b;
+        lp_buffers(c, g, 0, st.nlab, b);
+        return lp_run_small(c, g, level, seed, st, b, {0}, {n}, {0}, {st.nlab});
+    }
+    const LPSchedule& sched = *sched_p;
     // jobs that run the one-workgroup LP; the others take the launch-per-step path
     std::vector<int32_t> ss, sc, sl, sn;
     if (!st.jt.gid) {
@@ -1800,7 +1806,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     for (int32_t x : sc) small_nodes += x;
     const bool all_small = !ss.empty() && small_nodes == sched.off[kSegs];
     LPBuffers b;
-    lp_buffers(c, g, sched, st.nlab, b);
+    lp_buffers(c, g, sched.hub_slots_total, st.nlab, b);
     LPStats small;
     if (!ss.empty()) {
         small = lp_run_small(c, g, level, seed, st, b, ss, sc, sl, sn);
@@ -1817,7 +1823,7 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
 {
     if (g.n == 0) return 0;
     LPBuffers b;
-    lp_buffers(c, g, sched, st.nlab, b);
+    lp_buffers(c, g, sched.hub_slots_total, st.nlab, b);
     RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)round}), &b);
     a.level = (uint32_t)level;
     a.round = (uint32_t)round;

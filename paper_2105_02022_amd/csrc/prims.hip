@@ -732,6 +732,38 @@ void iota_i32(Ctx& c, int32_t* p, int64_t n)
     KMP_LAUNCH_CHECK();
 }
 
+namespace {
+
+// out[0] = xadj[n]; out[1] = max over v of xadj[v + 1] - xadj[v] (out zeroed)
+__global__ __launch_bounds__(kBlock) void k_max_deg(const int32_t* __restrict__ xadj, int32_t n, int32_t* out)
+{
+    int32_t m = 0;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
+        m = max(m, xadj[v + 1] - xadj[v]);
+    for (int q = 32; q > 0; q >>= 1) m = max(m, __shfl_xor(m, q, 64));
+    if ((threadIdx.x & 63) == 0 && m) atomicMax(&out[1], m);
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = xadj[n];
+}
+
+}  // namespace
+
+void entries_and_max_degree(Ctx& c, const int32_t* xadj, int32_t n, int64_t& m, int32_t& maxdeg, int32_t* zeroed2)
+{
+    DBuf<int32_t> own;
+    int32_t* out = zeroed2;
+    if (!out) {
+        own = DBuf<int32_t>(c, 2);
+        fill_bytes_many(c, {{own.p, 8, 0}});
+        out = own.p;
+    }
+    hipLaunchKernelGGL(k_max_deg, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, xadj, n, out);
+    KMP_LAUNCH_CHECK();
+    int32_t h[2];
+    c.read(h, out, sizeof(h));
+    m = h[0];
+    maxdeg = h[1];
+}
+
 int64_t node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n)
 {
     if (!vwgt) return n;
