@@ -42,10 +42,10 @@ constexpr int kCandChunk = 1024;    // contended entries staged in LDS per pass
 // contended-list length alternates between CTL_CONT and CTL_CONT + 1 by
 // sub-round parity, so that each apply clears the next one's; an abort records
 // its round stamp and sub-round), then one set of kSpreadSlots per-block move
-// counts per round (CTL_MS + r * kSpreadSlots), then the two segment tables of
-// the compacted lists (used by alternate rounds)
+// counts per round (CTL_MS + r * kSpreadSlots), then the segment table of the
+// lists without the skipped jobs (batches)
 enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_ABORT_STAMP = 2, CTL_CONT = 3, CTL_N = 8, CTL_MS = CTL_N };
-constexpr int kCtlWords = CTL_N + kRounds * kSpreadSlots + 2 * kSegs;  // int64 words
+constexpr int kCtlWords = CTL_N + kRounds * kSpreadSlots + kSegs;  // int64 words (the table: 2 kSegs int32)
 
 // Largest degree of tiers 0..3 (a tuning choice bounded by T0_DEG .. T3_DEG).
 struct TierCuts {
@@ -170,7 +170,8 @@ struct RateArgs {
     const int64_t* wt;
     const int64_t* cap_vec;
     int64_t cap_scalar;
-    const uint8_t* active;  // NULL = every listed node is rated
+    const uint8_t* active;  // NULL = every listed node is rated; else nodes with active[v] == stamp
+    uint8_t stamp;
     uint32_t hpre;          // H prefix over (seed; tag, level, round)
     int32_t* prop;          // [n], -1 = no proposal
     uint32_t* fav;          // [n] or NULL
@@ -218,7 +219,7 @@ __device__ inline bool aborted(const RateArgs& a) { return a.ctl && a.ctl[CTL_AB
 __device__ inline bool node_selected(const RateArgs& a, int32_t v)
 {
     if (a.over) return a.over[a.label[v]] != 0;
-    return !a.active || a.active[v];
+    return !a.active || a.active[v] == a.stamp;
 }
 
 __device__ inline void write_result(const RateArgs& a, int32_t v, const Key3& fav, const Key3& adm, uint32_t rown,
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
         const uint32_t own = (uint32_t)a.label[v];
         if (BAL) {
             if (!a.over[own]) continue;
-        } else if (a.active && !a.active[v]) {
+        } else if (a.active && a.active[v] != a.stamp) {
             continue;
         }
         const int32_t e0 = a.xadj[v];
@@ -567,6 +568,17 @@ __device__ inline int32_t class_pos(const ClassSegs& c, int64_t i)
     return -1;
 }
 
+// Rating tier of position i of the class (see class_pos).
+__device__ inline int class_tier(const ClassSegs& c, int64_t i)
+{
+#pragma unroll
+    for (int t = 0; t < kTiers; ++t) {
+        if (i < c.cnt[t]) return t;
+        i -= c.cnt[t];
+    }
+    return kTiers;
+}
+
 // Wave-aggregated reservation of one slot per requesting lane of a device cursor.
 __device__ inline int64_t reserve_slot(int64_t* cursor, bool want)
 {
@@ -699,7 +711,9 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
                                                   const uint32_t* __restrict__ ckeys,
                                                   const uint32_t* __restrict__ cvals,
                                                   const int64_t* __restrict__ wsnap, CapArgs caps, int cont_idx,
-                                                  int64_t small_cap)
+                                                  int64_t small_cap, const int32_t* __restrict__ xadj,
+                                                  const int32_t* __restrict__ adjncy, uint8_t* __restrict__ act_next,
+                                                  uint8_t stamp_next)
 {
     __shared__ int32_t bm;
     __shared__ uint64_t s_kv[kCandChunk];  // (target << 32) | id
@@ -763,6 +777,18 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
             atomicAdd((unsigned long long*)&wt[old], (unsigned long long)(-c));
             mflag[v] = stamp;
             ++mine;
+            // next round's active set: the neighbours of a moved node of degree
+            // <= T1_DEG are marked here (larger ones by k_push_active)
+            if (act_next && class_tier(cs, i) <= 1) {
+                const int32_t e0 = xadj[v], e1 = xadj[v + 1];
+                for (int32_t eb = e0; eb < e1; eb += 8) {
+                    int32_t u[8];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) u[q] = adjncy[eb + q < e1 ? eb + q : e1 - 1];
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) act_next[u[q]] = stamp_next;
+                }
+            }
         }
         prop[v] = -1;
         acc[v] = 0;
@@ -779,28 +805,24 @@ struct SegBounds {
     int32_t off[kSegs + 1];
 };
 
-// Mark the neighbours of the nodes moved in this round active for the next one
-// (active[u] = stamp, so the array never needs clearing); blockIdx.y selects
-// the segment of the round's lists.  The segment's degree tier picks the width
-// that walks a node's neighbours: one lane (degree <= 64), one wavefront
-// (<= 4096) or the whole workgroup (hubs).  Block (0, 0) also resets the next
-// round's segment table (offsets = the schedule's, counts 0).  Nothing happens
-// after an abort (the host redoes this step once the round is finished).
+// Mark the neighbours of the nodes moved in this round (mflag[v] == stamp)
+// active for the next one (active[u] = mark; the stamps never need clearing).
+// Segment seg0 + blockIdx.y of the lists; the segment's degree tier picks the
+// width that walks a node's neighbours: one lane (tiers 0, 1), one wavefront
+// (tiers 2, 3) or the whole workgroup (hubs).  k_apply marks the neighbours of
+// moved nodes of tiers 0 and 1 itself, so this runs over tiers 2-4 only.
+// Nothing happens after an abort (the host redoes this step once the round is
+// finished).
 __global__ __launch_bounds__(kBlock) void k_push_active(const int64_t* __restrict__ ctl,
                                                         const int32_t* __restrict__ list,
                                                         const int32_t* __restrict__ segtab,
                                                         const uint8_t* __restrict__ mflag, uint8_t stamp,
                                                         const int32_t* __restrict__ xadj,
                                                         const int32_t* __restrict__ adjncy,
-                                                        uint8_t* __restrict__ active, SegBounds b,
-                                                        int32_t* __restrict__ next_segtab)
+                                                        uint8_t* __restrict__ active, uint8_t mark, int seg0)
 {
     if (ctl[CTL_ABORT]) return;
-    const int seg = blockIdx.y;
-    if (blockIdx.x == 0 && seg == 0 && threadIdx.x < kSegs) {
-        next_segtab[threadIdx.x] = b.off[threadIdx.x];
-        next_segtab[kSegs + threadIdx.x] = 0;
-    }
+    const int seg = seg0 + blockIdx.y;
     const int tier = seg / kSub;
     const int32_t off = segtab[seg], cnt = segtab[kSegs + seg];
     if (tier <= 1) {
@@ -814,7 +836,7 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int64_t* __restric
 #pragma unroll
                 for (int q = 0; q < 8; ++q) u[q] = adjncy[eb + q < e1 ? eb + q : e1 - 1];
 #pragma unroll
-                for (int q = 0; q < 8; ++q) active[u[q]] = stamp;
+                for (int q = 0; q < 8; ++q) active[u[q]] = mark;
             }
         }
         return;
@@ -828,44 +850,14 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int64_t* __restric
         const int32_t v = list[off + i];
         if (mflag[v] != stamp) continue;
         const int32_t e1 = xadj[v + 1];
-        for (int32_t e = xadj[v] + gl; e < e1; e += W) active[adjncy[e]] = stamp;
+        for (int32_t e = xadj[v] + gl; e < e1; e += W) active[adjncy[e]] = mark;
     }
 }
 
-// Append the nodes of `order` segment blockIdx.y with active == stamp to the
-// same segment region of `alist`; counts go to next_segtab[kSegs + seg].  The
-// order inside a segment is free (results do not depend on it), so each block
-// reserves its slots with one atomic.
-__global__ __launch_bounds__(kBlock) void k_active_append(const int64_t* __restrict__ ctl,
-                                                          const int32_t* __restrict__ order, SegBounds b,
-                                                          const uint8_t* __restrict__ active, uint8_t stamp,
-                                                          int32_t* __restrict__ alist,
-                                                          int32_t* __restrict__ next_segtab)
-{
-    __shared__ int32_t s_cnt, s_base;
-    if (ctl[CTL_ABORT]) return;
-    const int seg = blockIdx.y;
-    const int32_t lo = b.off[seg], hi = b.off[seg + 1];
-    for (int64_t i0 = lo + (int64_t)xcd_block() * kBlock; i0 < hi; i0 += (int64_t)gridDim.x * kBlock) {
-        if (threadIdx.x == 0) s_cnt = 0;
-        __syncthreads();
-        const int64_t i = i0 + threadIdx.x;
-        int32_t v = -1, slot = -1;
-        if (i < hi) {
-            v = order[i];
-            if (active[v] == stamp) slot = atomicAdd(&s_cnt, 1);
-        }
-        __syncthreads();
-        if (threadIdx.x == 0 && s_cnt) s_base = atomicAdd(&next_segtab[kSegs + seg], s_cnt);
-        __syncthreads();
-        if (slot >= 0) alist[lo + s_base + slot] = v;
-        __syncthreads();
-    }
-}
-
-// Round-0 lists without the nodes of skipped jobs: the nodes of `order`
-// segment blockIdx.y whose job is not skipped, appended to the same segment
-// region of `alist`; counts go to segtab[kSegs + seg] (zero before), the
+// Lists without the nodes of skipped jobs: the nodes of `order` segment
+// blockIdx.y whose job is not skipped, appended to the same segment region of
+// `alist` (each block reserves its slots with one atomic; the order inside a
+// segment is free); counts go to segtab[kSegs + seg] (zero before), the
 // segment's start to segtab[seg].
 __global__ __launch_bounds__(kBlock) void k_order_skip_jobs(const int32_t* __restrict__ order, SegBounds b,
                                                             const int32_t* __restrict__ gid,
@@ -1348,7 +1340,7 @@ struct LPBuffers {
     DBuf<uint32_t> ckeys, cvals;   // contended (target, id), unordered
     DBuf<int64_t> base;            // [nlab] weight before a target's first proposal
     DBuf<int64_t> ctl;
-    DBuf<uint8_t> active;          // round stamp of the active set (lp_run)
+    DBuf<uint8_t> active;          // [2n] active stamps of the rounds, by round parity (lp_run)
     DBuf<int64_t> sout;            // one-workgroup LP: moves per round, round count
 };
 
@@ -1366,7 +1358,7 @@ void lp_buffers(Ctx& c, const DGraph& g, int64_t hub_slots, int32_t nlab, LPBuff
     b.cvals = DBuf<uint32_t>(c, (size_t)g.n);
     b.base = DBuf<int64_t>(c, (size_t)nlab);
     b.ctl = DBuf<int64_t>(c, kCtlWords);
-    b.active = DBuf<uint8_t>(c, (size_t)g.n);
+    b.active = DBuf<uint8_t>(c, 2 * (size_t)g.n);
     b.sout = DBuf<int64_t>(c, kRounds + 1);
     // prop = -1, everything else 0, in one launch
     fill_bytes_many(c, {{b.prop.p, 4 * (int64_t)g.n, 0xFF},
@@ -1374,7 +1366,7 @@ void lp_buffers(Ctx& c, const DGraph& g, int64_t hub_slots, int32_t nlab, LPBuff
                         {b.demand.p, 4 * (int64_t)nlab, 0},
                         {b.mflag.p, (int64_t)g.n, 0},
                         {b.ctl.p, (int64_t)sizeof(int64_t) * kCtlWords, 0},
-                        {b.active.p, (int64_t)g.n, 0},
+                        {b.active.p, 2 * (int64_t)g.n, 0},
                         {b.sout.p, (int64_t)sizeof(int64_t) * (kRounds + 1), 0}});
 }
 
@@ -1407,6 +1399,10 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
     }
     return a;
 }
+
+// The LDS tables of tiers 1-3 hold at least twice as many slots as the largest
+// degree a tier may take (the tuning may only lower the cut-offs).
+static_assert((1 << 7) >= 2 * T1_DEG && (1 << 10) >= 2 * T2_DEG && (1 << 13) >= 2 * T3_DEG, "LDS table sizes");
 
 // Launch the rating kernels of class s over the lists described by segtab;
 // grids are sized by the level's segment sizes (upper bounds of the lists).
@@ -1491,7 +1487,8 @@ void launch_admit(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, co
 }
 
 void launch_apply(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, const int32_t* segtab,
-                  const DGraph& g, LPState& st, LPBuffers& b, uint8_t* mflag, uint8_t stamp, int ms)
+                  const DGraph& g, LPState& st, LPBuffers& b, uint8_t* mflag, uint8_t stamp, int ms,
+                  uint8_t* act_next)
 {
     const int32_t ub = class_ub(ubs, s);
     if (ub == 0) return;
@@ -1500,7 +1497,7 @@ void launch_apply(Ctx& c, const int32_t* ubs, int32_t s, const int32_t* list, co
     hipLaunchKernelGGL(k_apply, dim3(grid_for(ub, bs, 8192)), dim3(bs), 0, c.stream, b.ctl.p, list, segtab,
                        s, b.prop.p, b.acc.p, b.demand.p, st.label, st.wt, g.vwgt, mflag, stamp, ms, b.ckeys.p,
                        b.cvals.p, b.base.p, cap_args(st), CTL_CONT + (s & 1),
-                       (int64_t)(c.force_exact ? 0 : kSmallCap));
+                       (int64_t)(c.force_exact ? 0 : kSmallCap), g.xadj, g.adjncy, act_next, (uint8_t)(stamp + 1));
     KMP_LAUNCH_CHECK();
 }
 
@@ -1542,14 +1539,14 @@ void resolve_exact(Ctx& c, const DGraph& g, LPState& st, LPBuffers& b, int32_t s
 // One sub-round on the exact path (host synchronised after admission).
 void subround_exact(Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t s, const int32_t* list,
                     const int32_t* segtab, const int32_t* ubs, LPState& st, LPBuffers& b, const RateArgs& a,
-                    bool rate, uint8_t* mflag, uint8_t stamp, int ms)
+                    bool rate, uint8_t* mflag, uint8_t stamp, int ms, uint8_t* act_next)
 {
     if (rate) {
         launch_rate(c, a, sched, s, list, segtab, ubs);
         launch_admit(c, ubs, s, list, segtab, st, b);
     }
     resolve_exact(c, g, st, b, s);
-    launch_apply(c, ubs, s, list, segtab, g, st, b, mflag, stamp, ms);
+    launch_apply(c, ubs, s, list, segtab, g, st, b, mflag, stamp, ms, act_next);
 }
 
 }  // namespace
@@ -1681,42 +1678,20 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
 {
     LPStats out;
     const int32_t n = g.n;
-    DBuf<uint8_t>& active = b.active;
-    DBuf<int32_t> alist0(c, (size_t)n), alist1(c, (size_t)n);
-    int32_t* alist[2] = {alist0.p, alist1.p};
-    int32_t* segtab_r[2] = {reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kRounds * kSpreadSlots),
-                            reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kRounds * kSpreadSlots) + 2 * kSegs};
     SegBounds bounds;
     for (int j = 0; j <= kSegs; ++j) bounds.off[j] = sched.off[j];
     int32_t ub[kSegs];
     memcpy(ub, sched.cnt, sizeof(ub));
-    // enqueue: next-round active set (neighbours of nodes moved in round r),
-    // appended segment by segment to list buffer q
-    auto enqueue_next_lists = [&](int32_t r, const int32_t* list, const int32_t* segtab, int q) {
-        int32_t mx = 1, mseg = 1;
-        for (int j = 0; j < kSegs; ++j) {
-            mx = std::max(mx, ub[j]);
-            mseg = std::max(mseg, sched.cnt[j]);
-        }
-        const uint8_t stamp = (uint8_t)(r + 1);
-        ProfScope ps(c, KMP_PROF_ACTIVE);
-        hipLaunchKernelGGL(k_push_active, dim3(grid_for(mx, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream, b.ctl.p,
-                           list, segtab, b.mflag.p, stamp, g.xadj, g.adjncy, active.p, bounds, segtab_r[q]);
-        KMP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_active_append, dim3(grid_for(mseg, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream,
-                           b.ctl.p, sched.order.p, bounds, active.p, stamp, alist[q], segtab_r[q]);
-        KMP_LAUNCH_CHECK();
-    };
-    struct {
-        int64_t ctl[CTL_N];
-        int64_t moved[kRounds][kSpreadSlots];
-        int32_t seg[2][2 * kSegs];
-    } h;
-    static_assert(sizeof(h) == sizeof(int64_t) * kCtlWords, "control block layout");
-    const int32_t* list0 = sched.order.p;
-    const int32_t* segtab0 = sched.segtab.p;
+    // Every round walks the same lists: round 0 rates all of them, later rounds
+    // the nodes whose stamp in act[r & 1] is r + 1, set when a neighbour moved in
+    // round r - 1 (by k_apply for moved nodes of tiers 0-1, k_push_active above).
+    const int32_t* list = sched.order.p;
+    const int32_t* segtab = sched.segtab.p;
+    DBuf<int32_t> flist;
     if (!skip.empty()) {
-        // round 0 lists without the skipped jobs' nodes
+        // batches: the lists without the skipped jobs' nodes
+        int32_t* ftab = reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kRounds * kSpreadSlots);
+        flist = DBuf<int32_t>(c, (size_t)n);
         std::vector<uint8_t> flag((size_t)st.njobs, 0);
         for (int32_t j : skip) flag[j] = 1;
         DBuf<uint8_t> dflag(c, flag.size());
@@ -1724,53 +1699,65 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
         int32_t mseg = 1;
         for (int j = 0; j < kSegs; ++j) mseg = std::max(mseg, sched.cnt[j]);
         hipLaunchKernelGGL(k_order_skip_jobs, dim3(grid_for(mseg, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream,
-                           sched.order.p, bounds, st.jt.gid, dflag.p, alist[0], segtab_r[0]);
+                           sched.order.p, bounds, st.jt.gid, dflag.p, flist.p, ftab);
         KMP_LAUNCH_CHECK();
         int32_t tab[2 * kSegs];
-        c.read(tab, segtab_r[0], sizeof(tab));
+        c.read(tab, ftab, sizeof(tab));
         for (int j = 0; j < kSegs; ++j) ub[j] = tab[kSegs + j];
-        list0 = alist[0];
-        segtab0 = segtab_r[0];
+        list = flist.p;
+        segtab = ftab;
     }
+    uint8_t* act[2] = {b.active.p, b.active.p + n};
+    int32_t mbig = 0;  // largest segment of tiers 2-4 (their marking is a launch of its own)
+    for (int j = 2 * kSub; j < kSegs; ++j) mbig = std::max(mbig, ub[j]);
+    auto push_big = [&](int32_t r) {
+        if (mbig == 0 || r + 1 >= kRounds) return;
+        ProfScope ps(c, KMP_PROF_ACTIVE);
+        hipLaunchKernelGGL(k_push_active, dim3(grid_for(mbig, kBlock, 1024), kSegs - 2 * kSub), dim3(kBlock), 0,
+                           c.stream, b.ctl.p, list, segtab, b.mflag.p, (uint8_t)(r + 1), g.xadj, g.adjncy,
+                           act[(r + 1) & 1], (uint8_t)(r + 2), 2 * kSub);
+        KMP_LAUNCH_CHECK();
+    };
+    struct {
+        int64_t ctl[CTL_N];
+        int64_t moved[kRounds][kSpreadSlots];
+    } h;
+    static_assert(sizeof(h) <= sizeof(int64_t) * kCtlWords, "control block layout");
     for (int32_t r = 0; r < kRounds; ++r) {
         out.rounds = r + 1;
-        const int cur = r & 1, nxt = cur ^ 1;
         const uint8_t stamp = (uint8_t)(r + 1);
         const int ms = CTL_MS + r * kSpreadSlots;  // this round's move-count set
-        const int32_t* list = r == 0 ? list0 : alist[cur];
-        const int32_t* segtab = r == 0 ? segtab0 : segtab_r[cur];
+        uint8_t* next = r + 1 < kRounds ? act[(r + 1) & 1] : nullptr;
         RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
         a.level = (uint32_t)level;
         a.round = (uint32_t)r;
+        a.active = r == 0 ? nullptr : act[r & 1];
+        a.stamp = stamp;
         // speculative sub-rounds: no host synchronisation in between
         for (int32_t s = 0; s < kSub; ++s) {
             launch_rate(c, a, sched, s, list, segtab, ub);
             launch_admit(c, ub, s, list, segtab, st, b);
-            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, stamp, ms);
+            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, stamp, ms, next);
         }
-        const bool more = r + 1 < kRounds;
-        if (more) enqueue_next_lists(r, list, segtab, nxt);
+        push_big(r);
         c.read(&h, b.ctl.p, sizeof(h));
         if (h.ctl[CTL_ABORT]) {
             // finish the round on the exact path from the aborted sub-round on
-            // (the next round's list building did nothing; the current lists are
-            // untouched: the next round writes the other buffer)
+            // (every launch after the abort did nothing)
             const int32_t s0 = (int32_t)h.ctl[CTL_ABORT_SUB];
             if (h.ctl[CTL_ABORT_STAMP] != stamp) throw Error(KMP_EHIP, "LP abort recorded for an unexpected round");
             ctl_set(c, b, CTL_ABORT, 0);
-            subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp, ms);
+            subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp, ms, next);
             for (int32_t s = s0 + 1; s < kSub; ++s)
-                subround_exact(c, g, sched, s, list, segtab, ub, st, b, a, true, b.mflag.p, stamp, ms);
-            if (more) enqueue_next_lists(r, list, segtab, nxt);
+                subround_exact(c, g, sched, s, list, segtab, ub, st, b, a, true, b.mflag.p, stamp, ms, next);
+            push_big(r);
             c.read(&h, b.ctl.p, sizeof(h));
             out.exact_subrounds += kSub - s0;
         }
         int64_t nm = 0;
         for (int q = 0; q < kSpreadSlots; ++q) nm += h.moved[r][q];
         out.moves[r] = nm;
-        if (nm == 0 || !more) break;
-        // the next round's lists are exactly sized
-        for (int j = 0; j < kSegs; ++j) ub[j] = h.seg[nxt][kSegs + j];
+        if (nm == 0) break;
     }
     return out;
 }
@@ -1828,7 +1815,9 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
     a.level = (uint32_t)level;
     a.round = (uint32_t)round;
     a.active = active;
-    subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, sched.cnt, st, b, a, true, moved, 1, CTL_MS);
+    a.stamp = 1;  // the caller's active flags are 0 / 1
+    subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, sched.cnt, st, b, a, true, moved, 1, CTL_MS,
+                   nullptr);
     int64_t slots[kSpreadSlots];
     c.read(slots, b.ctl.p + CTL_MS, sizeof(slots));
     int64_t nm = 0;
