@@ -1723,41 +1723,65 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
         int64_t moved[kRounds][kSpreadSlots];
     } h;
     static_assert(sizeof(h) <= sizeof(int64_t) * kCtlWords, "control block layout");
-    for (int32_t r = 0; r < kRounds; ++r) {
-        out.rounds = r + 1;
-        const uint8_t stamp = (uint8_t)(r + 1);
-        const int ms = CTL_MS + r * kSpreadSlots;  // this round's move-count set
-        uint8_t* next = r + 1 < kRounds ? act[(r + 1) & 1] : nullptr;
+    auto args_of = [&](int32_t r) {
         RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), &b);
         a.level = (uint32_t)level;
         a.round = (uint32_t)r;
         a.active = r == 0 ? nullptr : act[r & 1];
-        a.stamp = stamp;
-        // speculative sub-rounds: no host synchronisation in between
+        a.stamp = (uint8_t)(r + 1);
+        return a;
+    };
+    auto next_of = [&](int32_t r) { return r + 1 < kRounds ? act[(r + 1) & 1] : nullptr; };
+    // One round: S sub-rounds with no host synchronisation in between.
+    auto launch_round = [&](int32_t r) {
+        const RateArgs a = args_of(r);
         for (int32_t s = 0; s < kSub; ++s) {
             launch_rate(c, a, sched, s, list, segtab, ub);
             launch_admit(c, ub, s, list, segtab, st, b);
-            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, stamp, ms, next);
+            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, (uint8_t)(r + 1), CTL_MS + r * kSpreadSlots,
+                         next_of(r));
         }
         push_big(r);
+    };
+    // Clustering rarely converges before the last round, so its rounds are all
+    // enqueued before the host reads the move counts once (a round after one
+    // without moves has no active node and changes nothing).  Refinement usually
+    // stops after a round or two: it reads the counts after every round.
+    const bool ahead = st.tag == TAG_CL;
+    int32_t r = 0;
+    while (r < kRounds) {
+        const int32_t last = ahead ? kRounds - 1 : r;
+        for (int32_t q = r; q <= last; ++q) launch_round(q);
         c.read(&h, b.ctl.p, sizeof(h));
+        int32_t done = last;  // rounds up to `done` are final
         if (h.ctl[CTL_ABORT]) {
-            // finish the round on the exact path from the aborted sub-round on
-            // (every launch after the abort did nothing)
+            // round r0 stopped at sub-round s0 and every launch after it did
+            // nothing: finish r0 on the exact path, then carry on from r0 + 1
             const int32_t s0 = (int32_t)h.ctl[CTL_ABORT_SUB];
-            if (h.ctl[CTL_ABORT_STAMP] != stamp) throw Error(KMP_EHIP, "LP abort recorded for an unexpected round");
+            const int32_t r0 = (int32_t)h.ctl[CTL_ABORT_STAMP] - 1;
+            if (r0 < r || r0 > last) throw Error(KMP_EHIP, "LP abort recorded for an unexpected round");
+            const RateArgs a = args_of(r0);
+            const uint8_t stamp = (uint8_t)(r0 + 1);
+            const int ms = CTL_MS + r0 * kSpreadSlots;
             ctl_set(c, b, CTL_ABORT, 0);
-            subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp, ms, next);
+            subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp, ms, next_of(r0));
             for (int32_t s = s0 + 1; s < kSub; ++s)
-                subround_exact(c, g, sched, s, list, segtab, ub, st, b, a, true, b.mflag.p, stamp, ms, next);
-            push_big(r);
+                subround_exact(c, g, sched, s, list, segtab, ub, st, b, a, true, b.mflag.p, stamp, ms, next_of(r0));
+            push_big(r0);
             c.read(&h, b.ctl.p, sizeof(h));
             out.exact_subrounds += kSub - s0;
+            done = r0;
         }
-        int64_t nm = 0;
-        for (int q = 0; q < kSpreadSlots; ++q) nm += h.moved[r][q];
-        out.moves[r] = nm;
-        if (nm == 0) break;
+        bool stop = false;
+        for (int32_t q = r; q <= done && !stop; ++q) {
+            int64_t nm = 0;
+            for (int k = 0; k < kSpreadSlots; ++k) nm += h.moved[q][k];
+            out.moves[q] = nm;
+            out.rounds = q + 1;
+            stop = nm == 0;
+        }
+        if (stop) break;
+        r = done + 1;
     }
     return out;
 }
