@@ -22,8 +22,11 @@
 // Sub-rounds are enqueued speculatively: if the contended list of a sub-round
 // is longer than kSmallCap, a device flag aborts the rest of the round and the
 // host finishes it on the exact path (sort in global memory), one sub-round at
-// a time.  Rounds after the first rate only the active nodes, compacted per
-// (tier, class) segment on the device.
+// a time.  Every round walks the same static class lists; a node is rated in a
+// round after the first only if its stamp in that round's parity array says a
+// neighbour moved (the apply kernel stamps the neighbours of moved nodes of
+// tiers 0 and 1, a marking kernel those of the wider tiers).  Small levels and
+// small batch jobs run the whole LP in one workgroup with its state in LDS.
 #include <mutex>
 
 #include "kmp_dev.h"

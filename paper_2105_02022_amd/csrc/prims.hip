@@ -360,7 +360,11 @@ void Ctx::prof_collect(int64_t* launches, double* ms, int64_t* bytes)
         launches[r.cls] += 1;
         ms[r.cls] += t;
     }
-    for (int i = 0; i < KMP_PROF_CLASSES; ++i) bytes[i] = read_spread(SP_BYTES + i);
+    // the classes' counters are adjacent: one read-back for all of them
+    std::vector<int64_t> v((size_t)KMP_PROF_CLASSES * kSpreadSlots);
+    read(v.data(), spread(SP_BYTES), v.size() * sizeof(int64_t));
+    for (int i = 0; i < KMP_PROF_CLASSES; ++i)
+        for (int j = 0; j < kSpreadSlots; ++j) bytes[i] += v[(size_t)i * kSpreadSlots + j];
 }
 
 int bits_for(uint64_t max_value)
