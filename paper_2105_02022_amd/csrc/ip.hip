@@ -10,7 +10,10 @@
 // grown side weighs less than floor(c(B) f0 / f), the frontier node with the
 // largest gain (smallest local id on ties) that fits under f0 * L_k, or, when
 // no frontier node fits, the fitting unassigned node with the smallest hash
-// H(seed; 5, level, first, f, j, local id).
+// H(seed; 5, level, first, f, j, local id).  A growth step is one pass over a
+// packed 64-bit key per node (frontier flag, gain, id) and one wave maximum.
+#include <mutex>
+
 #include "kmp_dev.h"
 
 namespace kmp {
@@ -87,18 +90,43 @@ struct GGGArgs {
     char* scratch;      // global variant
 };
 
+// A growth keeps one 64-bit key per node, so that finding the next node is one
+// load per node and a maximum:
+//   bit 63      node is on the frontier (adjacent to the grown side)
+//   bits 62-31  gain + 2^31 (gain = weight to the grown side - weight to the rest)
+//   bits 30-0   2^31 - 1 - local id (ties go to the smaller id)
+// Key 0 marks a grown node (and the padding up to a multiple of 64 nodes);
+// key 1 a node that no longer fits under the cap (the grown weight only
+// increases, so it never fits again and its gain no longer matters).
+constexpr uint64_t kFront = 1ull << 63;
+constexpr uint64_t kUnfit = 1;
+
+__device__ inline uint64_t ggg_key(int32_t gain, uint32_t i)
+{
+    return ((uint64_t)((uint32_t)gain ^ 0x80000000u) << 31) | (uint64_t)(0x7FFFFFFFu - i);
+}
+__device__ inline int32_t ggg_gain(uint64_t k) { return (int32_t)((uint32_t)(k >> 31) ^ 0x80000000u); }
+__device__ inline int32_t ggg_id(uint64_t k) { return (int32_t)(0x7FFFFFFFu - (uint32_t)(k & 0x7FFFFFFFu)); }
+
+__host__ __device__ inline int64_t ggg_pad(int64_t nv) { return (nv + 63) & ~(int64_t)63; }
+
 __host__ __device__ inline int64_t ggg_bytes(int64_t nv, int64_t d)
 {
-    // lxadj (nv+1) + lvw (nv) + ladj (d) + lw (d) + gain (R*nv) int32, state (R*nv) bytes
-    int64_t words = (nv + 1) + nv + 2 * d + (int64_t)kSeeds * nv;
-    int64_t bytes = words * 4 + (int64_t)kSeeds * nv;
+    // keys (R x padded nv) u64, entries (d) and nodes (nv + 1) as int32 pairs
+    const int64_t bytes = 8 * ((int64_t)kSeeds * ggg_pad(nv) + d + nv + 1);
     return (bytes + 15) & ~(int64_t)15;
 }
 
+// Orders a wavefront's own earlier memory operations before its later ones.
+// LDS operations of a wavefront complete in issue order, so the LDS variant
+// needs only the compiler ordering; the global variant waits for its stores.
 template <bool LDS>
 __device__ inline void fence_wave()
 {
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    if (LDS)
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    else
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -113,32 +141,39 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
 
     const GGGJob job = a.jobs[blockIdx.x];
     const int32_t nv = job.nverts;
+    const int32_t nvp = (int32_t)ggg_pad(nv);
     const int32_t b = job.b;
     const uint32_t* vlist = a.verts + a.bstart[b];
     char* base = LDS ? lds_raw : a.scratch + job.scratch;
-    int32_t* lxadj = reinterpret_cast<int32_t*>(base);
-    int32_t* lvw = lxadj + (nv + 1);
-    int32_t* ladj = lvw + nv;
-    int32_t* lw = ladj + job.dsum;
-    int32_t* gain_all = lw + job.dsum;
-    uint8_t* st_all = reinterpret_cast<uint8_t*>(gain_all + (int64_t)kSeeds * nv);
+    // key[R][nvp]; ed[e] = (local neighbour, edge weight); nd[i] = (row start, node weight), nd[nv].x = entries
+    uint64_t* key_all = reinterpret_cast<uint64_t*>(base);
+    int2* ed = reinterpret_cast<int2*>(key_all + (int64_t)kSeeds * nvp);
+    int2* nd = ed + job.dsum;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-    // ---- internal degrees and block weight
+    // ---- internal degrees (in nd[i + 1].x) and node weights (a row's loads in groups of 8)
     int64_t cacc = 0;
     for (int32_t i = tid; i < nv; i += GGG_THREADS) {
         const int32_t v = (int32_t)vlist[i];
+        const int32_t e1 = a.xadj[v + 1];
         int32_t cnt = 0;
-        for (int32_t e = a.xadj[v]; e < a.xadj[v + 1]; ++e) cnt += a.part[a.adjncy[e]] == b;
-        lxadj[i + 1] = cnt;
+        for (int32_t e0 = a.xadj[v]; e0 < e1; e0 += 8) {
+            int32_t u[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] = e0 + q < e1 ? a.adjncy[e0 + q] : -1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) cnt += u[q] >= 0 && a.part[u[q]] == b;
+        }
+        nd[i + 1].x = cnt;
         const int32_t c = a.vwgt ? a.vwgt[v] : 1;
-        lvw[i] = c;
+        nd[i].y = c;
         cacc += c;
     }
     for (int d = 32; d > 0; d >>= 1) cacc += __shfl_xor(cacc, d, 64);
     if (lane == 0) s_red[wv] = cacc;
     if (tid == 0) {
-        lxadj[0] = 0;
+        nd[0].x = 0;
+        nd[nv].y = 0;
         s_carry = 0;
     }
     __syncthreads();
@@ -147,7 +182,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     // ---- prefix sum of internal degrees (chunks of GGG_THREADS, carry in LDS)
     for (int32_t c0 = 0; c0 < nv; c0 += GGG_THREADS) {
         const int32_t i = c0 + tid;
-        int32_t x = i < nv ? lxadj[i + 1] : 0;
+        int32_t x = i < nv ? nd[i + 1].x : 0;
         // inclusive scan in the wave
         for (int d = 1; d < 64; d <<= 1) {
             int32_t y = __shfl_up(x, d, 64);
@@ -158,7 +193,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
         __syncthreads();
         int32_t pre = s_carry;
         for (int q = 0; q < wv; ++q) pre += (int32_t)s_red[q];
-        if (i < nv) lxadj[i + 1] = pre + x;
+        if (i < nv) nd[i + 1].x = pre + x;
         __syncthreads();
         if (tid == GGG_THREADS - 1) s_carry = pre + x;
         __syncthreads();
@@ -166,13 +201,24 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     // ---- local adjacency (ascending node id => ascending local id)
     for (int32_t i = tid; i < nv; i += GGG_THREADS) {
         const int32_t v = (int32_t)vlist[i];
-        int32_t pos = lxadj[i];
-        for (int32_t e = a.xadj[v]; e < a.xadj[v + 1]; ++e) {
-            const int32_t u = a.adjncy[e];
-            if (a.part[u] != b) continue;
-            ladj[pos] = a.local[u];
-            lw[pos] = a.adjwgt ? a.adjwgt[e] : 1;
-            ++pos;
+        const int32_t e1 = a.xadj[v + 1];
+        int32_t pos = nd[i].x;
+        for (int32_t e0 = a.xadj[v]; e0 < e1; e0 += 8) {
+            int32_t u[8], p[8], lu[8], w[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] = e0 + q < e1 ? a.adjncy[e0 + q] : -1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                p[q] = u[q] >= 0 ? a.part[u[q]] : -1;
+                lu[q] = u[q] >= 0 ? a.local[u[q]] : 0;
+                w[q] = u[q] >= 0 ? (a.adjwgt ? a.adjwgt[e0 + q] : 1) : 0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (p[q] != b) continue;
+                ed[pos] = make_int2(lu[q], w[q]);
+                ++pos;
+            }
         }
     }
     __syncthreads();
@@ -182,50 +228,39 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     const int64_t t0 = cB * f0 / f;
     const int64_t cap0 = (int64_t)f0 * job.lk, cap1 = (int64_t)f1 * job.lk;
     const int j = wv;
-    int32_t* gain = gain_all + (int64_t)j * nv;
-    uint8_t* st = st_all + (int64_t)j * nv;  // 0 free, 1 frontier, 2 grown side
+    uint64_t* key = key_all + (int64_t)j * nvp;
     const uint32_t hj = hash_step(hash_step(hash_step(job.hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
-    for (int32_t i = lane; i < nv; i += 64) {
-        int32_t s = 0;
-        for (int32_t e = lxadj[i]; e < lxadj[i + 1]; ++e) s += lw[e];
-        gain[i] = -s;
-        st[i] = 0;
+    for (int32_t i = lane; i < nvp; i += 64) {
+        uint64_t k = 0;
+        if (i < nv) {
+            int32_t s = 0;
+            for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) s += ed[e].y;
+            k = ggg_key(-s, (uint32_t)i);
+        }
+        key[i] = k;
     }
     fence_wave<LDS>();
     int64_t w0 = 0;
-    // Each step's loads are unconditional and issued together (state, weight
-    // and gain of up to four nodes per lane; adjacency entry and weight, then
-    // the neighbour's state and gain), so a step waits on a few LDS round
-    // trips instead of one per predicated load.
-    const int32_t last = nv - 1;
+    const int32_t nchunks = nvp / 64;
     while (w0 < t0) {
-        uint64_t best = 0;  // (gain biased << 32) | ~id ; 0 = none
-        for (int32_t i0 = lane; i0 < nv; i0 += 256) {
-            uint8_t sv[4];
-            int32_t wv[4], gv[4];
+        // the largest key: lane l reads nodes l, l + 64, ... (8 loads in flight)
+        uint64_t best = 0;
+        for (int32_t c0 = 0; c0 < nchunks; c0 += 8) {
+            uint64_t k[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int32_t i = i0 + 64 * j <= last ? i0 + 64 * j : last;
-                sv[j] = st[i];
-                wv[j] = lvw[i];
-                gv[j] = gain[i];
-            }
+            for (int q = 0; q < 8; ++q) k[q] = c0 + q < nchunks ? key[(c0 + q) * 64 + lane] : 0;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uint32_t i = (uint32_t)(i0 + 64 * j);
-                const uint64_t k = ((uint64_t)((uint32_t)gv[j] ^ 0x80000000u) << 32) | (uint64_t)(0xFFFFFFFFu - i);
-                const bool ok = (int32_t)i <= last && sv[j] == 1 && w0 + wv[j] <= cap0;
-                best = ok && k > best ? k : best;
-            }
+            for (int q = 0; q < 8; ++q) best = k[q] > best ? k[q] : best;
         }
         best = wave_max_u64(best);
         int32_t pick;
-        if (best != 0) {
-            pick = (int32_t)(0xFFFFFFFFu - (uint32_t)(best & 0xFFFFFFFFu));
+        if (best >= kFront) {
+            pick = ggg_id(best);
         } else {
+            // no frontier node fits: the fitting unassigned node of smallest hash
             uint64_t hb = ~0ull;  // (hash << 32) | id ; max = none
             for (int32_t i = lane; i < nv; i += 64) {
-                if (st[i] == 2 || w0 + lvw[i] > cap0) continue;
+                if (key[i] == 0 || w0 + nd[i].y > cap0) continue;
                 const uint64_t k = ((uint64_t)hash_step(hj, (uint32_t)i, 6) << 32) | (uint32_t)i;
                 if (k < hb) hb = k;
             }
@@ -233,26 +268,33 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
             if (hb == ~0ull) break;
             pick = (int32_t)(hb & 0xFFFFFFFFu);
         }
-        const int32_t pw = lvw[pick], pe0 = lxadj[pick], pe1 = lxadj[pick + 1];
-        if (lane == 0) st[pick] = 2;
+        const int2 pa = nd[pick], pb = nd[pick + 1];
+        // both entries before the branch: one LDS round trip for the weight and the row
+        asm volatile("" ::"v"(pa.x), "v"(pa.y), "v"(pb.x));
+        const int32_t pw = pa.y, pe0 = pa.x, pe1 = pb.x;
+        if (w0 + pw > cap0) {
+            // a frontier node that does not fit: drop it for the rest of the growth
+            if (lane == 0) key[pick] = kUnfit;
+            fence_wave<LDS>();
+            continue;
+        }
+        if (lane == 0) key[pick] = 0;
         w0 += pw;
         fence_wave<LDS>();
         for (int32_t e = pe0 + lane; e < pe1; e += 64) {
-            const int32_t u = ladj[e];
-            const int32_t we = lw[e];
-            const uint8_t su = st[u];
-            const int32_t gu = gain[u];
-            if (su == 2) continue;
-            gain[u] = (int32_t)((int64_t)gu + 2 * (int64_t)we);
-            st[u] = 1;
+            const int2 uw = ed[e];
+            asm volatile("" ::"v"(uw.x), "v"(uw.y));  // one load for both halves
+            const uint64_t k = key[uw.x];
+            if (k > kUnfit)
+                key[uw.x] = kFront | ggg_key((int32_t)((int64_t)ggg_gain(k) + 2 * (int64_t)uw.y), (uint32_t)uw.x);
         }
         fence_wave<LDS>();
     }
     int64_t cut = 0;
     for (int32_t i = lane; i < nv; i += 64) {
-        if (st[i] != 2) continue;
-        for (int32_t e = lxadj[i]; e < lxadj[i + 1]; ++e)
-            if (st[ladj[e]] != 2) cut += lw[e];
+        if (key[i] != 0) continue;
+        for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e)
+            if (key[ed[e].x] != 0) cut += ed[e].y;
     }
     for (int d = 32; d > 0; d >>= 1) cut += __shfl_xor(cut, d, 64);
     if (lane == 0) {
@@ -273,8 +315,8 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
         s_best = bj;
     }
     __syncthreads();
-    const uint8_t* stb = st_all + (int64_t)s_best * nv;
-    for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = stb[i] == 2 ? 0 : 1;
+    const uint64_t* kb = key_all + (int64_t)s_best * nvp;
+    for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
 }
 
 __global__ void k_relabel(int32_t* __restrict__ part, const uint8_t* __restrict__ side,
@@ -368,7 +410,9 @@ __global__ __launch_bounds__(kBlock) void k_cut_jobs(const int32_t* __restrict__
     }
 }
 
-constexpr int64_t kLdsBudget = 64 * 1024;
+// LDS of a GGG workgroup (gfx950: 160 KiB per workgroup; the static tables
+// take a few hundred bytes); larger blocks run on global scratch
+constexpr int64_t kLdsBudget = 144 * 1024;
 
 }  // namespace
 
@@ -444,6 +488,11 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             DBuf<GGGJob> jobs(c, lds_jobs.size());
             c.write(jobs.p, lds_jobs.data(), sizeof(GGGJob) * lds_jobs.size());
             a.jobs = jobs.p;
+            static std::once_flag once;  // LDS beyond the 64 KiB default
+            std::call_once(once, [] {
+                (void)hipFuncSetAttribute((const void*)k_ggg<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                          (int)kLdsBudget);
+            });
             ProfScope ps(c, KMP_PROF_GGG);
             hipLaunchKernelGGL(k_ggg<true>, dim3((unsigned)lds_jobs.size()), dim3(GGG_THREADS), (size_t)lds_max,
                                c.stream, a);

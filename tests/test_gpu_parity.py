@@ -197,9 +197,18 @@ def test_bipartition_round(kmp, k):
         assert np.array_equal(d_part.cpu().numpy(), part)
 
 
+def _heavy_nodes(n, seed):
+    # 12% of the nodes weigh 50: near the end of a growth such frontier nodes no longer fit under the cap
+    g = gen.random_graph(n, 4.0, seed)
+    g.vwgt = np.where(np.random.default_rng(seed + 1).random(n) < 0.12, 50, 1).astype(np.int32)
+    return g
+
+
 def test_bipartition_weighted_and_degenerate(kmp):
     cases = [
         ("weighted", gen.random_graph(900, 5.0, 31, max_vw=20, max_ew=5), 7),
+        ("heavy", _heavy_nodes(300, 33), 4),
+        ("heavy-lds-and-global", _heavy_nodes(3000, 35), 6),
         ("cliques", csr_from_dense(two_cliques(40)), 2),
         ("tiny", gen.grid(1, 3), 8),
         ("isolated", gen.random_graph(500, 1.0, 32, isolated_frac=0.6), 4),
