@@ -507,11 +507,13 @@ int64_t two_hop_core(Ctx& c, const DGraph& g, const JobTabs& jt, int64_t U, int6
 
 }  // namespace
 
-int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav, bool count)
+int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav, bool count,
+                int32_t* nonempty_out)
 {
     const int32_t n = g.n;
     const int32_t nc = count_nonempty(c, cw, n);
     const int64_t half = n / 2;
+    if (nonempty_out) *nonempty_out = nc <= half ? nc : -1;
     if (nc <= half) return 0;
     const int64_t limit = (int64_t)nc - half;
     const int64_t E = two_hop_core(c, g, JobTabs{}, U, limit, nullptr, nullptr, nullptr, 1, label, cw, fav, count);
@@ -525,14 +527,14 @@ void two_hop_jobs(Ctx& c, const DGraph& g, const JobTabs& jt, const int64_t* gU,
 }
 
 int32_t contract_ids(Ctx& c, const DGraph& g, const int64_t* cw, DBuf<int32_t>& cid, const JobTabs& jt,
-                     const uint8_t* gkeep)
+                     const uint8_t* gkeep, int32_t known)
 {
     const int32_t n = g.n;
     cid = DBuf<int32_t>(c, (size_t)n + 1);
     hipLaunchKernelGGL(k_nonempty_flags, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, cw, n, jt.gid, gkeep, cid.p);
     KMP_LAUNCH_CHECK();
     scan_excl_i32(c, cid.p, cid.p, n, cid.p + n);
-    return c.read1(cid.p + n);
+    return known >= 0 ? known : c.read1(cid.p + n);
 }
 
 void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, int32_t* map, OwnedGraph& out,

@@ -252,10 +252,23 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
 #pragma unroll
             for (int q = 0; q < 8; ++q) best = k[q] > best ? k[q] : best;
         }
-        best = wave_max_u64(best);
+        // each lane fetches its own candidate's row and weight while the maximum is
+        // reduced; the winner (node i lives in lane i mod 64) hands them over
+        int2 ca = make_int2(0, 0), cb = make_int2(0, 0);
+        if (best >= kFront) {
+            const int32_t ci = ggg_id(best);
+            ca = nd[ci];
+            cb = nd[ci + 1];
+        }
+        best = wave_max_u64_split(best);
         int32_t pick;
+        int32_t pw, pe0, pe1;
         if (best >= kFront) {
             pick = ggg_id(best);
+            const int src = pick & 63;
+            pw = __builtin_amdgcn_readlane(ca.y, src);
+            pe0 = __builtin_amdgcn_readlane(ca.x, src);
+            pe1 = __builtin_amdgcn_readlane(cb.x, src);
         } else {
             // no frontier node fits: the fitting unassigned node of smallest hash
             uint64_t hb = ~0ull;  // (hash << 32) | id ; max = none
@@ -264,14 +277,14 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
                 const uint64_t k = ((uint64_t)hash_step(hj, (uint32_t)i, 6) << 32) | (uint32_t)i;
                 if (k < hb) hb = k;
             }
-            hb = wave_min_u64(hb);
+            hb = ~wave_max_u64_split(~hb);
             if (hb == ~0ull) break;
             pick = (int32_t)(hb & 0xFFFFFFFFu);
+            const int2 pa = nd[pick], pb = nd[pick + 1];
+            pw = pa.y;
+            pe0 = pa.x;
+            pe1 = pb.x;
         }
-        const int2 pa = nd[pick], pb = nd[pick + 1];
-        // both entries before the branch: one LDS round trip for the weight and the row
-        asm volatile("" ::"v"(pa.x), "v"(pa.y), "v"(pb.x));
-        const int32_t pw = pa.y, pe0 = pa.x, pe1 = pb.x;
         if (w0 + pw > cap0) {
             // a frontier node that does not fit: drop it for the rest of the growth
             if (lane == 0) key[pick] = kUnfit;

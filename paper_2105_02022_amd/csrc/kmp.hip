@@ -610,8 +610,9 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         std::vector<int64_t> nc;
         DBuf<int32_t> cid;  // one graph: the coarse ids, computed once for the test and the contraction
         if (!batch) {
-            two_hop(c, g, U[0], label.p, cw.p, fav.p, false);
-            nc.assign(1, contract_ids(c, g, cw.p, cid));
+            int32_t nonempty = -1;  // known when no two-hop merge ran
+            two_hop(c, g, U[0], label.p, cw.p, fav.p, false, &nonempty);
+            nc.assign(1, contract_ids(c, g, cw.p, cid, JobTabs{}, nullptr, nonempty));
         } else {
             count_nonempty_jobs(c, cw.p, g.n, jt, nj, nc);
             std::vector<int64_t> lim(nj, 0);

@@ -143,6 +143,39 @@ __device__ inline uint64_t wave_min_u64(uint64_t v)
     return ~wave_max_u64(~v);
 }
 
+// Wavefront max of 32 bits in DPP steps only: within rows of 16 lanes (quad
+// swaps, half-row and row mirrors), then row_bcast:15 into rows 1 and 3 and
+// row_bcast:31 into rows 2 and 3, so lane 63 holds the maximum.  Every lane
+// must be active.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_max_step(uint32_t v)
+{
+    // lanes the step does not write read 0, the identity of the maximum
+    const uint32_t o = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+    return o > v ? o : v;
+}
+
+__device__ inline uint32_t wave_max_u32_dpp(uint32_t v)
+{
+    v = dpp_max_step<0xB1, 0xF>(v);   // quad_perm [1,0,3,2]
+    v = dpp_max_step<0x4E, 0xF>(v);   // quad_perm [2,3,0,1]
+    v = dpp_max_step<0x141, 0xF>(v);  // row_half_mirror
+    v = dpp_max_step<0x140, 0xF>(v);  // row_mirror
+    v = dpp_max_step<0x142, 0xA>(v);  // row_bcast:15
+    v = dpp_max_step<0x143, 0xC>(v);  // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// Wavefront max of a 64-bit key in two 32-bit passes: the largest high word,
+// then the largest low word among the lanes holding it (the same order as a
+// 64-bit comparison).  Every lane must be active; the result is uniform.
+__device__ inline uint64_t wave_max_u64_split(uint64_t v)
+{
+    const uint32_t hi = wave_max_u32_dpp((uint32_t)(v >> 32));
+    const uint32_t lo = wave_max_u32_dpp((uint32_t)(v >> 32) == hi ? (uint32_t)v : 0u);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // LDS slot for a key in a table of 2^bits slots (multiplicative hashing).
 __device__ inline uint32_t slot_of(uint32_t key, int bits)
 {
@@ -524,9 +557,11 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
 
 // ---------------------------------------------------------------- coarsening (coarsen.hip)
 // Two-hop of one graph; returns the number of merges when `count` is set
-// (one more read-back), else 0.
+// (one more read-back), else 0.  nonempty_out (may be NULL) receives the
+// number of non-empty labels when no merge ran (they are then unchanged),
+// else -1.
 int64_t two_hop(Ctx& c, const DGraph& g, int64_t U, int32_t* label, int64_t* cw, const uint32_t* fav,
-                bool count = true);
+                bool count = true, int32_t* nonempty_out = nullptr);
 // Two-hop of a batch: per-job bounds gU, merge limits glimit and node range
 // ends gend (device, by job; jobs with limit 0 do not take part).
 void two_hop_jobs(Ctx& c, const DGraph& g, const JobTabs& jt, const int64_t* gU, const int64_t* glimit,
@@ -545,9 +580,10 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
               int32_t& cn, int64_t& cm, const JobTabs& jt = {}, const uint8_t* gkeep = nullptr,
               DBuf<int32_t>* cid_in = nullptr, int32_t nc_in = 0, int32_t* maxdeg = nullptr);
 // Coarse id of every non-empty label (exclusive prefix of the non-empty
-// flags, jobs with gkeep[job] == 0 excluded); returns their number.
+// flags, jobs with gkeep[job] == 0 excluded); returns their number (read
+// back unless the caller already knows it: known >= 0).
 int32_t contract_ids(Ctx& c, const DGraph& g, const int64_t* cw, DBuf<int32_t>& cid, const JobTabs& jt = {},
-                     const uint8_t* gkeep = nullptr);
+                     const uint8_t* gkeep = nullptr, int32_t known = -1);
 
 // ---------------------------------------------------------------- IP (ip.hip)
 // Block table of a level: blocks in job order, ascending `first` inside a job.

@@ -739,14 +739,22 @@ void iota_i32(Ctx& c, int32_t* p, int64_t n)
 namespace {
 
 // out[0] = xadj[n]; out[1] = max over v of xadj[v + 1] - xadj[v] (out zeroed)
+// One atomic per workgroup (atomics on one address serialise; the grid is
+// capped at one workgroup per compute unit).
 __global__ __launch_bounds__(kBlock) void k_max_deg(const int32_t* __restrict__ xadj, int32_t n, int32_t* out)
 {
+    __shared__ int32_t s_m[kBlock / 64];
     int32_t m = 0;
     for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x)
         m = max(m, xadj[v + 1] - xadj[v]);
     for (int q = 32; q > 0; q >>= 1) m = max(m, __shfl_xor(m, q, 64));
-    if ((threadIdx.x & 63) == 0 && m) atomicMax(&out[1], m);
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = xadj[n];
+    if ((threadIdx.x & 63) == 0) s_m[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) m = max(m, s_m[w]);
+        if (m) atomicMax(&out[1], m);
+        if (blockIdx.x == 0) out[0] = xadj[n];
+    }
 }
 
 }  // namespace
@@ -760,7 +768,7 @@ void entries_and_max_degree(Ctx& c, const int32_t* xadj, int32_t n, int64_t& m, 
         fill_bytes_many(c, {{own.p, 8, 0}});
         out = own.p;
     }
-    hipLaunchKernelGGL(k_max_deg, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, xadj, n, out);
+    hipLaunchKernelGGL(k_max_deg, dim3(grid_for(n, kBlock, 256)), dim3(kBlock), 0, c.stream, xadj, n, out);
     KMP_LAUNCH_CHECK();
     int32_t h[2];
     c.read(h, out, sizeof(h));
