@@ -166,6 +166,33 @@ __device__ inline uint32_t wave_max_u32_dpp(uint32_t v)
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
+// Sum over groups of WIDTH = 16 (one row) or 64 lanes in DPP steps: row
+// butterflies (quad swaps, half-row and row mirrors), then for 64 lanes
+// row_bcast:15 and row_bcast:31 and lane 63's total to every lane.  Every
+// lane of the group ends with the group's sum; every lane must be active.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_add_step(uint32_t v)
+{
+    // lanes the step does not write read 0, the identity of the sum
+    return v + (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int WIDTH>
+__device__ inline uint32_t group_sum_u32(uint32_t v)
+{
+    static_assert(WIDTH == 16 || WIDTH == 64, "DPP groups are rows or the wavefront");
+    v = dpp_add_step<0xB1, 0xF>(v);
+    v = dpp_add_step<0x4E, 0xF>(v);
+    v = dpp_add_step<0x141, 0xF>(v);
+    v = dpp_add_step<0x140, 0xF>(v);
+    if (WIDTH == 64) {
+        v = dpp_add_step<0x142, 0xA>(v);
+        v = dpp_add_step<0x143, 0xC>(v);
+        v = (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+    }
+    return v;
+}
+
 // Wavefront max of a 64-bit key in two 32-bit passes: the largest high word,
 // then the largest low word among the lanes holding it (the same order as a
 // 64-bit comparison).  Every lane must be active; the result is uniform.

@@ -150,16 +150,35 @@ __device__ inline bool better(const Key3& a, const Key3& b)
     return a.k < b.k;
 }
 
+// One DPP step of the group argmax; lanes the step does not write see their own key.
+template <int CTRL, int ROWS>
+__device__ inline void best_step(Key3& a)
+{
+    Key3 b;
+    b.r = (uint32_t)__builtin_amdgcn_update_dpp((int)a.r, (int)a.r, CTRL, ROWS, 0xF, false);
+    b.h = (uint32_t)__builtin_amdgcn_update_dpp((int)a.h, (int)a.h, CTRL, ROWS, 0xF, false);
+    b.k = (uint32_t)__builtin_amdgcn_update_dpp((int)a.k, (int)a.k, CTRL, ROWS, 0xF, false);
+    if (better(b, a)) a = b;
+}
+
+// Best key of a group of WIDTH = 16 (one row) or 64 lanes, in every lane of the
+// group: row butterflies, then for 64 lanes row_bcast:15 / row_bcast:31 and
+// lane 63's result to every lane (`better` is a strict total order, so the
+// order of the comparisons does not matter).  Every lane must be active.
 template <int WIDTH>
 __device__ inline Key3 group_best(Key3 a)
 {
-#pragma unroll
-    for (int d = WIDTH / 2; d > 0; d >>= 1) {
-        Key3 b;
-        b.r = __shfl_xor(a.r, d, WIDTH);
-        b.h = __shfl_xor(a.h, d, WIDTH);
-        b.k = __shfl_xor(a.k, d, WIDTH);
-        if (better(b, a)) a = b;
+    static_assert(WIDTH == 16 || WIDTH == 64, "DPP groups are rows or the wavefront");
+    best_step<0xB1, 0xF>(a);   // quad_perm [1,0,3,2]
+    best_step<0x4E, 0xF>(a);   // quad_perm [2,3,0,1]
+    best_step<0x141, 0xF>(a);  // row_half_mirror
+    best_step<0x140, 0xF>(a);  // row_mirror
+    if (WIDTH == 64) {
+        best_step<0x142, 0xA>(a);  // row_bcast:15
+        best_step<0x143, 0xC>(a);  // row_bcast:31
+        a.r = (uint32_t)__builtin_amdgcn_readlane((int)a.r, 63);
+        a.h = (uint32_t)__builtin_amdgcn_readlane((int)a.h, 63);
+        a.k = (uint32_t)__builtin_amdgcn_readlane((int)a.k, 63);
     }
     return a;
 }
@@ -257,13 +276,12 @@ __device__ inline void consider(const RateArgs& a, const NodeKey& nk, uint32_t k
     }
 }
 
-// per-wave statistic: rated entries and algorithmic bytes
-__device__ inline void flush_stats(const RateArgs& a, int64_t nodes, int64_t edges)
+// per-wave statistic: rated entries and algorithmic bytes (a wave rates fewer
+// than 2^31 entries: a single graph has fewer, batches stay below 2^31)
+__device__ inline void flush_stats(const RateArgs& a, int64_t nodes_in, int64_t edges_in)
 {
-    for (int d = 32; d > 0; d >>= 1) {
-        edges += __shfl_xor(edges, d, 64);
-        nodes += __shfl_xor(nodes, d, 64);
-    }
+    const int64_t edges = group_sum_u32<64>((uint32_t)edges_in);
+    const int64_t nodes = group_sum_u32<64>((uint32_t)nodes_in);
     if ((threadIdx.x & 63) == 0 && nodes) {
         spread_add(a.counters, edges);
         spread_add(a.bytes_ctr, 25 * nodes + (a.adjwgt ? 12 : 8) * edges);
@@ -430,16 +448,14 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             cv = a.vwgt ? a.vwgt[v] : 1;
             for (int j = gl; j < HS; j += G) consider(a, nk, keys[j], vals[j], own, cv, fav, adm, rown);
         }
-        if (G <= 64) {
+        if constexpr (G <= 64) {
             fav = group_best<G>(fav);
             adm = group_best<G>(adm);
-#pragma unroll
-            for (int d = G / 2; d > 0; d >>= 1) rown += __shfl_xor(rown, d, G);
+            rown = group_sum_u32<G>(rown);
         } else {
             fav = group_best<64>(fav);
             adm = group_best<64>(adm);
-#pragma unroll
-            for (int d = 32; d > 0; d >>= 1) rown += __shfl_xor(rown, d, 64);
+            rown = group_sum_u32<64>(rown);
             const int w = tid >> 6;
             if ((tid & 63) == 0) {
                 s_red[0][w] = fav;
@@ -517,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
         }
         fav = group_best<64>(fav);
         adm = group_best<64>(adm);
-        for (int dd = 32; dd > 0; dd >>= 1) rown += __shfl_xor(rown, dd, 64);
+        rown = group_sum_u32<64>(rown);
         const int w = tid >> 6;
         if ((tid & 63) == 0) {
             s_red[0][w] = fav;
@@ -797,7 +813,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
         acc[v] = 0;
         demand[K] = 0;
     }
-    for (int d = 32; d > 0; d >>= 1) mine += __shfl_xor(mine, d, 64);
+    mine = (int32_t)group_sum_u32<64>((uint32_t)mine);
     if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&bm, mine);
     __syncthreads();
     if (threadIdx.x == 0 && bm)
@@ -1127,8 +1143,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 }
                 fav = group_best<64>(fav);
                 adm = group_best<64>(adm);
-#pragma unroll
-                for (int dd = 32; dd > 0; dd >>= 1) rown += __shfl_xor(rown, dd, 64);
+                rown = group_sum_u32<64>(rown);
                 if (lane == 0) {
                     if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
                     if (adm.r > rown) {
@@ -1246,7 +1261,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
             }
             __syncthreads();
         }
-        for (int dd = 32; dd > 0; dd >>= 1) mine += __shfl_xor(mine, dd, 64);
+        mine = (int32_t)group_sum_u32<64>((uint32_t)mine);
         if (lane == 0 && mine) atomicAdd(&s_moves, mine);
         __syncthreads();
         const int32_t moved = s_moves;

@@ -392,16 +392,57 @@ struct OpMax {
 template <typename T>
 __device__ inline T shfl_up_t(T v, unsigned d) { return __shfl_up(v, d, 64); }
 
+// One DPP step of a 32-bit wavefront scan: lanes without a source (or outside
+// ROWS) combine with the identity.
+template <int CTRL, int ROWS, typename T, typename Op>
+__device__ inline T dpp_scan_step(T v, Op op, T identity)
+{
+    const T o = (T)__builtin_amdgcn_update_dpp((int)identity, (int)v, CTRL, ROWS, 0xF, false);
+    return op(o, v);
+}
+
+// Inclusive wavefront scan: row_shr 1, 2, 4, 8 inside rows of 16 lanes, then
+// row_bcast:15 into rows 1 and 3 and row_bcast:31 into rows 2 and 3 (32-bit
+// values in DPP steps; wider ones through lane shuffles).  All lanes active.
+template <typename T, typename Op>
+__device__ inline T wave_scan_incl(T v, Op op, T identity)
+{
+    if constexpr (sizeof(T) == 4) {
+        v = dpp_scan_step<0x111, 0xF>(v, op, identity);  // row_shr:1
+        v = dpp_scan_step<0x112, 0xF>(v, op, identity);  // row_shr:2
+        v = dpp_scan_step<0x114, 0xF>(v, op, identity);  // row_shr:4
+        v = dpp_scan_step<0x118, 0xF>(v, op, identity);  // row_shr:8
+        v = dpp_scan_step<0x142, 0xA>(v, op, identity);  // row_bcast:15
+        v = dpp_scan_step<0x143, 0xC>(v, op, identity);  // row_bcast:31
+    } else {
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            T y = shfl_up_t(v, d);
+            if (lane >= d) v = op(y, v);
+        }
+    }
+    return v;
+}
+
+// The value of the previous lane (lane 0: identity).
+template <typename T>
+__device__ inline T wave_prev(T v, T identity)
+{
+    if constexpr (sizeof(T) == 4) {
+        return (T)__builtin_amdgcn_update_dpp((int)identity, (int)v, 0x138, 0xF, 0xF, false);  // wave_shr:1
+    } else {
+        const T p = __shfl_up(v, 1, 64);
+        return (threadIdx.x & 63) ? p : identity;
+    }
+}
+
 // Inclusive scan of one value per thread across a 256-thread block.
 template <typename T, typename Op>
-__device__ T block_scan_incl(T v, Op op, T* lds_waves)
+__device__ T block_scan_incl(T v, Op op, T* lds_waves, T identity)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        T y = shfl_up_t(v, d);
-        if (lane >= d) v = op(y, v);
-    }
+    v = wave_scan_incl<T, Op>(v, op, identity);
     if (lane == 63) lds_waves[w] = v;
     __syncthreads();
     if (w > 0) {
@@ -425,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_reduce(const T* __restrict__ in
 #pragma unroll
     for (int j = 0; j < SCAN_IT; ++j)
         if (base + j < n) acc = op(acc, in[base + j]);
-    T tot = block_scan_incl<T, Op>(acc, op, lds);
+    T tot = block_scan_incl<T, Op>(acc, op, lds, identity);
     if (threadIdx.x == kBlock - 1) partial[blockIdx.x] = tot;
 }
 
@@ -452,11 +493,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const T* in, T* out, int6
             v[j] = base + j < n ? in[base + j] : identity;
             acc = op(acc, v[j]);
         }
-        T incl = block_scan_incl<T, Op>(acc, op, lds);
+        T incl = block_scan_incl<T, Op>(acc, op, lds, identity);
         // exclusive prefix of this thread = incl - own (recompute via op: prefix before thread)
         T run = op(carry, incl);
         // derive this thread's exclusive start: shift inclusive totals by one thread
-        T prev = __shfl_up(incl, 1, 64);
+        T prev = wave_prev<T>(incl, identity);
         __shared__ T wave_last[4];
         const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
         if (lane == 63) wave_last[w] = incl;
