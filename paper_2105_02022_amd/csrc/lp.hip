@@ -342,14 +342,25 @@ __device__ inline void rate_lane_node(const RateArgs& a, int32_t v, uint32_t own
     for (int j = 0; j < DEG; ++j) ov[j] = BAL ? a.over[lab[j] != EMPTY ? lab[j] : own] != 0 : false;
     Key3 fav{0, 0, 0}, adm{0, 0, 0};
     uint32_t rown = 0;
+    if (a.fav) {  // clustering keeps the favoured cluster too (uniform branch)
 #pragma unroll
-    for (int j = 0; j < DEG; ++j) {
-        const bool is_own = lab[j] == own;
-        rown = is_own ? w[j] : rown;
-        const bool cand = lab[j] != EMPTY && !is_own;
-        const Key3 c{w[j], hash_step(nk.hp, lab[j] - nk.lo, 4), lab[j]};
-        if (cand && better(c, fav)) fav = c;
-        if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
+        for (int j = 0; j < DEG; ++j) {
+            const bool is_own = lab[j] == own;
+            rown = is_own ? w[j] : rown;
+            const bool cand = lab[j] != EMPTY && !is_own;
+            const Key3 c{w[j], hash_step(nk.hp, lab[j] - nk.lo, 4), lab[j]};
+            if (cand && better(c, fav)) fav = c;
+            if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) {
+            const bool is_own = lab[j] == own;
+            rown = is_own ? w[j] : rown;
+            const bool cand = lab[j] != EMPTY && !is_own;
+            const Key3 c{w[j], hash_step(nk.hp, lab[j] - nk.lo, 4), lab[j]};
+            if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
+        }
     }
     write_result(a, v, fav, adm, rown, cv);
 }
@@ -988,17 +999,31 @@ __device__ inline void rate_lane_local(const RateArgs& a, int32_t v, int32_t sta
         }
         lab[k] = dup ? EMPTY : lab[k];
     }
+    if (a.fav) {  // clustering keeps the favoured cluster too (uniform branch)
 #pragma unroll
-    for (int j = 0; j < DEG; ++j) {
-        const bool is_own = lab[j] == own;
-        rown = is_own ? w[j] : rown;
-        const bool cand = lab[j] != EMPTY && !is_own;
-        const uint32_t l = cand ? lab[j] : own;
-        const int64_t wk = s_wt[l];
-        const int64_t ck = CAPV ? a.cap_vec[lo + l] : nk.cap;
-        const Key3 c{w[j], hash_step(nk.hp, lab[j], 4), lab[j]};
-        if (cand && better(c, fav)) fav = c;
-        if (cand && wk + cv <= ck && better(c, adm)) adm = c;
+        for (int j = 0; j < DEG; ++j) {
+            const bool is_own = lab[j] == own;
+            rown = is_own ? w[j] : rown;
+            const bool cand = lab[j] != EMPTY && !is_own;
+            const uint32_t l = cand ? lab[j] : own;
+            const int64_t wk = s_wt[l];
+            const int64_t ck = CAPV ? a.cap_vec[lo + l] : nk.cap;
+            const Key3 c{w[j], hash_step(nk.hp, lab[j], 4), lab[j]};
+            if (cand && better(c, fav)) fav = c;
+            if (cand && wk + cv <= ck && better(c, adm)) adm = c;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < DEG; ++j) {
+            const bool is_own = lab[j] == own;
+            rown = is_own ? w[j] : rown;
+            const bool cand = lab[j] != EMPTY && !is_own;
+            const uint32_t l = cand ? lab[j] : own;
+            const int64_t wk = s_wt[l];
+            const int64_t ck = CAPV ? a.cap_vec[lo + l] : nk.cap;
+            const Key3 c{w[j], hash_step(nk.hp, lab[j], 4), lab[j]};
+            if (cand && wk + cv <= ck && better(c, adm)) adm = c;
+        }
     }
 }
 
