@@ -1107,8 +1107,9 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
         for (int s = 0; s < kSub; ++s) {
             const int32_t o0 = s_off[3 * s], c0 = s_cnt[3 * s] + s_cnt[3 * s + 1], o1 = s_off[3 * s + 2],
                           c1 = s_cnt[3 * s + 2];
-            // rate, tier 0: one lane per node
-            for (int32_t i = tid; i < c0; i += kSmallBlock) {
+            const int32_t cn = s_cnt[3 * s], ow = o0 + cn, cw = s_cnt[3 * s + 1];
+            // rate, tier 0 up to degree T0_NARROW: one lane per node, neighbours in registers
+            for (int32_t i = tid; i < cn; i += kSmallBlock) {
                 const int32_t li = s_ord[o0 + i];
                 if (r > 0 && act[li] != stamp) continue;
                 const int32_t v = start + li;
@@ -1118,12 +1119,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
                 Key3 fav{0, 0, 0}, adm{0, 0, 0};
                 uint32_t rown = 0;
-                if (ballot64(d > T0_NARROW))
-                    rate_lane_local<T0_DEG, EW, CAPV>(a, v, start, lo, own, e0, d, cv, nk, s_lab, s_wt, fav, adm,
-                                                      rown);
-                else
-                    rate_lane_local<T0_NARROW, EW, CAPV>(a, v, start, lo, own, e0, d, cv, nk, s_lab, s_wt, fav,
-                                                         adm, rown);
+                rate_lane_local<T0_NARROW, EW, CAPV>(a, v, start, lo, own, e0, d, cv, nk, s_lab, s_wt, fav, adm,
+                                                     rown);
                 if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
                 if (adm.r > rown) {
                     s_prop[li] = (int16_t)adm.k;
@@ -1131,6 +1128,74 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 }
                 edges += d;
                 nodes += 1;
+            }
+            // rate, the rest of tier 0 (degree <= cut0 <= 16): 16 lanes per node, one
+            // neighbour per lane into a 32-slot LDS table of the group (the per-wave
+            // tables below, split in four); the trip count is uniform in the block so
+            // that the group reductions see whole wavefronts
+            {
+                constexpr int GW = 16, GS = 32, NG = kSmallBlock / GW;
+                const int g = tid / GW, gl = tid % GW;
+                uint32_t* gk = s_keys + g * GS;
+                uint32_t* gv = s_vals + g * GS;
+                for (int32_t i0 = 0; i0 < cw; i0 += NG) {
+                    const int32_t i = i0 + g;
+                    int32_t li = i < cw ? s_ord[ow + i] : -1;
+                    if (li >= 0 && r > 0 && act[li] != stamp) li = -1;
+                    gk[gl] = EMPTY;
+                    gk[gl + GW] = EMPTY;
+                    gv[gl] = 0;
+                    gv[gl + GW] = 0;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    int32_t v = 0, d = 0;
+                    int64_t cv = 0;
+                    uint32_t own = EMPTY;
+                    if (li >= 0) {
+                        v = start + li;
+                        const int32_t e0 = a.xadj[v];
+                        d = a.xadj[v + 1] - e0;
+                        cv = a.vwgt ? a.vwgt[v] : 1;
+                        own = (uint32_t)s_lab[li];
+                        if (gl < d)
+                            lds_insert(gk, gv, 5, (uint32_t)s_lab[a.adjncy[e0 + gl] - start],
+                                       EW ? (uint32_t)a.adjwgt[e0 + gl] : 1u);
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    Key3 fav{0, 0, 0}, adm{0, 0, 0};
+                    uint32_t rown = 0;
+                    if (li >= 0) {
+                        for (int j = gl; j < GS; j += GW) {
+                            const uint32_t key = gk[j], val = gv[j];
+                            if (key == EMPTY) continue;
+                            if (key == own) {
+                                rown = val;
+                                continue;
+                            }
+                            const Key3 c{val, hash_step(nk.hp, key, 4), key};
+                            if (a.fav && better(c, fav)) fav = c;
+                            if (better(c, adm)) {
+                                const int64_t ck = CAPV ? a.cap_vec[lo + key] : nk.cap;
+                                if (s_wt[key] + cv <= ck) adm = c;
+                            }
+                        }
+                    }
+                    fav = group_best<GW>(fav);
+                    adm = group_best<GW>(adm);
+                    rown = group_sum_u32<GW>(rown);
+                    if (li >= 0 && gl == 0) {
+                        if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
+                        if (adm.r > rown) {
+                            s_prop[li] = (int16_t)adm.k;
+                            atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                        }
+                        edges += d;
+                        nodes += 1;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();  // the table is reused only after every read
+                }
             }
             // rate, tier 1: one wavefront per node (the loop is uniform in the wave)
             for (int32_t i = wv; i < c1; i += NW) {
