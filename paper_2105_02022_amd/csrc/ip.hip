@@ -585,13 +585,19 @@ void block_weights(Ctx& c, const DGraph& g, const int32_t* part, int32_t nb, int
     KMP_LAUNCH_CHECK();
 }
 
-int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part)
+void edge_cut_launch(Ctx& c, const DGraph& g, const int32_t* part)
 {
-    if (g.n <= 0) return 0;
     c.zero_spread(SP_CUT);
+    if (g.n <= 0) return;
     hipLaunchKernelGGL(k_cut, dim3(grid_for(g.n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
                        g.adjwgt, part, g.n, c.spread(SP_CUT));
     KMP_LAUNCH_CHECK();
+}
+
+int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part)
+{
+    if (g.n <= 0) return 0;
+    edge_cut_launch(c, g, part);
     return c.read_spread(SP_CUT) / 2;
 }
 

@@ -799,20 +799,30 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
                            L0.gid.p, L0.dnoff.p, dptr.p, L0.g.n);
         KMP_LAUNCH_CHECK();
     }
-    std::vector<int64_t> hw(nb);
-    c.read(hw.data(), wt.p, sizeof(int64_t) * nb);
+    // block weights, rated entries, move counts (and one graph's cut) in one read-back
+    if (!batch) edge_cut_launch(c, L0.g, part.p);
+    constexpr int32_t nm = 2 * (kRounds + 1);
+    std::vector<std::pair<const int64_t*, int32_t>> segs = {
+        {wt.p, nb}, {c.spread(SP_RATED), kSpreadSlots}, {dmoves.p, nm}};
+    if (!batch) segs.push_back({c.spread(SP_CUT), kSpreadSlots});
+    std::vector<int64_t> h((size_t)nb + kSpreadSlots + nm + (batch ? 0 : kSpreadSlots));
+    read_segments(c, segs, h.data());
+    const int64_t* hw = h.data();
+    const int64_t* hr = hw + nb;
+    const int64_t* hm = hr + kSpreadSlots;
     for (int32_t b = 0; b < nb; ++b) jobs[bt.job[b]].maxw = std::max(jobs[bt.job[b]].maxw, hw[b]);
     if (!batch) {
-        jobs[0].cut = edge_cut(c, L0.g, part.p);
+        int64_t cut2 = 0;
+        for (int q = 0; q < kSpreadSlots; ++q) cut2 += hm[nm + q];
+        jobs[0].cut = cut2 / 2;
     } else {
         std::vector<int64_t> cuts;
         edge_cut_jobs(c, L0.g, part.p, L0.gid.p, nj, cuts);
         for (int32_t j : L0.mem) jobs[j].cut = cuts[j];
     }
     for (int32_t j : L0.mem) jobs[j].status = jobs[j].maxw > jobs[j].lk ? KMP_IMBALANCED : KMP_OK;
-    t.rated = c.read_spread(SP_RATED);
-    int64_t hm[2 * (kRounds + 1)];
-    c.read(hm, dmoves.p, sizeof(hm));
+    t.rated = 0;
+    for (int q = 0; q < kSpreadSlots; ++q) t.rated += hr[q];
     for (int r = 0; r < kRounds; ++r) {
         t.moves_cl += hm[r];
         t.moves_ref += hm[kRounds + 1 + r];

@@ -487,6 +487,9 @@ void fill_i64(Ctx& c, int64_t* p, int64_t v, int64_t n);
 inline void set_i64(Ctx& c, int64_t* p, int64_t v) { fill_i64(c, p, v, 1); }
 void iota_i32(Ctx& c, int32_t* p, int64_t n);
 // Sum of node / edge weights (int64; NULL weights count 1 each).
+// Read several device int64 ranges (pointer, count) with one read-back, in order.
+constexpr int kMaxReadSegs = 4;
+void read_segments(Ctx& c, const std::vector<std::pair<const int64_t*, int32_t>>& segs, int64_t* host);
 int64_t node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n);
 int64_t edge_weight_sum(Ctx& c, const int32_t* adjwgt, int64_t m);
 int bits_for(uint64_t max_value);
@@ -630,6 +633,8 @@ void project_jobs(Ctx& c, const int32_t* coarse_part, const int32_t* map, const 
                   const int32_t* gid, const int32_t* start_block, int32_t* fine_part, int32_t n);
 void block_weights(Ctx& c, const DGraph& g, const int32_t* part, int32_t nb, int64_t* wt);
 int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part);
+// Enqueue the cut count into spread counter SP_CUT (twice the cut) without reading it.
+void edge_cut_launch(Ctx& c, const DGraph& g, const int32_t* part);
 // Cut of every job (gid by node).
 void edge_cut_jobs(Ctx& c, const DGraph& g, const int32_t* part, const int32_t* gid, int32_t njobs,
                    std::vector<int64_t>& out);

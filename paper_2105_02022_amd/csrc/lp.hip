@@ -765,14 +765,23 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
     int32_t mine = 0;
     for (int64_t i0 = (int64_t)xcd_block() * blockDim.x; i0 < cs.total; i0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = i0 + threadIdx.x;
-        int32_t v = -1, K = -1;
+        int32_t v = -1, K = -1, cw = 1, old = 0, e0 = 0, e1 = 0;
         uint8_t a = 0;
+        const bool mark = act_next && i < cs.total && class_tier(cs, i) <= 1;
         if (i < cs.total) {
             v = list[class_pos(cs, i)];
+            // everything a move needs, loaded together (acc[v] is 0 without a proposal)
             K = prop[v];
-            if (K >= 0) a = acc[v];
+            a = acc[v];
+            if (vwgt) cw = vwgt[v];
+            old = label[v];
+            if (mark) {
+                e0 = xadj[v];
+                e1 = xadj[v + 1];
+            }
+            asm volatile("" ::"v"(K), "v"((int32_t)a), "v"(cw), "v"(old), "v"(e0), "v"(e1));
         }
-        const bool contended = a == 2;
+        const bool contended = K >= 0 && a == 2;
         if (__syncthreads_or(contended)) {
             int64_t pre = 0;
             for (int64_t c0 = 0; c0 < C; c0 += kCandChunk) {
@@ -800,8 +809,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
         }
         if (K < 0) continue;
         if (a == 1) {
-            const int64_t c = vwgt ? vwgt[v] : 1;
-            const int32_t old = label[v];
+            const int64_t c = cw;
             label[v] = K;
             atomicAdd((unsigned long long*)&wt[K], (unsigned long long)c);
             atomicAdd((unsigned long long*)&wt[old], (unsigned long long)(-c));
@@ -809,8 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
             ++mine;
             // next round's active set: the neighbours of a moved node of degree
             // <= T1_DEG are marked here (larger ones by k_push_active)
-            if (act_next && class_tier(cs, i) <= 1) {
-                const int32_t e0 = xadj[v], e1 = xadj[v + 1];
+            if (mark) {
                 for (int32_t eb = e0; eb < e1; eb += 8) {
                     int32_t u[8];
 #pragma unroll

@@ -817,6 +817,42 @@ void entries_and_max_degree(Ctx& c, const int32_t* xadj, int32_t n, int64_t& m, 
     maxdeg = h[1];
 }
 
+// ---------------------------------------------------------------- packed read-back
+namespace {
+struct Segs {
+    const int64_t* p[kMaxReadSegs];
+    int32_t n[kMaxReadSegs];
+    int32_t count;
+};
+
+__global__ __launch_bounds__(kBlock) void k_gather_segs(Segs s, int64_t* __restrict__ out)
+{
+    int64_t o = 0;
+    for (int q = 0; q < s.count; ++q) {
+        for (int32_t i = threadIdx.x; i < s.n[q]; i += blockDim.x) out[o + i] = s.p[q][i];
+        o += s.n[q];
+    }
+}
+}  // namespace
+
+void read_segments(Ctx& c, const std::vector<std::pair<const int64_t*, int32_t>>& segs, int64_t* host)
+{
+    if (segs.empty() || segs.size() > (size_t)kMaxReadSegs) throw std::invalid_argument("read_segments");
+    Segs s{};
+    int64_t total = 0;
+    s.count = (int32_t)segs.size();
+    for (size_t q = 0; q < segs.size(); ++q) {
+        s.p[q] = segs[q].first;
+        s.n[q] = segs[q].second;
+        total += segs[q].second;
+    }
+    if (total == 0) return;
+    DBuf<int64_t> buf(c, (size_t)total);
+    hipLaunchKernelGGL(k_gather_segs, dim3(1), dim3(kBlock), 0, c.stream, s, buf.p);
+    KMP_LAUNCH_CHECK();
+    c.read(host, buf.p, sizeof(int64_t) * (size_t)total);
+}
+
 int64_t node_weight_sum(Ctx& c, const int32_t* vwgt, int32_t n)
 {
     if (!vwgt) return n;
