@@ -232,10 +232,18 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
         if (tid == 0) s_pmax = 2;
         __syncthreads();
         if (row >= 0) {
-            for (int32_t mi = a.mstart[row]; mi < a.mstart[row + 1]; ++mi) {
+            // the group's lanes split over the row's members (a power-of-two share
+            // each, all G lanes for a single member), so the members' rows are
+            // read side by side rather than one after another
+            const int32_t m0 = a.mstart[row], m1 = a.mstart[row + 1];
+            const int32_t nm = m1 - m0 < G ? m1 - m0 : G;
+            int sw = G;  // lanes per member
+            while (sw > 1 && (G / sw) < nm) sw >>= 1;
+            const int sub = gl / sw, sl = gl % sw, par = G / sw;
+            for (int32_t mi = m0 + sub; mi < m1; mi += par) {
                 const int32_t v = a.members[mi];
                 const int32_t e1 = a.xadj[v + 1];
-                for (int32_t e = a.xadj[v] + gl; e < e1; e += G) {
+                for (int32_t e = a.xadj[v] + sl; e < e1; e += sw) {
                     const int32_t cu = a.map[a.adjncy[e]];
                     if (cu == row) continue;
                     const uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
