@@ -971,21 +971,21 @@ struct SmallLP {
 // Tier-0 rating of local node li (global id v) against the LDS labels and
 // weights; labels are local (global label - lo), which is also what the
 // tie-break hash takes.
-template <int DEG, bool EW, bool CAPV>
-__device__ inline void rate_lane_local(const RateArgs& a, int32_t v, int32_t start, int32_t lo, uint32_t own,
-                                       int32_t e0, int32_t d, int64_t cv, const NodeKey& nk,
-                                       const int16_t* s_lab, const int32_t* s_wt, Key3& fav, Key3& adm,
-                                       uint32_t& rown)
+// nbr(e) gives entry e's neighbour as a local id, ewt(e) its weight.
+template <int DEG, bool EW, bool CAPV, class NB, class EWT>
+__device__ inline void rate_lane_local(const RateArgs& a, int32_t lo, uint32_t own, int32_t e0, int32_t d, int64_t cv,
+                                       const NodeKey& nk, const int16_t* s_lab, const int32_t* s_wt, NB nbr, EWT ewt,
+                                       Key3& fav, Key3& adm, uint32_t& rown)
 {
     uint32_t lab[DEG], w[DEG];
     if (d > 0) {
         int32_t u[DEG];
 #pragma unroll
-        for (int j = 0; j < DEG; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
+        for (int j = 0; j < DEG; ++j) u[j] = nbr(e0 + (j < d ? j : d - 1));
 #pragma unroll
-        for (int j = 0; j < DEG; ++j) w[j] = EW ? (uint32_t)a.adjwgt[e0 + (j < d ? j : d - 1)] : 1u;
+        for (int j = 0; j < DEG; ++j) w[j] = ewt(e0 + (j < d ? j : d - 1));
 #pragma unroll
-        for (int j = 0; j < DEG; ++j) lab[j] = j < d ? (uint32_t)s_lab[u[j] - start] : EMPTY;
+        for (int j = 0; j < DEG; ++j) lab[j] = j < d ? (uint32_t)s_lab[u[j]] : EMPTY;
 #pragma unroll
         for (int j = 0; j < DEG; ++j) w[j] = j < d ? w[j] : 0u;
     } else {
@@ -1034,7 +1034,9 @@ __device__ inline void rate_lane_local(const RateArgs& a, int32_t v, int32_t sta
     }
 }
 
-template <bool EW, bool CAPV>
+// LCSR: the job's CSR is copied to LDS first (row starts relative to the job's
+// first entry, node weights, edge weights, neighbours as local ids).
+template <bool EW, bool CAPV, bool LCSR>
 __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
 {
     constexpr int HB = 7, HS = 1 << HB, NW = kSmallBlock / 64;
@@ -1061,6 +1063,29 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
     int16_t* s_prop = s_lab + nj;
     uint8_t* s_acc = reinterpret_cast<uint8_t*>(s_prop + nj);
     uint8_t* s_act[2] = {s_acc + nj, s_acc + 2 * nj};
+    int32_t *s_xa = nullptr, *s_vw = nullptr, *s_ew = nullptr;
+    int16_t* s_adj = nullptr;
+    if (LCSR) {
+        const int32_t ebase = a.xadj[start], mj = a.xadj[start + nj] - ebase;
+        char* q = reinterpret_cast<char*>(((uintptr_t)(s_act[1] + nj) + 15) & ~(uintptr_t)15);
+        s_xa = reinterpret_cast<int32_t*>(q);
+        s_vw = s_xa + (nj + 1);
+        s_ew = s_vw + (a.vwgt ? nj : 0);
+        s_adj = reinterpret_cast<int16_t*>(s_ew + (EW ? mj : 0));
+        for (int32_t i = tid; i <= nj; i += kSmallBlock) s_xa[i] = a.xadj[start + i] - ebase;
+        if (a.vwgt)
+            for (int32_t i = tid; i < nj; i += kSmallBlock) s_vw[i] = a.vwgt[start + i];
+        for (int32_t e = tid; e < mj; e += kSmallBlock) {
+            s_adj[e] = (int16_t)(a.adjncy[ebase + e] - start);
+            if (EW) s_ew[e] = a.adjwgt[ebase + e];
+        }
+    }
+    // row start (entry index: local with LCSR, global without), neighbour (local id),
+    // edge weight, node weight of local node li / entry e
+    auto row0 = [&](int32_t li) -> int32_t { return LCSR ? s_xa[li] : a.xadj[start + li]; };
+    auto nbr = [&](int32_t e) -> int32_t { return LCSR ? (int32_t)s_adj[e] : a.adjncy[e] - start; };
+    auto ewt = [&](int32_t e) -> uint32_t { return !EW ? 1u : LCSR ? (uint32_t)s_ew[e] : (uint32_t)a.adjwgt[e]; };
+    auto nwt = [&](int32_t li) -> int32_t { return !a.vwgt ? 1 : LCSR ? s_vw[li] : a.vwgt[start + li]; };
     for (int32_t i = tid; i < nj; i += kSmallBlock) {
         s_lab[i] = (int16_t)(p.label[start + i] - lo);
         s_prop[i] = -1;
@@ -1078,7 +1103,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
     // T0_NARROW, the other tier-0 nodes, then tier-1 nodes (list 3 s + 0, 1, 2).
     // The order inside a list does not matter.
     auto list_of = [&](int32_t i) -> int {
-        const int32_t d = a.xadj[start + i + 1] - a.xadj[start + i];
+        const int32_t d = row0(i + 1) - row0(i);
         const int t = d > p.cut0 ? 2 : d <= T0_NARROW ? 0 : 1;
         return 3 * (int)(hash_step(hs, (uint32_t)i, 3) % kSub) + t;
     };
@@ -1121,12 +1146,12 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 if (r > 0 && act[li] != stamp) continue;
                 const int32_t v = start + li;
                 const uint32_t own = (uint32_t)s_lab[li];
-                const int32_t e0 = a.xadj[v];
-                const int32_t d = a.xadj[v + 1] - e0;
-                const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
+                const int32_t e0 = row0(li);
+                const int32_t d = row0(li + 1) - e0;
+                const int64_t cv = nwt(li);
                 Key3 fav{0, 0, 0}, adm{0, 0, 0};
                 uint32_t rown = 0;
-                rate_lane_local<T0_NARROW, EW, CAPV>(a, v, start, lo, own, e0, d, cv, nk, s_lab, s_wt, fav, adm,
+                rate_lane_local<T0_NARROW, EW, CAPV>(a, lo, own, e0, d, cv, nk, s_lab, s_wt, nbr, ewt, fav, adm,
                                                      rown);
                 if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
                 if (adm.r > rown) {
@@ -1160,13 +1185,11 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                     uint32_t own = EMPTY;
                     if (li >= 0) {
                         v = start + li;
-                        const int32_t e0 = a.xadj[v];
-                        d = a.xadj[v + 1] - e0;
-                        cv = a.vwgt ? a.vwgt[v] : 1;
+                        const int32_t e0 = row0(li);
+                        d = row0(li + 1) - e0;
+                        cv = nwt(li);
                         own = (uint32_t)s_lab[li];
-                        if (gl < d)
-                            lds_insert(gk, gv, 5, (uint32_t)s_lab[a.adjncy[e0 + gl] - start],
-                                       EW ? (uint32_t)a.adjwgt[e0 + gl] : 1u);
+                        if (gl < d) lds_insert(gk, gv, 5, (uint32_t)s_lab[nbr(e0 + gl)], ewt(e0 + gl));
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
@@ -1215,13 +1238,12 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();
-                const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
-                for (int32_t e = e0 + lane; e < e1; e += 64)
-                    lds_insert(keys, vals, HB, (uint32_t)s_lab[a.adjncy[e] - start], EW ? (uint32_t)a.adjwgt[e] : 1u);
+                const int32_t e0 = row0(li), e1 = row0(li + 1);
+                for (int32_t e = e0 + lane; e < e1; e += 64) lds_insert(keys, vals, HB, (uint32_t)s_lab[nbr(e)], ewt(e));
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();
                 const uint32_t own = (uint32_t)s_lab[li];
-                const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
+                const int64_t cv = nwt(li);
                 Key3 fav{0, 0, 0}, adm{0, 0, 0};
                 uint32_t rown = 0;
                 for (int j = lane; j < HS; j += 64) {
@@ -1271,7 +1293,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                     s_ws[K] = (int32_t)wK;  // every proposal into K writes the same value
                     const int32_t slot = atomicAdd(&s_cont, 1);
                     const uint32_t kv = ((uint32_t)K << 16) | (uint32_t)li;
-                    const int32_t w = a.vwgt ? a.vwgt[start + li] : 1;
+                    const int32_t w = nwt(li);
                     if (slot < kCandChunk) {
                         s_kv[slot] = kv;
                         s_w[slot] = w;
@@ -1315,7 +1337,7 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                         for (int j = tid; j < len; j += kSmallBlock) {
                             const uint32_t kv = p.cont[start + q0 + j];
                             s_kv[j] = kv;
-                            s_w[j] = a.vwgt ? a.vwgt[start + (int32_t)(kv & 0xFFFFu)] : 1;
+                            s_w[j] = nwt((int32_t)(kv & 0xFFFFu));
                         }
                         __syncthreads();
                         if (contended) {
@@ -1333,21 +1355,20 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 }
                 if (K < 0) continue;
                 if (ac == 1) {
-                    const int32_t v = start + li;
-                    const int32_t c = a.vwgt ? a.vwgt[v] : 1;
+                    const int32_t c = nwt(li);
                     const int32_t old = s_lab[li];
                     s_lab[li] = (int16_t)K;
                     atomicAdd(&s_wt[K], c);
                     atomicAdd(&s_wt[old], -c);
                     if (r + 1 < kRounds) {
                         // neighbour ids in batches of 8 loads issued together
-                        const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
+                        const int32_t e0 = row0(li), e1 = row0(li + 1);
                         for (int32_t eb = e0; eb < e1; eb += 8) {
                             int32_t u[8];
 #pragma unroll
-                            for (int q = 0; q < 8; ++q) u[q] = a.adjncy[eb + q < e1 ? eb + q : e1 - 1];
+                            for (int q = 0; q < 8; ++q) u[q] = nbr(eb + q < e1 ? eb + q : e1 - 1);
 #pragma unroll
-                            for (int q = 0; q < 8; ++q) act_next[u[q] - start] = stamp_next;
+                            for (int q = 0; q < 8; ++q) act_next[u[q]] = stamp_next;
                         }
                     }
                     ++mine;
@@ -1703,15 +1724,15 @@ bool small_level(const Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t
     return true;
 }
 
-template <bool EW, bool CAPV>
+template <bool EW, bool CAPV, bool LCSR>
 void launch_small(Ctx& c, unsigned jobs, size_t lds, const SmallLP& p)
 {
     static std::once_flag once;  // LDS beyond the 64 KiB default, once per instantiation
     std::call_once(once, [] {
-        (void)hipFuncSetAttribute((const void*)k_lp_small<EW, CAPV>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)kSmallLdsBudget);
+        (void)hipFuncSetAttribute((const void*)k_lp_small<EW, CAPV, LCSR>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLdsBudget);
     });
-    KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<EW, CAPV>), dim3(jobs), dim3(kSmallBlock), lds, p);
+    KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<EW, CAPV, LCSR>), dim3(jobs), dim3(kSmallBlock), lds, p);
 }
 
 // The LP of the given jobs (node ranges and label ranges), one workgroup each.
@@ -1756,10 +1777,28 @@ LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSt
     int64_t lds = 0;
     for (size_t q = 0; q < nj; ++q) lds = std::max(lds, small_lds_bytes(count[q], nlab[q]));
     const bool ew = g.adjwgt != nullptr, capv = st.cap_vec != nullptr;
-    if (ew && capv) launch_small<true, true>(c, (unsigned)nj, (size_t)lds, p);
-    else if (ew) launch_small<true, false>(c, (unsigned)nj, (size_t)lds, p);
-    else if (capv) launch_small<false, true>(c, (unsigned)nj, (size_t)lds, p);
-    else launch_small<false, false>(c, (unsigned)nj, (size_t)lds, p);
+    // one job over the whole graph: its CSR goes to LDS too when it fits
+    bool lcsr = false;
+    if (nj == 1 && start[0] == 0 && count[0] == g.n) {
+        const int64_t csr = ((lds + 15) & ~(int64_t)15) + 4 * ((int64_t)g.n + 1) + (g.vwgt ? 4 * (int64_t)g.n : 0) +
+                            (ew ? 4 * g.m : 0) + 2 * g.m;
+        if (csr <= kSmallLdsBudget) {
+            lds = csr;
+            lcsr = true;
+        }
+    }
+    const size_t L = (size_t)lds;
+    if (lcsr) {
+        if (ew && capv) launch_small<true, true, true>(c, 1, L, p);
+        else if (ew) launch_small<true, false, true>(c, 1, L, p);
+        else if (capv) launch_small<false, true, true>(c, 1, L, p);
+        else launch_small<false, false, true>(c, 1, L, p);
+    } else {
+        if (ew && capv) launch_small<true, true, false>(c, (unsigned)nj, L, p);
+        else if (ew) launch_small<true, false, false>(c, (unsigned)nj, L, p);
+        else if (capv) launch_small<false, true, false>(c, (unsigned)nj, L, p);
+        else launch_small<false, false, false>(c, (unsigned)nj, L, p);
+    }
     LPStats out;
     if (st.moves_out) return out;  // the caller reads the accumulated counts later
     int64_t h[kRounds + 1];
