@@ -220,7 +220,20 @@ struct RateArgs {
     const int32_t* loff;
     const int64_t* gcap;
     uint32_t tag, level, round;
+    // byte sizes of adjncy and label for buffer loads (bufok: both below 2^31, so
+    // every byte offset fits the 32-bit offset of a buffer load)
+    uint32_t nr_adj, nr_lab;
+    int32_t bufok;
 };
+
+// Buffer loads for gathers (gfx9 raw buffer descriptor): an offset at or past
+// the buffer's size returns 0 without a memory access, so lanes with nothing
+// to load take part in a gather without touching memory.
+constexpr int kBufMiss = (int)0xFFFFFFF0u;
+__device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
 
 // Per-node part of the rating key: hash prefix, label offset, scalar cap.
 struct NodeKey {
@@ -294,17 +307,28 @@ __device__ inline void flush_stats(const RateArgs& a, int64_t nodes_in, int64_t 
 // back with a single wait; duplicates are merged into their first occurrence
 // with selects.  EW: edge weights present; CAPV: per-label caps; BAL: balance
 // mode.
-template <int DEG, bool EW, bool CAPV, bool BAL>
+template <int DEG, bool EW, bool CAPV, bool BAL, bool BUF>
 __device__ inline void rate_lane_node(const RateArgs& a, int32_t v, uint32_t own, int32_t e0, int32_t d, int64_t cv,
                                       const NodeKey& nk)
 {
     uint32_t lab[DEG], w[DEG];
     if (d > 0) {
         int32_t u[DEG];
+        if constexpr (BUF) {
+            // only the node's own entries are loaded (lanes past their degree miss)
+            const __amdgpu_buffer_rsrc_t radj = buf_rsrc(a.adjncy, a.nr_adj), rlab = buf_rsrc(a.label, a.nr_lab);
 #pragma unroll
-        for (int j = 0; j < DEG; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
+            for (int j = 0; j < DEG; ++j)
+                u[j] = __builtin_amdgcn_raw_buffer_load_b32(radj, j < d ? (e0 + j) * 4 : kBufMiss, 0, 0);
 #pragma unroll
-        for (int j = 0; j < DEG; ++j) lab[j] = (uint32_t)a.label[u[j]];
+            for (int j = 0; j < DEG; ++j)
+                lab[j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rlab, j < d ? u[j] * 4 : kBufMiss, 0, 0);
+        } else {
+#pragma unroll
+            for (int j = 0; j < DEG; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
+#pragma unroll
+            for (int j = 0; j < DEG; ++j) lab[j] = (uint32_t)a.label[u[j]];
+        }
 #pragma unroll
         for (int j = 0; j < DEG; ++j) w[j] = EW ? (uint32_t)a.adjwgt[e0 + (j < d ? j : d - 1)] : 1u;
 #pragma unroll
@@ -367,7 +391,7 @@ __device__ inline void rate_lane_node(const RateArgs& a, int32_t v, uint32_t own
 
 // A tier-0 segment lists its nodes of degree <= T0_NARROW first, so most
 // wavefronts take the half-width body as a whole (a wave-uniform branch).
-template <bool EW, bool CAPV, bool BAL>
+template <bool EW, bool CAPV, bool BAL, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
 {
     if (aborted(a)) return;
@@ -386,8 +410,8 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
         const int32_t d = a.xadj[v + 1] - e0;
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
         const NodeKey nk = node_key(a, v);
-        if (ballot64(d > T0_NARROW)) rate_lane_node<T0_DEG, EW, CAPV, BAL>(a, v, own, e0, d, cv, nk);
-        else rate_lane_node<T0_NARROW, EW, CAPV, BAL>(a, v, own, e0, d, cv, nk);
+        if (ballot64(d > T0_NARROW)) rate_lane_node<T0_DEG, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
+        else rate_lane_node<T0_NARROW, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
         edges += d;
         nodes += 1;
     }
@@ -1526,6 +1550,12 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
     a.loff = st.loff;
     a.gcap = st.gcap;
     a.tag = st.tag;
+    const int64_t badj = 4 * g.m, blab = 4 * (int64_t)g.n;
+    if (g.m > 0 && badj < (int64_t(1) << 31) && blab < (int64_t(1) << 31)) {
+        a.bufok = 1;
+        a.nr_adj = (uint32_t)badj;
+        a.nr_lab = (uint32_t)blab;
+    }
     if (b) {
         a.prop = b->prop.p;
         a.demand = b->demand.p;
@@ -1568,14 +1598,22 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
                 const dim3 grid(grid_for(ub, bs, 65536)), block(bs);
                 const bool ew = a.adjwgt != nullptr;
                 if (a.over) {
-                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, true>), grid, block, 0, a);
-                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, true>), grid, block, 0, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, true, false>), grid, block, 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, true, false>), grid, block, 0, a);
+                } else if (a.bufok) {
+                    if (a.cap_vec) {
+                        if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, false, true>), grid, block, 0, a);
+                        else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, false, true>), grid, block, 0, a);
+                    } else {
+                        if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, false, false, true>), grid, block, 0, a);
+                        else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, false, false, true>), grid, block, 0, a);
+                    }
                 } else if (a.cap_vec) {
-                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, false>), grid, block, 0, a);
-                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, false>), grid, block, 0, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, true, false, false>), grid, block, 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, true, false, false>), grid, block, 0, a);
                 } else {
-                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, false, false>), grid, block, 0, a);
-                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, false, false>), grid, block, 0, a);
+                    if (ew) KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<true, false, false, false>), grid, block, 0, a);
+                    else KMP_LAUNCH_TIMED(c, cls, (k_rate_lane<false, false, false, false>), grid, block, 0, a);
                 }
                 break;
             }
