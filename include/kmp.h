@@ -67,7 +67,10 @@ typedef struct kmp_options {
     int32_t small_level_n;  /* LP calls on levels of at most this many nodes (and no node of degree > 64)
                                run in one workgroup launch: 0 = default (8192), -1 = never.  The output
                                does not depend on it. */
-    int32_t reserved[3];
+    int32_t plain_loads;    /* 1: the lane rating kernel gathers with plain loads instead of buffer loads
+                               (used on graphs of 2^29 or more entries anyway); for tests.  The output
+                               does not depend on it. */
+    int32_t reserved[2];
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */

@@ -28,7 +28,8 @@ PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "
 
 class KmpOptions(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
-                ("force_exact", ctypes.c_int32), ("small_level_n", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("force_exact", ctypes.c_int32), ("small_level_n", ctypes.c_int32), ("plain_loads", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class KmpStats(ctypes.Structure):
@@ -214,10 +215,11 @@ def kmp_autotune(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed
 def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
                      stream=None, validate: bool = False, profile: bool = False,
                      profile_classes=None, force_exact: bool = False,
-                     small_level_n: int = 0) -> Tuple[int, "torch.Tensor", Dict]:
+                     small_level_n: int = 0, plain_loads: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
     (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path.
-    `small_level_n`: largest level run by the one-workgroup LP (0 default, -1 never)."""
+    `small_level_n`: largest level run by the one-workgroup LP (0 default, -1 never).
+    `plain_loads`: the lane rating kernel gathers with plain loads (the buffer-load path is the default)."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -228,6 +230,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt.profile = int(profile)
     opt.force_exact = int(force_exact)
     opt.small_level_n = int(small_level_n)
+    opt.plain_loads = int(plain_loads)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -252,7 +255,7 @@ def _stats_dict(st: "KmpStats", profile: bool) -> Dict:
 
 def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool = False,
                         profile_classes=None, force_exact: bool = False,
-                        small_level_n: int = 0) -> Tuple[int, List[Dict], Dict]:
+                        small_level_n: int = 0, plain_loads: bool = False) -> Tuple[int, List[Dict], Dict]:
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
@@ -265,6 +268,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     opt.profile = int(profile)
     opt.force_exact = int(force_exact)
     opt.small_level_n = int(small_level_n)
+    opt.plain_loads = int(plain_loads)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()

@@ -886,6 +886,7 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
     }
     c.force_exact = opt && opt->force_exact;
     c.small_level_n = opt ? opt->small_level_n : 0;
+    c.plain_loads = opt && opt->plain_loads;
     std::vector<JobRun> jobs(1);
     JobRun& jb = jobs[0];
     jb.g = g0;
@@ -925,6 +926,7 @@ int partition_batch_impl(const kmp_graph_desc* gd, int32_t count, kmp_job_result
     }
     c.force_exact = opt && opt->force_exact;
     c.small_level_n = opt ? opt->small_level_n : 0;
+    c.plain_loads = opt && opt->plain_loads;
     std::vector<JobRun> jobs(count);
     for (int32_t i = 0; i < count; ++i) {
         JobRun& jb = jobs[i];

@@ -349,6 +349,7 @@ class Ctx {
 
     Prof* prof = nullptr;  // profiling enabled when non-null
     bool force_exact = false;    // LP: contended sub-rounds take the exact path
+    bool plain_loads = false;    // lane rating: plain loads instead of buffer loads
     int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0: tune's, < 0 never)
     Tuning tune;                 // the process-wide tuning when the call started
     int prof_begin(int cls);

@@ -1551,7 +1551,7 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
     a.gcap = st.gcap;
     a.tag = st.tag;
     const int64_t badj = 4 * g.m, blab = 4 * (int64_t)g.n;
-    if (g.m > 0 && badj < (int64_t(1) << 31) && blab < (int64_t(1) << 31)) {
+    if (!c.plain_loads && g.m > 0 && badj < (int64_t(1) << 31) && blab < (int64_t(1) << 31)) {
         a.bufok = 1;
         a.nr_adj = (uint32_t)badj;
         a.nr_lab = (uint32_t)blab;

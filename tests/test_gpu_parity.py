@@ -298,6 +298,22 @@ def test_partition_small(kmp, name, k, eps, seed):
     _e2e(kmp, g, k, eps, seed, name)
 
 
+@pytest.mark.parametrize("name,k", [("rgg20000", 16), ("rand_w", 7)])
+def test_plain_loads_same_partition(kmp, name, k):
+    """The lane rating kernel's plain-load path (graphs of 2^29 or more entries) gives the
+    buffer-load path's partition, which is the oracle's."""
+    g = {"rgg20000": lambda: gen.rgg(20000, 8.0, 2),
+         "rand_w": lambda: gen.random_graph(5000, 5.0, 7, max_vw=4, max_ew=6)}[name]()
+    say(f"[plain_loads] {name} k={k}")
+    ref = oracle.partition(g, k, 0.03, 5)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    for plain in (False, True):
+        rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, 5, plain_loads=plain)
+        assert rc == ref.status
+        assert np.array_equal(part.cpu().numpy(), ref.part)
+        assert stats["cut"] == ref.stats["cut"]
+
+
 def test_partition_validation_errors(kmp):
     g = gen.grid(8, 8)
     bad = gen.Graph(g.xadj.copy(), g.adjncy.copy())
