@@ -374,8 +374,9 @@ class Ctx {
     // are recycled when the call ends.
     std::vector<std::pair<void*, size_t>> pinned_chunks_;
     size_t pinned_used_ = 0;
-    void* read_buf_ = nullptr;
+    void* read_buf_ = nullptr;  // pinned: a flag word, then the data of the last read-back
     size_t read_bytes_ = 0;
+    uint32_t read_seq_ = 0;
     int64_t* counters_ = nullptr;
     int64_t* spread_ = nullptr;
     void* stage(size_t bytes);

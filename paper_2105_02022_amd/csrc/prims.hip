@@ -1,5 +1,6 @@
 // Data-parallel building blocks: per-call context, prefix scans, stable LSD
 // radix sort (wave-ballot ranking, 64-wide wavefronts), fills, reductions.
+#include <chrono>
 #include <map>
 #include <mutex>
 
@@ -192,16 +193,40 @@ void* Ctx::stage(size_t bytes)
     return chunk;
 }
 
+namespace {
+// Small read-backs: one wavefront copies the bytes into the pinned read buffer,
+// makes them visible to the host (system-scope fence) and then sets the buffer's
+// flag word to `seq`; the host spins on the flag instead of synchronising the
+// stream (a kernel launch and a fence instead of a runtime copy and a wake-up).
+// Seeing the flag also means every earlier command of the stream has finished.
+__global__ __launch_bounds__(64) void k_readback(const char* __restrict__ src, char* __restrict__ dst,
+                                                 uint32_t bytes, uint32_t* flag, uint32_t seq)
+{
+    if ((((uintptr_t)src | (uintptr_t)dst | (uintptr_t)bytes) & 3u) == 0) {
+        const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+        uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+        for (uint32_t i = threadIdx.x; i < bytes / 4; i += 64) d[i] = s[i];
+    } else {
+        for (uint32_t i = threadIdx.x; i < bytes; i += 64) dst[i] = src[i];
+    }
+    __threadfence_system();
+    if (threadIdx.x == 0) __hip_atomic_store(flag, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+constexpr size_t kFlagBytes = 64;                 // the flag word's line at the start of the buffer
+constexpr size_t kFlagReadMax = 4096 - kFlagBytes;  // larger reads take the runtime copy
+}  // namespace
+
 void Ctx::read(void* host, const void* dev, size_t bytes)
 {
     if (!bytes) return;
-    if (read_bytes_ < bytes) {
+    if (read_bytes_ < bytes + kFlagBytes) {
         if (read_buf_) {
             std::lock_guard<std::mutex> lk(g_pinned_mu);
             g_pinned_free.emplace_back(read_buf_, read_bytes_);
         }
         read_buf_ = nullptr;
-        const size_t want = bytes < 4096 ? 4096 : bytes;
+        const size_t want = bytes + kFlagBytes < 4096 ? 4096 : bytes + kFlagBytes;
         {
             std::lock_guard<std::mutex> lk(g_pinned_mu);
             for (size_t i = 0; i < g_pinned_free.size(); ++i)
@@ -217,10 +242,36 @@ void Ctx::read(void* host, const void* dev, size_t bytes)
             KMP_HIP(hipHostMalloc(&read_buf_, want, hipHostMallocDefault));
             read_bytes_ = want;
         }
+        __atomic_store_n(static_cast<uint32_t*>(read_buf_), 0u, __ATOMIC_RELEASE);  // no stale flag value
     }
-    KMP_HIP(hipMemcpyAsync(read_buf_, dev, bytes, hipMemcpyDeviceToHost, stream));
-    KMP_HIP(hipStreamSynchronize(stream));
-    memcpy(host, read_buf_, bytes);
+    char* data = static_cast<char*>(read_buf_) + kFlagBytes;
+    if (bytes > kFlagReadMax) {
+        KMP_HIP(hipMemcpyAsync(data, dev, bytes, hipMemcpyDeviceToHost, stream));
+        KMP_HIP(hipStreamSynchronize(stream));
+        memcpy(host, data, bytes);
+        return;
+    }
+    uint32_t* flag = static_cast<uint32_t*>(read_buf_);
+    const uint32_t want = ++read_seq_ ? read_seq_ : ++read_seq_;  // never 0 (the cleared value)
+    hipLaunchKernelGGL(k_readback, dim3(1), dim3(64), 0, stream, static_cast<const char*>(dev), data,
+                       (uint32_t)bytes, flag, want);
+    KMP_LAUNCH_CHECK();
+    // spin for a short wait; a long one (or an error) falls back to the stream
+    // synchronisation, which also reports asynchronous errors
+    const auto t0 = std::chrono::steady_clock::now();
+    bool seen = false;
+    for (uint32_t i = 1;; ++i) {
+        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) == want) {
+            seen = true;
+            break;
+        }
+        if ((i & 1023u) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) break;
+    }
+    if (!seen) {
+        KMP_HIP(hipStreamSynchronize(stream));
+        if (__atomic_load_n(flag, __ATOMIC_ACQUIRE) != want) throw Error(KMP_EHIP, "read-back flag not set");
+    }
+    memcpy(host, data, bytes);
 }
 
 void Ctx::write(void* dev, const void* host, size_t bytes)
