@@ -693,12 +693,97 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
 
 }  // namespace
 
+// Small sorts in one workgroup: the pairs stay in LDS (two buffers) and every
+// 4-bit digit pass is a stable counting sort: thread t owns a contiguous chunk,
+// counts its digits into column t of a digit-major table, the table is scanned,
+// and each thread places its chunk in order.  Same result as the multi-pass
+// sort (a stable sort by key is unique).
+constexpr int kRsSmallMax = 8192;
+constexpr int kRsSmallThreads = kBlock;  // the block scan assumes kBlock threads
+
+__global__ __launch_bounds__(kRsSmallThreads) void k_rs_small(uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                           int32_t n, int key_bits)
+{
+    extern __shared__ __align__(16) uint32_t s_rs[];
+    uint32_t* bk[2] = {s_rs, s_rs + n};
+    uint32_t* bv[2] = {s_rs + 2 * n, s_rs + 3 * n};
+    uint32_t* cnt = s_rs + 4 * n;  // [16 digits][kRsSmallThreads]
+    __shared__ uint32_t s_w4[kRsSmallThreads / 64];
+    const int t = threadIdx.x;
+    for (int32_t i = t; i < n; i += kRsSmallThreads) {
+        bk[0][i] = keys[i];
+        bv[0][i] = vals[i];
+    }
+    const int32_t chunk = (n + kRsSmallThreads - 1) / kRsSmallThreads;
+    const int32_t lo = t * chunk < n ? t * chunk : n, hi = lo + chunk < n ? lo + chunk : n;
+    int cur = 0;
+    for (int shift = 0; shift < key_bits; shift += 4) {
+        __syncthreads();
+        uint32_t c16[16];
+#pragma unroll
+        for (int d = 0; d < 16; ++d) c16[d] = 0;
+        for (int32_t i = lo; i < hi; ++i) {
+            const uint32_t d = (bk[cur][i] >> shift) & 15u;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) c16[q] += d == (uint32_t)q;
+        }
+#pragma unroll
+        for (int d = 0; d < 16; ++d) cnt[d * kRsSmallThreads + t] = c16[d];
+        __syncthreads();
+        // exclusive scan of the 16 x kRsSmallThreads table in digit-major order:
+        // thread t sums entries [16 t, 16 t + 16), the totals are scanned, then
+        // each thread rewrites its 16 entries as starts
+        uint32_t run = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) run += cnt[16 * t + q];
+        uint32_t base = block_scan_incl<uint32_t, OpAdd>(run, OpAdd{}, s_w4, 0u) - run;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const uint32_t x = cnt[16 * t + q];
+            cnt[16 * t + q] = base;
+            base += x;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int d = 0; d < 16; ++d) c16[d] = cnt[d * kRsSmallThreads + t];
+        for (int32_t i = lo; i < hi; ++i) {
+            const uint32_t k = bk[cur][i], d = (k >> shift) & 15u;
+            uint32_t pos = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                pos = d == (uint32_t)q ? c16[q] : pos;
+                c16[q] += d == (uint32_t)q;
+            }
+            bk[cur ^ 1][pos] = k;
+            bv[cur ^ 1][pos] = bv[cur][i];
+        }
+        cur ^= 1;
+    }
+    __syncthreads();
+    for (int32_t i = t; i < n; i += kRsSmallThreads) {
+        keys[i] = bk[cur][i];
+        vals[i] = bv[cur][i];
+    }
+}
+
 void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
                       int key_bits, uint32_t** out_keys, uint32_t** out_vals)
 {
     if (out_keys) *out_keys = keys;
     if (out_vals) *out_vals = vals;
     if (n <= 1 || key_bits <= 0) return;
+    if (n <= kRsSmallMax) {
+        const size_t lds = sizeof(uint32_t) * (4 * (size_t)n + 16 * kRsSmallThreads);
+        static std::once_flag once;  // LDS beyond the 64 KiB default
+        std::call_once(once, [] {
+            (void)hipFuncSetAttribute((const void*)k_rs_small, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)(sizeof(uint32_t) * (4 * kRsSmallMax + 16 * kRsSmallThreads)));
+        });
+        hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(kRsSmallThreads), lds, c.stream, keys, vals, (int32_t)n,
+                           key_bits);
+        KMP_LAUNCH_CHECK();
+        return;
+    }
     const int nblk = (int)((n + RS_TILE - 1) / RS_TILE);
     DBuf<int32_t> hist(c, (size_t)nblk * 256);
     uint32_t *ks = keys, *vs = vals, *kd = keys_alt, *vd = vals_alt;
