@@ -130,6 +130,122 @@ __device__ inline void fence_wave()
     __builtin_amdgcn_wave_barrier();
 }
 
+// Key layouts of a growth: 64-bit as above, or 32-bit when the block has at
+// most 2048 nodes and every node's weighted degree is below 2^19 (a gain lies
+// within plus or minus the node's weighted degree): bit 31 frontier, bits
+// 30-11 gain + 2^19, bits 10-0 2047 - local id.  Both order candidates the
+// same way; 0 and 1 keep their meaning.
+struct Key64 {
+    using T = uint64_t;
+    static constexpr T front = kFront, unfit = kUnfit;
+    __device__ static T make(int32_t gain, uint32_t i) { return ggg_key(gain, i); }
+    __device__ static int32_t gain(T k) { return ggg_gain(k); }
+    __device__ static int32_t id(T k) { return ggg_id(k); }
+    __device__ static T wave_max(T v) { return wave_max_u64_split(v); }
+};
+struct Key32 {
+    using T = uint32_t;
+    static constexpr T front = 1u << 31, unfit = 1u;
+    __device__ static T make(int32_t gain, uint32_t i) { return ((uint32_t)(gain + (1 << 19)) << 11) | (2047u - i); }
+    __device__ static int32_t gain(T k) { return (int32_t)((k >> 11) & 0xFFFFFu) - (1 << 19); }
+    __device__ static int32_t id(T k) { return (int32_t)(2047u - (k & 2047u)); }
+    __device__ static T wave_max(T v) { return wave_max_u32_dpp(v); }
+};
+
+// One growth in one wavefront (seed j); lane 0 leaves the cut and the overload.
+template <class KT, bool LDS>
+__device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const int2* nd, const int2* ed, int j,
+                                int lane, uint32_t hj, int64_t cB, int64_t t0, int64_t cap0, int64_t cap1,
+                                int64_t* s_cut, int64_t* s_over)
+{
+    using T = typename KT::T;
+    T* key = reinterpret_cast<T*>(key_base) + (int64_t)j * nvp;
+    for (int32_t i = lane; i < nvp; i += 64) {
+        T k = 0;
+        if (i < nv) {
+            int32_t s = 0;
+            for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) s += ed[e].y;
+            k = KT::make(-s, (uint32_t)i);
+        }
+        key[i] = k;
+    }
+    fence_wave<LDS>();
+    int64_t w0 = 0;
+    const int32_t nchunks = nvp / 64;
+    while (w0 < t0) {
+        // the largest key: lane l reads nodes l, l + 64, ... (8 loads in flight)
+        T best = 0;
+        for (int32_t c0 = 0; c0 < nchunks; c0 += 8) {
+            T k[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) k[q] = c0 + q < nchunks ? key[(c0 + q) * 64 + lane] : 0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) best = k[q] > best ? k[q] : best;
+        }
+        // each lane fetches its own candidate's row and weight while the maximum is
+        // reduced; the winner (node i lives in lane i mod 64) hands them over
+        int2 ca = make_int2(0, 0), cb = make_int2(0, 0);
+        if (best >= KT::front) {
+            const int32_t ci = KT::id(best);
+            ca = nd[ci];
+            cb = nd[ci + 1];
+        }
+        best = KT::wave_max(best);
+        int32_t pick;
+        int32_t pw, pe0, pe1;
+        if (best >= KT::front) {
+            pick = KT::id(best);
+            const int src = pick & 63;
+            pw = __builtin_amdgcn_readlane(ca.y, src);
+            pe0 = __builtin_amdgcn_readlane(ca.x, src);
+            pe1 = __builtin_amdgcn_readlane(cb.x, src);
+        } else {
+            // no frontier node fits: the fitting unassigned node of smallest hash
+            uint64_t hb = ~0ull;  // (hash << 32) | id ; max = none
+            for (int32_t i = lane; i < nv; i += 64) {
+                if (key[i] == 0 || w0 + nd[i].y > cap0) continue;
+                const uint64_t k = ((uint64_t)hash_step(hj, (uint32_t)i, 6) << 32) | (uint32_t)i;
+                if (k < hb) hb = k;
+            }
+            hb = ~wave_max_u64_split(~hb);
+            if (hb == ~0ull) break;
+            pick = (int32_t)(hb & 0xFFFFFFFFu);
+            const int2 pa = nd[pick], pb = nd[pick + 1];
+            pw = pa.y;
+            pe0 = pa.x;
+            pe1 = pb.x;
+        }
+        if (w0 + pw > cap0) {
+            // a frontier node that does not fit: drop it for the rest of the growth
+            if (lane == 0) key[pick] = KT::unfit;
+            fence_wave<LDS>();
+            continue;
+        }
+        if (lane == 0) key[pick] = 0;
+        w0 += pw;
+        fence_wave<LDS>();
+        for (int32_t e = pe0 + lane; e < pe1; e += 64) {
+            const int2 uw = ed[e];
+            asm volatile("" ::"v"(uw.x), "v"(uw.y));  // one load for both halves
+            const T k = key[uw.x];
+            if (k > KT::unfit)
+                key[uw.x] = KT::front | KT::make((int32_t)((int64_t)KT::gain(k) + 2 * (int64_t)uw.y), (uint32_t)uw.x);
+        }
+        fence_wave<LDS>();
+    }
+    int64_t cut = 0;
+    for (int32_t i = lane; i < nv; i += 64) {
+        if (key[i] != 0) continue;
+        for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e)
+            if (key[ed[e].x] != 0) cut += ed[e].y;
+    }
+    for (int d = 32; d > 0; d >>= 1) cut += __shfl_xor(cut, d, 64);
+    if (lane == 0) {
+        s_cut[j] = cut;
+        s_over[j] = (w0 > cap0 ? w0 - cap0 : 0) + (cB - w0 > cap1 ? cB - w0 - cap1 : 0);
+    }
+}
+
 template <bool LDS>
 __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
 {
@@ -137,6 +253,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     __shared__ int64_t s_red[GGG_THREADS / 64];
     __shared__ int64_t s_cut[kSeeds], s_over[kSeeds];
     __shared__ int32_t s_best;
+    __shared__ int32_t s_wmax;
     __shared__ int32_t s_carry;
 
     const GGGJob job = a.jobs[blockIdx.x];
@@ -223,97 +340,31 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     }
     __syncthreads();
 
+    // ---- the key width: 32 bits when every gain fits (largest weighted degree)
+    if (tid == 0) s_wmax = 0;
+    __syncthreads();
+    {
+        int32_t m = 0;
+        for (int32_t i = tid; i < nv; i += GGG_THREADS) {
+            int32_t sum = 0;
+            for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) sum += ed[e].y;
+            m = sum > m ? sum : m;
+        }
+        if (m) atomicMax(&s_wmax, m);
+    }
+    __syncthreads();
+    const bool k32 = nv <= 2048 && s_wmax < (1 << 19);
+
     // ---- one growth per wavefront
     const int32_t f = job.f, f0 = f / 2, f1 = f - f0;
     const int64_t t0 = cB * f0 / f;
     const int64_t cap0 = (int64_t)f0 * job.lk, cap1 = (int64_t)f1 * job.lk;
     const int j = wv;
-    uint64_t* key = key_all + (int64_t)j * nvp;
     const uint32_t hj = hash_step(hash_step(hash_step(job.hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
-    for (int32_t i = lane; i < nvp; i += 64) {
-        uint64_t k = 0;
-        if (i < nv) {
-            int32_t s = 0;
-            for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) s += ed[e].y;
-            k = ggg_key(-s, (uint32_t)i);
-        }
-        key[i] = k;
-    }
-    fence_wave<LDS>();
-    int64_t w0 = 0;
-    const int32_t nchunks = nvp / 64;
-    while (w0 < t0) {
-        // the largest key: lane l reads nodes l, l + 64, ... (8 loads in flight)
-        uint64_t best = 0;
-        for (int32_t c0 = 0; c0 < nchunks; c0 += 8) {
-            uint64_t k[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) k[q] = c0 + q < nchunks ? key[(c0 + q) * 64 + lane] : 0;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) best = k[q] > best ? k[q] : best;
-        }
-        // each lane fetches its own candidate's row and weight while the maximum is
-        // reduced; the winner (node i lives in lane i mod 64) hands them over
-        int2 ca = make_int2(0, 0), cb = make_int2(0, 0);
-        if (best >= kFront) {
-            const int32_t ci = ggg_id(best);
-            ca = nd[ci];
-            cb = nd[ci + 1];
-        }
-        best = wave_max_u64_split(best);
-        int32_t pick;
-        int32_t pw, pe0, pe1;
-        if (best >= kFront) {
-            pick = ggg_id(best);
-            const int src = pick & 63;
-            pw = __builtin_amdgcn_readlane(ca.y, src);
-            pe0 = __builtin_amdgcn_readlane(ca.x, src);
-            pe1 = __builtin_amdgcn_readlane(cb.x, src);
-        } else {
-            // no frontier node fits: the fitting unassigned node of smallest hash
-            uint64_t hb = ~0ull;  // (hash << 32) | id ; max = none
-            for (int32_t i = lane; i < nv; i += 64) {
-                if (key[i] == 0 || w0 + nd[i].y > cap0) continue;
-                const uint64_t k = ((uint64_t)hash_step(hj, (uint32_t)i, 6) << 32) | (uint32_t)i;
-                if (k < hb) hb = k;
-            }
-            hb = ~wave_max_u64_split(~hb);
-            if (hb == ~0ull) break;
-            pick = (int32_t)(hb & 0xFFFFFFFFu);
-            const int2 pa = nd[pick], pb = nd[pick + 1];
-            pw = pa.y;
-            pe0 = pa.x;
-            pe1 = pb.x;
-        }
-        if (w0 + pw > cap0) {
-            // a frontier node that does not fit: drop it for the rest of the growth
-            if (lane == 0) key[pick] = kUnfit;
-            fence_wave<LDS>();
-            continue;
-        }
-        if (lane == 0) key[pick] = 0;
-        w0 += pw;
-        fence_wave<LDS>();
-        for (int32_t e = pe0 + lane; e < pe1; e += 64) {
-            const int2 uw = ed[e];
-            asm volatile("" ::"v"(uw.x), "v"(uw.y));  // one load for both halves
-            const uint64_t k = key[uw.x];
-            if (k > kUnfit)
-                key[uw.x] = kFront | ggg_key((int32_t)((int64_t)ggg_gain(k) + 2 * (int64_t)uw.y), (uint32_t)uw.x);
-        }
-        fence_wave<LDS>();
-    }
-    int64_t cut = 0;
-    for (int32_t i = lane; i < nv; i += 64) {
-        if (key[i] != 0) continue;
-        for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e)
-            if (key[ed[e].x] != 0) cut += ed[e].y;
-    }
-    for (int d = 32; d > 0; d >>= 1) cut += __shfl_xor(cut, d, 64);
-    if (lane == 0) {
-        s_cut[j] = cut;
-        s_over[j] = (w0 > cap0 ? w0 - cap0 : 0) + (cB - w0 > cap1 ? cB - w0 - cap1 : 0);
-    }
+    if (k32)
+        ggg_grow<Key32, LDS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over);
+    else
+        ggg_grow<Key64, LDS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over);
     __syncthreads();
     if (tid == 0) {
         int bj = 0;
@@ -328,8 +379,13 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
         s_best = bj;
     }
     __syncthreads();
-    const uint64_t* kb = key_all + (int64_t)s_best * nvp;
-    for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
+    if (k32) {
+        const uint32_t* kb = reinterpret_cast<const uint32_t*>(key_all) + (int64_t)s_best * nvp;
+        for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
+    } else {
+        const uint64_t* kb = key_all + (int64_t)s_best * nvp;
+        for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
+    }
 }
 
 __global__ void k_relabel(int32_t* __restrict__ part, const uint8_t* __restrict__ side,
