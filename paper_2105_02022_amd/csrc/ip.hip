@@ -557,11 +557,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             DBuf<GGGJob> jobs(c, lds_jobs.size());
             c.write(jobs.p, lds_jobs.data(), sizeof(GGGJob) * lds_jobs.size());
             a.jobs = jobs.p;
-            static std::once_flag once;  // LDS beyond the 64 KiB default
-            std::call_once(once, [] {
-                (void)hipFuncSetAttribute((const void*)k_ggg<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                          (int)kLdsBudget);
-            });
+            allow_lds((const void*)k_ggg<true>, (int)kLdsBudget);  // beyond the 64 KiB default
             ProfScope ps(c, KMP_PROF_GGG);
             hipLaunchKernelGGL(k_ggg<true>, dim3((unsigned)lds_jobs.size()), dim3(GGG_THREADS), (size_t)lds_max,
                                c.stream, a);

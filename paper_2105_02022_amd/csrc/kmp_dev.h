@@ -489,6 +489,10 @@ void fill_i64(Ctx& c, int64_t* p, int64_t v, int64_t n);
 inline void set_i64(Ctx& c, int64_t* p, int64_t v) { fill_i64(c, p, v, 1); }
 void iota_i32(Ctx& c, int32_t* p, int64_t n);
 // Sum of node / edge weights (int64; NULL weights count 1 each).
+// Allow `bytes` of dynamic LDS for kernel `fn` on the current device (once per
+// kernel and device; throws on failure).
+void allow_lds(const void* fn, int bytes);
+
 // Read several device int64 ranges (pointer, count) with one read-back, in order.
 constexpr int kMaxReadSegs = 4;
 void read_segments(Ctx& c, const std::vector<std::pair<const int64_t*, int32_t>>& segs, int64_t* host);

@@ -1765,11 +1765,7 @@ bool small_level(const Ctx& c, const DGraph& g, const LPSchedule& sched, int32_t
 template <bool EW, bool CAPV, bool LCSR>
 void launch_small(Ctx& c, unsigned jobs, size_t lds, const SmallLP& p)
 {
-    static std::once_flag once;  // LDS beyond the 64 KiB default, once per instantiation
-    std::call_once(once, [] {
-        (void)hipFuncSetAttribute((const void*)k_lp_small<EW, CAPV, LCSR>,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kSmallLdsBudget);
-    });
+    allow_lds((const void*)k_lp_small<EW, CAPV, LCSR>, (int)kSmallLdsBudget);  // beyond the 64 KiB default
     KMP_LAUNCH_TIMED(c, KMP_PROF_LP_SMALL, (k_lp_small<EW, CAPV, LCSR>), dim3(jobs), dim3(kSmallBlock), lds, p);
 }
 

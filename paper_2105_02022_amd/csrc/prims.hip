@@ -774,11 +774,8 @@ void radix_sort_pairs(Ctx& c, uint32_t* keys, uint32_t* vals, uint32_t* keys_alt
     if (n <= 1 || key_bits <= 0) return;
     if (n <= kRsSmallMax) {
         const size_t lds = sizeof(uint32_t) * (4 * (size_t)n + 16 * kRsSmallThreads);
-        static std::once_flag once;  // LDS beyond the 64 KiB default
-        std::call_once(once, [] {
-            (void)hipFuncSetAttribute((const void*)k_rs_small, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)(sizeof(uint32_t) * (4 * kRsSmallMax + 16 * kRsSmallThreads)));
-        });
+        // LDS beyond the 64 KiB default
+        allow_lds((const void*)k_rs_small, (int)(sizeof(uint32_t) * (4 * kRsSmallMax + 16 * kRsSmallThreads)));
         hipLaunchKernelGGL(k_rs_small, dim3(1), dim3(kRsSmallThreads), lds, c.stream, keys, vals, (int32_t)n,
                            key_bits);
         KMP_LAUNCH_CHECK();
@@ -951,6 +948,20 @@ void entries_and_max_degree(Ctx& c, const int32_t* xadj, int32_t n, int64_t& m, 
     c.read(h, out, sizeof(h));
     m = h[0];
     maxdeg = h[1];
+}
+
+// ---------------------------------------------------------------- kernel attributes
+void allow_lds(const void* fn, int bytes)
+{
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, int>> done;  // (kernel, device)
+    int dev = 0;
+    KMP_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(mu);
+    for (const auto& d : done)
+        if (d.first == fn && d.second == dev) return;
+    KMP_HIP(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    done.emplace_back(fn, dev);
 }
 
 // ---------------------------------------------------------------- packed read-back
