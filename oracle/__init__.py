@@ -83,7 +83,7 @@ def _load():
             "or_validate": (ctypes.c_int, [i32, P32, P32, P32, P32]),
             "or_partition_traced": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, dbl, u64, P32,
                                                    ctypes.POINTER(Stats), ctypes.c_int, TRACE_FN,
-                                                   ctypes.c_void_p]),
+                                                   ctypes.c_void_p, i32]),
             "or_step_lp_cluster": (i32, [i32, P32, P32, P32, P32, i32, i64, u64, P32, P64, PU32, P64]),
             "or_step_lp_generic": (i32, [i32, P32, P32, P32, P32, i32, u32, u64, P32, P64, i32, P64, i64,
                                          PU32, P64]),
@@ -91,12 +91,13 @@ def _load():
             "or_step_contract": (ctypes.c_int, [i32, P32, P32, P32, P32, P32, P32, P32, P64, P32, P32, P32,
                                                 P32]),
             "or_step_bipartition_round": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, P32, P32, P32, P32,
-                                                         i64, u64]),
-            "or_ggg": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64]),
+                                                         i64, u64, i32]),
+            "or_ggg": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, i32]),
+            "or_fm2_stall": (ctypes.c_int, [i32, P32, P32, P32, P32, PU8, i64, i64, i32, i32, P64]),
             "or_step_balance": (i32, [i32, P32, P32, P32, P32, i32, u64, P32, P64, i32, P64]),
             "or_step_cut": (i64, [i32, P32, P32, P32, P32]),
             "or_ggg_traced": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, P32,
-                                             P32, P32]),
+                                             P32, P32, i32]),
             "or_rg_cmp": (ctypes.c_int, [i64, i64, i64, i64]),
             "or_step_lp_subround": (i64, [i32, P32, P32, P32, P32, i32, i32, i32, u32, u64, P32, P64, i32, P64,
                                           i64, PU8, PU32, PU8]),
@@ -172,7 +173,7 @@ class Result:
 
 
 def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
-              validate_input: bool = True) -> Result:
+              validate_input: bool = True, fm_passes: int = 0) -> Result:
     lib = _load()
     xadj, adjncy = _i32(g.xadj), _i32(g.adjncy)
     vw = None if g.vwgt is None else _i32(g.vwgt)
@@ -188,7 +189,7 @@ def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
 
     cb = TRACE_FN(_cb) if trace else TRACE_FN()
     rc = lib.or_partition_traced(g.n, _p(xadj), _p(adjncy), _p(vw), _p(ew), k, eps, seed & (2**64 - 1),
-                                 _p(out), ctypes.byref(st), int(validate_input), cb, None)
+                                 _p(out), ctypes.byref(st), int(validate_input), cb, None, int(fm_passes))
     L = st.levels
     stats = dict(cut=st.cut, levels=L, level_n=list(st.level_n[:L + 1]), level_m=list(st.level_m[:L + 1]),
                  bipartitions=st.bipartitions, balance_rounds=st.balance_rounds,
@@ -255,7 +256,7 @@ def contract(g, label):
     return mp[:n], Graph(cx[:nc + 1].copy(), ca[:mc].copy(), cv[:nc].copy(), cw[:mc].copy(), "coarse")
 
 
-def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int):
+def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, fm_passes: int = 0):
     vw, ew = _weights(g)
     part = _i32(part).copy()
     nb = ctypes.c_int32(len(first))
@@ -265,16 +266,16 @@ def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int):
     fa[:len(first)] = first
     fc[:len(first)] = fcount
     rc = _load().or_step_bipartition_round(g.n, _p(_i32(g.xadj)), _p(_i32(g.adjncy)), _p(vw), _p(ew), level,
-                                           _p(part), ctypes.byref(nb), _p(fa), _p(fc), lk_, seed)
+                                           _p(part), ctypes.byref(nb), _p(fa), _p(fc), lk_, seed, int(fm_passes))
     if rc != 0:
         raise RuntimeError(f"oracle bipartition failed: {rc}")
     q = nb.value
     return part, fa[:q].copy(), fc[:q].copy()
 
 
-def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bool = False):
-    """O8 on a subgraph given in local ids; returns (side, cut) or
-    (side, cut, insertion order of the kept run, index j of the kept run)."""
+def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bool = False, fm_passes: int = 0):
+    """O8 (with O8b when fm_passes > 0) on a subgraph given in local ids; returns (side, cut) or
+    (side, cut, growth order of the kept run, index j of the kept run)."""
     vw, ew = _weights(sub)
     side = np.zeros(max(sub.n, 1), np.uint8)
     cut = ctypes.c_int64(0)
@@ -283,12 +284,30 @@ def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bo
     jbest = ctypes.c_int32(-1)
     rc = _load().or_ggg_traced(sub.n, _p(_i32(sub.xadj)), _p(_i32(sub.adjncy)), _p(ew), _p(vw), level, first, f,
                                lk_, seed, _p(side, PU8), ctypes.byref(cut), _p(order), ctypes.byref(norder),
-                               ctypes.byref(jbest))
+                               ctypes.byref(jbest), int(fm_passes))
     if rc != 0:
         raise RuntimeError(f"oracle ggg failed: {rc}")
     if with_order:
         return side[:sub.n], int(cut.value), order[:norder.value].copy(), int(jbest.value)
     return side[:sub.n], int(cut.value)
+
+
+FM_STALL = 64
+
+
+def fm2(sub, side, cap0: int, cap1: int, passes: int, stall: int = FM_STALL):
+    """O8b on a subgraph in local ids from the bipartition `side` (0/1);
+    returns (refined side, total cut decrease)."""
+    vw, ew = _weights(sub)
+    sd = np.ascontiguousarray(side, dtype=np.uint8).copy()
+    if sd.shape[0] == 0:
+        sd = np.zeros(1, np.uint8)
+    dec = ctypes.c_int64(0)
+    rc = _load().or_fm2_stall(sub.n, _p(_i32(sub.xadj)), _p(_i32(sub.adjncy)), _p(ew), _p(vw), _p(sd, PU8),
+                              cap0, cap1, passes, stall, ctypes.byref(dec))
+    if rc != 0:
+        raise RuntimeError(f"oracle fm2 failed: {rc}")
+    return sd[:sub.n], int(dec.value)
 
 
 def rg_cmp(d1: int, c1: int, d2: int, c2: int) -> int:

@@ -22,6 +22,7 @@
  *   O6  block table with final block counts f_B      (Sec. 4 "Handling General k")
  *   O7  bipartitionBlocks                            (Alg. 2)
  *   O8  greedy graph growing, R seeds, best cut      (Sec. 5.2, Alg. 2)
+ *   O8b 2-way FM refinement of each growth (optional) (Sec. 5.2 "Initial Bipartitioning")
  *   O9  k-way balancer by relative gain              (Sec. 5.3 "Balancing")
  *   O10 driver                                       (Alg. 1, Sec. 4)
  *   O11 edge cut                                     (Sec. 2 "Notation and Definitions")
@@ -40,6 +41,9 @@
 #define OR_ROUNDS 5       /* LP rounds, coarsening and refinement           */
 #define OR_S 4            /* sub-rounds per LP round                         */
 #define OR_R 8            /* GGG bipartitions per block                      */
+#define OR_FM_STALL 64    /* FM: a pass ends after this many moves in a row
+                             that do not improve its best prefix           */
+#define OR_FM_MAXPASS 16  /* FM: largest accepted pass count               */
 #define OR_PPM 1000000LL  /* epsilon fixed point                             */
 #define OR_MAXLEV 64      /* level guard                                     */
 #define OR_NONE 0xFFFFFFFFu
@@ -591,6 +595,97 @@ int or_contract(const or_graph* g, const int32_t* label, or_graph* cg, int32_t* 
     return rc;
 }
 
+/* ---------------- O8b: 2-way FM refinement -----------------------------
+ * Sec. 5.2 refines the initial bipartitions with 2-way FM (Fiduccia and
+ * Mattheyses).  Reading (the paper gives no further detail):
+ *  - gain(v) = weight of v's edges to the other side - weight to its own side
+ *    (the cut decrease if v alone changes side);
+ *  - a pass starts with every node unlocked and repeatedly moves the unlocked
+ *    node of largest gain among those whose move keeps the target side within
+ *    its cap (ties: smallest local id), locks it and updates the gains of its
+ *    unlocked neighbours;
+ *  - a pass ends when no unlocked node may move, or after `stall` moves in a
+ *    row that did not improve its best prefix; it then returns to the best
+ *    prefix: least overload, then largest total gain, then fewest moves;
+ *  - passes repeat until a pass keeps no move or `passes` have run.
+ * A move never lets its target side exceed its cap, so the overload never
+ * grows.  side[] (0/1) is updated in place; *decrease (may be NULL) receives
+ * the total cut decrease, which is negative only where the overload fell.  */
+int or_fm2_stall(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt,
+                 const int32_t* vwgt, uint8_t* side, int64_t cap0, int64_t cap1, int32_t passes, int32_t stall,
+                 int64_t* decrease)
+{
+    if (decrease) *decrease = 0;
+    if (nb <= 0 || passes <= 0) return OR_OK;
+    int64_t* gain = (int64_t*)malloc(sizeof(int64_t) * (size_t)nb);
+    int32_t* moved = (int32_t*)malloc(sizeof(int32_t) * (size_t)nb); /* move index, -1 = unlocked */
+    if (!gain || !moved) {
+        free(gain); free(moved);
+        return OR_ENOMEM;
+    }
+    const int64_t cap[2] = {cap0, cap1};
+    int64_t total = 0;
+    for (int32_t p = 0; p < passes; ++p) {
+        int64_t W[2] = {0, 0};
+        for (int32_t v = 0; v < nb; ++v) {
+            W[side[v]] += vwgt[v];
+            int64_t g = 0;
+            for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e)
+                g += side[adjncy[e]] != side[v] ? adjwgt[e] : -(int64_t)adjwgt[e];
+            gain[v] = g;
+            moved[v] = -1;
+        }
+#define OR_OVER(W) ((W[0] > cap[0] ? W[0] - cap[0] : 0) + (W[1] > cap[1] ? W[1] - cap[1] : 0))
+        int64_t G = 0, bestG = 0, bestOver = OR_OVER(W);
+        int32_t t = 0, bestT = 0, since = 0;
+        for (;;) {
+            int32_t pick = -1;
+            for (int32_t v = 0; v < nb; ++v) {
+                if (moved[v] >= 0) continue;
+                int to = 1 - side[v];
+                if (W[to] + vwgt[v] > cap[to]) continue;
+                if (pick < 0 || gain[v] > gain[pick]) pick = v; /* ascending scan: ties to smallest id */
+            }
+            if (pick < 0) break;
+            int from = side[pick], to = 1 - from;
+            side[pick] = (uint8_t)to;
+            W[from] -= vwgt[pick];
+            W[to] += vwgt[pick];
+            G += gain[pick];
+            moved[pick] = t++;
+            for (int32_t e = xadj[pick]; e < xadj[pick + 1]; ++e) {
+                int32_t u = adjncy[e];
+                if (moved[u] >= 0) continue;
+                /* u now shares pick's side: the edge left the cut; else it joined it */
+                gain[u] += side[u] == to ? -2 * (int64_t)adjwgt[e] : 2 * (int64_t)adjwgt[e];
+            }
+            int64_t over = OR_OVER(W);
+            if (over < bestOver || (over == bestOver && G > bestG)) {
+                bestOver = over;
+                bestG = G;
+                bestT = t;
+                since = 0;
+            } else if (++since >= stall) {
+                break;
+            }
+        }
+#undef OR_OVER
+        for (int32_t v = 0; v < nb; ++v)
+            if (moved[v] >= bestT) side[v] ^= 1; /* undo the moves after the best prefix */
+        total += bestG;
+        if (bestT == 0) break;
+    }
+    free(gain); free(moved);
+    if (decrease) *decrease = total;
+    return OR_OK;
+}
+
+int or_fm2(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt, const int32_t* vwgt,
+           uint8_t* side, int64_t cap0, int64_t cap1, int32_t passes, int64_t* decrease)
+{
+    return or_fm2_stall(nb, xadj, adjncy, adjwgt, vwgt, side, cap0, cap1, passes, OR_FM_STALL, decrease);
+}
+
 /* ---------------- O8: greedy graph growing ------------------------------
  * Sec. 5.2: the initial bipartitioner keeps the lowest cut of several runs of
  * simple algorithms with different seeds; greedy graph growing (GGG, from
@@ -603,8 +698,10 @@ int or_contract(const or_graph* g, const int32_t* label, or_graph* cg, int32_t* 
  * Input: subgraph in local ids. Output side[v] in {0,1}.                   */
 int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt,
                   const int32_t* vwgt, int32_t level, int32_t first, int32_t f, int64_t lk, uint64_t seed,
-                  uint8_t* side, int64_t* cut_out, int32_t* order_out, int32_t* norder_out, int32_t* jbest_out)
+                  uint8_t* side, int64_t* cut_out, int32_t* order_out, int32_t* norder_out, int32_t* jbest_out,
+                  int32_t fm_passes)
 {
+    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS) return OR_EINVAL;
     int32_t f0 = f / 2, f1 = f - f0;
     int64_t cB = 0;
     for (int32_t v = 0; v < nb; ++v) cB += vwgt[v];
@@ -612,10 +709,11 @@ int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const 
     int64_t cap0 = (int64_t)f0 * lk, cap1 = (int64_t)f1 * lk;
     int64_t* gain = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nb > 0 ? nb : 1));
     uint8_t* st = (uint8_t*)malloc((size_t)(nb > 0 ? nb : 1)); /* 0 free, 1 frontier, 2 in block 0 */
-    uint8_t* bestst = (uint8_t*)malloc((size_t)(nb > 0 ? nb : 1));
+    uint8_t* bestst = (uint8_t*)malloc((size_t)(nb > 0 ? nb : 1)); /* side of the kept run */
+    uint8_t* sj = (uint8_t*)malloc((size_t)(nb > 0 ? nb : 1));     /* side of run j */
     int32_t* ord = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nb > 0 ? nb : 1));
-    if (!gain || !st || !bestst || !ord) {
-        free(gain); free(st); free(bestst); free(ord);
+    if (!gain || !st || !bestst || !sj || !ord) {
+        free(gain); free(st); free(bestst); free(sj); free(ord);
         return OR_ENOMEM;
     }
     int have = 0;
@@ -660,11 +758,21 @@ int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const 
                 st[u] = 1;
             }
         }
+        for (int32_t v = 0; v < nb; ++v) sj[v] = st[v] == 2 ? 0 : 1;
+        if (fm_passes > 0) {
+            if (or_fm2(nb, xadj, adjncy, adjwgt, vwgt, sj, cap0, cap1, fm_passes, NULL) != OR_OK) {
+                free(gain); free(st); free(bestst); free(sj); free(ord);
+                return OR_ENOMEM;
+            }
+            w0 = 0;
+            for (int32_t v = 0; v < nb; ++v)
+                if (sj[v] == 0) w0 += vwgt[v];
+        }
         int64_t cut = 0;
         for (int32_t v = 0; v < nb; ++v) {
-            if (st[v] != 2) continue;
+            if (sj[v] != 0) continue;
             for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e)
-                if (st[adjncy[e]] != 2) cut += adjwgt[e];
+                if (sj[adjncy[e]] != 0) cut += adjwgt[e];
         }
         int64_t over = (w0 > cap0 ? w0 - cap0 : 0) + (cB - w0 > cap1 ? cB - w0 - cap1 : 0);
         /* lexicographic min of (over>0, over, cut, j): j ascending, so strict */
@@ -677,23 +785,24 @@ int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const 
             have = 1;
             bo = over;
             bc = cut;
-            memcpy(bestst, st, (size_t)nb);
+            memcpy(bestst, sj, (size_t)nb);
             if (order_out) memcpy(order_out, ord, sizeof(int32_t) * (size_t)nord);
             if (norder_out) *norder_out = nord;
             if (jbest_out) *jbest_out = j;
         }
     }
-    for (int32_t v = 0; v < nb; ++v) side[v] = bestst[v] == 2 ? 0 : 1;
+    memcpy(side, bestst, (size_t)nb);
     if (cut_out) *cut_out = bc;
-    free(gain); free(st); free(bestst); free(ord);
+    free(gain); free(st); free(bestst); free(sj); free(ord);
     return OR_OK;
 }
 
 int or_ggg(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt, const int32_t* vwgt,
-           int32_t level, int32_t first, int32_t f, int64_t lk, uint64_t seed, uint8_t* side, int64_t* cut_out)
+           int32_t level, int32_t first, int32_t f, int64_t lk, uint64_t seed, uint8_t* side, int64_t* cut_out,
+           int32_t fm_passes)
 {
     return or_ggg_traced(nb, xadj, adjncy, adjwgt, vwgt, level, first, f, lk, seed, side, cut_out, NULL, NULL,
-                         NULL);
+                         NULL, fm_passes);
 }
 
 /* ---------------- O6/O7: block table and bipartitionBlocks --------------
@@ -702,7 +811,7 @@ int or_ggg(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t
  * bipartitions every block (here: every block with f >= 2) once per call.
  * Blocks are kept sorted by 'first' (first final block id).               */
 int or_bipartition_round(const or_graph* g, int32_t level, int32_t* part, int32_t* nblocks, int32_t* first,
-                         int32_t* fcount, int64_t lk, uint64_t seed, int32_t* ncalls)
+                         int32_t* fcount, int64_t lk, uint64_t seed, int32_t* ncalls, int32_t fm_passes)
 {
     int32_t n = g->n, nb = *nblocks;
     int32_t* local = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
@@ -747,7 +856,7 @@ int or_bipartition_round(const or_graph* g, int32_t level, int32_t* part, int32_
             }
             sx[i + 1] = pos;
         }
-        int rc = or_ggg(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, NULL);
+        int rc = or_ggg(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, NULL, fm_passes);
         if (rc != OR_OK) return rc;
         if (ncalls) (*ncalls)++;
         for (int32_t i = 0; i < cnt; ++i) sidev[verts[bstart[b] + i]] = side[i];
@@ -967,10 +1076,11 @@ static void trace(or_trace_fn fn, void* user, int32_t phase, int32_t level, cons
 
 int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                         const int32_t* adjwgt, int32_t k, double eps, uint64_t seed, int32_t* out_part,
-                        or_stats* st, int validate, or_trace_fn tfn, void* tuser)
+                        or_stats* st, int validate, or_trace_fn tfn, void* tuser, int32_t fm_passes)
 {
     if (st) memset(st, 0, sizeof(*st));
     if (n < 0 || k < 1 || !(eps >= 0.0) || eps > 1000.0) return OR_EINVAL;
+    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS) return OR_EINVAL;
     if (n == 0) return OR_OK;
     if (!xadj || (xadj[n] > 0 && !adjncy) || !out_part) return OR_EINVAL;
     if (validate) {
@@ -1076,7 +1186,7 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
         if (kp < 2) kp = 2;
         while (nb < kp) {
             int32_t calls = 0;
-            rc = or_bipartition_round(g, l, part, &nb, first, fcount, lk, seed, &calls);
+            rc = or_bipartition_round(g, l, part, &nb, first, fcount, lk, seed, &calls, fm_passes);
             if (rc != OR_OK) return rc;
             if (st) st->bipartitions += calls;
         }
@@ -1116,7 +1226,7 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
 int or_partition(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
                  int32_t k, double eps, uint64_t seed, int32_t* out_part, or_stats* st)
 {
-    return or_partition_traced(n, xadj, adjncy, vwgt, adjwgt, k, eps, seed, out_part, st, 1, NULL, NULL);
+    return or_partition_traced(n, xadj, adjncy, vwgt, adjwgt, k, eps, seed, out_part, st, 1, NULL, NULL, 0);
 }
 
 /* ---------------- flat entry points for the tests ------------------------
@@ -1189,10 +1299,10 @@ int or_step_contract(int32_t n, const int32_t* xadj, const int32_t* adjncy, cons
 
 int or_step_bipartition_round(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                               const int32_t* adjwgt, int32_t level, int32_t* part, int32_t* nblocks,
-                              int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed)
+                              int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed, int32_t fm_passes)
 {
     or_graph g = view(n, xadj, adjncy, vwgt, adjwgt);
-    return or_bipartition_round(&g, level, part, nblocks, first, fcount, lk, seed, NULL);
+    return or_bipartition_round(&g, level, part, nblocks, first, fcount, lk, seed, NULL, fm_passes);
 }
 
 int32_t or_step_balance(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,

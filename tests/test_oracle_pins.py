@@ -344,6 +344,144 @@ def test_ggg_steps_follow_cut_gain(case):
     assert cu == cut_dense(A, (~inB0).astype(int))
 
 
+# ---------------------------------------------------------------- 2-way FM (Sec. 5.2 refinement)
+
+def _undirected(n, edges):
+    A = np.zeros((n, n), np.int64)
+    for u, v, w in edges:
+        A[u, v] = A[v, u] = w
+    return A
+
+
+def _overload(c, side, cap0, cap1):
+    w0 = int(c[side == 0].sum())
+    w1 = int(c[side == 1].sum())
+    return max(0, w0 - cap0) + max(0, w1 - cap1)
+
+
+def test_fm_two_triangles_worked_example():
+    """Two triangles {0,1,2} and {3,4,5} joined by the edge 2-3, started from
+    sides {0,1,3} | {2,4,5} (cut 5) with caps 4 | 4.  Gains: 2 and 3 gain 3,
+    the rest 0; node 2 moves (smaller id), which drops 3's gain to 1 and makes
+    side 0 full, so 3 moves next: cut 1 after two moves.  Every later prefix
+    is worse, so the pass keeps those two moves; the next pass keeps none."""
+    A = _undirected(6, [(0, 1, 1), (0, 2, 1), (1, 2, 1), (3, 4, 1), (3, 5, 1), (4, 5, 1), (2, 3, 1)])
+    g = _sub(A)
+    start = np.array([0, 0, 1, 0, 1, 1], np.uint8)
+    assert cut_dense(A, start) == 5
+    for passes in (1, 2, 16):
+        side, dec = oracle.fm2(g, start, 4, 4, passes)
+        assert side.tolist() == [0, 0, 0, 1, 1, 1]
+        assert dec == 4
+        assert cut_dense(A, side) == 1
+
+
+def test_fm_climbs_through_a_negative_move():
+    """Nodes 0 and 1 (side 0) are tied by weight 5 and each tied to side 1 by
+    weight 3; side 0 has no room.  Every single move loses or is infeasible at
+    first (0 or 1 alone: gain -2), yet moving both removes the whole cut: the
+    pass goes through the prefix of gain -2 and keeps the prefix of gain 6."""
+    A = _undirected(4, [(0, 1, 5), (0, 2, 3), (1, 3, 3), (2, 3, 1)])
+    g = _sub(A)
+    start = np.array([0, 0, 1, 1], np.uint8)
+    cap0, cap1 = 2, 4
+    c = np.ones(4, np.int64)
+    for v in range(4):  # no single feasible move improves the cut
+        t = start.copy()
+        t[v] ^= 1
+        if _overload(c, t, cap0, cap1) == 0:
+            assert cut_dense(A, t) >= cut_dense(A, start)
+    side, dec = oracle.fm2(g, start, cap0, cap1, 4)
+    assert side.tolist() == [1, 1, 1, 1]
+    assert dec == 6 and cut_dense(A, side) == 0
+
+
+@pytest.mark.parametrize("stall", [5, 64])
+def test_fm_stall_limit(stall):
+    """A path c_0..c_L on side 0 (full: cap0 = L + 1) with heavy nodes X - c_0
+    and Y - c_L on side 1 that never fit on side 0.  Walking the path costs
+    nothing (gain 0 per move, the smallest id first) and only the last node
+    gains 2, after L moves that do not improve the best prefix: the pass finds
+    it iff L < stall."""
+    for L, found in ((stall - 1, True), (stall, False)):
+        n = L + 3
+        X, Y = L + 1, L + 2
+        edges = [(i, i + 1, 1) for i in range(L)] + [(0, X, 1), (L, Y, 1)]
+        A = _undirected(n, edges)
+        vw = np.ones(n, np.int64)
+        vw[X] = vw[Y] = 1000
+        g = _sub(A, vw)
+        start = np.zeros(n, np.uint8)
+        start[X] = start[Y] = 1
+        side, dec = oracle.fm2(g, start, L + 1, 10**6, 1, stall=stall)
+        if found:
+            assert dec == 2 and (side == 1).all()
+        else:
+            assert dec == 0 and side.tolist() == start.tolist()
+
+
+@pytest.mark.parametrize("case", range(8))
+def test_fm_converged_is_one_move_optimal(case):
+    """Run to convergence: the cut decrease is what the sides show, the
+    overload never grows, and no single feasible move reduces the cut (else the
+    last pass would have kept at least that move)."""
+    rng = np.random.default_rng(900 + case)
+    n = 40
+    g = gen.random_graph(n, 4.0, 900 + case, max_vw=3 if case % 2 else 1, max_ew=4,
+                         isolated_frac=0.1 if case >= 4 else 0.0)
+    A = dense_adj(g)
+    c = node_w(g)
+    half = int(c.sum()) // 2
+    cap0, cap1 = half + case, int(c.sum()) - half + 2
+    start = rng.integers(0, 2, n).astype(np.uint8)
+    side, dec = oracle.fm2(g, start, cap0, cap1, 1000)
+    assert dec == cut_dense(A, start) - cut_dense(A, side)
+    o0, o1 = _overload(c, start, cap0, cap1), _overload(c, side, cap0, cap1)
+    assert o1 <= o0
+    if o0 == 0:
+        assert dec >= 0
+    base = cut_dense(A, side)
+    for v in range(n):
+        t = side.copy()
+        t[v] ^= 1
+        tgt = int(t[v])
+        wt = int(c[t == tgt].sum())
+        if wt <= (cap0 if tgt == 0 else cap1):
+            assert cut_dense(A, t) >= base, f"node {v} still improves"
+
+
+@pytest.mark.parametrize("case", range(6))
+def test_ggg_with_fm_refines_the_kept_growth(case):
+    """With FM the kept run is the growth of run j refined by FM under the
+    same caps, and its (overload, cut) is never worse than without FM."""
+    n = 36
+    g = gen.random_graph(n, 3.5, 500 + case, max_vw=3 if case % 2 else 1, max_ew=5,
+                         isolated_frac=0.1 if case >= 3 else 0.0)
+    A = dense_adj(g)
+    c = node_w(g)
+    f = 2 + case % 3
+    lk_ = int(c.sum()) // f + 2
+    f0, f1 = f // 2, f - f // 2
+    cap0, cap1 = f0 * lk_, f1 * lk_
+    level, first, seed = case, 3 * case, 70 + case
+    for passes in (1, 3):
+        side, cu, order, j = oracle.ggg(g, level, first, f, lk_, seed, with_order=True, fm_passes=passes)
+        grown = np.ones(n, np.uint8)
+        grown[order] = 0
+        ref, _ = oracle.fm2(g, grown, cap0, cap1, passes)
+        assert side.tolist() == ref.tolist()
+        assert cu == cut_dense(A, side)
+        ps, pc = oracle.ggg(g, level, first, f, lk_, seed)
+        assert (_overload(c, side, cap0, cap1), cu) <= (_overload(c, ps, cap0, cap1), pc)
+
+
+def test_fm_pass_count_bounds():
+    g = gen.random_graph(50, 3.0, 1)
+    assert oracle.partition(g, 2, fm_passes=17).status == -1
+    assert oracle.partition(g, 2, fm_passes=-1).status == -1
+    assert oracle.partition(g, 2, fm_passes=16).status in (0, 1)
+
+
 # ---------------------------------------------------------------- balance
 
 def test_relative_gain_order_is_exact():
