@@ -70,7 +70,13 @@ typedef struct kmp_options {
     int32_t plain_loads;    /* 1: the lane rating kernel gathers with plain loads instead of buffer loads
                                (used on graphs of 2^29 or more entries anyway); for tests.  The output
                                does not depend on it. */
-    int32_t reserved[2];
+    int32_t fm_passes;      /* 0..16: passes of 2-way FM refinement (paper Sec. 5.2) applied to each of
+                               the R greedy-growing bipartitions before the best one is kept; 0 = none
+                               (the default).  Moves the unlocked node of largest cut gain whose target
+                               side has room, locks it; a pass returns to its best prefix (least overload,
+                               then most gain) and ends when no node fits or after 64 moves without a
+                               better prefix.  Out of range: KMP_EINVAL.  The output depends on it. */
+    int32_t reserved[1];
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */
@@ -335,6 +341,18 @@ int kmp_contract(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt
 int kmp_bipartition_round(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                           const int32_t* adjwgt, int32_t n, int32_t level, int32_t* part, int32_t* nblocks,
                           int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed, void* stream);
+
+/*
+ * kmp_bipartition_round_ex: kmp_bipartition_round with fm_passes (0..16,
+ * else KMP_EINVAL) passes of 2-way FM refinement (paper Sec. 5.2) applied to
+ * each growth before the lowest (overload, cut) is kept; the FM rule is the
+ * one described at kmp_options.fm_passes.  fm_passes = 0 is
+ * kmp_bipartition_round.
+ */
+int kmp_bipartition_round_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
+                             const int32_t* adjwgt, int32_t n, int32_t level, int32_t* part, int32_t* nblocks,
+                             int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed, int32_t fm_passes,
+                             void* stream);
 
 /*
  * kmp_balance: k-way balancing by relative gain (paper Sec. 5.3

@@ -88,6 +88,7 @@ struct GGGArgs {
     const GGGJob* jobs;
     uint8_t* side;      // [n]
     char* scratch;      // global variant
+    int32_t fm_passes;  // 2-way FM passes after each growth (0: none)
 };
 
 // A growth keeps one 64-bit key per node, so that finding the next node is one
@@ -110,12 +111,15 @@ __device__ inline int32_t ggg_id(uint64_t k) { return (int32_t)(0x7FFFFFFFu - (u
 
 __host__ __device__ inline int64_t ggg_pad(int64_t nv) { return (nv + 63) & ~(int64_t)63; }
 
-__host__ __device__ inline int64_t ggg_bytes(int64_t nv, int64_t d)
+__host__ __device__ inline int64_t ggg_bytes(int64_t nv, int64_t d, bool fm)
 {
-    // keys (R x padded nv) u64, entries (d) and nodes (nv + 1) as int32 pairs
-    const int64_t bytes = 8 * ((int64_t)kSeeds * ggg_pad(nv) + d + nv + 1);
+    // keys (R x padded nv) u64, entries (d) and nodes (nv + 1) as int32 pairs;
+    // with FM also one int32 (side << 31 | node weight) per run and node
+    const int64_t bytes = 8 * ((int64_t)kSeeds * ggg_pad(nv) + d + nv + 1) + (fm ? 4 * (int64_t)kSeeds * ggg_pad(nv) : 0);
     return (bytes + 15) & ~(int64_t)15;
 }
+
+constexpr int kFmStall = 64;  // an FM pass ends after this many moves without a better prefix
 
 // Orders a wavefront's own earlier memory operations before its later ones.
 // LDS operations of a wavefront complete in issue order, so the LDS variant
@@ -152,11 +156,130 @@ struct Key32 {
     __device__ static T wave_max(T v) { return wave_max_u32_dpp(v); }
 };
 
+__device__ inline int64_t fm_over(int64_t w0, int64_t w1, int64_t cap0, int64_t cap1)
+{
+    return (w0 > cap0 ? w0 - cap0 : 0) + (w1 > cap1 ? w1 - cap1 : 0);
+}
+
+__device__ inline int32_t fm_room(int64_t d) { return d < 0 ? -1 : (d > INT32_MAX ? INT32_MAX : (int32_t)d); }
+
+// 2-way FM (Fiduccia-Mattheyses) on one growth's bipartition, in its own
+// wavefront.  sw[i] holds side << 31 | node weight.  In a pass, an unlocked
+// node's key is front | (gain, id) with gain = weight to the other side minus
+// weight to its own side; a moved node is locked with key 2 + its move index,
+// so the undo after the pass needs no log.  Each step moves the unlocked node
+// of largest key whose target side still has room for it; the pass ends when
+// none fits or after kFmStall moves without a better prefix (less overload,
+// else more total gain) and goes back to its best prefix.  Passes repeat
+// until one keeps no move.  w0 (side 0's weight) is updated.
+template <class KT, bool LDS>
+__device__ inline void ggg_fm(typename KT::T* key, int32_t* sw, int32_t nvp, int32_t nv, const int2* nd,
+                              const int2* ed, int lane, int64_t& w0, int64_t cB, int64_t cap0, int64_t cap1,
+                              int passes)
+{
+    using T = typename KT::T;
+    constexpr int32_t kSide = (int32_t)0x80000000u;
+    for (int32_t i = lane; i < nvp; i += 64) sw[i] = i < nv ? ((key[i] != 0 ? kSide : 0) | nd[i].y) : 0;
+    fence_wave<LDS>();
+    const int32_t nchunks = nvp / 64;
+    for (int p = 0; p < passes; ++p) {
+        for (int32_t i = lane; i < nvp; i += 64) {
+            T k = 0;
+            if (i < nv) {
+                const int32_t si = sw[i];
+                int32_t g = 0;
+                for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) {
+                    const int2 uw = ed[e];
+                    g += (sw[uw.x] ^ si) < 0 ? uw.y : -uw.y;
+                }
+                k = KT::front | KT::make(g, (uint32_t)i);
+            }
+            key[i] = k;
+        }
+        fence_wave<LDS>();
+        int64_t W0 = w0, W1 = cB - w0;
+        int64_t G = 0, bestG = 0, bestOver = fm_over(W0, W1, cap0, cap1), bestW0 = W0;
+        int32_t t = 0, bestT = 0, since = 0;
+        for (;;) {
+            // a side-0 node needs room on side 1 and the other way round
+            const int32_t r0 = fm_room(cap0 - W0), r1 = fm_room(cap1 - W1);
+            T best = 0;
+            for (int32_t c0 = 0; c0 < nchunks; c0 += 8) {
+                T k[8];
+                int32_t sv[8];
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const bool in = c0 + q < nchunks;
+                    k[q] = in ? key[(c0 + q) * 64 + lane] : 0;
+                    sv[q] = in ? sw[(c0 + q) * 64 + lane] : 0;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int32_t room = sv[q] < 0 ? r0 : r1;
+                    const T cand = k[q] >= KT::front && (sv[q] & 0x7FFFFFFF) <= room ? k[q] : 0;
+                    best = cand > best ? cand : best;
+                }
+            }
+            best = KT::wave_max(best);
+            if (best < KT::front) break;
+            const int32_t pick = KT::id(best);
+            const int32_t sp = sw[pick];
+            const int2 pa = nd[pick], pb = nd[pick + 1];
+            const int32_t spn = sp ^ kSide;  // pick's side after the move
+            const int64_t c = sp & 0x7FFFFFFF;
+            if (sp < 0) {
+                W1 -= c;
+                W0 += c;
+            } else {
+                W0 -= c;
+                W1 += c;
+            }
+            G += KT::gain(best);
+            fence_wave<LDS>();  // every lane has read sw[pick] before it changes
+            if (lane == 0) {
+                key[pick] = (T)(2 + t);
+                sw[pick] = spn;
+            }
+            ++t;
+            fence_wave<LDS>();
+            for (int32_t e = pa.x + lane; e < pb.x; e += 64) {
+                const int2 uw = ed[e];
+                asm volatile("" ::"v"(uw.x), "v"(uw.y));  // one load for both halves
+                const T k = key[uw.x];
+                if (k >= KT::front) {
+                    // a neighbour now on pick's side loses the edge from its gain, one across gains it
+                    const int32_t d = (sw[uw.x] ^ spn) >= 0 ? -2 * uw.y : 2 * uw.y;
+                    key[uw.x] = KT::front | KT::make(KT::gain(k) + d, (uint32_t)uw.x);
+                }
+            }
+            fence_wave<LDS>();
+            const int64_t ov = fm_over(W0, W1, cap0, cap1);
+            if (ov < bestOver || (ov == bestOver && G > bestG)) {
+                bestOver = ov;
+                bestG = G;
+                bestT = t;
+                bestW0 = W0;
+                since = 0;
+            } else if (++since >= kFmStall) {
+                break;
+            }
+        }
+        // undo the moves after the best prefix
+        for (int32_t i = lane; i < nv; i += 64) {
+            const T k = key[i];
+            if (k < KT::front && k >= (T)(2 + bestT)) sw[i] ^= kSide;
+        }
+        w0 = bestW0;
+        fence_wave<LDS>();
+        if (bestT == 0) break;
+    }
+}
+
 // One growth in one wavefront (seed j); lane 0 leaves the cut and the overload.
 template <class KT, bool LDS>
 __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const int2* nd, const int2* ed, int j,
                                 int lane, uint32_t hj, int64_t cB, int64_t t0, int64_t cap0, int64_t cap1,
-                                int64_t* s_cut, int64_t* s_over)
+                                int64_t* s_cut, int64_t* s_over, int32_t* sw_base, int fm_passes)
 {
     using T = typename KT::T;
     T* key = reinterpret_cast<T*>(key_base) + (int64_t)j * nvp;
@@ -234,10 +357,20 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
         fence_wave<LDS>();
     }
     int64_t cut = 0;
-    for (int32_t i = lane; i < nv; i += 64) {
-        if (key[i] != 0) continue;
-        for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e)
-            if (key[ed[e].x] != 0) cut += ed[e].y;
+    if (fm_passes > 0) {
+        int32_t* sw = sw_base + (int64_t)j * nvp;
+        ggg_fm<KT, LDS>(key, sw, nvp, nv, nd, ed, lane, w0, cB, cap0, cap1, fm_passes);
+        for (int32_t i = lane; i < nv; i += 64) {
+            if (sw[i] < 0) continue;
+            for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e)
+                if (sw[ed[e].x] < 0) cut += ed[e].y;
+        }
+    } else {
+        for (int32_t i = lane; i < nv; i += 64) {
+            if (key[i] != 0) continue;
+            for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e)
+                if (key[ed[e].x] != 0) cut += ed[e].y;
+        }
     }
     for (int d = 32; d > 0; d >>= 1) cut += __shfl_xor(cut, d, 64);
     if (lane == 0) {
@@ -266,6 +399,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     uint64_t* key_all = reinterpret_cast<uint64_t*>(base);
     int2* ed = reinterpret_cast<int2*>(key_all + (int64_t)kSeeds * nvp);
     int2* nd = ed + job.dsum;
+    int32_t* sw_all = reinterpret_cast<int32_t*>(nd + nv + 1);  // FM sides, R x padded nv
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
     // ---- internal degrees (in nd[i + 1].x) and node weights (a row's loads in groups of 8)
@@ -362,9 +496,11 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     const int j = wv;
     const uint32_t hj = hash_step(hash_step(hash_step(job.hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
     if (k32)
-        ggg_grow<Key32, LDS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over);
+        ggg_grow<Key32, LDS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over, sw_all,
+                             a.fm_passes);
     else
-        ggg_grow<Key64, LDS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over);
+        ggg_grow<Key64, LDS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over, sw_all,
+                             a.fm_passes);
     __syncthreads();
     if (tid == 0) {
         int bj = 0;
@@ -379,7 +515,10 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
         s_best = bj;
     }
     __syncthreads();
-    if (k32) {
+    if (a.fm_passes > 0) {
+        const int32_t* sb = sw_all + (int64_t)s_best * nvp;
+        for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = sb[i] < 0 ? 1 : 0;
+    } else if (k32) {
         const uint32_t* kb = reinterpret_cast<const uint32_t*>(key_all) + (int64_t)s_best * nvp;
         for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
     } else {
@@ -531,7 +670,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             jb.hpre = hash_step(hash_step(hseed[jb_job], TAG_GGG, 1), (uint32_t)level, 2);
             jb.scratch = 0;
             jb.lk = lk[jb_job];
-            const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum);
+            const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum, c.fm_passes > 0);
             if (bytes <= kLdsBudget) {
                 lds_jobs.push_back(jb);
                 if (bytes > lds_max) lds_max = bytes;
@@ -553,6 +692,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         a.local = local.p;
         a.side = side.p;
         a.scratch = nullptr;
+        a.fm_passes = c.fm_passes;
         if (!lds_jobs.empty()) {
             DBuf<GGGJob> jobs(c, lds_jobs.size());
             c.write(jobs.p, lds_jobs.data(), sizeof(GGGJob) * lds_jobs.size());

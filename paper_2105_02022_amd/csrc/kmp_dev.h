@@ -25,6 +25,7 @@ constexpr int kC = 160;              // contraction limit C (Alg. 1)
 constexpr int kRounds = 5;           // LP rounds (Sec. 5.1, Sec. 5.3)
 constexpr int kSub = 4;              // sub-rounds per LP round
 constexpr int kSeeds = 8;            // GGG runs per block (Alg. 2 "R bipartitions")
+constexpr int kFmMaxPasses = 16;     // largest accepted number of 2-way FM passes
 constexpr int64_t kPPM = 1000000;    // epsilon fixed point
 constexpr int kMaxLevels = 64;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
@@ -350,6 +351,7 @@ class Ctx {
     Prof* prof = nullptr;  // profiling enabled when non-null
     bool force_exact = false;    // LP: contended sub-rounds take the exact path
     bool plain_loads = false;    // lane rating: plain loads instead of buffer loads
+    int32_t fm_passes = 0;       // 2-way FM passes after every GGG growth
     int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0: tune's, < 0 never)
     Tuning tune;                 // the process-wide tuning when the call started
     int prof_begin(int cls);

@@ -1,0 +1,128 @@
+"""GPU parity of the 2-way FM refinement that can follow every greedy growth
+(paper Sec. 5.2): bipartition rounds and whole partitions through the C ABI
+against the CPU oracle with the same pass count, bit-exact."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_02022_amd import gen
+from tests.helpers import csr_from_dense, node_w, two_cliques
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kmp():
+    import paper_2105_02022_amd as k
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    k.library()  # raises if libkmp.so is missing: no fallback
+    return k
+
+
+def dev(g):
+    import paper_2105_02022_amd as k
+    return k.to_device(g, "cuda")
+
+
+def t32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.int32)).cuda()
+
+
+def _heavy_nodes(n, seed):
+    g = gen.random_graph(n, 4.0, seed)
+    g.vwgt = np.where(np.random.default_rng(seed + 1).random(n) < 0.12, 50, 1).astype(np.int32)
+    return g
+
+
+def _rounds(kmp, g, k, level, seed, passes, name):
+    lk = oracle.lk(int(node_w(g).sum()), k, 0.03)
+    part = np.zeros(g.n, np.int32)
+    first, fcount = [0], [k]
+    d_part = t32(part)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    while max(fcount) >= 2:
+        say(f"[fm bipartition] {name} k={k} passes={passes} blocks={len(first)}")
+        part, ef, efc = oracle.bipartition_round(g, level, part, first, fcount, lk, seed, fm_passes=passes)
+        rc, first, fcount = kmp.kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, level, d_part, first, fcount, lk,
+                                                      seed, fm_passes=passes)
+        assert rc == 0
+        assert first == list(ef) and fcount == list(efc)
+        assert np.array_equal(d_part.cpu().numpy(), part)
+
+
+@pytest.mark.parametrize("k,passes", [(2, 1), (2, 3), (16, 1), (16, 3), (5, 16)])
+def test_bipartition_round_fm(kmp, k, passes):
+    # k = 2: one block of 4000 nodes (global scratch, 64-bit keys); k = 16: down to LDS-sized blocks
+    _rounds(kmp, gen.rgg(4000, 8.0, 21), k, 0, 3, passes, "rgg4000")
+
+
+@pytest.mark.parametrize("name", ["weighted", "heavy", "heavy-lds-and-global", "big-edge-weights", "cliques",
+                                  "tiny", "isolated", "path"])
+def test_bipartition_fm_weighted_and_degenerate(kmp, name):
+    g, k = {
+        "weighted": lambda: (gen.random_graph(900, 5.0, 31, max_vw=20, max_ew=5), 7),
+        "heavy": lambda: (_heavy_nodes(300, 33), 4),
+        "heavy-lds-and-global": lambda: (_heavy_nodes(3000, 35), 6),
+        # weighted degrees beyond 2^19: the 64-bit keys inside LDS-sized blocks
+        "big-edge-weights": lambda: (gen.random_graph(400, 5.0, 36, max_ew=300000), 4),
+        "cliques": lambda: (csr_from_dense(two_cliques(40)), 2),
+        "tiny": lambda: (gen.grid(1, 3), 8),
+        "isolated": lambda: (gen.random_graph(500, 1.0, 32, isolated_frac=0.6), 4),
+        "path": lambda: (gen.grid(1, 300), 3),
+    }[name]()
+    _rounds(kmp, g, k, 2, 8, 2, name)
+
+
+@pytest.mark.parametrize("name,k,passes", [
+    ("grid128", 8, 2), ("rgg20000", 64, 2), ("rgg20000", 12, 5), ("rand_w", 7, 2), ("rand_iso", 16, 1),
+])
+def test_partition_fm(kmp, name, k, passes):
+    g = {
+        "grid128": lambda: gen.grid(128, 128),
+        "rgg20000": lambda: gen.rgg(20000, 8.0, 2),
+        "rand_w": lambda: gen.random_graph(5000, 5.0, 7, max_vw=4, max_ew=6),
+        "rand_iso": lambda: gen.random_graph(8000, 3.0, 8, isolated_frac=0.3),
+    }[name]()
+    say(f"[fm partition] {name} k={k} passes={passes}")
+    ref = oracle.partition(g, k, 0.03, 1, fm_passes=passes)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, 1, fm_passes=passes)
+    assert rc == ref.status
+    assert np.array_equal(part.cpu().numpy(), ref.part)
+    assert stats["cut"] == ref.stats["cut"]
+
+
+def test_batch_fm_equals_single_calls(kmp):
+    graphs = [(gen.grid(40, 40), 6), (gen.random_graph(3000, 5.0, 41, max_vw=3, max_ew=4), 9),
+              (gen.rgg(5000, 8.0, 42), 16)]
+    jobs = []
+    for i, (g, k) in enumerate(graphs):
+        xadj, adjncy, vwgt, adjwgt = dev(g)
+        jobs.append(dict(xadj=xadj, adjncy=adjncy, vwgt=vwgt, adjwgt=adjwgt, k=k, epsilon=0.03, seed=10 + i,
+                         out=torch.empty(g.n, dtype=torch.int32, device="cuda")))
+    say("[fm batch] 3 jobs passes=2")
+    rc, res, _ = kmp.kmp_partition_batch(jobs, fm_passes=2)
+    assert rc == 0
+    for i, (g, k) in enumerate(graphs):
+        ref = oracle.partition(g, k, 0.03, 10 + i, fm_passes=2)
+        assert res[i]["status"] == ref.status
+        assert np.array_equal(jobs[i]["out"].cpu().numpy(), ref.part)
+
+
+def test_fm_pass_count_rejected(kmp):
+    g = gen.grid(8, 8)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    for bad in (-1, 17):
+        rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, 4, 0.03, 1, fm_passes=bad)
+        assert rc == kmp.KMP_EINVAL
+        d_part = t32(np.zeros(g.n, np.int32))
+        rc, _, _ = kmp.kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, 0, d_part, [0], [4], 20, 1, fm_passes=bad)
+        assert rc == kmp.KMP_EINVAL
