@@ -28,8 +28,9 @@
  *   O11 edge cut                                     (Sec. 2 "Notation and Definitions")
  *
  * Parity status per function: see the table in the repository design notes;
- * every function here is pinned by a test except GGG solution quality, which
- * is a heuristic ("parity unpinned" for quality; its invariants are pinned).
+ * every function here is pinned by a test except the solution quality of GGG
+ * and of 2-way FM, which are heuristics ("parity unpinned" for quality; their
+ * invariants and worked examples are pinned).
  */
 #include <stdint.h>
 #include <stdlib.h>
