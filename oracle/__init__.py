@@ -29,7 +29,7 @@ S = 4
 R = 8
 PPM = 1_000_000
 NONE = 0xFFFFFFFF
-T_SUB, T_CL, T_REF, T_BAL, T_GGG = 1, 2, 3, 4, 5
+T_SUB, T_CL, T_REF, T_BAL, T_GGG, T_BFS, T_RND = 1, 2, 3, 4, 5, 6, 7
 
 OK, IMBALANCED, EINVAL, EGRAPH, EOVERFLOW, ENOMEM = 0, 1, -1, -2, -3, -4
 
@@ -83,7 +83,7 @@ def _load():
             "or_validate": (ctypes.c_int, [i32, P32, P32, P32, P32]),
             "or_partition_traced": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, dbl, u64, P32,
                                                    ctypes.POINTER(Stats), ctypes.c_int, TRACE_FN,
-                                                   ctypes.c_void_p, i32]),
+                                                   ctypes.c_void_p, i32, i32]),
             "or_step_lp_cluster": (i32, [i32, P32, P32, P32, P32, i32, i64, u64, P32, P64, PU32, P64]),
             "or_step_lp_generic": (i32, [i32, P32, P32, P32, P32, i32, u32, u64, P32, P64, i32, P64, i64,
                                          PU32, P64]),
@@ -91,13 +91,13 @@ def _load():
             "or_step_contract": (ctypes.c_int, [i32, P32, P32, P32, P32, P32, P32, P32, P64, P32, P32, P32,
                                                 P32]),
             "or_step_bipartition_round": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, P32, P32, P32, P32,
-                                                         i64, u64, i32]),
-            "or_ggg": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, i32]),
+                                                         i64, u64, i32, i32]),
+            "or_ggg": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, i32, i32]),
             "or_fm2_stall": (ctypes.c_int, [i32, P32, P32, P32, P32, PU8, i64, i64, i32, i32, P64]),
             "or_step_balance": (i32, [i32, P32, P32, P32, P32, i32, u64, P32, P64, i32, P64]),
             "or_step_cut": (i64, [i32, P32, P32, P32, P32]),
             "or_ggg_traced": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, P32,
-                                             P32, P32, i32]),
+                                             P32, P32, i32, i32]),
             "or_rg_cmp": (ctypes.c_int, [i64, i64, i64, i64]),
             "or_step_lp_subround": (i64, [i32, P32, P32, P32, P32, i32, i32, i32, u32, u64, P32, P64, i32, P64,
                                           i64, PU8, PU32, PU8]),
@@ -173,7 +173,7 @@ class Result:
 
 
 def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
-              validate_input: bool = True, fm_passes: int = 0) -> Result:
+              validate_input: bool = True, fm_passes: int = 0, pool: bool = False) -> Result:
     lib = _load()
     xadj, adjncy = _i32(g.xadj), _i32(g.adjncy)
     vw = None if g.vwgt is None else _i32(g.vwgt)
@@ -189,7 +189,7 @@ def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
 
     cb = TRACE_FN(_cb) if trace else TRACE_FN()
     rc = lib.or_partition_traced(g.n, _p(xadj), _p(adjncy), _p(vw), _p(ew), k, eps, seed & (2**64 - 1),
-                                 _p(out), ctypes.byref(st), int(validate_input), cb, None, int(fm_passes))
+                                 _p(out), ctypes.byref(st), int(validate_input), cb, None, int(fm_passes), int(pool))
     L = st.levels
     stats = dict(cut=st.cut, levels=L, level_n=list(st.level_n[:L + 1]), level_m=list(st.level_m[:L + 1]),
                  bipartitions=st.bipartitions, balance_rounds=st.balance_rounds,
@@ -256,7 +256,8 @@ def contract(g, label):
     return mp[:n], Graph(cx[:nc + 1].copy(), ca[:mc].copy(), cv[:nc].copy(), cw[:mc].copy(), "coarse")
 
 
-def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, fm_passes: int = 0):
+def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, fm_passes: int = 0,
+                      pool: bool = False):
     vw, ew = _weights(g)
     part = _i32(part).copy()
     nb = ctypes.c_int32(len(first))
@@ -266,16 +267,17 @@ def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, f
     fa[:len(first)] = first
     fc[:len(first)] = fcount
     rc = _load().or_step_bipartition_round(g.n, _p(_i32(g.xadj)), _p(_i32(g.adjncy)), _p(vw), _p(ew), level,
-                                           _p(part), ctypes.byref(nb), _p(fa), _p(fc), lk_, seed, int(fm_passes))
+                                           _p(part), ctypes.byref(nb), _p(fa), _p(fc), lk_, seed, int(fm_passes), int(pool))
     if rc != 0:
         raise RuntimeError(f"oracle bipartition failed: {rc}")
     q = nb.value
     return part, fa[:q].copy(), fc[:q].copy()
 
 
-def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bool = False, fm_passes: int = 0):
-    """O8 (with O8b when fm_passes > 0) on a subgraph given in local ids; returns (side, cut) or
-    (side, cut, growth order of the kept run, index j of the kept run)."""
+def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bool = False, fm_passes: int = 0,
+        pool: bool = False):
+    """O8 (with O8b when fm_passes > 0, O8c when pool) on a subgraph given in local ids; returns (side, cut)
+    or (side, cut, growth order of the kept run, index q = algorithm * R + j of the kept run)."""
     vw, ew = _weights(sub)
     side = np.zeros(max(sub.n, 1), np.uint8)
     cut = ctypes.c_int64(0)
@@ -284,7 +286,7 @@ def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bo
     jbest = ctypes.c_int32(-1)
     rc = _load().or_ggg_traced(sub.n, _p(_i32(sub.xadj)), _p(_i32(sub.adjncy)), _p(ew), _p(vw), level, first, f,
                                lk_, seed, _p(side, PU8), ctypes.byref(cut), _p(order), ctypes.byref(norder),
-                               ctypes.byref(jbest), int(fm_passes))
+                               ctypes.byref(jbest), int(fm_passes), int(pool))
     if rc != 0:
         raise RuntimeError(f"oracle ggg failed: {rc}")
     if with_order:

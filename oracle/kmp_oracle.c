@@ -23,6 +23,7 @@
  *   O7  bipartitionBlocks                            (Alg. 2)
  *   O8  greedy graph growing, R seeds, best cut      (Sec. 5.2, Alg. 2)
  *   O8b 2-way FM refinement of each growth (optional) (Sec. 5.2 "Initial Bipartitioning")
+ *   O8c pool: BFS and random runs beside GGG (optional) (Sec. 5.2 "Initial Bipartitioning")
  *   O9  k-way balancer by relative gain              (Sec. 5.3 "Balancing")
  *   O10 driver                                       (Alg. 1, Sec. 4)
  *   O11 edge cut                                     (Sec. 2 "Notation and Definitions")
@@ -49,7 +50,7 @@
 #define OR_MAXLEV 64      /* level guard                                     */
 #define OR_NONE 0xFFFFFFFFu
 #define OR_PHI 0x9E3779B9u
-enum { T_SUB = 1, T_CL = 2, T_REF = 3, T_BAL = 4, T_GGG = 5 };
+enum { T_SUB = 1, T_CL = 2, T_REF = 3, T_BAL = 4, T_GGG = 5, T_BFS = 6, T_RND = 7 };
 
 /* status codes */
 #define OR_OK 0
@@ -696,13 +697,22 @@ int or_fm2(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t
  * gain = (weight to block 0) - (weight to the rest); ties by smallest local
  * id; the seed and every restart take the unassigned fitting node with the
  * smallest hash H(seed; T_GGG, l, first, f, j, local id).
+ * O8c (pool = 1): Sec. 5.2 bipartitions the coarsest subgraph with a pool of
+ * simple algorithms, random bipartitioning, breadth-first search and GGG, each
+ * repeated with different seeds, and keeps the lowest cut.  Reading: every
+ * run grows block 0 to the same target under the same cap; a BFS run takes the
+ * discovered node of smallest discovery index that fits (neighbours are
+ * discovered in adjacency order when a node joins block 0; seed and restarts
+ * as in GGG, hashed with T_BFS); a random run takes the fitting node of
+ * smallest H(seed; T_RND, l, first, f, j, local id), ties by smallest id.  R
+ * runs of each; runs are compared in the order GGG, BFS, random, then j.
  * Input: subgraph in local ids. Output side[v] in {0,1}.                   */
 int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt,
                   const int32_t* vwgt, int32_t level, int32_t first, int32_t f, int64_t lk, uint64_t seed,
                   uint8_t* side, int64_t* cut_out, int32_t* order_out, int32_t* norder_out, int32_t* jbest_out,
-                  int32_t fm_passes)
+                  int32_t fm_passes, int32_t pool)
 {
-    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS) return OR_EINVAL;
+    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS || pool < 0 || pool > 1) return OR_EINVAL;
     int32_t f0 = f / 2, f1 = f - f0;
     int64_t cB = 0;
     for (int32_t v = 0; v < nb; ++v) cB += vwgt[v];
@@ -720,31 +730,48 @@ int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const 
     int have = 0;
     int32_t nord = 0;
     int64_t bo = 0, bc = 0;
-    for (int32_t j = 0; j < OR_R; ++j) {
+    /* runs in the order (algorithm, j): GGG, then with the pool BFS and random; the first of equal runs is kept */
+    static const int32_t tags[3] = {T_GGG, T_BFS, T_RND};
+    for (int32_t q = 0; q < (pool ? 3 : 1) * OR_R; ++q) {
+        const int32_t alg = q / OR_R, j = q % OR_R;
+        /* gain: GGG the cut gain; BFS minus the discovery index; random unused */
         for (int32_t v = 0; v < nb; ++v) {
             int64_t s = 0;
             for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e) s += adjwgt[e];
-            gain[v] = -s;
-            st[v] = 0;
+            gain[v] = alg == 0 ? -s : 0;
+            st[v] = alg == 2 ? 1 : 0; /* random: every node is a candidate from the start */
         }
-        int64_t w0 = 0;
+        int64_t w0 = 0, disc = 0;
         nord = 0;
         while (w0 < t0) {
             int32_t pick = -1;
-            for (int32_t v = 0; v < nb; ++v) {
-                if (st[v] != 1 || w0 + vwgt[v] > cap0) continue;
-                if (pick < 0 || gain[v] > gain[pick]) pick = v; /* ties: smallest id (ascending scan) */
-            }
-            if (pick < 0) {
-                uint32_t hp = 0;
+            uint32_t hp = 0;
+            if (alg == 2) {
+                /* random order: the smallest H(seed; T_RND, l, first, f, j, v), ties by smallest id */
                 for (int32_t v = 0; v < nb; ++v) {
-                    if (st[v] == 2 || w0 + vwgt[v] > cap0) continue;
-                    uint32_t a6[6] = {T_GGG, (uint32_t)level, (uint32_t)first, (uint32_t)f, (uint32_t)j,
-                                      (uint32_t)v};
+                    if (st[v] != 1 || w0 + vwgt[v] > cap0) continue;
+                    uint32_t a6[6] = {T_RND, (uint32_t)level, (uint32_t)first, (uint32_t)f, (uint32_t)j, (uint32_t)v};
                     uint32_t h = or_hash(seed, 6, a6);
                     if (pick < 0 || h < hp) {
                         pick = v;
                         hp = h;
+                    }
+                }
+            } else {
+                for (int32_t v = 0; v < nb; ++v) {
+                    if (st[v] != 1 || w0 + vwgt[v] > cap0) continue;
+                    if (pick < 0 || gain[v] > gain[pick]) pick = v; /* ties: smallest id (ascending scan) */
+                }
+                if (pick < 0) {
+                    for (int32_t v = 0; v < nb; ++v) {
+                        if (st[v] == 2 || w0 + vwgt[v] > cap0) continue;
+                        uint32_t a6[6] = {(uint32_t)tags[alg], (uint32_t)level, (uint32_t)first, (uint32_t)f,
+                                          (uint32_t)j, (uint32_t)v};
+                        uint32_t h = or_hash(seed, 6, a6);
+                        if (pick < 0 || h < hp) {
+                            pick = v;
+                            hp = h;
+                        }
                     }
                 }
             }
@@ -752,11 +779,17 @@ int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const 
             st[pick] = 2;
             ord[nord++] = pick;
             w0 += vwgt[pick];
+            if (alg == 2) continue;
             for (int32_t e = xadj[pick]; e < xadj[pick + 1]; ++e) {
                 int32_t u = adjncy[e];
                 if (st[u] == 2) continue;
-                gain[u] += 2 * (int64_t)adjwgt[e];
-                st[u] = 1;
+                if (alg == 0) {
+                    gain[u] += 2 * (int64_t)adjwgt[e];
+                    st[u] = 1;
+                } else if (st[u] == 0) { /* BFS: discovered in adjacency order */
+                    gain[u] = -(disc++);
+                    st[u] = 1;
+                }
             }
         }
         for (int32_t v = 0; v < nb; ++v) sj[v] = st[v] == 2 ? 0 : 1;
@@ -789,7 +822,7 @@ int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const 
             memcpy(bestst, sj, (size_t)nb);
             if (order_out) memcpy(order_out, ord, sizeof(int32_t) * (size_t)nord);
             if (norder_out) *norder_out = nord;
-            if (jbest_out) *jbest_out = j;
+            if (jbest_out) *jbest_out = q;
         }
     }
     memcpy(side, bestst, (size_t)nb);
@@ -800,10 +833,10 @@ int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const 
 
 int or_ggg(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt, const int32_t* vwgt,
            int32_t level, int32_t first, int32_t f, int64_t lk, uint64_t seed, uint8_t* side, int64_t* cut_out,
-           int32_t fm_passes)
+           int32_t fm_passes, int32_t pool)
 {
     return or_ggg_traced(nb, xadj, adjncy, adjwgt, vwgt, level, first, f, lk, seed, side, cut_out, NULL, NULL,
-                         NULL, fm_passes);
+                         NULL, fm_passes, pool);
 }
 
 /* ---------------- O6/O7: block table and bipartitionBlocks --------------
@@ -812,7 +845,8 @@ int or_ggg(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t
  * bipartitions every block (here: every block with f >= 2) once per call.
  * Blocks are kept sorted by 'first' (first final block id).               */
 int or_bipartition_round(const or_graph* g, int32_t level, int32_t* part, int32_t* nblocks, int32_t* first,
-                         int32_t* fcount, int64_t lk, uint64_t seed, int32_t* ncalls, int32_t fm_passes)
+                         int32_t* fcount, int64_t lk, uint64_t seed, int32_t* ncalls, int32_t fm_passes,
+                         int32_t pool)
 {
     int32_t n = g->n, nb = *nblocks;
     int32_t* local = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
@@ -857,7 +891,7 @@ int or_bipartition_round(const or_graph* g, int32_t level, int32_t* part, int32_
             }
             sx[i + 1] = pos;
         }
-        int rc = or_ggg(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, NULL, fm_passes);
+        int rc = or_ggg(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, NULL, fm_passes, pool);
         if (rc != OR_OK) return rc;
         if (ncalls) (*ncalls)++;
         for (int32_t i = 0; i < cnt; ++i) sidev[verts[bstart[b] + i]] = side[i];
@@ -1077,11 +1111,12 @@ static void trace(or_trace_fn fn, void* user, int32_t phase, int32_t level, cons
 
 int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                         const int32_t* adjwgt, int32_t k, double eps, uint64_t seed, int32_t* out_part,
-                        or_stats* st, int validate, or_trace_fn tfn, void* tuser, int32_t fm_passes)
+                        or_stats* st, int validate, or_trace_fn tfn, void* tuser, int32_t fm_passes,
+                        int32_t pool)
 {
     if (st) memset(st, 0, sizeof(*st));
     if (n < 0 || k < 1 || !(eps >= 0.0) || eps > 1000.0) return OR_EINVAL;
-    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS) return OR_EINVAL;
+    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS || pool < 0 || pool > 1) return OR_EINVAL;
     if (n == 0) return OR_OK;
     if (!xadj || (xadj[n] > 0 && !adjncy) || !out_part) return OR_EINVAL;
     if (validate) {
@@ -1187,7 +1222,7 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
         if (kp < 2) kp = 2;
         while (nb < kp) {
             int32_t calls = 0;
-            rc = or_bipartition_round(g, l, part, &nb, first, fcount, lk, seed, &calls, fm_passes);
+            rc = or_bipartition_round(g, l, part, &nb, first, fcount, lk, seed, &calls, fm_passes, pool);
             if (rc != OR_OK) return rc;
             if (st) st->bipartitions += calls;
         }
@@ -1227,7 +1262,7 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
 int or_partition(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
                  int32_t k, double eps, uint64_t seed, int32_t* out_part, or_stats* st)
 {
-    return or_partition_traced(n, xadj, adjncy, vwgt, adjwgt, k, eps, seed, out_part, st, 1, NULL, NULL, 0);
+    return or_partition_traced(n, xadj, adjncy, vwgt, adjwgt, k, eps, seed, out_part, st, 1, NULL, NULL, 0, 0);
 }
 
 /* ---------------- flat entry points for the tests ------------------------
@@ -1300,10 +1335,11 @@ int or_step_contract(int32_t n, const int32_t* xadj, const int32_t* adjncy, cons
 
 int or_step_bipartition_round(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                               const int32_t* adjwgt, int32_t level, int32_t* part, int32_t* nblocks,
-                              int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed, int32_t fm_passes)
+                              int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed, int32_t fm_passes,
+                              int32_t pool)
 {
     or_graph g = view(n, xadj, adjncy, vwgt, adjwgt);
-    return or_bipartition_round(&g, level, part, nblocks, first, fcount, lk, seed, NULL, fm_passes);
+    return or_bipartition_round(&g, level, part, nblocks, first, fcount, lk, seed, NULL, fm_passes, pool);
 }
 
 int32_t or_step_balance(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,

@@ -482,6 +482,132 @@ def test_fm_pass_count_bounds():
     assert oracle.partition(g, 2, fm_passes=16).status in (0, 1)
 
 
+# ---------------------------------------------------------------- IP pool (Sec. 5.2): BFS and random runs
+
+def _pool_restated(g, level, first, f, lk_, seed):
+    """Every run of the pool written out independently: GGG by dense cut gains,
+    BFS with a FIFO queue, random by sorting the hashes; returns the kept
+    (side, order, q) under the (overload > 0, overload, cut, q) order."""
+    from collections import deque
+    A = dense_adj(g)
+    c = node_w(g)
+    n = g.n
+    f0, f1 = f // 2, f - f // 2
+    cB = int(c.sum())
+    t0, cap0, cap1 = cB * f0 // f, f0 * lk_, f1 * lk_
+    best = None
+    for q in range(3 * oracle.R):
+        alg, j = divmod(q, oracle.R)
+        tag = (oracle.T_GGG, oracle.T_BFS, oracle.T_RND)[alg]
+        h = [oracle.hash_(seed, tag, level, first, f, j, v) for v in range(n)]
+        inB0 = np.zeros(n, bool)
+        order, w0 = [], 0
+
+        def fits(v):
+            return w0 + c[v] <= cap0
+
+        def restart():
+            cand = [v for v in range(n) if not inB0[v] and fits(v)]
+            return min(cand, key=lambda v: (h[v], v)) if cand else None
+
+        if alg == 2:
+            for v in sorted(range(n), key=lambda v: (h[v], v)):
+                if w0 >= t0:
+                    break
+                if fits(v):
+                    inB0[v] = True
+                    order.append(v)
+                    w0 += c[v]
+        elif alg == 1:
+            seen = np.zeros(n, bool)
+            queue = deque()
+            while w0 < t0:
+                while queue and not fits(queue[0]):
+                    queue.popleft()  # never fits again: block 0 only grows
+                if queue:
+                    v = queue.popleft()
+                else:
+                    v = restart()
+                    if v is None:
+                        break
+                    seen[v] = True
+                inB0[v] = True
+                order.append(v)
+                w0 += c[v]
+                for u in np.nonzero(A[v])[0]:
+                    if not seen[u] and not inB0[u]:
+                        seen[u] = True
+                        queue.append(int(u))
+        else:
+            while w0 < t0:
+                idx = np.nonzero(inB0)[0]
+                front = [u for u in range(n) if not inB0[u] and A[u, idx].sum() > 0 and fits(u)]
+                if front:
+                    gains = {u: int(A[u, idx].sum() - A[u, ~inB0].sum()) for u in front}
+                    v = max(front, key=lambda u: (gains[u], -u))
+                else:
+                    v = restart()
+                    if v is None:
+                        break
+                inB0[v] = True
+                order.append(v)
+                w0 += c[v]
+        side = (~inB0).astype(np.uint8)
+        over = max(0, w0 - cap0) + max(0, cB - w0 - cap1)
+        key = (over > 0, over, cut_dense(A, side), q)
+        if best is None or key < best[0]:
+            best = (key, side, order, q)
+    return best[1], best[2], best[3]
+
+
+# (graph seed, max node weight, f, tight caps, expected algorithm of the kept run): GGG, BFS
+# (heavy nodes) and random (tight caps: a random order packs side 0 with less overload) each win
+POOL_CASES = [(700, 1, 2, False, 0), (703, 3, 2, False, 0), (708, 9, 4, False, 1), (711, 9, 4, False, 1),
+              (713, 9, 3, False, 1), (1034, 30, 2, True, 2), (1058, 30, 2, True, 2), (1088, 30, 2, True, 2)]
+
+
+@pytest.mark.parametrize("gseed,mv,f,tight,alg", POOL_CASES)
+def test_pool_matches_restated_runs(gseed, mv, f, tight, alg):
+    if tight:
+        case = gseed - 1000
+        g = gen.random_graph(24, 3.0, gseed, max_vw=mv, max_ew=3)
+        lk_ = -(-int(node_w(g).sum()) // f)
+        level, first, seed = 1, 0, 40 + case
+    else:
+        case = gseed - 700
+        g = gen.random_graph(28, 3.0, gseed, max_vw=mv, max_ew=4, isolated_frac=0.15 if case % 2 else 0.0)
+        lk_ = int(node_w(g).sum()) // f + 1 + case % 2
+        level, first, seed = case + 1, 5 * case, 40 + case
+    side, cu, order, q = oracle.ggg(g, level, first, f, lk_, seed, with_order=True, pool=True)
+    rside, rorder, rq = _pool_restated(g, level, first, f, lk_, seed)
+    assert q // oracle.R == alg
+    assert q == rq
+    assert order.tolist() == rorder
+    assert side.tolist() == rside.tolist()
+    assert cu == cut_dense(dense_adj(g), side)
+
+
+def test_pool_bfs_on_a_path_is_contiguous_and_never_worse():
+    from tests.helpers import path
+    g = _sub(path(20))
+    for seed in range(6):
+        ps, pc = oracle.ggg(g, 0, 0, 2, 10**6, seed)
+        side, cu, order, q = oracle.ggg(g, 0, 0, 2, 10**6, seed, with_order=True, pool=True)
+        assert cu <= pc
+        if q // oracle.R == 1:  # a BFS run was kept: from its seed it walks the path outwards
+            idx = np.nonzero(side == 0)[0]
+            assert (np.diff(idx) == 1).all()
+    for case in range(5):
+        g = gen.random_graph(40, 3.5, 800 + case, max_vw=2, max_ew=3)
+        c = node_w(g)
+        lk_ = int(c.sum()) // 3 + 2
+        for fm in (0, 2):
+            ps, pc = oracle.ggg(g, 0, 0, 3, lk_, 9, fm_passes=fm)
+            qs, qc = oracle.ggg(g, 0, 0, 3, lk_, 9, fm_passes=fm, pool=True)
+            o = lambda s: _overload(c, s, lk_, 2 * lk_)
+            assert (o(qs), qc) <= (o(ps), pc)
+
+
 # ---------------------------------------------------------------- balance
 
 def test_relative_gain_order_is_exact():
