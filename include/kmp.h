@@ -76,7 +76,12 @@ typedef struct kmp_options {
                                side has room, locks it; a pass returns to its best prefix (least overload,
                                then most gain) and ends when no node fits or after 64 moves without a
                                better prefix.  Out of range: KMP_EINVAL.  The output depends on it. */
-    int32_t reserved[1];
+    int32_t ip_pool;        /* 1: the initial bipartitioning pool of paper Sec. 5.2: besides the R greedy
+                               growths, R breadth-first growths (discovery order; seed and restarts by
+                               hash) and R random growths (hash order), all to the same target under the
+                               same caps (and each refined when fm_passes > 0); the lowest (overload, cut)
+                               is kept, the first of equal runs in the order GGG, BFS, random.  0: GGG
+                               only (the default); other values: KMP_EINVAL.  The output depends on it. */
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */
@@ -345,14 +350,15 @@ int kmp_bipartition_round(const int32_t* xadj, const int32_t* adjncy, const int3
 /*
  * kmp_bipartition_round_ex: kmp_bipartition_round with fm_passes (0..16,
  * else KMP_EINVAL) passes of 2-way FM refinement (paper Sec. 5.2) applied to
- * each growth before the lowest (overload, cut) is kept; the FM rule is the
- * one described at kmp_options.fm_passes.  fm_passes = 0 is
+ * each growth before the lowest (overload, cut) is kept, and ip_pool (0 or 1,
+ * else KMP_EINVAL) adding the breadth-first and random growths of the paper's
+ * pool; both as described at kmp_options.  fm_passes = ip_pool = 0 is
  * kmp_bipartition_round.
  */
 int kmp_bipartition_round_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                              const int32_t* adjwgt, int32_t n, int32_t level, int32_t* part, int32_t* nblocks,
                              int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed, int32_t fm_passes,
-                             void* stream);
+                             int32_t ip_pool, void* stream);
 
 /*
  * kmp_balance: k-way balancing by relative gain (paper Sec. 5.3

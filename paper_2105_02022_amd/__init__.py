@@ -29,7 +29,7 @@ PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "
 class KmpOptions(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
                 ("force_exact", ctypes.c_int32), ("small_level_n", ctypes.c_int32), ("plain_loads", ctypes.c_int32),
-                ("fm_passes", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("fm_passes", ctypes.c_int32), ("ip_pool", ctypes.c_int32)]
 
 
 class KmpStats(ctypes.Structure):
@@ -107,7 +107,7 @@ SIGNATURES = {
     "kmp_bipartition_round": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _vp, _P32, _P32, _P32, _i64, _u64,
                                              _vp]),
     "kmp_bipartition_round_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _vp, _P32, _P32, _P32, _i64,
-                                                _u64, _i32, _vp]),
+                                                _u64, _i32, _i32, _vp]),
     "kmp_balance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _vp, _vp, _i32, _vp, _vp]),
     "kmp_lp_refine": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _vp, _vp, _i32, _vp, _P64, _vp]),
     "kmp_lp_subround": (_i64, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _u32, _u64, _vp, _vp, _i32, _vp, _i64,
@@ -218,12 +218,13 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
                      stream=None, validate: bool = False, profile: bool = False,
                      profile_classes=None, force_exact: bool = False,
                      small_level_n: int = 0, plain_loads: bool = False,
-                     fm_passes: int = 0) -> Tuple[int, "torch.Tensor", Dict]:
+                     fm_passes: int = 0, ip_pool: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
     (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path.
     `small_level_n`: largest level run by the one-workgroup LP (0 default, -1 never).
     `plain_loads`: the lane rating kernel gathers with plain loads (the buffer-load path is the default).
-    `fm_passes`: 2-way FM passes after every greedy growth (0..16; 0 = none)."""
+    `fm_passes`: 2-way FM passes after every greedy growth (0..16; 0 = none).
+    `ip_pool`: the initial bipartitioning also runs BFS and random growths."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -236,6 +237,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt.small_level_n = int(small_level_n)
     opt.plain_loads = int(plain_loads)
     opt.fm_passes = int(fm_passes)
+    opt.ip_pool = int(ip_pool)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -261,7 +263,7 @@ def _stats_dict(st: "KmpStats", profile: bool) -> Dict:
 def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool = False,
                         profile_classes=None, force_exact: bool = False,
                         small_level_n: int = 0, plain_loads: bool = False,
-                        fm_passes: int = 0) -> Tuple[int, List[Dict], Dict]:
+                        fm_passes: int = 0, ip_pool: bool = False) -> Tuple[int, List[Dict], Dict]:
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
@@ -276,6 +278,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     opt.small_level_n = int(small_level_n)
     opt.plain_loads = int(plain_loads)
     opt.fm_passes = int(fm_passes)
+    opt.ip_pool = int(ip_pool)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -404,20 +407,21 @@ def kmp_contract(xadj, adjncy, vwgt, adjwgt, label, stream=None):
 
 
 def kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, level: int, part, first: Sequence[int],
-                          fcount: Sequence[int], lk: int, seed: int, stream=None, fm_passes: int = 0):
-    """part updated in place; returns (status, first, fcount) as lists.  fm_passes > 0 calls
-    kmp_bipartition_round_ex (2-way FM after every growth)."""
+                          fcount: Sequence[int], lk: int, seed: int, stream=None, fm_passes: int = 0,
+                          ip_pool: int = 0):
+    """part updated in place; returns (status, first, fcount) as lists.  fm_passes or ip_pool
+    calls kmp_bipartition_round_ex (2-way FM after every growth; BFS and random growths)."""
     _check_i32(xadj, adjncy, vwgt, adjwgt, part)
     n = xadj.numel() - 1
     nb = len(first)
     fa = (ctypes.c_int32 * (2 * nb + 1))(*first)
     fc = (ctypes.c_int32 * (2 * nb + 1))(*fcount)
     nbl = ctypes.c_int32(nb)
-    if fm_passes:
+    if fm_passes or ip_pool:
         rc = library().kmp_bipartition_round_ex(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level,
                                                 _ptr(part), ctypes.byref(nbl), ctypes.cast(fa, _P32),
                                                 ctypes.cast(fc, _P32), lk, seed & (2**64 - 1), int(fm_passes),
-                                                _stream(stream))
+                                                int(ip_pool), _stream(stream))
     else:
         rc = library().kmp_bipartition_round(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level,
                                              _ptr(part), ctypes.byref(nbl), ctypes.cast(fa, _P32),

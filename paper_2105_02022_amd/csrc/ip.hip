@@ -72,6 +72,8 @@ struct GGGJob {
     int32_t b, first, f, nverts;
     int32_t dsum;      // sum of degrees of the block's nodes (bound on internal entries)
     uint32_t hpre;     // H prefix over (seed; T_GGG, level) of the block's job
+    uint32_t hpre_bfs; // the same over (seed; T_BFS, level) and (seed; T_RND, level)
+    uint32_t hpre_rnd;
     int64_t scratch;   // byte offset into the global scratch (global variant)
     int64_t lk;        // L_k of the block's job
 };
@@ -89,6 +91,7 @@ struct GGGArgs {
     uint8_t* side;      // [n]
     char* scratch;      // global variant
     int32_t fm_passes;  // 2-way FM passes after each growth (0: none)
+    int32_t pool;       // 1: BFS and random growths after the GGG ones
 };
 
 // A growth keeps one 64-bit key per node, so that finding the next node is one
@@ -275,23 +278,40 @@ __device__ inline void ggg_fm(typename KT::T* key, int32_t* sw, int32_t nvp, int
     }
 }
 
+// Growth algorithms of the initial-bipartitioning pool.  All three grow block
+// 0 to the same target under the same cap with the same key machinery and
+// differ in the key: GGG the cut gain, BFS minus the discovery index (a node
+// is discovered, in adjacency order, when a neighbour joins block 0), random
+// the inverted hash of the node (64-bit keys only).
+enum { ALG_GGG = 0, ALG_BFS = 1, ALG_RND = 2 };
+
 // One growth in one wavefront (seed j); lane 0 leaves the cut and the overload.
-template <class KT, bool LDS>
+template <class KT, bool LDS, int ALG>
 __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const int2* nd, const int2* ed, int j,
                                 int lane, uint32_t hj, int64_t cB, int64_t t0, int64_t cap0, int64_t cap1,
                                 int64_t* s_cut, int64_t* s_over, int32_t* sw_base, int fm_passes)
 {
     using T = typename KT::T;
+    static_assert(ALG != ALG_RND || sizeof(T) == 8, "random growth keys hold a 32-bit hash");
     T* key = reinterpret_cast<T*>(key_base) + (int64_t)j * nvp;
     for (int32_t i = lane; i < nvp; i += 64) {
         T k = 0;
         if (i < nv) {
-            int32_t s = 0;
-            for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) s += ed[e].y;
-            k = KT::make(-s, (uint32_t)i);
+            if constexpr (ALG == ALG_GGG) {
+                int32_t s = 0;
+                for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) s += ed[e].y;
+                k = KT::make(-s, (uint32_t)i);
+            } else if constexpr (ALG == ALG_BFS) {
+                k = KT::make(0, (uint32_t)i);  // undiscovered
+            } else {
+                // the gain field holds ~hash: the largest key is the smallest hash
+                const uint32_t h = hash_step(hj, (uint32_t)i, 6);
+                k = KT::front | KT::make((int32_t)(~h ^ 0x80000000u), (uint32_t)i);
+            }
         }
         key[i] = k;
     }
+    uint32_t disc = 0;  // BFS: nodes discovered so far
     fence_wave<LDS>();
     int64_t w0 = 0;
     const int32_t nchunks = nvp / 64;
@@ -347,12 +367,30 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
         if (lane == 0) key[pick] = 0;
         w0 += pw;
         fence_wave<LDS>();
-        for (int32_t e = pe0 + lane; e < pe1; e += 64) {
-            const int2 uw = ed[e];
-            asm volatile("" ::"v"(uw.x), "v"(uw.y));  // one load for both halves
-            const T k = key[uw.x];
-            if (k > KT::unfit)
-                key[uw.x] = KT::front | KT::make((int32_t)((int64_t)KT::gain(k) + 2 * (int64_t)uw.y), (uint32_t)uw.x);
+        if constexpr (ALG == ALG_GGG) {
+            for (int32_t e = pe0 + lane; e < pe1; e += 64) {
+                const int2 uw = ed[e];
+                asm volatile("" ::"v"(uw.x), "v"(uw.y));  // one load for both halves
+                const T k = key[uw.x];
+                if (k > KT::unfit)
+                    key[uw.x] =
+                        KT::front | KT::make((int32_t)((int64_t)KT::gain(k) + 2 * (int64_t)uw.y), (uint32_t)uw.x);
+            }
+        } else if constexpr (ALG == ALG_BFS) {
+            // undiscovered neighbours get the next discovery indices in adjacency order
+            for (int32_t e0 = pe0; e0 < pe1; e0 += 64) {
+                const int32_t e = e0 + lane;
+                const bool in = e < pe1;
+                const int32_t u = in ? ed[e].x : 0;
+                const T k = in ? key[u] : 0;
+                const bool nw = in && k > KT::unfit && k < KT::front;
+                const uint64_t m = __ballot(nw);
+                if (nw) {
+                    const uint32_t idx = disc + (uint32_t)__popcll(m & ((1ull << lane) - 1));
+                    key[u] = KT::front | KT::make(-(int32_t)idx, (uint32_t)u);
+                }
+                disc += (uint32_t)__popcll(m);
+            }
         }
         fence_wave<LDS>();
     }
@@ -386,6 +424,8 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     __shared__ int64_t s_red[GGG_THREADS / 64];
     __shared__ int64_t s_cut[kSeeds], s_over[kSeeds];
     __shared__ int32_t s_best;
+    __shared__ int64_t s_keep_over, s_keep_cut;  // the kept run so far
+    __shared__ bool s_take;
     __shared__ int32_t s_wmax;
     __shared__ int32_t s_carry;
 
@@ -494,36 +534,71 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     const int64_t t0 = cB * f0 / f;
     const int64_t cap0 = (int64_t)f0 * job.lk, cap1 = (int64_t)f1 * job.lk;
     const int j = wv;
-    const uint32_t hj = hash_step(hash_step(hash_step(job.hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
-    if (k32)
-        ggg_grow<Key32, LDS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over, sw_all,
-                             a.fm_passes);
-    else
-        ggg_grow<Key64, LDS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over, sw_all,
-                             a.fm_passes);
-    __syncthreads();
-    if (tid == 0) {
-        int bj = 0;
-        for (int q = 1; q < kSeeds; ++q) {
-            const bool fq = s_over[q] > 0, fb = s_over[bj] > 0;
-            bool better;
-            if (fq != fb) better = !fq;
-            else if (s_over[q] != s_over[bj]) better = s_over[q] < s_over[bj];
-            else better = s_cut[q] < s_cut[bj];
-            if (better) bj = q;
+    // phases: the R GGG growths, then (pool) R BFS and R random growths; a phase's best run
+    // replaces the kept one only if it is strictly better, so the first of equal runs is kept
+    const int nalg = a.pool ? 3 : 1;
+    for (int alg = 0; alg < nalg; ++alg) {
+        const uint32_t hpre = alg == ALG_GGG ? job.hpre : (alg == ALG_BFS ? job.hpre_bfs : job.hpre_rnd);
+        const uint32_t hj =
+            hash_step(hash_step(hash_step(hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
+        const bool use32 = k32 && alg != ALG_RND;
+        if (alg == ALG_GGG) {
+            if (use32)
+                ggg_grow<Key32, LDS, ALG_GGG>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut,
+                                              s_over, sw_all, a.fm_passes);
+            else
+                ggg_grow<Key64, LDS, ALG_GGG>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut,
+                                              s_over, sw_all, a.fm_passes);
+        } else if (alg == ALG_BFS) {
+            if (use32)
+                ggg_grow<Key32, LDS, ALG_BFS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut,
+                                              s_over, sw_all, a.fm_passes);
+            else
+                ggg_grow<Key64, LDS, ALG_BFS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut,
+                                              s_over, sw_all, a.fm_passes);
+        } else {
+            ggg_grow<Key64, LDS, ALG_RND>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over,
+                                          sw_all, a.fm_passes);
         }
-        s_best = bj;
-    }
-    __syncthreads();
-    if (a.fm_passes > 0) {
-        const int32_t* sb = sw_all + (int64_t)s_best * nvp;
-        for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = sb[i] < 0 ? 1 : 0;
-    } else if (k32) {
-        const uint32_t* kb = reinterpret_cast<const uint32_t*>(key_all) + (int64_t)s_best * nvp;
-        for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
-    } else {
-        const uint64_t* kb = key_all + (int64_t)s_best * nvp;
-        for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
+        __syncthreads();
+        if (tid == 0) {
+            int bj = 0;
+            for (int q = 1; q < kSeeds; ++q) {
+                const bool fq = s_over[q] > 0, fb = s_over[bj] > 0;
+                bool better;
+                if (fq != fb) better = !fq;
+                else if (s_over[q] != s_over[bj]) better = s_over[q] < s_over[bj];
+                else better = s_cut[q] < s_cut[bj];
+                if (better) bj = q;
+            }
+            bool take = alg == 0;
+            if (!take) {
+                const bool fq = s_over[bj] > 0, fb = s_keep_over > 0;
+                if (fq != fb) take = !fq;
+                else if (s_over[bj] != s_keep_over) take = s_over[bj] < s_keep_over;
+                else take = s_cut[bj] < s_keep_cut;
+            }
+            if (take) {
+                s_keep_over = s_over[bj];
+                s_keep_cut = s_cut[bj];
+            }
+            s_take = take;
+            s_best = bj;
+        }
+        __syncthreads();
+        if (s_take) {
+            if (a.fm_passes > 0) {
+                const int32_t* sb = sw_all + (int64_t)s_best * nvp;
+                for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = sb[i] < 0 ? 1 : 0;
+            } else if (use32) {
+                const uint32_t* kb = reinterpret_cast<const uint32_t*>(key_all) + (int64_t)s_best * nvp;
+                for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
+            } else {
+                const uint64_t* kb = key_all + (int64_t)s_best * nvp;
+                for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
+            }
+        }
+        __syncthreads();  // the next phase rewrites the keys
     }
 }
 
@@ -668,6 +743,8 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             jb.nverts = hb[bb + 1] - hb[bb];
             jb.dsum = hd[bb];
             jb.hpre = hash_step(hash_step(hseed[jb_job], TAG_GGG, 1), (uint32_t)level, 2);
+            jb.hpre_bfs = hash_step(hash_step(hseed[jb_job], TAG_BFS, 1), (uint32_t)level, 2);
+            jb.hpre_rnd = hash_step(hash_step(hseed[jb_job], TAG_RND, 1), (uint32_t)level, 2);
             jb.scratch = 0;
             jb.lk = lk[jb_job];
             const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum, c.fm_passes > 0);
@@ -693,6 +770,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         a.side = side.p;
         a.scratch = nullptr;
         a.fm_passes = c.fm_passes;
+        a.pool = c.ip_pool ? 1 : 0;
         if (!lds_jobs.empty()) {
             DBuf<GGGJob> jobs(c, lds_jobs.size());
             c.write(jobs.p, lds_jobs.data(), sizeof(GGGJob) * lds_jobs.size());

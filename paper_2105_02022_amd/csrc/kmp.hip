@@ -888,7 +888,9 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
     c.small_level_n = opt ? opt->small_level_n : 0;
     c.plain_loads = opt && opt->plain_loads;
     if (opt && (opt->fm_passes < 0 || opt->fm_passes > kFmMaxPasses)) return KMP_EINVAL;
+    if (opt && opt->ip_pool != 0 && opt->ip_pool != 1) return KMP_EINVAL;
     c.fm_passes = opt ? opt->fm_passes : 0;
+    c.ip_pool = opt && opt->ip_pool;
     std::vector<JobRun> jobs(1);
     JobRun& jb = jobs[0];
     jb.g = g0;
@@ -930,7 +932,9 @@ int partition_batch_impl(const kmp_graph_desc* gd, int32_t count, kmp_job_result
     c.small_level_n = opt ? opt->small_level_n : 0;
     c.plain_loads = opt && opt->plain_loads;
     if (opt && (opt->fm_passes < 0 || opt->fm_passes > kFmMaxPasses)) return KMP_EINVAL;
+    if (opt && opt->ip_pool != 0 && opt->ip_pool != 1) return KMP_EINVAL;
     c.fm_passes = opt ? opt->fm_passes : 0;
+    c.ip_pool = opt && opt->ip_pool;
     std::vector<JobRun> jobs(count);
     for (int32_t i = 0; i < count; ++i) {
         JobRun& jb = jobs[i];
@@ -1287,19 +1291,21 @@ int kmp_bipartition_round(const int32_t* xadj, const int32_t* adjncy, const int3
                           int64_t lk, uint64_t seed, void* stream)
 {
     return kmp_bipartition_round_ex(xadj, adjncy, vwgt, adjwgt, n, level, part, nblocks, first, fcount, lk, seed, 0,
-                                    stream);
+                                    0, stream);
 }
 
 int kmp_bipartition_round_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
                              int32_t n, int32_t level, int32_t* part, int32_t* nblocks, int32_t* first,
-                             int32_t* fcount, int64_t lk, uint64_t seed, int32_t fm_passes, void* stream)
+                             int32_t* fcount, int64_t lk, uint64_t seed, int32_t fm_passes, int32_t ip_pool,
+                             void* stream)
 {
     if (n < 0 || !nblocks || *nblocks < 1 || !first || !fcount || (n > 0 && (!xadj || !part))) return KMP_EINVAL;
-    if (fm_passes < 0 || fm_passes > kFmMaxPasses) return KMP_EINVAL;
+    if (fm_passes < 0 || fm_passes > kFmMaxPasses || (ip_pool != 0 && ip_pool != 1)) return KMP_EINVAL;
     return (int)guarded([&]() -> int64_t {
         init_pool_once();
         Ctx c((hipStream_t)stream);
         c.fm_passes = fm_passes;
+        c.ip_pool = ip_pool != 0;
         int32_t m32 = 0;
         if (n > 0) c.read(&m32, xadj + n, sizeof(int32_t));
         DGraph g = make_graph(xadj, adjncy, vwgt, adjwgt, n, m32);

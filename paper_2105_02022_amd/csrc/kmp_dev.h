@@ -30,7 +30,7 @@ constexpr int64_t kPPM = 1000000;    // epsilon fixed point
 constexpr int kMaxLevels = 64;
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kPhi = 0x9E3779B9u;
-enum : uint32_t { TAG_SUB = 1, TAG_CL = 2, TAG_REF = 3, TAG_BAL = 4, TAG_GGG = 5 };
+enum : uint32_t { TAG_SUB = 1, TAG_CL = 2, TAG_REF = 3, TAG_BAL = 4, TAG_GGG = 5, TAG_BFS = 6, TAG_RND = 7 };
 
 // ---------------------------------------------------------------- errors
 struct Error : std::runtime_error {
@@ -352,6 +352,7 @@ class Ctx {
     bool force_exact = false;    // LP: contended sub-rounds take the exact path
     bool plain_loads = false;    // lane rating: plain loads instead of buffer loads
     int32_t fm_passes = 0;       // 2-way FM passes after every GGG growth
+    bool ip_pool = false;        // initial bipartitioning also runs BFS and random growths
     int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0: tune's, < 0 never)
     Tuning tune;                 // the process-wide tuning when the call started
     int prof_begin(int cls);

@@ -1,6 +1,7 @@
-"""GPU parity of the 2-way FM refinement that can follow every greedy growth
-(paper Sec. 5.2): bipartition rounds and whole partitions through the C ABI
-against the CPU oracle with the same pass count, bit-exact."""
+"""GPU parity of the initial-bipartitioning options of paper Sec. 5.2: the
+2-way FM refinement that can follow every growth, and the pool of BFS and
+random growths beside GGG.  Bipartition rounds and whole partitions through
+the C ABI against the CPU oracle with the same options, bit-exact."""
 import sys
 
 import numpy as np
@@ -42,17 +43,18 @@ def _heavy_nodes(n, seed):
     return g
 
 
-def _rounds(kmp, g, k, level, seed, passes, name):
+def _rounds(kmp, g, k, level, seed, passes, name, pool=False):
     lk = oracle.lk(int(node_w(g).sum()), k, 0.03)
     part = np.zeros(g.n, np.int32)
     first, fcount = [0], [k]
     d_part = t32(part)
     xadj, adjncy, vwgt, adjwgt = dev(g)
     while max(fcount) >= 2:
-        say(f"[fm bipartition] {name} k={k} passes={passes} blocks={len(first)}")
-        part, ef, efc = oracle.bipartition_round(g, level, part, first, fcount, lk, seed, fm_passes=passes)
+        say(f"[ip bipartition] {name} k={k} passes={passes} pool={pool} blocks={len(first)}")
+        part, ef, efc = oracle.bipartition_round(g, level, part, first, fcount, lk, seed, fm_passes=passes,
+                                                 pool=pool)
         rc, first, fcount = kmp.kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, level, d_part, first, fcount, lk,
-                                                      seed, fm_passes=passes)
+                                                      seed, fm_passes=passes, ip_pool=int(pool))
         assert rc == 0
         assert first == list(ef) and fcount == list(efc)
         assert np.array_equal(d_part.cpu().numpy(), part)
@@ -126,3 +128,69 @@ def test_fm_pass_count_rejected(kmp):
         d_part = t32(np.zeros(g.n, np.int32))
         rc, _, _ = kmp.kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, 0, d_part, [0], [4], 20, 1, fm_passes=bad)
         assert rc == kmp.KMP_EINVAL
+
+
+# ------------------------------------------------------------------ pool: BFS and random growths
+
+@pytest.mark.parametrize("k,passes", [(2, 0), (16, 0), (16, 2), (5, 1)])
+def test_bipartition_round_pool(kmp, k, passes):
+    _rounds(kmp, gen.rgg(4000, 8.0, 21), k, 0, 3, passes, "rgg4000", pool=True)
+
+
+@pytest.mark.parametrize("name", ["weighted", "heavy-lds-and-global", "big-edge-weights", "heavy-30", "isolated",
+                                  "path"])
+def test_bipartition_pool_weighted_and_degenerate(kmp, name):
+    g, k = {
+        "weighted": lambda: (gen.random_graph(900, 5.0, 31, max_vw=20, max_ew=5), 7),
+        "heavy-lds-and-global": lambda: (_heavy_nodes(3000, 35), 6),
+        "big-edge-weights": lambda: (gen.random_graph(400, 5.0, 36, max_ew=300000), 4),
+        # node weights up to 30
+        "heavy-30": lambda: (gen.random_graph(600, 3.0, 37, max_vw=30, max_ew=3), 8),
+        "isolated": lambda: (gen.random_graph(500, 1.0, 32, isolated_frac=0.6), 4),
+        "path": lambda: (gen.grid(1, 300), 3),
+    }[name]()
+    for passes in (0, 2):
+        _rounds(kmp, g, k, 2, 8, passes, name, pool=True)
+
+
+@pytest.mark.parametrize("name,k,passes", [("grid128", 8, 0), ("rgg20000", 64, 0), ("rgg20000", 64, 2),
+                                           ("rand_w", 7, 1)])
+def test_partition_pool(kmp, name, k, passes):
+    g = {
+        "grid128": lambda: gen.grid(128, 128),
+        "rgg20000": lambda: gen.rgg(20000, 8.0, 2),
+        "rand_w": lambda: gen.random_graph(5000, 5.0, 7, max_vw=4, max_ew=6),
+    }[name]()
+    say(f"[pool partition] {name} k={k} passes={passes}")
+    ref = oracle.partition(g, k, 0.03, 1, fm_passes=passes, pool=True)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, 1, fm_passes=passes, ip_pool=True)
+    assert rc == ref.status
+    assert np.array_equal(part.cpu().numpy(), ref.part)
+    assert stats["cut"] == ref.stats["cut"]
+
+
+def test_batch_pool_equals_oracle(kmp):
+    graphs = [(gen.grid(40, 40), 6), (gen.random_graph(3000, 5.0, 41, max_vw=3, max_ew=4), 9)]
+    jobs = []
+    for i, (g, k) in enumerate(graphs):
+        xadj, adjncy, vwgt, adjwgt = dev(g)
+        jobs.append(dict(xadj=xadj, adjncy=adjncy, vwgt=vwgt, adjwgt=adjwgt, k=k, epsilon=0.03, seed=20 + i,
+                         out=torch.empty(g.n, dtype=torch.int32, device="cuda")))
+    say("[pool batch] 2 jobs passes=1")
+    rc, res, _ = kmp.kmp_partition_batch(jobs, fm_passes=1, ip_pool=True)
+    assert rc == 0
+    for i, (g, k) in enumerate(graphs):
+        ref = oracle.partition(g, k, 0.03, 20 + i, fm_passes=1, pool=True)
+        assert res[i]["status"] == ref.status
+        assert np.array_equal(jobs[i]["out"].cpu().numpy(), ref.part)
+
+
+def test_pool_flag_rejected(kmp):
+    g = gen.grid(8, 8)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, 4, 0.03, 1, ip_pool=2)
+    assert rc == kmp.KMP_EINVAL
+    d_part = t32(np.zeros(g.n, np.int32))
+    rc, _, _ = kmp.kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, 0, d_part, [0], [4], 20, 1, ip_pool=2)
+    assert rc == kmp.KMP_EINVAL
