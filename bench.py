@@ -19,10 +19,11 @@ from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, if present.
 
 cpu_baseline: the CPU oracle (single thread) on the same workload.
 
-fm: the same workload with 2-way FM refinement after every greedy growth
-(--fm-compare passes; the timed steps use --fm-passes, 0 by default): cut,
-time per partition without events, GGG class time, and the oracle's cut,
-time and parity for that pass count.
+ip_options: the same workload under the initial-bipartitioning options,
+2-way FM after every growth (--fm-compare passes), the BFS + random pool,
+and both (the timed steps use --fm-passes and --ip-pool, off by default):
+cut, time per partition without events, GGG class time, and the oracle's
+cut, time and parity for each.
 """
 import argparse
 import json
@@ -61,9 +62,12 @@ def parse():
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     ap.add_argument("--fm-passes", type=int, default=0,
                     help="2-way FM passes after every greedy growth in the timed steps (0: none, the default)")
-    ap.add_argument("--fm-compare", type=int, default=2,
-                    help="also run the workload with this many FM passes and report cut and time (0: skip)")
-    ap.add_argument("--fm-steps", type=int, default=5)
+    ap.add_argument("--ip-pool", action="store_true",
+                    help="BFS and random growths beside GGG in the timed steps (off by default)")
+    ap.add_argument("--fm-compare", type=int, default=2, help="FM passes of the compared configurations")
+    ap.add_argument("--ip-compare", type=int, default=1,
+                    help="1: also run the workload with FM, the pool and both and report cut and time; 0: skip")
+    ap.add_argument("--ip-steps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -234,12 +238,14 @@ def main():
     print(f"# graph n={g.n} m={g.m} maxdeg={g.maxdeg}; warmup {args.warmup}, steps {args.steps}",
           file=sys.stderr, flush=True)
     fm = args.fm_passes
+    pool = int(args.ip_pool)
     for _ in range(args.warmup):
-        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, fm_passes=fm)
+        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, fm_passes=fm,
+                                         ip_pool=pool)
         assert rc == 0, kmp.kmp_strerror(rc)
     # one untimed step with every kernel class timed: the per-class breakdown
     _, _, st_all = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True,
-                                        fm_passes=fm)
+                                        fm_passes=fm, ip_pool=pool)
     torch.cuda.synchronize()
     # the dominant kernel class: most event time among the classes that count algorithmic bytes
     dom = max((c for c in BYTE_CLASSES if st_all["prof"][c]["bytes"] > 0), key=lambda c: st_all["prof"][c]["ms"])
@@ -249,7 +255,7 @@ def main():
     t0 = time.perf_counter()
     for i in range(args.steps):
         rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True,
-                                         profile_classes=[dom], fm_passes=fm)
+                                         profile_classes=[dom], fm_passes=fm, ip_pool=pool)
         stats.append(st)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -258,39 +264,50 @@ def main():
     # context only (not `value`): the same steps with no launch stamped, to show what the events cost
     t1 = time.perf_counter()
     for i in range(args.steps):
-        rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, fm_passes=fm)
+        rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, fm_passes=fm,
+                                        ip_pool=pool)
     torch.cuda.synchronize()
     ms_plain = (time.perf_counter() - t1) * 1e3 / args.steps
     print(f"# the same {args.steps} steps without events: {ms_plain:.2f} ms/step", file=sys.stderr, flush=True)
     part = out.cpu().numpy()
     # the same workload with 2-way FM after every greedy growth (or without, if the timed steps had it):
     # cut, time per partition without events, and the GGG class time from one all-class profiled run
-    fm_cmp = None
-    cmp_passes = 0 if fm else args.fm_compare
-    if args.fm_compare:
+    # the same workload under the initial-bipartitioning options (2-way FM after every growth, the
+    # BFS + random pool, both): cut, time per partition without events, and the GGG class time from
+    # one all-class profiled run each; the timed configuration is listed with its own figures
+    ip_cmp = None
+    ip_parts = {}
+    if args.ip_compare:
+        configs = [(fm, pool)]
+        for c in ((args.fm_compare, 0), (0, 1), (args.fm_compare, 1)):
+            if c not in configs and (c[0] or c[1]):
+                configs.append(c)
+        ip_cmp = {"steps": args.ip_steps}
         out2 = torch.empty_like(out)
-        for _ in range(2):
-            kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2, fm_passes=cmp_passes)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        for _ in range(args.fm_steps):
-            rc2, _, st2 = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2,
-                                               fm_passes=cmp_passes)
-            assert rc2 == 0, kmp.kmp_strerror(rc2)
-        torch.cuda.synchronize()
-        ms2 = (time.perf_counter() - t2) * 1e3 / args.fm_steps
-        _, _, st2p = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2, profile=True,
-                                          fm_passes=cmp_passes)
-        runs = {fm: (st_all, ms_plain), cmp_passes: (st2, ms2)}
-        prof = {fm: st_all["prof"]["ggg"], cmp_passes: st2p["prof"]["ggg"]}
-        fm_cmp = {f"passes_{p}": {"cut": runs[p][0]["cut"], "ms_per_partition_without_events": round(runs[p][1], 3),
-                                  "ggg_ms_per_partition": round(prof[p]["ms"], 3),
-                                  "ggg_launches": prof[p]["launches"]}
-                  for p in sorted(runs)}
-        fm_cmp["compared_passes"] = max(fm, cmp_passes)
-        fm_cmp["steps"] = args.fm_steps
-        fm_part = (out if fm else out2).cpu().numpy()
-        print(f"# fm: {fm_cmp}", file=sys.stderr, flush=True)
+        for (p, q) in configs:
+            name = f"fm{p}_pool{q}"
+            if (p, q) == (fm, pool):
+                st_c, ms_c2, prof_c, part_c = st_all, ms_plain, st_all["prof"]["ggg"], part
+            else:
+                for _ in range(2):
+                    kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2, fm_passes=p, ip_pool=q)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                for _ in range(args.ip_steps):
+                    rc2, _, st_c = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2,
+                                                        fm_passes=p, ip_pool=q)
+                    assert rc2 == 0, kmp.kmp_strerror(rc2)
+                torch.cuda.synchronize()
+                ms_c2 = (time.perf_counter() - t2) * 1e3 / args.ip_steps
+                part_c = out2.cpu().numpy()
+                _, _, st_p = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2, profile=True,
+                                                  fm_passes=p, ip_pool=q)
+                prof_c = st_p["prof"]["ggg"]
+            ip_cmp[name] = {"fm_passes": p, "ip_pool": q, "cut": st_c["cut"],
+                            "ms_per_partition_without_events": round(ms_c2, 3),
+                            "ggg_ms_per_partition": round(prof_c["ms"], 3), "ggg_launches": prof_c["launches"]}
+            ip_parts[name] = part_c
+        print(f"# ip options: {ip_cmp}", file=sys.stderr, flush=True)
     # the timed steps ran at the default tuning, the one the committed rocprofv3 summaries were taken at;
     # then the autotuner picks launch choices (never changing the output) for this workload on this GPU,
     # reported with its own timings, and the batched and serving runs use its choice
@@ -337,7 +354,7 @@ def main():
         times = []
         while len(times) < args.cpu_runs or sum(times) < args.cpu_seconds:
             t = time.perf_counter()
-            ref = oracle.partition(g, k, eps, seed, validate_input=False, fm_passes=fm)
+            ref = oracle.partition(g, k, eps, seed, validate_input=False, fm_passes=fm, pool=bool(pool))
             times.append(time.perf_counter() - t)
             print(f"# oracle run {len(times) - 1}: {times[-1]:.2f} s", file=sys.stderr, flush=True)
         t_med = statistics.median(times)
@@ -346,14 +363,17 @@ def main():
                "sample": f"whole partition of the same workload (the same LP+contraction entries per "
                          f"partition), {len(times)} runs, {sum(times):.1f} s in total, median "
                          f"{t_med:.2f} s; single-threaded C oracle, -O2"}
-        if fm_cmp is not None:
-            p = fm_cmp["compared_passes"]
-            t = time.perf_counter()
-            ref_fm = oracle.partition(g, k, eps, seed, validate_input=False, fm_passes=p)
-            fm_cmp["oracle_s"] = round(time.perf_counter() - t, 2)
-            fm_cmp["oracle_cut"] = ref_fm.stats["cut"]
-            fm_cmp["parity_with_oracle"] = bool(np.array_equal(ref_fm.part, fm_part)) and \
-                ref_fm.stats["cut"] == fm_cmp[f"passes_{p}"]["cut"]
+        if ip_cmp is not None:
+            for name, row in ip_cmp.items():
+                if not isinstance(row, dict):
+                    continue
+                t = time.perf_counter()
+                ref_c = oracle.partition(g, k, eps, seed, validate_input=False, fm_passes=row["fm_passes"],
+                                         pool=bool(row["ip_pool"]))
+                row["oracle_s"] = round(time.perf_counter() - t, 2)
+                row["oracle_cut"] = ref_c.stats["cut"]
+                row["parity_with_oracle"] = bool(np.array_equal(ref_c.part, ip_parts[name])) and \
+                    ref_c.stats["cut"] == row["cut"]
     line = {
         "metric": METRIC, "value": round(value), "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 3), "higher_is_better": True, "scaling": "weak",
@@ -361,12 +381,13 @@ def main():
         "vs_baseline": None, "dtype": "int32", "data": "synthetic",
         "config": {"workload": "rgg20: 2D random geometric graph, n=2^20, avg degree 8, k=64, eps=0.03, seed 1",
                    "n": g.n, "m_directed": g.m, "k": k, "eps": eps, "seed": seed, "fm_passes": fm,
+                   "ip_pool": pool,
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
         "e2e_edges_per_s": round(g.m / (ms_step / 1e3)),
         "lp_plus_contraction_edges_per_step": edges, "cut": st0["cut"], "levels": st0["levels"],
         "parity_with_oracle": parity, "tuning": tuning, "batched": batched, "serving": serving,
-        "fm": fm_cmp,
+        "ip_options": ip_cmp,
     }
     print(json.dumps(line), flush=True)
 
