@@ -26,11 +26,12 @@ import numpy as np  # noqa: E402
 import oracle  # noqa: E402
 from paper_2105_02022_amd import gen  # noqa: E402
 
-# (file name, generator workload, k, eps, seed)
+# (file name, generator workload, k, eps, seed[, initial-bipartitioning options])
 CASES = {
     "grid128_k8": ("grid128", 8, 0.03, 1),
     "rgg20_k64": ("rgg20", 64, 0.03, 1),
     "rmat22_k32768": ("rmat22", 1 << 15, 0.03, 1),
+    "rgg20_k64_pool_fm2": ("rgg20", 64, 0.03, 1, {"fm_passes": 2, "ip_pool": 1}),
 }
 
 
@@ -49,16 +50,17 @@ def block_weights(part, vwgt, k):
 
 
 def make(name):
-    wl, k, eps, seed = CASES[name]
+    wl, k, eps, seed = CASES[name][:4]
+    opts = CASES[name][4] if len(CASES[name]) > 4 else {}
     t = time.time()
     g = gen.workload(wl)
     t_gen = time.time() - t
     t = time.time()
-    r = oracle.partition(g, k, eps, seed)
+    r = oracle.partition(g, k, eps, seed, fm_passes=opts.get("fm_passes", 0), pool=bool(opts.get("ip_pool", 0)))
     t_or = time.time() - t
     bw = block_weights(r.part, g.vwgt, k)
     out = {
-        "workload": wl, "k": k, "eps": eps, "seed": seed, "graph": graph_fingerprint(g),
+        "workload": wl, "k": k, "eps": eps, "seed": seed, "options": opts, "graph": graph_fingerprint(g),
         "status": r.status, "part_sha256": sha(np.asarray(r.part, np.int32)),
         "block_weights_sha256": sha(bw), "block_weight_max": int(bw.max()), "block_weight_min": int(bw.min()),
         "stats": {kk: (list(map(int, v)) if isinstance(v, list) else int(v)) for kk, v in r.stats.items()},

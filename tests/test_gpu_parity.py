@@ -441,7 +441,9 @@ def test_partition_golden(kmp, case):
     assert _sha(np.asarray(g.adjncy, np.int32)) == gx["adjncy_sha256"]
     k = exp["k"]
     say(f"[golden] {case}: n={g.n} m={g.m} k={k}")
-    rc, part, stats = kmp.partition(g, k, exp["eps"], exp["seed"])
+    opts = exp.get("options", {})
+    rc, part, stats = kmp.partition(g, k, exp["eps"], exp["seed"], fm_passes=opts.get("fm_passes", 0),
+                                    ip_pool=bool(opts.get("ip_pool", 0)))
     assert rc == exp["status"]
     bw = np.bincount(part, minlength=k).astype(np.int64)
     assert stats["cut"] == exp["stats"]["cut"]
