@@ -237,6 +237,16 @@ int kmp_server_wait(kmp_server* server, uint64_t job_id, kmp_job_result* result,
 int kmp_server_stats_get(kmp_server* server, kmp_server_stats* stats);
 void kmp_server_destroy(kmp_server* server);
 
+/*
+ * kmp_server_set_options: the initial-bipartitioning options (fm_passes,
+ * ip_pool; meaning and ranges as in kmp_options) for every batch that a worker
+ * forms after the call; the other fields of *opt are ignored.  opt == NULL
+ * restores the defaults.  Out-of-range values give KMP_EINVAL and change
+ * nothing.  Each job's output then equals kmp_partition_ex's with the same
+ * options for it alone.
+ */
+int kmp_server_set_options(kmp_server* server, const kmp_options* opt);
+
 /* ------------------------------------------------------------------------
  * Tuning.  Launch choices that change how the path runs on the device but
  * never its output (the partition depends only on graph, k, epsilon and seed).

@@ -95,6 +95,7 @@ SIGNATURES = {
                                        ctypes.POINTER(ctypes.c_double)]),
     "kmp_server_stats_get": (ctypes.c_int, [_vp, ctypes.POINTER(KmpServerStats)]),
     "kmp_server_destroy": (None, [_vp]),
+    "kmp_server_set_options": (ctypes.c_int, [_vp, ctypes.POINTER(KmpOptions)]),
     "kmp_set_tuning": (ctypes.c_int, [ctypes.POINTER(KmpTuning)]),
     "kmp_get_tuning": (ctypes.c_int, [ctypes.POINTER(KmpTuning)]),
     "kmp_autotune": (ctypes.c_int, [ctypes.POINTER(KmpGraphDesc), _i32, _vp, ctypes.POINTER(KmpTuning),
@@ -336,6 +337,13 @@ class Server:
         out = _result_dict(r)
         out["latency_ms"] = lat.value
         return out
+
+    def set_options(self, fm_passes: int = 0, ip_pool: bool = False) -> int:
+        """Initial-bipartitioning options for batches formed from now on (kmp_server_set_options)."""
+        o = KmpOptions()
+        o.fm_passes = int(fm_passes)
+        o.ip_pool = int(ip_pool)
+        return library().kmp_server_set_options(self._h, ctypes.byref(o))
 
     def poll(self, jid: int) -> Optional[Dict]:
         return self._take(library().kmp_server_poll, jid)

@@ -39,6 +39,7 @@ struct kmp_server {
     int running = 0;
     bool stop = false;
     kmp_server_stats st = {};
+    kmp_options opt = {};  // only fm_passes and ip_pool are used
 };
 
 namespace kmp {
@@ -62,6 +63,7 @@ void worker_main(kmp_server* s, int w)
     std::vector<uint64_t> ids;
     std::vector<kmp_graph_desc> descs;
     std::vector<kmp_job_result> res;
+    kmp_options opt = {};
     for (;;) {
         size_t reserved = 0;
         {
@@ -90,9 +92,10 @@ void worker_main(kmp_server* s, int w)
             ++s->running;
             descs.resize(ids.size());
             for (size_t i = 0; i < ids.size(); ++i) descs[i] = s->jobs[ids[i]].d;
+            opt = s->opt;
         }
         res.assign(ids.size(), kmp_job_result{});
-        const int rc = run_batch(descs.data(), (int32_t)ids.size(), res.data(), stream, nullptr, nullptr);
+        const int rc = run_batch(descs.data(), (int32_t)ids.size(), res.data(), stream, &opt, nullptr);
         const auto t_done = kmp_server::clk::now();
         {
             std::lock_guard<std::mutex> lk(s->mu);
@@ -158,6 +161,21 @@ kmp_server* kmp_server_create(size_t hbm_budget_bytes, int32_t workers)
         return nullptr;
     }
     return s;
+}
+
+int kmp_server_set_options(kmp_server* s, const kmp_options* opt)
+{
+    if (!s) return KMP_EINVAL;
+    kmp_options o = {};
+    if (opt) {
+        if (opt->fm_passes < 0 || opt->fm_passes > kmp::kFmMaxPasses || (opt->ip_pool != 0 && opt->ip_pool != 1))
+            return KMP_EINVAL;
+        o.fm_passes = opt->fm_passes;
+        o.ip_pool = opt->ip_pool;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->opt = o;
+    return KMP_OK;
 }
 
 int kmp_server_submit(kmp_server* s, const kmp_graph_desc* job, uint64_t* job_id)

@@ -2,6 +2,7 @@
 submitted over time from a separate thread; every result must equal the
 oracle's partition of that job alone (bit-exact), and the same job run alone
 through kmp_partition_ex must give the same output as in the mix."""
+import ctypes
 import sys
 import threading
 import time
@@ -122,3 +123,21 @@ def test_server_destroy_finishes_submitted_jobs(kmp):
     for j in jobs:
         ref = oracle.partition(j["g"], j["k"], j["epsilon"], j["seed"])
         assert np.array_equal(j["out"].cpu().numpy(), ref.part), j["name"]
+
+
+def test_server_with_ip_options_matches_oracle(kmp):
+    """kmp_server_set_options: served jobs get 2-way FM and the IP pool, as in the oracle."""
+    jobs = _device_jobs(kmp, small_serving_jobs(8, seed=11))
+    say(f"[server options] {len(jobs)} jobs, fm_passes=2, ip_pool=1")
+    with kmp.Server(8 << 30, workers=2) as srv:
+        o = kmp.KmpOptions()
+        o.fm_passes = 17
+        assert kmp.library().kmp_server_set_options(srv._h, ctypes.byref(o)) == kmp.KMP_EINVAL
+        assert srv.set_options(fm_passes=2, ip_pool=True) == kmp.KMP_OK
+        ids = [srv.submit(j) for j in jobs]
+        res = [srv.wait(i) for i in ids]
+    for j, r in zip(jobs, res):
+        ref = oracle.partition(j["g"], j["k"], j["epsilon"], j["seed"], fm_passes=2, pool=True)
+        assert r["status"] == ref.status, j["name"]
+        assert np.array_equal(j["out"].cpu().numpy(), ref.part), j["name"]
+        assert r["cut"] == ref.stats["cut"], j["name"]
