@@ -204,7 +204,7 @@ KERNEL_OF_CLASS = {"rate_t0": "k_rate_lane", "rate_hub": "k_rate_hub", "lp_small
 def traffic_from_profiles(family):
     """HBM bytes per launch of a kernel family from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
     summary (the JSON block at its end), or None if absent or taken on other kernel sources."""
-    from paper_2105_02022_amd.profsum import source_hash
+    from profsum import source_hash
     if family is None or not os.path.exists(TRAFFIC_SUMMARY):
         return None
     m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_SUMMARY).read(), re.S)

@@ -27,8 +27,14 @@
  *   - Sum of node weights and half the sum of edge weights must fit in int32.
  *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
  *     The library enqueues all work on it and synchronises it before return
- *     (the scheduler reads per-level scalars).  Workspace comes from the
- *     stream-ordered pool of the current device and is released before return.
+ *     (the scheduler reads per-level scalars).  Workspace comes from a
+ *     process-wide caching pool of device blocks on the current device: a
+ *     call takes blocks from it (allocating only when no cached block fits)
+ *     and hands them back when it returns, so after the first calls of a size
+ *     nothing is allocated; the cached blocks stay allocated until the
+ *     process ends.  The environment variable KMP_WORKSPACE_LIMIT (bytes,
+ *     read at the start of every call) caps the workspace one call may take;
+ *     a call that needs more fails with KMP_ENOMEM (for tests of that path).
  *   - Calls on different streams may run concurrently from different threads.
  *   - Return value: 0 = OK; 1 = KMP_IMBALANCED (output written, but some block
  *     exceeds L_k; possible only with non-unit node weights); negative codes
@@ -188,7 +194,10 @@ typedef struct kmp_job_result {
  * A job with invalid arguments gets its error code in results[i].status and
  * does not stop the others.  results may be NULL; opt / stats as for
  * kmp_partition_ex (stats: counters summed over the batch, cut = sum of cuts).
- * The call synchronises `stream` before returning.  Returns KMP_OK once every
+ * The call synchronises `stream` before returning (the scheduler reads
+ * per-level scalars of every job, so the batch is not asynchronous; callers
+ * that need asynchrony submit to the server below, whose worker threads run
+ * the batches).  Returns KMP_OK once every
  * job has its status, or a negative code for the call itself (count < 0,
  * graphs == NULL with count > 0, HIP errors, device memory exhausted).
  */
@@ -199,23 +208,33 @@ int kmp_partition_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_res
  * Serving loop with continuous batching (jobs arriving over time).
  *
  * kmp_server_create starts `workers` (1..16) host threads on the current
- * device, each with its own non-blocking HIP stream.  Submitted jobs wait in
- * arrival order; a free worker takes the longest run of waiting jobs from the
- * front whose estimated device footprint (160 B per node + 96 B per directed
- * entry + 1 MiB) fits in what is left of hbm_budget_bytes, and runs them as
- * one batch (as kmp_partition_batch).  A job larger than the whole budget runs
- * alone once nothing else is running.  Jobs that arrive while batches run are
+ * device, each with its own non-blocking HIP stream (the server owns its
+ * streams: it takes a worker count, not a caller stream, because batches
+ * overlap on the device only from streams of their own).  Submitted jobs wait
+ * in arrival order.  A free worker opens a batch with the oldest waiting job
+ * once its estimated device footprint (160 B per node + 96 B per directed
+ * entry + 1 MiB) fits in what is left of hbm_budget_bytes, or nothing else
+ * runs (a job larger than the whole budget then runs alone); it adds later
+ * waiting jobs of the same size class (n + m within a factor of four) and the
+ * same options whose footprints still fit, up to 256, and runs them as one
+ * batch (as kmp_partition_batch).  Jobs that arrive while batches run are
  * admitted by the next free worker, so their work overlaps on the device.
- * Each job's output equals kmp_partition's for it alone.  Returns NULL on
- * invalid arguments or when no stream / thread can be created.
+ * The footprint is an estimate used for admission; the memory itself comes
+ * from the caching pool described above.  Each job's output equals
+ * kmp_partition_ex's for it alone with the options current at its
+ * submission.  Returns NULL on invalid arguments or when no stream / thread
+ * can be created.
  *
  * kmp_server_submit copies the descriptor and returns at once with a job id;
  * the job's device arrays must stay valid and untouched until its result has
- * been taken.  kmp_server_poll returns 0 while the job is pending and 1 once
- * it is done, filling `result` and `latency_ms` (completion minus submission,
- * host steady clock; both may be NULL) and forgetting the job;
- * kmp_server_wait blocks until then.  Unknown ids give KMP_EINVAL.
- * kmp_server_destroy finishes every submitted job, then stops the workers.
+ * been taken.  kmp_server_poll (non-blocking) returns 0 while the job is
+ * pending and 1 once it is done, filling `result` (the job's status, cut,
+ * levels; the status is inside `result`, not a separate int) and
+ * `latency_ms` (completion minus submission, host steady clock; both may be
+ * NULL) and forgetting the job; kmp_server_wait blocks until then.  Unknown
+ * ids, and ids whose result another thread has taken meanwhile, give
+ * KMP_EINVAL.  kmp_server_destroy finishes every submitted job, then stops
+ * the workers.
  */
 typedef struct kmp_server kmp_server;
 
@@ -239,11 +258,12 @@ void kmp_server_destroy(kmp_server* server);
 
 /*
  * kmp_server_set_options: the initial-bipartitioning options (fm_passes,
- * ip_pool; meaning and ranges as in kmp_options) for every batch that a worker
- * forms after the call; the other fields of *opt are ignored.  opt == NULL
- * restores the defaults.  Out-of-range values give KMP_EINVAL and change
- * nothing.  Each job's output then equals kmp_partition_ex's with the same
- * options for it alone.
+ * ip_pool; meaning and ranges as in kmp_options) for every job submitted
+ * after the call (a job keeps the options current at its submission; only
+ * jobs with equal options share a batch); the other fields of *opt are
+ * ignored.  opt == NULL restores the defaults.  Out-of-range values give
+ * KMP_EINVAL and change nothing.  Each job's output then equals
+ * kmp_partition_ex's with its options for it alone.
  */
 int kmp_server_set_options(kmp_server* server, const kmp_options* opt);
 

@@ -251,8 +251,10 @@ __device__ inline void ggg_fm(typename KT::T* key, int32_t* sw, int32_t nvp, int
                 const T k = key[uw.x];
                 if (k >= KT::front) {
                     // a neighbour now on pick's side loses the edge from its gain, one across gains it
-                    const int32_t d = (sw[uw.x] ^ spn) >= 0 ? -2 * uw.y : 2 * uw.y;
-                    key[uw.x] = KT::front | KT::make(KT::gain(k) + d, (uint32_t)uw.x);
+                    // in 64 bits: one edge may weigh more than 2^30; the new gain (within the
+                    // node's weighted degree, at most 2^31 - 1) fits 32 bits again
+                    const int64_t d = (sw[uw.x] ^ spn) >= 0 ? -2 * (int64_t)uw.y : 2 * (int64_t)uw.y;
+                    key[uw.x] = KT::front | KT::make((int32_t)((int64_t)KT::gain(k) + d), (uint32_t)uw.x);
                 }
             }
             fence_wave<LDS>();

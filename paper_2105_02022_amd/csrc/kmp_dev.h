@@ -371,6 +371,8 @@ class Ctx {
     // same call (stream order makes that safe) and return to the shared pool
     // when the call ends, after the stream has drained.
     int device_ = 0;
+    size_t ws_limit_ = 0;  // KMP_WORKSPACE_LIMIT: largest workspace this call may take (0: none)
+    size_t ws_taken_ = 0;  // capacity of the blocks taken by this call so far
     std::vector<std::pair<void*, size_t>> live_;   // (block, capacity) in use
     std::vector<std::pair<void*, size_t>> freed_;  // freed during this call
     // Pinned host staging: writes are enqueued without waiting; the chunks

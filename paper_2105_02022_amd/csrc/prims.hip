@@ -1,6 +1,7 @@
 // Data-parallel building blocks: per-call context, prefix scans, stable LSD
 // radix sort (wave-ballot ranking, 64-wide wavefronts), fills, reductions.
 #include <chrono>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 
@@ -82,6 +83,13 @@ void tuning_set(const Tuning& t)
 Ctx::Ctx(hipStream_t s) : stream(s), tune(tuning_get())
 {
     if (hipGetDevice(&device_) != hipSuccess || device_ < 0 || device_ >= 64) device_ = 0;
+    // a host-side cap on the workspace of one call, so tests can drive the
+    // out-of-memory path without exhausting the device
+    if (const char* lim = getenv("KMP_WORKSPACE_LIMIT")) {
+        char* end = nullptr;
+        const unsigned long long v = strtoull(lim, &end, 10);
+        if (end != lim) ws_limit_ = (size_t)v;
+    }
 }
 
 Ctx::~Ctx()
@@ -114,6 +122,9 @@ void* Ctx::alloc_bytes(size_t bytes)
             return b.first;
         }
     }
+    if (ws_limit_ && ws_taken_ + cap > ws_limit_)
+        throw Error(KMP_ENOMEM, "device workspace above KMP_WORKSPACE_LIMIT (" + std::to_string(ws_taken_ + cap) +
+                                    " bytes)");
     void* p = nullptr;
     {
         DevicePool& dp = device_pool();
@@ -137,6 +148,7 @@ void* Ctx::alloc_bytes(size_t bytes)
             }
         }
     }
+    ws_taken_ += got;
     live_.emplace_back(p, got);
     return p;
 }

@@ -1,16 +1,21 @@
 // Serving loop: partition jobs that arrive over time, with continuous batching.
 //
-// Submitted jobs wait in arrival order.  Each worker thread owns a HIP stream;
-// when a worker is free it takes the longest run of waiting jobs, from the
-// front, whose estimated device footprint fits the free part of the HBM
-// budget (at most kMaxBatchJobs), and partitions them as one batch (the
-// level-by-level union pass of kmp_partition_batch).  Jobs that arrive while
-// other batches run are admitted by the next free worker, so their work
-// overlaps on the device with the batches already running.  Every job's
-// result is the one kmp_partition gives for it alone.
+// Submitted jobs wait in arrival order.  Each worker thread owns a HIP stream.
+// When a worker is free it opens a batch with the oldest waiting job, provided
+// its estimated device footprint fits the free part of the HBM budget (or
+// nothing else runs), and adds later waiting jobs of the same size class
+// (n + m within a factor of four of the first job's) and the same
+// initial-bipartitioning options whose footprints still fit (at most
+// kMaxBatchJobs); the others keep their place in the queue.  The batch is
+// partitioned in one level-by-level union pass (as kmp_partition_batch).
+// Jobs that arrive while other batches run are admitted by the next free
+// worker, so their work overlaps on the device with the batches already
+// running, and small jobs are not held behind a large one of the same
+// batch.  Every job's result is the one kmp_partition gives for it alone
+// with the options that were current when it was submitted.
 #include <chrono>
 #include <condition_variable>
-#include <deque>
+#include <list>
 #include <mutex>
 #include <new>
 #include <thread>
@@ -22,6 +27,8 @@ struct kmp_server {
     using clk = std::chrono::steady_clock;
     struct Job {
         kmp_graph_desc d;
+        kmp_options opt = {};  // fm_passes and ip_pool current at submission
+        int size_class = 0;    // floor(log2(n + m + 1)) / 2
         size_t foot = 0;
         int state = 0;  // 0 waiting, 1 running, 2 done
         kmp_job_result res;
@@ -33,13 +40,13 @@ struct kmp_server {
     std::vector<hipStream_t> streams;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
-    std::deque<uint64_t> queue;
+    std::list<uint64_t> queue;  // waiting jobs in arrival order
     std::unordered_map<uint64_t, Job> jobs;
     uint64_t next_id = 1;
     int running = 0;
     bool stop = false;
     kmp_server_stats st = {};
-    kmp_options opt = {};  // only fm_passes and ip_pool are used
+    kmp_options opt = {};  // fm_passes and ip_pool given to jobs submitted from now on
 };
 
 namespace kmp {
@@ -56,6 +63,19 @@ size_t footprint(const kmp_graph_desc& d)
     return (size_t)(160.0 * n + 96.0 * m) + ((size_t)1 << 20);
 }
 
+int size_class_of(const kmp_graph_desc& d)
+{
+    const uint64_t w = (uint64_t)(d.n > 0 ? d.n : 0) + (uint64_t)(d.m > 0 ? d.m : 0) + 1;
+    int b = 0;
+    while ((w >> (b + 1)) != 0) ++b;
+    return b / 2;
+}
+
+bool same_options(const kmp_options& a, const kmp_options& b)
+{
+    return a.fm_passes == b.fm_passes && a.ip_pool == b.ip_pool;
+}
+
 void worker_main(kmp_server* s, int w)
 {
     (void)hipSetDevice(s->device);
@@ -68,8 +88,8 @@ void worker_main(kmp_server* s, int w)
         size_t reserved = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            // the front job fits, or nothing else is running (a job larger than
-            // the whole budget then runs alone)
+            // the oldest waiting job fits, or nothing else is running (a job
+            // larger than the whole budget then runs alone)
             s->cv_work.wait(lk, [&] {
                 if (s->stop && s->queue.empty()) return true;
                 if (s->queue.empty()) return false;
@@ -78,21 +98,36 @@ void worker_main(kmp_server* s, int w)
             });
             if (s->queue.empty()) return;  // stopping and drained
             ids.clear();
-            while (!s->queue.empty() && (int)ids.size() < kMaxBatchJobs) {
-                kmp_server::Job& jb = s->jobs[s->queue.front()];
-                const bool fits = s->in_use + reserved + jb.foot <= s->budget;
-                if (!fits && !(ids.empty() && s->in_use == 0)) break;
+            const kmp_server::Job& head = s->jobs[s->queue.front()];
+            const int cls = head.size_class;
+            opt = head.opt;
+            // batch entries and nodes stay below 2^30 each (the union's indices are int32)
+            int64_t sum_n = 0, sum_m = 0;
+            for (auto it = s->queue.begin(); it != s->queue.end() && (int)ids.size() < kMaxBatchJobs;) {
+                kmp_server::Job& jb = s->jobs[*it];
+                const bool first = ids.empty();
+                bool take = first;
+                if (!first) {
+                    take = same_options(jb.opt, opt) && jb.size_class >= cls - 1 && jb.size_class <= cls + 1 &&
+                           s->in_use + reserved + jb.foot <= s->budget && sum_n + jb.d.n < (int64_t(1) << 30) &&
+                           sum_m + jb.d.m < (int64_t(1) << 30);
+                }
+                if (!take) {
+                    ++it;
+                    continue;
+                }
                 reserved += jb.foot;
+                sum_n += jb.d.n > 0 ? jb.d.n : 0;
+                sum_m += jb.d.m > 0 ? jb.d.m : 0;
                 jb.state = 1;
                 jb.t_start = kmp_server::clk::now();
-                ids.push_back(s->queue.front());
-                s->queue.pop_front();
+                ids.push_back(*it);
+                it = s->queue.erase(it);
             }
             s->in_use += reserved;
             ++s->running;
             descs.resize(ids.size());
             for (size_t i = 0; i < ids.size(); ++i) descs[i] = s->jobs[ids[i]].d;
-            opt = s->opt;
         }
         res.assign(ids.size(), kmp_job_result{});
         const int rc = run_batch(descs.data(), (int32_t)ids.size(), res.data(), stream, &opt, nullptr);
@@ -121,9 +156,15 @@ int take_result(kmp_server* s, uint64_t id, kmp_job_result* result, double* late
 {
     std::unique_lock<std::mutex> lk(s->mu);
     if (s->jobs.find(id) == s->jobs.end()) return KMP_EINVAL;
-    // look the job up again after every wake-up: submissions may rehash the map
-    if (block) s->cv_done.wait(lk, [&] { return s->jobs.find(id)->second.state == 2; });
+    // look the job up again after every wake-up: submissions may rehash the
+    // map, and another thread waiting on the same id may have taken it
+    if (block)
+        s->cv_done.wait(lk, [&] {
+            auto it = s->jobs.find(id);
+            return it == s->jobs.end() || it->second.state == 2;
+        });
     auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return KMP_EINVAL;  // taken by another caller meanwhile
     if (it->second.state != 2) return 0;
     if (result) *result = it->second.res;
     if (latency_ms)
@@ -186,6 +227,8 @@ int kmp_server_submit(kmp_server* s, const kmp_graph_desc* job, uint64_t* job_id
     const uint64_t id = s->next_id++;
     kmp_server::Job& jb = s->jobs[id];
     jb.d = *job;
+    jb.opt = s->opt;
+    jb.size_class = size_class_of(*job);
     jb.foot = footprint(*job);
     jb.t_submit = kmp_server::clk::now();
     s->queue.push_back(id);

@@ -1,9 +1,9 @@
 """Summaries of rocprofv3 output (kernel dispatch statistics, PMC counters).
 
-    python -m paper_2105_02022_amd.profsum stats <run_results.db> [top]
-    python -m paper_2105_02022_amd.profsum pmc <counter_collection.csv>...
-    python -m paper_2105_02022_amd.profsum copy <MiB> [reps]
-    python -m paper_2105_02022_amd.profsum traffic <fetch.csv> <write.csv> <copy_fetch.csv> <copy_write.csv> <MiB>
+    python profsum.py stats <run_results.db> [top]
+    python profsum.py pmc <counter_collection.csv>...
+    python profsum.py copy <MiB> [reps]
+    python profsum.py traffic <fetch.csv> <write.csv> <copy_fetch.csv> <copy_write.csv> <MiB>
 
 `stats` reads the rocpd SQLite database written by
 ``rocprofv3 --kernel-trace --stats`` and prints per-kernel launch counts and
@@ -30,7 +30,7 @@ import os
 
 def source_hash() -> str:
     """Digest of the HIP sources, so a stored counter summary is used only for the kernels it measured."""
-    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2105_02022_amd", "csrc")
     h = hashlib.sha256()
     for f in sorted(os.listdir(d)):
         if f.endswith((".hip", ".h")):

@@ -43,6 +43,22 @@ def _heavy_nodes(n, seed):
     return g
 
 
+def _one_huge_edge(n, seed):
+    """A weighted random graph in which one edge weighs more than 2^30 (half the edge-weight sum still
+    fits in int32): FM gain updates of its endpoints pass 2^31 unless they are computed in 64 bits."""
+    g = gen.random_graph(n, 5.0, seed, max_ew=3)
+    w = np.asarray(g.adjwgt, np.int64).copy()
+    xadj, adj = np.asarray(g.xadj), np.asarray(g.adjncy)
+    u = int(np.argmax(np.diff(xadj)))
+    v = int(adj[xadj[u]])
+    w[xadj[u]] = (1 << 30) + 7
+    rev = xadj[v] + int(np.nonzero(adj[xadj[v]:xadj[v + 1]] == u)[0][0])
+    w[rev] = (1 << 30) + 7
+    assert w.sum() // 2 < 2**31 - 1
+    g.adjwgt = w.astype(np.int32)
+    return g
+
+
 def _rounds(kmp, g, k, level, seed, passes, name, pool=False):
     lk = oracle.lk(int(node_w(g).sum()), k, 0.03)
     part = np.zeros(g.n, np.int32)
@@ -66,8 +82,8 @@ def test_bipartition_round_fm(kmp, k, passes):
     _rounds(kmp, gen.rgg(4000, 8.0, 21), k, 0, 3, passes, "rgg4000")
 
 
-@pytest.mark.parametrize("name", ["weighted", "heavy", "heavy-lds-and-global", "big-edge-weights", "cliques",
-                                  "tiny", "isolated", "path"])
+@pytest.mark.parametrize("name", ["weighted", "heavy", "heavy-lds-and-global", "big-edge-weights",
+                                  "edge-above-2^30", "cliques", "tiny", "isolated", "path"])
 def test_bipartition_fm_weighted_and_degenerate(kmp, name):
     g, k = {
         "weighted": lambda: (gen.random_graph(900, 5.0, 31, max_vw=20, max_ew=5), 7),
@@ -75,6 +91,7 @@ def test_bipartition_fm_weighted_and_degenerate(kmp, name):
         "heavy-lds-and-global": lambda: (_heavy_nodes(3000, 35), 6),
         # weighted degrees beyond 2^19: the 64-bit keys inside LDS-sized blocks
         "big-edge-weights": lambda: (gen.random_graph(400, 5.0, 36, max_ew=300000), 4),
+        "edge-above-2^30": lambda: (_one_huge_edge(400, 37), 4),
         "cliques": lambda: (csr_from_dense(two_cliques(40)), 2),
         "tiny": lambda: (gen.grid(1, 3), 8),
         "isolated": lambda: (gen.random_graph(500, 1.0, 32, isolated_frac=0.6), 4),

@@ -141,3 +141,49 @@ def test_server_with_ip_options_matches_oracle(kmp):
         assert r["status"] == ref.status, j["name"]
         assert np.array_equal(j["out"].cpu().numpy(), ref.part), j["name"]
         assert r["cut"] == ref.stats["cut"], j["name"]
+
+
+def test_server_options_bound_at_submission(kmp):
+    """Options changed while earlier jobs still wait apply only to jobs submitted after the change: each
+    result equals the oracle's with the options that were current when that job was submitted."""
+    specs = small_serving_jobs(12, seed=13)
+    jobs = _device_jobs(kmp, specs)
+    with kmp.Server(8 << 30, workers=1) as srv:
+        ids, opts = [], []
+        for i, j in enumerate(jobs):
+            if i % 4 == 0:
+                o = [(0, False), (2, True), (1, False)][(i // 4) % 3]
+                assert srv.set_options(fm_passes=o[0], ip_pool=o[1]) == kmp.KMP_OK
+            ids.append(srv.submit(j))
+            opts.append(o)
+        res = [srv.wait(i) for i in ids]
+    for j, r, (p, q) in zip(jobs, res, opts):
+        ref = oracle.partition(j["g"], j["k"], j["epsilon"], j["seed"], fm_passes=p, pool=q)
+        assert r["status"] == ref.status, j["name"]
+        assert np.array_equal(j["out"].cpu().numpy(), ref.part), (j["name"], p, q)
+        assert r["cut"] == ref.stats["cut"], j["name"]
+
+
+def test_server_two_waiters_on_one_job(kmp):
+    """Two threads wait on the same job: one receives the result, the other an error, and nothing
+    crashes."""
+    jobs = _device_jobs(kmp, small_serving_jobs(3, seed=17))
+    with kmp.Server(8 << 30, workers=1) as srv:
+        ids = [srv.submit(j) for j in jobs]
+        got, errs = [], []
+
+        def waiter():
+            try:
+                got.append(srv.wait(ids[-1]))
+            except KeyError:
+                errs.append(1)
+
+        ths = [threading.Thread(target=waiter) for _ in range(2)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        for i in ids[:-1]:
+            srv.wait(i)
+    assert len(got) == 1 and len(errs) == 1
+    _check(jobs[-1], got[0])
