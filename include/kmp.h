@@ -57,6 +57,7 @@ extern "C" {
 #define KMP_EOVERFLOW (-3) /* sum(vwgt) or sum(adjwgt)/2 exceeds INT32_MAX */
 #define KMP_ENOMEM (-4)    /* device workspace allocation failed */
 #define KMP_EHIP (-5)      /* a HIP runtime call failed */
+#define KMP_ETOOLARGE (-6) /* input beyond the limits of kmp_partition_noalloc */
 
 #define KMP_MAX_LEVELS 64
 
@@ -142,6 +143,7 @@ typedef struct kmp_stats {
     int64_t prof_launches[KMP_PROF_CLASSES];
     double prof_ms[KMP_PROF_CLASSES];
     int64_t prof_bytes[KMP_PROF_CLASSES];
+    int64_t workspace_bytes;                /* device workspace the call took (block capacities) */
 } kmp_stats;
 
 /*
@@ -159,6 +161,32 @@ int kmp_partition(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwg
 int kmp_partition_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
                      int32_t n, int64_t m, int32_t k, double epsilon, uint64_t seed, int32_t* out_part,
                      void* stream, const kmp_options* opt, kmp_stats* stats);
+
+/*
+ * kmp_partition_noalloc: kmp_partition_ex that allocates nothing, for callers
+ * that cannot allocate device or pinned host memory (code around graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Every
+ * device buffer of the call is carved from a fixed scratch region of
+ * KMP_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on,
+ * from the first call there until the process ends; host reads and writes
+ * are plain stream-ordered copies followed by a synchronisation of `stream`.
+ * The output equals kmp_partition_ex's for the same arguments.
+ * Limits: n <= KMP_NOALLOC_MAX_N and m <= KMP_NOALLOC_MAX_M, else
+ * KMP_ETOOLARGE and nothing runs; opt->profile must be 0 (KMP_EINVAL), the
+ * other options are honoured; a call whose workspace would still exceed the
+ * region returns KMP_ENOMEM.  The region is shared by all calls on a device:
+ * calls from this process on one device run one at a time (a lock is held
+ * for the whole call), and each call clears what it needs, so no state
+ * carries from one call to the next.  Two processes each hold their own
+ * region.  stats (may be NULL) as for kmp_partition_ex; workspace_bytes
+ * reports how much of the region the call used.
+ */
+#define KMP_NOALLOC_MAX_N 65536
+#define KMP_NOALLOC_MAX_M 1048576
+#define KMP_NOALLOC_SCRATCH_BYTES (256ull << 20)
+int kmp_partition_noalloc(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                          int32_t n, int64_t m, int32_t k, double epsilon, uint64_t seed, int32_t* out_part,
+                          void* stream, const kmp_options* opt, kmp_stats* stats);
 
 /* One job of a batch: a graph in the layout above plus its own k, eps, seed
  * and output array (all device pointers owned by the caller). */

@@ -19,6 +19,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkmp.so")
 
 KMP_OK, KMP_IMBALANCED, KMP_EINVAL, KMP_EGRAPH, KMP_EOVERFLOW, KMP_ENOMEM, KMP_EHIP = 0, 1, -1, -2, -3, -4, -5
+KMP_ETOOLARGE = -6
+# limits of kmp_partition_noalloc (include/kmp.h)
+NOALLOC_MAX_N, NOALLOC_MAX_M, NOALLOC_SCRATCH_BYTES = 65536, 1048576, 256 << 20
 MAX_LEVELS = 64
 
 
@@ -42,7 +45,7 @@ class KmpStats(ctypes.Structure):
                 ("ms_coarsen_lp", ctypes.c_double), ("ms_contract", ctypes.c_double),
                 ("ms_initial", ctypes.c_double), ("ms_refine", ctypes.c_double),
                 ("prof_launches", ctypes.c_int64 * 16), ("prof_ms", ctypes.c_double * 16),
-                ("prof_bytes", ctypes.c_int64 * 16)]
+                ("prof_bytes", ctypes.c_int64 * 16), ("workspace_bytes", ctypes.c_int64)]
 
 
 _vp = ctypes.c_void_p
@@ -85,6 +88,8 @@ SIGNATURES = {
     "kmp_partition": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp]),
     "kmp_partition_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp,
                                         ctypes.POINTER(KmpOptions), ctypes.POINTER(KmpStats)]),
+    "kmp_partition_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _dbl, _u64, _vp, _vp,
+                                             ctypes.POINTER(KmpOptions), ctypes.POINTER(KmpStats)]),
     "kmp_partition_batch": (ctypes.c_int, [ctypes.POINTER(KmpGraphDesc), _i32, ctypes.POINTER(KmpJobResult), _vp,
                                            ctypes.POINTER(KmpOptions), ctypes.POINTER(KmpStats)]),
     "kmp_server_create": (_vp, [ctypes.c_size_t, _i32]),
@@ -247,6 +252,30 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
                                     ctypes.byref(st))
     stats = _stats_dict(st, profile)
     return rc, out, stats
+
+
+def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
+                          stream=None, validate: bool = False, force_exact: bool = False, small_level_n: int = 0,
+                          fm_passes: int = 0, ip_pool: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+    """kmp_partition_noalloc: as kmp_partition_ex, with every device buffer inside the library's fixed
+    scratch region (n <= NOALLOC_MAX_N, m <= NOALLOC_MAX_M, else KMP_ETOOLARGE).  `out` should be
+    given by callers that must not allocate."""
+    import torch
+    _check_i32(xadj, adjncy, vwgt, adjwgt)
+    n = xadj.numel() - 1
+    if out is None:
+        out = torch.empty(max(n, 0), dtype=torch.int32, device=xadj.device)
+    opt = KmpOptions()
+    opt.validate = int(validate)
+    opt.force_exact = int(force_exact)
+    opt.small_level_n = int(small_level_n)
+    opt.fm_passes = int(fm_passes)
+    opt.ip_pool = int(ip_pool)
+    st = KmpStats()
+    rc = library().kmp_partition_noalloc(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
+                                         epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream),
+                                         ctypes.byref(opt), ctypes.byref(st))
+    return rc, out, _stats_dict(st, False)
 
 
 def _stats_dict(st: "KmpStats", profile: bool) -> Dict:

@@ -873,11 +873,12 @@ void fill_stats(kmp_stats* st, const JobRun& jb, const Totals& t)
 }
 
 int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32_t* out_part, hipStream_t stream,
-                   const kmp_options* opt, kmp_stats* st)
+                   const kmp_options* opt, kmp_stats* st, void* arena, size_t arena_bytes)
 {
     auto t_start = clk::now();
-    init_pool_once();
-    Ctx c(stream);
+    if (!arena) init_pool_once();
+    std::unique_ptr<Ctx> ctx(arena ? new Ctx(stream, arena, arena_bytes) : new Ctx(stream));
+    Ctx& c = *ctx;
     std::unique_ptr<Prof> prof;
     if (opt && opt->profile) {
         prof.reset(new Prof());
@@ -911,6 +912,7 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
         fill_stats(st, jb, t);
         st->ms_total = ms_since(t_start);
         if (prof) c.prof_collect(st->prof_launches, st->prof_ms, st->prof_bytes);
+        st->workspace_bytes = (int64_t)c.workspace_taken();
     }
     c.prof = nullptr;
     return jb.status;
@@ -986,6 +988,7 @@ int partition_batch_impl(const kmp_graph_desc* gd, int32_t count, kmp_job_result
         fill_stats(st, JobRun(), t);
         for (auto& jb : jobs) st->cut += jb.cut;
         st->ms_total = ms_since(t_start);
+        st->workspace_bytes = (int64_t)c.workspace_taken();
         if (prof) c.prof_collect(st->prof_launches, st->prof_ms, st->prof_bytes);
     }
     c.prof = nullptr;
@@ -1117,6 +1120,11 @@ int run_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_result* resul
 
 using namespace kmp;
 
+namespace {
+std::mutex g_noalloc_mu[64];   // one call at a time per device: the scratch region is shared
+void* g_noalloc_ptr[64] = {};  // device address of the scratch region per device, set at the first call
+}  // namespace
+
 extern "C" {
 
 int kmp_partition_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
@@ -1129,7 +1137,7 @@ int kmp_partition_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* 
     if (n == 0) return m == 0 ? KMP_OK : KMP_EINVAL;
     return (int)guarded([&]() -> int64_t {
         return partition_impl(make_graph(xadj, adjncy, vwgt, adjwgt, n, m), k, epsilon, seed, out_part,
-                              (hipStream_t)stream, opt, stats);
+                              (hipStream_t)stream, opt, stats, nullptr, 0);
     });
 }
 
@@ -1197,6 +1205,7 @@ const char* kmp_strerror(int code)
         case KMP_EOVERFLOW: return "weight sum exceeds int32";
         case KMP_ENOMEM: return "device memory allocation failed";
         case KMP_EHIP: return "HIP runtime error";
+        case KMP_ETOOLARGE: return "input beyond the size limits of the allocation-free entry point";
         default: return "unknown status";
     }
 }
@@ -1396,6 +1405,40 @@ int64_t kmp_lp_subround(const int32_t* xadj, const int32_t* adjncy, const int32_
         int64_t r = lp_subround(c, g, level, round, s, seed, sched, ls, active, moved);
         c.sync();
         return r;
+    });
+}
+
+// ---------------------------------------------------------------- allocation-free entry point
+// The scratch region of kmp_partition_noalloc: one copy per device, loaded
+// with the code object.  Host code never passes this name to a kernel (on the
+// host it is a stand-in, not a device address); it uses the address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[KMP_NOALLOC_SCRATCH_BYTES];
+
+int kmp_partition_noalloc(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                          int32_t n, int64_t m, int32_t k, double epsilon, uint64_t seed, int32_t* out_part,
+                          void* stream, const kmp_options* opt, kmp_stats* stats)
+{
+    if (stats) memset(stats, 0, sizeof(*stats));
+    int rc = check_args(xadj, n, m, k, epsilon, out_part);
+    if (rc != KMP_OK) return rc;
+    if (n > KMP_NOALLOC_MAX_N || m > KMP_NOALLOC_MAX_M) return KMP_ETOOLARGE;
+    if (opt && opt->profile) return KMP_EINVAL;  // profiling records events, which the runtime allocates
+    if (n == 0) return m == 0 ? KMP_OK : KMP_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return KMP_EHIP;
+    std::lock_guard<std::mutex> lk(g_noalloc_mu[dev]);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return KMP_EHIP;
+        }
+        g_noalloc_ptr[dev] = p;
+    }
+    return (int)guarded([&]() -> int64_t {
+        return partition_impl(make_graph(xadj, adjncy, vwgt, adjwgt, n, m), k, epsilon, seed, out_part,
+                              (hipStream_t)stream, opt, stats, g_noalloc_ptr[dev], (size_t)KMP_NOALLOC_SCRATCH_BYTES);
     });
 }
 

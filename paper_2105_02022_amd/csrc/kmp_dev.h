@@ -314,6 +314,13 @@ void tuning_set(const Tuning& t);
 class Ctx {
   public:
     explicit Ctx(hipStream_t s);
+    // Arena mode: every device buffer of the call is carved from
+    // [arena, arena + arena_bytes), a region the caller owns; nothing is
+    // allocated on the device or pinned on the host, reads and writes are
+    // stream-ordered copies to and from the caller's host memory followed by
+    // a stream synchronisation, and buffers are cleared by fill kernels.  A
+    // call that needs more than the region fails with KMP_ENOMEM.
+    Ctx(hipStream_t s, void* arena, size_t arena_bytes);
     ~Ctx();
     Ctx(const Ctx&) = delete;
     Ctx& operator=(const Ctx&) = delete;
@@ -364,6 +371,8 @@ class Ctx {
     // Resolve the recorded events into per-class launches / ms and read the
     // per-class algorithmic byte counters.
     void prof_collect(int64_t* launches, double* ms, int64_t* bytes);
+    // Device workspace taken so far (capacities of the blocks obtained).
+    size_t workspace_taken() const { return ws_taken_; }
 
   private:
     // Device memory comes from a process-wide caching pool (per device):
@@ -373,6 +382,9 @@ class Ctx {
     int device_ = 0;
     size_t ws_limit_ = 0;  // KMP_WORKSPACE_LIMIT: largest workspace this call may take (0: none)
     size_t ws_taken_ = 0;  // capacity of the blocks taken by this call so far
+    char* arena_ = nullptr;    // arena mode: the caller's region (nullptr: the caching pool)
+    size_t arena_bytes_ = 0;
+    void* arena_take(size_t cap);
     std::vector<std::pair<void*, size_t>> live_;   // (block, capacity) in use
     std::vector<std::pair<void*, size_t>> freed_;  // freed during this call
     // Pinned host staging: writes are enqueued without waiting; the chunks

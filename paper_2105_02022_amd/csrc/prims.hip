@@ -92,9 +92,28 @@ Ctx::Ctx(hipStream_t s) : stream(s), tune(tuning_get())
     }
 }
 
+Ctx::Ctx(hipStream_t s, void* arena, size_t arena_bytes)
+    : stream(s), tune(tuning_get()), arena_(static_cast<char*>(arena)), arena_bytes_(arena_bytes)
+{
+    if (hipGetDevice(&device_) != hipSuccess || device_ < 0 || device_ >= 64) device_ = 0;
+}
+
+// Bump allocation in the caller's region (256-byte aligned blocks); blocks
+// freed during the call are reused through freed_ as in pool mode.
+void* Ctx::arena_take(size_t cap)
+{
+    if (ws_taken_ + cap > arena_bytes_)
+        throw Error(KMP_ENOMEM, "scratch region exhausted (" + std::to_string(ws_taken_ + cap) + " of " +
+                                    std::to_string(arena_bytes_) + " bytes)");
+    void* p = arena_ + ws_taken_;
+    ws_taken_ += cap;
+    return p;
+}
+
 Ctx::~Ctx()
 {
     (void)hipStreamSynchronize(stream);
+    if (arena_) return;  // the region stays the caller's; nothing was taken from the pools
     DevicePool& dp = device_pool();
     {
         std::lock_guard<std::mutex> lk(dp.mu);
@@ -121,6 +140,12 @@ void* Ctx::alloc_bytes(size_t bytes)
             live_.push_back(b);
             return b.first;
         }
+    }
+    if (arena_) {
+        const size_t cap256 = (cap + 255) & ~(size_t)255;  // keeps every block 256-byte aligned
+        void* p = arena_take(cap256);
+        live_.emplace_back(p, cap256);
+        return p;
     }
     if (ws_limit_ && ws_taken_ + cap > ws_limit_)
         throw Error(KMP_ENOMEM, "device workspace above KMP_WORKSPACE_LIMIT (" + std::to_string(ws_taken_ + cap) +
@@ -167,7 +192,9 @@ void Ctx::free(void* p)
 
 void Ctx::zero(void* p, size_t bytes)
 {
-    if (bytes) KMP_HIP(hipMemsetAsync(p, 0, bytes, stream));
+    if (!bytes) return;
+    if (arena_) fill_bytes_many(*this, {{p, (int64_t)bytes, 0}});
+    else KMP_HIP(hipMemsetAsync(p, 0, bytes, stream));
 }
 
 void Ctx::sync() { KMP_HIP(hipStreamSynchronize(stream)); }
@@ -232,6 +259,11 @@ constexpr size_t kFlagReadMax = 4096 - kFlagBytes;  // larger reads take the run
 void Ctx::read(void* host, const void* dev, size_t bytes)
 {
     if (!bytes) return;
+    if (arena_) {
+        KMP_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, stream));
+        KMP_HIP(hipStreamSynchronize(stream));
+        return;
+    }
     if (read_bytes_ < bytes + kFlagBytes) {
         if (read_buf_) {
             std::lock_guard<std::mutex> lk(g_pinned_mu);
@@ -289,6 +321,11 @@ void Ctx::read(void* host, const void* dev, size_t bytes)
 void Ctx::write(void* dev, const void* host, size_t bytes)
 {
     if (!bytes) return;
+    if (arena_) {
+        KMP_HIP(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, stream));
+        KMP_HIP(hipStreamSynchronize(stream));  // the host buffer may be temporary
+        return;
+    }
     void* st = stage(bytes);
     memcpy(st, host, bytes);
     KMP_HIP(hipMemcpyAsync(dev, st, bytes, hipMemcpyHostToDevice, stream));
@@ -296,6 +333,10 @@ void Ctx::write(void* dev, const void* host, size_t bytes)
 
 int64_t* Ctx::counters()
 {
+    if (!counters_ && arena_) {
+        counters_ = static_cast<int64_t*>(arena_take(512));
+        zero_counters();
+    }
     if (!counters_) {
         size_t got = 0;
         void* p = nullptr;
@@ -319,6 +360,11 @@ void Ctx::zero_counters() { zero(counters(), 64 * sizeof(int64_t)); }
 
 int64_t* Ctx::spread(int idx)
 {
+    if (!spread_ && arena_) {
+        const size_t bytes = (size_t)SP_COUNT * kSpreadSlots * sizeof(int64_t);
+        spread_ = static_cast<int64_t*>(arena_take((bytes + 255) & ~(size_t)255));
+        zero(spread_, bytes);
+    }
     if (!spread_) {
         const size_t bytes = (size_t)SP_COUNT * kSpreadSlots * sizeof(int64_t);
         size_t got = 0;

@@ -49,6 +49,33 @@ def test_argument_errors_before_any_device_work():
     assert lib.kmp_partition(None, None, None, None, 0, 0, 4, 0.03, 1, None, None) == kmp.KMP_OK
 
 
+def test_noalloc_limits_before_any_device_work():
+    """kmp_partition_noalloc rejects inputs beyond its stated limits, and profiling, before touching
+    the device; the header's limits and the binding's agree."""
+    import ctypes
+    import re
+    lib = kmp.library()
+    h = open(os.path.join(ROOT, "include", "kmp.h")).read()
+    lim = {k: int(v) for k, v in re.findall(r"#define (KMP_NOALLOC_MAX_[NM]) (\d+)", h)}
+    assert lim == {"KMP_NOALLOC_MAX_N": kmp.NOALLOC_MAX_N, "KMP_NOALLOC_MAX_M": kmp.NOALLOC_MAX_M}
+    sc = re.search(r"#define KMP_NOALLOC_SCRATCH_BYTES \((\d+)ull << (\d+)\)", h)
+    assert int(sc.group(1)) << int(sc.group(2)) == kmp.NOALLOC_SCRATCH_BYTES
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: the checks come first
+    big_n, big_m = kmp.NOALLOC_MAX_N + 1, kmp.NOALLOC_MAX_M + 1
+    assert lib.kmp_partition_noalloc(fake, fake, None, None, big_n, 0, 2, 0.03, 1, fake, None, None,
+                                     None) == kmp.KMP_ETOOLARGE
+    assert lib.kmp_partition_noalloc(fake, fake, None, None, 10, big_m, 2, 0.03, 1, fake, None, None,
+                                     None) == kmp.KMP_ETOOLARGE
+    opt = kmp.KmpOptions()
+    opt.profile = 1
+    assert lib.kmp_partition_noalloc(fake, fake, None, None, 10, 20, 2, 0.03, 1, fake, None, ctypes.byref(opt),
+                                     None) == kmp.KMP_EINVAL
+    assert lib.kmp_partition_noalloc(None, None, None, None, 10, 0, 0, 0.03, 1, None, None, None,
+                                     None) == kmp.KMP_EINVAL
+    assert lib.kmp_partition_noalloc(None, None, None, None, 0, 0, 4, 0.03, 1, None, None, None, None) == kmp.KMP_OK
+    assert "limits" in kmp.kmp_strerror(kmp.KMP_ETOOLARGE)
+
+
 def test_batch_argument_errors_before_any_device_work():
     lib = kmp.library()
     assert lib.kmp_partition_batch(None, -1, None, None, None, None) == kmp.KMP_EINVAL
