@@ -55,10 +55,10 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")
-    ap.add_argument("--serving-jobs", type=int, default=400)
-    ap.add_argument("--serving-loads", type=str, default="0.7",
+    ap.add_argument("--serving-jobs", type=int, default=2000)
+    ap.add_argument("--serving-loads", type=str, default="0.25,0.5,0.7,0.9",
                     help="offered loads as fractions of the measured capacity, comma separated")
-    ap.add_argument("--serving-workers", type=int, default=2)
+    ap.add_argument("--serving-workers", type=int, default=4)
     ap.add_argument("--serving-budget-gib", type=float, default=64.0)
     ap.add_argument("--fm-passes", type=int, default=0,
                     help="2-way FM passes after every greedy growth in the timed steps (0: none, the default)")
@@ -68,6 +68,10 @@ def parse():
     ap.add_argument("--ip-compare", type=int, default=1,
                     help="1: also run the workload with FM, the pool and both and report cut and time; 0: skip")
     ap.add_argument("--ip-steps", type=int, default=5)
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the grid 128x128 (k = 8) and RMAT 2^22 (k = 2^15) workloads")
+    ap.add_argument("--rmat-steps", type=int, default=3)
+    ap.add_argument("--grid-steps", type=int, default=20)
     return ap.parse_args()
 
 
@@ -75,8 +79,10 @@ def serving_run(kmp, gen, torch, count, loads, workers, budget_gib):
     """Serving workload: `count` jobs (type uniform over grid / RGG / RMAT with edge factor 8, n log-uniform
     in [2^12, 2^21], k uniform over {2, 8, 64, 512, 4096}, eps 0.03, seed j), each on a graph of a shared
     pool of generated graphs (the job's type at the nearest pool size), CSRs resident in HBM before the run.
-    Capacity: every job submitted at once.  Then Poisson arrivals at each offered load (fraction of the
-    capacity).  Latency = completion - submission, from the server's own clock."""
+    Capacity: every job submitted at once.  One at a time: the same jobs as serial kmp_partition_ex calls on
+    one stream (also each job's result alone).  Then Poisson arrivals at each offered load (fraction of the
+    capacity).  Latency = completion - submission, from the server's own clock.  Every job's output of
+    every served run is compared with its output alone."""
     import numpy as np
     specs = gen.serving_jobs(count)
     keys = sorted(set(gen.serving_pool_key(t, n) for t, n, _, _ in specs))
@@ -90,17 +96,19 @@ def serving_run(kmp, gen, torch, count, loads, workers, budget_gib):
     for typ, n, k, seed in specs:
         g, (xadj, adjncy, vwgt, adjwgt) = pool[gen.serving_pool_key(typ, n)]
         jobs.append(dict(xadj=xadj, adjncy=adjncy, vwgt=vwgt, adjwgt=adjwgt, k=k, epsilon=0.03, seed=seed,
-                         out=torch.empty(g.n, dtype=torch.int32, device="cuda:0")))
+                         out=torch.empty(g.n, dtype=torch.int32, device="cuda:0"), typ=typ))
     torch.cuda.synchronize()
     budget = int(budget_gib * (1 << 30))
+    sum_m = sum(int(j["adjncy"].numel()) for j in jobs)
 
-    def run(rate):
+    def run(rate, subset=None):
+        js = jobs if subset is None else jobs[:subset]
         rng = np.random.default_rng(12345)
-        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count)) if rate else None
+        arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(js))) if rate else None
         with kmp.Server(budget, workers) as srv:
             t0 = time.perf_counter()
             ids = []
-            for j, job in enumerate(jobs):
+            for j, job in enumerate(js):
                 if arrivals is not None:
                     dt = t0 + arrivals[j] - time.perf_counter()
                     if dt > 0:
@@ -109,40 +117,55 @@ def serving_run(kmp, gen, torch, count, loads, workers, budget_gib):
             res = []
             for q, i in enumerate(ids):
                 res.append(srv.wait(i))
-                if (q + 1) % max(1, count // 8) == 0:
-                    print(f"#   {q + 1}/{count} done after {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+                if (q + 1) % max(1, len(js) // 4) == 0:
+                    print(f"#   {q + 1}/{len(js)} done after {time.perf_counter() - t0:.1f} s", file=sys.stderr,
                           flush=True)
             t_end = time.perf_counter()
             st = srv.stats()
         lat = np.array([r["latency_ms"] for r in res])
-        return {"graphs_per_s": round(count / (t_end - t0), 1), "p50_ms": round(float(np.percentile(lat, 50)), 2),
-                "p99_ms": round(float(np.percentile(lat, 99)), 2), "batches": st["batches"],
-                "max_batch_jobs": st["max_batch_jobs"], "all_ok": all(r["status"] in (0, 1) for r in res),
-                "seconds": round(t_end - t0, 2)}, res
+        by_type = {t: round(float(np.percentile([r["latency_ms"] for r, j in zip(res, js) if j["typ"] == t], 50)),
+                            2) for t in ("grid", "rgg", "rmat")}
+        return {"graphs_per_s": round(len(js) / (t_end - t0), 1), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                "p99_ms": round(float(np.percentile(lat, 99)), 2), "p50_ms_by_type": by_type,
+                "batches": st["batches"], "max_batch_jobs": st["max_batch_jobs"],
+                "all_ok": all(r["status"] in (0, 1) for r in res), "seconds": round(t_end - t0, 2)}, res
 
     print("# serving: warmup run", file=sys.stderr, flush=True)
-    run(None)  # warmup: pools, events, code objects
+    run(None, subset=min(count, 200))  # warmup: pools, events, code objects
+    print("# serving: one job at a time (serial kmp_partition_ex calls)", file=sys.stderr, flush=True)
+    alone = []
+    t = time.perf_counter()
+    for j in jobs:
+        rc, o, _ = kmp.kmp_partition_ex(j["xadj"], j["adjncy"], j["vwgt"], j["adjwgt"], j["k"], j["epsilon"],
+                                        j["seed"])
+        assert rc in (0, 1), kmp.kmp_strerror(rc)
+        alone.append(o)
+    torch.cuda.synchronize()
+    t_serial = time.perf_counter() - t
+    serial_gps = count / t_serial
+    print(f"# serving one at a time: {serial_gps:.1f} graphs/s ({t_serial:.1f} s)", file=sys.stderr, flush=True)
+
+    def same_as_alone():
+        return sum(int(torch.equal(j["out"], a)) for j, a in zip(jobs, alone))
+
     print("# serving: capacity run (every job submitted at once)", file=sys.stderr, flush=True)
     cap, _ = run(None)
+    cap["jobs_equal_alone"] = same_as_alone()
     capacity = cap["graphs_per_s"]
     print(f"# serving capacity: {cap}", file=sys.stderr, flush=True)
     runs = []
     for frac in loads:
         r, res = run(frac * capacity)
         r = dict(offered_load=frac, arrival_rate_per_s=round(frac * capacity, 1), **r)
+        r["jobs_equal_alone"] = same_as_alone()
         runs.append(r)
         print(f"# serving load {frac}: {r}", file=sys.stderr, flush=True)
-    # each result is the same alone and in the mix
-    sample = list(range(0, count, max(1, count // 24)))
-    same = True
-    for j in sample:
-        job = jobs[j]
-        rc, alone, st = kmp.kmp_partition_ex(job["xadj"], job["adjncy"], job["vwgt"], job["adjwgt"], job["k"],
-                                             job["epsilon"], job["seed"])
-        same &= bool(torch.equal(alone, job["out"])) and rc in (0, 1)
-    return {"jobs": count, "pool_graphs": len(keys), "workers": workers, "hbm_budget_gib": budget_gib,
-            "saturated": cap, "capacity_graphs_per_s": capacity, "poisson": runs,
-            "alone_equals_mix_sample": len(sample), "alone_equals_mix": bool(same)}
+    every = cap["jobs_equal_alone"] == count and all(r["jobs_equal_alone"] == count for r in runs)
+    return {"jobs": count, "sum_m_directed": sum_m, "pool_graphs": len(keys), "workers": workers,
+            "hbm_budget_gib": budget_gib, "one_at_a_time_graphs_per_s": round(serial_gps, 1),
+            "one_at_a_time_s": round(t_serial, 2), "saturated": cap, "capacity_graphs_per_s": capacity,
+            "served_vs_one_at_a_time": round(capacity / serial_gps, 2), "poisson": runs,
+            "alone_equals_mix_jobs_checked": count * (1 + len(runs)), "alone_equals_mix": bool(every)}
 
 
 def batched_comparison(kmp, gen, torch, count, reps):
@@ -191,7 +214,13 @@ def batched_comparison(kmp, gen, torch, count, reps):
             "speedup_vs_serial": round(t_serial / t_batch, 2), "identical_to_serial": bool(identical)}
 
 
-TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "hbm_traffic_rgg20.md")
+def traffic_summary(workload):
+    return os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+
+
+# kernel classes of LP (rating, admission, apply, one-workgroup LP, next-round marking) and of contraction
+LP_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "lp_small", "active"]
+CONTRACT_CLASSES = ["contract_rows", "contract"]
 
 # kernel classes whose launches count algorithmic bytes (LP rating tiers, contraction rows)
 BYTE_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "lp_small", "contract_rows"]
@@ -201,13 +230,15 @@ KERNEL_OF_CLASS = {"rate_t0": "k_rate_lane", "rate_hub": "k_rate_hub", "lp_small
                    "contract_rows": "k_contract_rows"}
 
 
-def traffic_from_profiles(family):
+def traffic_from_profiles(family, workload="rgg20"):
     """HBM bytes per launch of a kernel family from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary (the JSON block at its end), or None if absent or taken on other kernel sources."""
+    summary of the workload (the JSON block at its end), or None if absent or taken on other kernel
+    sources."""
     from profsum import source_hash
-    if family is None or not os.path.exists(TRAFFIC_SUMMARY):
+    path = traffic_summary(workload)
+    if family is None or not os.path.exists(path):
         return None
-    m = re.search(r"```json\n(.*?)\n```", open(TRAFFIC_SUMMARY).read(), re.S)
+    m = re.search(r"```json\n(.*?)\n```", open(path).read(), re.S)
     if not m:
         return None
     d = json.loads(m.group(1))
@@ -215,6 +246,135 @@ def traffic_from_profiles(family):
     if not e or d.get("source_hash") != source_hash():
         return None
     return e["hbm_bytes_per_launch"]
+
+
+def phase_rates(st_all):
+    """LP edges/s = rated directed entries / summed event time of the LP kernel classes; contraction
+    edges/s = contracted directed entries (sum of m_l over contracted levels) / summed event time of the
+    contraction classes; both from one step with every kernel class timed."""
+    lp_ms = sum(st_all["prof"][c]["ms"] for c in LP_CLASSES)
+    con_ms = sum(st_all["prof"][c]["ms"] for c in CONTRACT_CLASSES)
+    return {"lp_edges_per_s": round(st_all["lp_rated_edges"] / (lp_ms / 1e3)) if lp_ms > 0 else None,
+            "lp_kernel_ms_per_step": round(lp_ms, 3), "lp_rated_edges_per_step": st_all["lp_rated_edges"],
+            "contraction_edges_per_s": round(st_all["contracted_edges"] / (con_ms / 1e3)) if con_ms > 0 else None,
+            "contraction_kernel_ms_per_step": round(con_ms, 3),
+            "contracted_edges_per_step": st_all["contracted_edges"]}
+
+
+def roofline_of(kmp, stats, dom, st_all, workload):
+    classes = kmp.PROF_CLASSES
+    ms = sum(s["prof"][dom]["ms"] for s in stats)
+    by = sum(s["prof"][dom]["bytes"] for s in stats)
+    ln = sum(s["prof"][dom]["launches"] for s in stats)
+    avg_ms = ms / ln
+    bytes_per_launch = by / ln
+    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles(KERNEL_OF_CLASS.get(dom), workload),
+            "kernel": KERNEL_OF_CLASS.get(dom, dom), "class": dom,
+            "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": ln / len(stats),
+            "algorithmic_bytes_per_launch": round(bytes_per_launch),
+            "class_ms_per_step": {c: round(st_all["prof"][c]["ms"], 3) for c in classes
+                                  if st_all["prof"][c]["launches"]}}
+
+
+def golden_parity(name, part, st):
+    """The partition's sha256 and cut against the oracle-written golden file of the workload."""
+    import hashlib
+    import numpy as np
+    path = os.path.join(ROOT, "tests", "golden", f"{name}.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    same = hashlib.sha256(np.ascontiguousarray(part, np.int32).tobytes()).hexdigest() == d["part_sha256"]
+    return {"golden": os.path.basename(path), "part_sha256_equal": bool(same),
+            "cut_equal": st["cut"] == d["stats"]["cut"], "oracle_seconds_recorded": d.get("oracle_seconds")}
+
+
+def extra_workload(kmp, gen, torch, name, steps, warmup, cpu):
+    """Another configuration timed like the headline: whole kmp_partition calls with the CSR resident,
+    the dominant byte-counting class stamped, one all-class step for the per-phase rates, the output
+    compared with the oracle-written golden digest.  cpu: None (skip), "partition" (the oracle's whole
+    partition of the same graph, repeated for at least 2 s) or "lp0" (the oracle's level-0 LP clustering
+    of the same graph, against the GPU's kmp_lp_cluster of that same call)."""
+    import numpy as np
+    w = gen.WORKLOADS[name]
+    k, eps, seed = w["k"], w["eps"], w["seed"]
+    t = time.perf_counter()
+    g = gen.workload(name)
+    print(f"# {name}: n={g.n} m={g.m} maxdeg={g.maxdeg} generated in {time.perf_counter() - t:.1f} s",
+          file=sys.stderr, flush=True)
+    xadj, adjncy, vwgt, adjwgt = kmp.to_device(g, "cuda:0")
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out)
+        assert rc == 0, kmp.kmp_strerror(rc)
+    _, _, st_all = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True)
+    torch.cuda.synchronize()
+    dom = max((c for c in BYTE_CLASSES if st_all["prof"][c]["bytes"] > 0), key=lambda c: st_all["prof"][c]["ms"])
+    stats = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, profile=True,
+                                         profile_classes=[dom])
+        stats.append(st)
+    torch.cuda.synchronize()
+    ms_step = (time.perf_counter() - t0) * 1e3 / steps
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out)
+    torch.cuda.synchronize()
+    ms_plain = (time.perf_counter() - t1) * 1e3 / steps
+    part = out.cpu().numpy()
+    st0 = stats[0]
+    edges = st0["lp_rated_edges"] + st0["contracted_edges"]
+    row = {"workload": w.get("desc", name), "n": g.n, "m_directed": g.m, "max_degree": g.maxdeg, "k": k,
+           "eps": eps, "seed": seed, "steps": steps, "warmup": warmup,
+           "ms_per_partition": round(ms_step, 3), "ms_per_partition_without_events": round(ms_plain, 3),
+           "value": round(edges / (ms_step / 1e3)), "unit": "edges/s",
+           "e2e_edges_per_s": round(g.m / (ms_step / 1e3)), "lp_plus_contraction_edges_per_step": edges,
+           **phase_rates(st_all), "cut": st0["cut"], "levels": st0["levels"],
+           "parity": golden_parity(f"{name}_k{k}", part, st0),
+           "roofline": roofline_of(kmp, stats, dom, st_all, name), "cpu_baseline": None}
+    print(f"# {name}: {ms_step:.2f} ms per partition ({ms_plain:.2f} without events), parity {row['parity']}",
+          file=sys.stderr, flush=True)
+    if cpu == "partition":
+        import oracle
+        times = []
+        while len(times) < 3 or sum(times) < 2.0:
+            t = time.perf_counter()
+            ref = oracle.partition(g, k, eps, seed, validate_input=False)
+            times.append(time.perf_counter() - t)
+        t_med = statistics.median(times)
+        row["cpu_baseline"] = {
+            "value": round(edges / t_med), "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": f"whole partition of the same graph, {len(times)} runs, median {t_med * 1e3:.1f} ms; "
+                      f"single-threaded C oracle, -O2", "same_partition": bool(np.array_equal(ref.part, part))}
+    elif cpu == "lp0":
+        import oracle
+        U, _ = oracle.level_U(g.n, min(k, g.n // oracle.C), g.n, eps)
+        t = time.perf_counter()
+        label, cw, fav, moves, rounds = oracle.lp_cluster(g, 0, U, seed)
+        t_or = time.perf_counter() - t
+        kmp.kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, 0, U, seed)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r, dlabel, dcw, dfav, dmoves = kmp.kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, 0, U, seed)
+        torch.cuda.synchronize()
+        t_gpu = time.perf_counter() - t
+        same = bool(np.array_equal(dlabel.cpu().numpy(), label)) and r == rounds
+        row["cpu_baseline"] = {
+            "value": round(g.m / t_or), "unit": "level-0 LP clustering calls x directed entries per s",
+            "cores": 1, "kind": "oracle",
+            "sample": f"the level-0 LP clustering call of this graph (U = {U}, {rounds} rounds): oracle "
+                      f"{t_or:.2f} s on one core, the GPU's kmp_lp_cluster of the same call "
+                      f"{t_gpu * 1e3:.1f} ms ({t_or / t_gpu:.0f}x), same labels: {same}; the oracle's whole "
+                      f"partition took {row['parity']['oracle_seconds_recorded'] if row['parity'] else '?'} s "
+                      f"when the golden file was written",
+            "gpu_same_call_ms": round(t_gpu * 1e3, 2), "oracle_s": round(t_or, 2), "same_labels": same}
+    return row
 
 
 def main():
@@ -323,21 +483,7 @@ def main():
     edges = st0["lp_rated_edges"] + st0["contracted_edges"]
     value = edges / (ms_step / 1e3)
     # roofline: dominant class with algorithmic bytes
-    classes = kmp.PROF_CLASSES
-    ms_c = {c: sum(s["prof"][c]["ms"] for s in stats) for c in classes}
-    by_c = {c: sum(s["prof"][c]["bytes"] for s in stats) for c in classes}
-    ln_c = {c: sum(s["prof"][c]["launches"] for s in stats) for c in classes}
-    avg_ms = ms_c[dom] / ln_c[dom]
-    bytes_per_launch = by_c[dom] / ln_c[dom]
-    achieved = bytes_per_launch / (avg_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles(KERNEL_OF_CLASS.get(dom))
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": KERNEL_OF_CLASS.get(dom, dom), "class": dom,
-                "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": ln_c[dom] / args.steps,
-                "algorithmic_bytes_per_launch": round(bytes_per_launch),
-                "class_ms_per_step": {c: round(st_all["prof"][c]["ms"], 3) for c in classes
-                                      if st_all["prof"][c]["launches"]}}
+    roofline = roofline_of(kmp, stats, dom, st_all, WORKLOAD["name"])
     batched = None
     if not args.no_batched:
         batched = batched_comparison(kmp, gen, torch, args.batch_count, args.batch_reps)
@@ -347,6 +493,13 @@ def main():
         loads = [float(x) for x in args.serving_loads.split(",") if x]
         serving = serving_run(kmp, gen, torch, args.serving_jobs, loads, args.serving_workers,
                               args.serving_budget_gib)
+    workloads = None
+    if not args.no_workloads:
+        workloads = {}
+        for name, steps, cpu_mode in (("grid128", args.grid_steps, None if args.no_cpu_baseline else "partition"),
+                                      ("rmat22", args.rmat_steps, None if args.no_cpu_baseline else "lp0")):
+            workloads[name] = extra_workload(kmp, gen, torch, name, steps, 1, cpu_mode)
+            print(f"# workload {name}: {json.dumps(workloads[name])}", file=sys.stderr, flush=True)
     cpu = None
     parity = None
     if not args.no_cpu_baseline:
@@ -385,9 +538,10 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu,
         "e2e_edges_per_s": round(g.m / (ms_step / 1e3)),
-        "lp_plus_contraction_edges_per_step": edges, "cut": st0["cut"], "levels": st0["levels"],
+        "lp_plus_contraction_edges_per_step": edges, **phase_rates(st_all), "cut": st0["cut"],
+        "levels": st0["levels"],
         "parity_with_oracle": parity, "tuning": tuning, "batched": batched, "serving": serving,
-        "ip_options": ip_cmp,
+        "ip_options": ip_cmp, "workloads": workloads,
     }
     print(json.dumps(line), flush=True)
 

@@ -221,9 +221,12 @@ def pool_graph(key) -> Graph:
 
 
 WORKLOADS = {
-    "grid128": dict(k=8, eps=0.03, seed=1),
-    "rgg20": dict(k=64, eps=0.03, seed=1),
-    "rmat22": dict(k=1 << 15, eps=0.03, seed=1),
+    "grid128": dict(k=8, eps=0.03, seed=1, desc="grid128: 2D 5-point grid 128x128, k=8, eps=0.03, seed 1"),
+    "rgg20": dict(k=64, eps=0.03, seed=1,
+                  desc="rgg20: 2D random geometric graph, n=2^20, avg degree 8, k=64, eps=0.03, seed 1"),
+    "rmat22": dict(k=1 << 15, eps=0.03, seed=1,
+                   desc="rmat22: symmetrised RMAT, n=2^22, 2^25 generated edges (0.57, 0.19, 0.19), "
+                        "k=2^15, eps=0.03, seed 1"),
 }
 
 
