@@ -118,9 +118,14 @@ __host__ __device__ inline int64_t ggg_bytes(int64_t nv, int64_t d, bool fm)
 {
     // keys (R x padded nv) u64, entries (d) and nodes (nv + 1) as int32 pairs;
     // with FM also one int32 (side << 31 | node weight) per run and node
-    const int64_t bytes = 8 * ((int64_t)kSeeds * ggg_pad(nv) + d + nv + 1) + (fm ? 4 * (int64_t)kSeeds * ggg_pad(nv) : 0);
+    // and one int32 per node for its internal weighted degree
+    const int64_t bytes = 8 * ((int64_t)kSeeds * ggg_pad(nv) + d + nv + 1) + (fm ? 4 * (int64_t)kSeeds * ggg_pad(nv) : 0) +
+                          4 * ggg_pad(nv);
     return (bytes + 15) & ~(int64_t)15;
 }
+
+// LDS of the hybrid layout (the entries live in the global scratch)
+__host__ __device__ inline int64_t ggg_hybrid_lds(int64_t nv, bool fm) { return ggg_bytes(nv, 0, fm); }
 
 constexpr int kFmStall = 64;  // an FM pass ends after this many moves without a better prefix
 
@@ -289,9 +294,10 @@ enum { ALG_GGG = 0, ALG_BFS = 1, ALG_RND = 2 };
 
 // One growth in one wavefront (seed j); lane 0 leaves the cut and the overload.
 template <class KT, bool LDS, int ALG>
-__device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const int2* nd, const int2* ed, int j,
-                                int lane, uint32_t hj, int64_t cB, int64_t t0, int64_t cap0, int64_t cap1,
-                                int64_t* s_cut, int64_t* s_over, int32_t* sw_base, int fm_passes)
+__device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const int2* nd, const int2* ed,
+                                const int32_t* wdeg, int j, int lane, uint32_t hj, int64_t cB, int64_t t0,
+                                int64_t cap0, int64_t cap1, int64_t* s_cut, int64_t* s_over, int32_t* sw_base,
+                                int fm_passes)
 {
     using T = typename KT::T;
     static_assert(ALG != ALG_RND || sizeof(T) == 8, "random growth keys hold a 32-bit hash");
@@ -300,9 +306,7 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
         T k = 0;
         if (i < nv) {
             if constexpr (ALG == ALG_GGG) {
-                int32_t s = 0;
-                for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) s += ed[e].y;
-                k = KT::make(-s, (uint32_t)i);
+                k = KT::make(-wdeg[i], (uint32_t)i);  // gain = weight to the grown side - weight to the rest
             } else if constexpr (ALG == ALG_BFS) {
                 k = KT::make(0, (uint32_t)i);  // undiscovered
             } else {
@@ -316,6 +320,9 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
     uint32_t disc = 0;  // BFS: nodes discovered so far
     fence_wave<LDS>();
     int64_t w0 = 0;
+    // GGG keeps every unassigned node's gain in its key, and adding node v to
+    // the grown side changes the cut by -gain(v): the cut is summed on the way
+    int64_t gcut = 0;
     const int32_t nchunks = nvp / 64;
     while (w0 < t0) {
         // the largest key: lane l reads nodes l, l + 64, ... (8 loads in flight)
@@ -338,12 +345,14 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
         best = KT::wave_max(best);
         int32_t pick;
         int32_t pw, pe0, pe1;
+        int32_t pgain = 0;  // GGG: the pick's gain
         if (best >= KT::front) {
             pick = KT::id(best);
             const int src = pick & 63;
             pw = __builtin_amdgcn_readlane(ca.y, src);
             pe0 = __builtin_amdgcn_readlane(ca.x, src);
             pe1 = __builtin_amdgcn_readlane(cb.x, src);
+            if constexpr (ALG == ALG_GGG) pgain = KT::gain(best);
         } else {
             // no frontier node fits: the fitting unassigned node of smallest hash
             uint64_t hb = ~0ull;  // (hash << 32) | id ; max = none
@@ -359,6 +368,7 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
             pw = pa.y;
             pe0 = pa.x;
             pe1 = pb.x;
+            if constexpr (ALG == ALG_GGG) pgain = KT::gain(key[pick]);
         }
         if (w0 + pw > cap0) {
             // a frontier node that does not fit: drop it for the rest of the growth
@@ -368,6 +378,7 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
         }
         if (lane == 0) key[pick] = 0;
         w0 += pw;
+        gcut -= pgain;
         fence_wave<LDS>();
         if constexpr (ALG == ALG_GGG) {
             for (int32_t e = pe0 + lane; e < pe1; e += 64) {
@@ -405,7 +416,7 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
             for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e)
                 if (sw[ed[e].x] < 0) cut += ed[e].y;
         }
-    } else {
+    } else if constexpr (ALG != ALG_GGG) {
         for (int32_t i = lane; i < nv; i += 64) {
             if (key[i] != 0) continue;
             for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e)
@@ -413,15 +424,25 @@ __device__ inline void ggg_grow(void* key_base, int32_t nvp, int32_t nv, const i
         }
     }
     for (int d = 32; d > 0; d >>= 1) cut += __shfl_xor(cut, d, 64);
+    if constexpr (ALG == ALG_GGG)
+        if (fm_passes == 0) cut = gcut;
     if (lane == 0) {
         s_cut[j] = cut;
         s_over[j] = (w0 > cap0 ? w0 - cap0 : 0) + (cB - w0 > cap1 ? cB - w0 - cap1 : 0);
     }
 }
 
-template <bool LDS>
+// Where a block's working set lives: every array in LDS, or keys, node rows
+// and FM sides in LDS with the local adjacency in the global scratch (blocks
+// of many internal entries: the growth reads only the winner's row there), or
+// everything in the global scratch (blocks too large for either).
+enum { GGG_GLOBAL = 0, GGG_LDS = 1, GGG_HYBRID = 2 };
+constexpr int32_t kGggLightRow = 32;  // rows walked by one thread while a block is extracted
+
+template <int MODE>
 __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
 {
+    constexpr bool LDS = MODE != GGG_GLOBAL;  // keys and sides in LDS
     extern __shared__ __align__(16) char lds_raw[];
     __shared__ int64_t s_red[GGG_THREADS / 64];
     __shared__ int64_t s_cut[kSeeds], s_over[kSeeds];
@@ -430,6 +451,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     __shared__ bool s_take;
     __shared__ int32_t s_wmax;
     __shared__ int32_t s_carry;
+    __shared__ int32_t s_nheavy;
 
     const GGGJob job = a.jobs[blockIdx.x];
     const int32_t nv = job.nverts;
@@ -441,26 +463,78 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     uint64_t* key_all = reinterpret_cast<uint64_t*>(base);
     int2* ed = reinterpret_cast<int2*>(key_all + (int64_t)kSeeds * nvp);
     int2* nd = ed + job.dsum;
+    if (MODE == GGG_HYBRID) {
+        nd = reinterpret_cast<int2*>(key_all + (int64_t)kSeeds * nvp);
+        ed = reinterpret_cast<int2*>(a.scratch + job.scratch);
+    }
     int32_t* sw_all = reinterpret_cast<int32_t*>(nd + nv + 1);  // FM sides, R x padded nv
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 
-    // ---- internal degrees (in nd[i + 1].x) and node weights (a row's loads in groups of 8)
+    int32_t* wdeg = sw_all + (a.fm_passes > 0 ? (int64_t)kSeeds * nvp : 0);  // internal weighted degrees
+    constexpr int kWaves = GGG_THREADS / 64;
+    // ---- internal degrees (in nd[i + 1].x), internal weighted degrees and node weights.  A row
+    // of the level graph can hold 10^5 entries, most of them outside the block: rows of up to
+    // kGggLightRow entries are walked by one thread each (loads in groups of 8), longer ones are
+    // listed (in the key array, which the growths initialise later) and walked by a whole
+    // wavefront each, four 64-entry chunks in flight
+    int32_t* heavy = reinterpret_cast<int32_t*>(key_all);
+    if (tid == 0) s_nheavy = 0;
+    __syncthreads();
     int64_t cacc = 0;
     for (int32_t i = tid; i < nv; i += GGG_THREADS) {
         const int32_t v = (int32_t)vlist[i];
         const int32_t e1 = a.xadj[v + 1];
-        int32_t cnt = 0;
+        const int32_t c = a.vwgt ? a.vwgt[v] : 1;
+        nd[i].y = c;
+        cacc += c;
+        if (e1 - a.xadj[v] > kGggLightRow) {
+            heavy[atomicAdd(&s_nheavy, 1)] = i;
+            continue;
+        }
+        int32_t cnt = 0, ws = 0;
         for (int32_t e0 = a.xadj[v]; e0 < e1; e0 += 8) {
             int32_t u[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) u[q] = e0 + q < e1 ? a.adjncy[e0 + q] : -1;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) cnt += u[q] >= 0 && a.part[u[q]] == b;
+            for (int q = 0; q < 8; ++q)
+                if (u[q] >= 0 && a.part[u[q]] == b) {
+                    ++cnt;
+                    ws += a.adjwgt ? a.adjwgt[e0 + q] : 1;
+                }
         }
         nd[i + 1].x = cnt;
-        const int32_t c = a.vwgt ? a.vwgt[v] : 1;
-        nd[i].y = c;
-        cacc += c;
+        wdeg[i] = ws;
+    }
+    __syncthreads();
+    const int32_t nheavy = s_nheavy;
+    for (int32_t h = wv; h < nheavy; h += kWaves) {
+        const int32_t i = heavy[h];
+        const int32_t v = (int32_t)vlist[i];
+        const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
+        uint32_t cnt = 0, ws = 0;
+        for (int32_t base = e0; base < e1; base += 256) {
+            int32_t u[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t e = base + q * 64 + lane;
+                u[q] = e < e1 ? a.adjncy[e] : -1;
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int32_t e = base + q * 64 + lane;
+                if (u[q] >= 0 && a.part[u[q]] == b) {
+                    ++cnt;
+                    ws += a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
+                }
+            }
+        }
+        cnt = group_sum_u32<64>(cnt);
+        ws = group_sum_u32<64>(ws);
+        if (lane == 0) {
+            nd[i + 1].x = (int32_t)cnt;
+            wdeg[i] = (int32_t)ws;
+        }
     }
     for (int d = 32; d > 0; d >>= 1) cacc += __shfl_xor(cacc, d, 64);
     if (lane == 0) s_red[wv] = cacc;
@@ -491,10 +565,13 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
         if (tid == GGG_THREADS - 1) s_carry = pre + x;
         __syncthreads();
     }
-    // ---- local adjacency (ascending node id => ascending local id)
+    // ---- local adjacency (ascending node id => ascending local id): short rows by one thread
+    // each, the listed long rows by a wavefront each (the internal entries of a chunk keep their
+    // order: ballot, then the count of lower lanes)
     for (int32_t i = tid; i < nv; i += GGG_THREADS) {
         const int32_t v = (int32_t)vlist[i];
         const int32_t e1 = a.xadj[v + 1];
+        if (e1 - a.xadj[v] > kGggLightRow) continue;
         int32_t pos = nd[i].x;
         for (int32_t e0 = a.xadj[v]; e0 < e1; e0 += 8) {
             int32_t u[8], p[8], lu[8], w[8];
@@ -514,6 +591,22 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
             }
         }
     }
+    for (int32_t h = wv; h < nheavy; h += kWaves) {
+        const int32_t i = heavy[h];
+        const int32_t v = (int32_t)vlist[i];
+        const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
+        int32_t pos = nd[i].x;
+        for (int32_t base = e0; base < e1; base += 64) {
+            const int32_t e = base + lane;
+            const int32_t u = e < e1 ? a.adjncy[e] : -1;
+            const bool in = u >= 0 && a.part[u] == b;
+            int2 val = make_int2(0, 0);
+            if (in) val = make_int2(a.local[u], a.adjwgt ? a.adjwgt[e] : 1);
+            const uint64_t m = __ballot(in);
+            if (in) ed[pos + __popcll(m & ((1ull << lane) - 1))] = val;
+            pos += __popcll(m);
+        }
+    }
     __syncthreads();
 
     // ---- the key width: 32 bits when every gain fits (largest weighted degree)
@@ -521,11 +614,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     __syncthreads();
     {
         int32_t m = 0;
-        for (int32_t i = tid; i < nv; i += GGG_THREADS) {
-            int32_t sum = 0;
-            for (int32_t e = nd[i].x; e < nd[i + 1].x; ++e) sum += ed[e].y;
-            m = sum > m ? sum : m;
-        }
+        for (int32_t i = tid; i < nv; i += GGG_THREADS) m = wdeg[i] > m ? wdeg[i] : m;
         if (m) atomicMax(&s_wmax, m);
     }
     __syncthreads();
@@ -546,20 +635,20 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
         const bool use32 = k32 && alg != ALG_RND;
         if (alg == ALG_GGG) {
             if (use32)
-                ggg_grow<Key32, LDS, ALG_GGG>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut,
+                ggg_grow<Key32, LDS, ALG_GGG>(key_all, nvp, nv, nd, ed, wdeg, j, lane, hj, cB, t0, cap0, cap1, s_cut,
                                               s_over, sw_all, a.fm_passes);
             else
-                ggg_grow<Key64, LDS, ALG_GGG>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut,
+                ggg_grow<Key64, LDS, ALG_GGG>(key_all, nvp, nv, nd, ed, wdeg, j, lane, hj, cB, t0, cap0, cap1, s_cut,
                                               s_over, sw_all, a.fm_passes);
         } else if (alg == ALG_BFS) {
             if (use32)
-                ggg_grow<Key32, LDS, ALG_BFS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut,
+                ggg_grow<Key32, LDS, ALG_BFS>(key_all, nvp, nv, nd, ed, wdeg, j, lane, hj, cB, t0, cap0, cap1, s_cut,
                                               s_over, sw_all, a.fm_passes);
             else
-                ggg_grow<Key64, LDS, ALG_BFS>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut,
+                ggg_grow<Key64, LDS, ALG_BFS>(key_all, nvp, nv, nd, ed, wdeg, j, lane, hj, cB, t0, cap0, cap1, s_cut,
                                               s_over, sw_all, a.fm_passes);
         } else {
-            ggg_grow<Key64, LDS, ALG_RND>(key_all, nvp, nv, nd, ed, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over,
+            ggg_grow<Key64, LDS, ALG_RND>(key_all, nvp, nv, nd, ed, wdeg, j, lane, hj, cB, t0, cap0, cap1, s_cut, s_over,
                                           sw_all, a.fm_passes);
         }
         __syncthreads();
@@ -653,45 +742,68 @@ __global__ __launch_bounds__(kBlock) void k_block_weights(const int32_t* __restr
             if (h[i]) atomicAdd((unsigned long long*)&wt[i], h[i]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_cut(const int32_t* __restrict__ xadj, const int32_t* __restrict__ adjncy,
-                                                const int32_t* __restrict__ adjwgt, const int32_t* __restrict__ part,
-                                                int32_t n, int64_t* out)
+// Cut entries: a node's own lane walks rows of up to kCutLight entries; longer
+// rows are split into runs of kCutRun entries, appended to a list and walked by
+// whole workgroups in a second launch, so a hub of 10^5 neighbours does not
+// hold one lane for the whole kernel.  gid == NULL: one graph, the sum goes to
+// spread counters; else per job (each cut edge counted from both ends).
+constexpr int32_t kCutLight = 256;
+constexpr int32_t kCutRun = 4096;
+
+__device__ inline void cut_out(int64_t* out, const int32_t* gid, int32_t j, int64_t acc)
 {
-    __shared__ int64_t ws[kBlock / 64];
-    int64_t acc = 0;
-    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t p = part[v];
-        for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e)
-            if (part[adjncy[e]] != p) acc += adjwgt ? adjwgt[e] : 1;
-    }
-    for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
-    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t t = 0;
-        for (int q = 0; q < kBlock / 64; ++q) t += ws[q];
-        if (t) spread_add(out, t);
+    if (gid) {
+        job_add(out, j, acc);
+    } else {
+        for (int d = 32; d > 0; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if ((threadIdx.x & 63) == 0 && acc) spread_add(out, acc);
     }
 }
 
-// cut entries of every job (each cut edge counted from both ends)
-__global__ __launch_bounds__(kBlock) void k_cut_jobs(const int32_t* __restrict__ xadj,
-                                                     const int32_t* __restrict__ adjncy,
-                                                     const int32_t* __restrict__ adjwgt,
-                                                     const int32_t* __restrict__ part, const int32_t* __restrict__ gid,
-                                                     int32_t n, int64_t* out)
+__global__ __launch_bounds__(kBlock) void k_cut(const int32_t* __restrict__ xadj, const int32_t* __restrict__ adjncy,
+                                                const int32_t* __restrict__ adjwgt, const int32_t* __restrict__ part,
+                                                const int32_t* __restrict__ gid, int32_t n, int64_t* out,
+                                                int2* __restrict__ runs, int32_t* __restrict__ nruns)
 {
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < n; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t v = base + threadIdx.x;
         int64_t acc = 0;
         int32_t j = -1;
         if (v < n) {
-            j = gid[v];
-            const int32_t p = part[v];
-            for (int32_t e = xadj[v]; e < xadj[v + 1]; ++e)
-                if (part[adjncy[e]] != p) acc += adjwgt ? adjwgt[e] : 1;
+            j = gid ? gid[v] : 0;
+            const int32_t e0 = xadj[v], e1 = xadj[v + 1];
+            if (e1 - e0 <= kCutLight) {
+                const int32_t p = part[v];
+                for (int32_t e = e0; e < e1; ++e)
+                    if (part[adjncy[e]] != p) acc += adjwgt ? adjwgt[e] : 1;
+            } else {
+                const int32_t k = (e1 - e0 + kCutRun - 1) / kCutRun;
+                const int32_t at = atomicAdd(nruns, k);
+                for (int32_t q = 0; q < k; ++q) runs[at + q] = make_int2((int32_t)v, q);
+            }
         }
-        job_add(out, j, acc);
+        cut_out(out, gid, j, acc);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cut_runs(const int32_t* __restrict__ xadj,
+                                                     const int32_t* __restrict__ adjncy,
+                                                     const int32_t* __restrict__ adjwgt,
+                                                     const int32_t* __restrict__ part, const int32_t* __restrict__ gid,
+                                                     int64_t* out, const int2* __restrict__ runs,
+                                                     const int32_t* __restrict__ nruns)
+{
+    const int32_t total = *nruns;
+    for (int32_t r = blockIdx.x; r < total; r += gridDim.x) {
+        const int2 run = runs[r];
+        const int32_t v = run.x;
+        const int32_t e1 = xadj[v + 1];
+        const int32_t r0 = xadj[v] + run.y * kCutRun, r1 = r0 + kCutRun < e1 ? r0 + kCutRun : e1;
+        const int32_t p = part[v];
+        int64_t acc = 0;
+        for (int32_t e = r0 + threadIdx.x; e < r1; e += kBlock)
+            if (part[adjncy[e]] != p) acc += adjwgt ? adjwgt[e] : 1;
+        cut_out(out, gid, gid ? gid[v] : 0, acc);
     }
 }
 
@@ -733,8 +845,17 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         c.read(hbd.data(), bsd.p, sizeof(int32_t) * hbd.size());
         const int32_t* hb = hbd.data();
         const int32_t* hd = hbd.data() + nb + 1;
-        std::vector<GGGJob> lds_jobs, glob_jobs;
-        int64_t lds_max = 0, glob_total = 0;
+        // LDS launches by size class when there are more blocks than one launch at the
+        // largest size keeps resident (a launch's LDS size is its largest block's), so
+        // that blocks of small subgraphs share a CU (four 512-thread workgroups fit one
+        // CU when each takes at most 40 KiB); else one LDS launch (launches run one
+        // after the other, so splitting few blocks only serialises them); then the
+        // hybrid and the global layouts
+        constexpr int kLdsClasses = 4;
+        const int64_t lds_class_max[kLdsClasses] = {40 << 10, 53 << 10, 80 << 10, kLdsBudget};
+        std::vector<GGGJob> lds_jobs[kLdsClasses], hyb_jobs, glob_jobs;
+        int64_t lds_max[kLdsClasses] = {0, 0, 0, 0}, hyb_max = 0, scratch_total = 0;
+        const bool fm = c.fm_passes > 0;
         for (int32_t bb = 0; bb < nb; ++bb) {
             if (!split[bb]) continue;
             const int32_t jb_job = bt.job.empty() ? 0 : bt.job[bb];
@@ -749,16 +870,40 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             jb.hpre_rnd = hash_step(hash_step(hseed[jb_job], TAG_RND, 1), (uint32_t)level, 2);
             jb.scratch = 0;
             jb.lk = lk[jb_job];
-            const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum, c.fm_passes > 0);
+            const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum, fm);
+            const int64_t hbytes = ggg_hybrid_lds(jb.nverts, fm);
             if (bytes <= kLdsBudget) {
-                lds_jobs.push_back(jb);
-                if (bytes > lds_max) lds_max = bytes;
+                int q = 0;
+                while (bytes > lds_class_max[q]) ++q;
+                lds_jobs[q].push_back(jb);
+                lds_max[q] = std::max(lds_max[q], bytes);
+            } else if (hbytes <= kLdsBudget) {
+                jb.scratch = scratch_total;
+                scratch_total += ((int64_t)jb.dsum * 8 + 255) & ~(int64_t)255;
+                hyb_jobs.push_back(jb);
+                hyb_max = std::max(hyb_max, hbytes);
             } else {
-                jb.scratch = glob_total;
-                glob_total += bytes;
+                jb.scratch = scratch_total;
+                scratch_total += (bytes + 255) & ~(int64_t)255;
                 glob_jobs.push_back(jb);
             }
             ++calls;
+        }
+        {
+            size_t nl = 0;
+            int64_t mx = 0;
+            for (int q = 0; q < kLdsClasses; ++q) {
+                nl += lds_jobs[q].size();
+                mx = std::max(mx, lds_max[q]);
+            }
+            const int64_t resident = 256 * std::max<int64_t>(1, std::min<int64_t>(4, (160 << 10) / std::max<int64_t>(mx, 1)));
+            if ((int64_t)nl <= resident)
+                for (int q = 0; q + 1 < kLdsClasses; ++q) {
+                    lds_jobs[kLdsClasses - 1].insert(lds_jobs[kLdsClasses - 1].end(), lds_jobs[q].begin(),
+                                                     lds_jobs[q].end());
+                    lds_jobs[q].clear();
+                    lds_max[kLdsClasses - 1] = mx;
+                }
         }
         GGGArgs a;
         a.xadj = g.xadj;
@@ -773,24 +918,44 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         a.scratch = nullptr;
         a.fm_passes = c.fm_passes;
         a.pool = c.ip_pool ? 1 : 0;
-        if (!lds_jobs.empty()) {
-            DBuf<GGGJob> jobs(c, lds_jobs.size());
-            c.write(jobs.p, lds_jobs.data(), sizeof(GGGJob) * lds_jobs.size());
-            a.jobs = jobs.p;
-            allow_lds((const void*)k_ggg<true>, (int)kLdsBudget);  // beyond the 64 KiB default
+        DBuf<char> scratch;
+        if (scratch_total > 0) scratch = DBuf<char>(c, (size_t)scratch_total);
+        a.scratch = scratch.p;
+        // every job list of the round in one upload
+        size_t njobs_all = hyb_jobs.size() + glob_jobs.size();
+        for (int q = 0; q < kLdsClasses; ++q) njobs_all += lds_jobs[q].size();
+        std::vector<GGGJob> all;
+        all.reserve(njobs_all);
+        for (int q = 0; q < kLdsClasses; ++q) all.insert(all.end(), lds_jobs[q].begin(), lds_jobs[q].end());
+        all.insert(all.end(), hyb_jobs.begin(), hyb_jobs.end());
+        all.insert(all.end(), glob_jobs.begin(), glob_jobs.end());
+        DBuf<GGGJob> jobs(c, std::max<size_t>(all.size(), 1));
+        if (!all.empty()) c.write(jobs.p, all.data(), sizeof(GGGJob) * all.size());
+        size_t at = 0;
+        for (int q = 0; q < kLdsClasses; ++q) {
+            if (lds_jobs[q].empty()) continue;
+            a.jobs = jobs.p + at;
+            allow_lds((const void*)k_ggg<GGG_LDS>, (int)kLdsBudget);  // beyond the 64 KiB default
             ProfScope ps(c, KMP_PROF_GGG);
-            hipLaunchKernelGGL(k_ggg<true>, dim3((unsigned)lds_jobs.size()), dim3(GGG_THREADS), (size_t)lds_max,
-                               c.stream, a);
+            hipLaunchKernelGGL(k_ggg<GGG_LDS>, dim3((unsigned)lds_jobs[q].size()), dim3(GGG_THREADS),
+                               (size_t)lds_max[q], c.stream, a);
             KMP_LAUNCH_CHECK();
+            at += lds_jobs[q].size();
+        }
+        if (!hyb_jobs.empty()) {
+            a.jobs = jobs.p + at;
+            allow_lds((const void*)k_ggg<GGG_HYBRID>, (int)kLdsBudget);
+            ProfScope ps(c, KMP_PROF_GGG);
+            hipLaunchKernelGGL(k_ggg<GGG_HYBRID>, dim3((unsigned)hyb_jobs.size()), dim3(GGG_THREADS),
+                               (size_t)hyb_max, c.stream, a);
+            KMP_LAUNCH_CHECK();
+            at += hyb_jobs.size();
         }
         if (!glob_jobs.empty()) {
-            DBuf<GGGJob> jobs(c, glob_jobs.size());
-            c.write(jobs.p, glob_jobs.data(), sizeof(GGGJob) * glob_jobs.size());
-            DBuf<char> scratch(c, (size_t)glob_total);
-            a.jobs = jobs.p;
-            a.scratch = scratch.p;
+            a.jobs = jobs.p + at;
             ProfScope ps(c, KMP_PROF_GGG);
-            hipLaunchKernelGGL(k_ggg<false>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream, a);
+            hipLaunchKernelGGL(k_ggg<GGG_GLOBAL>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream,
+                               a);
             KMP_LAUNCH_CHECK();
         }
     }
@@ -857,13 +1022,28 @@ void block_weights(Ctx& c, const DGraph& g, const int32_t* part, int32_t nb, int
     KMP_LAUNCH_CHECK();
 }
 
+namespace {
+// k_cut then k_cut_runs for the long rows (their runs listed by k_cut)
+void launch_cut(Ctx& c, const DGraph& g, const int32_t* part, const int32_t* gid, int64_t* out)
+{
+    const int64_t cap = g.m / (kCutLight / 2) + 1;  // runs: rows above kCutLight entries hold < m / 128 of them
+    DBuf<int2> runs(c, (size_t)cap);
+    DBuf<int32_t> nruns(c, 1);
+    c.zero(nruns.p, sizeof(int32_t));
+    hipLaunchKernelGGL(k_cut, dim3(grid_for(g.n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
+                       g.adjwgt, part, gid, g.n, out, runs.p, nruns.p);
+    KMP_LAUNCH_CHECK();
+    hipLaunchKernelGGL(k_cut_runs, dim3(grid_for(cap, 1, 4096)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
+                       g.adjwgt, part, gid, out, runs.p, nruns.p);
+    KMP_LAUNCH_CHECK();
+}
+}  // namespace
+
 void edge_cut_launch(Ctx& c, const DGraph& g, const int32_t* part)
 {
     c.zero_spread(SP_CUT);
     if (g.n <= 0) return;
-    hipLaunchKernelGGL(k_cut, dim3(grid_for(g.n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
-                       g.adjwgt, part, g.n, c.spread(SP_CUT));
-    KMP_LAUNCH_CHECK();
+    launch_cut(c, g, part, nullptr, c.spread(SP_CUT));
 }
 
 int64_t edge_cut(Ctx& c, const DGraph& g, const int32_t* part)
@@ -880,9 +1060,7 @@ void edge_cut_jobs(Ctx& c, const DGraph& g, const int32_t* part, const int32_t* 
     if (g.n <= 0) return;
     DBuf<int64_t> d(c, (size_t)njobs);
     c.zero(d.p, sizeof(int64_t) * njobs);
-    hipLaunchKernelGGL(k_cut_jobs, dim3(grid_for(g.n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, g.adjncy,
-                       g.adjwgt, part, gid, g.n, d.p);
-    KMP_LAUNCH_CHECK();
+    launch_cut(c, g, part, gid, d.p);
     c.read(out.data(), d.p, sizeof(int64_t) * njobs);
     for (auto& x : out) x /= 2;
 }

@@ -12,7 +12,9 @@
 //   tier 1  deg <= 64    16 lanes per node, 128-slot LDS hash per node
 //   tier 2  deg <= 512   one wavefront per node, 1024-slot LDS hash
 //   tier 3  deg <= 4096  one workgroup per node, 8192-slot LDS hash
-//   tier 4  deg >  4096  one workgroup per hub, global-memory hash table
+//   tier 4  deg >  4096  global-memory hash table per hub, split into chunks
+//                         of 8192 slots: many workgroups insert a hub's entries,
+//                         many scan its table, one wave per hub picks the best
 //
 // Admission: proposals add their weight to demand[K]; targets whose whole
 // demand fits are admitted at once.  The others ("contended") are appended to
@@ -205,9 +207,10 @@ struct RateArgs {
     const int32_t* segtab;  // [kSegs offsets][kSegs counts]
     int seg;
     // hubs
-    uint32_t* hub_keys;
-    uint32_t* hub_vals;
-    const int64_t* hub_off;  // by node id
+    uint64_t* hub_tab;       // hash tables, one slot = label << 32 | rating; kEmptySlot when free
+    const int64_t* hub_off;  // by node id: first slot of the hub's table
+    int32_t* hub_plan;       // [count + 1]: first chunk of each hub of the launch's segment, then the total
+    uint32_t* hub_part;      // per chunk: the chunk's best keys and own rating (kHubPart words)
     // balance mode (over != NULL): rate the nodes of overloaded blocks only,
     // targets must be non-overloaded; write best target / gain
     const uint8_t* over;
@@ -456,17 +459,27 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             v = a.list[off + i];
             if (!node_selected(a, v)) v = -1;
         }
-        for (int j = gl; j < HS; j += G) {
+        // the node's table: the smallest power of two of at least 2 d slots (at most
+        // HS, which the tier's degree range guarantees); only those slots are cleared
+        // and scanned
+        int32_t e0 = 0, e1 = 0;
+        if (v >= 0) {
+            e0 = a.xadj[v];
+            e1 = a.xadj[v + 1];
+        }
+        int bits = 1;
+        while ((1 << bits) < 2 * (e1 - e0) && bits < HB) ++bits;
+        const int hsn = v >= 0 ? 1 << bits : 0;
+        for (int j = gl; j < hsn; j += G) {
             keys[j] = EMPTY;
             vals[j] = 0;
         }
         __syncthreads();
         if (v >= 0) {
-            const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
             for (int32_t e = e0 + gl; e < e1; e += G) {
                 uint32_t K = (uint32_t)a.label[a.adjncy[e]];
                 uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
-                lds_insert(keys, vals, HB, K, w);
+                lds_insert(keys, vals, bits, K, w);
             }
             if (gl == 0) {
                 edges += e1 - e0;
@@ -481,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             const uint32_t own = (uint32_t)a.label[v];
             const NodeKey nk = node_key(a, v);
             cv = a.vwgt ? a.vwgt[v] : 1;
-            for (int j = gl; j < HS; j += G) consider(a, nk, keys[j], vals[j], own, cv, fav, adm, rown);
+            for (int j = gl; j < hsn; j += G) consider(a, nk, keys[j], vals[j], own, cv, fav, adm, rown);
         }
         if constexpr (G <= 64) {
             fav = group_best<G>(fav);
@@ -512,59 +525,138 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
     flush_stats(a, nodes, edges);
 }
 
-// Tier 4: one workgroup per hub node, hash table in global memory.
-__global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
+// Tier 4: hubs.  Each hub has a global hash table of 2^b >= 2 d slots (64-bit
+// slots: label in the high word, summed edge weight in the low word; the sum
+// is a part of the hub's weighted degree, below 2^31, so it never carries into
+// the label).  A hub's table is split into chunks of kHubTS slots and its
+// entries into as many runs of equal length, so that a sub-round runs
+//   k_hub_plan    one workgroup: chunk offsets of the segment's rated hubs
+//   k_hub_insert  one workgroup per chunk: its run of entries into the table
+//   k_hub_scan    one workgroup per chunk: the chunk's slots rated (and freed,
+//                 so the table is empty for the next use), best keys per chunk
+//   k_hub_final   one wavefront per hub: the best over its chunks, result
+// instead of one workgroup walking the whole hub.  Every step follows the
+// same rule as the other tiers (ratings summed per label, the best admissible
+// and the favoured label by the strict key order), so the layout does not
+// change any result.
+constexpr int kHubTS = 8192;
+constexpr int kHubPart = 8;
+constexpr uint64_t kEmptySlot = 0xFFFFFFFF00000000ull;
+
+__device__ inline int hub_bits(int64_t d)
 {
-    __shared__ Key3 s_red[2][4];
-    __shared__ uint32_t s_rown[4];
+    int b = 1;
+    while ((1ll << b) < 2 * d) ++b;
+    return b;
+}
+
+__device__ inline int32_t hub_chunks_of(const RateArgs& a, int32_t v)
+{
+    if (!node_selected(a, v)) return 0;
+    const int64_t hs = 1ll << hub_bits(a.xadj[v + 1] - a.xadj[v]);
+    return (int32_t)((hs + kHubTS - 1) / kHubTS);
+}
+
+__global__ __launch_bounds__(kBlock) void k_hub_plan(RateArgs a)
+{
+    __shared__ int32_t s_wsum[kBlock / 64];
+    __shared__ int32_t s_carry;
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
-    const int tid = threadIdx.x;
-    int64_t edges = 0, nodes = 0;
-    for (int64_t i = xcd_block(); i < count; i += gridDim.x) {
-        const int32_t v = a.list[off + i];
-        if (!node_selected(a, v)) continue;  // uniform across the block
-        const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
-        const int64_t d = e1 - e0;
-        int bits = 1;
-        while ((1ll << bits) < 2 * d) ++bits;
-        const int64_t hs = 1ll << bits;
-        uint32_t* keys = a.hub_keys + a.hub_off[v];
-        uint32_t* vals = a.hub_vals + a.hub_off[v];
-        for (int64_t j = tid; j < hs; j += kBlock) {
-            keys[j] = EMPTY;
-            vals[j] = 0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    if (tid == 0) s_carry = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < count; base += kBlock) {
+        const int32_t i = base + tid;
+        const int32_t x = i < count ? hub_chunks_of(a, a.list[off + i]) : 0;
+        int32_t incl = x;  // inclusive scan within the wavefront
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t y = __shfl_up(incl, d, 64);
+            if (lane >= d) incl += y;
         }
-        // the table is global memory used by this workgroup only (one CU, one
-        // L2): a workgroup-scope fence orders the clears (and below, the
-        // atomics) before the other waves use the slots
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        if (lane == 63) s_wsum[wv] = incl;
         __syncthreads();
-        for (int32_t e = e0 + tid; e < e1; e += kBlock) {
-            uint32_t K = (uint32_t)a.label[a.adjncy[e]];
-            uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
-            const uint32_t mask = (uint32_t)(hs - 1);
-            uint32_t h = slot_of(K, bits) & mask;
+        int32_t before = s_carry;
+        for (int q = 0; q < wv; ++q) before += s_wsum[q];
+        if (i < count) a.hub_plan[i] = before + incl - x;
+        __syncthreads();
+        if (tid == kBlock - 1) s_carry = before + incl;
+        __syncthreads();
+    }
+    if (tid == 0) a.hub_plan[count] = s_carry;
+}
+
+// The hub whose chunks contain chunk ch: the last i with plan[i] <= ch.
+__device__ inline int32_t hub_of_chunk(const int32_t* plan, int32_t count, int32_t ch)
+{
+    int32_t lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (plan[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_hub_insert(RateArgs a)
+{
+    if (aborted(a)) return;
+    const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
+    const int32_t total = count > 0 ? a.hub_plan[count] : 0;
+    for (int32_t ch = xcd_block(); ch < total; ch += gridDim.x) {
+        const int32_t i = hub_of_chunk(a.hub_plan, count, ch);
+        const int32_t v = a.list[off + i];
+        const int32_t nch = a.hub_plan[i + 1] - a.hub_plan[i], j = ch - a.hub_plan[i];
+        const int64_t e0 = a.xadj[v], e1 = a.xadj[v + 1], d = e1 - e0;
+        const int bits = hub_bits(d);
+        const uint64_t mask = (1ull << bits) - 1;
+        const int64_t per = (d + nch - 1) / nch;
+        const int64_t c0 = e0 + j * per, c1 = c0 + per < e1 ? c0 + per : e1;
+        unsigned long long* tab = reinterpret_cast<unsigned long long*>(a.hub_tab + a.hub_off[v]);
+        for (int64_t e = c0 + threadIdx.x; e < c1; e += kBlock) {
+            const uint32_t K = (uint32_t)a.label[a.adjncy[e]];
+            const uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
+            const unsigned long long mine = ((unsigned long long)K << 32) | w;
+            uint64_t h = slot_of(K, bits) & mask;
             while (true) {
-                uint32_t old = atomicCAS(&keys[h], EMPTY, K);
-                if (old == EMPTY || old == K) {
-                    atomicAdd(&vals[h], w);
+                const unsigned long long old = atomicCAS(&tab[h], kEmptySlot, mine);
+                if (old == kEmptySlot) break;
+                if ((uint32_t)(old >> 32) == K) {
+                    atomicAdd(&tab[h], (unsigned long long)w);
                     break;
                 }
                 h = (h + 1) & mask;
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_hub_scan(RateArgs a)
+{
+    __shared__ Key3 s_red[2][kBlock / 64];
+    __shared__ uint32_t s_rown[kBlock / 64];
+    if (aborted(a)) return;
+    const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
+    const int32_t total = count > 0 ? a.hub_plan[count] : 0;
+    const int tid = threadIdx.x;
+    for (int32_t ch = xcd_block(); ch < total; ch += gridDim.x) {
+        const int32_t i = hub_of_chunk(a.hub_plan, count, ch);
+        const int32_t v = a.list[off + i];
+        const int32_t j = ch - a.hub_plan[i];
+        const int64_t hs = 1ll << hub_bits(a.xadj[v + 1] - a.xadj[v]);
+        const int64_t s0 = (int64_t)j * kHubTS, s1 = s0 + kHubTS < hs ? s0 + kHubTS : hs;
+        uint64_t* tab = a.hub_tab + a.hub_off[v];
         const uint32_t own = (uint32_t)a.label[v];
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
         const NodeKey nk = node_key(a, v);
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0;
-        for (int64_t j = tid; j < hs; j += kBlock) {
-            uint32_t key = __hip_atomic_load(&keys[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint32_t val = __hip_atomic_load(&vals[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            consider(a, nk, key, val, own, cv, fav, adm, rown);
+        for (int64_t q = s0 + tid; q < s1; q += kBlock) {
+            const uint64_t x = tab[q];
+            if (x != kEmptySlot) {
+                consider(a, nk, (uint32_t)(x >> 32), (uint32_t)x, own, cv, fav, adm, rown);
+                tab[q] = kEmptySlot;
+            }
         }
         fav = group_best<64>(fav);
         adm = group_best<64>(adm);
@@ -577,18 +669,55 @@ __global__ __launch_bounds__(kBlock) void k_rate_hub(RateArgs a)
         }
         __syncthreads();
         if (tid == 0) {
-            for (int q = 1; q < 4; ++q) {
+            for (int q = 1; q < kBlock / 64; ++q) {
                 if (better(s_red[0][q], fav)) fav = s_red[0][q];
                 if (better(s_red[1][q], adm)) adm = s_red[1][q];
                 rown += s_rown[q];
             }
-            write_result(a, v, fav, adm, rown, cv);
-            edges += d;
-            nodes += 1;
+            uint32_t* p = a.hub_part + (int64_t)ch * kHubPart;
+            p[0] = fav.r;
+            p[1] = fav.h;
+            p[2] = fav.k;
+            p[3] = adm.r;
+            p[4] = adm.h;
+            p[5] = adm.k;
+            p[6] = rown;
         }
         __syncthreads();
     }
-    if (tid < 64) flush_stats(a, nodes, edges);
+}
+
+__global__ __launch_bounds__(kBlock) void k_hub_final(RateArgs a)
+{
+    if (aborted(a)) return;
+    const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
+    const int lane = threadIdx.x & 63;
+    constexpr int kWaves = kBlock / 64;
+    int64_t edges = 0, nodes = 0;
+    for (int64_t i = (int64_t)xcd_block() * kWaves + (threadIdx.x >> 6); i < count;
+         i += (int64_t)gridDim.x * kWaves) {
+        const int32_t c0 = a.hub_plan[i], c1 = a.hub_plan[i + 1];
+        if (c1 == c0) continue;  // not rated in this round (uniform across the wavefront)
+        const int32_t v = a.list[off + i];
+        Key3 fav{0, 0, 0}, adm{0, 0, 0};
+        uint32_t rown = 0;
+        for (int32_t ch = c0 + lane; ch < c1; ch += 64) {
+            const uint32_t* p = a.hub_part + (int64_t)ch * kHubPart;
+            const Key3 f{p[0], p[1], p[2]}, m{p[3], p[4], p[5]};
+            if (better(f, fav)) fav = f;
+            if (better(m, adm)) adm = m;
+            rown += p[6];
+        }
+        fav = group_best<64>(fav);
+        adm = group_best<64>(adm);
+        rown = group_sum_u32<64>(rown);
+        if (lane == 0) {
+            write_result(a, v, fav, adm, rown, a.vwgt ? a.vwgt[v] : 1);
+            edges += a.xadj[v + 1] - a.xadj[v];
+            nodes += 1;
+        }
+    }
+    flush_stats(a, nodes, edges);
 }
 
 // ---------------------------------------------------------------- admission
@@ -1491,11 +1620,37 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
 
 namespace {
 
+// Hub tables of a level (every slot free), the chunk plan of one launch and
+// the per-chunk partial results; the tables return to free after every use.
+struct HubBufs {
+    DBuf<uint64_t> tab;
+    DBuf<int32_t> plan;
+    DBuf<uint32_t> part;
+};
+
+void hub_buffers(Ctx& c, const LPSchedule& sched, HubBufs& h)
+{
+    if (sched.hub_slots_total <= 0) return;
+    const int32_t nh = sched.off[kSegs] - sched.hub_start;
+    h.tab = DBuf<uint64_t>(c, (size_t)sched.hub_slots_total);
+    h.plan = DBuf<int32_t>(c, (size_t)nh + 1);
+    // chunks of all hubs: at most one per kHubTS slots of their tables, plus one per hub
+    h.part = DBuf<uint32_t>(c, (size_t)(sched.hub_slots_total / kHubTS + nh) * kHubPart);
+    fill_i64(c, reinterpret_cast<int64_t*>(h.tab.p), (int64_t)kEmptySlot, sched.hub_slots_total);
+}
+
+void set_hub_args(RateArgs& a, const HubBufs& h)
+{
+    a.hub_tab = h.tab.p;
+    a.hub_plan = h.plan.p;
+    a.hub_part = h.part.p;
+}
+
 struct LPBuffers {
     DBuf<int32_t> prop;
     DBuf<uint8_t> acc;
     DBuf<uint32_t> demand;
-    DBuf<uint32_t> hub_keys, hub_vals;
+    HubBufs hub;
     DBuf<uint8_t> mflag;           // round stamp of the last move of every node
     DBuf<uint32_t> ckeys, cvals;   // contended (target, id), unordered
     DBuf<int64_t> base;            // [nlab] weight before a target's first proposal
@@ -1504,15 +1659,12 @@ struct LPBuffers {
     DBuf<int64_t> sout;            // one-workgroup LP: moves per round, round count
 };
 
-void lp_buffers(Ctx& c, const DGraph& g, int64_t hub_slots, int32_t nlab, LPBuffers& b)
+void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule* sched, int32_t nlab, LPBuffers& b)
 {
     b.prop = DBuf<int32_t>(c, (size_t)g.n);
     b.acc = DBuf<uint8_t>(c, (size_t)g.n);
     b.demand = DBuf<uint32_t>(c, (size_t)nlab);
-    if (hub_slots > 0) {
-        b.hub_keys = DBuf<uint32_t>(c, (size_t)hub_slots);
-        b.hub_vals = DBuf<uint32_t>(c, (size_t)hub_slots);
-    }
+    if (sched) hub_buffers(c, *sched, b.hub);
     b.mflag = DBuf<uint8_t>(c, (size_t)g.n);
     b.ckeys = DBuf<uint32_t>(c, (size_t)g.n);
     b.cvals = DBuf<uint32_t>(c, (size_t)g.n);
@@ -1560,8 +1712,7 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
         a.prop = b->prop.p;
         a.demand = b->demand.p;
         a.ctl = b->ctl.p;
-        a.hub_keys = b->hub_keys.p;
-        a.hub_vals = b->hub_vals.p;
+        set_hub_args(a, b->hub);
     }
     return a;
 }
@@ -1628,9 +1779,16 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
             case 3:
                 KMP_LAUNCH_TIMED(c, cls, (k_rate_lds<256, 13>), dim3(grid_for(ub, 1, 65536)), dim3(kBlock), 0, a);
                 break;
-            default:
-                KMP_LAUNCH_TIMED(c, cls, k_rate_hub, dim3(grid_for(ub, 1, 4096)), dim3(kBlock), 0, a);
+            default: {
+                // chunks of the segment: at most one per kHubTS slots of the level's hub tables, plus one per hub
+                const int64_t chunks = sched.hub_slots_total / kHubTS + ub;
+                const dim3 cgrid(grid_for(chunks, 1, 16384));
+                KMP_LAUNCH_TIMED(c, cls, k_hub_plan, dim3(1), dim3(kBlock), 0, a);
+                KMP_LAUNCH_TIMED(c, cls, k_hub_insert, cgrid, dim3(kBlock), 0, a);
+                KMP_LAUNCH_TIMED(c, cls, k_hub_scan, cgrid, dim3(kBlock), 0, a);
+                KMP_LAUNCH_TIMED(c, cls, k_hub_final, dim3(grid_for(ub, kBlock / 64, 65536)), dim3(kBlock), 0, a);
                 break;
+            }
         }
     }
 }
@@ -1739,13 +1897,9 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
     a.over = over;
     a.bal_t = bal_t;
     a.bal_d = bal_d;
-    DBuf<uint32_t> hk, hv;
-    if (sched.hub_slots_total > 0) {
-        hk = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
-        hv = DBuf<uint32_t>(c, (size_t)sched.hub_slots_total);
-    }
-    a.hub_keys = hk.p;
-    a.hub_vals = hv.p;
+    HubBufs hb;
+    hub_buffers(c, sched, hb);
+    set_hub_args(a, hb);
     for (int32_t s = 0; s < kSub; ++s) launch_rate(c, a, sched, s, sched.order.p, sched.segtab.p, sched.cnt);
 }
 
@@ -1982,7 +2136,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     if (n == 0) return LPStats();
     if (!sched_p) {  // a small single graph: no schedule needed
         LPBuffers b;
-        lp_buffers(c, g, 0, st.nlab, b);
+        lp_buffers(c, g, nullptr, st.nlab, b);
         return lp_run_small(c, g, level, seed, st, b, {0}, {n}, {0}, {st.nlab});
     }
     const LPSchedule& sched = *sched_p;
@@ -2005,7 +2159,7 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     for (int32_t x : sc) small_nodes += x;
     const bool all_small = !ss.empty() && small_nodes == sched.off[kSegs];
     LPBuffers b;
-    lp_buffers(c, g, sched.hub_slots_total, st.nlab, b);
+    lp_buffers(c, g, &sched, st.nlab, b);
     LPStats small;
     if (!ss.empty()) {
         small = lp_run_small(c, g, level, seed, st, b, ss, sc, sl, sn);
@@ -2022,7 +2176,7 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
 {
     if (g.n == 0) return 0;
     LPBuffers b;
-    lp_buffers(c, g, sched.hub_slots_total, st.nlab, b);
+    lp_buffers(c, g, &sched, st.nlab, b);
     RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)round}), &b);
     a.level = (uint32_t)level;
     a.round = (uint32_t)round;

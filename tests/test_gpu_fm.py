@@ -82,13 +82,15 @@ def test_bipartition_round_fm(kmp, k, passes):
     _rounds(kmp, gen.rgg(4000, 8.0, 21), k, 0, 3, passes, "rgg4000")
 
 
-@pytest.mark.parametrize("name", ["weighted", "heavy", "heavy-lds-and-global", "big-edge-weights",
+@pytest.mark.parametrize("name", ["weighted", "heavy", "heavy-lds-and-global", "dense-hybrid", "big-edge-weights",
                                   "edge-above-2^30", "cliques", "tiny", "isolated", "path"])
 def test_bipartition_fm_weighted_and_degenerate(kmp, name):
     g, k = {
         "weighted": lambda: (gen.random_graph(900, 5.0, 31, max_vw=20, max_ew=5), 7),
         "heavy": lambda: (_heavy_nodes(300, 33), 4),
         "heavy-lds-and-global": lambda: (_heavy_nodes(3000, 35), 6),
+        # many internal entries per block: keys in LDS, entries in global memory (then LDS as blocks shrink)
+        "dense-hybrid": lambda: (gen.random_graph(1200, 48.0, 38, max_ew=3), 5),
         # weighted degrees beyond 2^19: the 64-bit keys inside LDS-sized blocks
         "big-edge-weights": lambda: (gen.random_graph(400, 5.0, 36, max_ew=300000), 4),
         "edge-above-2^30": lambda: (_one_huge_edge(400, 37), 4),
@@ -154,12 +156,14 @@ def test_bipartition_round_pool(kmp, k, passes):
     _rounds(kmp, gen.rgg(4000, 8.0, 21), k, 0, 3, passes, "rgg4000", pool=True)
 
 
-@pytest.mark.parametrize("name", ["weighted", "heavy-lds-and-global", "big-edge-weights", "heavy-30", "isolated",
-                                  "path"])
+@pytest.mark.parametrize("name", ["weighted", "heavy-lds-and-global", "dense-hybrid", "big-edge-weights", "heavy-30",
+                                  "isolated", "path"])
 def test_bipartition_pool_weighted_and_degenerate(kmp, name):
     g, k = {
         "weighted": lambda: (gen.random_graph(900, 5.0, 31, max_vw=20, max_ew=5), 7),
         "heavy-lds-and-global": lambda: (_heavy_nodes(3000, 35), 6),
+        # many internal entries per block: keys in LDS, entries in global memory (then LDS as blocks shrink)
+        "dense-hybrid": lambda: (gen.random_graph(1200, 48.0, 38, max_ew=3), 5),
         "big-edge-weights": lambda: (gen.random_graph(400, 5.0, 36, max_ew=300000), 4),
         # node weights up to 30
         "heavy-30": lambda: (gen.random_graph(600, 3.0, 37, max_vw=30, max_ew=3), 8),

@@ -209,6 +209,8 @@ def test_bipartition_weighted_and_degenerate(kmp):
         ("weighted", gen.random_graph(900, 5.0, 31, max_vw=20, max_ew=5), 7),
         ("heavy", _heavy_nodes(300, 33), 4),
         ("heavy-lds-and-global", _heavy_nodes(3000, 35), 6),
+        # many internal entries per block: keys in LDS, entries in global memory (then LDS as blocks shrink)
+        ("dense-hybrid", gen.random_graph(1200, 48.0, 38, max_ew=3), 5),
         ("cliques", csr_from_dense(two_cliques(40)), 2),
         ("tiny", gen.grid(1, 3), 8),
         ("isolated", gen.random_graph(500, 1.0, 32, isolated_frac=0.6), 4),
