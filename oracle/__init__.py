@@ -91,13 +91,15 @@ def _load():
             "or_step_contract": (ctypes.c_int, [i32, P32, P32, P32, P32, P32, P32, P32, P64, P32, P32, P32,
                                                 P32]),
             "or_step_bipartition_round": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, P32, P32, P32, P32,
-                                                         i64, u64, i32, i32]),
+                                                         i64, u64, i32, i32, i64, i32, i64]),
             "or_ggg": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, i32, i32]),
             "or_fm2_stall": (ctypes.c_int, [i32, P32, P32, P32, P32, PU8, i64, i64, i32, i32, P64]),
             "or_step_balance": (i32, [i32, P32, P32, P32, P32, i32, u64, P32, P64, i32, P64]),
             "or_step_cut": (i64, [i32, P32, P32, P32, P32]),
             "or_ggg_traced": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, P32,
-                                             P32, P32, i32, i32]),
+                                             P32, P32, i32, i32, i64, i64]),
+            "or_eps_root": (u64, [u64, i32]),
+            "or_adaptive_caps": (None, [i64, i32, i64, i64, i32, P64, P64]),
             "or_rg_cmp": (ctypes.c_int, [i64, i64, i64, i64]),
             "or_step_lp_subround": (i64, [i32, P32, P32, P32, P32, i32, i32, i32, u32, u64, P32, P64, i32, P64,
                                           i64, PU8, PU32, PU8]),
@@ -172,8 +174,16 @@ class Result:
     trace: Dict[Tuple[str, int], np.ndarray] = field(default_factory=dict)
 
 
+IP_POOL, IP_ADAPTIVE = 1, 2
+
+
+def _ipflags(pool, adaptive_eps):
+    return (IP_POOL if pool else 0) | (IP_ADAPTIVE if adaptive_eps else 0)
+
+
 def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
-              validate_input: bool = True, fm_passes: int = 0, pool: bool = False) -> Result:
+              validate_input: bool = True, fm_passes: int = 0, pool: bool = False,
+              adaptive_eps: bool = False) -> Result:
     lib = _load()
     xadj, adjncy = _i32(g.xadj), _i32(g.adjncy)
     vw = None if g.vwgt is None else _i32(g.vwgt)
@@ -189,7 +199,8 @@ def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
 
     cb = TRACE_FN(_cb) if trace else TRACE_FN()
     rc = lib.or_partition_traced(g.n, _p(xadj), _p(adjncy), _p(vw), _p(ew), k, eps, seed & (2**64 - 1),
-                                 _p(out), ctypes.byref(st), int(validate_input), cb, None, int(fm_passes), int(pool))
+                                 _p(out), ctypes.byref(st), int(validate_input), cb, None, int(fm_passes),
+                                 _ipflags(pool, adaptive_eps))
     L = st.levels
     stats = dict(cut=st.cut, levels=L, level_n=list(st.level_n[:L + 1]), level_m=list(st.level_m[:L + 1]),
                  bipartitions=st.bipartitions, balance_rounds=st.balance_rounds,
@@ -257,7 +268,8 @@ def contract(g, label):
 
 
 def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, fm_passes: int = 0,
-                      pool: bool = False):
+                      pool: bool = False, adaptive: Optional[Tuple[int, int, float]] = None):
+    """O7 round; `adaptive` = (c(V), k, eps) bounds each side by the adaptive imbalance (O8d)."""
     vw, ew = _weights(g)
     part = _i32(part).copy()
     nb = ctypes.c_int32(len(first))
@@ -267,7 +279,10 @@ def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, f
     fa[:len(first)] = first
     fc[:len(first)] = fcount
     rc = _load().or_step_bipartition_round(g.n, _p(_i32(g.xadj)), _p(_i32(g.adjncy)), _p(vw), _p(ew), level,
-                                           _p(part), ctypes.byref(nb), _p(fa), _p(fc), lk_, seed, int(fm_passes), int(pool))
+                                           _p(part), ctypes.byref(nb), _p(fa), _p(fc), lk_, seed, int(fm_passes),
+                                           _ipflags(pool, adaptive is not None),
+                                           adaptive[0] if adaptive else 0, adaptive[1] if adaptive else 1,
+                                           eps_ppm(adaptive[2]) if adaptive else 0)
     if rc != 0:
         raise RuntimeError(f"oracle bipartition failed: {rc}")
     q = nb.value
@@ -275,7 +290,7 @@ def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, f
 
 
 def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bool = False, fm_passes: int = 0,
-        pool: bool = False):
+        pool: bool = False, caps: Optional[Tuple[int, int]] = None):
     """O8 (with O8b when fm_passes > 0, O8c when pool) on a subgraph given in local ids; returns (side, cut)
     or (side, cut, growth order of the kept run, index q = algorithm * R + j of the kept run)."""
     vw, ew = _weights(sub)
@@ -286,7 +301,8 @@ def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bo
     jbest = ctypes.c_int32(-1)
     rc = _load().or_ggg_traced(sub.n, _p(_i32(sub.xadj)), _p(_i32(sub.adjncy)), _p(ew), _p(vw), level, first, f,
                                lk_, seed, _p(side, PU8), ctypes.byref(cut), _p(order), ctypes.byref(norder),
-                               ctypes.byref(jbest), int(fm_passes), int(pool))
+                               ctypes.byref(jbest), int(fm_passes), int(pool), -1 if caps is None else caps[0],
+                               -1 if caps is None else caps[1])
     if rc != 0:
         raise RuntimeError(f"oracle ggg failed: {rc}")
     if with_order:
@@ -310,6 +326,18 @@ def fm2(sub, side, cap0: int, cap1: int, passes: int, stall: int = FM_STALL):
     if rc != 0:
         raise RuntimeError(f"oracle fm2 failed: {rc}")
     return sd[:sub.n], int(dec.value)
+
+
+def eps_root(x: int, r: int) -> int:
+    """O8d: the largest q with P_r(q) <= x (2^32-scaled r-th root of x / 2^32)."""
+    return int(_load().or_eps_root(x, r))
+
+
+def adaptive_caps(cV: int, k: int, eps: float, cB: int, f: int) -> Tuple[int, int]:
+    """O8d: caps of the two sides of a block of weight cB and final count f."""
+    c0, c1 = ctypes.c_int64(0), ctypes.c_int64(0)
+    _load().or_adaptive_caps(cV, k, eps_ppm(eps), cB, f, ctypes.byref(c0), ctypes.byref(c1))
+    return int(c0.value), int(c1.value)
 
 
 def rg_cmp(d1: int, c1: int, d2: int, c2: int) -> int:

@@ -24,6 +24,8 @@
  *   O8  greedy graph growing, R seeds, best cut      (Sec. 5.2, Alg. 2)
  *   O8b 2-way FM refinement of each growth (optional) (Sec. 5.2 "Initial Bipartitioning")
  *   O8c pool: BFS and random runs beside GGG (optional) (Sec. 5.2 "Initial Bipartitioning")
+ *   O8d adaptive imbalance of a bipartition (optional)  (Sec. 2 "Maintaining the Balance
+ *       Constraint", Alg. 2, Sec. 5.2 bound L_2)
  *   O9  k-way balancer by relative gain              (Sec. 5.3 "Balancing")
  *   O10 driver                                       (Alg. 1, Sec. 4)
  *   O11 edge cut                                     (Sec. 2 "Notation and Definitions")
@@ -51,6 +53,8 @@
 #define OR_NONE 0xFFFFFFFFu
 #define OR_PHI 0x9E3779B9u
 enum { T_SUB = 1, T_CL = 2, T_REF = 3, T_BAL = 4, T_GGG = 5, T_BFS = 6, T_RND = 7 };
+/* initial-bipartitioning options (bit flags): the pool of O8c, the adaptive caps of O8d */
+enum { OR_IP_POOL = 1, OR_IP_ADAPTIVE = 2, OR_IP_ALL = 3 };
 
 /* status codes */
 #define OR_OK 0
@@ -710,14 +714,15 @@ int or_fm2(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t
 int or_ggg_traced(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt,
                   const int32_t* vwgt, int32_t level, int32_t first, int32_t f, int64_t lk, uint64_t seed,
                   uint8_t* side, int64_t* cut_out, int32_t* order_out, int32_t* norder_out, int32_t* jbest_out,
-                  int32_t fm_passes, int32_t pool)
+                  int32_t fm_passes, int32_t pool, int64_t cap0_in, int64_t cap1_in)
 {
     if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS || pool < 0 || pool > 1) return OR_EINVAL;
     int32_t f0 = f / 2, f1 = f - f0;
     int64_t cB = 0;
     for (int32_t v = 0; v < nb; ++v) cB += vwgt[v];
     int64_t t0 = cB * f0 / f;
-    int64_t cap0 = (int64_t)f0 * lk, cap1 = (int64_t)f1 * lk;
+    /* caps of the two sides: f_j L_k (invariant (B)), or the given ones (O8d) */
+    int64_t cap0 = cap0_in >= 0 ? cap0_in : (int64_t)f0 * lk, cap1 = cap1_in >= 0 ? cap1_in : (int64_t)f1 * lk;
     int64_t* gain = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nb > 0 ? nb : 1));
     uint8_t* st = (uint8_t*)malloc((size_t)(nb > 0 ? nb : 1)); /* 0 free, 1 frontier, 2 in block 0 */
     uint8_t* bestst = (uint8_t*)malloc((size_t)(nb > 0 ? nb : 1)); /* side of the kept run */
@@ -836,7 +841,76 @@ int or_ggg(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t
            int32_t fm_passes, int32_t pool)
 {
     return or_ggg_traced(nb, xadj, adjncy, adjwgt, vwgt, level, first, f, lk, seed, side, cut_out, NULL, NULL,
-                         NULL, fm_passes, pool);
+                         NULL, fm_passes, pool, -1, -1);
+}
+
+/* ---------------- O8d: adaptive imbalance -----------------------------
+ * Sec. 2 ("Maintaining the Balance Constraint") and Alg. 2 bipartition a
+ * subgraph V' that is to end as k' blocks with the imbalance
+ *     eps' = ((1 + eps) (c(V) / k) (k' / c(V')))^(1 / ceil(log2 k')) - 1
+ * and Sec. 5.2 bounds a side of the bipartition by L_2 = (1 + eps') ceil(c(V') / 2).
+ * Reading for general k (a block B with final count f splits into f0 =
+ * floor(f / 2) and f1 = f - f0): k' = f, c(V') = c(B), and side j is bounded by
+ * (1 + eps') ceil(c(B) f_j / f), which is L_2 when f is even.  In integers:
+ *   X  = floor(2^32 (PPM + e) c(V) f / (PPM k c(B)))      (2^32 (1 + eps')^r, exact floor)
+ *   r  = ceil(log2 f)
+ *   P(q) = q^r / 2^(32 (r - 1)) evaluated as r steps p <- floor(p q / 2^32) from p = 2^32
+ *   rho = the largest q with P(q) <= X                     (2^32 (1 + eps'), fixed point)
+ *   cap_j = floor(rho ceil(c(B) f_j / f) / 2^32)
+ * P is monotone in q, so rho is unique (found here by bisection).  When
+ * (1 + eps')^r >= 2^32 the sides are unbounded (cap 2^62); an empty block
+ * gets caps 0.                                                              */
+#define OR_CAP_INF ((int64_t)1 << 62)
+
+typedef unsigned __int128 or_u128;
+
+/* P(q) <= x, stepping p <- floor(p q / 2^32) r times from p = 2^32 (x < 2^64, q < 2^64).
+ * For q >= 2^32 p never decreases, so a step above x decides (and keeps p q
+ * below 2^128); for q < 2^32 p never exceeds 2^32.                          */
+static int root_fits(uint64_t q, int32_t r, uint64_t x)
+{
+    or_u128 p = (or_u128)1 << 32;
+    for (int32_t i = 0; i < r; ++i) {
+        p = (p * q) >> 32;
+        if (q >= ((uint64_t)1 << 32) && p > x) return 0;
+    }
+    return p <= x;
+}
+
+uint64_t or_eps_root(uint64_t x, int32_t r)
+{
+    /* the largest q in [0, 2^64) with P(q) <= x; P(0) = 0 <= x */
+    uint64_t lo = 0, hi = ~(uint64_t)0;
+    if (root_fits(hi, r, x)) return hi;
+    while (hi - lo > 1) { /* invariant: fits(lo), !fits(hi) */
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (root_fits(mid, r, x)) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+void or_adaptive_caps(int64_t cV, int32_t k, int64_t e, int64_t cB, int32_t f, int64_t* cap0, int64_t* cap1)
+{
+    int32_t f0 = f / 2, f1 = f - f0;
+    if (cB <= 0) {
+        *cap0 = *cap1 = 0;
+        return;
+    }
+    int32_t r = 0;
+    while (((int64_t)1 << r) < f) ++r; /* ceil(log2 f), f >= 2 */
+    or_u128 num = ((or_u128)1 << 32) * (or_u128)(OR_PPM + e) * (or_u128)cV * (or_u128)f;
+    or_u128 den = (or_u128)OR_PPM * (or_u128)k * (or_u128)cB;
+    or_u128 x = num / den;
+    if (x >> 64) {
+        *cap0 = *cap1 = OR_CAP_INF;
+        return;
+    }
+    uint64_t rho = or_eps_root((uint64_t)x, r);
+    int64_t t0 = (cB * f0 + f - 1) / f, t1 = (cB * f1 + f - 1) / f; /* ceil(c(B) f_j / f) */
+    or_u128 c0 = ((or_u128)rho * (or_u128)t0) >> 32, c1 = ((or_u128)rho * (or_u128)t1) >> 32;
+    *cap0 = c0 > (or_u128)OR_CAP_INF ? OR_CAP_INF : (int64_t)c0;
+    *cap1 = c1 > (or_u128)OR_CAP_INF ? OR_CAP_INF : (int64_t)c1;
 }
 
 /* ---------------- O6/O7: block table and bipartitionBlocks --------------
@@ -846,8 +920,9 @@ int or_ggg(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t
  * Blocks are kept sorted by 'first' (first final block id).               */
 int or_bipartition_round(const or_graph* g, int32_t level, int32_t* part, int32_t* nblocks, int32_t* first,
                          int32_t* fcount, int64_t lk, uint64_t seed, int32_t* ncalls, int32_t fm_passes,
-                         int32_t pool)
+                         int32_t ipflags, int64_t cV, int32_t k, int64_t e)
 {
+    const int32_t pool = (ipflags & OR_IP_POOL) != 0;
     int32_t n = g->n, nb = *nblocks;
     int32_t* local = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
     int32_t* bstart = (int32_t*)calloc((size_t)nb + 1, sizeof(int32_t));
@@ -891,7 +966,14 @@ int or_bipartition_round(const or_graph* g, int32_t level, int32_t* part, int32_
             }
             sx[i + 1] = pos;
         }
-        int rc = or_ggg(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, NULL, fm_passes, pool);
+        int64_t cap0 = -1, cap1 = -1;
+        if (ipflags & OR_IP_ADAPTIVE) {
+            int64_t cB = 0;
+            for (int32_t i = 0; i < cnt; ++i) cB += svw[i];
+            or_adaptive_caps(cV, k, e, cB, fcount[b], &cap0, &cap1);
+        }
+        int rc = or_ggg_traced(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, NULL, NULL, NULL,
+                               NULL, fm_passes, pool, cap0, cap1);
         if (rc != OR_OK) return rc;
         if (ncalls) (*ncalls)++;
         for (int32_t i = 0; i < cnt; ++i) sidev[verts[bstart[b] + i]] = side[i];
@@ -1112,11 +1194,11 @@ static void trace(or_trace_fn fn, void* user, int32_t phase, int32_t level, cons
 int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                         const int32_t* adjwgt, int32_t k, double eps, uint64_t seed, int32_t* out_part,
                         or_stats* st, int validate, or_trace_fn tfn, void* tuser, int32_t fm_passes,
-                        int32_t pool)
+                        int32_t ipflags)
 {
     if (st) memset(st, 0, sizeof(*st));
     if (n < 0 || k < 1 || !(eps >= 0.0) || eps > 1000.0) return OR_EINVAL;
-    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS || pool < 0 || pool > 1) return OR_EINVAL;
+    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS || ipflags < 0 || (ipflags & ~OR_IP_ALL)) return OR_EINVAL;
     if (n == 0) return OR_OK;
     if (!xadj || (xadj[n] > 0 && !adjncy) || !out_part) return OR_EINVAL;
     if (validate) {
@@ -1222,7 +1304,7 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
         if (kp < 2) kp = 2;
         while (nb < kp) {
             int32_t calls = 0;
-            rc = or_bipartition_round(g, l, part, &nb, first, fcount, lk, seed, &calls, fm_passes, pool);
+            rc = or_bipartition_round(g, l, part, &nb, first, fcount, lk, seed, &calls, fm_passes, ipflags, cV, k, e);
             if (rc != OR_OK) return rc;
             if (st) st->bipartitions += calls;
         }
@@ -1336,10 +1418,12 @@ int or_step_contract(int32_t n, const int32_t* xadj, const int32_t* adjncy, cons
 int or_step_bipartition_round(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                               const int32_t* adjwgt, int32_t level, int32_t* part, int32_t* nblocks,
                               int32_t* first, int32_t* fcount, int64_t lk, uint64_t seed, int32_t fm_passes,
-                              int32_t pool)
+                              int32_t ipflags, int64_t cV, int32_t k, int64_t e)
 {
+    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS || ipflags < 0 || (ipflags & ~OR_IP_ALL)) return OR_EINVAL;
     or_graph g = view(n, xadj, adjncy, vwgt, adjwgt);
-    return or_bipartition_round(&g, level, part, nblocks, first, fcount, lk, seed, NULL, fm_passes, pool);
+    return or_bipartition_round(&g, level, part, nblocks, first, fcount, lk, seed, NULL, fm_passes, ipflags, cV, k,
+                                e);
 }
 
 int32_t or_step_balance(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
