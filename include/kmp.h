@@ -89,6 +89,14 @@ typedef struct kmp_options {
                                same caps (and each refined when fm_passes > 0); the lowest (overload, cut)
                                is kept, the first of equal runs in the order GGG, BFS, random.  0: GGG
                                only (the default); other values: KMP_EINVAL.  The output depends on it. */
+    int32_t adaptive_eps;   /* 1: every bipartition bounds its sides by the adaptive imbalance of paper
+                               Sec. 2 / Alg. 2 (the L_2 bound of Sec. 5.2): a block B that is to end as f
+                               blocks is split with eps' = ((1 + eps) c(V) f / (k c(B)))^(1/ceil(log2 f)) - 1
+                               and side j (f_j = floor(f/2) or ceil(f/2) blocks) bounded by
+                               (1 + eps') ceil(c(B) f_j / f), evaluated exactly in integers (2^32 fixed
+                               point: the largest q whose r-fold stepwise-floored power p <- p q / 2^32
+                               stays within floor(2^32 (1 + eps')^r)).  0: sides bounded by f_j L_k (the
+                               default); other values: KMP_EINVAL.  The output depends on it. */
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */
@@ -286,7 +294,7 @@ void kmp_server_destroy(kmp_server* server);
 
 /*
  * kmp_server_set_options: the initial-bipartitioning options (fm_passes,
- * ip_pool; meaning and ranges as in kmp_options) for every job submitted
+ * ip_pool, adaptive_eps; meaning and ranges as in kmp_options) for every job submitted
  * after the call (a job keeps the options current at its submission; only
  * jobs with equal options share a batch); the other fields of *opt are
  * ignored.  opt == NULL restores the defaults.  Out-of-range values give

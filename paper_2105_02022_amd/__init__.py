@@ -32,7 +32,7 @@ PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "
 class KmpOptions(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
                 ("force_exact", ctypes.c_int32), ("small_level_n", ctypes.c_int32), ("plain_loads", ctypes.c_int32),
-                ("fm_passes", ctypes.c_int32), ("ip_pool", ctypes.c_int32)]
+                ("fm_passes", ctypes.c_int32), ("ip_pool", ctypes.c_int32), ("adaptive_eps", ctypes.c_int32)]
 
 
 class KmpStats(ctypes.Structure):
@@ -224,13 +224,15 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
                      stream=None, validate: bool = False, profile: bool = False,
                      profile_classes=None, force_exact: bool = False,
                      small_level_n: int = 0, plain_loads: bool = False,
-                     fm_passes: int = 0, ip_pool: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+                     fm_passes: int = 0, ip_pool: bool = False,
+                     adaptive_eps: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
     (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path.
     `small_level_n`: largest level run by the one-workgroup LP (0 default, -1 never).
     `plain_loads`: the lane rating kernel gathers with plain loads (the buffer-load path is the default).
     `fm_passes`: 2-way FM passes after every greedy growth (0..16; 0 = none).
-    `ip_pool`: the initial bipartitioning also runs BFS and random growths."""
+    `ip_pool`: the initial bipartitioning also runs BFS and random growths.
+    `adaptive_eps`: bipartitions bound their sides by the adaptive imbalance (paper Sec. 2, Alg. 2)."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -244,6 +246,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt.plain_loads = int(plain_loads)
     opt.fm_passes = int(fm_passes)
     opt.ip_pool = int(ip_pool)
+    opt.adaptive_eps = int(adaptive_eps)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -256,7 +259,8 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
 
 def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
                           stream=None, validate: bool = False, force_exact: bool = False, small_level_n: int = 0,
-                          fm_passes: int = 0, ip_pool: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+                          fm_passes: int = 0, ip_pool: bool = False,
+                          adaptive_eps: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """kmp_partition_noalloc: as kmp_partition_ex, with every device buffer inside the library's fixed
     scratch region (n <= NOALLOC_MAX_N, m <= NOALLOC_MAX_M, else KMP_ETOOLARGE).  `out` should be
     given by callers that must not allocate."""
@@ -271,6 +275,7 @@ def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0
     opt.small_level_n = int(small_level_n)
     opt.fm_passes = int(fm_passes)
     opt.ip_pool = int(ip_pool)
+    opt.adaptive_eps = int(adaptive_eps)
     st = KmpStats()
     rc = library().kmp_partition_noalloc(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
                                          epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream),
@@ -293,7 +298,8 @@ def _stats_dict(st: "KmpStats", profile: bool) -> Dict:
 def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool = False,
                         profile_classes=None, force_exact: bool = False,
                         small_level_n: int = 0, plain_loads: bool = False,
-                        fm_passes: int = 0, ip_pool: bool = False) -> Tuple[int, List[Dict], Dict]:
+                        fm_passes: int = 0, ip_pool: bool = False,
+                        adaptive_eps: bool = False) -> Tuple[int, List[Dict], Dict]:
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
@@ -309,6 +315,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     opt.plain_loads = int(plain_loads)
     opt.fm_passes = int(fm_passes)
     opt.ip_pool = int(ip_pool)
+    opt.adaptive_eps = int(adaptive_eps)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -367,11 +374,12 @@ class Server:
         out["latency_ms"] = lat.value
         return out
 
-    def set_options(self, fm_passes: int = 0, ip_pool: bool = False) -> int:
-        """Initial-bipartitioning options for batches formed from now on (kmp_server_set_options)."""
+    def set_options(self, fm_passes: int = 0, ip_pool: bool = False, adaptive_eps: bool = False) -> int:
+        """Initial-bipartitioning options for jobs submitted from now on (kmp_server_set_options)."""
         o = KmpOptions()
         o.fm_passes = int(fm_passes)
         o.ip_pool = int(ip_pool)
+        o.adaptive_eps = int(adaptive_eps)
         return library().kmp_server_set_options(self._h, ctypes.byref(o))
 
     def poll(self, jid: int) -> Optional[Dict]:

@@ -14,6 +14,8 @@
 // packed 64-bit key per node (frontier flag, gain, id) and one wave maximum.
 #include <mutex>
 
+#include <cmath>
+
 #include "kmp_dev.h"
 
 namespace kmp {
@@ -76,6 +78,7 @@ struct GGGJob {
     uint32_t hpre_rnd;
     int64_t scratch;   // byte offset into the global scratch (global variant)
     int64_t lk;        // L_k of the block's job
+    int64_t cap0, cap1;  // bounds of the two sides (f_j L_k, or the adaptive imbalance's)
 };
 
 struct GGGArgs {
@@ -623,7 +626,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     // ---- one growth per wavefront
     const int32_t f = job.f, f0 = f / 2, f1 = f - f0;
     const int64_t t0 = cB * f0 / f;
-    const int64_t cap0 = (int64_t)f0 * job.lk, cap1 = (int64_t)f1 * job.lk;
+    const int64_t cap0 = job.cap0, cap1 = job.cap1;
     const int j = wv;
     // phases: the R GGG growths, then (pool) R BFS and R random growths; a phase's best run
     // replaces the kept one only if it is strictly better, so the first of equal runs is kept
@@ -813,9 +816,84 @@ constexpr int64_t kLdsBudget = 144 * 1024;
 
 }  // namespace
 
+// ---------------------------------------------------------------- adaptive imbalance
+// Paper Sec. 2 / Alg. 2: a block that is to end as f blocks is bisected with
+// eps' = ((1 + eps) c(V) f / (k c(B)))^(1/r) - 1, r = ceil(log2 f); side j is
+// bounded by (1 + eps') ceil(c(B) f_j / f) (Sec. 5.2's L_2 for even f).  In
+// 2^32 fixed point: x = floor(2^32 (1 + eps')^r) exactly, and 2^32 (1 + eps')
+// is the largest q whose power, taken in r steps p <- floor(p q / 2^32) from
+// p = 2^32, stays within x.  The search starts at a floating-point estimate
+// and settles on that q with exact integer comparisons only (the estimate
+// never decides the result).
+namespace {
+using u128 = unsigned __int128;
+constexpr int64_t kCapInf = int64_t(1) << 62;
+
+bool fixed_pow_within(uint64_t q, int r, uint64_t x)
+{
+    const bool grows = q >= (uint64_t(1) << 32);  // then p never decreases and p q stays below 2^128
+    u128 p = u128(1) << 32;
+    for (int i = 0; i < r; ++i) {
+        p = (p * q) >> 32;
+        if (grows && p > x) return false;
+    }
+    return p <= x;
+}
+
+uint64_t fixed_root(uint64_t x, int r)
+{
+    const long double est = std::pow((long double)x / 4294967296.0L, 1.0L / (long double)r) * 4294967296.0L;
+    uint64_t q = !(est > 0) ? 0 : est >= 1.8e19L ? ~uint64_t(0) : (uint64_t)est;
+    if (fixed_pow_within(q, r, x)) {
+        // gallop up while q + step still fits, then halve the step
+        uint64_t step = 1;
+        while (step && q <= ~uint64_t(0) - step && fixed_pow_within(q + step, r, x)) {
+            q += step;
+            step <<= 1;
+        }
+        for (; step; step >>= 1)
+            if (q <= ~uint64_t(0) - step && fixed_pow_within(q + step, r, x)) q += step;
+    } else {
+        // gallop down until q - step fits, then climb back by halving steps
+        uint64_t step = 1;
+        while (q >= step && !fixed_pow_within(q - step, r, x)) step <<= 1;
+        uint64_t lo = q >= step ? q - step : 0;  // fits (P(0) = 0)
+        for (uint64_t s2 = step >> 1; s2; s2 >>= 1)
+            if (fixed_pow_within(lo + s2, r, x)) lo += s2;
+        q = lo;
+    }
+    return q;
+}
+}  // namespace
+
+void adaptive_side_caps(const AdaptiveJob& j, int64_t cB, int32_t f, int64_t& cap0, int64_t& cap1)
+{
+    if (cB <= 0) {
+        cap0 = cap1 = 0;
+        return;
+    }
+    int r = 1;
+    while ((int64_t(1) << r) < f) ++r;
+    const u128 x = (u128(1) << 32) * u128(kPPM + j.e) * u128(j.cV) * u128(f) / (u128(kPPM) * u128(j.k) * u128(cB));
+    if (x >> 64) {
+        cap0 = cap1 = kCapInf;
+        return;
+    }
+    const uint64_t rho = fixed_root((uint64_t)x, r);
+    const int32_t f0 = f / 2;
+    const int64_t share[2] = {(cB * f0 + f - 1) / f, (cB * (f - f0) + f - 1) / f};
+    int64_t caps[2];
+    for (int s2 = 0; s2 < 2; ++s2) {
+        const u128 cap = (u128(rho) * u128(share[s2])) >> 32;
+        caps[s2] = cap > u128(kCapInf) ? kCapInf : (int64_t)cap;
+    }
+    cap0 = caps[0];
+    cap1 = caps[1];
+}
+
 int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, BlockTab& bt,
                           const std::vector<uint8_t>& split, const std::vector<int64_t>& lk,
-                          const std::vector<uint32_t>& hseed)
+                          const std::vector<uint32_t>& hseed, const std::vector<AdaptiveJob>* adapt)
 {
     const int32_t n = g.n;
     const int32_t nb = bt.size();
@@ -843,6 +921,13 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         KMP_LAUNCH_CHECK();
         std::vector<int32_t> hbd(2 * (size_t)nb + 1);
         c.read(hbd.data(), bsd.p, sizeof(int32_t) * hbd.size());
+        std::vector<int64_t> hbw;  // block weights, for the adaptive caps
+        if (adapt) {
+            DBuf<int64_t> bw(c, (size_t)nb);
+            block_weights(c, g, part, nb, bw.p);
+            hbw.resize(nb);
+            c.read(hbw.data(), bw.p, sizeof(int64_t) * nb);
+        }
         const int32_t* hb = hbd.data();
         const int32_t* hd = hbd.data() + nb + 1;
         // LDS launches by size class when there are more blocks than one launch at the
@@ -870,6 +955,9 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             jb.hpre_rnd = hash_step(hash_step(hseed[jb_job], TAG_RND, 1), (uint32_t)level, 2);
             jb.scratch = 0;
             jb.lk = lk[jb_job];
+            jb.cap0 = (int64_t)(jb.f / 2) * jb.lk;
+            jb.cap1 = (int64_t)(jb.f - jb.f / 2) * jb.lk;
+            if (adapt) adaptive_side_caps((*adapt)[jb_job], hbw[bb], jb.f, jb.cap0, jb.cap1);
             const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum, fm);
             const int64_t hbytes = ggg_hybrid_lds(jb.nverts, fm);
             if (bytes <= kLdsBudget) {

@@ -548,10 +548,12 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
     std::vector<uint32_t> hseed(nj);
     std::vector<uint64_t> seeds(nj);
     std::vector<int64_t> lkv(nj);
+    std::vector<AdaptiveJob> adapt(nj);
     for (int32_t j = 0; j < nj; ++j) {
         hseed[j] = seed_hash(jobs[j].seed);
         seeds[j] = jobs[j].seed;
         lkv[j] = jobs[j].lk;
+        adapt[j] = AdaptiveJob{jobs[j].cV, jobs[j].k, jobs[j].e};
     }
     DBuf<uint32_t> dghash;
     if (batch) dghash = upload(c, hseed);
@@ -741,7 +743,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
                 any |= split[b] != 0;
             }
             if (!any) break;
-            t.bip += bipartition_round(c, g, l, part.p, bt, split, lkv, hseed);
+            t.bip += bipartition_round(c, g, l, part.p, bt, split, lkv, hseed, c.adaptive_eps ? &adapt : nullptr);
         }
         if (phase_sync) c.sync();
         t.ms_ip += ms_since(t1);
@@ -888,10 +890,7 @@ int partition_impl(const DGraph& g0, int32_t k, double eps, uint64_t seed, int32
     c.force_exact = opt && opt->force_exact;
     c.small_level_n = opt ? opt->small_level_n : 0;
     c.plain_loads = opt && opt->plain_loads;
-    if (opt && (opt->fm_passes < 0 || opt->fm_passes > kFmMaxPasses)) return KMP_EINVAL;
-    if (opt && opt->ip_pool != 0 && opt->ip_pool != 1) return KMP_EINVAL;
-    c.fm_passes = opt ? opt->fm_passes : 0;
-    c.ip_pool = opt && opt->ip_pool;
+    if (set_ip_options(c, opt) != KMP_OK) return KMP_EINVAL;
     std::vector<JobRun> jobs(1);
     JobRun& jb = jobs[0];
     jb.g = g0;
@@ -933,10 +932,7 @@ int partition_batch_impl(const kmp_graph_desc* gd, int32_t count, kmp_job_result
     c.force_exact = opt && opt->force_exact;
     c.small_level_n = opt ? opt->small_level_n : 0;
     c.plain_loads = opt && opt->plain_loads;
-    if (opt && (opt->fm_passes < 0 || opt->fm_passes > kFmMaxPasses)) return KMP_EINVAL;
-    if (opt && opt->ip_pool != 0 && opt->ip_pool != 1) return KMP_EINVAL;
-    c.fm_passes = opt ? opt->fm_passes : 0;
-    c.ip_pool = opt && opt->ip_pool;
+    if (set_ip_options(c, opt) != KMP_OK) return KMP_EINVAL;
     std::vector<JobRun> jobs(count);
     for (int32_t i = 0; i < count; ++i) {
         JobRun& jb = jobs[i];
@@ -1107,6 +1103,17 @@ int64_t autotune_impl(const kmp_graph_desc& d, int32_t reps, hipStream_t stream,
 }
 
 }  // namespace
+
+int set_ip_options(Ctx& c, const kmp_options* opt)
+{
+    if (opt && (opt->fm_passes < 0 || opt->fm_passes > kFmMaxPasses)) return KMP_EINVAL;
+    if (opt && opt->ip_pool != 0 && opt->ip_pool != 1) return KMP_EINVAL;
+    if (opt && opt->adaptive_eps != 0 && opt->adaptive_eps != 1) return KMP_EINVAL;
+    c.fm_passes = opt ? opt->fm_passes : 0;
+    c.ip_pool = opt && opt->ip_pool;
+    c.adaptive_eps = opt && opt->adaptive_eps;
+    return KMP_OK;
+}
 
 int run_batch(const kmp_graph_desc* graphs, int32_t count, kmp_job_result* results, hipStream_t stream,
               const kmp_options* opt, kmp_stats* stats)

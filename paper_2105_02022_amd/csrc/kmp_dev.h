@@ -360,6 +360,7 @@ class Ctx {
     bool plain_loads = false;    // lane rating: plain loads instead of buffer loads
     int32_t fm_passes = 0;       // 2-way FM passes after every GGG growth
     bool ip_pool = false;        // initial bipartitioning also runs BFS and random growths
+    bool adaptive_eps = false;   // bipartition sides bounded by the adaptive imbalance
     int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0: tune's, < 0 never)
     Tuning tune;                 // the process-wide tuning when the call started
     int prof_begin(int cls);
@@ -646,9 +647,20 @@ struct BlockTab {
 };
 // One bipartitionBlocks round over the blocks with split[b] != 0 (f >= 2);
 // the table is updated.  Per job: L_k (lk) and the seed part of the hash.
+// Per job: what the adaptive imbalance of a bipartition needs (c(V), k, eps in ppm).
+struct AdaptiveJob {
+    int64_t cV;
+    int32_t k;
+    int64_t e;
+};
+// Side caps of a block of weight cB that is to end as f blocks, bounded by the
+// adaptive imbalance (both 0 for an empty block, 2^62 when unbounded).
+void adaptive_side_caps(const AdaptiveJob& j, int64_t cB, int32_t f, int64_t& cap0, int64_t& cap1);
+// Validates and copies the initial-bipartitioning options (fm_passes, ip_pool, adaptive_eps).
+int set_ip_options(Ctx& c, const kmp_options* opt);
 int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, BlockTab& bt,
                           const std::vector<uint8_t>& split, const std::vector<int64_t>& lk,
-                          const std::vector<uint32_t>& hseed);
+                          const std::vector<uint32_t>& hseed, const std::vector<AdaptiveJob>* adapt = nullptr);
 void project(Ctx& c, const int32_t* coarse_part, const int32_t* map, int32_t* fine_part, int32_t n);
 // Batches: nodes with map >= 0 take remap[coarse block]; the others start in
 // their job's single block start_block[job].

@@ -215,3 +215,51 @@ def test_pool_flag_rejected(kmp):
     d_part = t32(np.zeros(g.n, np.int32))
     rc, _, _ = kmp.kmp_bipartition_round(xadj, adjncy, vwgt, adjwgt, 0, d_part, [0], [4], 20, 1, ip_pool=2)
     assert rc == kmp.KMP_EINVAL
+
+
+# ------------------------------------------------------------------ adaptive imbalance of the bipartitions
+
+@pytest.mark.parametrize("name,k,passes,pool", [
+    ("grid128", 8, 0, False), ("rgg20000", 64, 0, False), ("rgg20000", 12, 2, False), ("rand_w", 7, 0, False),
+    ("rand_w", 7, 1, True), ("rand_iso", 16, 0, False), ("rmat13", 100, 0, False), ("heavy3000", 6, 2, True),
+])
+def test_partition_adaptive_eps(kmp, name, k, passes, pool):
+    g = {
+        "grid128": lambda: gen.grid(128, 128),
+        "rgg20000": lambda: gen.rgg(20000, 8.0, 2),
+        "rand_w": lambda: gen.random_graph(5000, 5.0, 7, max_vw=4, max_ew=6),
+        "rand_iso": lambda: gen.random_graph(8000, 3.0, 8, isolated_frac=0.3),
+        "rmat13": lambda: gen.rmat(13, 8 << 13, seed=4),
+        "heavy3000": lambda: _heavy_nodes(3000, 35),
+    }[name]()
+    say(f"[adaptive eps partition] {name} k={k} passes={passes} pool={pool}")
+    ref = oracle.partition(g, k, 0.03, 1, fm_passes=passes, pool=pool, adaptive_eps=True)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, 1, fm_passes=passes,
+                                           ip_pool=pool, adaptive_eps=True)
+    assert rc == ref.status
+    assert np.array_equal(part.cpu().numpy(), ref.part)
+    assert stats["cut"] == ref.stats["cut"]
+
+
+def test_batch_adaptive_eps_equals_oracle(kmp):
+    specs = [(gen.grid(40, 60), 5, 1), (gen.rgg(3000, 8.0, 5), 16, 2), (gen.random_graph(2500, 4.0, 6, max_vw=3), 9, 3)]
+    jobs = []
+    for g, k, seed in specs:
+        xadj, adjncy, vwgt, adjwgt = dev(g)
+        jobs.append(dict(xadj=xadj, adjncy=adjncy, vwgt=vwgt, adjwgt=adjwgt, k=k, epsilon=0.03, seed=seed,
+                         out=torch.empty(g.n, dtype=torch.int32, device="cuda")))
+    say("[adaptive eps batch] 3 jobs")
+    rc, res, _ = kmp.kmp_partition_batch(jobs, adaptive_eps=True)
+    assert rc == 0
+    for (g, k, seed), j, r in zip(specs, jobs, res):
+        ref = oracle.partition(g, k, 0.03, seed, adaptive_eps=True)
+        assert r["status"] == ref.status and r["cut"] == ref.stats["cut"]
+        assert np.array_equal(j["out"].cpu().numpy(), ref.part)
+
+
+def test_adaptive_eps_flag_rejected(kmp):
+    g = gen.grid(10, 10)
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, 4, 0.03, 1, adaptive_eps=2)
+    assert rc == kmp.KMP_EINVAL
