@@ -95,6 +95,7 @@ def _load():
             "or_ggg": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, i32, i32]),
             "or_fm2_stall": (ctypes.c_int, [i32, P32, P32, P32, P32, PU8, i64, i64, i32, i32, P64]),
             "or_step_balance": (i32, [i32, P32, P32, P32, P32, i32, u64, P32, P64, i32, P64]),
+            "or_step_balance_pq": (i32, [i32, P32, P32, P32, P32, i32, u64, P32, P64, i32, P64]),
             "or_step_cut": (i64, [i32, P32, P32, P32, P32]),
             "or_ggg_traced": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, P32,
                                              P32, P32, i32, i32, i64, i64]),
@@ -174,16 +175,16 @@ class Result:
     trace: Dict[Tuple[str, int], np.ndarray] = field(default_factory=dict)
 
 
-IP_POOL, IP_ADAPTIVE = 1, 2
+IP_POOL, IP_ADAPTIVE, BAL_PQ = 1, 2, 4
 
 
-def _ipflags(pool, adaptive_eps):
-    return (IP_POOL if pool else 0) | (IP_ADAPTIVE if adaptive_eps else 0)
+def _ipflags(pool, adaptive_eps, pq_balance=False):
+    return (IP_POOL if pool else 0) | (IP_ADAPTIVE if adaptive_eps else 0) | (BAL_PQ if pq_balance else 0)
 
 
 def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
               validate_input: bool = True, fm_passes: int = 0, pool: bool = False,
-              adaptive_eps: bool = False) -> Result:
+              adaptive_eps: bool = False, pq_balance: bool = False) -> Result:
     lib = _load()
     xadj, adjncy = _i32(g.xadj), _i32(g.adjncy)
     vw = None if g.vwgt is None else _i32(g.vwgt)
@@ -200,7 +201,7 @@ def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
     cb = TRACE_FN(_cb) if trace else TRACE_FN()
     rc = lib.or_partition_traced(g.n, _p(xadj), _p(adjncy), _p(vw), _p(ew), k, eps, seed & (2**64 - 1),
                                  _p(out), ctypes.byref(st), int(validate_input), cb, None, int(fm_passes),
-                                 _ipflags(pool, adaptive_eps))
+                                 _ipflags(pool, adaptive_eps, pq_balance))
     L = st.levels
     stats = dict(cut=st.cut, levels=L, level_n=list(st.level_n[:L + 1]), level_m=list(st.level_m[:L + 1]),
                  bipartitions=st.bipartitions, balance_rounds=st.balance_rounds,
@@ -375,6 +376,16 @@ def balance(g, level: int, seed: int, part, wt, cap):
     wt = np.ascontiguousarray(wt, dtype=np.int64).copy()
     cap = np.ascontiguousarray(cap, dtype=np.int64)
     rounds = _load().or_step_balance(g.n, _p(_i32(g.xadj)), _p(_i32(g.adjncy)), _p(vw), _p(ew), level, seed,
+                                     _p(part), _p(wt, P64), int(wt.shape[0]), _p(cap, P64))
+    return part, wt, int(rounds)
+
+
+def balance_pq(g, level: int, seed: int, part, wt, cap):
+    vw, ew = _weights(g)
+    part = _i32(part).copy()
+    wt = np.ascontiguousarray(wt, dtype=np.int64).copy()
+    cap = np.ascontiguousarray(cap, dtype=np.int64)
+    rounds = _load().or_step_balance_pq(g.n, _p(_i32(g.xadj)), _p(_i32(g.adjncy)), _p(vw), _p(ew), level, seed,
                                      _p(part), _p(wt, P64), int(wt.shape[0]), _p(cap, P64))
     return part, wt, int(rounds)
 

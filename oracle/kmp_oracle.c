@@ -27,6 +27,7 @@
  *   O8d adaptive imbalance of a bipartition (optional)  (Sec. 2 "Maintaining the Balance
  *       Constraint", Alg. 2, Sec. 5.2 bound L_2)
  *   O9  k-way balancer by relative gain              (Sec. 5.3 "Balancing")
+ *   O9b the same with the paper's priority queues (optional) (Sec. 5.3 "Balancing")
  *   O10 driver                                       (Alg. 1, Sec. 4)
  *   O11 edge cut                                     (Sec. 2 "Notation and Definitions")
  *
@@ -53,8 +54,8 @@
 #define OR_NONE 0xFFFFFFFFu
 #define OR_PHI 0x9E3779B9u
 enum { T_SUB = 1, T_CL = 2, T_REF = 3, T_BAL = 4, T_GGG = 5, T_BFS = 6, T_RND = 7 };
-/* initial-bipartitioning options (bit flags): the pool of O8c, the adaptive caps of O8d */
-enum { OR_IP_POOL = 1, OR_IP_ADAPTIVE = 2, OR_IP_ALL = 3 };
+/* options (bit flags): the pool of O8c, the adaptive caps of O8d, the queue balancer of O9b */
+enum { OR_IP_POOL = 1, OR_IP_ADAPTIVE = 2, OR_BAL_PQ = 4, OR_IP_ALL = 7 };
 
 /* status codes */
 #define OR_OK 0
@@ -1172,6 +1173,213 @@ int64_t or_cut(const or_graph* g, const int32_t* part)
     return s / 2;
 }
 
+/* ---------------- O9b: priority-queue balancer (optional) ---------------
+ * Sec. 5.3 "Balancing" as the paper describes its queues.  For every
+ * overloaded block B a queue P_B holds just enough nodes of B to remove the
+ * excess o(B) = c(B) - cap(B), ordered by relative gain (d c(v) for d >= 0,
+ * d / c(v) otherwise; d = the largest cut reduction of moving v to a block
+ * that would not become overloaded).  Reading, per pass:
+ *  - target of v in block b (current weights): the adjacent block t != b with
+ *    c(t) + c(v) <= cap(t) of largest connection (ties by H(seed; T_BAL, l,
+ *    pass, t), then index); else the block t != b of most free room cap - c
+ *    (ties smallest index) if v fits there; else none.  d = w(v,t) - w(v,b).
+ *  - offer(B, v): if the weight in P_B is below o(B), insert; else insert only
+ *    if v's key beats the queue's lowest key, then drop lowest elements while
+ *    the queue weighs more than o(B) + max c(v).  Keys: larger relative gain
+ *    first, then smaller id.
+ *  - initialisation: every node of an overloaded block with a target is
+ *    offered, in ascending id, against the pass-start weights.
+ *  - then the overloaded blocks in ascending index: while B is overloaded and
+ *    P_B is not empty, take the node of largest key; recompute its target and
+ *    d; if d changed or its designated target can no longer take it, offer it
+ *    again if it is still a border node (a neighbour in another block), else
+ *    move it to its designated target and offer each neighbour still in B
+ *    that is not in P_B and was not offered this way before (in row order:
+ *    each node is tried once as a neighbour).
+ *  - passes repeat while a block is overloaded and the last pass moved a node.
+ * Queues here are plain arrays scanned for their extremes (slow, simple).   */
+typedef struct {
+    int64_t d, c;
+    int32_t v, t;
+} or_pqe;
+
+/* > 0: a ranks before b (larger relative gain, then smaller id) */
+static int pqe_cmp(const or_pqe* a, const or_pqe* b)
+{
+    int r = or_rg_cmp(a->d, a->c, b->d, b->c);
+    if (r != 0) return r;
+    return (a->v < b->v) - (a->v > b->v);
+}
+
+typedef struct {
+    or_pqe* e;
+    int32_t n, cap;
+    int64_t w;
+    uint8_t* inq; /* per node: currently in some queue */
+} or_pq;
+
+static int pq_push(or_pq* q, or_pqe x)
+{
+    q->inq[x.v] = 1;
+    if (q->n == q->cap) {
+        int32_t nc = q->cap ? 2 * q->cap : 16;
+        or_pqe* ne = (or_pqe*)realloc(q->e, sizeof(or_pqe) * (size_t)nc);
+        if (!ne) return OR_ENOMEM;
+        q->e = ne;
+        q->cap = nc;
+    }
+    q->e[q->n++] = x;
+    q->w += x.c;
+    return OR_OK;
+}
+
+/* index of the first (best, dir = 1) or last (worst, dir = -1) element */
+static int32_t pq_extreme(const or_pq* q, int dir)
+{
+    int32_t b = -1;
+    for (int32_t i = 0; i < q->n; ++i)
+        if (b < 0 || dir * pqe_cmp(&q->e[i], &q->e[b]) > 0) b = i;
+    return b;
+}
+
+static or_pqe pq_take(or_pq* q, int32_t i)
+{
+    or_pqe x = q->e[i];
+    q->e[i] = q->e[--q->n];
+    q->w -= x.c;
+    q->inq[x.v] = 0;
+    return x;
+}
+
+/* target and d of v against the current weights; 0 if no block can take v */
+static int pq_target(const or_graph* g, const int32_t* part, const int64_t* wt, const int64_t* cap, int32_t nb,
+                     int32_t level, uint64_t seed, int32_t pass, int32_t v, int64_t* conn, int32_t* touched,
+                     or_pqe* out)
+{
+    const int32_t b = part[v];
+    const int64_t cv = g->vwgt[v];
+    int32_t nt = 0;
+    for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e) {
+        int32_t t = part[g->adjncy[e]];
+        if (conn[t] == 0) touched[nt++] = t;
+        conn[t] += g->adjwgt[e];
+    }
+    int32_t best = -1;
+    uint32_t hb = 0;
+    for (int32_t i = 0; i < nt; ++i) {
+        int32_t t = touched[i];
+        if (t == b || wt[t] + cv > cap[t]) continue;
+        uint32_t a4[4] = {T_BAL, (uint32_t)level, (uint32_t)pass, (uint32_t)t};
+        uint32_t h = or_hash(seed, 4, a4);
+        if (best < 0 || key_better(conn[t], h, t, conn[best], hb, best)) {
+            best = t;
+            hb = h;
+        }
+    }
+    if (best < 0) {
+        int32_t tf = -1;
+        for (int32_t t = 0; t < nb; ++t)
+            if (t != b && (tf < 0 || cap[t] - wt[t] > cap[tf] - wt[tf])) tf = t;
+        if (tf >= 0 && wt[tf] + cv <= cap[tf]) best = tf;
+    }
+    int found = best >= 0;
+    if (found) {
+        out->v = v;
+        out->t = best;
+        out->c = cv;
+        out->d = conn[best] - conn[b];
+    }
+    for (int32_t i = 0; i < nt; ++i) conn[touched[i]] = 0;
+    return found;
+}
+
+static int pq_offer(or_pq* q, or_pqe x, int64_t over, int64_t maxc)
+{
+    if (q->w < over) return pq_push(q, x);
+    int32_t lo = pq_extreme(q, -1);
+    if (lo < 0 || pqe_cmp(&x, &q->e[lo]) <= 0) return OR_OK;
+    int rc = pq_push(q, x);
+    if (rc != OR_OK) return rc;
+    while (q->n > 0 && q->w > over + maxc) pq_take(q, pq_extreme(q, -1));
+    return OR_OK;
+}
+
+static int is_border(const or_graph* g, const int32_t* part, int32_t v)
+{
+    for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e)
+        if (part[g->adjncy[e]] != part[v]) return 1;
+    return 0;
+}
+
+int32_t or_balance_pq(const or_graph* g, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,
+                      const int64_t* cap)
+{
+    int32_t n = g->n;
+    int64_t maxc = 0;
+    for (int32_t v = 0; v < n; ++v)
+        if (g->vwgt[v] > maxc) maxc = g->vwgt[v];
+    int64_t* conn = (int64_t*)calloc((size_t)(nb > 0 ? nb : 1), sizeof(int64_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nb > 0 ? nb : 1) + 4);
+    uint8_t* over = (uint8_t*)malloc((size_t)(nb > 0 ? nb : 1));
+    uint8_t* tried = (uint8_t*)malloc((size_t)(n > 0 ? n : 1)); /* offered as a neighbour this pass */
+    uint8_t* inq = (uint8_t*)calloc((size_t)(n > 0 ? n : 1), 1);
+    or_pq* q = (or_pq*)calloc((size_t)(nb > 0 ? nb : 1), sizeof(or_pq));
+    int rc = OR_OK;
+    int32_t pass = 0;
+    if (!conn || !touched || !over || !tried || !inq || !q) rc = OR_ENOMEM;
+    if (rc == OR_OK)
+        for (int32_t b = 0; b < nb; ++b) q[b].inq = inq;
+    int moved_prev = 1;
+    while (rc == OR_OK) {
+        int any = 0;
+        for (int32_t b = 0; b < nb; ++b) {
+            over[b] = wt[b] > cap[b];
+            any |= over[b];
+            while (q[b].n > 0) pq_take(&q[b], 0);
+        }
+        if (!any || !moved_prev) break;
+        memset(tried, 0, (size_t)(n > 0 ? n : 1));
+        for (int32_t v = 0; v < n && rc == OR_OK; ++v) {
+            int32_t b = part[v];
+            or_pqe x;
+            if (!over[b] || !pq_target(g, part, wt, cap, nb, level, seed, pass, v, conn, touched, &x)) continue;
+            rc = pq_offer(&q[b], x, wt[b] - cap[b], maxc);
+        }
+        int64_t moves = 0;
+        for (int32_t b = 0; b < nb && rc == OR_OK; ++b) {
+            if (!over[b]) continue;
+            while (rc == OR_OK && wt[b] > cap[b] && q[b].n > 0) {
+                or_pqe x = pq_take(&q[b], pq_extreme(&q[b], 1));
+                int32_t v = x.v;
+                or_pqe y;
+                if (!pq_target(g, part, wt, cap, nb, level, seed, pass, v, conn, touched, &y)) continue;
+                if (y.d != x.d || wt[x.t] + x.c > cap[x.t]) {
+                    if (is_border(g, part, v)) rc = pq_offer(&q[b], y, wt[b] - cap[b], maxc);
+                    continue;
+                }
+                wt[x.t] += x.c;
+                wt[b] -= x.c;
+                part[v] = x.t;
+                ++moves;
+                for (int64_t e = g->xadj[v]; e < g->xadj[v + 1] && rc == OR_OK; ++e) {
+                    int32_t u = g->adjncy[e];
+                    or_pqe z;
+                    if (part[u] != b || tried[u] || inq[u]) continue;
+                    tried[u] = 1;
+                    if (pq_target(g, part, wt, cap, nb, level, seed, pass, u, conn, touched, &z))
+                        rc = pq_offer(&q[b], z, wt[b] - cap[b], maxc);
+                }
+            }
+        }
+        moved_prev = moves > 0;
+        ++pass;
+    }
+    if (q)
+        for (int32_t b = 0; b < nb; ++b) free(q[b].e);
+    free(conn); free(touched); free(over); free(tried); free(inq); free(q);
+    return rc == OR_OK ? pass : rc;
+}
+
 /* ---------------- O10: driver (Alg. 1 unrolled) ------------------------- */
 static int32_t ceil2_div_C(int32_t n_l)
 {
@@ -1311,7 +1519,8 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
         trace(tfn, tuser, TR_BIPART, l, part, g->n);
         block_weights(g, part, nb, bw);
         for (int32_t b = 0; b < nb; ++b) cap[b] = (int64_t)fcount[b] * lk;
-        int32_t brounds = or_balance(g, l, seed, part, bw, nb, cap);
+        int32_t brounds = (ipflags & OR_BAL_PQ) ? or_balance_pq(g, l, seed, part, bw, nb, cap)
+                                                : or_balance(g, l, seed, part, bw, nb, cap);
         if (brounds < 0) return brounds;
         if (st) st->balance_rounds += brounds;
         trace(tfn, tuser, TR_BALANCE, l, part, g->n);
@@ -1432,6 +1641,14 @@ int32_t or_step_balance(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
 {
     or_graph g = view(n, xadj, adjncy, vwgt, adjwgt);
     return or_balance(&g, level, seed, part, wt, nb, cap);
+}
+
+int32_t or_step_balance_pq(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
+                        const int32_t* adjwgt, int32_t level, uint64_t seed, int32_t* part, int64_t* wt,
+                        int32_t nb, const int64_t* cap)
+{
+    or_graph g = view(n, xadj, adjncy, vwgt, adjwgt);
+    return or_balance_pq(&g, level, seed, part, wt, nb, cap);
 }
 
 int64_t or_step_cut(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt,
