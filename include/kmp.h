@@ -97,6 +97,9 @@ typedef struct kmp_options {
                                point: the largest q whose r-fold stepwise-floored power p <- p q / 2^32
                                stays within floor(2^32 (1 + eps')^r)).  0: sides bounded by f_j L_k (the
                                default); other values: KMP_EINVAL.  The output depends on it. */
+    int32_t pq_balance;     /* reserved for the queue balancer of paper Sec. 5.3 (per overloaded block a
+                               queue of just enough nodes by relative gain, re-insertion, neighbour offers).
+                               It is switched off in this version: any value but 0 gives KMP_EINVAL. */
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */
@@ -294,7 +297,7 @@ void kmp_server_destroy(kmp_server* server);
 
 /*
  * kmp_server_set_options: the initial-bipartitioning options (fm_passes,
- * ip_pool, adaptive_eps; meaning and ranges as in kmp_options) for every job submitted
+ * ip_pool, adaptive_eps, pq_balance; meaning and ranges as in kmp_options) for every job submitted
  * after the call (a job keeps the options current at its submission; only
  * jobs with equal options share a batch); the other fields of *opt are
  * ignored.  opt == NULL restores the defaults.  Out-of-range values give
@@ -434,6 +437,15 @@ int kmp_bipartition_round_ex(const int32_t* xadj, const int32_t* adjncy, const i
 int kmp_balance(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
                 int32_t n, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,
                 const int64_t* cap, void* stream);
+
+/*
+ * kmp_balance_ex: kmp_balance with pq selecting the queue balancer described
+ * at kmp_options.pq_balance; switched off in this version, so only pq = 0 is
+ * accepted (else KMP_EINVAL).  Returns the rounds run.
+ */
+int kmp_balance_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                   int32_t n, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,
+                   const int64_t* cap, int32_t pq, void* stream);
 
 /*
  * kmp_lp_refine: k-way LP refinement (paper Sec. 5.3 "Local Improvement")

@@ -32,7 +32,8 @@ PROF_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "admit", "apply", "
 class KmpOptions(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
                 ("force_exact", ctypes.c_int32), ("small_level_n", ctypes.c_int32), ("plain_loads", ctypes.c_int32),
-                ("fm_passes", ctypes.c_int32), ("ip_pool", ctypes.c_int32), ("adaptive_eps", ctypes.c_int32)]
+                ("fm_passes", ctypes.c_int32), ("ip_pool", ctypes.c_int32), ("adaptive_eps", ctypes.c_int32),
+                ("pq_balance", ctypes.c_int32)]
 
 
 class KmpStats(ctypes.Structure):
@@ -115,6 +116,7 @@ SIGNATURES = {
     "kmp_bipartition_round_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _vp, _P32, _P32, _P32, _i64,
                                                 _u64, _i32, _i32, _vp]),
     "kmp_balance": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _vp, _vp, _i32, _vp, _vp]),
+    "kmp_balance_ex": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _vp, _vp, _i32, _vp, _i32, _vp]),
     "kmp_lp_refine": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _vp, _vp, _i32, _vp, _P64, _vp]),
     "kmp_lp_subround": (_i64, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _u32, _u64, _vp, _vp, _i32, _vp, _i64,
                                _vp, _vp, _vp, _vp]),
@@ -225,14 +227,15 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
                      profile_classes=None, force_exact: bool = False,
                      small_level_n: int = 0, plain_loads: bool = False,
                      fm_passes: int = 0, ip_pool: bool = False,
-                     adaptive_eps: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+                     adaptive_eps: bool = False, pq_balance: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
     (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path.
     `small_level_n`: largest level run by the one-workgroup LP (0 default, -1 never).
     `plain_loads`: the lane rating kernel gathers with plain loads (the buffer-load path is the default).
     `fm_passes`: 2-way FM passes after every greedy growth (0..16; 0 = none).
     `ip_pool`: the initial bipartitioning also runs BFS and random growths.
-    `adaptive_eps`: bipartitions bound their sides by the adaptive imbalance (paper Sec. 2, Alg. 2)."""
+    `adaptive_eps`: bipartitions bound their sides by the adaptive imbalance (paper Sec. 2, Alg. 2).
+    `pq_balance`: the queue balancer of paper Sec. 5.3 instead of sorted rounds."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -247,6 +250,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt.fm_passes = int(fm_passes)
     opt.ip_pool = int(ip_pool)
     opt.adaptive_eps = int(adaptive_eps)
+    opt.pq_balance = int(pq_balance)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -260,7 +264,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
 def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
                           stream=None, validate: bool = False, force_exact: bool = False, small_level_n: int = 0,
                           fm_passes: int = 0, ip_pool: bool = False,
-                          adaptive_eps: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+                          adaptive_eps: bool = False, pq_balance: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """kmp_partition_noalloc: as kmp_partition_ex, with every device buffer inside the library's fixed
     scratch region (n <= NOALLOC_MAX_N, m <= NOALLOC_MAX_M, else KMP_ETOOLARGE).  `out` should be
     given by callers that must not allocate."""
@@ -276,6 +280,7 @@ def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0
     opt.fm_passes = int(fm_passes)
     opt.ip_pool = int(ip_pool)
     opt.adaptive_eps = int(adaptive_eps)
+    opt.pq_balance = int(pq_balance)
     st = KmpStats()
     rc = library().kmp_partition_noalloc(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
                                          epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream),
@@ -299,7 +304,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
                         profile_classes=None, force_exact: bool = False,
                         small_level_n: int = 0, plain_loads: bool = False,
                         fm_passes: int = 0, ip_pool: bool = False,
-                        adaptive_eps: bool = False) -> Tuple[int, List[Dict], Dict]:
+                        adaptive_eps: bool = False, pq_balance: bool = False) -> Tuple[int, List[Dict], Dict]:
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
@@ -316,6 +321,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     opt.fm_passes = int(fm_passes)
     opt.ip_pool = int(ip_pool)
     opt.adaptive_eps = int(adaptive_eps)
+    opt.pq_balance = int(pq_balance)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -374,12 +380,14 @@ class Server:
         out["latency_ms"] = lat.value
         return out
 
-    def set_options(self, fm_passes: int = 0, ip_pool: bool = False, adaptive_eps: bool = False) -> int:
+    def set_options(self, fm_passes: int = 0, ip_pool: bool = False, adaptive_eps: bool = False,
+                    pq_balance: bool = False) -> int:
         """Initial-bipartitioning options for jobs submitted from now on (kmp_server_set_options)."""
         o = KmpOptions()
         o.fm_passes = int(fm_passes)
         o.ip_pool = int(ip_pool)
         o.adaptive_eps = int(adaptive_eps)
+        o.pq_balance = int(pq_balance)
         return library().kmp_server_set_options(self._h, ctypes.byref(o))
 
     def poll(self, jid: int) -> Optional[Dict]:
@@ -480,6 +488,16 @@ def kmp_balance(xadj, adjncy, vwgt, adjwgt, level: int, seed: int, part, wt, cap
     n = xadj.numel() - 1
     return library().kmp_balance(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level, seed & (2**64 - 1),
                                  _ptr(part), _ptr(wt), wt.numel(), _ptr(cap), _stream(stream))
+
+
+def kmp_balance_ex(xadj, adjncy, vwgt, adjwgt, level: int, seed: int, part, wt, cap, pq: bool = False,
+                   stream=None) -> int:
+    """kmp_balance_ex: pq selects the queue balancer (paper Sec. 5.3 queues)."""
+    _check_i32(xadj, adjncy, vwgt, adjwgt, part)
+    n = xadj.numel() - 1
+    return library().kmp_balance_ex(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level,
+                                    seed & (2**64 - 1), _ptr(part), _ptr(wt), wt.numel(), _ptr(cap), int(pq),
+                                    _stream(stream))
 
 
 def kmp_lp_refine(xadj, adjncy, vwgt, adjwgt, level: int, seed: int, part, wt, cap, stream=None):

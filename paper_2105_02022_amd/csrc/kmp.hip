@@ -771,8 +771,9 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         };
         const bool small_lp = !batch && L.maxdeg >= 0 && L.maxdeg <= c.tune.cut[1] && small_job_fits(c, g.n, nb);
         if (!small_lp) level_sched();
-        t.brounds += balance(c, g, l, batch ? seeds : std::vector<uint64_t>{seed0}, level_sched, part.p, wt.p, bt,
-                             cap.p, jt, dboff.p, &hcap);
+        t.brounds += (c.pq_balance ? balance_pq : balance)(c, g, l, batch ? seeds : std::vector<uint64_t>{seed0},
+                                                            level_sched, part.p, wt.p, bt, cap.p, jt, dboff.p,
+                                                            &hcap);
         LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF, jt, dboff.p, nullptr};
         if (batch) {
             std::vector<int32_t> nbk(nj, 0);
@@ -1109,9 +1110,12 @@ int set_ip_options(Ctx& c, const kmp_options* opt)
     if (opt && (opt->fm_passes < 0 || opt->fm_passes > kFmMaxPasses)) return KMP_EINVAL;
     if (opt && opt->ip_pool != 0 && opt->ip_pool != 1) return KMP_EINVAL;
     if (opt && opt->adaptive_eps != 0 && opt->adaptive_eps != 1) return KMP_EINVAL;
+    // the GPU queue balancer is switched off: its first GPU run faulted and the cause is not yet shown
+    if (opt && opt->pq_balance != 0) return KMP_EINVAL;
     c.fm_passes = opt ? opt->fm_passes : 0;
     c.ip_pool = opt && opt->ip_pool;
     c.adaptive_eps = opt && opt->adaptive_eps;
+    c.pq_balance = opt && opt->pq_balance;
     return KMP_OK;
 }
 
@@ -1347,7 +1351,15 @@ int kmp_balance(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                 int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb, const int64_t* cap,
                 void* stream)
 {
-    if (n < 0 || nb < 1 || (n > 0 && (!xadj || !part || !wt || !cap))) return KMP_EINVAL;
+    return kmp_balance_ex(xadj, adjncy, vwgt, adjwgt, n, level, seed, part, wt, nb, cap, 0, stream);
+}
+
+int kmp_balance_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
+                   int32_t n, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,
+                   const int64_t* cap, int32_t pq, void* stream)
+{
+    // pq = 1 (the queue balancer) is switched off: its first GPU run faulted and the cause is not yet shown
+    if (n < 0 || nb < 1 || (n > 0 && (!xadj || !part || !wt || !cap)) || pq != 0) return KMP_EINVAL;
     if (n == 0) return 0;
     return (int)guarded([&]() -> int64_t {
         init_pool_once();
@@ -1361,8 +1373,9 @@ int kmp_balance(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
         bt.first.assign(nb, 0);
         bt.f.assign(nb, 1);
         bt.job.assign(nb, 0);
-        int32_t r = balance(c, g, level, std::vector<uint64_t>{seed}, [&]() -> const LPSchedule& { return sched; },
-                            part, wt, bt, cap);
+        int32_t r = (pq ? balance_pq : balance)(c, g, level, std::vector<uint64_t>{seed},
+                                                [&]() -> const LPSchedule& { return sched; }, part, wt, bt, cap,
+                                                JobTabs{}, nullptr, nullptr);
         c.sync();
         return r;
     });

@@ -361,6 +361,7 @@ class Ctx {
     int32_t fm_passes = 0;       // 2-way FM passes after every GGG growth
     bool ip_pool = false;        // initial bipartitioning also runs BFS and random growths
     bool adaptive_eps = false;   // bipartition sides bounded by the adaptive imbalance
+    bool pq_balance = false;     // balancing by the queue balancer
     int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0: tune's, < 0 never)
     Tuning tune;                 // the process-wide tuning when the call started
     int prof_begin(int cls);
@@ -682,6 +683,11 @@ void edge_cut_jobs(Ctx& c, const DGraph& g, const int32_t* part, const int32_t* 
 // sched builds (or returns) the level's schedule; it is called only when some
 // block is overloaded.
 int32_t balance(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64_t>& seeds,
+                const std::function<const LPSchedule&()>& sched, int32_t* part, int64_t* wt, const BlockTab& bt,
+                const int64_t* cap, const JobTabs& jt = {}, const int32_t* boff = nullptr,
+                const std::vector<int64_t>* hcap = nullptr);
+// The queue balancer (paper Sec. 5.3 queues; kmp_options.pq_balance), same arguments.
+int32_t balance_pq(Ctx& c, const DGraph& g, int32_t level, const std::vector<uint64_t>& seeds,
                 const std::function<const LPSchedule&()>& sched, int32_t* part, int64_t* wt, const BlockTab& bt,
                 const int64_t* cap, const JobTabs& jt = {}, const int32_t* boff = nullptr,
                 const std::vector<int64_t>* hcap = nullptr);
