@@ -87,6 +87,8 @@ def _load():
             "or_step_lp_cluster": (i32, [i32, P32, P32, P32, P32, i32, i64, u64, P32, P64, PU32, P64]),
             "or_step_lp_generic": (i32, [i32, P32, P32, P32, P32, i32, u32, u64, P32, P64, i32, P64, i64,
                                          PU32, P64]),
+            "or_step_lp_async": (i32, [i32, P32, P32, P32, P32, i32, u32, u64, P32, P64, i32, P64, i64,
+                                       PU32, P64]),
             "or_step_two_hop": (i64, [i32, P32, P32, P32, P32, i64, P32, P64, PU32]),
             "or_step_contract": (ctypes.c_int, [i32, P32, P32, P32, P32, P32, P32, P32, P64, P32, P32, P32,
                                                 P32]),
@@ -175,16 +177,18 @@ class Result:
     trace: Dict[Tuple[str, int], np.ndarray] = field(default_factory=dict)
 
 
-IP_POOL, IP_ADAPTIVE, BAL_PQ = 1, 2, 4
+IP_POOL, IP_ADAPTIVE, BAL_PQ, LP_ASYNC = 1, 2, 4, 8
 
 
-def _ipflags(pool, adaptive_eps, pq_balance=False):
-    return (IP_POOL if pool else 0) | (IP_ADAPTIVE if adaptive_eps else 0) | (BAL_PQ if pq_balance else 0)
+def _ipflags(pool, adaptive_eps, pq_balance=False, async_lp=False):
+    return (IP_POOL if pool else 0) | (IP_ADAPTIVE if adaptive_eps else 0) | (BAL_PQ if pq_balance else 0) | \
+        (LP_ASYNC if async_lp else 0)
 
 
 def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
               validate_input: bool = True, fm_passes: int = 0, pool: bool = False,
-              adaptive_eps: bool = False, pq_balance: bool = False) -> Result:
+              adaptive_eps: bool = False, pq_balance: bool = False, async_lp: bool = False) -> Result:
+    """O10; async_lp: every LP call is the one-PE execution of the asynchronous LP (O3b)."""
     lib = _load()
     xadj, adjncy = _i32(g.xadj), _i32(g.adjncy)
     vw = None if g.vwgt is None else _i32(g.vwgt)
@@ -201,7 +205,7 @@ def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
     cb = TRACE_FN(_cb) if trace else TRACE_FN()
     rc = lib.or_partition_traced(g.n, _p(xadj), _p(adjncy), _p(vw), _p(ew), k, eps, seed & (2**64 - 1),
                                  _p(out), ctypes.byref(st), int(validate_input), cb, None, int(fm_passes),
-                                 _ipflags(pool, adaptive_eps, pq_balance))
+                                 _ipflags(pool, adaptive_eps, pq_balance, async_lp))
     L = st.levels
     stats = dict(cut=st.cut, levels=L, level_n=list(st.level_n[:L + 1]), level_m=list(st.level_m[:L + 1]),
                  bipartitions=st.bipartitions, balance_rounds=st.balance_rounds,
@@ -236,6 +240,21 @@ def lp_generic(g, level: int, tag: int, seed: int, label, wt, capv=None, caps: i
     r = _load().or_step_lp_generic(g.n, _p(_i32(g.xadj)), _p(_i32(g.adjncy)), _p(vw), _p(ew), level, tag,
                                    seed, _p(label), _p(wt, P64), int(wt.shape[0]), _p(capv, P64), caps,
                                    _p(favv, PU32), _p(moves, P64))
+    return label, wt, favv, moves, int(r)
+
+
+def lp_async(g, level: int, tag: int, seed: int, label, wt, capv=None, caps: int = 0, fav=None):
+    """O3b (asynchronous LP executed by one PE, visits by degree bucket) from an arbitrary state; returns
+    (label, wt, fav, moves per round, rounds) like lp_generic."""
+    vw, ew = _weights(g)
+    label = _i32(label).copy()
+    wt = np.ascontiguousarray(wt, dtype=np.int64).copy()
+    favv = None if fav is None else np.ascontiguousarray(fav, dtype=np.uint32).copy()
+    capv = None if capv is None else np.ascontiguousarray(capv, dtype=np.int64)
+    moves = np.zeros(ROUNDS, np.int64)
+    r = _load().or_step_lp_async(g.n, _p(_i32(g.xadj)), _p(_i32(g.adjncy)), _p(vw), _p(ew), level, tag,
+                                 seed, _p(label), _p(wt, P64), int(wt.shape[0]), _p(capv, P64), caps,
+                                 _p(favv, PU32), _p(moves, P64))
     return label, wt, favv, moves, int(r)
 
 

@@ -17,6 +17,8 @@
  *   O2  sub-round classes                            (replaces Sec. 5.1 "Parallelization")
  *   O3  size-constrained label propagation           (Sec. 2 "Size-Constrained LP";
  *                                                     Sec. 5.1; Sec. 5.3 "Local Improvement")
+ *   O3b asynchronous LP, one-PE execution (optional)  (Sec. 5.1 "Parallelization" and
+ *                                                     "Iteration Order"; Sec. 5.3 "Local Improvement")
  *   O4  two-hop clustering of singletons             (Sec. 5.1 "Two-hop Clustering")
  *   O5  contraction                                  (Sec. 2 "Multilevel Graph Partitioning")
  *   O6  block table with final block counts f_B      (Sec. 4 "Handling General k")
@@ -54,8 +56,9 @@
 #define OR_NONE 0xFFFFFFFFu
 #define OR_PHI 0x9E3779B9u
 enum { T_SUB = 1, T_CL = 2, T_REF = 3, T_BAL = 4, T_GGG = 5, T_BFS = 6, T_RND = 7 };
-/* options (bit flags): the pool of O8c, the adaptive caps of O8d, the queue balancer of O9b */
-enum { OR_IP_POOL = 1, OR_IP_ADAPTIVE = 2, OR_BAL_PQ = 4, OR_IP_ALL = 7 };
+/* options (bit flags): the pool of O8c, the adaptive caps of O8d, the queue balancer of O9b,
+ * the asynchronous LP of O3b for every LP call (clustering and refinement) */
+enum { OR_IP_POOL = 1, OR_IP_ADAPTIVE = 2, OR_BAL_PQ = 4, OR_LP_ASYNC = 8, OR_IP_ALL = 15 };
 
 /* status codes */
 #define OR_OK 0
@@ -433,6 +436,121 @@ int32_t or_lp(const or_graph* g, int32_t level, uint64_t seed, uint32_t tag, int
     }
     free(active); free(moved);
     return rounds;
+}
+
+/* ---------------- O3b: asynchronous LP, one-PE execution ---------------
+ * Sec. 5.1 "Parallelization": the asynchronous mode loops over all nodes in
+ * parallel; a move updates the two cluster weights at once with
+ * fetch-and-add, so nodes visited later see it, and the clustering bound is
+ * not enforced strictly.  Sec. 5.3 "Local Improvement": refinement runs the
+ * same loop but enforces the block bound strictly with compare-and-swap.
+ * Sec. 5.1 "Iteration Order": nodes are visited by exponentially spaced
+ * degree buckets, bucket i holding the degrees 2^i <= d < 2^(i+1).
+ *
+ * A parallel run may interleave the visits in any way; this function is the
+ * execution by a single processing element, which fixes one of them: nodes in
+ * ascending (bucket, id), degree 0 with bucket 0 (the paper's shuffling
+ * inside chunks is left out).  An active node is rated against the current
+ * labels and weights with the key order and tie-break hash of O3 (the round
+ * and the node's label, no sub-round), moves to the best cluster that fits
+ * (current weight + c(v) <= bound) if its rating beats the rating of its own
+ * cluster, and the move is applied before the next visit.  With one
+ * processing element the bound holds strictly in both uses.  Rounds, early
+ * exit and the active rule are those of O3.  Returns the rounds run or a
+ * negative error.                                                         */
+static int32_t deg_bucket(int64_t d)
+{
+    int32_t b = 0;
+    while (d >= 2) {
+        d >>= 1;
+        ++b;
+    }
+    return b;
+}
+
+int32_t or_lp_async(const or_graph* g, int32_t level, uint64_t seed, uint32_t tag, int32_t* label, int64_t* wt,
+                    int32_t nlab, const int64_t* capv, int64_t caps, uint32_t* fav, int64_t* moves_out)
+{
+    int32_t n = g->n;
+    if (n == 0) return 0;
+    int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int64_t* rating = (int64_t*)calloc((size_t)(nlab > 0 ? nlab : 1), sizeof(int64_t));
+    int32_t* touched = (int32_t*)malloc(sizeof(int32_t) * ((size_t)(n > nlab ? n : nlab) + 1));
+    uint8_t* active = (uint8_t*)malloc((size_t)n);
+    uint8_t* moved = (uint8_t*)malloc((size_t)n);
+    if (!order || !rating || !touched || !active || !moved) {
+        free(order); free(rating); free(touched); free(active); free(moved);
+        return OR_ENOMEM;
+    }
+    /* visit order: buckets ascending, ids ascending inside a bucket */
+    int32_t pos = 0;
+    for (int32_t b = 0; b < 32; ++b)
+        for (int32_t v = 0; v < n; ++v)
+            if (deg_bucket(g->xadj[v + 1] - g->xadj[v]) == b) order[pos++] = v;
+    memset(active, 1, (size_t)n);
+    int32_t rounds = 0;
+    for (int32_t r = 0; r < OR_ROUNDS; ++r) {
+        rounds = r + 1;
+        memset(moved, 0, (size_t)n);
+        int64_t nmoved = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            int32_t v = order[i];
+            if (!active[v]) continue;
+            int32_t nt = 0;
+            for (int64_t e = g->xadj[v]; e < g->xadj[v + 1]; ++e) {
+                int32_t K = label[g->adjncy[e]];
+                if (rating[K] == 0) touched[nt++] = K;
+                rating[K] += g->adjwgt[e];
+            }
+            int32_t own = label[v];
+            int64_t rho_own = rating[own];
+            int32_t best = -1, fbest = -1;
+            int64_t rb = 0, rf = 0;
+            uint32_t hb = 0, hf = 0;
+            for (int32_t t = 0; t < nt; ++t) {
+                int32_t K = touched[t];
+                if (K == own) continue;
+                int64_t rk = rating[K];
+                uint32_t a4[4] = {tag, (uint32_t)level, (uint32_t)r, (uint32_t)K};
+                uint32_t hk = or_hash(seed, 4, a4);
+                if (fbest < 0 || key_better(rk, hk, K, rf, hf, fbest)) {
+                    fbest = K; rf = rk; hf = hk;
+                }
+                if (wt[K] + g->vwgt[v] <= cap_of(capv, caps, K)) {
+                    if (best < 0 || key_better(rk, hk, K, rb, hb, best)) {
+                        best = K; rb = rk; hb = hk;
+                    }
+                }
+            }
+            for (int32_t t = 0; t < nt; ++t) rating[touched[t]] = 0;
+            if (fav) fav[v] = fbest < 0 ? OR_NONE : (uint32_t)fbest;
+            if (best >= 0 && rb > rho_own) {
+                label[v] = best;
+                wt[best] += g->vwgt[v];
+                wt[own] -= g->vwgt[v];
+                moved[v] = 1;
+                ++nmoved;
+            }
+        }
+        if (moves_out) moves_out[r] = nmoved;
+        if (nmoved == 0) break;
+        for (int32_t v = 0; v < n; ++v) {
+            uint8_t a = 0;
+            for (int64_t e = g->xadj[v]; e < g->xadj[v + 1] && !a; ++e) a = moved[g->adjncy[e]];
+            active[v] = a;
+        }
+    }
+    free(order); free(rating); free(touched); free(active); free(moved);
+    return rounds;
+}
+
+/* The LP of one call: O3, or O3b when the option asks for it. */
+static int32_t lp_call(const or_graph* g, int32_t level, uint64_t seed, uint32_t tag, int32_t* label, int64_t* wt,
+                       int32_t nlab, const int64_t* capv, int64_t caps, uint32_t* fav, int64_t* moves_out,
+                       int32_t ipflags)
+{
+    if (ipflags & OR_LP_ASYNC) return or_lp_async(g, level, seed, tag, label, wt, nlab, capv, caps, fav, moves_out);
+    return or_lp(g, level, seed, tag, label, wt, nlab, capv, caps, fav, moves_out);
 }
 
 /* ---------------- O4: two-hop clustering --------------------------------
@@ -1456,7 +1574,7 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
             fav[v] = OR_NONE;
         }
         memset(lp_moves, 0, sizeof(lp_moves));
-        int32_t rr = or_lp(g, L, seed, T_CL, label, cw, g->n, NULL, U, fav, lp_moves);
+        int32_t rr = lp_call(g, L, seed, T_CL, label, cw, g->n, NULL, U, fav, lp_moves, ipflags);
         if (rr < 0) return rr;
         for (int i = 0; i < OR_ROUNDS; ++i)
             if (st) st->lp_cluster_moves += lp_moves[i];
@@ -1525,7 +1643,7 @@ int or_partition_traced(int32_t n, const int32_t* xadj, const int32_t* adjncy, c
         if (st) st->balance_rounds += brounds;
         trace(tfn, tuser, TR_BALANCE, l, part, g->n);
         memset(lp_moves, 0, sizeof(lp_moves));
-        int32_t rr = or_lp(g, l, seed, T_REF, part, bw, nb, cap, 0, NULL, lp_moves);
+        int32_t rr = lp_call(g, l, seed, T_REF, part, bw, nb, cap, 0, NULL, lp_moves, ipflags);
         if (rr < 0) return rr;
         for (int i = 0; i < OR_ROUNDS; ++i)
             if (st) st->lp_refine_moves += lp_moves[i];
@@ -1594,6 +1712,16 @@ int32_t or_step_lp_generic(int32_t n, const int32_t* xadj, const int32_t* adjncy
 {
     or_graph g = view(n, xadj, adjncy, vwgt, adjwgt);
     return or_lp(&g, level, seed, tag, label, wt, nlab, capv, caps, fav, moves);
+}
+
+/* O3b from an arbitrary state. */
+int32_t or_step_lp_async(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
+                         const int32_t* adjwgt, int32_t level, uint32_t tag, uint64_t seed, int32_t* label,
+                         int64_t* wt, int32_t nlab, const int64_t* capv, int64_t caps, uint32_t* fav,
+                         int64_t* moves)
+{
+    or_graph g = view(n, xadj, adjncy, vwgt, adjwgt);
+    return or_lp_async(&g, level, seed, tag, label, wt, nlab, capv, caps, fav, moves);
 }
 
 int64_t or_step_two_hop(int32_t n, const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
