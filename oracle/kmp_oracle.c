@@ -447,10 +447,14 @@ int32_t or_lp(const or_graph* g, int32_t level, uint64_t seed, uint32_t tag, int
  * Sec. 5.1 "Iteration Order": nodes are visited by exponentially spaced
  * degree buckets, bucket i holding the degrees 2^i <= d < 2^(i+1).
  *
- * A parallel run may interleave the visits in any way; this function is the
- * execution by a single processing element, which fixes one of them: nodes in
- * ascending (bucket, id), degree 0 with bucket 0 (the paper's shuffling
- * inside chunks is left out).  An active node is rated against the current
+ * The paper splits the buckets into chunks and randomises the traversal
+ * between and inside chunks.  Reading: the chunks are the hash classes of O2
+ * (a random quarter of the nodes each), taken in ascending class order, and
+ * inside a class the nodes go by (bucket, id), degree 0 with bucket 0; one
+ * class at a time runs concurrently, so moves of earlier classes are seen.
+ * A parallel run may interleave the visits inside a class in any way; this
+ * function is the execution by a single processing element, which visits in
+ * ascending (class, bucket, id).  An active node is rated against the current
  * labels and weights with the key order and tie-break hash of O3 (the round
  * and the node's label, no sub-round), moves to the best cluster that fits
  * (current weight + c(v) <= bound) if its rating beats the rating of its own
@@ -482,11 +486,12 @@ int32_t or_lp_async(const or_graph* g, int32_t level, uint64_t seed, uint32_t ta
         free(order); free(rating); free(touched); free(active); free(moved);
         return OR_ENOMEM;
     }
-    /* visit order: buckets ascending, ids ascending inside a bucket */
+    /* visit order: classes ascending, then buckets ascending, then ids */
     int32_t pos = 0;
-    for (int32_t b = 0; b < 32; ++b)
-        for (int32_t v = 0; v < n; ++v)
-            if (deg_bucket(g->xadj[v + 1] - g->xadj[v]) == b) order[pos++] = v;
+    for (uint32_t s = 0; s < OR_S; ++s)
+        for (int32_t b = 0; b < 32; ++b)
+            for (int32_t v = 0; v < n; ++v)
+                if (sub_class(seed, level, v) == s && deg_bucket(g->xadj[v + 1] - g->xadj[v]) == b) order[pos++] = v;
     memset(active, 1, (size_t)n);
     int32_t rounds = 0;
     for (int32_t r = 0; r < OR_ROUNDS; ++r) {

@@ -5,14 +5,16 @@ oracle exactly.
 Sec. 5.1 "Parallelization": the asynchronous mode updates cluster weights at
 once, so a node visited later sees every earlier move.  Sec. 5.1 "Iteration
 Order": nodes are visited by exponentially spaced degree buckets
-(2^i <= d < 2^(i+1)).  Executed by one processing element this is a
-sequential LP: visits in ascending (bucket, id), each against the current
-state, with the rounds, early exit and active rule of the deterministic LP
+(2^i <= d < 2^(i+1)), split into chunks traversed in random order; the
+reading takes the hash classes of the sub-round LP as those chunks, class
+by class.  Executed by one processing element this is a sequential LP:
+visits in ascending (class, bucket, id), each against the current state,
+with the rounds, early exit and active rule of the deterministic LP
 (Sec. 5.1 Coarsening, Sec. 5.3 Local Improvement).
 
 Each test also checks that its cases exercise the rule: immediate updates
 change the result against rating a round's nodes on its start state, the
-bucket order changes it against plain id order, and later rounds move.
+bucket order and the class order each change it, and later rounds move.
 """
 import numpy as np
 import pytest
@@ -26,9 +28,10 @@ def _bucket(d):
     return 0 if d <= 1 else int(d).bit_length() - 1
 
 
-def _visit_order(g):
+def _visit_order(g, seed, level, classes=True, buckets=True):
     deg = np.diff(np.asarray(g.xadj, np.int64))
-    return sorted(range(g.n), key=lambda v: (_bucket(int(deg[v])), v))
+    return sorted(range(g.n), key=lambda v: (oracle.sub_class(seed, level, v) if classes else 0,
+                                             _bucket(int(deg[v])) if buckets else 0, v))
 
 
 def _rate_one(A, label, v, nlab):
@@ -45,7 +48,7 @@ def _async_call(g, level, tag, seed, label, wt, cap, order=None, immediate=True)
     c = node_w(g)
     n = g.n
     nlab = wt.shape[0]
-    order = _visit_order(g) if order is None else order
+    order = _visit_order(g, seed, level) if order is None else order
     label, wt = label.copy(), wt.copy()
     fav = {}
     active = np.ones(n, bool)
@@ -90,6 +93,7 @@ def test_async_lp_restated_visit_by_visit(tag):
     later_rounds = 0  # cases whose later rounds moved something
     sees_moves = 0    # cases where seeing earlier moves at once changed the result
     bucket_order = 0  # cases where the degree-bucket order changed the result against id order
+    class_order = 0   # cases where the class order changed the result against bucket order alone
     for seed, g in _cases():
         n = g.n
         c = node_w(g)
@@ -124,11 +128,14 @@ def test_async_lp_restated_visit_by_visit(tag):
         later_rounds += any(m > 0 for m in exp_moves[1:])
         jac = _async_call(g, level, t, hseed, label, wt, cap, immediate=False)
         sees_moves += not np.array_equal(jac[0], exp_label)
-        ids = _async_call(g, level, t, hseed, label, wt, cap, order=list(range(n)))
+        ids = _async_call(g, level, t, hseed, label, wt, cap, order=_visit_order(g, hseed, level, buckets=False))
         bucket_order += not np.array_equal(ids[0], exp_label)
+        nocl = _async_call(g, level, t, hseed, label, wt, cap, order=_visit_order(g, hseed, level, classes=False))
+        class_order += not np.array_equal(nocl[0], exp_label)
     assert later_rounds >= 5
     assert sees_moves >= 10
     assert bucket_order >= 5
+    assert class_order >= 5
 
 
 def test_async_lp_weights_follow_labels_and_clusters_respect_bound():
