@@ -100,6 +100,18 @@ typedef struct kmp_options {
     int32_t pq_balance;     /* reserved for the queue balancer of paper Sec. 5.3 (per overloaded block a
                                queue of just enough nodes by relative gain, re-insertion, neighbour offers).
                                It is switched off in this version: any value but 0 gives KMP_EINVAL. */
+    int32_t async_lp;       /* every LP call (coarsening and refinement) in the asynchronous mode of paper
+                               Sec. 5.1 "Parallelization" / Sec. 5.3 "Local Improvement" instead of the
+                               deterministic sub-rounds: nodes visited by degree bucket floor(log2 d) then
+                               id (Sec. 5.1 "Iteration Order"), all at once, each rated against the current
+                               labels and weights and moved at once; clustering updates the two cluster
+                               weights with fetch-and-add after checking the bound against the weights it
+                               read (concurrent moves may exceed U, as in the paper), refinement reserves
+                               the target's weight with compare-and-swap (the bound holds strictly).
+                               0: deterministic (the default); 1: asynchronous (the output may differ from
+                               run to run); 2: asynchronous executed one node per launch in visit order,
+                               the execution by a single processing element (deterministic; for tests,
+                               slow); other values: KMP_EINVAL.  The output depends on it. */
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */
@@ -470,6 +482,26 @@ int64_t kmp_lp_subround(const int32_t* xadj, const int32_t* adjncy, const int32_
                         uint64_t seed, int32_t* label, int64_t* wt, int32_t nlab, const int64_t* cap_vec,
                         int64_t cap_scalar, const uint8_t* active, uint32_t* fav, uint8_t* moved,
                         void* stream);
+
+/*
+ * kmp_lp_async: a whole LP call in the asynchronous mode described at
+ * kmp_options.async_lp (paper Sec. 5.1 "Parallelization" and "Iteration
+ * Order", Sec. 5.3 "Local Improvement") from an arbitrary state: at most 5
+ * rounds, stop after a round without moves, round r > 0 rates only nodes with
+ * a neighbour that moved in round r - 1.  tag 2: clustering (fetch-and-add,
+ * the bound may be exceeded by concurrent moves); tag 3: refinement
+ * (compare-and-swap, the bound holds strictly); other tags: KMP_EINVAL.
+ * label[n] in [0, nlab) and wt[nlab] (int64, the label sums) are updated; the
+ * bound of label K is cap_vec[K] if cap_vec is non-NULL, else cap_scalar;
+ * fav[n] (may be NULL) receives the favoured label of every rated node
+ * (0xFFFFFFFF = none).  serial = 1 runs one node per launch in visit order
+ * (deterministic, slow; 0 or 1, else KMP_EINVAL).  moves[5] (host, may be
+ * NULL) receives moves per round.  Returns the rounds run or an error.
+ */
+int kmp_lp_async(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt, int32_t n,
+                 int32_t level, uint32_t tag, uint64_t seed, int32_t* label, int64_t* wt, int32_t nlab,
+                 const int64_t* cap_vec, int64_t cap_scalar, uint32_t* fav, int64_t* moves, int32_t serial,
+                 void* stream);
 
 #ifdef __cplusplus
 }

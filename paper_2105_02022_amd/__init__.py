@@ -33,7 +33,7 @@ class KmpOptions(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
                 ("force_exact", ctypes.c_int32), ("small_level_n", ctypes.c_int32), ("plain_loads", ctypes.c_int32),
                 ("fm_passes", ctypes.c_int32), ("ip_pool", ctypes.c_int32), ("adaptive_eps", ctypes.c_int32),
-                ("pq_balance", ctypes.c_int32)]
+                ("pq_balance", ctypes.c_int32), ("async_lp", ctypes.c_int32)]
 
 
 class KmpStats(ctypes.Structure):
@@ -120,6 +120,8 @@ SIGNATURES = {
     "kmp_lp_refine": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u64, _vp, _vp, _i32, _vp, _P64, _vp]),
     "kmp_lp_subround": (_i64, [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _u32, _u64, _vp, _vp, _i32, _vp, _i64,
                                _vp, _vp, _vp, _vp]),
+    "kmp_lp_async": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i32, _i32, _u32, _u64, _vp, _vp, _i32, _vp, _i64, _vp, _P64,
+                                    _i32, _vp]),
 }
 
 _lib = None
@@ -227,7 +229,8 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
                      profile_classes=None, force_exact: bool = False,
                      small_level_n: int = 0, plain_loads: bool = False,
                      fm_passes: int = 0, ip_pool: bool = False,
-                     adaptive_eps: bool = False, pq_balance: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+                     adaptive_eps: bool = False, pq_balance: bool = False,
+                     async_lp: int = 0) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
     (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path.
     `small_level_n`: largest level run by the one-workgroup LP (0 default, -1 never).
@@ -235,7 +238,8 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     `fm_passes`: 2-way FM passes after every greedy growth (0..16; 0 = none).
     `ip_pool`: the initial bipartitioning also runs BFS and random growths.
     `adaptive_eps`: bipartitions bound their sides by the adaptive imbalance (paper Sec. 2, Alg. 2).
-    `pq_balance`: the queue balancer of paper Sec. 5.3 instead of sorted rounds."""
+    `pq_balance`: the queue balancer of paper Sec. 5.3 instead of sorted rounds.
+    `async_lp`: 1 = asynchronous LP (paper Sec. 5.1 / 5.3), 2 = the same one node per launch (tests)."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -251,6 +255,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt.ip_pool = int(ip_pool)
     opt.adaptive_eps = int(adaptive_eps)
     opt.pq_balance = int(pq_balance)
+    opt.async_lp = int(async_lp)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -264,7 +269,8 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
 def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, seed: int = 1, out=None,
                           stream=None, validate: bool = False, force_exact: bool = False, small_level_n: int = 0,
                           fm_passes: int = 0, ip_pool: bool = False,
-                          adaptive_eps: bool = False, pq_balance: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
+                          adaptive_eps: bool = False, pq_balance: bool = False,
+                          async_lp: int = 0) -> Tuple[int, "torch.Tensor", Dict]:
     """kmp_partition_noalloc: as kmp_partition_ex, with every device buffer inside the library's fixed
     scratch region (n <= NOALLOC_MAX_N, m <= NOALLOC_MAX_M, else KMP_ETOOLARGE).  `out` should be
     given by callers that must not allocate."""
@@ -281,6 +287,7 @@ def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0
     opt.ip_pool = int(ip_pool)
     opt.adaptive_eps = int(adaptive_eps)
     opt.pq_balance = int(pq_balance)
+    opt.async_lp = int(async_lp)
     st = KmpStats()
     rc = library().kmp_partition_noalloc(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
                                          epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream),
@@ -304,7 +311,8 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
                         profile_classes=None, force_exact: bool = False,
                         small_level_n: int = 0, plain_loads: bool = False,
                         fm_passes: int = 0, ip_pool: bool = False,
-                        adaptive_eps: bool = False, pq_balance: bool = False) -> Tuple[int, List[Dict], Dict]:
+                        adaptive_eps: bool = False, pq_balance: bool = False,
+                        async_lp: int = 0) -> Tuple[int, List[Dict], Dict]:
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
@@ -322,6 +330,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     opt.ip_pool = int(ip_pool)
     opt.adaptive_eps = int(adaptive_eps)
     opt.pq_balance = int(pq_balance)
+    opt.async_lp = int(async_lp)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -381,13 +390,14 @@ class Server:
         return out
 
     def set_options(self, fm_passes: int = 0, ip_pool: bool = False, adaptive_eps: bool = False,
-                    pq_balance: bool = False) -> int:
-        """Initial-bipartitioning options for jobs submitted from now on (kmp_server_set_options)."""
+                    pq_balance: bool = False, async_lp: int = 0) -> int:
+        """Options for jobs submitted from now on (kmp_server_set_options)."""
         o = KmpOptions()
         o.fm_passes = int(fm_passes)
         o.ip_pool = int(ip_pool)
         o.adaptive_eps = int(adaptive_eps)
         o.pq_balance = int(pq_balance)
+        o.async_lp = int(async_lp)
         return library().kmp_server_set_options(self._h, ctypes.byref(o))
 
     def poll(self, jid: int) -> Optional[Dict]:
@@ -517,6 +527,19 @@ def kmp_lp_subround(xadj, adjncy, vwgt, adjwgt, level: int, round_: int, s: int,
     return library().kmp_lp_subround(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level, round_, s, tag,
                                      seed & (2**64 - 1), _ptr(label), _ptr(wt), wt.numel(), _ptr(cap_vec),
                                      cap_scalar, _ptr(active), _ptr(fav), _ptr(moved), _stream(stream))
+
+
+def kmp_lp_async(xadj, adjncy, vwgt, adjwgt, level: int, tag: int, seed: int, label, wt, cap_vec=None,
+                 cap_scalar: int = 0, fav=None, serial: bool = False, stream=None):
+    """kmp_lp_async: a whole asynchronous LP call (tag 2 clustering, 3 refinement); returns (rounds or error,
+    moves per round)."""
+    _check_i32(xadj, adjncy, vwgt, adjwgt, label)
+    n = xadj.numel() - 1
+    moves = (ctypes.c_int64 * 5)()
+    r = library().kmp_lp_async(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, level, tag,
+                               seed & (2**64 - 1), _ptr(label), _ptr(wt), wt.numel(), _ptr(cap_vec), cap_scalar,
+                               _ptr(fav), ctypes.cast(moves, _P64), int(serial), _stream(stream))
+    return r, list(moves)
 
 
 def to_device(g, device="cuda"):

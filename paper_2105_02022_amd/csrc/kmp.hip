@@ -309,6 +309,8 @@ struct Level {
     DBuf<int32_t> map;            // to the next coarser level (-1: the job's coarsest level is this one)
     std::unique_ptr<LPSchedule> sched;
     bool sched_full = false;      // the schedule holds every node (refinement can reuse it)
+    std::unique_ptr<LPSchedule> asched;  // asynchronous LP: visit-order schedule
+    bool asched_full = false;
     std::vector<int32_t> mem;     // member jobs, ascending
     std::vector<int64_t> moff;    // by member: first node; moff[mem.size()] = n
     std::vector<int32_t> nn;      // by job: nodes at this level
@@ -591,7 +593,11 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         }
         // a small single graph skips the schedule: its LP builds its own class lists
         const bool small_lp = !batch && L.maxdeg >= 0 && L.maxdeg <= c.tune.cut[1] && small_job_fits(c, g.n, g.n);
-        if (!small_lp) {
+        if (c.async_lp) {
+            L.asched.reset(new LPSchedule());
+            lp_build_async_schedule(c, g, l, seed0, *L.asched, jt, dtakes.p);
+            L.asched_full = full;
+        } else if (!small_lp) {
             L.sched.reset(new LPSchedule());
             lp_build_schedule(c, g, l, seed0, *L.sched, jt, dtakes.p, nj);
             L.sched_full = full;
@@ -604,9 +610,9 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
         KMP_LAUNCH_CHECK();
         LPState ls{label.p, cw.p, g.n, nullptr, batch ? 0 : U[0], fav.p, TAG_CL, jt,
                    batch ? L.dnoff.p : nullptr, batch ? dU.p : nullptr};
-        if (batch) pick_small_jobs(c, L, &takes, nj, ls);
+        if (batch && !c.async_lp) pick_small_jobs(c, L, &takes, nj, ls);
         ls.moves_out = dmoves.p;
-        LPStats lps = lp_run(c, g, l, seed0, small_lp ? nullptr : L.sched.get(), ls);
+        LPStats lps = lp_run(c, g, l, seed0, c.async_lp ? L.asched.get() : small_lp ? nullptr : L.sched.get(), ls);
         for (int r = 0; r < kRounds; ++r) t.moves_cl += lps.moves[r];
         t.exact += lps.exact_subrounds;
         std::vector<int64_t> nc;
@@ -775,13 +781,24 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
                                                             level_sched, part.p, wt.p, bt, cap.p, jt, dboff.p,
                                                             &hcap);
         LPState ls{part.p, wt.p, nb, cap.p, 0, nullptr, TAG_REF, jt, dboff.p, nullptr};
-        if (batch) {
+        if (batch && !c.async_lp) {
             std::vector<int32_t> nbk(nj, 0);
             for (int32_t b = 0; b < nb; ++b) ++nbk[bt.job[b]];
             pick_small_jobs(c, L, nullptr, nj, ls, &boff, &nbk);
         }
         ls.moves_out = dmoves.p + kRounds + 1;
-        LPStats lps = lp_run(c, g, l, seed0, small_lp ? nullptr : &level_sched(), ls);
+        const LPSchedule* rsched = nullptr;
+        if (c.async_lp) {
+            if (!L.asched || !L.asched_full) {
+                L.asched.reset(new LPSchedule());
+                lp_build_async_schedule(c, g, l, seed0, *L.asched, jt, nullptr);
+                L.asched_full = true;
+            }
+            rsched = L.asched.get();
+        } else if (!small_lp) {
+            rsched = &level_sched();
+        }
+        LPStats lps = lp_run(c, g, l, seed0, rsched, ls);
         for (int r = 0; r < kRounds; ++r) t.moves_ref += lps.moves[r];
         t.exact += lps.exact_subrounds;
         if (phase_sync) c.sync();
@@ -1112,7 +1129,9 @@ int set_ip_options(Ctx& c, const kmp_options* opt)
     if (opt && opt->adaptive_eps != 0 && opt->adaptive_eps != 1) return KMP_EINVAL;
     // the GPU queue balancer is switched off: its first GPU run faulted and the cause is not yet shown
     if (opt && opt->pq_balance != 0) return KMP_EINVAL;
+    if (opt && (opt->async_lp < 0 || opt->async_lp > 2)) return KMP_EINVAL;
     c.fm_passes = opt ? opt->fm_passes : 0;
+    c.async_lp = opt ? opt->async_lp : 0;
     c.ip_pool = opt && opt->ip_pool;
     c.adaptive_eps = opt && opt->adaptive_eps;
     c.pq_balance = opt && opt->pq_balance;
@@ -1425,6 +1444,35 @@ int64_t kmp_lp_subround(const int32_t* xadj, const int32_t* adjncy, const int32_
         int64_t r = lp_subround(c, g, level, round, s, seed, sched, ls, active, moved);
         c.sync();
         return r;
+    });
+}
+
+int kmp_lp_async(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt, int32_t n,
+                 int32_t level, uint32_t tag, uint64_t seed, int32_t* label, int64_t* wt, int32_t nlab,
+                 const int64_t* cap_vec, int64_t cap_scalar, uint32_t* fav, int64_t* moves, int32_t serial,
+                 void* stream)
+{
+    if (n < 0 || nlab < 1 || (tag != TAG_CL && tag != TAG_REF) || (serial != 0 && serial != 1) ||
+        (n > 0 && (!xadj || !label || !wt)))
+        return KMP_EINVAL;
+    if (moves)
+        for (int r = 0; r < kRounds; ++r) moves[r] = 0;
+    if (n == 0) return 0;
+    return (int)guarded([&]() -> int64_t {
+        init_pool_once();
+        Ctx c((hipStream_t)stream);
+        c.async_lp = serial ? 2 : 1;
+        int32_t m32 = 0;
+        c.read(&m32, xadj + n, sizeof(int32_t));
+        DGraph g = make_graph(xadj, adjncy, vwgt, adjwgt, n, m32);
+        LPSchedule sched;
+        lp_build_async_schedule(c, g, level, seed, sched);
+        LPState ls{label, wt, nlab, cap_vec, cap_scalar, fav, tag};
+        LPStats r = lp_run(c, g, level, seed, &sched, ls);
+        c.sync();
+        if (moves)
+            for (int q = 0; q < kRounds; ++q) moves[q] = r.moves[q];
+        return r.rounds;
     });
 }
 

@@ -362,6 +362,8 @@ class Ctx {
     bool ip_pool = false;        // initial bipartitioning also runs BFS and random growths
     bool adaptive_eps = false;   // bipartition sides bounded by the adaptive imbalance
     bool pq_balance = false;     // balancing by the queue balancer
+    int32_t async_lp = 0;        // LP: 0 deterministic sub-rounds, 1 asynchronous, 2 asynchronous one node
+                                 // per launch in visit order (the one-processing-element execution)
     int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0: tune's, < 0 never)
     Tuning tune;                 // the process-wide tuning when the call started
     int prof_begin(int cls);
@@ -593,7 +595,14 @@ struct LPSchedule {
 // only the nodes of jobs with gpart[job] != 0 are scheduled (gpart NULL: all).
 void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched,
                        const JobTabs& jt = {}, const uint8_t* gpart = nullptr, int32_t njobs = 0);
+// Visit-order schedule of the asynchronous LP: segments (tier, class) as in
+// lp_build_schedule, each in (degree bucket, id) order, tiers aligned to
+// buckets.  Only the nodes of jobs with gpart[job] != 0 are scheduled (gpart
+// NULL: all).
+void lp_build_async_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched,
+                             const JobTabs& jt = {}, const uint8_t* gpart = nullptr);
 // Rated entries accumulate in the context's SP_RATED spread counter.
+// With c.async_lp set, sched must be an asynchronous schedule.
 // sched NULL: a single graph whose level the caller found small (at most the
 // one-workgroup cut-off, no degree above the tier-1 cut-off, state fits LDS).
 LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule* sched, LPState& st);

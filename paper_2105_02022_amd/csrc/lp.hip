@@ -140,6 +140,50 @@ __global__ void k_hub_scatter(const int32_t* __restrict__ hubs, const int64_t* _
     if (i < nh) off_by_node[hubs[i]] = incl[i] - slots[i];
 }
 
+// Visit order of the asynchronous LP (paper Sec. 5.1 "Iteration Order"): the
+// buckets' random chunks are the sub-round hash classes, taken one after
+// another; inside a class the nodes go by degree bucket floor(log2 d) (degree
+// 0 with bucket 0), then id.  A rating tier takes whole buckets (tier t the
+// buckets up to blim[t]), so the class-s nodes of tier t are one contiguous
+// segment (t, s) in (bucket, id) order.  The sort key is 32 * segment +
+// bucket; nodes of jobs that do not take part get segment kSegs.
+struct BucketCuts {
+    int32_t blim[4];
+};
+
+__device__ inline int deg_bucket(int32_t d) { return d <= 1 ? 0 : 31 - __clz(d); }
+
+__global__ __launch_bounds__(kBlock) void k_async_keys(const int32_t* __restrict__ xadj, int32_t n, uint32_t hsub,
+                                                       JobTabs jt, const uint8_t* __restrict__ gpart, uint32_t level,
+                                                       BucketCuts bc, uint32_t* __restrict__ key,
+                                                       uint32_t* __restrict__ val, int32_t* __restrict__ cnt)
+{
+    __shared__ int32_t h[kSegs + 1];
+    if (threadIdx.x <= kSegs) h[threadIdx.x] = 0;
+    __syncthreads();
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (int64_t)gridDim.x * blockDim.x) {
+        uint32_t hs = hsub, vl = (uint32_t)v;
+        bool takes = true;
+        if (jt.gid) {  // the class hash of the node's own job, on its job-local id
+            const int32_t j = jt.gid[v];
+            hs = hash_step(hash_step(jt.ghash[j], TAG_SUB, 1), level, 2);
+            vl = (uint32_t)(v - jt.noff[j]);
+            takes = !gpart || gpart[j];
+        }
+        const uint32_t cls = hash_step(hs, vl, 3) % kSub;
+        const int b = deg_bucket(xadj[v + 1] - xadj[v]);
+        int t = kTiers - 1;
+        for (int q = kTiers - 2; q >= 0; --q)
+            if (b <= bc.blim[q]) t = q;
+        const uint32_t seg = takes ? (uint32_t)t * kSub + cls : (uint32_t)kSegs;
+        key[v] = 32 * seg + (uint32_t)b;
+        val[v] = (uint32_t)v;
+        atomicAdd(&h[seg], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x <= kSegs && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+}
+
 // ---------------------------------------------------------------- rating
 struct Key3 {
     uint32_t r, h, k;  // rating (0 = none), hash, label
@@ -227,6 +271,16 @@ struct RateArgs {
     // every byte offset fits the 32-bit offset of a buffer load)
     uint32_t nr_adj, nr_lab;
     int32_t bufok;
+    // asynchronous LP (amode != 0): a node that finds a better admissible label
+    // moves at once.  1: fetch-and-add on the two weights (clustering: the bound
+    // was checked against the weights the node read, so concurrent moves may
+    // exceed it); 2: compare-and-swap on the target's weight keeps the bound
+    // strictly (refinement).  label_w aliases label; a mover gets mflag[v] =
+    // stamp and is counted in moved_ctr (spread counter).
+    int32_t amode;
+    int32_t* label_w;
+    uint8_t* mflag;
+    int64_t* moved_ctr;
 };
 
 // Buffer loads for gathers (gfx9 raw buffer descriptor): an offset at or past
@@ -260,19 +314,46 @@ __device__ inline bool node_selected(const RateArgs& a, int32_t v)
     return !a.active || a.active[v] == a.stamp;
 }
 
-__device__ inline void write_result(const RateArgs& a, int32_t v, const Key3& fav, const Key3& adm, uint32_t rown,
-                                    int64_t cv)
+// Asynchronous move of v from `own` to t (weight cv); returns 1 if it moved.
+__device__ inline int async_move(const RateArgs& a, int32_t v, uint32_t own, uint32_t t, int64_t cv)
+{
+    unsigned long long* w = reinterpret_cast<unsigned long long*>(const_cast<int64_t*>(a.wt));
+    if (a.amode == 2) {
+        const int64_t cap = a.cap_vec ? a.cap_vec[t] : a.gcap ? a.gcap[a.gid[v]] : a.cap_scalar;
+        unsigned long long old = w[t];
+        // every failed exchange returns a weight another move wrote, and a launch
+        // moves every node at most once, so the loop ends
+        while ((int64_t)old + cv <= cap) {
+            const unsigned long long seen = atomicCAS(&w[t], old, old + (unsigned long long)cv);
+            if (seen == old) break;
+            old = seen;
+        }
+        if ((int64_t)old + cv > cap) return 0;
+    } else {
+        atomicAdd(&w[t], (unsigned long long)cv);
+    }
+    atomicAdd(&w[own], (unsigned long long)(-cv));
+    a.label_w[v] = (int32_t)t;
+    a.mflag[v] = a.stamp;
+    return 1;
+}
+
+// Returns 1 if the node moved (asynchronous mode), else 0.
+__device__ inline int write_result(const RateArgs& a, int32_t v, uint32_t own, const Key3& fav, const Key3& adm,
+                                   uint32_t rown, int64_t cv)
 {
     if (a.over) {
         a.bal_t[v] = adm.r ? (int32_t)adm.k : -1;
         a.bal_d[v] = adm.r ? (int64_t)adm.r - (int64_t)rown : -(int64_t)rown;
-        return;
+        return 0;
     }
     if (a.fav) a.fav[v] = fav.r ? fav.k : kNone;
     if (adm.r > rown) {
+        if (a.amode) return async_move(a, v, own, adm.k, cv);
         a.prop[v] = (int32_t)adm.k;
         atomicAdd(&a.demand[adm.k], (uint32_t)cv);
     }
+    return 0;
 }
 
 // Evaluate one aggregated (label, rating) entry for the lane-local bests.
@@ -294,13 +375,17 @@ __device__ inline void consider(const RateArgs& a, const NodeKey& nk, uint32_t k
 
 // per-wave statistic: rated entries and algorithmic bytes (a wave rates fewer
 // than 2^31 entries: a single graph has fewer, batches stay below 2^31)
-__device__ inline void flush_stats(const RateArgs& a, int64_t nodes_in, int64_t edges_in)
+__device__ inline void flush_stats(const RateArgs& a, int64_t nodes_in, int64_t edges_in, int64_t moves_in = 0)
 {
     const int64_t edges = group_sum_u32<64>((uint32_t)edges_in);
     const int64_t nodes = group_sum_u32<64>((uint32_t)nodes_in);
     if ((threadIdx.x & 63) == 0 && nodes) {
         spread_add(a.counters, edges);
         spread_add(a.bytes_ctr, 25 * nodes + (a.adjwgt ? 12 : 8) * edges);
+    }
+    if (a.moved_ctr) {  // uniform: asynchronous mode only
+        const int64_t moves = group_sum_u32<64>((uint32_t)moves_in);
+        if ((threadIdx.x & 63) == 0 && moves) spread_add(a.moved_ctr, moves);
     }
 }
 
@@ -311,8 +396,8 @@ __device__ inline void flush_stats(const RateArgs& a, int64_t nodes_in, int64_t 
 // with selects.  EW: edge weights present; CAPV: per-label caps; BAL: balance
 // mode.
 template <int DEG, bool EW, bool CAPV, bool BAL, bool BUF>
-__device__ inline void rate_lane_node(const RateArgs& a, int32_t v, uint32_t own, int32_t e0, int32_t d, int64_t cv,
-                                      const NodeKey& nk)
+__device__ inline int rate_lane_node(const RateArgs& a, int32_t v, uint32_t own, int32_t e0, int32_t d, int64_t cv,
+                                     const NodeKey& nk)
 {
     uint32_t lab[DEG], w[DEG];
     if (d > 0) {
@@ -389,7 +474,7 @@ __device__ inline void rate_lane_node(const RateArgs& a, int32_t v, uint32_t own
             if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
         }
     }
-    write_result(a, v, fav, adm, rown, cv);
+    return write_result(a, v, own, fav, adm, rown, cv);
 }
 
 // A tier-0 segment lists its nodes of degree <= T0_NARROW first, so most
@@ -399,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
 {
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
-    int64_t edges = 0, nodes = 0;
+    int64_t edges = 0, nodes = 0, moves = 0;
     for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < count;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int32_t v = a.list[off + i];
@@ -413,12 +498,12 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
         const int32_t d = a.xadj[v + 1] - e0;
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
         const NodeKey nk = node_key(a, v);
-        if (ballot64(d > T0_NARROW)) rate_lane_node<T0_DEG, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
-        else rate_lane_node<T0_NARROW, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
+        if (ballot64(d > T0_NARROW)) moves += rate_lane_node<T0_DEG, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
+        else moves += rate_lane_node<T0_NARROW, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
         edges += d;
         nodes += 1;
     }
-    flush_stats(a, nodes, edges);
+    flush_stats(a, nodes, edges, moves);
 }
 
 __device__ inline void lds_insert(uint32_t* keys, uint32_t* vals, int bits, uint32_t K, uint32_t w)
@@ -451,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
     const int grp = tid / G, gl = tid % G;
     uint32_t* keys = s_keys + grp * HS;
     uint32_t* vals = s_vals + grp * HS;
-    int64_t edges = 0, nodes = 0;
+    int64_t edges = 0, nodes = 0, moves = 0;
     for (int64_t base = (int64_t)xcd_block() * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
         const int64_t i = base + grp;
         int32_t v = -1;
@@ -488,10 +573,10 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
         }
         __syncthreads();
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
-        uint32_t rown = 0;
+        uint32_t rown = 0, own = 0;
         int64_t cv = 0;
         if (v >= 0) {
-            const uint32_t own = (uint32_t)a.label[v];
+            own = (uint32_t)a.label[v];
             const NodeKey nk = node_key(a, v);
             cv = a.vwgt ? a.vwgt[v] : 1;
             for (int j = gl; j < hsn; j += G) consider(a, nk, keys[j], vals[j], own, cv, fav, adm, rown);
@@ -519,10 +604,10 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
                 }
             }
         }
-        if (v >= 0 && gl == 0) write_result(a, v, fav, adm, rown, cv);
+        if (v >= 0 && gl == 0) moves += write_result(a, v, own, fav, adm, rown, cv);
         __syncthreads();
     }
-    flush_stats(a, nodes, edges);
+    flush_stats(a, nodes, edges, moves);
 }
 
 // Tier 4: hubs.  Each hub has a global hash table of 2^b >= 2 d slots (64-bit
@@ -693,7 +778,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_final(RateArgs a)
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     const int lane = threadIdx.x & 63;
     constexpr int kWaves = kBlock / 64;
-    int64_t edges = 0, nodes = 0;
+    int64_t edges = 0, nodes = 0, moves = 0;
     for (int64_t i = (int64_t)xcd_block() * kWaves + (threadIdx.x >> 6); i < count;
          i += (int64_t)gridDim.x * kWaves) {
         const int32_t c0 = a.hub_plan[i], c1 = a.hub_plan[i + 1];
@@ -712,12 +797,12 @@ __global__ __launch_bounds__(kBlock) void k_hub_final(RateArgs a)
         adm = group_best<64>(adm);
         rown = group_sum_u32<64>(rown);
         if (lane == 0) {
-            write_result(a, v, fav, adm, rown, a.vwgt ? a.vwgt[v] : 1);
+            moves += write_result(a, v, (uint32_t)a.label[v], fav, adm, rown, a.vwgt ? a.vwgt[v] : 1);
             edges += a.xadj[v + 1] - a.xadj[v];
             nodes += 1;
         }
     }
-    flush_stats(a, nodes, edges);
+    flush_stats(a, nodes, edges, moves);
 }
 
 // ---------------------------------------------------------------- admission
@@ -1553,6 +1638,8 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
 
 // ================================================================ host side
 
+void hub_tables(Ctx& c, const DGraph& g, LPSchedule& sched);
+
 void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched, const JobTabs& jt,
                        const uint8_t* gpart, int32_t njobs)
 {
@@ -1602,6 +1689,13 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
         tab[kSegs + j] = sched.cnt[j];
     }
     c.write(sched.segtab.p, tab, sizeof(tab));
+    hub_tables(c, g, sched);
+}
+
+// Global hash tables of the hubs (the last tier, all classes contiguous).
+void hub_tables(Ctx& c, const DGraph& g, LPSchedule& sched)
+{
+    const int32_t n = g.n;
     sched.hub_start = sched.off[(kTiers - 1) * kSub];
     const int32_t nh = sched.off[kSegs] - sched.hub_start;
     if (nh > 0) {
@@ -1616,6 +1710,60 @@ void lp_build_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LP
                            sched.hub_slot_off.p);
         KMP_LAUNCH_CHECK();
     }
+}
+
+void lp_build_async_schedule(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSchedule& sched,
+                             const JobTabs& jt, const uint8_t* gpart)
+{
+    const int32_t n = g.n;
+    sched.order = DBuf<int32_t>(c, (size_t)n);
+    memset(sched.off, 0, sizeof(sched.off));
+    memset(sched.cnt, 0, sizeof(sched.cnt));
+    sched.hub_slots_total = 0;
+    sched.hub_start = n;
+    sched.segtab = DBuf<int32_t>(c, 2 * kSegs);
+    if (n == 0) {
+        c.zero(sched.segtab.p, sizeof(int32_t) * 2 * kSegs);
+        return;
+    }
+    DBuf<uint32_t> key(c, n), key2(c, n);
+    DBuf<int32_t> val(c, n), val2(c, n);
+    DBuf<int32_t> cnt(c, kSegs + 1);
+    c.zero(cnt.p, (kSegs + 1) * sizeof(int32_t));
+    // tier t takes the buckets b with 2^(b+1) - 1 <= its degree cut-off
+    BucketCuts bc;
+    for (int t = 0; t < 4; ++t) {
+        int b = -1;
+        while ((int64_t(2) << (b + 1)) - 1 <= c.tune.cut[t]) ++b;
+        bc.blim[t] = b;
+    }
+    const uint32_t hsub = hash_prefix(seed, {TAG_SUB, (uint32_t)level});
+    {
+        ProfScope ps(c, KMP_PROF_SCHEDULE);
+        hipLaunchKernelGGL(k_async_keys, dim3(grid_for(n, kBlock, 1024)), dim3(kBlock), 0, c.stream, g.xadj, n, hsub,
+                           jt, gpart, (uint32_t)level, bc, key.p, reinterpret_cast<uint32_t*>(val.p), cnt.p);
+        KMP_LAUNCH_CHECK();
+    }
+    uint32_t* sorted = nullptr;
+    radix_sort_pairs(c, key.p, reinterpret_cast<uint32_t*>(val.p), key2.p, reinterpret_cast<uint32_t*>(val2.p), n,
+                     bits_for(32 * kSegs + 31), nullptr, &sorted);
+    sched.order = reinterpret_cast<int32_t*>(sorted) == val.p ? std::move(val) : std::move(val2);
+    int32_t h[kSegs + 1];
+    c.read(h, cnt.p, sizeof(h));
+    int32_t pos = 0;
+    for (int j = 0; j < kSegs; ++j) {
+        sched.off[j] = pos;
+        sched.cnt[j] = h[j];
+        pos += h[j];
+    }
+    sched.off[kSegs] = pos;
+    int32_t tab[2 * kSegs];
+    for (int j = 0; j < kSegs; ++j) {
+        tab[j] = sched.off[j];
+        tab[kSegs + j] = sched.cnt[j];
+    }
+    c.write(sched.segtab.p, tab, sizeof(tab));
+    hub_tables(c, g, sched);
 }
 
 namespace {
@@ -2128,12 +2276,103 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
     return out;
 }
 
+// Asynchronous LP (paper Sec. 5.1 "Parallelization", Sec. 5.3 "Local
+// Improvement") over an asynchronous schedule: per round and class one rating
+// launch per tier, each rated node moving at once (clustering: fetch-and-add,
+// refinement: compare-and-swap), so later classes see the moves of earlier
+// ones; then the neighbours of the round's movers are marked for the next
+// round.  Serial mode (c.async_lp == 2) launches the kernels once per node in
+// visit order, which is the execution by one processing element.
+LPStats lp_async_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule& sched, LPState& st)
+{
+    LPStats out;
+    const int32_t n = g.n;
+    HubBufs hub;
+    hub_buffers(c, sched, hub);
+    DBuf<uint8_t> mflag(c, (size_t)n), active(c, 2 * (size_t)n);
+    DBuf<int64_t> ctl(c, kCtlWords);
+    fill_bytes_many(c, {{mflag.p, (int64_t)n, 0},
+                        {active.p, 2 * (int64_t)n, 0},
+                        {ctl.p, (int64_t)sizeof(int64_t) * kCtlWords, 0}});
+    const bool serial = c.async_lp == 2;
+    DBuf<int32_t> one;  // serial mode: every segment starts at 0 and holds one node
+    if (serial) {
+        int32_t tab[2 * kSegs];
+        for (int j = 0; j < kSegs; ++j) {
+            tab[j] = 0;
+            tab[kSegs + j] = 1;
+        }
+        one = DBuf<int32_t>(c, 2 * kSegs);
+        c.write(one.p, tab, sizeof(tab));
+    }
+    uint8_t* act[2] = {active.p, active.p + n};
+    int32_t mseg = 0;
+    for (int j = 0; j < kSegs; ++j) mseg = std::max(mseg, sched.cnt[j]);
+    auto launch_round = [&](int32_t r) {
+        RateArgs a = make_rate_args(c, g, st, hash_prefix(seed, {st.tag, (uint32_t)level, (uint32_t)r}), nullptr);
+        a.ctl = ctl.p;
+        set_hub_args(a, hub);
+        a.level = (uint32_t)level;
+        a.round = (uint32_t)r;
+        a.active = r == 0 ? nullptr : act[r & 1];
+        a.stamp = (uint8_t)(r + 1);
+        a.amode = st.tag == TAG_REF ? 2 : 1;
+        a.label_w = st.label;
+        a.mflag = mflag.p;
+        a.moved_ctr = ctl.p + CTL_MS + r * kSpreadSlots;
+        for (int32_t s = 0; s < kSub; ++s) {
+            if (!serial) {
+                launch_rate(c, a, sched, s, sched.order.p, sched.segtab.p, sched.cnt);
+                continue;
+            }
+            for (int t = 0; t < kTiers; ++t) {
+                const int seg = t * kSub + s;
+                int32_t u1[kSegs] = {};
+                u1[seg] = 1;
+                const int32_t* base = sched.order.p + sched.off[seg];
+                for (int32_t p = 0; p < sched.cnt[seg]; ++p) launch_rate(c, a, sched, s, base + p, one.p, u1);
+            }
+        }
+        if (r + 1 < kRounds && mseg > 0) {
+            ProfScope ps(c, KMP_PROF_ACTIVE);
+            hipLaunchKernelGGL(k_push_active, dim3(grid_for(mseg, kBlock, 1024), kSegs), dim3(kBlock), 0, c.stream,
+                               ctl.p, sched.order.p, sched.segtab.p, mflag.p, (uint8_t)(r + 1), g.xadj, g.adjncy,
+                               act[(r + 1) & 1], (uint8_t)(r + 2), 0);
+            KMP_LAUNCH_CHECK();
+        }
+    };
+    int64_t moved[kRounds][kSpreadSlots];
+    // clustering enqueues every round before one read-back (a round after one
+    // without moves rates nothing); refinement reads the count after each round
+    const bool ahead = st.tag == TAG_CL;
+    for (int32_t r = 0; r < kRounds;) {
+        const int32_t last = ahead ? kRounds - 1 : r;
+        for (int32_t q = r; q <= last; ++q) launch_round(q);
+        c.read(moved, ctl.p + CTL_MS, sizeof(moved));
+        bool stop = false;
+        for (int32_t q = r; q <= last && !stop; ++q) {
+            int64_t nm = 0;
+            for (int k = 0; k < kSpreadSlots; ++k) nm += moved[q][k];
+            out.moves[q] = nm;
+            out.rounds = q + 1;
+            stop = nm == 0;
+        }
+        if (stop) break;
+        r = last + 1;
+    }
+    return out;
+}
+
 }  // namespace
 
 LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSchedule* sched_p, LPState& st)
 {
     const int32_t n = g.n;
     if (n == 0) return LPStats();
+    if (c.async_lp) {
+        if (!sched_p) throw Error(KMP_EHIP, "the asynchronous LP needs its visit-order schedule");
+        return lp_async_rounds(c, g, level, seed, *sched_p, st);
+    }
     if (!sched_p) {  // a small single graph: no schedule needed
         LPBuffers b;
         lp_buffers(c, g, nullptr, st.nlab, b);

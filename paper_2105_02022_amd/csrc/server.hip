@@ -27,7 +27,7 @@ struct kmp_server {
     using clk = std::chrono::steady_clock;
     struct Job {
         kmp_graph_desc d;
-        kmp_options opt = {};  // fm_passes, ip_pool, adaptive_eps and pq_balance current at submission
+        kmp_options opt = {};  // fm_passes, ip_pool, adaptive_eps, pq_balance, async_lp current at submission
         int size_class = 0;    // floor(log2(n + m + 1)) / 2
         size_t foot = 0;
         int state = 0;  // 0 waiting, 1 running, 2 done
@@ -46,7 +46,7 @@ struct kmp_server {
     int running = 0;
     bool stop = false;
     kmp_server_stats st = {};
-    kmp_options opt = {};  // fm_passes, ip_pool, adaptive_eps and pq_balance given to jobs submitted from now on
+    kmp_options opt = {};  // the options given to jobs submitted from now on
 };
 
 namespace kmp {
@@ -74,7 +74,7 @@ int size_class_of(const kmp_graph_desc& d)
 bool same_options(const kmp_options& a, const kmp_options& b)
 {
     return a.fm_passes == b.fm_passes && a.ip_pool == b.ip_pool && a.adaptive_eps == b.adaptive_eps &&
-           a.pq_balance == b.pq_balance;
+           a.pq_balance == b.pq_balance && a.async_lp == b.async_lp;
 }
 
 void worker_main(kmp_server* s, int w)
@@ -211,12 +211,14 @@ int kmp_server_set_options(kmp_server* s, const kmp_options* opt)
     kmp_options o = {};
     if (opt) {
         if (opt->fm_passes < 0 || opt->fm_passes > kmp::kFmMaxPasses || (opt->ip_pool != 0 && opt->ip_pool != 1) ||
-            (opt->adaptive_eps != 0 && opt->adaptive_eps != 1) || opt->pq_balance != 0)
+            (opt->adaptive_eps != 0 && opt->adaptive_eps != 1) || opt->pq_balance != 0 || opt->async_lp < 0 ||
+            opt->async_lp > 2)
             return KMP_EINVAL;
         o.fm_passes = opt->fm_passes;
         o.ip_pool = opt->ip_pool;
         o.adaptive_eps = opt->adaptive_eps;
         o.pq_balance = opt->pq_balance;
+        o.async_lp = opt->async_lp;
     }
     std::lock_guard<std::mutex> lk(s->mu);
     s->opt = o;
