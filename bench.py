@@ -24,6 +24,10 @@ ip_options: the same workload under the initial-bipartitioning options,
 and both (the timed steps use --fm-passes and --ip-pool, off by default):
 cut, time per partition without events, GGG class time, and the oracle's
 cut, time and parity for each.
+
+async_lp: the same workload (and each extra workload) with the asynchronous
+LP mode of paper Sec. 5.1 / 5.3 instead of the deterministic sub-rounds:
+time per partition and the cut of every run, beside the deterministic ones.
 """
 import argparse
 import json
@@ -292,6 +296,33 @@ def golden_parity(name, part, st):
             "cut_equal": st["cut"] == d["stats"]["cut"], "oracle_seconds_recorded": d.get("oracle_seconds")}
 
 
+def async_compare(kmp, torch, dev_graph, k, eps, seed, steps, det_ms, det_cut):
+    """The asynchronous LP mode (paper Sec. 5.1 / 5.3; kmp_options.async_lp = 1) on the same graph: time per
+    partition without events and the cut of every run (the mode is not deterministic), beside the
+    deterministic figures of the same graph."""
+    xadj, adjncy, vwgt, adjwgt = dev_graph
+    n = xadj.numel() - 1
+    out = torch.empty(n, dtype=torch.int32, device=xadj.device)
+    for _ in range(2):
+        rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, async_lp=1)
+        assert rc == 0, kmp.kmp_strerror(rc)
+    torch.cuda.synchronize()
+    cuts, balanced = [], True
+    t = time.perf_counter()
+    for _ in range(steps):
+        rc, _, st = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out, async_lp=1)
+        cuts.append(st["cut"])
+        balanced = balanced and rc == 0 and st["max_block_weight"] <= st["lk"]
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    return {"steps": steps, "ms_per_partition_without_events": round(ms, 3),
+            "deterministic_ms_per_partition_without_events": round(det_ms, 3),
+            "speedup_vs_deterministic": round(det_ms / ms, 3),
+            "cut_median": int(statistics.median(cuts)), "cut_min": min(cuts), "cut_max": max(cuts),
+            "deterministic_cut": det_cut, "cut_ratio_vs_deterministic": round(statistics.median(cuts) / det_cut, 4),
+            "all_balanced": balanced}
+
+
 def extra_workload(kmp, gen, torch, name, steps, warmup, cpu):
     """Another configuration timed like the headline: whole kmp_partition calls with the CSR resident,
     the dominant byte-counting class stamped, one all-class step for the per-phase rates, the output
@@ -340,6 +371,9 @@ def extra_workload(kmp, gen, torch, name, steps, warmup, cpu):
            "roofline": roofline_of(kmp, stats, dom, st_all, name), "cpu_baseline": None}
     print(f"# {name}: {ms_step:.2f} ms per partition ({ms_plain:.2f} without events), parity {row['parity']}",
           file=sys.stderr, flush=True)
+    row["async_lp"] = async_compare(kmp, torch, (xadj, adjncy, vwgt, adjwgt), k, eps, seed, steps, ms_plain,
+                                    st0["cut"])
+    print(f"# {name} asynchronous LP: {row['async_lp']}", file=sys.stderr, flush=True)
     if cpu == "partition":
         import oracle
         times = []
@@ -468,6 +502,9 @@ def main():
                             "ggg_ms_per_partition": round(prof_c["ms"], 3), "ggg_launches": prof_c["launches"]}
             ip_parts[name] = part_c
         print(f"# ip options: {ip_cmp}", file=sys.stderr, flush=True)
+    async_cmp = async_compare(kmp, torch, (xadj, adjncy, vwgt, adjwgt), k, eps, seed, args.steps, ms_plain,
+                              stats[0]["cut"]) if not (fm or pool) else None
+    print(f"# asynchronous LP: {async_cmp}", file=sys.stderr, flush=True)
     # the timed steps ran at the default tuning, the one the committed rocprofv3 summaries were taken at;
     # then the autotuner picks launch choices (never changing the output) for this workload on this GPU,
     # reported with its own timings, and the batched and serving runs use its choice
@@ -541,7 +578,7 @@ def main():
         "lp_plus_contraction_edges_per_step": edges, **phase_rates(st_all), "cut": st0["cut"],
         "levels": st0["levels"],
         "parity_with_oracle": parity, "tuning": tuning, "batched": batched, "serving": serving,
-        "ip_options": ip_cmp, "workloads": workloads,
+        "ip_options": ip_cmp, "async_lp": async_cmp, "workloads": workloads,
     }
     print(json.dumps(line), flush=True)
 
