@@ -1274,6 +1274,36 @@ __device__ inline void rate_lane_local(const RateArgs& a, int32_t lo, uint32_t o
 
 // LCSR: the job's CSR is copied to LDS first (row starts relative to the job's
 // first entry, node weights, edge weights, neighbours as local ids).
+// Asynchronous move of local node li from label own to K inside the
+// one-workgroup LP (weights and labels in LDS): strict (refinement) reserves
+// K's weight with compare-and-swap, else fetch-and-add; the neighbours are
+// marked for round r + 1.  Returns 1 if li moved.
+template <class ROW, class NBR>
+__device__ inline int32_t small_async_move(int32_t li, int32_t K, int32_t own, int32_t cv, int64_t cap, bool strict,
+                                           int16_t* s_lab, int32_t* s_wt, uint8_t* act_next, uint8_t stamp_next,
+                                           bool mark, ROW row0, NBR nbr)
+{
+    if (strict) {
+        int32_t old = s_wt[K];
+        // a failed exchange returns a weight another move wrote; every node moves at most once per class
+        while ((int64_t)old + cv <= cap) {
+            const int32_t seen = atomicCAS(&s_wt[K], old, old + cv);
+            if (seen == old) break;
+            old = seen;
+        }
+        if ((int64_t)old + cv > cap) return 0;
+    } else {
+        atomicAdd(&s_wt[K], cv);
+    }
+    atomicAdd(&s_wt[own], -cv);
+    s_lab[li] = (int16_t)K;
+    if (mark) {
+        const int32_t e0 = row0(li), e1 = row0(li + 1);
+        for (int32_t e = e0; e < e1; ++e) act_next[nbr(e)] = stamp_next;
+    }
+    return 1;
+}
+
 template <bool EW, bool CAPV, bool LCSR>
 __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
 {
@@ -1393,8 +1423,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                                                      rown);
                 if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
                 if (adm.r > rown) {
-                    s_prop[li] = (int16_t)adm.k;
-                    atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                    if (a.amode) {
+                        mine += small_async_move((int32_t)li, (int32_t)adm.k, (int32_t)own, (int32_t)cv,
+                                                 CAPV ? a.cap_vec[lo + adm.k] : nk.cap, a.amode == 2, s_lab, s_wt,
+                                                 act_next, stamp_next, r + 1 < kRounds, row0, nbr);
+                    } else {
+                        s_prop[li] = (int16_t)adm.k;
+                        atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                    }
                 }
                 edges += d;
                 nodes += 1;
@@ -1455,8 +1491,14 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                     if (li >= 0 && gl == 0) {
                         if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
                         if (adm.r > rown) {
-                            s_prop[li] = (int16_t)adm.k;
-                            atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                            if (a.amode) {
+                                mine += small_async_move(li, (int32_t)adm.k, (int32_t)own, (int32_t)cv,
+                                                         CAPV ? a.cap_vec[lo + adm.k] : nk.cap, a.amode == 2, s_lab,
+                                                         s_wt, act_next, stamp_next, r + 1 < kRounds, row0, nbr);
+                            } else {
+                                s_prop[li] = (int16_t)adm.k;
+                                atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                            }
                         }
                         edges += d;
                         nodes += 1;
@@ -1504,14 +1546,24 @@ __global__ __launch_bounds__(kSmallBlock) void k_lp_small(SmallLP p)
                 if (lane == 0) {
                     if (a.fav) a.fav[v] = fav.r ? fav.k + (uint32_t)lo : kNone;
                     if (adm.r > rown) {
-                        s_prop[li] = (int16_t)adm.k;
-                        atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                        if (a.amode) {
+                            mine += small_async_move(li, (int32_t)adm.k, (int32_t)own, (int32_t)cv,
+                                                     CAPV ? a.cap_vec[lo + adm.k] : nk.cap, a.amode == 2, s_lab,
+                                                     s_wt, act_next, stamp_next, r + 1 < kRounds, row0, nbr);
+                        } else {
+                            s_prop[li] = (int16_t)adm.k;
+                            atomicAdd(&s_dem[adm.k], (int32_t)cv);
+                        }
                     }
                     edges += e1 - e0;
                     nodes += 1;
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
                 __builtin_amdgcn_wave_barrier();  // the table is cleared for the next node only after every read
+            }
+            if (a.amode) {  // asynchronous: moves are already applied; the next class sees them
+                __syncthreads();
+                continue;
             }
             if (tid == 0) s_cont = 0;
             __syncthreads();
@@ -2079,6 +2131,7 @@ LPStats lp_run_small(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, LPSt
     SmallLP p;
     memset(&p, 0, sizeof(p));
     p.a = make_rate_args(c, g, st, 0, &b);
+    p.a.amode = c.async_lp == 1 ? (st.tag == TAG_REF ? 2 : 1) : 0;
     p.a.level = (uint32_t)level;
     p.a.ctl = nullptr;
     p.a.bytes_ctr = c.spread(SP_BYTES + KMP_PROF_LP_SMALL);
@@ -2371,6 +2424,13 @@ LPStats lp_run(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const LPSc
     if (n == 0) return LPStats();
     if (c.async_lp) {
         if (!sched_p) throw Error(KMP_EHIP, "the asynchronous LP needs its visit-order schedule");
+        // a small single graph runs its whole call in one workgroup (not in serial mode, whose
+        // one-node launches are the one-processing-element execution)
+        if (c.async_lp == 1 && !st.jt.gid && small_level(c, g, *sched_p, st.nlab)) {
+            LPBuffers b;
+            lp_buffers(c, g, nullptr, st.nlab, b);
+            return lp_run_small(c, g, level, seed, st, b, {0}, {n}, {0}, {st.nlab});
+        }
         return lp_async_rounds(c, g, level, seed, *sched_p, st);
     }
     if (!sched_p) {  // a small single graph: no schedule needed

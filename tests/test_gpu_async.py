@@ -158,7 +158,6 @@ def test_lp_async_parallel_valid(kmp, name):
     assert lab.min() >= 0 and lab.max() < n
     assert np.array_equal(w, np.bincount(lab, weights=c, minlength=n).astype(np.int64))
     nc = len(np.unique(lab))
-    _, _, _, det_moves, _ = oracle.lp_cluster(g, 0, U, 7)
     say(f"  clusters {nc} of {n}, moves {moves}, largest {w.max()} (U {U})")
     assert nc < 0.7 * n
     # refinement: the bounds hold strictly, weights follow the labels
@@ -177,6 +176,39 @@ def test_lp_async_parallel_valid(kmp, name):
     assert (w <= cap).all()
     A_cut_before = oracle.cut(g, part)
     assert oracle.cut(g, p) < A_cut_before
+
+
+@pytest.mark.parametrize("name", ["grid60", "rgg5000", "weighted4000"])
+def test_lp_async_small_level_valid(kmp, name):
+    """Levels of at most 8192 nodes run the asynchronous call in one workgroup (LDS labels and weights):
+    the same validity checks as the launch path."""
+    g = {"grid60": lambda: gen.grid(60, 60), "rgg5000": lambda: gen.rgg(5000, 8.0, seed=6),
+         "weighted4000": lambda: gen.random_graph(4000, 6.0, 3, max_vw=4, max_ew=9)}[name]()
+    c = node_w(g)
+    n = g.n
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    U = int(c.sum() // 300) + int(c.max())
+    say(f"[lp_async small cluster] {name} U={U}")
+    label, cw = t32(np.arange(n)), t64(c)
+    r, moves = kmp.kmp_lp_async(xadj, adjncy, vwgt, adjwgt, 1, oracle.T_CL, 3, label, cw, cap_scalar=U)
+    lab, w = label.cpu().numpy(), cw.cpu().numpy()
+    assert 1 <= r <= oracle.ROUNDS and moves[0] > 0
+    assert lab.min() >= 0 and lab.max() < n
+    assert np.array_equal(w, np.bincount(lab, weights=c, minlength=n).astype(np.int64))
+    assert len(np.unique(lab)) < 0.7 * n
+    nb = 16
+    rng = np.random.default_rng(2)
+    part = rng.integers(0, nb, n).astype(np.int32)
+    wt = np.bincount(part, weights=c, minlength=nb).astype(np.int64)
+    cap = wt + int(c.sum() // (nb * 40)) + 1
+    say(f"[lp_async small refine] {name} nb={nb}")
+    d_part, d_wt = t32(part), t64(wt)
+    r, moves = kmp.kmp_lp_async(xadj, adjncy, vwgt, adjwgt, 1, oracle.T_REF, 4, d_part, d_wt, cap_vec=t64(cap))
+    p, w = d_part.cpu().numpy(), d_wt.cpu().numpy()
+    assert 1 <= r <= oracle.ROUNDS and moves[0] > 0
+    assert np.array_equal(w, np.bincount(p, weights=c, minlength=nb).astype(np.int64))
+    assert (w <= cap).all()
+    assert oracle.cut(g, p) < oracle.cut(g, part)
 
 
 @pytest.mark.parametrize("name,k", [("rgg65536", 64), ("grid128", 8), ("rmat16", 256), ("weighted50000", 31)])
