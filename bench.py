@@ -76,6 +76,9 @@ def parse():
                     help="skip the grid 128x128 (k = 8) and RMAT 2^22 (k = 2^15) workloads")
     ap.add_argument("--rmat-steps", type=int, default=3)
     ap.add_argument("--grid-steps", type=int, default=20)
+    ap.add_argument("--only-workload", type=str, default=None,
+                    help="run only this extra workload (grid128 or rmat22) and print its row; for profiling")
+    ap.add_argument("--no-async", action="store_true", help="skip the asynchronous-LP comparison runs")
     return ap.parse_args()
 
 
@@ -323,7 +326,7 @@ def async_compare(kmp, torch, dev_graph, k, eps, seed, steps, det_ms, det_cut):
             "all_balanced": balanced}
 
 
-def extra_workload(kmp, gen, torch, name, steps, warmup, cpu):
+def extra_workload(kmp, gen, torch, name, steps, warmup, cpu, with_async=True):
     """Another configuration timed like the headline: whole kmp_partition calls with the CSR resident,
     the dominant byte-counting class stamped, one all-class step for the per-phase rates, the output
     compared with the oracle-written golden digest.  cpu: None (skip), "partition" (the oracle's whole
@@ -372,7 +375,7 @@ def extra_workload(kmp, gen, torch, name, steps, warmup, cpu):
     print(f"# {name}: {ms_step:.2f} ms per partition ({ms_plain:.2f} without events), parity {row['parity']}",
           file=sys.stderr, flush=True)
     row["async_lp"] = async_compare(kmp, torch, (xadj, adjncy, vwgt, adjwgt), k, eps, seed, steps, ms_plain,
-                                    st0["cut"])
+                                    st0["cut"]) if with_async else None
     print(f"# {name} asynchronous LP: {row['async_lp']}", file=sys.stderr, flush=True)
     if cpu == "partition":
         import oracle
@@ -424,6 +427,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     kmp.library()
+    if args.only_workload:
+        steps = args.rmat_steps if args.only_workload == "rmat22" else args.grid_steps
+        row = extra_workload(kmp, gen, torch, args.only_workload, steps, 1, None, not args.no_async)
+        print(json.dumps(row), flush=True)
+        return
     g = gen.workload(WORKLOAD["name"])
     k, eps, seed = WORKLOAD["k"], WORKLOAD["eps"], WORKLOAD["seed"]
     xadj, adjncy, vwgt, adjwgt = kmp.to_device(g, "cuda:0")
@@ -503,7 +511,7 @@ def main():
             ip_parts[name] = part_c
         print(f"# ip options: {ip_cmp}", file=sys.stderr, flush=True)
     async_cmp = async_compare(kmp, torch, (xadj, adjncy, vwgt, adjwgt), k, eps, seed, args.steps, ms_plain,
-                              stats[0]["cut"]) if not (fm or pool) else None
+                              stats[0]["cut"]) if not (fm or pool or args.no_async) else None
     print(f"# asynchronous LP: {async_cmp}", file=sys.stderr, flush=True)
     # the timed steps ran at the default tuning, the one the committed rocprofv3 summaries were taken at;
     # then the autotuner picks launch choices (never changing the output) for this workload on this GPU,
@@ -535,7 +543,7 @@ def main():
         workloads = {}
         for name, steps, cpu_mode in (("grid128", args.grid_steps, None if args.no_cpu_baseline else "partition"),
                                       ("rmat22", args.rmat_steps, None if args.no_cpu_baseline else "lp0")):
-            workloads[name] = extra_workload(kmp, gen, torch, name, steps, 1, cpu_mode)
+            workloads[name] = extra_workload(kmp, gen, torch, name, steps, 1, cpu_mode, not args.no_async)
             print(f"# workload {name}: {json.dumps(workloads[name])}", file=sys.stderr, flush=True)
     cpu = None
     parity = None
