@@ -101,6 +101,8 @@ def _load():
             "or_step_cut": (i64, [i32, P32, P32, P32, P32]),
             "or_ggg_traced": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, P64, P32,
                                              P32, P32, i32, i32, i64, i64]),
+            "or_ml_bipartition": (ctypes.c_int, [i32, P32, P32, P32, P32, i32, i32, i32, i64, u64, PU8, i32, i32,
+                                                 i64, i64, P32]),
             "or_eps_root": (u64, [u64, i32]),
             "or_adaptive_caps": (None, [i64, i32, i64, i64, i32, P64, P64]),
             "or_rg_cmp": (ctypes.c_int, [i64, i64, i64, i64]),
@@ -177,18 +179,21 @@ class Result:
     trace: Dict[Tuple[str, int], np.ndarray] = field(default_factory=dict)
 
 
-IP_POOL, IP_ADAPTIVE, BAL_PQ, LP_ASYNC = 1, 2, 4, 8
+IP_POOL, IP_ADAPTIVE, BAL_PQ, LP_ASYNC, IP_ML = 1, 2, 4, 8, 16
+IP_CCF, IP_MAXLEV = 18, 32
 
 
-def _ipflags(pool, adaptive_eps, pq_balance=False, async_lp=False):
+def _ipflags(pool, adaptive_eps, pq_balance=False, async_lp=False, ml=False):
     return (IP_POOL if pool else 0) | (IP_ADAPTIVE if adaptive_eps else 0) | (BAL_PQ if pq_balance else 0) | \
-        (LP_ASYNC if async_lp else 0)
+        (LP_ASYNC if async_lp else 0) | (IP_ML if ml else 0)
 
 
 def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
               validate_input: bool = True, fm_passes: int = 0, pool: bool = False,
-              adaptive_eps: bool = False, pq_balance: bool = False, async_lp: bool = False) -> Result:
-    """O10; async_lp: every LP call is the one-PE execution of the asynchronous LP (O3b)."""
+              adaptive_eps: bool = False, pq_balance: bool = False, async_lp: bool = False,
+              ip_multilevel: bool = False) -> Result:
+    """O10; async_lp: every LP call is the one-PE execution of the asynchronous LP (O3b); ip_multilevel:
+    every bipartition is the multilevel one of O8e."""
     lib = _load()
     xadj, adjncy = _i32(g.xadj), _i32(g.adjncy)
     vw = None if g.vwgt is None else _i32(g.vwgt)
@@ -205,7 +210,7 @@ def partition(g, k: int, eps: float = 0.03, seed: int = 1, trace: bool = False,
     cb = TRACE_FN(_cb) if trace else TRACE_FN()
     rc = lib.or_partition_traced(g.n, _p(xadj), _p(adjncy), _p(vw), _p(ew), k, eps, seed & (2**64 - 1),
                                  _p(out), ctypes.byref(st), int(validate_input), cb, None, int(fm_passes),
-                                 _ipflags(pool, adaptive_eps, pq_balance, async_lp))
+                                 _ipflags(pool, adaptive_eps, pq_balance, async_lp, ip_multilevel))
     L = st.levels
     stats = dict(cut=st.cut, levels=L, level_n=list(st.level_n[:L + 1]), level_m=list(st.level_m[:L + 1]),
                  bipartitions=st.bipartitions, balance_rounds=st.balance_rounds,
@@ -288,7 +293,7 @@ def contract(g, label):
 
 
 def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, fm_passes: int = 0,
-                      pool: bool = False, adaptive: Optional[Tuple[int, int, float]] = None):
+                      pool: bool = False, adaptive: Optional[Tuple[int, int, float]] = None, ml: bool = False):
     """O7 round; `adaptive` = (c(V), k, eps) bounds each side by the adaptive imbalance (O8d)."""
     vw, ew = _weights(g)
     part = _i32(part).copy()
@@ -300,7 +305,7 @@ def bipartition_round(g, level: int, part, first, fcount, lk_: int, seed: int, f
     fc[:len(first)] = fcount
     rc = _load().or_step_bipartition_round(g.n, _p(_i32(g.xadj)), _p(_i32(g.adjncy)), _p(vw), _p(ew), level,
                                            _p(part), ctypes.byref(nb), _p(fa), _p(fc), lk_, seed, int(fm_passes),
-                                           _ipflags(pool, adaptive is not None),
+                                           _ipflags(pool, adaptive is not None, ml=ml),
                                            adaptive[0] if adaptive else 0, adaptive[1] if adaptive else 1,
                                            eps_ppm(adaptive[2]) if adaptive else 0)
     if rc != 0:
@@ -328,6 +333,21 @@ def ggg(sub, level: int, first: int, f: int, lk_: int, seed: int, with_order: bo
     if with_order:
         return side[:sub.n], int(cut.value), order[:norder.value].copy(), int(jbest.value)
     return side[:sub.n], int(cut.value)
+
+
+def ml_bipartition(sub, level: int, first: int, f: int, lk_: int, seed: int, fm_passes: int = 0,
+                   pool: bool = False, caps: Optional[Tuple[int, int]] = None):
+    """O8e on a subgraph in local ids; returns (side, coarsening levels)."""
+    vw, ew = _weights(sub)
+    side = np.zeros(max(sub.n, 1), np.uint8)
+    nlev = ctypes.c_int32(0)
+    rc = _load().or_ml_bipartition(sub.n, _p(_i32(sub.xadj)), _p(_i32(sub.adjncy)), _p(ew), _p(vw), level, first,
+                                   f, lk_, seed, _p(side, PU8), int(fm_passes), int(pool),
+                                   -1 if caps is None else caps[0], -1 if caps is None else caps[1],
+                                   ctypes.byref(nlev))
+    if rc != 0:
+        raise RuntimeError(f"oracle ml_bipartition failed: {rc}")
+    return side[:sub.n], int(nlev.value)
 
 
 FM_STALL = 64

@@ -28,6 +28,7 @@
  *   O8c pool: BFS and random runs beside GGG (optional) (Sec. 5.2 "Initial Bipartitioning")
  *   O8d adaptive imbalance of a bipartition (optional)  (Sec. 2 "Maintaining the Balance
  *       Constraint", Alg. 2, Sec. 5.2 bound L_2)
+ *   O8e multilevel initial bipartitioning (optional)  (Sec. 5.2 "Initial Bipartitioning")
  *   O9  k-way balancer by relative gain              (Sec. 5.3 "Balancing")
  *   O9b the same with the paper's priority queues (optional) (Sec. 5.3 "Balancing")
  *   O10 driver                                       (Alg. 1, Sec. 4)
@@ -57,8 +58,11 @@
 #define OR_PHI 0x9E3779B9u
 enum { T_SUB = 1, T_CL = 2, T_REF = 3, T_BAL = 4, T_GGG = 5, T_BFS = 6, T_RND = 7 };
 /* options (bit flags): the pool of O8c, the adaptive caps of O8d, the queue balancer of O9b,
- * the asynchronous LP of O3b for every LP call (clustering and refinement) */
-enum { OR_IP_POOL = 1, OR_IP_ADAPTIVE = 2, OR_BAL_PQ = 4, OR_LP_ASYNC = 8, OR_IP_ALL = 15 };
+ * the asynchronous LP of O3b for every LP call (clustering and refinement), the multilevel
+ * initial bipartitioning of O8e */
+enum { OR_IP_POOL = 1, OR_IP_ADAPTIVE = 2, OR_BAL_PQ = 4, OR_LP_ASYNC = 8, OR_IP_ML = 16, OR_IP_ALL = 31 };
+#define OR_IP_CCF 18      /* O8e: cluster bound = largest side bound / this factor */
+#define OR_IP_MAXLEV 32   /* O8e: coarsening level guard */
 
 /* status codes */
 #define OR_OK 0
@@ -1037,6 +1041,102 @@ void or_adaptive_caps(int64_t cV, int32_t k, int64_t e, int64_t cB, int32_t f, i
     *cap1 = c1 > (or_u128)OR_CAP_INF ? OR_CAP_INF : (int64_t)c1;
 }
 
+/* ---------------- O8e: multilevel initial bipartitioning ----------------
+ * Sec. 5.2 "Initial Bipartitioning": the subgraph of a block is coarsened
+ * with label propagation until no further contraction is possible, the
+ * coarsest graph is bipartitioned by the pool of simple algorithms, and
+ * 2-way FM refines the bipartition on every level on the way back up.  The
+ * paper sets the cluster weight bound to the value KaHIP uses, without
+ * stating it.  Reading:
+ *  - the bound is U' = max(largest node weight, floor(max(cap0, cap1) /
+ *    OR_IP_CCF)) on every coarsening level: KaHIP divides the block bound by
+ *    a cluster coarsening factor, taken here as 18;
+ *  - coarsening level i (i = 0 is the subgraph in local ids) runs the O3
+ *    clustering (no two-hop) keyed by the block's own seed
+ *    s_B = seed XOR (first << 32) and the level key 64 + 64 l + i; it stops
+ *    when the clustering left every node alone, or after OR_IP_MAXLEV levels;
+ *    otherwise O5 contracts and the next level follows;
+ *  - the coarsest graph is bipartitioned as in O8 (with O8b, O8c and the
+ *    caps of O8d as set), under the seeds of the single-level call;
+ *  - each finer level takes the sides of its coarse nodes and runs
+ *    fm_passes passes of O8b under the same caps (none when fm_passes = 0).
+ * Returns OR_OK or an error; side[nb] receives the bipartition.            */
+int or_ml_bipartition(int32_t nb, const int32_t* xadj, const int32_t* adjncy, const int32_t* adjwgt,
+                      const int32_t* vwgt, int32_t level, int32_t first, int32_t f, int64_t lk, uint64_t seed,
+                      uint8_t* side, int32_t fm_passes, int32_t pool, int64_t cap0_in, int64_t cap1_in,
+                      int32_t* nlevels_out)
+{
+    if (fm_passes < 0 || fm_passes > OR_FM_MAXPASS || pool < 0 || pool > 1) return OR_EINVAL;
+    const int32_t f0 = f / 2, f1 = f - f0;
+    const int64_t cap0 = cap0_in >= 0 ? cap0_in : (int64_t)f0 * lk, cap1 = cap1_in >= 0 ? cap1_in : (int64_t)f1 * lk;
+    const uint64_t sB = seed ^ ((uint64_t)(uint32_t)first << 32);
+    or_graph G[OR_IP_MAXLEV + 1];
+    int32_t* maps[OR_IP_MAXLEV + 1];
+    memset(G, 0, sizeof(G));
+    memset(maps, 0, sizeof(maps));
+    G[0].n = nb;
+    G[0].m = xadj[nb];
+    G[0].xadj = (int32_t*)xadj;
+    G[0].adjncy = (int32_t*)adjncy;
+    G[0].vwgt = (int32_t*)vwgt;
+    G[0].adjwgt = (int32_t*)adjwgt;
+    int rc = OR_OK;
+    int32_t L = 0;
+    while (L < OR_IP_MAXLEV) {
+        or_graph* g = &G[L];
+        int64_t maxc = 0;
+        for (int32_t v = 0; v < g->n; ++v) maxc = g->vwgt[v] > maxc ? g->vwgt[v] : maxc;
+        const int64_t big = cap0 > cap1 ? cap0 : cap1;
+        const int64_t U = big / OR_IP_CCF > maxc ? big / OR_IP_CCF : maxc;
+        int32_t* label = (int32_t*)malloc(sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1));
+        int64_t* cw = (int64_t*)malloc(sizeof(int64_t) * (size_t)(g->n > 0 ? g->n : 1));
+        if (!label || !cw) {
+            free(label); free(cw);
+            rc = OR_ENOMEM;
+            break;
+        }
+        for (int32_t v = 0; v < g->n; ++v) {
+            label[v] = v;
+            cw[v] = g->vwgt[v];
+        }
+        int32_t rr = or_lp(g, 64 + 64 * level + L, sB, T_CL, label, cw, g->n, NULL, U, NULL, NULL);
+        int32_t nc = rr < 0 ? 0 : or_count_labels(g->n, label);
+        if (rr < 0) rc = rr;
+        if (rc == OR_OK && nc < g->n) {
+            maps[L] = (int32_t*)malloc(sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1));
+            rc = maps[L] ? or_contract(g, label, &G[L + 1], maps[L]) : OR_ENOMEM;
+        }
+        free(label);
+        free(cw);
+        if (rc != OR_OK || nc == g->n) break;
+        ++L;
+    }
+    uint8_t* sd[OR_IP_MAXLEV + 1];
+    memset(sd, 0, sizeof(sd));
+    if (rc == OR_OK) {
+        for (int32_t i = 0; i <= L && rc == OR_OK; ++i) {
+            sd[i] = (uint8_t*)malloc((size_t)(G[i].n > 0 ? G[i].n : 1));
+            if (!sd[i]) rc = OR_ENOMEM;
+        }
+    }
+    if (rc == OR_OK)
+        rc = or_ggg_traced(G[L].n, G[L].xadj, G[L].adjncy, G[L].adjwgt, G[L].vwgt, level, first, f, lk, seed, sd[L],
+                           NULL, NULL, NULL, NULL, fm_passes, pool, cap0, cap1);
+    for (int32_t i = L - 1; i >= 0 && rc == OR_OK; --i) {
+        for (int32_t v = 0; v < G[i].n; ++v) sd[i][v] = sd[i + 1][maps[i][v]];
+        if (fm_passes > 0)
+            rc = or_fm2(G[i].n, G[i].xadj, G[i].adjncy, G[i].adjwgt, G[i].vwgt, sd[i], cap0, cap1, fm_passes, NULL);
+    }
+    if (rc == OR_OK) memcpy(side, sd[0], (size_t)nb);
+    if (nlevels_out) *nlevels_out = L;
+    for (int32_t i = 0; i <= L; ++i) {
+        free(sd[i]);
+        free(maps[i]);
+        if (i > 0) graph_free(&G[i]);
+    }
+    return rc;
+}
+
 /* ---------------- O6/O7: block table and bipartitionBlocks --------------
  * Sec. 4 "Handling General k": a block B with final count f_B splits into
  * B0 with floor(f_B/2) and B1 with ceil(f_B/2), weight in that ratio.  Alg. 2
@@ -1096,8 +1196,11 @@ int or_bipartition_round(const or_graph* g, int32_t level, int32_t* part, int32_
             for (int32_t i = 0; i < cnt; ++i) cB += svw[i];
             or_adaptive_caps(cV, k, e, cB, fcount[b], &cap0, &cap1);
         }
-        int rc = or_ggg_traced(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, NULL, NULL, NULL,
-                               NULL, fm_passes, pool, cap0, cap1);
+        int rc = (ipflags & OR_IP_ML)
+                     ? or_ml_bipartition(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, fm_passes,
+                                         pool, cap0, cap1, NULL)
+                     : or_ggg_traced(cnt, sx, sa, sw, svw, level, first[b], fcount[b], lk, seed, side, NULL, NULL,
+                                     NULL, NULL, fm_passes, pool, cap0, cap1);
         if (rc != OR_OK) return rc;
         if (ncalls) (*ncalls)++;
         for (int32_t i = 0; i < cnt; ++i) sidev[verts[bstart[b] + i]] = side[i];
