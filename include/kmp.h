@@ -112,6 +112,14 @@ typedef struct kmp_options {
                                run to run); 2: asynchronous executed one node per launch in visit order,
                                the execution by a single processing element (deterministic; for tests,
                                slow); other values: KMP_EINVAL.  The output depends on it. */
+    int32_t ip_multilevel;  /* 1: multilevel initial bipartitioning (paper Sec. 5.2): the subgraph of every
+                               block to split is coarsened with the deterministic LP (cluster bound
+                               max(heaviest node, larger side bound / 18), the block's own seed
+                               seed XOR (first << 32), no two-hop) and contraction until a clustering
+                               leaves every node alone; the coarsest graph is bipartitioned by the growths
+                               above (with FM and the pool as set), and each finer level refines the
+                               projected sides with fm_passes FM passes.  0: single-level growths (the
+                               default); other values: KMP_EINVAL.  The output depends on it. */
 } kmp_options;
 
 /* Kernel classes reported when kmp_options.profile is set. */

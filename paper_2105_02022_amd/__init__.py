@@ -33,7 +33,7 @@ class KmpOptions(ctypes.Structure):
     _fields_ = [("validate", ctypes.c_int32), ("profile", ctypes.c_int32), ("profile_classes", ctypes.c_uint32),
                 ("force_exact", ctypes.c_int32), ("small_level_n", ctypes.c_int32), ("plain_loads", ctypes.c_int32),
                 ("fm_passes", ctypes.c_int32), ("ip_pool", ctypes.c_int32), ("adaptive_eps", ctypes.c_int32),
-                ("pq_balance", ctypes.c_int32), ("async_lp", ctypes.c_int32)]
+                ("pq_balance", ctypes.c_int32), ("async_lp", ctypes.c_int32), ("ip_multilevel", ctypes.c_int32)]
 
 
 class KmpStats(ctypes.Structure):
@@ -230,7 +230,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
                      small_level_n: int = 0, plain_loads: bool = False,
                      fm_passes: int = 0, ip_pool: bool = False,
                      adaptive_eps: bool = False, pq_balance: bool = False,
-                     async_lp: int = 0) -> Tuple[int, "torch.Tensor", Dict]:
+                     async_lp: int = 0, ip_multilevel: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """Returns (status, out_part, stats dict).  `profile_classes`: names from PROF_CLASSES to time
     (None: all).  `force_exact`: contended LP sub-rounds take the host-synchronised exact path.
     `small_level_n`: largest level run by the one-workgroup LP (0 default, -1 never).
@@ -239,7 +239,8 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     `ip_pool`: the initial bipartitioning also runs BFS and random growths.
     `adaptive_eps`: bipartitions bound their sides by the adaptive imbalance (paper Sec. 2, Alg. 2).
     `pq_balance`: the queue balancer of paper Sec. 5.3 instead of sorted rounds.
-    `async_lp`: 1 = asynchronous LP (paper Sec. 5.1 / 5.3), 2 = the same one node per launch (tests)."""
+    `async_lp`: 1 = asynchronous LP (paper Sec. 5.1 / 5.3), 2 = the same one node per launch (tests).
+    `ip_multilevel`: multilevel initial bipartitioning (paper Sec. 5.2)."""
     import torch
     _check_i32(xadj, adjncy, vwgt, adjwgt)
     n = xadj.numel() - 1
@@ -256,6 +257,7 @@ def kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0.03, 
     opt.adaptive_eps = int(adaptive_eps)
     opt.pq_balance = int(pq_balance)
     opt.async_lp = int(async_lp)
+    opt.ip_multilevel = int(ip_multilevel)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -270,7 +272,7 @@ def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0
                           stream=None, validate: bool = False, force_exact: bool = False, small_level_n: int = 0,
                           fm_passes: int = 0, ip_pool: bool = False,
                           adaptive_eps: bool = False, pq_balance: bool = False,
-                          async_lp: int = 0) -> Tuple[int, "torch.Tensor", Dict]:
+                          async_lp: int = 0, ip_multilevel: bool = False) -> Tuple[int, "torch.Tensor", Dict]:
     """kmp_partition_noalloc: as kmp_partition_ex, with every device buffer inside the library's fixed
     scratch region (n <= NOALLOC_MAX_N, m <= NOALLOC_MAX_M, else KMP_ETOOLARGE).  `out` should be
     given by callers that must not allocate."""
@@ -288,6 +290,7 @@ def kmp_partition_noalloc(xadj, adjncy, vwgt, adjwgt, k: int, epsilon: float = 0
     opt.adaptive_eps = int(adaptive_eps)
     opt.pq_balance = int(pq_balance)
     opt.async_lp = int(async_lp)
+    opt.ip_multilevel = int(ip_multilevel)
     st = KmpStats()
     rc = library().kmp_partition_noalloc(_ptr(xadj), _ptr(adjncy), _ptr(vwgt), _ptr(adjwgt), n, adjncy.numel(), k,
                                          epsilon, seed & (2**64 - 1), _ptr(out), _stream(stream),
@@ -312,7 +315,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
                         small_level_n: int = 0, plain_loads: bool = False,
                         fm_passes: int = 0, ip_pool: bool = False,
                         adaptive_eps: bool = False, pq_balance: bool = False,
-                        async_lp: int = 0) -> Tuple[int, List[Dict], Dict]:
+                        async_lp: int = 0, ip_multilevel: bool = False) -> Tuple[int, List[Dict], Dict]:
     """Partition many graphs in one pass.  `jobs`: sequence of dicts with device tensors
     xadj, adjncy, vwgt (or None), adjwgt (or None), out (int32 [n]) and k, epsilon, seed.
     Returns (call status, per-job result dicts, aggregate stats)."""
@@ -331,6 +334,7 @@ def kmp_partition_batch(jobs, stream=None, validate: bool = False, profile: bool
     opt.adaptive_eps = int(adaptive_eps)
     opt.pq_balance = int(pq_balance)
     opt.async_lp = int(async_lp)
+    opt.ip_multilevel = int(ip_multilevel)
     if profile_classes:
         opt.profile_classes = sum(1 << PROF_CLASSES.index(c) for c in profile_classes)
     st = KmpStats()
@@ -390,7 +394,7 @@ class Server:
         return out
 
     def set_options(self, fm_passes: int = 0, ip_pool: bool = False, adaptive_eps: bool = False,
-                    pq_balance: bool = False, async_lp: int = 0) -> int:
+                    pq_balance: bool = False, async_lp: int = 0, ip_multilevel: bool = False) -> int:
         """Options for jobs submitted from now on (kmp_server_set_options)."""
         o = KmpOptions()
         o.fm_passes = int(fm_passes)
@@ -398,6 +402,7 @@ class Server:
         o.adaptive_eps = int(adaptive_eps)
         o.pq_balance = int(pq_balance)
         o.async_lp = int(async_lp)
+        o.ip_multilevel = int(ip_multilevel)
         return library().kmp_server_set_options(self._h, ctypes.byref(o))
 
     def poll(self, jid: int) -> Optional[Dict]:

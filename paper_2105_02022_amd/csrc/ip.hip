@@ -12,9 +12,9 @@
 // no frontier node fits, the fitting unassigned node with the smallest hash
 // H(seed; 5, level, first, f, j, local id).  A growth step is one pass over a
 // packed 64-bit key per node (frontier flag, gain, id) and one wave maximum.
-#include <mutex>
-
 #include <cmath>
+#include <memory>
+#include <mutex>
 
 #include "kmp_dev.h"
 
@@ -95,6 +95,7 @@ struct GGGArgs {
     char* scratch;      // global variant
     int32_t fm_passes;  // 2-way FM passes after each growth (0: none)
     int32_t pool;       // 1: BFS and random growths after the GGG ones
+    const uint8_t* given;  // non-NULL: no growth; FM refines these sides (by vertex) into `side`
 };
 
 // A growth keeps one 64-bit key per node, so that finding the next node is one
@@ -623,6 +624,36 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     __syncthreads();
     const bool k32 = nv <= 2048 && s_wmax < (1 << 19);
 
+    if (a.given) {
+        // refinement of a given bipartition (the finer levels of the multilevel
+        // bipartitioning): wavefront 0 runs the FM passes on it
+        if (wv != 0) return;
+        int64_t w0 = 0;
+        if (k32) {
+            uint32_t* key = reinterpret_cast<uint32_t*>(key_all);
+            for (int32_t i = lane; i < nvp; i += 64) {
+                const uint32_t sd = i < nv ? a.given[vlist[i]] : 0u;
+                key[i] = sd;
+                if (i < nv && sd == 0) w0 += nd[i].y;
+            }
+        } else {
+            for (int32_t i = lane; i < nvp; i += 64) {
+                const uint64_t sd = i < nv ? a.given[vlist[i]] : 0u;
+                key_all[i] = sd;
+                if (i < nv && sd == 0) w0 += nd[i].y;
+            }
+        }
+        for (int d = 32; d > 0; d >>= 1) w0 += __shfl_xor(w0, d, 64);
+        fence_wave<LDS>();
+        if (k32)
+            ggg_fm<Key32, LDS>(reinterpret_cast<uint32_t*>(key_all), sw_all, nvp, nv, nd, ed, lane, w0, cB, job.cap0,
+                               job.cap1, a.fm_passes);
+        else
+            ggg_fm<Key64, LDS>(key_all, sw_all, nvp, nv, nd, ed, lane, w0, cB, job.cap0, job.cap1, a.fm_passes);
+        for (int32_t i = lane; i < nv; i += 64) a.side[vlist[i]] = sw_all[i] < 0 ? 1 : 0;
+        return;
+    }
+
     // ---- one growth per wavefront
     const int32_t f = job.f, f0 = f / 2, f1 = f - f0;
     const int64_t t0 = cB * f0 / f;
@@ -891,9 +922,514 @@ void adaptive_side_caps(const AdaptiveJob& j, int64_t cB, int32_t f, int64_t& ca
     cap1 = caps[1];
 }
 
+namespace {
+
+template <typename T>
+DBuf<T> to_dev(Ctx& c, const std::vector<T>& v)
+{
+    DBuf<T> d(c, std::max<size_t>(v.size(), 1));
+    if (!v.empty()) c.write(d.p, v.data(), sizeof(T) * v.size());
+    return d;
+}
+
+// Launches k_ggg for `jobs` over the graph and block arrays of `a`: blocks
+// whose working set fits LDS go by LDS size class when there are more blocks
+// than one launch at the largest size keeps resident (a launch's LDS size is
+// its largest block's, and four 512-thread workgroups fit one CU when each
+// takes at most 40 KiB), else in one LDS launch (launches run one after the
+// other, so splitting few blocks only serialises them); then the hybrid and
+// the global layouts.
+void launch_ggg_jobs(Ctx& c, GGGArgs a, const std::vector<GGGJob>& jobs_in)
+{
+    if (jobs_in.empty()) return;
+    constexpr int kLdsClasses = 4;
+    const int64_t lds_class_max[kLdsClasses] = {40 << 10, 53 << 10, 80 << 10, kLdsBudget};
+    std::vector<GGGJob> lds_jobs[kLdsClasses], hyb_jobs, glob_jobs;
+    int64_t lds_max[kLdsClasses] = {0, 0, 0, 0}, hyb_max = 0, scratch_total = 0;
+    const bool fm = a.fm_passes > 0;
+    for (GGGJob jb : jobs_in) {
+        const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum, fm);
+        const int64_t hbytes = ggg_hybrid_lds(jb.nverts, fm);
+        jb.scratch = 0;
+        if (bytes <= kLdsBudget) {
+            int q = 0;
+            while (bytes > lds_class_max[q]) ++q;
+            lds_jobs[q].push_back(jb);
+            lds_max[q] = std::max(lds_max[q], bytes);
+        } else if (hbytes <= kLdsBudget) {
+            jb.scratch = scratch_total;
+            scratch_total += ((int64_t)jb.dsum * 8 + 255) & ~(int64_t)255;
+            hyb_jobs.push_back(jb);
+            hyb_max = std::max(hyb_max, hbytes);
+        } else {
+            jb.scratch = scratch_total;
+            scratch_total += (bytes + 255) & ~(int64_t)255;
+            glob_jobs.push_back(jb);
+        }
+    }
+    {
+        size_t nl = 0;
+        int64_t mx = 0;
+        for (int q = 0; q < kLdsClasses; ++q) {
+            nl += lds_jobs[q].size();
+            mx = std::max(mx, lds_max[q]);
+        }
+        const int64_t resident = 256 * std::max<int64_t>(1, std::min<int64_t>(4, (160 << 10) / std::max<int64_t>(mx, 1)));
+        if ((int64_t)nl <= resident)
+            for (int q = 0; q + 1 < kLdsClasses; ++q) {
+                lds_jobs[kLdsClasses - 1].insert(lds_jobs[kLdsClasses - 1].end(), lds_jobs[q].begin(),
+                                                 lds_jobs[q].end());
+                lds_jobs[q].clear();
+                lds_max[kLdsClasses - 1] = mx;
+            }
+    }
+    DBuf<char> scratch;
+    if (scratch_total > 0) scratch = DBuf<char>(c, (size_t)scratch_total);
+    a.scratch = scratch.p;
+    // every job list in one upload
+    std::vector<GGGJob> all;
+    all.reserve(jobs_in.size());
+    for (int q = 0; q < kLdsClasses; ++q) all.insert(all.end(), lds_jobs[q].begin(), lds_jobs[q].end());
+    all.insert(all.end(), hyb_jobs.begin(), hyb_jobs.end());
+    all.insert(all.end(), glob_jobs.begin(), glob_jobs.end());
+    DBuf<GGGJob> jobs(c, all.size());
+    c.write(jobs.p, all.data(), sizeof(GGGJob) * all.size());
+    size_t at = 0;
+    for (int q = 0; q < kLdsClasses; ++q) {
+        if (lds_jobs[q].empty()) continue;
+        a.jobs = jobs.p + at;
+        allow_lds((const void*)k_ggg<GGG_LDS>, (int)kLdsBudget);  // beyond the 64 KiB default
+        ProfScope ps(c, KMP_PROF_GGG);
+        hipLaunchKernelGGL(k_ggg<GGG_LDS>, dim3((unsigned)lds_jobs[q].size()), dim3(GGG_THREADS), (size_t)lds_max[q],
+                           c.stream, a);
+        KMP_LAUNCH_CHECK();
+        at += lds_jobs[q].size();
+    }
+    if (!hyb_jobs.empty()) {
+        a.jobs = jobs.p + at;
+        allow_lds((const void*)k_ggg<GGG_HYBRID>, (int)kLdsBudget);
+        ProfScope ps(c, KMP_PROF_GGG);
+        hipLaunchKernelGGL(k_ggg<GGG_HYBRID>, dim3((unsigned)hyb_jobs.size()), dim3(GGG_THREADS), (size_t)hyb_max,
+                           c.stream, a);
+        KMP_LAUNCH_CHECK();
+        at += hyb_jobs.size();
+    }
+    if (!glob_jobs.empty()) {
+        a.jobs = jobs.p + at;
+        ProfScope ps(c, KMP_PROF_GGG);
+        hipLaunchKernelGGL(k_ggg<GGG_GLOBAL>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream, a);
+        KMP_LAUNCH_CHECK();
+    }
+}
+
+// ---------------------------------------------------------------- multilevel IP
+// Multilevel initial bipartitioning (paper Sec. 5.2 "Initial Bipartitioning";
+// kmp_options.ip_multilevel): the subgraphs of the blocks to split become the
+// jobs of one union graph (jobs in block order, a node's union id = its job's
+// offset + its local id, entries in the level graph's row order), which the
+// batch LP (own seed per block, level key 64 + 64 l + i, cluster bound
+// max(heaviest node, larger side bound / kIpCcf)) and the batch contraction
+// coarsen level by level until a job's clustering leaves every node alone;
+// k_ggg bipartitions each job's coarsest graph (the single-level growths and
+// FM), and on the way back every finer level takes the projected sides and
+// k_ggg's refine mode runs the FM passes on them.
+constexpr int64_t kIpCcf = 18;
+constexpr int32_t kIpMaxLev = 32;
+
+// Level-0 union nodes: id, job, node weight, source vertex; rows of up to
+// kGggLightRow entries are counted here, longer ones listed for k_ml_heavy.
+__global__ void k_ml_nodes(const uint32_t* __restrict__ verts, const int32_t* __restrict__ part,
+                           const int32_t* __restrict__ bstart, const int32_t* __restrict__ qidx,
+                           const int32_t* __restrict__ uoff, const int32_t* __restrict__ xadj,
+                           const int32_t* __restrict__ adjncy, const int32_t* __restrict__ vwgt, int32_t n,
+                           int32_t* __restrict__ rows, int32_t* __restrict__ uvw, int32_t* __restrict__ ugid,
+                           int32_t* __restrict__ usrc, int32_t* __restrict__ heavy, int32_t* __restrict__ nheavy)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t v = (int32_t)verts[i];
+    const int32_t b = part[v];
+    const int32_t q = qidx[b];
+    if (q < 0) return;
+    const int32_t uid = uoff[q] + (int32_t)(i - bstart[b]);
+    usrc[uid] = v;
+    ugid[uid] = q;
+    uvw[uid] = vwgt ? vwgt[v] : 1;
+    const int32_t e0 = xadj[v], e1 = xadj[v + 1];
+    if (e1 - e0 > kGggLightRow) {
+        heavy[atomicAdd(nheavy, 1)] = uid;
+        return;
+    }
+    int32_t cnt = 0;
+    for (int32_t e = e0; e < e1; ++e) cnt += part[adjncy[e]] == b;
+    rows[uid] = cnt;
+}
+
+// Internal entries of the listed long rows, one wavefront per row (the grid
+// strides over the list, whose length is read on the device).
+__global__ __launch_bounds__(kBlock) void k_ml_heavy_count(const int32_t* __restrict__ heavy,
+                                                           const int32_t* __restrict__ nheavy,
+                                                           const int32_t* __restrict__ usrc,
+                                                           const int32_t* __restrict__ part,
+                                                           const int32_t* __restrict__ xadj,
+                                                           const int32_t* __restrict__ adjncy,
+                                                           int32_t* __restrict__ rows)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t nh = *nheavy;
+    for (int64_t h = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; h < nh;
+         h += ((int64_t)gridDim.x * blockDim.x) >> 6) {
+        const int32_t uid = heavy[h];
+        const int32_t v = usrc[uid];
+        const int32_t b = part[v];
+        uint32_t cnt = 0;
+        for (int32_t e = xadj[v] + lane; e < xadj[v + 1]; e += 64) cnt += part[adjncy[e]] == b;
+        cnt = group_sum_u32<64>(cnt);
+        if (lane == 0) rows[uid] = (int32_t)cnt;
+    }
+}
+
+// Entries of the union rows: light rows by their own thread, listed rows by a
+// wavefront (ballot keeps the row order).  Neighbour u becomes its job's
+// offset + local[u].
+__global__ __launch_bounds__(kBlock) void k_ml_fill(const int32_t* __restrict__ usrc, const int32_t* __restrict__ ugid,
+                                                    const int32_t* __restrict__ uoff, int32_t N,
+                                                    const int32_t* __restrict__ heavy,
+                                                    const int32_t* __restrict__ nheavy,
+                                                    const int32_t* __restrict__ part,
+                                                    const int32_t* __restrict__ local,
+                                                    const int32_t* __restrict__ xadj,
+                                                    const int32_t* __restrict__ adjncy,
+                                                    const int32_t* __restrict__ adjwgt,
+                                                    const int32_t* __restrict__ uxadj, int32_t* __restrict__ uadj,
+                                                    int32_t* __restrict__ uw)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t uid = t; uid < N; uid += stride) {
+        const int32_t v = usrc[uid];
+        const int32_t e0 = xadj[v], e1 = xadj[v + 1];
+        if (e1 - e0 > kGggLightRow) continue;
+        const int32_t b = part[v], base = uoff[ugid[uid]];
+        int32_t pos = uxadj[uid];
+        for (int32_t e = e0; e < e1; ++e) {
+            const int32_t u = adjncy[e];
+            if (part[u] != b) continue;
+            uadj[pos] = base + local[u];
+            uw[pos] = adjwgt ? adjwgt[e] : 1;
+            ++pos;
+        }
+    }
+    const int lane = threadIdx.x & 63;
+    const int32_t nh = *nheavy;
+    for (int64_t h = t >> 6; h < nh; h += stride >> 6) {
+        const int32_t uid = heavy[h];
+        const int32_t v = usrc[uid];
+        const int32_t b = part[v], base = uoff[ugid[uid]];
+        const int32_t e0 = xadj[v], e1 = xadj[v + 1];
+        int32_t pos = uxadj[uid];
+        for (int32_t c0 = e0; c0 < e1; c0 += 64) {
+            const int32_t e = c0 + lane;
+            const int32_t u = e < e1 ? adjncy[e] : -1;
+            const bool in = u >= 0 && part[u] == b;
+            const uint64_t m = __ballot(in);
+            if (in) {
+                const int32_t at = pos + __popcll(m & ((1ull << lane) - 1));
+                uadj[at] = base + local[u];
+                uw[at] = adjwgt ? adjwgt[e] : 1;
+            }
+            pos += __popcll(m);
+        }
+    }
+}
+
+// Job of every node of a level (members' node ranges in job order).
+__global__ void k_ml_gid(const int32_t* __restrict__ moff, const int32_t* __restrict__ mjob, int32_t cnt, int32_t N,
+                         int32_t* __restrict__ gid, int32_t* __restrict__ local, uint32_t* __restrict__ iota)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    int32_t lo = 0, hi = cnt - 1;  // the last member whose range starts at or before v
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (moff[mid] <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    gid[v] = mjob[lo];
+    local[v] = (int32_t)v - moff[lo];
+    iota[v] = (uint32_t)v;
+}
+
+__global__ void k_ml_init(const int32_t* __restrict__ vw, int32_t n, int32_t* __restrict__ label,
+                          int64_t* __restrict__ cw, int32_t* __restrict__ maxc, const int32_t* __restrict__ gid)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= n) return;
+    label[v] = (int32_t)v;
+    cw[v] = vw[v];
+    atomicMax(&maxc[gid[v]], vw[v]);
+}
+
+__global__ void k_ml_bounds(const int32_t* __restrict__ xadj, const int32_t* __restrict__ moff, int32_t cnt,
+                            int32_t* __restrict__ out)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= cnt) out[i] = xadj[moff[i]];
+}
+
+__global__ void k_ml_project(const int32_t* __restrict__ map, const uint8_t* __restrict__ cside, int32_t n,
+                             uint8_t* __restrict__ side)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v < n && map[v] >= 0) side[v] = cside[map[v]];
+}
+
+__global__ void k_ml_out(const int32_t* __restrict__ usrc, const uint8_t* __restrict__ uside, int32_t N,
+                         uint8_t* __restrict__ side)
+{
+    const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (u < N) side[usrc[u]] = uside[u];
+}
+
+struct MLLevel {
+    OwnedGraph own;
+    DGraph g;
+    std::vector<int32_t> mem;   // member jobs, ascending
+    std::vector<int32_t> moff;  // by member: first node; moff[mem.size()] = n
+    std::vector<int32_t> nq;    // by job: nodes at this level
+    DBuf<int32_t> gid, local, noff, map;
+    DBuf<uint32_t> iota;
+    DBuf<uint8_t> side;
+};
+
+// gid, local ids, identity list and per-job node offsets of a level.
+void ml_tables(Ctx& c, MLLevel& L, int32_t J)
+{
+    const int32_t cnt = (int32_t)L.mem.size();
+    const int32_t N = L.g.n;
+    std::vector<int32_t> noff(J, 0);
+    for (int32_t i = 0; i < cnt; ++i) noff[L.mem[i]] = L.moff[i];
+    L.noff = to_dev(c, noff);
+    DBuf<int32_t> dmoff = to_dev(c, L.moff), dmem = to_dev(c, L.mem);
+    L.gid = DBuf<int32_t>(c, (size_t)std::max(N, 1));
+    L.local = DBuf<int32_t>(c, (size_t)std::max(N, 1));
+    L.iota = DBuf<uint32_t>(c, (size_t)std::max(N, 1));
+    L.side = DBuf<uint8_t>(c, (size_t)std::max(N, 1));
+    if (N > 0) {
+        hipLaunchKernelGGL(k_ml_gid, dim3(grid_for(N)), dim3(kBlock), 0, c.stream, dmoff.p, dmem.p, cnt, N, L.gid.p,
+                           L.local.p, L.iota.p);
+        KMP_LAUNCH_CHECK();
+    }
+}
+
+void ml_bipartition_blocks(Ctx& c, const DGraph& g, int32_t level, const GGGArgs& ga, const std::vector<GGGJob>& gj,
+                           const std::vector<uint64_t>& jseed, const int32_t* hb, int32_t nb)
+{
+    const int32_t J = (int32_t)gj.size();
+    const int32_t n = g.n;
+    std::vector<int32_t> qidx(nb, -1), uoff(J + 1, 0);
+    for (int32_t q = 0; q < J; ++q) {
+        qidx[gj[q].b] = q;
+        uoff[q + 1] = uoff[q] + gj[q].nverts;
+    }
+    const int32_t N0 = uoff[J];
+    if (N0 == 0) return;
+    // ---- level 0: the union of the blocks' subgraphs
+    std::vector<std::unique_ptr<MLLevel>> L;
+    L.emplace_back(new MLLevel());
+    MLLevel& L0 = *L[0];
+    DBuf<int32_t> usrc(c, (size_t)N0);
+    {
+        DBuf<int32_t> dq = to_dev(c, qidx), duoff = to_dev(c, uoff);
+        DBuf<int32_t> rows(c, (size_t)N0 + 1), heavy(c, (size_t)N0), nheavy(c, 1);
+        L0.own.vwgt = DBuf<int32_t>(c, (size_t)N0);
+        DBuf<int32_t> ugid(c, (size_t)N0);
+        c.zero(nheavy.p, sizeof(int32_t));
+        hipLaunchKernelGGL(k_ml_nodes, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, ga.verts, ga.part, ga.bstart, dq.p,
+                           duoff.p, g.xadj, g.adjncy, g.vwgt, n, rows.p, L0.own.vwgt.p, ugid.p, usrc.p, heavy.p,
+                           nheavy.p);
+        KMP_LAUNCH_CHECK();
+        hipLaunchKernelGGL(k_ml_heavy_count, dim3(grid_for(N0, kBlock / 64, 4096)), dim3(kBlock), 0, c.stream,
+                           heavy.p, nheavy.p, usrc.p, ga.part, g.xadj, g.adjncy, rows.p);
+        KMP_LAUNCH_CHECK();
+        L0.own.xadj = DBuf<int32_t>(c, (size_t)N0 + 1);
+        scan_excl_i32(c, rows.p, L0.own.xadj.p, N0, L0.own.xadj.p + N0);
+        const int32_t M0 = c.read1(L0.own.xadj.p + N0);
+        L0.own.adjncy = DBuf<int32_t>(c, (size_t)std::max(M0, 1));
+        L0.own.adjwgt = DBuf<int32_t>(c, (size_t)std::max(M0, 1));
+        hipLaunchKernelGGL(k_ml_fill, dim3(grid_for(N0, kBlock, 4096)), dim3(kBlock), 0, c.stream, usrc.p, ugid.p,
+                           duoff.p, N0, heavy.p, nheavy.p, ga.part, ga.local, g.xadj, g.adjncy, g.adjwgt,
+                           L0.own.xadj.p, L0.own.adjncy.p, L0.own.adjwgt.p);
+        KMP_LAUNCH_CHECK();
+        L0.g = L0.own.view(N0, M0);
+        L0.nq.assign(J, 0);
+        L0.moff.assign(1, 0);
+        for (int32_t q = 0; q < J; ++q) {
+            L0.mem.push_back(q);
+            L0.nq[q] = gj[q].nverts;
+            L0.moff.push_back(uoff[q + 1]);
+        }
+        ml_tables(c, L0, J);
+    }
+    // ---- coarsening (the deterministic sub-round LP, whatever the LP mode of the partition)
+    std::vector<uint32_t> gh(J);
+    for (int32_t q = 0; q < J; ++q) gh[q] = seed_hash(jseed[q]);
+    DBuf<uint32_t> dgh = to_dev(c, gh);
+    std::vector<int32_t> coarsest(J, 0);
+    const int32_t saved_async = c.async_lp;
+    c.async_lp = 0;
+    for (int32_t i = 0;; ++i) {
+        MLLevel& Li = *L[i];
+        const int32_t N = Li.g.n;
+        const uint32_t lvkey = 64u + 64u * (uint32_t)level + (uint32_t)i;
+        DBuf<int32_t> label(c, (size_t)N), maxc(c, (size_t)J);
+        DBuf<int64_t> cw(c, (size_t)N);
+        c.zero(maxc.p, sizeof(int32_t) * J);
+        hipLaunchKernelGGL(k_ml_init, dim3(grid_for(N)), dim3(kBlock), 0, c.stream, Li.g.vwgt, N, label.p, cw.p,
+                           maxc.p, Li.gid.p);
+        KMP_LAUNCH_CHECK();
+        std::vector<int32_t> hmax(J);
+        c.read(hmax.data(), maxc.p, sizeof(int32_t) * J);
+        std::vector<int64_t> U(J, 0);
+        for (int32_t q : Li.mem) U[q] = std::max<int64_t>(hmax[q], std::max(gj[q].cap0, gj[q].cap1) / kIpCcf);
+        DBuf<int64_t> dU = to_dev(c, U);
+        const JobTabs jt{Li.gid.p, dgh.p, Li.noff.p};
+        LPSchedule sched;
+        lp_build_schedule(c, Li.g, (int32_t)lvkey, 0, sched, jt, nullptr, J);
+        LPState ls{label.p, cw.p, N, nullptr, 0, nullptr, TAG_CL, jt, Li.noff.p, dU.p};
+        ls.njobs = J;
+        for (size_t mi = 0; mi < Li.mem.size(); ++mi) {
+            const int32_t q = Li.mem[mi];
+            if (Li.nq[q] > 0 && small_job_fits(c, Li.nq[q], Li.nq[q]) && sched.job_maxdeg[q] <= c.tune.cut[1]) {
+                ls.small_jobs.push_back(q);
+                ls.small_start.push_back(Li.moff[mi]);
+                ls.small_count.push_back(Li.nq[q]);
+                ls.small_loff.push_back(Li.moff[mi]);
+                ls.small_nlab.push_back(Li.nq[q]);
+            }
+        }
+        DBuf<int64_t> mv(c, kRounds + 1);
+        c.zero(mv.p, sizeof(int64_t) * (kRounds + 1));
+        ls.moves_out = mv.p;
+        lp_run(c, Li.g, (int32_t)lvkey, 0, &sched, ls);
+        std::vector<int64_t> nc;
+        count_nonempty_jobs(c, cw.p, N, jt, J, nc);
+        std::vector<uint8_t> keep(J, 0);
+        int32_t nkeep = 0;
+        for (int32_t q : Li.mem) {
+            if (nc[q] < Li.nq[q] && i + 1 < kIpMaxLev) {
+                keep[q] = 1;
+                ++nkeep;
+            } else {
+                coarsest[q] = i;
+            }
+        }
+        if (nkeep == 0) break;
+        std::unique_ptr<MLLevel> next(new MLLevel());
+        Li.map = DBuf<int32_t>(c, (size_t)N);
+        int32_t cn = 0;
+        int64_t cm = 0;
+        DBuf<uint8_t> dkeep = to_dev(c, keep);
+        contract(c, Li.g, label.p, cw.p, Li.map.p, next->own, cn, cm, jt, dkeep.p);
+        next->g = next->own.view(cn, cm);
+        next->nq.assign(J, 0);
+        next->moff.assign(1, 0);
+        for (int32_t q : Li.mem)
+            if (keep[q]) {
+                next->mem.push_back(q);
+                next->nq[q] = (int32_t)nc[q];
+                next->moff.push_back(next->moff.back() + (int32_t)nc[q]);
+            }
+        ml_tables(c, *next, J);
+        L.push_back(std::move(next));
+    }
+    c.async_lp = saved_async;
+    // ---- the growths on every job's coarsest graph
+    const int32_t depth = (int32_t)L.size() - 1;
+    for (int32_t i = 0; i <= depth; ++i) {
+        MLLevel& Li = *L[i];
+        std::vector<int32_t> qs;
+        for (int32_t q : Li.mem)
+            if (coarsest[q] == i) qs.push_back(q);
+        if (qs.empty()) continue;
+        const int32_t cnt = (int32_t)Li.mem.size();
+        DBuf<int32_t> dmoff = to_dev(c, Li.moff), bnd(c, (size_t)cnt + 1);
+        hipLaunchKernelGGL(k_ml_bounds, dim3(grid_for(cnt + 1)), dim3(kBlock), 0, c.stream, Li.g.xadj, dmoff.p, cnt,
+                           bnd.p);
+        KMP_LAUNCH_CHECK();
+        std::vector<int32_t> hbnd(cnt + 1);
+        c.read(hbnd.data(), bnd.p, sizeof(int32_t) * (cnt + 1));
+        std::vector<int32_t> ent(J, 0);
+        for (int32_t mi = 0; mi < cnt; ++mi) ent[Li.mem[mi]] = hbnd[mi + 1] - hbnd[mi];
+        std::vector<GGGJob> jobs;
+        for (int32_t q : qs) {
+            GGGJob jb = gj[q];
+            jb.b = q;
+            jb.nverts = Li.nq[q];
+            jb.dsum = ent[q];
+            jobs.push_back(jb);
+        }
+        GGGArgs a = ga;
+        a.xadj = Li.g.xadj;
+        a.adjncy = Li.g.adjncy;
+        a.vwgt = Li.g.vwgt;
+        a.adjwgt = Li.g.adjwgt;
+        a.part = Li.gid.p;
+        a.verts = Li.iota.p;
+        a.bstart = Li.noff.p;
+        a.local = Li.local.p;
+        a.side = Li.side.p;
+        a.given = nullptr;
+        launch_ggg_jobs(c, a, jobs);
+    }
+    // ---- back up: projection and FM on every finer level
+    for (int32_t i = depth - 1; i >= 0; --i) {
+        MLLevel& Li = *L[i];
+        hipLaunchKernelGGL(k_ml_project, dim3(grid_for(Li.g.n)), dim3(kBlock), 0, c.stream, Li.map.p, L[i + 1]->side.p,
+                           Li.g.n, Li.side.p);
+        KMP_LAUNCH_CHECK();
+        if (ga.fm_passes <= 0) continue;
+        const int32_t cnt = (int32_t)Li.mem.size();
+        DBuf<int32_t> dmoff = to_dev(c, Li.moff), bnd(c, (size_t)cnt + 1);
+        hipLaunchKernelGGL(k_ml_bounds, dim3(grid_for(cnt + 1)), dim3(kBlock), 0, c.stream, Li.g.xadj, dmoff.p, cnt,
+                           bnd.p);
+        KMP_LAUNCH_CHECK();
+        std::vector<int32_t> hbnd(cnt + 1);
+        c.read(hbnd.data(), bnd.p, sizeof(int32_t) * (cnt + 1));
+        std::vector<GGGJob> jobs;
+        for (int32_t mi = 0; mi < cnt; ++mi) {
+            const int32_t q = Li.mem[mi];
+            if (coarsest[q] <= i) continue;
+            GGGJob jb = gj[q];
+            jb.b = q;
+            jb.nverts = Li.nq[q];
+            jb.dsum = hbnd[mi + 1] - hbnd[mi];
+            jobs.push_back(jb);
+        }
+        GGGArgs a = ga;
+        a.xadj = Li.g.xadj;
+        a.adjncy = Li.g.adjncy;
+        a.vwgt = Li.g.vwgt;
+        a.adjwgt = Li.g.adjwgt;
+        a.part = Li.gid.p;
+        a.verts = Li.iota.p;
+        a.bstart = Li.noff.p;
+        a.local = Li.local.p;
+        a.side = Li.side.p;
+        a.given = Li.side.p;
+        a.pool = 0;
+        launch_ggg_jobs(c, a, jobs);
+    }
+    hipLaunchKernelGGL(k_ml_out, dim3(grid_for(N0)), dim3(kBlock), 0, c.stream, usrc.p, L0.side.p, N0, ga.side);
+    KMP_LAUNCH_CHECK();
+}
+
+}  // namespace
+
 int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, BlockTab& bt,
                           const std::vector<uint8_t>& split, const std::vector<int64_t>& lk,
-                          const std::vector<uint32_t>& hseed, const std::vector<AdaptiveJob>* adapt)
+                          const std::vector<uint32_t>& hseed, const std::vector<AdaptiveJob>* adapt,
+                          const std::vector<uint64_t>* seeds64)
 {
     const int32_t n = g.n;
     const int32_t nb = bt.size();
@@ -930,17 +1466,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         }
         const int32_t* hb = hbd.data();
         const int32_t* hd = hbd.data() + nb + 1;
-        // LDS launches by size class when there are more blocks than one launch at the
-        // largest size keeps resident (a launch's LDS size is its largest block's), so
-        // that blocks of small subgraphs share a CU (four 512-thread workgroups fit one
-        // CU when each takes at most 40 KiB); else one LDS launch (launches run one
-        // after the other, so splitting few blocks only serialises them); then the
-        // hybrid and the global layouts
-        constexpr int kLdsClasses = 4;
-        const int64_t lds_class_max[kLdsClasses] = {40 << 10, 53 << 10, 80 << 10, kLdsBudget};
-        std::vector<GGGJob> lds_jobs[kLdsClasses], hyb_jobs, glob_jobs;
-        int64_t lds_max[kLdsClasses] = {0, 0, 0, 0}, hyb_max = 0, scratch_total = 0;
-        const bool fm = c.fm_passes > 0;
+        std::vector<GGGJob> gjobs;
         for (int32_t bb = 0; bb < nb; ++bb) {
             if (!split[bb]) continue;
             const int32_t jb_job = bt.job.empty() ? 0 : bt.job[bb];
@@ -958,40 +1484,8 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             jb.cap0 = (int64_t)(jb.f / 2) * jb.lk;
             jb.cap1 = (int64_t)(jb.f - jb.f / 2) * jb.lk;
             if (adapt) adaptive_side_caps((*adapt)[jb_job], hbw[bb], jb.f, jb.cap0, jb.cap1);
-            const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum, fm);
-            const int64_t hbytes = ggg_hybrid_lds(jb.nverts, fm);
-            if (bytes <= kLdsBudget) {
-                int q = 0;
-                while (bytes > lds_class_max[q]) ++q;
-                lds_jobs[q].push_back(jb);
-                lds_max[q] = std::max(lds_max[q], bytes);
-            } else if (hbytes <= kLdsBudget) {
-                jb.scratch = scratch_total;
-                scratch_total += ((int64_t)jb.dsum * 8 + 255) & ~(int64_t)255;
-                hyb_jobs.push_back(jb);
-                hyb_max = std::max(hyb_max, hbytes);
-            } else {
-                jb.scratch = scratch_total;
-                scratch_total += (bytes + 255) & ~(int64_t)255;
-                glob_jobs.push_back(jb);
-            }
+            gjobs.push_back(jb);
             ++calls;
-        }
-        {
-            size_t nl = 0;
-            int64_t mx = 0;
-            for (int q = 0; q < kLdsClasses; ++q) {
-                nl += lds_jobs[q].size();
-                mx = std::max(mx, lds_max[q]);
-            }
-            const int64_t resident = 256 * std::max<int64_t>(1, std::min<int64_t>(4, (160 << 10) / std::max<int64_t>(mx, 1)));
-            if ((int64_t)nl <= resident)
-                for (int q = 0; q + 1 < kLdsClasses; ++q) {
-                    lds_jobs[kLdsClasses - 1].insert(lds_jobs[kLdsClasses - 1].end(), lds_jobs[q].begin(),
-                                                     lds_jobs[q].end());
-                    lds_jobs[q].clear();
-                    lds_max[kLdsClasses - 1] = mx;
-                }
         }
         GGGArgs a;
         a.xadj = g.xadj;
@@ -1006,45 +1500,16 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         a.scratch = nullptr;
         a.fm_passes = c.fm_passes;
         a.pool = c.ip_pool ? 1 : 0;
-        DBuf<char> scratch;
-        if (scratch_total > 0) scratch = DBuf<char>(c, (size_t)scratch_total);
-        a.scratch = scratch.p;
-        // every job list of the round in one upload
-        size_t njobs_all = hyb_jobs.size() + glob_jobs.size();
-        for (int q = 0; q < kLdsClasses; ++q) njobs_all += lds_jobs[q].size();
-        std::vector<GGGJob> all;
-        all.reserve(njobs_all);
-        for (int q = 0; q < kLdsClasses; ++q) all.insert(all.end(), lds_jobs[q].begin(), lds_jobs[q].end());
-        all.insert(all.end(), hyb_jobs.begin(), hyb_jobs.end());
-        all.insert(all.end(), glob_jobs.begin(), glob_jobs.end());
-        DBuf<GGGJob> jobs(c, std::max<size_t>(all.size(), 1));
-        if (!all.empty()) c.write(jobs.p, all.data(), sizeof(GGGJob) * all.size());
-        size_t at = 0;
-        for (int q = 0; q < kLdsClasses; ++q) {
-            if (lds_jobs[q].empty()) continue;
-            a.jobs = jobs.p + at;
-            allow_lds((const void*)k_ggg<GGG_LDS>, (int)kLdsBudget);  // beyond the 64 KiB default
-            ProfScope ps(c, KMP_PROF_GGG);
-            hipLaunchKernelGGL(k_ggg<GGG_LDS>, dim3((unsigned)lds_jobs[q].size()), dim3(GGG_THREADS),
-                               (size_t)lds_max[q], c.stream, a);
-            KMP_LAUNCH_CHECK();
-            at += lds_jobs[q].size();
-        }
-        if (!hyb_jobs.empty()) {
-            a.jobs = jobs.p + at;
-            allow_lds((const void*)k_ggg<GGG_HYBRID>, (int)kLdsBudget);
-            ProfScope ps(c, KMP_PROF_GGG);
-            hipLaunchKernelGGL(k_ggg<GGG_HYBRID>, dim3((unsigned)hyb_jobs.size()), dim3(GGG_THREADS),
-                               (size_t)hyb_max, c.stream, a);
-            KMP_LAUNCH_CHECK();
-            at += hyb_jobs.size();
-        }
-        if (!glob_jobs.empty()) {
-            a.jobs = jobs.p + at;
-            ProfScope ps(c, KMP_PROF_GGG);
-            hipLaunchKernelGGL(k_ggg<GGG_GLOBAL>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream,
-                               a);
-            KMP_LAUNCH_CHECK();
+        a.given = nullptr;
+        if (c.ip_multilevel) {
+            std::vector<uint64_t> jseed(gjobs.size());
+            for (size_t q = 0; q < gjobs.size(); ++q) {
+                const int32_t jb_job = bt.job.empty() ? 0 : bt.job[gjobs[q].b];
+                jseed[q] = (*seeds64)[jb_job] ^ ((uint64_t)(uint32_t)gjobs[q].first << 32);
+            }
+            ml_bipartition_blocks(c, g, level, a, gjobs, jseed, hb, nb);
+        } else {
+            launch_ggg_jobs(c, a, gjobs);
         }
     }
     // renumber blocks: split blocks become (first, f0) and (first + f0, f - f0)

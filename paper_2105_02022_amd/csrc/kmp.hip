@@ -749,7 +749,8 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
                 any |= split[b] != 0;
             }
             if (!any) break;
-            t.bip += bipartition_round(c, g, l, part.p, bt, split, lkv, hseed, c.adaptive_eps ? &adapt : nullptr);
+            t.bip += bipartition_round(c, g, l, part.p, bt, split, lkv, hseed, c.adaptive_eps ? &adapt : nullptr,
+                                       &seeds);
         }
         if (phase_sync) c.sync();
         t.ms_ip += ms_since(t1);
@@ -1130,7 +1131,9 @@ int set_ip_options(Ctx& c, const kmp_options* opt)
     // the GPU queue balancer is switched off: its first GPU run faulted and the cause is not yet shown
     if (opt && opt->pq_balance != 0) return KMP_EINVAL;
     if (opt && (opt->async_lp < 0 || opt->async_lp > 2)) return KMP_EINVAL;
+    if (opt && opt->ip_multilevel != 0 && opt->ip_multilevel != 1) return KMP_EINVAL;
     c.fm_passes = opt ? opt->fm_passes : 0;
+    c.ip_multilevel = opt && opt->ip_multilevel;
     c.async_lp = opt ? opt->async_lp : 0;
     c.ip_pool = opt && opt->ip_pool;
     c.adaptive_eps = opt && opt->adaptive_eps;

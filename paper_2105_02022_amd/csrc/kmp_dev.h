@@ -362,6 +362,7 @@ class Ctx {
     bool ip_pool = false;        // initial bipartitioning also runs BFS and random growths
     bool adaptive_eps = false;   // bipartition sides bounded by the adaptive imbalance
     bool pq_balance = false;     // balancing by the queue balancer
+    bool ip_multilevel = false;  // initial bipartitioning coarsens each block's subgraph first
     int32_t async_lp = 0;        // LP: 0 deterministic sub-rounds, 1 asynchronous, 2 asynchronous one node
                                  // per launch in visit order (the one-processing-element execution)
     int32_t small_level_n = 0;   // LP: one-workgroup levels up to this size (0: tune's, < 0 never)
@@ -668,9 +669,11 @@ struct AdaptiveJob {
 void adaptive_side_caps(const AdaptiveJob& j, int64_t cB, int32_t f, int64_t& cap0, int64_t& cap1);
 // Validates and copies the initial-bipartitioning options (fm_passes, ip_pool, adaptive_eps).
 int set_ip_options(Ctx& c, const kmp_options* opt);
+// seeds64 (per job, the 64-bit seeds) is needed with c.ip_multilevel.
 int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part, BlockTab& bt,
                           const std::vector<uint8_t>& split, const std::vector<int64_t>& lk,
-                          const std::vector<uint32_t>& hseed, const std::vector<AdaptiveJob>* adapt = nullptr);
+                          const std::vector<uint32_t>& hseed, const std::vector<AdaptiveJob>* adapt = nullptr,
+                          const std::vector<uint64_t>* seeds64 = nullptr);
 void project(Ctx& c, const int32_t* coarse_part, const int32_t* map, int32_t* fine_part, int32_t n);
 // Batches: nodes with map >= 0 take remap[coarse block]; the others start in
 // their job's single block start_block[job].

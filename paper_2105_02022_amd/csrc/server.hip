@@ -74,7 +74,7 @@ int size_class_of(const kmp_graph_desc& d)
 bool same_options(const kmp_options& a, const kmp_options& b)
 {
     return a.fm_passes == b.fm_passes && a.ip_pool == b.ip_pool && a.adaptive_eps == b.adaptive_eps &&
-           a.pq_balance == b.pq_balance && a.async_lp == b.async_lp;
+           a.pq_balance == b.pq_balance && a.async_lp == b.async_lp && a.ip_multilevel == b.ip_multilevel;
 }
 
 void worker_main(kmp_server* s, int w)
@@ -212,13 +212,14 @@ int kmp_server_set_options(kmp_server* s, const kmp_options* opt)
     if (opt) {
         if (opt->fm_passes < 0 || opt->fm_passes > kmp::kFmMaxPasses || (opt->ip_pool != 0 && opt->ip_pool != 1) ||
             (opt->adaptive_eps != 0 && opt->adaptive_eps != 1) || opt->pq_balance != 0 || opt->async_lp < 0 ||
-            opt->async_lp > 2)
+            opt->async_lp > 2 || (opt->ip_multilevel != 0 && opt->ip_multilevel != 1))
             return KMP_EINVAL;
         o.fm_passes = opt->fm_passes;
         o.ip_pool = opt->ip_pool;
         o.adaptive_eps = opt->adaptive_eps;
         o.pq_balance = opt->pq_balance;
         o.async_lp = opt->async_lp;
+        o.ip_multilevel = opt->ip_multilevel;
     }
     std::lock_guard<std::mutex> lk(s->mu);
     s->opt = o;

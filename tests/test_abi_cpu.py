@@ -89,7 +89,7 @@ def test_struct_layouts_match_header(tmp_path):
     fields = {"kmp_graph_desc": (kmp.KmpGraphDesc, ["n", "m", "seed", "out_part"]),
               "kmp_job_result": (kmp.KmpJobResult, ["cut", "lk", "level_n"]),
               "kmp_options": (kmp.KmpOptions, ["profile_classes", "force_exact", "small_level_n", "plain_loads",
-                                               "fm_passes", "ip_pool", "pq_balance", "async_lp"]),
+                                               "fm_passes", "ip_pool", "pq_balance", "async_lp", "ip_multilevel"]),
               "kmp_stats": (kmp.KmpStats, ["lp_exact_subrounds", "level_n", "level_m", "ms_total", "prof_bytes"]),
               "kmp_server_stats": (kmp.KmpServerStats, ["hbm_in_use", "running_batches"]),
               "kmp_tuning": (kmp.KmpTuning, ["tier3_deg", "reserved"]),
