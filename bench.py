@@ -21,7 +21,8 @@ cpu_baseline: the CPU oracle (single thread) on the same workload.
 
 ip_options: the same workload under the initial-bipartitioning options,
 2-way FM after every growth (--fm-compare passes), the BFS + random pool,
-and both (the timed steps use --fm-passes and --ip-pool, off by default):
+both, and the multilevel bipartitioning with FM (the timed steps use
+--fm-passes and --ip-pool, off by default):
 cut, time per partition without events, GGG class time, and the oracle's
 cut, time and parity for each.
 
@@ -480,32 +481,33 @@ def main():
     ip_cmp = None
     ip_parts = {}
     if args.ip_compare:
-        configs = [(fm, pool)]
-        for c in ((args.fm_compare, 0), (0, 1), (args.fm_compare, 1)):
-            if c not in configs and (c[0] or c[1]):
+        configs = [(fm, pool, 0)]
+        for c in ((args.fm_compare, 0, 0), (0, 1, 0), (args.fm_compare, 1, 0), (args.fm_compare, 0, 1)):
+            if c not in configs and (c[0] or c[1] or c[2]):
                 configs.append(c)
         ip_cmp = {"steps": args.ip_steps}
         out2 = torch.empty_like(out)
-        for (p, q) in configs:
-            name = f"fm{p}_pool{q}"
-            if (p, q) == (fm, pool):
+        for (p, q, ml) in configs:
+            name = f"fm{p}_pool{q}" + ("_multilevel" if ml else "")
+            if (p, q, ml) == (fm, pool, 0):
                 st_c, ms_c2, prof_c, part_c = st_all, ms_plain, st_all["prof"]["ggg"], part
             else:
                 for _ in range(2):
-                    kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2, fm_passes=p, ip_pool=q)
+                    kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2, fm_passes=p, ip_pool=q,
+                                         ip_multilevel=ml)
                 torch.cuda.synchronize()
                 t2 = time.perf_counter()
                 for _ in range(args.ip_steps):
                     rc2, _, st_c = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2,
-                                                        fm_passes=p, ip_pool=q)
+                                                        fm_passes=p, ip_pool=q, ip_multilevel=ml)
                     assert rc2 == 0, kmp.kmp_strerror(rc2)
                 torch.cuda.synchronize()
                 ms_c2 = (time.perf_counter() - t2) * 1e3 / args.ip_steps
                 part_c = out2.cpu().numpy()
                 _, _, st_p = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, eps, seed, out=out2, profile=True,
-                                                  fm_passes=p, ip_pool=q)
+                                                  fm_passes=p, ip_pool=q, ip_multilevel=ml)
                 prof_c = st_p["prof"]["ggg"]
-            ip_cmp[name] = {"fm_passes": p, "ip_pool": q, "cut": st_c["cut"],
+            ip_cmp[name] = {"fm_passes": p, "ip_pool": q, "ip_multilevel": ml, "cut": st_c["cut"],
                             "ms_per_partition_without_events": round(ms_c2, 3),
                             "ggg_ms_per_partition": round(prof_c["ms"], 3), "ggg_launches": prof_c["launches"]}
             ip_parts[name] = part_c
@@ -567,7 +569,7 @@ def main():
                     continue
                 t = time.perf_counter()
                 ref_c = oracle.partition(g, k, eps, seed, validate_input=False, fm_passes=row["fm_passes"],
-                                         pool=bool(row["ip_pool"]))
+                                         pool=bool(row["ip_pool"]), ip_multilevel=bool(row["ip_multilevel"]))
                 row["oracle_s"] = round(time.perf_counter() - t, 2)
                 row["oracle_cut"] = ref_c.stats["cut"]
                 row["parity_with_oracle"] = bool(np.array_equal(ref_c.part, ip_parts[name])) and \

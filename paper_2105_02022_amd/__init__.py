@@ -557,9 +557,10 @@ def to_device(g, device="cuda"):
 
 
 def partition(g, k: int, epsilon: float = 0.03, seed: int = 1, device="cuda", validate: bool = False,
-              fm_passes: int = 0, ip_pool: bool = False):
+              fm_passes: int = 0, ip_pool: bool = False, adaptive_eps: bool = False, ip_multilevel: bool = False):
     """Convenience: partition a generator Graph; returns (status, part numpy, stats)."""
     xadj, adjncy, vwgt, adjwgt = to_device(g, device)
     rc, out, stats = kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, epsilon, seed, validate=validate,
-                                      fm_passes=fm_passes, ip_pool=ip_pool)
+                                      fm_passes=fm_passes, ip_pool=ip_pool, adaptive_eps=adaptive_eps,
+                                      ip_multilevel=ip_multilevel)
     return rc, out.cpu().numpy(), stats

@@ -32,6 +32,7 @@ CASES = {
     "rgg20_k64": ("rgg20", 64, 0.03, 1),
     "rmat22_k32768": ("rmat22", 1 << 15, 0.03, 1),
     "rgg20_k64_pool_fm2": ("rgg20", 64, 0.03, 1, {"fm_passes": 2, "ip_pool": 1}),
+    "rgg20_k64_ml_fm2": ("rgg20", 64, 0.03, 1, {"fm_passes": 2, "ip_multilevel": 1}),
 }
 
 
@@ -56,7 +57,9 @@ def make(name):
     g = gen.workload(wl)
     t_gen = time.time() - t
     t = time.time()
-    r = oracle.partition(g, k, eps, seed, fm_passes=opts.get("fm_passes", 0), pool=bool(opts.get("ip_pool", 0)))
+    r = oracle.partition(g, k, eps, seed, fm_passes=opts.get("fm_passes", 0), pool=bool(opts.get("ip_pool", 0)),
+                         adaptive_eps=bool(opts.get("adaptive_eps", 0)),
+                         ip_multilevel=bool(opts.get("ip_multilevel", 0)))
     t_or = time.time() - t
     bw = block_weights(r.part, g.vwgt, k)
     out = {

@@ -445,7 +445,9 @@ def test_partition_golden(kmp, case):
     say(f"[golden] {case}: n={g.n} m={g.m} k={k}")
     opts = exp.get("options", {})
     rc, part, stats = kmp.partition(g, k, exp["eps"], exp["seed"], fm_passes=opts.get("fm_passes", 0),
-                                    ip_pool=bool(opts.get("ip_pool", 0)))
+                                    ip_pool=bool(opts.get("ip_pool", 0)),
+                                    adaptive_eps=bool(opts.get("adaptive_eps", 0)),
+                                    ip_multilevel=bool(opts.get("ip_multilevel", 0)))
     assert rc == exp["status"]
     bw = np.bincount(part, minlength=k).astype(np.int64)
     assert stats["cut"] == exp["stats"]["cut"]
