@@ -824,17 +824,17 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
     if (!batch) edge_cut_launch(c, L0.g, part.p);
     constexpr int32_t nm = 2 * (kRounds + 1);
     std::vector<std::pair<const int64_t*, int32_t>> segs = {
-        {wt.p, nb}, {c.spread(SP_RATED), kSpreadSlots}, {dmoves.p, nm}};
-    if (!batch) segs.push_back({c.spread(SP_CUT), kSpreadSlots});
-    std::vector<int64_t> h((size_t)nb + kSpreadSlots + nm + (batch ? 0 : kSpreadSlots));
+        {wt.p, nb}, {c.spread(SP_RATED), kSpreadWords}, {dmoves.p, nm}};
+    if (!batch) segs.push_back({c.spread(SP_CUT), kSpreadWords});
+    std::vector<int64_t> h((size_t)nb + kSpreadWords + nm + (batch ? 0 : kSpreadWords));
     read_segments(c, segs, h.data());
     const int64_t* hw = h.data();
     const int64_t* hr = hw + nb;
-    const int64_t* hm = hr + kSpreadSlots;
+    const int64_t* hm = hr + kSpreadWords;
     for (int32_t b = 0; b < nb; ++b) jobs[bt.job[b]].maxw = std::max(jobs[bt.job[b]].maxw, hw[b]);
     if (!batch) {
         int64_t cut2 = 0;
-        for (int q = 0; q < kSpreadSlots; ++q) cut2 += hm[nm + q];
+        for (int q = 0; q < kSpreadWords; ++q) cut2 += hm[nm + q];
         jobs[0].cut = cut2 / 2;
     } else {
         std::vector<int64_t> cuts;
@@ -843,7 +843,7 @@ void run_jobs(Ctx& c, std::vector<JobRun>& jobs, bool batch, const DBuf<JobPtrs>
     }
     for (int32_t j : L0.mem) jobs[j].status = jobs[j].maxw > jobs[j].lk ? KMP_IMBALANCED : KMP_OK;
     t.rated = 0;
-    for (int q = 0; q < kSpreadSlots; ++q) t.rated += hr[q];
+    for (int q = 0; q < kSpreadWords; ++q) t.rated += hr[q];
     for (int r = 0; r < kRounds; ++r) {
         t.moves_cl += hm[r];
         t.moves_ref += hm[kRounds + 1 + r];

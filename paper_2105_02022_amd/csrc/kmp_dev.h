@@ -259,11 +259,15 @@ struct Prof {
     ~Prof();
 };
 
-// Spread counters: every logical counter owns 64 slots; a block adds to slot
-// (blockIdx.x & 63) and the host sums the slots.  Atomics on one address from
-// thousands of wavefronts serialise (about 11 ns each), so no hot counter is
-// a single word.
-constexpr int kSpreadSlots = 64;
+// Spread counters: every logical counter owns kSpreadSlots slots, each on a
+// 128-byte line of its own (kSpreadStride words apart); a block (or wavefront)
+// adds to one slot and the host sums the counter's kSpreadWords words (the
+// words between the slots stay 0).  Atomics on one line serialise in the L2,
+// so a hot counter's adds spread over kSpreadSlots lines; kernels with many
+// waves add once per block.
+constexpr int kSpreadSlots = 8;
+constexpr int kSpreadStride = 16;
+constexpr int kSpreadWords = kSpreadSlots * kSpreadStride;
 enum SpreadCounter {
     SP_RATED = 0,           // LP rated directed entries
     SP_BYTES = 1,           // + class: algorithmic bytes per profiling class (16)
@@ -276,7 +280,8 @@ enum SpreadCounter {
 };
 __device__ inline void spread_add(int64_t* base, int64_t v)
 {
-    atomicAdd((unsigned long long*)&base[blockIdx.x & (kSpreadSlots - 1)], (unsigned long long)v);
+    const uint32_t slot = (blockIdx.x + (threadIdx.x >> 6)) & (kSpreadSlots - 1);
+    atomicAdd((unsigned long long*)&base[slot * kSpreadStride], (unsigned long long)v);
 }
 
 // out[j] += x for every lane with job j >= 0.  Node ids are grouped by job, so

@@ -46,11 +46,13 @@ constexpr int kCandChunk = 1024;    // contended entries staged in LDS per pass
 // ctl[] layout (int64, device): round control shared by the kernels (the
 // contended-list length alternates between CTL_CONT and CTL_CONT + 1 by
 // sub-round parity, so that each apply clears the next one's; an abort records
-// its round stamp and sub-round), then one set of kSpreadSlots per-block move
-// counts per round (CTL_MS + r * kSpreadSlots), then the segment table of the
-// lists without the skipped jobs (batches)
+// its round stamp and sub-round), then the per-block move counts of every round
+// as a spread counter whose slot lines hold one word per round (round r of slot
+// q at CTL_MS + q * kSpreadStride + r), then the segment table of the lists
+// without the skipped jobs (batches)
 enum { CTL_ABORT = 0, CTL_ABORT_SUB = 1, CTL_ABORT_STAMP = 2, CTL_CONT = 3, CTL_N = 8, CTL_MS = CTL_N };
-constexpr int kCtlWords = CTL_N + kRounds * kSpreadSlots + kSegs;  // int64 words (the table: 2 kSegs int32)
+static_assert(kRounds <= kSpreadStride, "a round count per word of a slot line");
+constexpr int kCtlWords = CTL_N + kSpreadWords + kSegs;  // int64 words (the table: 2 kSegs int32)
 
 // Largest degree of tiers 0..3 (a tuning choice bounded by T0_DEG .. T3_DEG).
 struct TierCuts {
@@ -267,9 +269,9 @@ struct RateArgs {
     const int32_t* loff;
     const int64_t* gcap;
     uint32_t tag, level, round;
-    // byte sizes of adjncy and label for buffer loads (bufok: both below 2^31, so
-    // every byte offset fits the 32-bit offset of a buffer load)
-    uint32_t nr_adj, nr_lab;
+    // byte sizes of adjncy, label and wt for buffer loads (bufok: all below 2^31,
+    // so every byte offset fits the 32-bit offset of a buffer load)
+    uint32_t nr_adj, nr_lab, nr_wt;
     int32_t bufok;
     // asynchronous LP (amode != 0): a node that finds a better admissible label
     // moves at once.  1: fetch-and-add on the two weights (clustering: the bound
@@ -287,6 +289,9 @@ struct RateArgs {
 // the buffer's size returns 0 without a memory access, so lanes with nothing
 // to load take part in a gather without touching memory.
 constexpr int kBufMiss = (int)0xFFFFFFF0u;
+// the miss offset of 16-byte loads: at or past every buffer size here (below
+// 2^31), and offset + 16 does not wrap
+constexpr int kBufMiss16 = (int)0x80000000u;
 __device__ inline __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes)
 {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
@@ -373,135 +378,293 @@ __device__ inline void consider(const RateArgs& a, const NodeKey& nk, uint32_t k
     }
 }
 
-// per-wave statistic: rated entries and algorithmic bytes (a wave rates fewer
-// than 2^31 entries: a single graph has fewer, batches stay below 2^31)
+// Per-block statistics: rated entries, algorithmic bytes and (asynchronous
+// mode) moves, summed per wavefront, then per block in LDS, one atomic each per
+// block (a wave rates fewer than 2^31 entries: a single graph has fewer,
+// batches stay below 2^31).  Every thread of the block must call this.
 __device__ inline void flush_stats(const RateArgs& a, int64_t nodes_in, int64_t edges_in, int64_t moves_in = 0)
 {
-    const int64_t edges = group_sum_u32<64>((uint32_t)edges_in);
-    const int64_t nodes = group_sum_u32<64>((uint32_t)nodes_in);
-    if ((threadIdx.x & 63) == 0 && nodes) {
-        spread_add(a.counters, edges);
-        spread_add(a.bytes_ctr, 25 * nodes + (a.adjwgt ? 12 : 8) * edges);
+    __shared__ unsigned long long s_stat[3];
+    if (threadIdx.x == 0) s_stat[0] = s_stat[1] = s_stat[2] = 0;
+    __syncthreads();
+    const uint32_t edges = group_sum_u32<64>((uint32_t)edges_in);
+    const uint32_t nodes = group_sum_u32<64>((uint32_t)nodes_in);
+    const uint32_t moves = a.moved_ctr ? group_sum_u32<64>((uint32_t)moves_in) : 0u;  // uniform branch
+    if ((threadIdx.x & 63) == 0 && (nodes | moves)) {
+        atomicAdd(&s_stat[0], (unsigned long long)edges);
+        atomicAdd(&s_stat[1], (unsigned long long)nodes);
+        atomicAdd(&s_stat[2], (unsigned long long)moves);
     }
-    if (a.moved_ctr) {  // uniform: asynchronous mode only
-        const int64_t moves = group_sum_u32<64>((uint32_t)moves_in);
-        if ((threadIdx.x & 63) == 0 && moves) spread_add(a.moved_ctr, moves);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t e = (int64_t)s_stat[0], nd = (int64_t)s_stat[1], mv = (int64_t)s_stat[2];
+        if (nd) {
+            spread_add(a.counters, e);
+            spread_add(a.bytes_ctr, 25 * nd + (a.adjwgt ? 12 : 8) * e);
+        }
+        if (a.moved_ctr && mv) spread_add(a.moved_ctr, mv);
     }
 }
 
-// Tier 0: one lane per node; labels and weights of the <= DEG neighbours live in
-// registers.  Loads use clamped indices so that they are unconditional and the
-// compiler issues each batch (neighbour ids, labels, candidate weights) back to
-// back with a single wait; duplicates are merged into their first occurrence
-// with selects.  EW: edge weights present; CAPV: per-label caps; BAL: balance
-// mode.
-template <int DEG, bool EW, bool CAPV, bool BAL, bool BUF>
+// Branch-free best-key update.  A candidate's key is (rating << 32 | ~hash):
+// a larger key is a larger rating, or an equal rating with a smaller hash;
+// equal keys fall back to the smaller label.  Key 0 marks "no candidate" and
+// never wins (a real rating is at least 1).
+__device__ inline void take_best(uint64_t& bk, uint32_t& bl, uint64_t key, uint32_t lab)
+{
+    const bool t = key > bk || (key == bk && lab < bl);
+    bk = t ? key : bk;
+    bl = t ? lab : bl;
+}
+
+__device__ inline Key3 key3_of(uint64_t key, uint32_t lab)
+{
+    return Key3{(uint32_t)(key >> 32), ~(uint32_t)key, lab};
+}
+
+// Batcher's odd-even merge sort as a compare-exchange network over N register
+// slots (19 exchanges for N = 8, 63 for N = 16): labels ascending, EMPTY last.
+// W: the weights travel with their labels (else every weight is 1).  Slots
+// that hold the constant EMPTY fold their exchanges away at compile time.
+template <int N, bool W>
+__device__ inline void sort_slots(uint32_t (&k)[N], uint32_t (&w)[N])
+{
+#pragma unroll
+    for (int p = 1; p < N; p <<= 1) {
+#pragma unroll
+        for (int s = p; s >= 1; s >>= 1) {
+#pragma unroll
+            for (int j = s % p; j + s < N; j += 2 * s) {
+#pragma unroll
+                for (int i = 0; i < s; ++i) {
+                    const int x = i + j, y = i + j + s;
+                    if (y < N && x / (2 * p) == y / (2 * p)) {
+                        const uint32_t kx = k[x], ky = k[y];
+                        k[x] = kx < ky ? kx : ky;
+                        k[y] = kx < ky ? ky : kx;
+                        if constexpr (W) {
+                            const uint32_t wx = w[x], wy = w[y];
+                            w[x] = kx > ky ? wy : wx;
+                            w[y] = kx > ky ? wx : wy;
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+// The rating of one node from its neighbours' labels and edge weights in the
+// first L of N register slots (N = 4, 8 or 16 >= L; slots at or past the
+// node's degree hold EMPTY): sort the slots by label, sum every run of equal
+// labels into its last slot, then walk the run ends once for the own label's
+// rating, the favoured label (FAV) and the best admissible label.
+// wt_of(l), cap_of(l), over_of(l): label l's weight, cap and overload flag;
+// the hash takes l - hoff.
+template <int N, int L, bool W, bool FAV, class WT, class CAP, class OV>
+__device__ inline void choose_slots(const uint32_t (&lab_in)[L], const uint32_t (&w_in)[L], uint32_t own,
+                                    uint32_t hp, uint32_t hoff, int64_t cv, WT wt_of, CAP cap_of, OV over_of,
+                                    Key3& fav, Key3& adm, uint32_t& rown)
+{
+    uint32_t lab[N], w[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        lab[j] = j < L ? lab_in[j] : EMPTY;
+        w[j] = j < L ? w_in[j] : 1u;
+    }
+    sort_slots<N, W>(lab, w);
+#pragma unroll
+    for (int j = 1; j < L; ++j) w[j] += lab[j] == lab[j - 1] ? w[j - 1] : 0u;
+    uint32_t cand[L];
+    int64_t wk[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint32_t K = lab[j];
+        const bool end = j == N - 1 || lab[j + 1] != K;
+        const bool real = end && K != EMPTY;
+        rown = real && K == own ? w[j] : rown;
+        cand[j] = real && K != own ? K : EMPTY;
+    }
+    // weights of the candidates (wt_of sees EMPTY for the other slots)
+#pragma unroll
+    for (int j = 0; j < L; ++j) wk[j] = wt_of(cand[j]);
+    uint64_t fk = 0, ak = 0;
+    uint32_t fl = 0, al = 0;
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        const uint32_t K = lab[j];
+        const bool c = cand[j] != EMPTY;
+        const uint32_t h = hash_step(hp, K - hoff, 4);
+        const uint64_t key = c ? ((uint64_t)w[j] << 32) | (uint64_t)(~h) : 0ull;
+        if constexpr (FAV) take_best(fk, fl, key, K);
+        const uint32_t l = c ? K : own;
+        const bool fits = c && wk[j] + cv <= cap_of(l) && !over_of(l);
+        take_best(ak, al, fits ? key : 0ull, K);
+    }
+    fav = key3_of(fk, fl);
+    adm = key3_of(ak, al);
+}
+
+// Tier 0: one lane per node; the neighbours' labels and edge weights live in
+// L registers (L >= the largest degree in the wavefront).  Gathers are
+// unconditional (clamped indices, or buffer loads in which lanes past their
+// degree miss), so each batch is issued back to back with one wait.  EW: edge
+// weights present; CAPV: per-label caps; BAL: balance mode.
+template <int L, bool EW, bool CAPV, bool BAL, bool BUF>
 __device__ inline int rate_lane_node(const RateArgs& a, int32_t v, uint32_t own, int32_t e0, int32_t d, int64_t cv,
                                      const NodeKey& nk)
 {
-    uint32_t lab[DEG], w[DEG];
+    constexpr int N = L <= 4 ? 4 : L <= 8 ? 8 : 16;
+    static_assert(L % 4 == 0, "rows are loaded four entries at a time");
+    uint32_t lab[L], w[L];
+#pragma unroll
+    for (int j = 0; j < L; ++j) {
+        lab[j] = EMPTY;
+        w[j] = 1u;
+    }
     if (d > 0) {
-        int32_t u[DEG];
+        int32_t u[L];
         if constexpr (BUF) {
-            // only the node's own entries are loaded (lanes past their degree miss)
+            // the row four entries per load (dword-aligned 16-byte loads); a load that
+            // would reach past the end of adjncy misses and its entries are fetched one
+            // by one below (only the last rows of the array); lanes past their degree miss
             const __amdgpu_buffer_rsrc_t radj = buf_rsrc(a.adjncy, a.nr_adj), rlab = buf_rsrc(a.label, a.nr_lab);
+            const uint32_t m = a.nr_adj >> 2;
+            bool tail = false;
 #pragma unroll
-            for (int j = 0; j < DEG; ++j)
-                u[j] = __builtin_amdgcn_raw_buffer_load_b32(radj, j < d ? (e0 + j) * 4 : kBufMiss, 0, 0);
+            for (int q = 0; q < L / 4; ++q) {
+                const bool inrow = 4 * q < d;
+                const bool whole = (uint32_t)(e0 + 4 * q + 4) <= m;
+                tail = tail || (inrow && !whole);
+                const auto x = __builtin_amdgcn_raw_buffer_load_b128(radj, inrow && whole ? (e0 + 4 * q) * 4 : kBufMiss16,
+                                                                     0, 0);
+                u[4 * q] = (int32_t)x[0];
+                u[4 * q + 1] = (int32_t)x[1];
+                u[4 * q + 2] = (int32_t)x[2];
+                u[4 * q + 3] = (int32_t)x[3];
+            }
+            if (tail) {
 #pragma unroll
-            for (int j = 0; j < DEG; ++j)
-                lab[j] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rlab, j < d ? u[j] * 4 : kBufMiss, 0, 0);
+                for (int j = 0; j < L; ++j)
+                    if (j < d && (uint32_t)(e0 + (j & ~3) + 4) > m)
+                        u[j] = __builtin_amdgcn_raw_buffer_load_b32(radj, (e0 + j) * 4, 0, 0);
+            }
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                const uint32_t l =
+                    (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rlab, j < d ? u[j] * 4 : kBufMiss, 0, 0);
+                lab[j] = j < d ? l : EMPTY;
+            }
+            if constexpr (EW) {
+                const __amdgpu_buffer_rsrc_t rew = buf_rsrc(a.adjwgt, a.nr_adj);
+#pragma unroll
+                for (int q = 0; q < L / 4; ++q) {
+                    const bool inrow = 4 * q < d;
+                    const bool whole = (uint32_t)(e0 + 4 * q + 4) <= m;
+                    const auto x = __builtin_amdgcn_raw_buffer_load_b128(
+                        rew, inrow && whole ? (e0 + 4 * q) * 4 : kBufMiss16, 0, 0);
+                    w[4 * q] = x[0];
+                    w[4 * q + 1] = x[1];
+                    w[4 * q + 2] = x[2];
+                    w[4 * q + 3] = x[3];
+                }
+                if (tail) {
+#pragma unroll
+                    for (int j = 0; j < L; ++j)
+                        if (j < d && (uint32_t)(e0 + (j & ~3) + 4) > m)
+                            w[j] = __builtin_amdgcn_raw_buffer_load_b32(rew, (e0 + j) * 4, 0, 0);
+                }
+            }
         } else {
 #pragma unroll
-            for (int j = 0; j < DEG; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
+            for (int j = 0; j < L; ++j) u[j] = a.adjncy[e0 + (j < d ? j : d - 1)];
 #pragma unroll
-            for (int j = 0; j < DEG; ++j) lab[j] = (uint32_t)a.label[u[j]];
-        }
+            for (int j = 0; j < L; ++j) {
+                const uint32_t l = (uint32_t)a.label[u[j]];
+                lab[j] = j < d ? l : EMPTY;
+            }
+            if constexpr (EW) {
 #pragma unroll
-        for (int j = 0; j < DEG; ++j) w[j] = EW ? (uint32_t)a.adjwgt[e0 + (j < d ? j : d - 1)] : 1u;
-#pragma unroll
-        for (int j = 0; j < DEG; ++j) {
-            lab[j] = j < d ? lab[j] : EMPTY;
-            w[j] = j < d ? w[j] : 0u;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < DEG; ++j) {
-            lab[j] = EMPTY;
-            w[j] = 0;
+                for (int j = 0; j < L; ++j) w[j] = (uint32_t)a.adjwgt[e0 + (j < d ? j : d - 1)];
+            }
         }
     }
-#pragma unroll
-    for (int k = 1; k < DEG; ++k) {
-        bool dup = false;
-#pragma unroll
-        for (int q = 0; q < k; ++q) {
-            const bool hit = !dup && lab[k] != EMPTY && lab[q] == lab[k];
-            w[q] += hit ? w[k] : 0u;
-            dup = dup || hit;
+    // candidate weights: through a buffer in which EMPTY misses (no memory access),
+    // else a plain load redirected to the own label
+    auto wt_of = [&](uint32_t l) -> int64_t {
+        if constexpr (BUF) {
+            const auto x = __builtin_amdgcn_raw_buffer_load_b64(buf_rsrc(a.wt, a.nr_wt),
+                                                                l != EMPTY ? (int)(l * 8u) : kBufMiss, 0, 0);
+            return (int64_t)(((uint64_t)(uint32_t)x[1] << 32) | (uint32_t)x[0]);
         }
-        lab[k] = dup ? EMPTY : lab[k];
-    }
-    // weight (and cap / overload flag) of every candidate, one batch of loads
-    int64_t wk[DEG];
-#pragma unroll
-    for (int j = 0; j < DEG; ++j) wk[j] = a.wt[lab[j] != EMPTY ? lab[j] : own];
-    int64_t ck[DEG];
-#pragma unroll
-    for (int j = 0; j < DEG; ++j) ck[j] = CAPV ? a.cap_vec[lab[j] != EMPTY ? lab[j] : own] : nk.cap;
-    bool ov[DEG];
-#pragma unroll
-    for (int j = 0; j < DEG; ++j) ov[j] = BAL ? a.over[lab[j] != EMPTY ? lab[j] : own] != 0 : false;
-    Key3 fav{0, 0, 0}, adm{0, 0, 0};
+        return a.wt[l != EMPTY ? l : own];
+    };
+    auto cap_of = [&](uint32_t l) -> int64_t { return CAPV ? a.cap_vec[l] : nk.cap; };
+    auto over_of = [&](uint32_t l) -> bool { return BAL ? a.over[l] != 0 : false; };
+    Key3 fav, adm;
     uint32_t rown = 0;
-    if (a.fav) {  // clustering keeps the favoured cluster too (uniform branch)
-#pragma unroll
-        for (int j = 0; j < DEG; ++j) {
-            const bool is_own = lab[j] == own;
-            rown = is_own ? w[j] : rown;
-            const bool cand = lab[j] != EMPTY && !is_own;
-            const Key3 c{w[j], hash_step(nk.hp, lab[j] - nk.lo, 4), lab[j]};
-            if (cand && better(c, fav)) fav = c;
-            if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < DEG; ++j) {
-            const bool is_own = lab[j] == own;
-            rown = is_own ? w[j] : rown;
-            const bool cand = lab[j] != EMPTY && !is_own;
-            const Key3 c{w[j], hash_step(nk.hp, lab[j] - nk.lo, 4), lab[j]};
-            if (cand && wk[j] + cv <= ck[j] && !ov[j] && better(c, adm)) adm = c;
-        }
-    }
+    if (a.fav)  // clustering keeps the favoured cluster too (uniform branch)
+        choose_slots<N, L, EW, true>(lab, w, own, nk.hp, nk.lo, cv, wt_of, cap_of, over_of, fav, adm, rown);
+    else
+        choose_slots<N, L, EW, false>(lab, w, own, nk.hp, nk.lo, cv, wt_of, cap_of, over_of, fav, adm, rown);
     return write_result(a, v, own, fav, adm, rown, cv);
 }
 
-// A tier-0 segment lists its nodes of degree <= T0_NARROW first, so most
-// wavefronts take the half-width body as a whole (a wave-uniform branch).
+// Rounds after the first (and balancing) rate only the selected nodes of a
+// list: every tile of blockDim.x entries is compacted in LDS first, so the
+// selected nodes fill the leading wavefronts and the others have no work.
 template <bool EW, bool CAPV, bool BAL, bool BUF>
 __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
 {
+    __shared__ int32_t s_v[kBlock];
+    __shared__ uint32_t s_cnt[kBlock / 64];
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
+    const bool filter = BAL || a.active != nullptr;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = (int)(blockDim.x >> 6);
     int64_t edges = 0, nodes = 0, moves = 0;
-    for (int64_t i = (int64_t)xcd_block() * blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int32_t v = a.list[off + i];
-        const uint32_t own = (uint32_t)a.label[v];
-        if (BAL) {
-            if (!a.over[own]) continue;
-        } else if (a.active && a.active[v] != a.stamp) {
-            continue;
+    for (int64_t base = (int64_t)xcd_block() * blockDim.x; base < count; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = base + tid;
+        int32_t v = i < count ? a.list[off + i] : -1;
+        if (filter) {
+            const bool sel = v >= 0 && node_selected(a, v);
+            const uint64_t m = ballot64(sel);
+            if (lane == 0) s_cnt[wv] = (uint32_t)__popcll(m);
+            __syncthreads();
+            uint32_t pre = 0, tot = 0;
+            for (int q = 0; q < nw; ++q) {
+                const uint32_t c = s_cnt[q];
+                pre += q < wv ? c : 0u;
+                tot += c;
+            }
+            if (sel)
+                s_v[pre + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u))] =
+                    v;
+            __syncthreads();
+            v = (uint32_t)tid < tot ? s_v[tid] : -1;
+            __syncthreads();  // the tables are rewritten by the next tile
         }
-        const int32_t e0 = a.xadj[v];
-        const int32_t d = a.xadj[v + 1] - e0;
-        const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
-        const NodeKey nk = node_key(a, v);
-        if (ballot64(d > T0_NARROW)) moves += rate_lane_node<T0_DEG, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
-        else moves += rate_lane_node<T0_NARROW, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
-        edges += d;
-        nodes += 1;
+        if (!ballot64(v >= 0)) continue;  // uniform in the wavefront
+        uint32_t own = 0;
+        int32_t e0 = 0, d = 0;
+        int64_t cv = 0;
+        if (v >= 0) {
+            own = (uint32_t)a.label[v];
+            e0 = a.xadj[v];
+            d = a.xadj[v + 1] - e0;
+            cv = a.vwgt ? a.vwgt[v] : 1;
+        }
+        // register slots for the largest degree in the wavefront (every lane is active here)
+        const uint32_t dmax = wave_max_u32_dpp((uint32_t)d);
+        if (v >= 0) {
+            const NodeKey nk = node_key(a, v);
+            if (dmax <= 4) moves += rate_lane_node<4, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
+            else if (dmax <= 8) moves += rate_lane_node<8, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
+            else if (dmax <= 12) moves += rate_lane_node<12, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
+            else moves += rate_lane_node<T0_DEG, EW, CAPV, BAL, BUF>(a, v, own, e0, d, cv, nk);
+            edges += d;
+            nodes += 1;
+        }
     }
     flush_stats(a, nodes, edges, moves);
 }
@@ -1073,7 +1236,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
     if ((threadIdx.x & 63) == 0 && mine) atomicAdd(&bm, mine);
     __syncthreads();
     if (threadIdx.x == 0 && bm)
-        atomicAdd((unsigned long long*)&ctl[ms + (blockIdx.x & (kSpreadSlots - 1))], (unsigned long long)bm);
+        atomicAdd((unsigned long long*)&ctl[ms + (blockIdx.x & (kSpreadSlots - 1)) * kSpreadStride],
+                  (unsigned long long)bm);
 }
 
 struct SegBounds {
@@ -1902,11 +2066,13 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
     a.loff = st.loff;
     a.gcap = st.gcap;
     a.tag = st.tag;
-    const int64_t badj = 4 * g.m, blab = 4 * (int64_t)g.n;
-    if (!c.plain_loads && g.m > 0 && badj < (int64_t(1) << 31) && blab < (int64_t(1) << 31)) {
+    const int64_t badj = 4 * g.m, blab = 4 * (int64_t)g.n, bwt = 8 * (int64_t)st.nlab;
+    const int64_t lim = int64_t(1) << 31;
+    if (!c.plain_loads && g.m > 0 && st.nlab > 0 && badj < lim && blab < lim && bwt < lim) {
         a.bufok = 1;
         a.nr_adj = (uint32_t)badj;
         a.nr_lab = (uint32_t)blab;
+        a.nr_wt = (uint32_t)bwt;
     }
     if (b) {
         a.prop = b->prop.p;
@@ -1937,7 +2103,7 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
         a.seg = seg;
         // LP launches count their algorithmic bytes per class (tier 3 joins tier 2); the
         // balancer's rating launches are timed under the balance class and count no LP bytes
-        if (!a.over) a.bytes_ctr = bytes + kSpreadSlots * (t < 3 ? t : t == 3 ? KMP_PROF_RATE_T2 : KMP_PROF_RATE_HUB);
+        if (!a.over) a.bytes_ctr = bytes + kSpreadWords * (t < 3 ? t : t == 3 ? KMP_PROF_RATE_T2 : KMP_PROF_RATE_HUB);
         const int cls = a.over ? KMP_PROF_BALANCE
                                : t == 0 ? KMP_PROF_RATE_T0
                                : t == 1 ? KMP_PROF_RATE_T1
@@ -2233,7 +2399,7 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
     DBuf<int32_t> flist;
     if (!skip.empty()) {
         // batches: the lists without the skipped jobs' nodes
-        int32_t* ftab = reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kRounds * kSpreadSlots);
+        int32_t* ftab = reinterpret_cast<int32_t*>(b.ctl.p + CTL_MS + kSpreadWords);
         flist = DBuf<int32_t>(c, (size_t)n);
         std::vector<uint8_t> flag((size_t)st.njobs, 0);
         for (int32_t j : skip) flag[j] = 1;
@@ -2263,7 +2429,7 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
     };
     struct {
         int64_t ctl[CTL_N];
-        int64_t moved[kRounds][kSpreadSlots];
+        int64_t moved[kSpreadWords];
     } h;
     static_assert(sizeof(h) <= sizeof(int64_t) * kCtlWords, "control block layout");
     auto args_of = [&](int32_t r) {
@@ -2281,7 +2447,7 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
         for (int32_t s = 0; s < kSub; ++s) {
             launch_rate(c, a, sched, s, list, segtab, ub);
             launch_admit(c, ub, s, list, segtab, st, b);
-            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, (uint8_t)(r + 1), CTL_MS + r * kSpreadSlots,
+            launch_apply(c, ub, s, list, segtab, g, st, b, b.mflag.p, (uint8_t)(r + 1), CTL_MS + r,
                          next_of(r));
         }
         push_big(r);
@@ -2305,7 +2471,7 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
             if (r0 < r || r0 > last) throw Error(KMP_EHIP, "LP abort recorded for an unexpected round");
             const RateArgs a = args_of(r0);
             const uint8_t stamp = (uint8_t)(r0 + 1);
-            const int ms = CTL_MS + r0 * kSpreadSlots;
+            const int ms = CTL_MS + r0;
             ctl_set(c, b, CTL_ABORT, 0);
             subround_exact(c, g, sched, s0, list, segtab, ub, st, b, a, false, b.mflag.p, stamp, ms, next_of(r0));
             for (int32_t s = s0 + 1; s < kSub; ++s)
@@ -2318,7 +2484,7 @@ LPStats lp_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, const L
         bool stop = false;
         for (int32_t q = r; q <= done && !stop; ++q) {
             int64_t nm = 0;
-            for (int k = 0; k < kSpreadSlots; ++k) nm += h.moved[q][k];
+            for (int k = 0; k < kSpreadSlots; ++k) nm += h.moved[k * kSpreadStride + q];
             out.moves[q] = nm;
             out.rounds = q + 1;
             stop = nm == 0;
@@ -2372,7 +2538,7 @@ LPStats lp_async_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, c
         a.amode = st.tag == TAG_REF ? 2 : 1;
         a.label_w = st.label;
         a.mflag = mflag.p;
-        a.moved_ctr = ctl.p + CTL_MS + r * kSpreadSlots;
+        a.moved_ctr = ctl.p + CTL_MS + r;
         for (int32_t s = 0; s < kSub; ++s) {
             if (!serial) {
                 launch_rate(c, a, sched, s, sched.order.p, sched.segtab.p, sched.cnt);
@@ -2394,7 +2560,7 @@ LPStats lp_async_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, c
             KMP_LAUNCH_CHECK();
         }
     };
-    int64_t moved[kRounds][kSpreadSlots];
+    int64_t moved[kSpreadWords];
     // clustering enqueues every round before one read-back (a round after one
     // without moves rates nothing); refinement reads the count after each round
     const bool ahead = st.tag == TAG_CL;
@@ -2405,7 +2571,7 @@ LPStats lp_async_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, c
         bool stop = false;
         for (int32_t q = r; q <= last && !stop; ++q) {
             int64_t nm = 0;
-            for (int k = 0; k < kSpreadSlots; ++k) nm += moved[q][k];
+            for (int k = 0; k < kSpreadSlots; ++k) nm += moved[k * kSpreadStride + q];
             out.moves[q] = nm;
             out.rounds = q + 1;
             stop = nm == 0;
@@ -2483,10 +2649,10 @@ int64_t lp_subround(Ctx& c, const DGraph& g, int32_t level, int32_t round, int32
     a.stamp = 1;  // the caller's active flags are 0 / 1
     subround_exact(c, g, sched, s, sched.order.p, sched.segtab.p, sched.cnt, st, b, a, true, moved, 1, CTL_MS,
                    nullptr);
-    int64_t slots[kSpreadSlots];
+    int64_t slots[kSpreadWords];
     c.read(slots, b.ctl.p + CTL_MS, sizeof(slots));
     int64_t nm = 0;
-    for (int q = 0; q < kSpreadSlots; ++q) nm += slots[q];
+    for (int q = 0; q < kSpreadSlots; ++q) nm += slots[q * kSpreadStride];
     return nm;
 }
 

@@ -120,7 +120,7 @@ Ctx::~Ctx()
         for (auto& b : live_) dp.free_blocks[device_].emplace(b.second, b.first);
         for (auto& b : freed_) dp.free_blocks[device_].emplace(b.second, b.first);
         if (counters_) dp.free_blocks[device_].emplace((size_t)512, (void*)counters_);
-        if (spread_) dp.free_blocks[device_].emplace((size_t)SP_COUNT * kSpreadSlots * 8, (void*)spread_);
+        if (spread_) dp.free_blocks[device_].emplace((size_t)SP_COUNT * kSpreadWords * 8, (void*)spread_);
     }
     std::lock_guard<std::mutex> lk(g_pinned_mu);
     for (auto& c : pinned_chunks_) g_pinned_free.push_back(c);
@@ -361,12 +361,12 @@ void Ctx::zero_counters() { zero(counters(), 64 * sizeof(int64_t)); }
 int64_t* Ctx::spread(int idx)
 {
     if (!spread_ && arena_) {
-        const size_t bytes = (size_t)SP_COUNT * kSpreadSlots * sizeof(int64_t);
+        const size_t bytes = (size_t)SP_COUNT * kSpreadWords * sizeof(int64_t);
         spread_ = static_cast<int64_t*>(arena_take((bytes + 255) & ~(size_t)255));
         zero(spread_, bytes);
     }
     if (!spread_) {
-        const size_t bytes = (size_t)SP_COUNT * kSpreadSlots * sizeof(int64_t);
+        const size_t bytes = (size_t)SP_COUNT * kSpreadWords * sizeof(int64_t);
         size_t got = 0;
         void* p = nullptr;
         {
@@ -382,17 +382,17 @@ int64_t* Ctx::spread(int idx)
         spread_ = static_cast<int64_t*>(p);
         zero(spread_, bytes);
     }
-    return spread_ + (size_t)idx * kSpreadSlots;
+    return spread_ + (size_t)idx * kSpreadWords;
 }
 
-void Ctx::zero_spread(int idx) { zero(spread(idx), kSpreadSlots * sizeof(int64_t)); }
+void Ctx::zero_spread(int idx) { zero(spread(idx), kSpreadWords * sizeof(int64_t)); }
 
 int64_t Ctx::read_spread(int idx)
 {
-    int64_t v[kSpreadSlots];
+    int64_t v[kSpreadWords];
     read(v, spread(idx), sizeof(v));
     int64_t s = 0;
-    for (int i = 0; i < kSpreadSlots; ++i) s += v[i];
+    for (int i = 0; i < kSpreadWords; ++i) s += v[i];
     return s;
 }
 
@@ -470,10 +470,10 @@ void Ctx::prof_collect(int64_t* launches, double* ms, int64_t* bytes)
         ms[r.cls] += t;
     }
     // the classes' counters are adjacent: one read-back for all of them
-    std::vector<int64_t> v((size_t)KMP_PROF_CLASSES * kSpreadSlots);
+    std::vector<int64_t> v((size_t)KMP_PROF_CLASSES * kSpreadWords);
     read(v.data(), spread(SP_BYTES), v.size() * sizeof(int64_t));
     for (int i = 0; i < KMP_PROF_CLASSES; ++i)
-        for (int j = 0; j < kSpreadSlots; ++j) bytes[i] += v[(size_t)i * kSpreadSlots + j];
+        for (int j = 0; j < kSpreadWords; ++j) bytes[i] += v[(size_t)i * kSpreadWords + j];
 }
 
 int bits_for(uint64_t max_value)
