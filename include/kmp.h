@@ -469,8 +469,9 @@ int kmp_balance_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vw
 
 /*
  * kmp_lp_refine: k-way LP refinement (paper Sec. 5.3 "Local Improvement")
- * of part[n] over nb blocks, block weights wt[nb] (int64, updated), strict
- * caps cap[nb] (int64).  moves[5] (host, may be NULL).  Returns rounds run.
+ * of part[n] over nb blocks, block weights wt[nb] (int64, updated; each the
+ * node weight of its block, below 2^31), strict caps cap[nb] (int64).
+ * moves[5] (host, may be NULL).  Returns rounds run.
  */
 int kmp_lp_refine(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
                   int32_t n, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,
@@ -481,8 +482,10 @@ int kmp_lp_refine(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwg
  * state: nodes of sub-round class s that are active (active[n] bytes, NULL =
  * all) are rated against the current labels; `tag` selects the tie-break
  * family (2 = clustering, 3 = refinement); cap is cap_vec[nlab] if non-NULL
- * else cap_scalar.  label[n], wt[nlab] (int64) updated; fav[n] (may be NULL)
- * written for rated nodes; moved[n] bytes set for moved nodes.
+ * else cap_scalar.  label[n], wt[nlab] (int64) updated; wt[L] must be the
+ * weight of label L (the node weights of its members, so below 2^31);
+ * fav[n] (may be NULL) written for rated nodes; moved[n] bytes set for moved
+ * nodes.
  * Returns the number of moves or an error.
  */
 int64_t kmp_lp_subround(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,

@@ -76,7 +76,9 @@ struct GGGJob {
     uint32_t hpre;     // H prefix over (seed; T_GGG, level) of the block's job
     uint32_t hpre_bfs; // the same over (seed; T_BFS, level) and (seed; T_RND, level)
     uint32_t hpre_rnd;
-    int64_t scratch;   // byte offset into the global scratch (global variant)
+    int64_t scratch;   // byte offset into the global scratch (global and hybrid variants)
+    int64_t sstride;   // the scratch of one workgroup (pool families in parallel: one each)
+    int64_t soff;      // pool families in parallel: offset of the job's sides, one nverts run per family
     int64_t lk;        // L_k of the block's job
     int64_t cap0, cap1;  // bounds of the two sides (f_j L_k, or the adaptive imbalance's)
 };
@@ -94,8 +96,15 @@ struct GGGArgs {
     uint8_t* side;      // [n]
     char* scratch;      // global variant
     int32_t fm_passes;  // 2-way FM passes after each growth (0: none)
-    int32_t pool;       // 1: BFS and random growths after the GGG ones
+    int32_t pool;       // 1: BFS and random growths besides the GGG ones
     const uint8_t* given;  // non-NULL: no growth; FM refines these sides (by vertex) into `side`
+    // set by launch_ggg_jobs: algs = 3 runs the pool's three families side by side, one
+    // workgroup each (workgroup 3 j + family); every workgroup writes its best run's
+    // sides (by local id) to side_alg and its (overload, cut) to res, and k_ggg_pick
+    // keeps the first strictly best family in the order GGG, BFS, random
+    int32_t algs;
+    uint8_t* side_alg;
+    int64_t* res;  // [job][family][2]
 };
 
 // A growth keeps one 64-bit key per node, so that finding the next node is one
@@ -457,19 +466,23 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     __shared__ int32_t s_carry;
     __shared__ int32_t s_nheavy;
 
-    const GGGJob job = a.jobs[blockIdx.x];
+    const int32_t jobi = (int32_t)(blockIdx.x / (uint32_t)a.algs);
+    const int alg_first = (int)(blockIdx.x % (uint32_t)a.algs);  // 0 unless the families run side by side
+    const GGGJob job = a.jobs[jobi];
     const int32_t nv = job.nverts;
     const int32_t nvp = (int32_t)ggg_pad(nv);
     const int32_t b = job.b;
     const uint32_t* vlist = a.verts + a.bstart[b];
-    char* base = LDS ? lds_raw : a.scratch + job.scratch;
+    // this workgroup's part of the global scratch (global and hybrid layouts)
+    char* const wscratch = a.scratch ? a.scratch + job.scratch + alg_first * job.sstride : nullptr;
+    char* base = LDS ? lds_raw : wscratch;
     // key[R][nvp]; ed[e] = (local neighbour, edge weight); nd[i] = (row start, node weight), nd[nv].x = entries
     uint64_t* key_all = reinterpret_cast<uint64_t*>(base);
     int2* ed = reinterpret_cast<int2*>(key_all + (int64_t)kSeeds * nvp);
     int2* nd = ed + job.dsum;
     if (MODE == GGG_HYBRID) {
         nd = reinterpret_cast<int2*>(key_all + (int64_t)kSeeds * nvp);
-        ed = reinterpret_cast<int2*>(a.scratch + job.scratch);
+        ed = reinterpret_cast<int2*>(wscratch);
     }
     int32_t* sw_all = reinterpret_cast<int32_t*>(nd + nv + 1);  // FM sides, R x padded nv
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -660,9 +673,15 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     const int64_t cap0 = job.cap0, cap1 = job.cap1;
     const int j = wv;
     // phases: the R GGG growths, then (pool) R BFS and R random growths; a phase's best run
-    // replaces the kept one only if it is strictly better, so the first of equal runs is kept
-    const int nalg = a.pool ? 3 : 1;
-    for (int alg = 0; alg < nalg; ++alg) {
+    // replaces the kept one only if it is strictly better, so the first of equal runs is kept.
+    // With the families side by side, this workgroup runs its own family only.
+    const int alg_end = a.algs > 1 ? alg_first + 1 : (a.pool ? 3 : 1);
+    uint8_t* const out_sides = a.algs > 1 ? a.side_alg + job.soff + (int64_t)alg_first * nv : nullptr;
+    auto put_side = [&](int32_t i, uint8_t sd) {
+        if (out_sides) out_sides[i] = sd;
+        else a.side[vlist[i]] = sd;
+    };
+    for (int alg = alg_first; alg < alg_end; ++alg) {
         const uint32_t hpre = alg == ALG_GGG ? job.hpre : (alg == ALG_BFS ? job.hpre_bfs : job.hpre_rnd);
         const uint32_t hj =
             hash_step(hash_step(hash_step(hpre, (uint32_t)job.first, 3), (uint32_t)f, 4), (uint32_t)j, 5);
@@ -696,7 +715,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
                 else better = s_cut[q] < s_cut[bj];
                 if (better) bj = q;
             }
-            bool take = alg == 0;
+            bool take = alg == alg_first;
             if (!take) {
                 const bool fq = s_over[bj] > 0, fb = s_keep_over > 0;
                 if (fq != fb) take = !fq;
@@ -714,17 +733,49 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
         if (s_take) {
             if (a.fm_passes > 0) {
                 const int32_t* sb = sw_all + (int64_t)s_best * nvp;
-                for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = sb[i] < 0 ? 1 : 0;
+                for (int32_t i = tid; i < nv; i += GGG_THREADS) put_side(i, sb[i] < 0 ? 1 : 0);
             } else if (use32) {
                 const uint32_t* kb = reinterpret_cast<const uint32_t*>(key_all) + (int64_t)s_best * nvp;
-                for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
+                for (int32_t i = tid; i < nv; i += GGG_THREADS) put_side(i, kb[i] == 0 ? 0 : 1);
             } else {
                 const uint64_t* kb = key_all + (int64_t)s_best * nvp;
-                for (int32_t i = tid; i < nv; i += GGG_THREADS) a.side[vlist[i]] = kb[i] == 0 ? 0 : 1;
+                for (int32_t i = tid; i < nv; i += GGG_THREADS) put_side(i, kb[i] == 0 ? 0 : 1);
             }
         }
         __syncthreads();  // the next phase rewrites the keys
     }
+    if (a.algs > 1 && tid == 0) {
+        a.res[((int64_t)jobi * a.algs + alg_first) * 2] = s_keep_over;
+        a.res[((int64_t)jobi * a.algs + alg_first) * 2 + 1] = s_keep_cut;
+    }
+}
+
+// The pool's families run side by side: per job, the family kept is GGG unless
+// BFS is strictly better (feasible first, then less overload, then a smaller
+// cut), and random replaces the kept one only if strictly better, the order in
+// which one workgroup would have run them; its sides go to the vertices.
+__global__ __launch_bounds__(kBlock) void k_ggg_pick(const GGGJob* __restrict__ jobs, const int64_t* __restrict__ res,
+                                                     const uint32_t* __restrict__ verts,
+                                                     const int32_t* __restrict__ bstart,
+                                                     const uint8_t* __restrict__ side_alg, uint8_t* __restrict__ side)
+{
+    const GGGJob job = jobs[blockIdx.x];
+    const int64_t* r = res + (int64_t)blockIdx.x * 6;
+    int w = 0;
+    int64_t ko = r[0], kc = r[1];
+    for (int q = 1; q < 3; ++q) {
+        const int64_t o = r[2 * q], cu = r[2 * q + 1];
+        const bool fq = o > 0, fb = ko > 0;
+        const bool better = fq != fb ? !fq : (o != ko ? o < ko : cu < kc);
+        if (better) {
+            w = q;
+            ko = o;
+            kc = cu;
+        }
+    }
+    const uint32_t* vlist = verts + bstart[job.b];
+    const uint8_t* sd = side_alg + job.soff + (int64_t)w * job.nverts;
+    for (int32_t i = threadIdx.x; i < job.nverts; i += blockDim.x) side[vlist[i]] = sd[i];
 }
 
 __global__ void k_relabel(int32_t* __restrict__ part, const uint8_t* __restrict__ side,
@@ -945,12 +996,17 @@ void launch_ggg_jobs(Ctx& c, GGGArgs a, const std::vector<GGGJob>& jobs_in)
     constexpr int kLdsClasses = 4;
     const int64_t lds_class_max[kLdsClasses] = {40 << 10, 53 << 10, 80 << 10, kLdsBudget};
     std::vector<GGGJob> lds_jobs[kLdsClasses], hyb_jobs, glob_jobs;
-    int64_t lds_max[kLdsClasses] = {0, 0, 0, 0}, hyb_max = 0, scratch_total = 0;
+    int64_t lds_max[kLdsClasses] = {0, 0, 0, 0}, hyb_max = 0, scratch_total = 0, sides_total = 0;
     const bool fm = a.fm_passes > 0;
+    // the pool's three families side by side: one workgroup each, with scratch and sides of its own
+    a.algs = a.pool && !a.given ? 3 : 1;
     for (GGGJob jb : jobs_in) {
         const int64_t bytes = ggg_bytes(jb.nverts, jb.dsum, fm);
         const int64_t hbytes = ggg_hybrid_lds(jb.nverts, fm);
         jb.scratch = 0;
+        jb.sstride = 0;
+        jb.soff = sides_total;
+        if (a.algs > 1) sides_total += ((int64_t)a.algs * jb.nverts + 15) & ~(int64_t)15;
         if (bytes <= kLdsBudget) {
             int q = 0;
             while (bytes > lds_class_max[q]) ++q;
@@ -958,12 +1014,14 @@ void launch_ggg_jobs(Ctx& c, GGGArgs a, const std::vector<GGGJob>& jobs_in)
             lds_max[q] = std::max(lds_max[q], bytes);
         } else if (hbytes <= kLdsBudget) {
             jb.scratch = scratch_total;
-            scratch_total += ((int64_t)jb.dsum * 8 + 255) & ~(int64_t)255;
+            jb.sstride = ((int64_t)jb.dsum * 8 + 255) & ~(int64_t)255;
+            scratch_total += a.algs * jb.sstride;
             hyb_jobs.push_back(jb);
             hyb_max = std::max(hyb_max, hbytes);
         } else {
             jb.scratch = scratch_total;
-            scratch_total += (bytes + 255) & ~(int64_t)255;
+            jb.sstride = (bytes + 255) & ~(int64_t)255;
+            scratch_total += a.algs * jb.sstride;
             glob_jobs.push_back(jb);
         }
     }
@@ -975,7 +1033,7 @@ void launch_ggg_jobs(Ctx& c, GGGArgs a, const std::vector<GGGJob>& jobs_in)
             mx = std::max(mx, lds_max[q]);
         }
         const int64_t resident = 256 * std::max<int64_t>(1, std::min<int64_t>(4, (160 << 10) / std::max<int64_t>(mx, 1)));
-        if ((int64_t)nl <= resident)
+        if ((int64_t)nl * a.algs <= resident)
             for (int q = 0; q + 1 < kLdsClasses; ++q) {
                 lds_jobs[kLdsClasses - 1].insert(lds_jobs[kLdsClasses - 1].end(), lds_jobs[q].begin(),
                                                  lds_jobs[q].end());
@@ -986,6 +1044,13 @@ void launch_ggg_jobs(Ctx& c, GGGArgs a, const std::vector<GGGJob>& jobs_in)
     DBuf<char> scratch;
     if (scratch_total > 0) scratch = DBuf<char>(c, (size_t)scratch_total);
     a.scratch = scratch.p;
+    DBuf<uint8_t> side_alg;
+    DBuf<int64_t> res;
+    if (a.algs > 1) {
+        side_alg = DBuf<uint8_t>(c, (size_t)std::max<int64_t>(sides_total, 16));
+        res = DBuf<int64_t>(c, jobs_in.size() * 6);
+    }
+    a.side_alg = side_alg.p;
     // every job list in one upload
     std::vector<GGGJob> all;
     all.reserve(jobs_in.size());
@@ -998,26 +1063,36 @@ void launch_ggg_jobs(Ctx& c, GGGArgs a, const std::vector<GGGJob>& jobs_in)
     for (int q = 0; q < kLdsClasses; ++q) {
         if (lds_jobs[q].empty()) continue;
         a.jobs = jobs.p + at;
+        a.res = res.p ? res.p + at * 6 : nullptr;
         allow_lds((const void*)k_ggg<GGG_LDS>, (int)kLdsBudget);  // beyond the 64 KiB default
         ProfScope ps(c, KMP_PROF_GGG);
-        hipLaunchKernelGGL(k_ggg<GGG_LDS>, dim3((unsigned)lds_jobs[q].size()), dim3(GGG_THREADS), (size_t)lds_max[q],
-                           c.stream, a);
+        hipLaunchKernelGGL(k_ggg<GGG_LDS>, dim3((unsigned)(lds_jobs[q].size() * a.algs)), dim3(GGG_THREADS),
+                           (size_t)lds_max[q], c.stream, a);
         KMP_LAUNCH_CHECK();
         at += lds_jobs[q].size();
     }
     if (!hyb_jobs.empty()) {
         a.jobs = jobs.p + at;
+        a.res = res.p ? res.p + at * 6 : nullptr;
         allow_lds((const void*)k_ggg<GGG_HYBRID>, (int)kLdsBudget);
         ProfScope ps(c, KMP_PROF_GGG);
-        hipLaunchKernelGGL(k_ggg<GGG_HYBRID>, dim3((unsigned)hyb_jobs.size()), dim3(GGG_THREADS), (size_t)hyb_max,
-                           c.stream, a);
+        hipLaunchKernelGGL(k_ggg<GGG_HYBRID>, dim3((unsigned)(hyb_jobs.size() * a.algs)), dim3(GGG_THREADS),
+                           (size_t)hyb_max, c.stream, a);
         KMP_LAUNCH_CHECK();
         at += hyb_jobs.size();
     }
     if (!glob_jobs.empty()) {
         a.jobs = jobs.p + at;
+        a.res = res.p ? res.p + at * 6 : nullptr;
         ProfScope ps(c, KMP_PROF_GGG);
-        hipLaunchKernelGGL(k_ggg<GGG_GLOBAL>, dim3((unsigned)glob_jobs.size()), dim3(GGG_THREADS), 0, c.stream, a);
+        hipLaunchKernelGGL(k_ggg<GGG_GLOBAL>, dim3((unsigned)(glob_jobs.size() * a.algs)), dim3(GGG_THREADS), 0,
+                           c.stream, a);
+        KMP_LAUNCH_CHECK();
+    }
+    if (a.algs > 1) {
+        ProfScope ps(c, KMP_PROF_GGG);
+        hipLaunchKernelGGL(k_ggg_pick, dim3((unsigned)all.size()), dim3(kBlock), 0, c.stream, jobs.p, res.p, a.verts,
+                           a.bstart, side_alg.p, a.side);
         KMP_LAUNCH_CHECK();
     }
 }

@@ -1212,8 +1212,11 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
         if (a == 1) {
             const int64_t c = cw;
             label[v] = K;
-            atomicAdd((unsigned long long*)&wt[K], (unsigned long long)c);
-            atomicAdd((unsigned long long*)&wt[old], (unsigned long long)(-c));
+            // 32-bit adds on the low words: a label's weight stays within [0, c(V)]
+            // at every point of the sub-round (its leavers are among its members),
+            // and c(V) < 2^31 is checked at the boundary, so the high word is 0
+            atomicAdd(reinterpret_cast<uint32_t*>(&wt[K]), (uint32_t)c);
+            atomicAdd(reinterpret_cast<uint32_t*>(&wt[old]), (uint32_t)(-c));
             mflag[v] = stamp;
             ++mine;
             // next round's active set: the neighbours of a moved node of degree
