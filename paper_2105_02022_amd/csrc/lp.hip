@@ -1383,60 +1383,29 @@ __device__ inline void rate_lane_local(const RateArgs& a, int32_t lo, uint32_t o
                                        Key3& fav, Key3& adm, uint32_t& rown)
 {
     uint32_t lab[DEG], w[DEG];
+#pragma unroll
+    for (int j = 0; j < DEG; ++j) {
+        lab[j] = EMPTY;
+        w[j] = 1u;
+    }
     if (d > 0) {
         int32_t u[DEG];
 #pragma unroll
         for (int j = 0; j < DEG; ++j) u[j] = nbr(e0 + (j < d ? j : d - 1));
+        if constexpr (EW) {
 #pragma unroll
-        for (int j = 0; j < DEG; ++j) w[j] = ewt(e0 + (j < d ? j : d - 1));
+            for (int j = 0; j < DEG; ++j) w[j] = ewt(e0 + (j < d ? j : d - 1));
+        }
 #pragma unroll
         for (int j = 0; j < DEG; ++j) lab[j] = j < d ? (uint32_t)s_lab[u[j]] : EMPTY;
-#pragma unroll
-        for (int j = 0; j < DEG; ++j) w[j] = j < d ? w[j] : 0u;
-    } else {
-#pragma unroll
-        for (int j = 0; j < DEG; ++j) {
-            lab[j] = EMPTY;
-            w[j] = 0;
-        }
     }
-#pragma unroll
-    for (int k = 1; k < DEG; ++k) {
-        bool dup = false;
-#pragma unroll
-        for (int q = 0; q < k; ++q) {
-            const bool hit = !dup && lab[k] != EMPTY && lab[q] == lab[k];
-            w[q] += hit ? w[k] : 0u;
-            dup = dup || hit;
-        }
-        lab[k] = dup ? EMPTY : lab[k];
-    }
-    if (a.fav) {  // clustering keeps the favoured cluster too (uniform branch)
-#pragma unroll
-        for (int j = 0; j < DEG; ++j) {
-            const bool is_own = lab[j] == own;
-            rown = is_own ? w[j] : rown;
-            const bool cand = lab[j] != EMPTY && !is_own;
-            const uint32_t l = cand ? lab[j] : own;
-            const int64_t wk = s_wt[l];
-            const int64_t ck = CAPV ? a.cap_vec[lo + l] : nk.cap;
-            const Key3 c{w[j], hash_step(nk.hp, lab[j], 4), lab[j]};
-            if (cand && better(c, fav)) fav = c;
-            if (cand && wk + cv <= ck && better(c, adm)) adm = c;
-        }
-    } else {
-#pragma unroll
-        for (int j = 0; j < DEG; ++j) {
-            const bool is_own = lab[j] == own;
-            rown = is_own ? w[j] : rown;
-            const bool cand = lab[j] != EMPTY && !is_own;
-            const uint32_t l = cand ? lab[j] : own;
-            const int64_t wk = s_wt[l];
-            const int64_t ck = CAPV ? a.cap_vec[lo + l] : nk.cap;
-            const Key3 c{w[j], hash_step(nk.hp, lab[j], 4), lab[j]};
-            if (cand && wk + cv <= ck && better(c, adm)) adm = c;
-        }
-    }
+    auto wt_of = [&](uint32_t l) -> int64_t { return l != EMPTY ? s_wt[l] : 0; };
+    auto cap_of = [&](uint32_t l) -> int64_t { return CAPV ? a.cap_vec[lo + l] : nk.cap; };
+    auto over_of = [](uint32_t) -> bool { return false; };
+    if (a.fav)  // clustering keeps the favoured cluster too (uniform branch)
+        choose_slots<DEG, DEG, EW, true>(lab, w, own, nk.hp, 0u, cv, wt_of, cap_of, over_of, fav, adm, rown);
+    else
+        choose_slots<DEG, DEG, EW, false>(lab, w, own, nk.hp, 0u, cv, wt_of, cap_of, over_of, fav, adm, rown);
 }
 
 // LCSR: the job's CSR is copied to LDS first (row starts relative to the job's
