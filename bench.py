@@ -234,8 +234,13 @@ CONTRACT_CLASSES = ["contract_rows", "contract"]
 BYTE_CLASSES = ["rate_t0", "rate_t1", "rate_t2", "rate_hub", "lp_small", "contract_rows"]
 
 # profiling class -> kernel family, where every launch of the class is a launch of that family
-KERNEL_OF_CLASS = {"rate_t0": "k_rate_lane", "rate_hub": "k_rate_hub", "lp_small": "k_lp_small",
-                   "contract_rows": "k_contract_rows"}
+KERNEL_OF_CLASS = {"rate_t0": "k_rate_lane", "rate_hub": ["k_hub_plan", "k_hub_split", "k_hub_agg", "k_hub_final"],
+                   "lp_small": "k_lp_small", "contract_rows": "k_contract_rows"}
+
+
+def kernel_name(cls):
+    k = KERNEL_OF_CLASS.get(cls, cls)
+    return "+".join(k) if isinstance(k, list) else k
 
 
 def traffic_from_profiles(family, workload="rgg20"):
@@ -250,10 +255,15 @@ def traffic_from_profiles(family, workload="rgg20"):
     if not m:
         return None
     d = json.loads(m.group(1))
-    e = d.get("kernels", {}).get(family)
-    if not e or d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash():
         return None
-    return e["hbm_bytes_per_launch"]
+    # a class of several kernels (the hub tier's four launches per sub-round): bytes over all their
+    # dispatches per dispatch
+    fams = family if isinstance(family, list) else [family]
+    es = [d.get("kernels", {}).get(f) for f in fams]
+    if any(not e for e in es):
+        return None
+    return round(sum(e["hbm_bytes_per_launch"] * e["dispatches"] for e in es) / sum(e["dispatches"] for e in es))
 
 
 def phase_rates(st_all):
@@ -280,7 +290,7 @@ def roofline_of(kmp, stats, dom, st_all, workload):
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic_from_profiles(KERNEL_OF_CLASS.get(dom), workload),
-            "kernel": KERNEL_OF_CLASS.get(dom, dom), "class": dom,
+            "kernel": kernel_name(dom), "class": dom,
             "avg_launch_us": round(avg_ms * 1e3, 2), "launches_per_step": ln / len(stats),
             "algorithmic_bytes_per_launch": round(bytes_per_launch),
             "class_ms_per_step": {c: round(st_all["prof"][c]["ms"], 3) for c in classes

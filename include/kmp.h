@@ -344,7 +344,10 @@ typedef struct kmp_tuning {
     int32_t tier1_deg;      /* tier0_deg .. 64, default 64      */
     int32_t tier2_deg;      /* tier1_deg .. 512, default 512    */
     int32_t tier3_deg;      /* tier2_deg .. 4096, default 4096  */
-    int32_t reserved[3];    /* 0 */
+    int32_t hub_lds_slots;  /* slots of the LDS table that sums a label partition of a hub (degree above
+                               tier3_deg): a power of two 64 .. 8192; 0 = the default 4096.  A partition
+                               with more distinct labels takes a global table instead. */
+    int32_t reserved[2];    /* 0 */
 } kmp_tuning;
 
 /* Set the process-wide tuning (NULL: the defaults).  KMP_EINVAL, and no

@@ -74,7 +74,8 @@ class KmpServerStats(ctypes.Structure):
 
 class KmpTuning(ctypes.Structure):
     _fields_ = [("small_level_n", ctypes.c_int32), ("tier0_deg", ctypes.c_int32), ("tier1_deg", ctypes.c_int32),
-                ("tier2_deg", ctypes.c_int32), ("tier3_deg", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("tier2_deg", ctypes.c_int32), ("tier3_deg", ctypes.c_int32), ("hub_lds_slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class KmpAutotuneReport(ctypes.Structure):
@@ -82,7 +83,7 @@ class KmpAutotuneReport(ctypes.Structure):
                 ("ms_best", ctypes.c_double)]
 
 
-TUNING_FIELDS = ("small_level_n", "tier0_deg", "tier1_deg", "tier2_deg", "tier3_deg")
+TUNING_FIELDS = ("small_level_n", "tier0_deg", "tier1_deg", "tier2_deg", "tier3_deg", "hub_lds_slots")
 
 
 SIGNATURES = {
@@ -199,12 +200,13 @@ def kmp_get_tuning() -> Dict:
 
 
 def kmp_set_tuning(tuning: Optional[Dict] = None) -> int:
-    """Set the process-wide tuning from a dict with the TUNING_FIELDS (None: the defaults)."""
+    """Set the process-wide tuning from a dict with the TUNING_FIELDS (None: the defaults; a missing
+    hub_lds_slots: its default)."""
     if tuning is None:
         return library().kmp_set_tuning(None)
     t = KmpTuning()
     for f in TUNING_FIELDS:
-        setattr(t, f, int(tuning[f]))
+        setattr(t, f, int(tuning.get(f, 0) if f == "hub_lds_slots" else tuning[f]))
     return library().kmp_set_tuning(ctypes.byref(t))
 
 

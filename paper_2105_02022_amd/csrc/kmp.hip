@@ -1099,6 +1099,12 @@ int64_t autotune_impl(const kmp_graph_desc& d, int32_t reps, hipStream_t stream,
                 t.cut[i] = v;
                 consider(t);
             }
+        for (int32_t v : {2048, 8192}) {  // the hub tier's LDS tables (no effect without hubs)
+            if (v == cur.hub_ts) continue;
+            Tuning t = cur;
+            t.hub_ts = v;
+            consider(t);
+        }
         tuning_set(cur);
         if (report) {
             report->configs = configs;
@@ -1117,6 +1123,7 @@ int64_t autotune_impl(const kmp_graph_desc& d, int32_t reps, hipStream_t stream,
         chosen->tier1_deg = cur.cut[1];
         chosen->tier2_deg = cur.cut[2];
         chosen->tier3_deg = cur.cut[3];
+        chosen->hub_lds_slots = cur.hub_ts;
     }
     return KMP_OK;
 }
@@ -1198,6 +1205,7 @@ int kmp_set_tuning(const kmp_tuning* t)
         u.cut[1] = t->tier1_deg;
         u.cut[2] = t->tier2_deg;
         u.cut[3] = t->tier3_deg;
+        u.hub_ts = t->hub_lds_slots ? t->hub_lds_slots : 4096;
         if (!tuning_valid(u)) return KMP_EINVAL;
     }
     tuning_set(u);
@@ -1214,6 +1222,7 @@ int kmp_get_tuning(kmp_tuning* t)
     t->tier1_deg = u.cut[1];
     t->tier2_deg = u.cut[2];
     t->tier3_deg = u.cut[3];
+    t->hub_lds_slots = u.hub_ts;
     return KMP_OK;
 }
 

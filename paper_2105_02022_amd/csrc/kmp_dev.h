@@ -308,6 +308,7 @@ __device__ inline void job_add(int64_t* out, int32_t j, int64_t x)
 struct Tuning {
     int32_t small_level_n = 8192;  // one-workgroup LP up to this many nodes (-1 never)
     int32_t cut[4] = {16, 64, 512, 4096};  // rating tiers: largest degree of tiers 0..3
+    int32_t hub_ts = 4096;                 // LDS table slots of a hub's label partition
 };
 bool tuning_valid(const Tuning& t);
 Tuning tuning_get();

@@ -122,19 +122,53 @@ __global__ __launch_bounds__(kBlock) void k_sched_keys(const int32_t* __restrict
     if (threadIdx.x <= kSegs && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
 
+// Hub sizing (the hub tier is described at k_hub_plan).
+constexpr int kHubTS = 8192;        // slots of the LDS table of a partition, at most (kmp_tuning)
+constexpr int kHubRun = 4096;       // entries of a run (k_hub_split)
+constexpr int kHubPartAvg = 1024;   // entries per label partition, on average
+constexpr int kHubMaxPart = 1024;   // label partitions of a hub, at most
+constexpr int kHubPart = 8;
+constexpr uint64_t kEmptySlot = 0xFFFFFFFF00000000ull;
+
+__host__ __device__ inline int64_t hub_runs(int64_t d) { return (d + kHubRun - 1) / kHubRun; }
+
+__host__ __device__ inline int32_t hub_parts(int64_t d)
+{
+    const int64_t p = (d + kHubPartAvg - 1) / kHubPartAvg;
+    return (int32_t)(p < 1 ? 1 : p > kHubMaxPart ? kHubMaxPart : p);
+}
+
+__host__ __device__ inline int64_t hub_region(int64_t d)
+{
+    const int64_t words = hub_runs(d) * (hub_parts(d) + 1) + hub_parts(d);  // int32 words after the slots
+    return 5 * d + (words + 1) / 2;
+}
+
+// Region size of every hub (8-byte slots).
 __global__ void k_hub_slots(const int32_t* __restrict__ xadj, const int32_t* __restrict__ hubs, int32_t nh,
                             int64_t* __restrict__ slots)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nh) return;
-    int32_t v = hubs[i];
-    int64_t d = xadj[v + 1] - xadj[v];
-    int64_t s = 1;
-    while (s < 2 * d) s <<= 1;
-    slots[i] = s;
+    const int32_t v = hubs[i];
+    slots[i] = hub_region(xadj[v + 1] - xadj[v]);
 }
 
-// table offset of every hub, indexed by node id (lists of later rounds are compacted)
+// The partition totals of every hub start at zero (the other parts of a region
+// are written before they are read).
+__global__ void k_hub_zero(const int32_t* __restrict__ xadj, const int32_t* __restrict__ hubs, int32_t nh,
+                           const int64_t* __restrict__ off_by_node, uint64_t* __restrict__ tab)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nh) return;
+    const int32_t v = hubs[i];
+    const int64_t d = xadj[v + 1] - xadj[v];
+    const int32_t P = hub_parts(d);
+    uint32_t* ptot = reinterpret_cast<uint32_t*>(tab + off_by_node[v] + 5 * d) + hub_runs(d) * (P + 1);
+    for (int32_t q = 0; q < P; ++q) ptot[q] = 0;
+}
+
+// region offset of every hub, indexed by node id (lists of later rounds are compacted)
 __global__ void k_hub_scatter(const int32_t* __restrict__ hubs, const int64_t* __restrict__ slots,
                               const int64_t* __restrict__ incl, int32_t nh, int64_t* __restrict__ off_by_node)
 {
@@ -253,10 +287,12 @@ struct RateArgs {
     const int32_t* segtab;  // [kSegs offsets][kSegs counts]
     int seg;
     // hubs
-    uint64_t* hub_tab;       // hash tables, one slot = label << 32 | rating; kEmptySlot when free
-    const int64_t* hub_off;  // by node id: first slot of the hub's table
-    int32_t* hub_plan;       // [count + 1]: first chunk of each hub of the launch's segment, then the total
-    uint32_t* hub_part;      // per chunk: the chunk's best keys and own rating (kHubPart words)
+    uint64_t* hub_tab;       // per hub a region of hub_region(d) 8-byte slots (layout at k_hub_split)
+    const int64_t* hub_off;  // by node id: first slot of the hub's region
+    int32_t* hub_plan;       // [count + 1]: first run of each hub of the launch's segment, then the total
+    int32_t* hub_pplan;      // [count + 1]: the same for the hubs' label partitions
+    int32_t hub_ts;          // slots of a partition's LDS table (a power of two, at most kHubTS)
+    uint32_t* hub_part;      // per label partition: its best keys and own rating (kHubPart words)
     // balance mode (over != NULL): rate the nodes of overloaded blocks only,
     // targets must be non-overloaded; write best target / gain
     const uint8_t* over;
@@ -669,6 +705,23 @@ __global__ __launch_bounds__(kBlock) void k_rate_lane(RateArgs a)
     flush_stats(a, nodes, edges, moves);
 }
 
+// As lds_insert, but every slot is probed at most once: false if the table is
+// full of other labels (the entry is then not inserted).
+__device__ inline bool lds_try_insert(uint32_t* keys, uint32_t* vals, int bits, uint32_t K, uint32_t w)
+{
+    const uint32_t mask = (1u << bits) - 1u;
+    uint32_t h = slot_of(K, bits);
+    for (uint32_t t = 0; t <= mask; ++t) {
+        const uint32_t old = atomicCAS(&keys[h], EMPTY, K);
+        if (old == EMPTY || old == K) {
+            atomicAdd(&vals[h], w);
+            return true;
+        }
+        h = (h + 1) & mask;
+    }
+    return false;
+}
+
 __device__ inline void lds_insert(uint32_t* keys, uint32_t* vals, int bits, uint32_t K, uint32_t w)
 {
     const uint32_t mask = (1u << bits) - 1u;
@@ -773,68 +826,95 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
     flush_stats(a, nodes, edges, moves);
 }
 
-// Tier 4: hubs.  Each hub has a global hash table of 2^b >= 2 d slots (64-bit
-// slots: label in the high word, summed edge weight in the low word; the sum
-// is a part of the hub's weighted degree, below 2^31, so it never carries into
-// the label).  A hub's table is split into chunks of kHubTS slots and its
-// entries into as many runs of equal length, so that a sub-round runs
-//   k_hub_plan    one workgroup: chunk offsets of the segment's rated hubs
-//   k_hub_insert  one workgroup per chunk: its run of entries into the table
-//   k_hub_scan    one workgroup per chunk: the chunk's slots rated (and freed,
-//                 so the table is empty for the next use), best keys per chunk
-//   k_hub_final   one wavefront per hub: the best over its chunks, result
-// instead of one workgroup walking the whole hub.  Every step follows the
-// same rule as the other tiers (ratings summed per label, the best admissible
-// and the favoured label by the strict key order), so the layout does not
-// change any result.
-constexpr int kHubTS = 8192;
-constexpr int kHubPart = 8;
-constexpr uint64_t kEmptySlot = 0xFFFFFFFF00000000ull;
-
-__device__ inline int hub_bits(int64_t d)
+// Tier 4: hubs (degree above the tier-3 cut-off).  A hub's entries are summed
+// per label in two passes that touch no global hash table:
+//   k_hub_plan    one workgroup: for the segment's rated hubs, the first run
+//                 (kHubRun entries of the row) and the first label partition
+//   k_hub_split   one workgroup per run: the run's labels and edge weights,
+//                 counting-sorted in LDS by label partition (P partitions per
+//                 hub, about kHubPartAvg entries each), written to the hub's
+//                 staging array with the run's partition offsets; the
+//                 partition totals are added to the hub's counters
+//   k_hub_agg     one workgroup per label partition: its entries from every
+//                 run summed per label in an LDS table (a partition of more
+//                 entries than the table could hold uses a global table of its
+//                 own, sized to never fill), rated, best keys per partition
+//   k_hub_final   one wavefront per hub: the best over its partitions, result;
+//                 the partition counters are cleared for the next use
+// A label's entries all land in one partition, so every step follows the same
+// rule as the other tiers (ratings summed per label, the best admissible and
+// the favoured label by the strict key order) and the layout changes no result.
+// A hub of degree d owns hub_region(d) 8-byte slots: d staging slots (label <<
+// 32 | weight), 4 d slots for the overflow tables, then int32 arrays: the run
+// offsets [runs][P + 1] and the partition totals [P] (zero between uses).
+// Label partition of K among P: a mixing hash of its own (the LDS table slot
+// takes the top bits of another multiplicative hash, which must not be constant
+// within a partition), scaled to [0, P).
+__device__ inline uint32_t hub_part_of(uint32_t K, int32_t P)
 {
-    int b = 1;
-    while ((1ll << b) < 2 * d) ++b;
-    return b;
+    return (uint32_t)(((uint64_t)fmix32(K ^ 0x5BD1E995u) * (uint64_t)P) >> 32);
 }
 
-__device__ inline int32_t hub_chunks_of(const RateArgs& a, int32_t v)
+__device__ inline int32_t hub_runs_of(const RateArgs& a, int32_t v)
 {
     if (!node_selected(a, v)) return 0;
-    const int64_t hs = 1ll << hub_bits(a.xadj[v + 1] - a.xadj[v]);
-    return (int32_t)((hs + kHubTS - 1) / kHubTS);
+    return (int32_t)hub_runs(a.xadj[v + 1] - a.xadj[v]);
 }
 
+// Exclusive prefixes of the rated hubs' run and partition counts.
 __global__ __launch_bounds__(kBlock) void k_hub_plan(RateArgs a)
 {
-    __shared__ int32_t s_wsum[kBlock / 64];
-    __shared__ int32_t s_carry;
+    __shared__ int32_t s_wsum[2][kBlock / 64];
+    __shared__ int32_t s_carry[2];
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    if (tid == 0) s_carry = 0;
+    if (tid < 2) s_carry[tid] = 0;
     __syncthreads();
     for (int32_t base = 0; base < count; base += kBlock) {
         const int32_t i = base + tid;
-        const int32_t x = i < count ? hub_chunks_of(a, a.list[off + i]) : 0;
-        int32_t incl = x;  // inclusive scan within the wavefront
-        for (int d = 1; d < 64; d <<= 1) {
-            const int32_t y = __shfl_up(incl, d, 64);
-            if (lane >= d) incl += y;
+        int32_t x[2] = {0, 0};
+        if (i < count) {
+            const int32_t v = a.list[off + i];
+            x[0] = hub_runs_of(a, v);
+            x[1] = x[0] ? hub_parts(a.xadj[v + 1] - a.xadj[v]) : 0;
         }
-        if (lane == 63) s_wsum[wv] = incl;
+        int32_t incl[2] = {x[0], x[1]};  // inclusive scans within the wavefront
+        for (int d = 1; d < 64; d <<= 1) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int32_t y = __shfl_up(incl[q], d, 64);
+                if (lane >= d) incl[q] += y;
+            }
+        }
+        if (lane == 63) {
+            s_wsum[0][wv] = incl[0];
+            s_wsum[1][wv] = incl[1];
+        }
         __syncthreads();
-        int32_t before = s_carry;
-        for (int q = 0; q < wv; ++q) before += s_wsum[q];
-        if (i < count) a.hub_plan[i] = before + incl - x;
+        int32_t before[2] = {s_carry[0], s_carry[1]};
+        for (int q = 0; q < wv; ++q) {
+            before[0] += s_wsum[0][q];
+            before[1] += s_wsum[1][q];
+        }
+        if (i < count) {
+            a.hub_plan[i] = before[0] + incl[0] - x[0];
+            a.hub_pplan[i] = before[1] + incl[1] - x[1];
+        }
         __syncthreads();
-        if (tid == kBlock - 1) s_carry = before + incl;
+        if (tid == kBlock - 1) {
+            s_carry[0] = before[0] + incl[0];
+            s_carry[1] = before[1] + incl[1];
+        }
         __syncthreads();
     }
-    if (tid == 0) a.hub_plan[count] = s_carry;
+    if (tid == 0) {
+        a.hub_plan[count] = s_carry[0];
+        a.hub_pplan[count] = s_carry[1];
+    }
 }
 
-// The hub whose chunks contain chunk ch: the last i with plan[i] <= ch.
+// The hub whose runs (or partitions) contain item ch: the last i with plan[i] <= ch.
 __device__ inline int32_t hub_of_chunk(const int32_t* plan, int32_t count, int32_t ch)
 {
     int32_t lo = 0, hi = count - 1;
@@ -846,74 +926,204 @@ __device__ inline int32_t hub_of_chunk(const int32_t* plan, int32_t count, int32
     return lo;
 }
 
-__global__ __launch_bounds__(kBlock) void k_hub_insert(RateArgs a)
+__global__ __launch_bounds__(kBlock) void k_hub_split(RateArgs a)
 {
+    constexpr int PER = kHubRun / kBlock;
+    __shared__ uint32_t s_cnt[kHubMaxPart];
+    __shared__ uint32_t s_cur[kHubMaxPart];
+    __shared__ uint32_t s_wsum[kBlock / 64];
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     const int32_t total = count > 0 ? a.hub_plan[count] : 0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int32_t ch = xcd_block(); ch < total; ch += gridDim.x) {
         const int32_t i = hub_of_chunk(a.hub_plan, count, ch);
         const int32_t v = a.list[off + i];
-        const int32_t nch = a.hub_plan[i + 1] - a.hub_plan[i], j = ch - a.hub_plan[i];
-        const int64_t e0 = a.xadj[v], e1 = a.xadj[v + 1], d = e1 - e0;
-        const int bits = hub_bits(d);
-        const uint64_t mask = (1ull << bits) - 1;
-        const int64_t per = (d + nch - 1) / nch;
-        const int64_t c0 = e0 + j * per, c1 = c0 + per < e1 ? c0 + per : e1;
-        unsigned long long* tab = reinterpret_cast<unsigned long long*>(a.hub_tab + a.hub_off[v]);
-        for (int64_t e = c0 + threadIdx.x; e < c1; e += kBlock) {
-            const uint32_t K = (uint32_t)a.label[a.adjncy[e]];
-            const uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
-            const unsigned long long mine = ((unsigned long long)K << 32) | w;
-            uint64_t h = slot_of(K, bits) & mask;
-            while (true) {
-                const unsigned long long old = atomicCAS(&tab[h], kEmptySlot, mine);
-                if (old == kEmptySlot) break;
-                if ((uint32_t)(old >> 32) == K) {
-                    atomicAdd(&tab[h], (unsigned long long)w);
-                    break;
-                }
-                h = (h + 1) & mask;
-            }
+        const int32_t r = ch - a.hub_plan[i];
+        const int64_t e0 = a.xadj[v], d = a.xadj[v + 1] - e0;
+        const int32_t P = hub_parts(d);
+        const int64_t c0 = e0 + (int64_t)r * kHubRun, c1 = c0 + kHubRun < e0 + d ? c0 + kHubRun : e0 + d;
+        uint64_t* reg = a.hub_tab + a.hub_off[v];
+        uint32_t* roff = reinterpret_cast<uint32_t*>(reg + 5 * d) + (int64_t)r * (P + 1);
+        uint32_t* ptot = reinterpret_cast<uint32_t*>(reg + 5 * d) + hub_runs(d) * (P + 1);
+        for (int q = tid; q < P; q += kBlock) s_cnt[q] = 0;
+        __syncthreads();
+        uint32_t K[PER], W[PER], pp[PER];
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const int64_t e = c0 + (int64_t)t * kBlock + tid;
+            const bool in = e < c1;
+            K[t] = in ? (uint32_t)a.label[a.adjncy[e]] : 0u;
+            W[t] = in ? (a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u) : 0u;
+            pp[t] = in ? hub_part_of(K[t], P) : 0xFFFFFFFFu;
         }
+#pragma unroll
+        for (int t = 0; t < PER; ++t)
+            if (pp[t] != 0xFFFFFFFFu) atomicAdd(&s_cnt[pp[t]], 1u);
+        __syncthreads();
+        // exclusive prefix of the P counts: four per thread, wavefront scans, wave totals
+        uint32_t loc[4], sum = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = 4 * tid + q;
+            loc[q] = idx < P ? s_cnt[idx] : 0u;
+            sum += loc[q];
+        }
+        uint32_t incl = sum;
+        for (int dd = 1; dd < 64; dd <<= 1) {
+            const uint32_t y = __shfl_up(incl, dd, 64);
+            if (lane >= dd) incl += y;
+        }
+        if (lane == 63) s_wsum[wv] = incl;
+        __syncthreads();
+        uint32_t run = incl - sum;
+        for (int q = 0; q < wv; ++q) run += s_wsum[q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = 4 * tid + q;
+            if (idx < P) {
+                s_cur[idx] = run;
+                roff[idx] = run;
+                if (loc[q]) atomicAdd(&ptot[idx], loc[q]);
+            }
+            run += loc[q];
+        }
+        if (tid == 0) roff[P] = (uint32_t)(c1 - c0);
+        __syncthreads();
+        // entries to the staging slots of the run, grouped by partition
+        uint64_t* st = reg + (c0 - e0);
+#pragma unroll
+        for (int t = 0; t < PER; ++t)
+            if (pp[t] != 0xFFFFFFFFu) st[atomicAdd(&s_cur[pp[t]], 1u)] = ((uint64_t)K[t] << 32) | W[t];
+        __syncthreads();  // the LDS counters are reset for the next run
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_hub_scan(RateArgs a)
+// The LDS table has a.hub_ts slots (keys, then sums), in the launch's dynamic
+// shared memory: a smaller table lets more workgroups share a compute unit.
+__global__ __launch_bounds__(kBlock) void k_hub_agg(RateArgs a)
 {
+    extern __shared__ __align__(16) uint32_t s_hub_lds[];
     __shared__ Key3 s_red[2][kBlock / 64];
     __shared__ uint32_t s_rown[kBlock / 64];
+    __shared__ int64_t s_sum[2][kBlock / 64];
+    __shared__ int32_t s_full;
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
-    const int32_t total = count > 0 ? a.hub_plan[count] : 0;
-    const int tid = threadIdx.x;
-    for (int32_t ch = xcd_block(); ch < total; ch += gridDim.x) {
-        const int32_t i = hub_of_chunk(a.hub_plan, count, ch);
+    const int32_t total = count > 0 ? a.hub_pplan[count] : 0;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    for (int32_t pc = xcd_block(); pc < total; pc += gridDim.x) {
+        const int32_t i = hub_of_chunk(a.hub_pplan, count, pc);
         const int32_t v = a.list[off + i];
-        const int32_t j = ch - a.hub_plan[i];
-        const int64_t hs = 1ll << hub_bits(a.xadj[v + 1] - a.xadj[v]);
-        const int64_t s0 = (int64_t)j * kHubTS, s1 = s0 + kHubTS < hs ? s0 + kHubTS : hs;
-        uint64_t* tab = a.hub_tab + a.hub_off[v];
+        const int32_t p = pc - a.hub_pplan[i];
+        const int64_t d = a.xadj[v + 1] - a.xadj[v];
+        const int32_t P = hub_parts(d);
+        const int64_t nr = hub_runs(d);
+        uint64_t* reg = a.hub_tab + a.hub_off[v];
+        const uint32_t* roff = reinterpret_cast<const uint32_t*>(reg + 5 * d);
+        const uint32_t* ptot = roff + nr * (P + 1);
+        // the partition's entry count and the counts of the partitions before it
+        int64_t e_own = 0, e_before = 0;
+        for (int q = tid; q < P; q += kBlock) {
+            const int64_t c = ptot[q];
+            e_own += q == p ? c : 0;
+            e_before += q < p ? c : 0;
+        }
+        for (int dd = 32; dd > 0; dd >>= 1) {
+            e_own += __shfl_xor(e_own, dd, 64);
+            e_before += __shfl_xor(e_before, dd, 64);
+        }
+        if (lane == 0) {
+            s_sum[0][wv] = e_own;
+            s_sum[1][wv] = e_before;
+        }
+        __syncthreads();
+        int64_t E = 0, before = 0;
+        for (int q = 0; q < kBlock / 64; ++q) {
+            E += s_sum[0][q];
+            before += s_sum[1][q];
+        }
         const uint32_t own = (uint32_t)a.label[v];
         const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
         const NodeKey nk = node_key(a, v);
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0;
-        for (int64_t q = s0 + tid; q < s1; q += kBlock) {
-            const uint64_t x = tab[q];
-            if (x != kEmptySlot) {
-                consider(a, nk, (uint32_t)(x >> 32), (uint32_t)x, own, cv, fav, adm, rown);
-                tab[q] = kEmptySlot;
+        // every run's entries of partition p: runs by wavefront, entries by lane
+        auto each_entry = [&](auto&& f) {
+            for (int64_t r = wv; r < nr; r += kBlock / 64) {
+                const uint32_t* ro = roff + r * (P + 1);
+                const uint64_t* st = reg + r * kHubRun;
+                const uint32_t s0 = ro[p], s1 = ro[p + 1];
+                for (uint32_t x = s0 + lane; x < s1; x += 64) f(st[x]);
+            }
+        };
+        // LDS table of at least 2 E slots, at most kts: a partition of fewer than kts entries
+        // never fills it; a larger one may (more distinct labels than slots), and then takes a
+        // global table of its own
+        const int kts = a.hub_ts;
+        uint32_t* const s_key = s_hub_lds;
+        uint32_t* const s_val = s_hub_lds + kts;
+        bool in_lds = E > 0;
+        if (in_lds) {
+            int lb = 1;
+            while ((1ll << lb) < 2 * E && (1 << lb) < kts) ++lb;
+            const int ls = 1 << lb;
+            for (int q = tid; q < ls; q += kBlock) {
+                s_key[q] = EMPTY;
+                s_val[q] = 0;
+            }
+            if (tid == 0) s_full = 0;
+            __syncthreads();
+            if (E < kts) {
+                each_entry([&](uint64_t x) { lds_insert(s_key, s_val, lb, (uint32_t)(x >> 32), (uint32_t)x); });
+            } else {
+                bool full = false;
+                each_entry([&](uint64_t x) {
+                    if (!full && !lds_try_insert(s_key, s_val, lb, (uint32_t)(x >> 32), (uint32_t)x)) full = true;
+                });
+                if (full) s_full = 1;
+            }
+            __syncthreads();
+            in_lds = s_full == 0;
+            if (in_lds)
+                for (int q = tid; q < ls; q += kBlock) consider(a, nk, s_key[q], s_val[q], own, cv, fav, adm, rown);
+        }
+        if (E > 0 && !in_lds) {
+            // overflow table of 2^b >= 2 E slots at slot d + 4 * before (2^b < 4 E and the
+            // partitions before it hold `before` entries, so the tables stay inside the 4 d slots)
+            int gb = 1;
+            while ((1ll << gb) < 2 * E) ++gb;
+            const int64_t gs = 1ll << gb;
+            const uint64_t mask = (uint64_t)gs - 1;
+            unsigned long long* tab = reinterpret_cast<unsigned long long*>(reg + d + 4 * before);
+            for (int64_t q = tid; q < gs; q += kBlock) tab[q] = kEmptySlot;
+            __syncthreads();
+            each_entry([&](uint64_t x) {
+                const uint32_t K = (uint32_t)(x >> 32), w = (uint32_t)x;
+                uint64_t h = slot_of(K, gb) & mask;
+                while (true) {
+                    const unsigned long long old = atomicCAS(&tab[h], kEmptySlot, (unsigned long long)x);
+                    if (old == kEmptySlot) break;
+                    if ((uint32_t)(old >> 32) == K) {
+                        atomicAdd(&tab[h], (unsigned long long)w);
+                        break;
+                    }
+                    h = (h + 1) & mask;
+                }
+            });
+            __syncthreads();
+            for (int64_t q = tid; q < gs; q += kBlock) {
+                const uint64_t x = tab[q];
+                if (x != kEmptySlot) consider(a, nk, (uint32_t)(x >> 32), (uint32_t)x, own, cv, fav, adm, rown);
             }
         }
         fav = group_best<64>(fav);
         adm = group_best<64>(adm);
         rown = group_sum_u32<64>(rown);
-        const int w = tid >> 6;
-        if ((tid & 63) == 0) {
-            s_red[0][w] = fav;
-            s_red[1][w] = adm;
-            s_rown[w] = rown;
+        if (lane == 0) {
+            s_red[0][wv] = fav;
+            s_red[1][wv] = adm;
+            s_rown[wv] = rown;
         }
         __syncthreads();
         if (tid == 0) {
@@ -922,16 +1132,16 @@ __global__ __launch_bounds__(kBlock) void k_hub_scan(RateArgs a)
                 if (better(s_red[1][q], adm)) adm = s_red[1][q];
                 rown += s_rown[q];
             }
-            uint32_t* p = a.hub_part + (int64_t)ch * kHubPart;
-            p[0] = fav.r;
-            p[1] = fav.h;
-            p[2] = fav.k;
-            p[3] = adm.r;
-            p[4] = adm.h;
-            p[5] = adm.k;
-            p[6] = rown;
+            uint32_t* out = a.hub_part + (int64_t)pc * kHubPart;
+            out[0] = fav.r;
+            out[1] = fav.h;
+            out[2] = fav.k;
+            out[3] = adm.r;
+            out[4] = adm.h;
+            out[5] = adm.k;
+            out[6] = rown;
         }
-        __syncthreads();
+        __syncthreads();  // the LDS tables and sums are reused by the next partition
     }
 }
 
@@ -944,9 +1154,16 @@ __global__ __launch_bounds__(kBlock) void k_hub_final(RateArgs a)
     int64_t edges = 0, nodes = 0, moves = 0;
     for (int64_t i = (int64_t)xcd_block() * kWaves + (threadIdx.x >> 6); i < count;
          i += (int64_t)gridDim.x * kWaves) {
-        const int32_t c0 = a.hub_plan[i], c1 = a.hub_plan[i + 1];
+        const int32_t c0 = a.hub_pplan[i], c1 = a.hub_pplan[i + 1];
         if (c1 == c0) continue;  // not rated in this round (uniform across the wavefront)
         const int32_t v = a.list[off + i];
+        {
+            // the partition totals start from zero at the hub's next use
+            const int64_t d = a.xadj[v + 1] - a.xadj[v];
+            const int32_t P = hub_parts(d);
+            uint32_t* ptot = reinterpret_cast<uint32_t*>(a.hub_tab + a.hub_off[v] + 5 * d) + hub_runs(d) * (P + 1);
+            for (int q = lane; q < P; q += 64) ptot[q] = 0;
+        }
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0;
         for (int32_t ch = c0 + lane; ch < c1; ch += 64) {
@@ -1960,25 +2177,30 @@ namespace {
 // the per-chunk partial results; the tables return to free after every use.
 struct HubBufs {
     DBuf<uint64_t> tab;
-    DBuf<int32_t> plan;
+    DBuf<int32_t> plan, pplan;
     DBuf<uint32_t> part;
 };
 
-void hub_buffers(Ctx& c, const LPSchedule& sched, HubBufs& h)
+void hub_buffers(Ctx& c, const DGraph& g, const LPSchedule& sched, HubBufs& h)
 {
     if (sched.hub_slots_total <= 0) return;
     const int32_t nh = sched.off[kSegs] - sched.hub_start;
     h.tab = DBuf<uint64_t>(c, (size_t)sched.hub_slots_total);
     h.plan = DBuf<int32_t>(c, (size_t)nh + 1);
-    // chunks of all hubs: at most one per kHubTS slots of their tables, plus one per hub
-    h.part = DBuf<uint32_t>(c, (size_t)(sched.hub_slots_total / kHubTS + nh) * kHubPart);
-    fill_i64(c, reinterpret_cast<int64_t*>(h.tab.p), (int64_t)kEmptySlot, sched.hub_slots_total);
+    h.pplan = DBuf<int32_t>(c, (size_t)nh + 1);
+    // label partitions of all hubs: a hub of degree d has at most d / kHubPartAvg + 1 and a
+    // region of at least 5 d slots
+    h.part = DBuf<uint32_t>(c, (size_t)(sched.hub_slots_total / (5 * kHubPartAvg) + nh) * kHubPart);
+    hipLaunchKernelGGL(k_hub_zero, dim3(grid_for(nh)), dim3(kBlock), 0, c.stream, g.xadj,
+                       sched.order.p + sched.hub_start, nh, sched.hub_slot_off.p, h.tab.p);
+    KMP_LAUNCH_CHECK();
 }
 
 void set_hub_args(RateArgs& a, const HubBufs& h)
 {
     a.hub_tab = h.tab.p;
     a.hub_plan = h.plan.p;
+    a.hub_pplan = h.pplan.p;
     a.hub_part = h.part.p;
 }
 
@@ -2000,7 +2222,7 @@ void lp_buffers(Ctx& c, const DGraph& g, const LPSchedule* sched, int32_t nlab, 
     b.prop = DBuf<int32_t>(c, (size_t)g.n);
     b.acc = DBuf<uint8_t>(c, (size_t)g.n);
     b.demand = DBuf<uint32_t>(c, (size_t)nlab);
-    if (sched) hub_buffers(c, *sched, b.hub);
+    if (sched) hub_buffers(c, g, *sched, b.hub);
     b.mflag = DBuf<uint8_t>(c, (size_t)g.n);
     b.ckeys = DBuf<uint32_t>(c, (size_t)g.n);
     b.cvals = DBuf<uint32_t>(c, (size_t)g.n);
@@ -2038,6 +2260,7 @@ RateArgs make_rate_args(Ctx& c, const DGraph& g, const LPState& st, uint32_t hpr
     a.loff = st.loff;
     a.gcap = st.gcap;
     a.tag = st.tag;
+    a.hub_ts = c.tune.hub_ts;
     const int64_t badj = 4 * g.m, blab = 4 * (int64_t)g.n, bwt = 8 * (int64_t)st.nlab;
     const int64_t lim = int64_t(1) << 31;
     if (!c.plain_loads && g.m > 0 && st.nlab > 0 && badj < lim && blab < lim && bwt < lim) {
@@ -2118,12 +2341,16 @@ void launch_rate(Ctx& c, RateArgs a, const LPSchedule& sched, int32_t s, const i
                 KMP_LAUNCH_TIMED(c, cls, (k_rate_lds<256, 13>), dim3(grid_for(ub, 1, 65536)), dim3(kBlock), 0, a);
                 break;
             default: {
-                // chunks of the segment: at most one per kHubTS slots of the level's hub tables, plus one per hub
-                const int64_t chunks = sched.hub_slots_total / kHubTS + ub;
-                const dim3 cgrid(grid_for(chunks, 1, 16384));
+                // runs and label partitions of the segment's hubs: a hub of degree d has at most
+                // d / kHubRun + 1 runs and d / kHubPartAvg + 1 partitions, and a region of 5 d slots
+                const int64_t runs = sched.hub_slots_total / (5 * kHubRun) + ub;
+                const int64_t parts = sched.hub_slots_total / (5 * kHubPartAvg) + ub;
+                // the partitions' LDS tables: the tuning's size (a power of two, 64 .. kHubTS)
+                if (a.hub_ts < 64 || a.hub_ts > kHubTS || (a.hub_ts & (a.hub_ts - 1))) a.hub_ts = kHubTS / 2;
                 KMP_LAUNCH_TIMED(c, cls, k_hub_plan, dim3(1), dim3(kBlock), 0, a);
-                KMP_LAUNCH_TIMED(c, cls, k_hub_insert, cgrid, dim3(kBlock), 0, a);
-                KMP_LAUNCH_TIMED(c, cls, k_hub_scan, cgrid, dim3(kBlock), 0, a);
+                KMP_LAUNCH_TIMED(c, cls, k_hub_split, dim3(grid_for(runs, 1, 16384)), dim3(kBlock), 0, a);
+                KMP_LAUNCH_TIMED(c, cls, k_hub_agg, dim3(grid_for(parts, 1, 16384)), dim3(kBlock),
+                                 (size_t)8 * a.hub_ts, a);
                 KMP_LAUNCH_TIMED(c, cls, k_hub_final, dim3(grid_for(ub, kBlock / 64, 65536)), dim3(kBlock), 0, a);
                 break;
             }
@@ -2236,7 +2463,7 @@ void rate_for_balance(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, int
     a.bal_t = bal_t;
     a.bal_d = bal_d;
     HubBufs hb;
-    hub_buffers(c, sched, hb);
+    hub_buffers(c, g, sched, hb);
     set_hub_args(a, hb);
     for (int32_t s = 0; s < kSub; ++s) launch_rate(c, a, sched, s, sched.order.p, sched.segtab.p, sched.cnt);
 }
@@ -2479,7 +2706,7 @@ LPStats lp_async_rounds(Ctx& c, const DGraph& g, int32_t level, uint64_t seed, c
     LPStats out;
     const int32_t n = g.n;
     HubBufs hub;
-    hub_buffers(c, sched, hub);
+    hub_buffers(c, g, sched, hub);
     DBuf<uint8_t> mflag(c, (size_t)n), active(c, 2 * (size_t)n);
     DBuf<int64_t> ctl(c, kCtlWords);
     fill_bytes_many(c, {{mflag.p, (int64_t)n, 0},

@@ -65,7 +65,7 @@ bool tuning_valid(const Tuning& t)
         if (t.cut[i] < lo || t.cut[i] > hi[i]) return false;
         lo = t.cut[i];
     }
-    return true;
+    return t.hub_ts >= 64 && t.hub_ts <= 8192 && (t.hub_ts & (t.hub_ts - 1)) == 0;
 }
 
 Tuning tuning_get()

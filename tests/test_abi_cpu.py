@@ -92,7 +92,7 @@ def test_struct_layouts_match_header(tmp_path):
                                                "fm_passes", "ip_pool", "pq_balance", "async_lp", "ip_multilevel"]),
               "kmp_stats": (kmp.KmpStats, ["lp_exact_subrounds", "level_n", "level_m", "ms_total", "prof_bytes"]),
               "kmp_server_stats": (kmp.KmpServerStats, ["hbm_in_use", "running_batches"]),
-              "kmp_tuning": (kmp.KmpTuning, ["tier3_deg", "reserved"]),
+              "kmp_tuning": (kmp.KmpTuning, ["tier3_deg", "hub_lds_slots", "reserved"]),
               "kmp_autotune_report": (kmp.KmpAutotuneReport, ["ms_start", "ms_best"])}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "kmp.h"', "int main(void) {"]
     for st, (_, fs) in fields.items():
@@ -130,16 +130,21 @@ def test_tuning_validation_without_device_work():
     lib = kmp.library()
     assert kmp.kmp_set_tuning(None) == kmp.KMP_OK
     dflt = kmp.kmp_get_tuning()
-    assert dflt == {"small_level_n": 8192, "tier0_deg": 16, "tier1_deg": 64, "tier2_deg": 512, "tier3_deg": 4096}
+    assert dflt == {"small_level_n": 8192, "tier0_deg": 16, "tier1_deg": 64, "tier2_deg": 512, "tier3_deg": 4096,
+                    "hub_lds_slots": 4096}
     bad = [dict(dflt, tier0_deg=17), dict(dflt, tier0_deg=0), dict(dflt, tier1_deg=8, tier0_deg=16),
            dict(dflt, tier2_deg=513), dict(dflt, tier3_deg=256), dict(dflt, small_level_n=-2),
-           dict(dflt, small_level_n=(1 << 30) + 1)]
+           dict(dflt, small_level_n=(1 << 30) + 1), dict(dflt, hub_lds_slots=32), dict(dflt, hub_lds_slots=16384),
+           dict(dflt, hub_lds_slots=1000)]
     for b in bad:
         assert kmp.kmp_set_tuning(b) == kmp.KMP_EINVAL, b
         assert kmp.kmp_get_tuning() == dflt
-    good = dict(small_level_n=-1, tier0_deg=8, tier1_deg=32, tier2_deg=256, tier3_deg=2048)
+    good = dict(small_level_n=-1, tier0_deg=8, tier1_deg=32, tier2_deg=256, tier3_deg=2048, hub_lds_slots=64)
     assert kmp.kmp_set_tuning(good) == kmp.KMP_OK
     assert kmp.kmp_get_tuning() == good
+    # a missing or zero hub_lds_slots is its default
+    assert kmp.kmp_set_tuning(dict(good, hub_lds_slots=0)) == kmp.KMP_OK
+    assert kmp.kmp_get_tuning() == dict(good, hub_lds_slots=4096)
     assert kmp.kmp_set_tuning(None) == kmp.KMP_OK
     assert kmp.kmp_get_tuning() == dflt
     assert lib.kmp_get_tuning(None) == kmp.KMP_EINVAL

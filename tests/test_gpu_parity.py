@@ -177,6 +177,27 @@ def test_hub_rating(kmp, gi):
         _check_contract(kmp, g, exp_label, name)
 
 
+@pytest.mark.parametrize("gi", range(2))
+def test_hub_rating_small_lds_tables(kmp, gi):
+    """Hub label partitions summed in 64-slot LDS tables: partitions of 64 or more entries try the LDS table
+    and, with more distinct labels than slots, fall back to a global table of their own; the result is the
+    oracle's either way."""
+    name, g = hub_graphs()[gi]
+    xadj, adjncy, vwgt, adjwgt = dev(g)
+    try:
+        t = kmp.kmp_get_tuning()
+        assert kmp.kmp_set_tuning(dict(t, hub_lds_slots=64)) == kmp.KMP_OK
+        for U, level, seed in ((6, 0, 9), (40, 2, 4)):
+            say(f"[lp_cluster hubs, 64-slot LDS tables] {name} U={U}")
+            exp_label, exp_cw, exp_fav, exp_moves, exp_rounds = oracle.lp_cluster(g, level, U, seed)
+            rounds, label, cw, fav, moves = kmp.kmp_lp_cluster(xadj, adjncy, vwgt, adjwgt, level, U, seed)
+            assert rounds == exp_rounds and moves == list(exp_moves)
+            assert np.array_equal(label.cpu().numpy(), exp_label)
+            assert np.array_equal(fav.cpu().numpy().view(np.uint32), exp_fav)
+    finally:
+        kmp.kmp_set_tuning(None)
+
+
 # ------------------------------------------------------------------ bipartition, balance, refine
 @pytest.mark.parametrize("k", [2, 5, 16])
 def test_bipartition_round(kmp, k):
@@ -397,7 +418,8 @@ def test_partition_under_other_tunings(kmp, name, k):
     xadj, adjncy, vwgt, adjwgt = dev(g)
     try:
         for small in (-1, 1 << 20):
-            t = dict(small_level_n=small, tier0_deg=8, tier1_deg=32, tier2_deg=256, tier3_deg=2048)
+            t = dict(small_level_n=small, tier0_deg=8, tier1_deg=32, tier2_deg=256, tier3_deg=2048,
+                     hub_lds_slots=64 if small < 0 else 8192)
             assert kmp.kmp_set_tuning(t) == kmp.KMP_OK
             say(f"[partition, tuning {t}] {name} n={g.n} k={k}")
             rc, part, stats = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, k, 0.03, 5)
