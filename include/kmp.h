@@ -97,9 +97,16 @@ typedef struct kmp_options {
                                point: the largest q whose r-fold stepwise-floored power p <- p q / 2^32
                                stays within floor(2^32 (1 + eps')^r)).  0: sides bounded by f_j L_k (the
                                default); other values: KMP_EINVAL.  The output depends on it. */
-    int32_t pq_balance;     /* reserved for the queue balancer of paper Sec. 5.3 (per overloaded block a
-                               queue of just enough nodes by relative gain, re-insertion, neighbour offers).
-                               It is switched off in this version: any value but 0 gives KMP_EINVAL. */
+    int32_t pq_balance;     /* 1: the queue balancer of paper Sec. 5.3 instead of sorted rounds: per pass,
+                               every overloaded block in ascending index fills a queue with just enough of
+                               its nodes by relative gain (d c(v) for d >= 0, d / c(v) otherwise; then id),
+                               from their pass-start targets, then takes the best node while overloaded:
+                               its target and gain are recomputed; if either changed it is offered again
+                               when it is a border node, else it moves and its neighbours still in the
+                               block are offered once per pass; passes repeat while a block is overloaded
+                               and the last pass moved.  One GPU thread per job runs a pass (the blocks of
+                               a job depend on each other).  0: sorted rounds (the default); other values:
+                               KMP_EINVAL.  The output depends on it. */
     int32_t async_lp;       /* every LP call (coarsening and refinement) in the asynchronous mode of paper
                                Sec. 5.1 "Parallelization" / Sec. 5.3 "Local Improvement" instead of the
                                deterministic sub-rounds: nodes visited by degree bucket floor(log2 d) then
@@ -462,9 +469,9 @@ int kmp_balance(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt,
                 const int64_t* cap, void* stream);
 
 /*
- * kmp_balance_ex: kmp_balance with pq selecting the queue balancer described
- * at kmp_options.pq_balance; switched off in this version, so only pq = 0 is
- * accepted (else KMP_EINVAL).  Returns the rounds run.
+ * kmp_balance_ex: kmp_balance with pq = 1 selecting the queue balancer
+ * described at kmp_options.pq_balance (pq = 0: sorted rounds; other values
+ * KMP_EINVAL).  Returns the rounds (passes) run.
  */
 int kmp_balance_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vwgt, const int32_t* adjwgt,
                    int32_t n, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,

@@ -33,6 +33,7 @@
 // independent: one workgroup per job; within a job the steps are sequential,
 // with the workgroup's lanes over a node's row and over the queue.
 #include "kmp_dev.h"
+#include "pq_pass.h"
 
 namespace kmp {
 
@@ -197,36 +198,10 @@ __global__ __launch_bounds__(kBlock) void k_bal_apply(const uint32_t* __restrict
 
 
 // ---------------------------------------------------------------- queue balancer
-constexpr int kPQThreads = 1024;
-
-struct PQEntry {
-    int64_t d;   // cut reduction of the move (may be negative)
-    int32_t c;   // node weight
-    int32_t v;   // node
-    int32_t t;   // designated target block
-    int32_t pad;
-};
-
-// > 0 if d1 / c1 ranks above d2 / c2 by relative gain (d c for d >= 0, d / c otherwise)
-__device__ inline int rel_gain_cmp(int64_t d1, int64_t c1, int64_t d2, int64_t c2)
-{
-    if (d1 >= 0 || d2 >= 0) {
-        if (d1 < 0) return -1;
-        if (d2 < 0) return 1;
-        const int64_t x = d1 * c1, y = d2 * c2;
-        return (x > y) - (x < y);
-    }
-    const int64_t x = d1 * c2, y = d2 * c1;  // both negative: compare d1 / c1 and d2 / c2
-    return (x > y) - (x < y);
-}
-
-// a ranks below b (queues are kept ascending: lowest first, best last)
-__device__ inline bool pq_below(const PQEntry& a, const PQEntry& b)
-{
-    const int r = rel_gain_cmp(a.d, a.c, b.d, b.c);
-    return r < 0 || (r == 0 && a.v > b.v);
-}
-
+// One thread per job runs the pass (pq_pass.h): the queues of a job depend on
+// each other through the block weights, block by block, so a job's pass is
+// sequential; the jobs of a batch run side by side.  The pass-start targets and
+// gains come from the parallel balance-mode rating.
 struct PQArgs {
     const int32_t* xadj;
     const int32_t* adjncy;
@@ -245,317 +220,46 @@ struct PQArgs {
     int32_t ncand;
     const int32_t* bal_t;      // pass-start targets and gains of the candidates
     const int64_t* bal_d;
-    PQEntry* q;                // queue storage, block b at qoff[b]
-    const int32_t* qoff;
+    PQItem* q;                 // queue storage, block b at qoff[b]
+    const int32_t* qoff;       // [nb + 1]
     uint8_t* inq;              // [n] queued now
     uint8_t* tried;            // [n] offered as a neighbour in this pass (zeroed before the pass)
     int64_t* conn;             // [nb] zero between uses
     int32_t* touched;          // [nb] scratch list per job (its block range)
     int64_t* moved;            // [njobs] moves of the pass
+    int32_t* full;             // set if a queue ran out of room (a broken invariant)
 };
 
-struct PQShared {
-    PQEntry best;         // broadcast entry
-    int32_t qn;           // current queue length and weight
-    int64_t qw;
-    int32_t ntouched;
-    int32_t border;
-    int32_t flag;
-    int32_t cnt;
-    int64_t rkey[kPQThreads / 64];  // per-wave reduction slots
-    uint32_t rh[kPQThreads / 64];
-    int32_t rk[kPQThreads / 64];
-    int32_t top[2];       // the two blocks of most free room (ties: smaller index)
-};
-
-// the two blocks of the job with the most free room cap - wt (ties by smaller index)
-__device__ void pq_top2(const PQArgs& a, int32_t b0, int32_t b1, PQShared& sh)
+__global__ __launch_bounds__(64) void k_pq_pass_seq(PQArgs a)
 {
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int round = 0; round < 2; ++round) {
-        const int32_t skip = round ? sh.top[0] : -1;
-        int64_t bf = INT64_MIN;
-        int32_t bt = INT32_MAX;
-        for (int32_t t = b0 + tid; t < b1; t += kPQThreads) {
-            if (t == skip) continue;
-            const int64_t f = a.cap[t] - a.wt[t];
-            if (f > bf || (f == bf && t < bt)) {
-                bf = f;
-                bt = t;
-            }
-        }
-        for (int d = 32; d > 0; d >>= 1) {
-            const int64_t of = __shfl_xor(bf, d, 64);
-            const int32_t ot = __shfl_xor(bt, d, 64);
-            if (of > bf || (of == bf && ot < bt)) {
-                bf = of;
-                bt = ot;
-            }
-        }
-        if (lane == 0) {
-            sh.rkey[wv] = bf;
-            sh.rk[wv] = bt;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            for (int q = 1; q < kPQThreads / 64; ++q)
-                if (sh.rkey[q] > bf || (sh.rkey[q] == bf && sh.rk[q] < bt)) {
-                    bf = sh.rkey[q];
-                    bt = sh.rk[q];
-                }
-            sh.top[round] = bt < b1 ? bt : -1;
-        }
-        __syncthreads();
-    }
-}
-
-// Target and gain of node v (block b) against the current weights: the
-// adjacent block t != b that can take v with the largest connection (ties by
-// H(seed; T_BAL, l, pass, local t), then index), else the block != b of most
-// free room if v fits there.  Returns false if no block can take v.  Also
-// reports whether v is a border node.
-__device__ bool pq_target(const PQArgs& a, int32_t j, int32_t b0, int32_t v, PQShared& sh, PQEntry& out,
-                          bool& border)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int32_t b = a.part[v];
-    const int64_t cv = a.vwgt ? a.vwgt[v] : 1;
-    if (tid == 0) {
-        sh.ntouched = 0;
-        sh.border = 0;
-    }
-    __syncthreads();
-    const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
-    int32_t* touched = a.touched + b0;
-    for (int32_t e = e0 + tid; e < e1; e += kPQThreads) {
-        const int32_t t = a.part[a.adjncy[e]];
-        const int64_t w = a.adjwgt ? a.adjwgt[e] : 1;
-        if (t != b) sh.border = 1;
-        if (atomicAdd((unsigned long long*)&a.conn[t], (unsigned long long)w) == 0ull)
-            touched[atomicAdd(&sh.ntouched, 1)] = t;
-    }
-    __syncthreads();
-    const int32_t nt = sh.ntouched;
-    const int64_t connb = a.conn[b];
-    int64_t br = -1;
-    uint32_t bh = 0;
-    int32_t bk = INT32_MAX;
-    for (int32_t i = tid; i < nt; i += kPQThreads) {
-        const int32_t t = touched[i];
-        if (t == b || a.wt[t] + cv > a.cap[t]) continue;
-        const int64_t r = a.conn[t];
-        const uint32_t h = hash_step(a.hpre[j], (uint32_t)(t - b0), 4);
-        if (r > br || (r == br && (h < bh || (h == bh && t < bk)))) {
-            br = r;
-            bh = h;
-            bk = t;
-        }
-    }
-    for (int d = 32; d > 0; d >>= 1) {
-        const int64_t orr = __shfl_xor(br, d, 64);
-        const uint32_t oh = __shfl_xor(bh, d, 64);
-        const int32_t ok = __shfl_xor(bk, d, 64);
-        if (orr > br || (orr == br && (oh < bh || (oh == bh && ok < bk)))) {
-            br = orr;
-            bh = oh;
-            bk = ok;
-        }
-    }
-    if (lane == 0) {
-        sh.rkey[wv] = br;
-        sh.rh[wv] = bh;
-        sh.rk[wv] = bk;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        for (int q = 1; q < kPQThreads / 64; ++q) {
-            const int64_t orr = sh.rkey[q];
-            const uint32_t oh = sh.rh[q];
-            const int32_t ok = sh.rk[q];
-            if (orr > br || (orr == br && (oh < bh || (oh == bh && ok < bk)))) {
-                br = orr;
-                bh = oh;
-                bk = ok;
-            }
-        }
-        int32_t t = br >= 0 ? bk : -1;
-        int64_t ct = br >= 0 ? br : 0;
-        if (t < 0) {
-            const int32_t tf = sh.top[0] != b ? sh.top[0] : sh.top[1];
-            if (tf >= 0 && a.wt[tf] + cv <= a.cap[tf]) {
-                t = tf;
-                ct = 0;  // not adjacent (else it would have been found above)
-            }
-        }
-        sh.flag = t >= 0;
-        sh.best.v = v;
-        sh.best.t = t;
-        sh.best.c = (int32_t)cv;
-        sh.best.d = ct - connb;
-    }
-    __syncthreads();
-    for (int32_t i = tid; i < nt; i += kPQThreads) a.conn[touched[i]] = 0;
-    out = sh.best;
-    border = sh.border != 0;
-    const bool found = sh.flag != 0;
-    __syncthreads();
-    return found;
-}
-
-// insert x into the ascending queue [q, q + qn)
-__device__ void pq_insert(PQEntry* q, PQShared& sh, const PQEntry& x, uint8_t* inq)
-{
-    const int tid = threadIdx.x;
-    const int32_t qn = sh.qn;
-    if (tid == 0) sh.cnt = 0;
-    __syncthreads();
-    int32_t below = 0;
-    for (int32_t i = tid; i < qn; i += kPQThreads) below += pq_below(q[i], x);
-    if (below) atomicAdd(&sh.cnt, below);
-    __syncthreads();
-    const int32_t pos = sh.cnt;
-    // shift [pos, qn) up by one, highest chunk first
-    for (int32_t hi = qn; hi > pos; hi -= kPQThreads) {
-        const int32_t lo = hi - kPQThreads > pos ? hi - kPQThreads : pos;
-        const int32_t i = lo + tid;
-        PQEntry e;
-        if (i < hi) e = q[i];
-        __syncthreads();
-        if (i < hi) q[i + 1] = e;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        q[pos] = x;
-        inq[x.v] = 1;
-        sh.qn = qn + 1;
-        sh.qw += x.c;
-    }
-    __syncthreads();
-}
-
-// remove the lowest entry (index 0)
-__device__ void pq_drop_lowest(PQEntry* q, PQShared& sh, uint8_t* inq)
-{
-    const int tid = threadIdx.x;
-    const int32_t qn = sh.qn;
-    const PQEntry low = q[0];
-    __syncthreads();
-    for (int32_t lo = 1; lo < qn; lo += kPQThreads) {
-        const int32_t i = lo + tid;
-        PQEntry e;
-        if (i < qn) e = q[i];
-        __syncthreads();
-        if (i < qn) q[i - 1] = e;
-        __syncthreads();
-    }
-    if (tid == 0) {
-        inq[low.v] = 0;
-        sh.qn = qn - 1;
-        sh.qw -= low.c;
-    }
-    __syncthreads();
-}
-
-__device__ void pq_offer(const PQArgs& a, int32_t b, PQEntry* q, PQShared& sh, const PQEntry& x, int64_t maxc)
-{
-    const int64_t over = a.wt[b] - a.cap[b];
-    if (sh.qw < over) {
-        pq_insert(q, sh, x, a.inq);
-        return;
-    }
-    if (sh.qn == 0 || !pq_below(q[0], x)) return;
-    pq_insert(q, sh, x, a.inq);
-    while (sh.qn > 0 && sh.qw > over + maxc) pq_drop_lowest(q, sh, a.inq);
-}
-
-__global__ __launch_bounds__(kPQThreads) void k_pq_pass(PQArgs a)
-{
-    __shared__ PQShared sh;
     const int32_t j = blockIdx.x;
-    if (!a.job_on[j]) return;
-    const int tid = threadIdx.x;
-    const int32_t b0 = a.job_b0[j], b1 = a.job_b0[j + 1];
-    const int64_t maxc = a.maxc[j];
-    pq_top2(a, b0, b1, sh);
-    int64_t moves = 0;
-    for (int32_t b = b0; b < b1; ++b) {
-        if (!a.over[b]) continue;
-        PQEntry* q = a.q + a.qoff[b];
-        if (tid == 0) {
-            sh.qn = 0;
-            sh.qw = 0;
-            // the block's candidates: [lower_bound(b), lower_bound(b + 1)) of the sorted block keys
-            int32_t lo = 0, hi = a.ncand;
-            while (lo < hi) {
-                const int32_t mid = (lo + hi) >> 1;
-                if ((int32_t)a.cand_blk[mid] < b) lo = mid + 1;
-                else hi = mid;
-            }
-            int32_t lo2 = lo, hi2 = a.ncand;
-            while (lo2 < hi2) {
-                const int32_t mid = (lo2 + hi2) >> 1;
-                if ((int32_t)a.cand_blk[mid] < b + 1) lo2 = mid + 1;
-                else hi2 = mid;
-            }
-            sh.rk[0] = lo;
-            sh.rk[1] = lo2;
-        }
-        __syncthreads();
-        const int32_t c0 = sh.rk[0], c1 = sh.rk[1];
-        __syncthreads();
-        // fill the queue from the pass-start candidates in ascending id
-        for (int32_t i = c0; i < c1; ++i) {
-            const int32_t v = (int32_t)a.cand_id[i];
-            PQEntry x;
-            x.v = v;
-            x.t = a.bal_t[v];
-            x.d = a.bal_d[v];
-            x.c = a.vwgt ? a.vwgt[v] : 1;
-            x.pad = 0;
-            pq_offer(a, b, q, sh, x, maxc);
-        }
-        // empty the block
-        while (a.wt[b] > a.cap[b] && sh.qn > 0) {
-            const PQEntry x = q[sh.qn - 1];
-            __syncthreads();
-            if (tid == 0) {
-                sh.qn -= 1;
-                sh.qw -= x.c;
-                a.inq[x.v] = 0;
-            }
-            __syncthreads();
-            PQEntry y;
-            bool border;
-            if (!pq_target(a, j, b0, x.v, sh, y, border)) continue;
-            if (y.d != x.d || a.wt[x.t] + x.c > a.cap[x.t]) {
-                if (border) pq_offer(a, b, q, sh, y, maxc);
-                continue;
-            }
-            if (tid == 0) {
-                a.wt[x.t] += x.c;
-                a.wt[b] -= x.c;
-                a.part[x.v] = x.t;
-            }
-            __syncthreads();
-            ++moves;
-            pq_top2(a, b0, b1, sh);
-            const int32_t e0 = a.xadj[x.v], e1 = a.xadj[x.v + 1];
-            for (int32_t e = e0; e < e1; ++e) {
-                const int32_t u = a.adjncy[e];
-                if (a.part[u] != b || a.tried[u] || a.inq[u]) continue;  // uniform: every lane reads the same
-                __syncthreads();
-                if (tid == 0) a.tried[u] = 1;
-                __syncthreads();
-                PQEntry z;
-                bool bu;
-                if (pq_target(a, j, b0, u, sh, z, bu)) pq_offer(a, b, q, sh, z, maxc);
-            }
-        }
-        // what is left in the queue is not queued any more
-        for (int32_t i = tid; i < sh.qn; i += kPQThreads) a.inq[q[i].v] = 0;
-        __syncthreads();
-    }
-    if (tid == 0) a.moved[j] = moves;
+    if (threadIdx.x != 0 || !a.job_on[j]) return;
+    PQJob J;
+    J.xadj = a.xadj;
+    J.adjncy = a.adjncy;
+    J.vwgt = a.vwgt;
+    J.adjwgt = a.adjwgt;
+    J.part = a.part;
+    J.wt = a.wt;
+    J.cap = a.cap;
+    J.b0 = a.job_b0[j];
+    J.b1 = a.job_b0[j + 1];
+    J.hpre = a.hpre[j];
+    J.maxc = a.maxc[j];
+    J.over = a.over;
+    J.cand_blk = a.cand_blk;
+    J.cand_id = a.cand_id;
+    J.ncand = a.ncand;
+    J.bal_t = a.bal_t;
+    J.bal_d = a.bal_d;
+    J.qs = a.q;
+    J.qoff = a.qoff;
+    J.inq = a.inq;
+    J.tried = a.tried;
+    J.conn = a.conn;
+    J.touched = a.touched + J.b0;
+    J.full = a.full;
+    a.moved[j] = pq_pass_job(J);
 }
 
 __global__ void k_block_nodes(const int32_t* __restrict__ part, int32_t n, int32_t* __restrict__ cnt)
@@ -604,9 +308,11 @@ int32_t balance_pq(Ctx& c, const DGraph& g, int32_t level, const std::vector<uin
     DBuf<int32_t> touched(c, (size_t)nb);
     DBuf<int64_t> bal_d(c, (size_t)n), conn(c, (size_t)nb), dmoved(c, (size_t)njobs);
     DBuf<uint32_t> kw0(c, (size_t)n), kw1(c, (size_t)n), kw2(c, (size_t)n), kcls(c, (size_t)n), dhpre(c, (size_t)njobs);
-    DBuf<PQEntry> q(c, (size_t)n);
+    DBuf<PQItem> q(c, (size_t)std::max(n, 1));
+    DBuf<int32_t> dfull(c, 1);
     c.write(db0.p, hb0.data(), sizeof(int32_t) * (njobs + 1));
-    fill_bytes_many(c, {{inq.p, (int64_t)n, 0}, {conn.p, 8 * (int64_t)nb, 0}, {maxc.p, 4 * (int64_t)njobs, 0}});
+    fill_bytes_many(c, {{inq.p, (int64_t)n, 0}, {conn.p, 8 * (int64_t)nb, 0}, {maxc.p, 4 * (int64_t)njobs, 0},
+                        {dfull.p, 4, 0}});
     hipLaunchKernelGGL(k_job_maxc, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, g.vwgt, jt.gid, n, maxc.p);
     KMP_LAUNCH_CHECK();
     if (batch) {
@@ -691,15 +397,17 @@ int32_t balance_pq(Ctx& c, const DGraph& g, int32_t level, const std::vector<uin
         a.conn = conn.p;
         a.touched = touched.p;
         a.moved = dmoved.p;
+        a.full = dfull.p;
         {
             ProfScope ps(c, KMP_PROF_BALANCE);
-            hipLaunchKernelGGL(k_pq_pass, dim3(njobs), dim3(kPQThreads), 0, c.stream, a);
+            hipLaunchKernelGGL(k_pq_pass_seq, dim3(njobs), dim3(64), 0, c.stream, a);
             KMP_LAUNCH_CHECK();
         }
         c.read(moved.data(), dmoved.p, sizeof(int64_t) * njobs);
         for (int32_t j = 0; j < njobs; ++j) active[j] = active[j] && moved[j] > 0;
         ++pass;
     }
+    if (pass > 0 && c.read1(dfull.p)) throw Error(KMP_EHIP, "queue balancer: a queue ran out of room");
     return pass;
 }
 

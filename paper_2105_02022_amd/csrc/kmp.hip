@@ -1135,8 +1135,7 @@ int set_ip_options(Ctx& c, const kmp_options* opt)
     if (opt && (opt->fm_passes < 0 || opt->fm_passes > kFmMaxPasses)) return KMP_EINVAL;
     if (opt && opt->ip_pool != 0 && opt->ip_pool != 1) return KMP_EINVAL;
     if (opt && opt->adaptive_eps != 0 && opt->adaptive_eps != 1) return KMP_EINVAL;
-    // the GPU queue balancer is switched off: its first GPU run faulted and the cause is not yet shown
-    if (opt && opt->pq_balance != 0) return KMP_EINVAL;
+    if (opt && opt->pq_balance != 0 && opt->pq_balance != 1) return KMP_EINVAL;
     if (opt && (opt->async_lp < 0 || opt->async_lp > 2)) return KMP_EINVAL;
     if (opt && opt->ip_multilevel != 0 && opt->ip_multilevel != 1) return KMP_EINVAL;
     c.fm_passes = opt ? opt->fm_passes : 0;
@@ -1389,8 +1388,7 @@ int kmp_balance_ex(const int32_t* xadj, const int32_t* adjncy, const int32_t* vw
                    int32_t n, int32_t level, uint64_t seed, int32_t* part, int64_t* wt, int32_t nb,
                    const int64_t* cap, int32_t pq, void* stream)
 {
-    // pq = 1 (the queue balancer) is switched off: its first GPU run faulted and the cause is not yet shown
-    if (n < 0 || nb < 1 || (n > 0 && (!xadj || !part || !wt || !cap)) || pq != 0) return KMP_EINVAL;
+    if (n < 0 || nb < 1 || (n > 0 && (!xadj || !part || !wt || !cap)) || (pq != 0 && pq != 1)) return KMP_EINVAL;
     if (n == 0) return 0;
     return (int)guarded([&]() -> int64_t {
         init_pool_once();

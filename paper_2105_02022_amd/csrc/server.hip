@@ -211,7 +211,7 @@ int kmp_server_set_options(kmp_server* s, const kmp_options* opt)
     kmp_options o = {};
     if (opt) {
         if (opt->fm_passes < 0 || opt->fm_passes > kmp::kFmMaxPasses || (opt->ip_pool != 0 && opt->ip_pool != 1) ||
-            (opt->adaptive_eps != 0 && opt->adaptive_eps != 1) || opt->pq_balance != 0 || opt->async_lp < 0 ||
+            (opt->adaptive_eps != 0 && opt->adaptive_eps != 1) || (opt->pq_balance != 0 && opt->pq_balance != 1) || opt->async_lp < 0 ||
             opt->async_lp > 2 || (opt->ip_multilevel != 0 && opt->ip_multilevel != 1))
             return KMP_EINVAL;
         o.fm_passes = opt->fm_passes;

@@ -11,10 +11,7 @@ import oracle
 from paper_2105_02022_amd import gen
 from tests.test_oracle_pins_pq import _case
 
-pytestmark = [pytest.mark.gpu,
-              pytest.mark.skip(reason="the GPU queue balancer is switched off: its first GPU run (the balancing "
-                                      "step on _case(4)) faulted the GPU and the cause has not been shown; a CPU "
-                                      "emulation of the kernel's indexing stays in bounds")]
+pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 

@@ -75,13 +75,13 @@ def test_workspace_limit_batch_and_steps(kmp, limit):
         assert np.array_equal(j["out"].cpu().numpy(), ref.part)
 
 
-def test_queue_balancer_switched_off(kmp):
-    """The GPU queue balancer is switched off: the option and the step flag are rejected before any work."""
+def test_queue_balancer_flag_range(kmp):
+    """The queue balancer flag takes 0 or 1; other values are rejected before any work."""
     g = gen.grid(10, 10)
     xadj, adjncy, vwgt, adjwgt = kmp.to_device(g, "cuda")
-    rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, 4, 0.03, 1, pq_balance=True)
+    rc, _, _ = kmp.kmp_partition_ex(xadj, adjncy, vwgt, adjwgt, 4, 0.03, 1, pq_balance=2)
     assert rc == kmp.KMP_EINVAL
     part = torch.zeros(g.n, dtype=torch.int32, device="cuda")
     wt = torch.tensor([100, 0], dtype=torch.int64, device="cuda")
     cap = torch.tensor([50, 60], dtype=torch.int64, device="cuda")
-    assert kmp.kmp_balance_ex(xadj, adjncy, vwgt, adjwgt, 0, 1, part, wt, cap, pq=True) == kmp.KMP_EINVAL
+    assert kmp.kmp_balance_ex(xadj, adjncy, vwgt, adjwgt, 0, 1, part, wt, cap, pq=2) == kmp.KMP_EINVAL
