@@ -29,6 +29,9 @@ cut, time and parity for each.
 async_lp: the same workload (and each extra workload) with the asynchronous
 LP mode of paper Sec. 5.1 / 5.3 instead of the deterministic sub-rounds:
 time per partition and the cut of every run, beside the deterministic ones.
+
+balancers: the sorted-round and the queue balancer (paper Sec. 5.3) on a
+weighted graph whose levels need balancing, with the oracle's partitions.
 """
 import argparse
 import json
@@ -80,6 +83,8 @@ def parse():
     ap.add_argument("--only-workload", type=str, default=None,
                     help="run only this extra workload (grid128 or rmat22) and print its row; for profiling")
     ap.add_argument("--no-async", action="store_true", help="skip the asynchronous-LP comparison runs")
+    ap.add_argument("--no-balancers", action="store_true",
+                    help="skip the comparison of the sorted-round and queue balancers")
     return ap.parse_args()
 
 
@@ -425,6 +430,36 @@ def extra_workload(kmp, gen, torch, name, steps, warmup, cpu, with_async=True):
     return row
 
 
+def balancer_compare(kmp, gen, torch, np, steps, with_oracle):
+    """The two balancers of paper Sec. 5.3 on a graph whose levels need balancing: a random graph of
+    100,000 nodes and average degree 8 in which 5% of the nodes weigh 200 (the rest 1), k = 64,
+    eps = 0.03, seed 1.  Time per partition without events, cut, balancing rounds of the whole partition,
+    and the oracle's partition for each."""
+    g = gen.random_graph(100000, 8.0, 21)
+    g.vwgt = np.where(np.random.default_rng(22).random(g.n) < 0.05, 200, 1).astype(np.int32)
+    dev = kmp.to_device(g, "cuda:0")
+    out = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    res = {"workload": "random graph n=100000, avg degree 8, 5% of nodes weight 200, k=64, eps=0.03, seed 1"}
+    for name, pq in (("sorted_rounds", False), ("queues", True)):
+        rc, _, st = kmp.kmp_partition_ex(*dev, 64, 0.03, 1, out=out, pq_balance=pq)
+        assert rc in (0, 1), kmp.kmp_strerror(rc)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(steps):
+            kmp.kmp_partition_ex(*dev, 64, 0.03, 1, out=out, pq_balance=pq)
+        torch.cuda.synchronize()
+        row = {"ms_per_partition_without_events": round((time.perf_counter() - t) * 1e3 / steps, 3),
+               "status": rc, "cut": st["cut"], "balance_rounds": st["balance_rounds"],
+               "max_block_weight": st["max_block_weight"]}
+        if with_oracle:
+            import oracle
+            ref = oracle.partition(g, 64, 0.03, 1, pq_balance=pq)
+            row["parity_with_oracle"] = bool(np.array_equal(ref.part, out.cpu().numpy())) and \
+                ref.stats["cut"] == st["cut"] and ref.status == rc
+        res[name] = row
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -550,6 +585,9 @@ def main():
         loads = [float(x) for x in args.serving_loads.split(",") if x]
         serving = serving_run(kmp, gen, torch, args.serving_jobs, loads, args.serving_workers,
                               args.serving_budget_gib)
+    balancers = None if args.no_balancers else balancer_compare(kmp, gen, torch, np, args.ip_steps,
+                                                                 not args.no_cpu_baseline)
+    print(f"# balancers: {balancers}", file=sys.stderr, flush=True)
     workloads = None
     if not args.no_workloads:
         workloads = {}
@@ -598,7 +636,7 @@ def main():
         "lp_plus_contraction_edges_per_step": edges, **phase_rates(st_all), "cut": st0["cut"],
         "levels": st0["levels"],
         "parity_with_oracle": parity, "tuning": tuning, "batched": batched, "serving": serving,
-        "ip_options": ip_cmp, "async_lp": async_cmp, "workloads": workloads,
+        "ip_options": ip_cmp, "async_lp": async_cmp, "balancers": balancers, "workloads": workloads,
     }
     print(json.dumps(line), flush=True)
 
