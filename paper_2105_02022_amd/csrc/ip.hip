@@ -668,7 +668,7 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
     }
 
     // ---- one growth per wavefront
-    const int32_t f = job.f, f0 = f / 2, f1 = f - f0;
+    const int32_t f = job.f, f0 = f / 2;
     const int64_t t0 = cB * f0 / f;
     const int64_t cap0 = job.cap0, cap1 = job.cap1;
     const int j = wv;

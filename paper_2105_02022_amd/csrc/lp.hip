@@ -736,7 +736,26 @@ __device__ inline void lds_insert(uint32_t* keys, uint32_t* vals, int bits, uint
     }
 }
 
-// Tiers 1-3: G lanes per node, 2^HB slots per node in LDS, 256 threads.
+// Orders the LDS accesses of a group of G lanes: a group of at most 64 lanes
+// lies in one wavefront, whose LDS operations take effect in issue order, so
+// only the compiler has to be kept from moving them across; a larger group
+// spans the workgroup.
+template <int G>
+__device__ inline void group_sync()
+{
+    if constexpr (G <= 64) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    } else {
+        __syncthreads();
+    }
+}
+
+// Tiers 1-3: G lanes per node, 2^HB slots per node in LDS, 256 threads.  Groups
+// of at most 64 lanes synchronise only within their wavefront, so the waves of
+// a workgroup rate their nodes independently.  A lane loads four of its row's
+// entries (and their labels) before inserting any, keeping four gathers in
+// flight.
 template <int G, int HB>
 __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
 {
@@ -775,19 +794,31 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             keys[j] = EMPTY;
             vals[j] = 0;
         }
-        __syncthreads();
+        group_sync<G>();
         if (v >= 0) {
-            for (int32_t e = e0 + gl; e < e1; e += G) {
-                uint32_t K = (uint32_t)a.label[a.adjncy[e]];
-                uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
-                lds_insert(keys, vals, bits, K, w);
+            // at most d distinct labels in at least 2 d slots: every insert finds its
+            // slot within one sweep of the table
+            constexpr int U = 4;
+            for (int32_t e = e0 + gl; e < e1; e += U * G) {
+                int32_t u[U];
+                uint32_t K[U], w[U];
+#pragma unroll
+                for (int q = 0; q < U; ++q) u[q] = e + q * G < e1 ? a.adjncy[e + q * G] : -1;
+#pragma unroll
+                for (int q = 0; q < U; ++q) {
+                    K[q] = u[q] >= 0 ? (uint32_t)a.label[u[q]] : EMPTY;
+                    w[q] = a.adjwgt && u[q] >= 0 ? (uint32_t)a.adjwgt[e + q * G] : 1u;
+                }
+#pragma unroll
+                for (int q = 0; q < U; ++q)
+                    if (K[q] != EMPTY) lds_try_insert(keys, vals, bits, K[q], w[q]);
             }
             if (gl == 0) {
                 edges += e1 - e0;
                 nodes += 1;
             }
         }
-        __syncthreads();
+        group_sync<G>();
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0, own = 0;
         int64_t cv = 0;
@@ -821,7 +852,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             }
         }
         if (v >= 0 && gl == 0) moves += write_result(a, v, own, fav, adm, rown, cv);
-        __syncthreads();
+        group_sync<G>();  // the table is cleared for the next node only after every read
     }
     flush_stats(a, nodes, edges, moves);
 }
