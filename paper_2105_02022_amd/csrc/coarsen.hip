@@ -204,7 +204,9 @@ struct RowArgs {
 };
 
 // G lanes per coarse row, 2^HB LDS slots per row; rows carry at most 2^(HB-1)
-// fine entries.  After aggregation the occupied slots are compacted to the
+// fine entries, and a row of f fine entries uses the first 2^b >= 2 f slots.
+// A lane loads four of its member's entries (and their coarse ids) before
+// inserting any.  After aggregation the occupied slots are compacted to the
 // front of the table (through registers) and only the next power of two above
 // their count is sorted (bitonic).
 template <int G, int HB>
@@ -224,7 +226,13 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
     for (int64_t base = (int64_t)xcd_block() * GPB; base < count; base += (int64_t)gridDim.x * GPB) {
         const int64_t i = base + grp;
         const int32_t row = i < count ? rows[i] : -1;
-        for (int j = gl; j < HS; j += G) {
+        int bits = 1;
+        if (row >= 0) {
+            const int32_t fine = a.dstart[row + 1] - a.dstart[row];
+            while ((1 << bits) < 2 * fine && bits < HB) ++bits;
+        }
+        const int hsz = row >= 0 ? 1 << bits : 0;
+        for (int j = gl; j < hsz; j += G) {
             keys[j] = EMPTY;
             vals[j] = 0;
         }
@@ -240,22 +248,31 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
             int sw = G;  // lanes per member
             while (sw > 1 && (G / sw) < nm) sw >>= 1;
             const int sub = gl / sw, sl = gl % sw, par = G / sw;
+            const uint32_t mask = (1u << bits) - 1u;
+            constexpr int U = 4;
             for (int32_t mi = m0 + sub; mi < m1; mi += par) {
                 const int32_t v = a.members[mi];
                 const int32_t e1 = a.xadj[v + 1];
-                for (int32_t e = a.xadj[v] + sl; e < e1; e += sw) {
-                    const int32_t cu = a.map[a.adjncy[e]];
-                    if (cu == row) continue;
-                    const uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
-                    const uint32_t mask = HS - 1;
-                    uint32_t h = slot_of((uint32_t)cu, HB);
-                    while (true) {
-                        uint32_t old = atomicCAS(&keys[h], EMPTY, (uint32_t)cu);
-                        if (old == EMPTY || old == (uint32_t)cu) {
-                            atomicAdd(&vals[h], w);
-                            break;
+                for (int32_t e = a.xadj[v] + sl; e < e1; e += U * sw) {
+                    int32_t u[U], cu[U];
+#pragma unroll
+                    for (int q = 0; q < U; ++q) u[q] = e + q * sw < e1 ? a.adjncy[e + q * sw] : -1;
+#pragma unroll
+                    for (int q = 0; q < U; ++q) cu[q] = u[q] >= 0 ? a.map[u[q]] : row;
+#pragma unroll
+                    for (int q = 0; q < U; ++q) {
+                        if (cu[q] == row) continue;
+                        const uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e + q * sw] : 1u;
+                        // at most f distinct ids in at least 2 f slots: one sweep finds a slot
+                        uint32_t h = slot_of((uint32_t)cu[q], bits);
+                        for (uint32_t t = 0; t <= mask; ++t) {
+                            const uint32_t old = atomicCAS(&keys[h], EMPTY, (uint32_t)cu[q]);
+                            if (old == EMPTY || old == (uint32_t)cu[q]) {
+                                atomicAdd(&vals[h], w);
+                                break;
+                            }
+                            h = (h + 1) & mask;
                         }
-                        h = (h + 1) & mask;
                     }
                 }
             }
@@ -265,8 +282,9 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
         uint32_t rk[PER], rv[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            rk[q] = keys[q * G + gl];
-            rv[q] = vals[q * G + gl];
+            const bool in = q * G + gl < hsz;
+            rk[q] = in ? keys[q * G + gl] : EMPTY;
+            rv[q] = in ? vals[q * G + gl] : 0u;
         }
         __syncthreads();
 #pragma unroll

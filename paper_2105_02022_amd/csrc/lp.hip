@@ -1039,6 +1039,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_agg(RateArgs a)
     __shared__ uint32_t s_rown[kBlock / 64];
     __shared__ int64_t s_sum[2][kBlock / 64];
     __shared__ int32_t s_full;
+    __shared__ uint32_t s_pre[kBlock + 1];  // a group of runs: exclusive prefix of their entries in the partition
+    __shared__ uint32_t s_beg[kBlock];      // and where the partition starts in each run
+    __shared__ uint32_t s_ws[kBlock / 64];
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     const int32_t total = count > 0 ? a.hub_pplan[count] : 0;
@@ -1079,13 +1082,60 @@ __global__ __launch_bounds__(kBlock) void k_hub_agg(RateArgs a)
         const NodeKey nk = node_key(a, v);
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0;
-        // every run's entries of partition p: runs by wavefront, entries by lane
+        // every run's entries of partition p, in groups of up to kBlock runs: a thread reads
+        // one run's offsets, a block scan numbers the group's entries, and thread t takes
+        // entries t, t + kBlock, ... (four loads in flight), each found by a binary search
+        // over the prefix, so no load waits for another
         auto each_entry = [&](auto&& f) {
-            for (int64_t r = wv; r < nr; r += kBlock / 64) {
-                const uint32_t* ro = roff + r * (P + 1);
-                const uint64_t* st = reg + r * kHubRun;
-                const uint32_t s0 = ro[p], s1 = ro[p + 1];
-                for (uint32_t x = s0 + lane; x < s1; x += 64) f(st[x]);
+            for (int64_t g0 = 0; g0 < nr; g0 += kBlock) {
+                const int gn = nr - g0 < kBlock ? (int)(nr - g0) : kBlock;
+                uint32_t s0 = 0, cnt = 0;
+                if (tid < gn) {
+                    const uint32_t* ro = roff + (g0 + tid) * (P + 1);
+                    s0 = ro[p];
+                    cnt = ro[p + 1] - s0;
+                }
+                uint32_t incl = cnt;
+                for (int dd = 1; dd < 64; dd <<= 1) {
+                    const uint32_t y = __shfl_up(incl, dd, 64);
+                    if (lane >= dd) incl += y;
+                }
+                if (lane == 63) s_ws[wv] = incl;
+                __syncthreads();
+                uint32_t excl = incl - cnt;
+                for (int q = 0; q < wv; ++q) excl += s_ws[q];
+                s_pre[tid] = excl;
+                s_beg[tid] = s0;
+                if (tid == kBlock - 1) s_pre[kBlock] = excl + cnt;
+                __syncthreads();
+                const uint32_t tot = s_pre[kBlock];
+                int top = 1;  // the largest power of two below gn (0: a single run)
+                while (2 * top < gn) top *= 2;
+                if (gn == 1) top = 0;
+                constexpr int U = 4;
+                for (uint32_t x0 = tid; x0 < tot; x0 += U * kBlock) {
+                    int lo[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) lo[u] = 0;
+                    // the last run whose prefix is at most x holds entry x
+                    for (int step = top; step > 0; step >>= 1) {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const int t = lo[u] + step;
+                            if (t < gn && s_pre[t] <= x0 + u * kBlock) lo[u] = t;
+                        }
+                    }
+                    uint64_t y[U];
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const uint32_t x = x0 + u * kBlock;
+                        y[u] = x < tot ? reg[(g0 + lo[u]) * kHubRun + s_beg[lo[u]] + (x - s_pre[lo[u]])] : 0;
+                    }
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+                        if (x0 + u * kBlock < tot) f(y[u]);
+                }
+                __syncthreads();  // the group's prefix is rewritten by the next group
             }
         };
         // LDS table of at least 2 E slots, at most kts: a partition of fewer than kts entries
