@@ -42,6 +42,7 @@ constexpr int T0_NARROW = 8;  // tier-0 nodes of at most this degree are listed 
 constexpr uint32_t EMPTY = 0xFFFFFFFFu;
 constexpr int kSmallCap = 4096;     // contended entries resolved on the device
 constexpr int kCandChunk = 1024;    // contended entries staged in LDS per pass
+constexpr int kWaveScanMax = 32;    // contended nodes of a wavefront scanned one by one by the whole wavefront
 
 // ctl[] layout (int64, device): round control shared by the kernels (the
 // contended-list length alternates between CTL_CONT and CTL_CONT + 1 by
@@ -1482,6 +1483,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
         }
         const bool contended = K >= 0 && a == 2;
         if (__syncthreads_or(contended)) {
+            const int lane = threadIdx.x & 63;
             int64_t pre = 0;
             for (int64_t c0 = 0; c0 < C; c0 += kCandChunk) {
                 const int len = (int)(C - c0 < kCandChunk ? C - c0 : kCandChunk);
@@ -1491,9 +1493,23 @@ __global__ __launch_bounds__(kBlock) void k_apply(int64_t* ctl, const int32_t* _
                     if (vwgt) s_w[j] = vwgt[u];
                 }
                 __syncthreads();
-                if (contended) {
-                    // entries of target K with id <= v: keys in [K << 32, (K << 32) | v]
-                    const uint64_t lo = (uint64_t)(uint32_t)K << 32, hi = lo | (uint32_t)v;
+                // entries of target K with id <= v: keys in [K << 32, (K << 32) | v].  A
+                // wavefront with few contended nodes scans the chunk once per node with all its
+                // lanes; with many, each contended lane scans the whole chunk
+                const uint64_t lo = (uint64_t)(uint32_t)K << 32, hi = lo | (uint32_t)v;
+                const uint64_t cmask = __ballot(contended);
+                if (__popcll(cmask) <= kWaveScanMax) {
+                    for (uint64_t m = cmask; m != 0; m &= m - 1) {
+                        const int t = __ffsll((long long)m) - 1;
+                        const uint64_t lt = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(lo >> 32), t) << 32);
+                        const uint64_t ht = lt | (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)hi, t);
+                        int64_t part = 0;
+                        for (int j = lane; j < len; j += 64)
+                            part += (s_kv[j] >= lt && s_kv[j] <= ht) ? (vwgt ? s_w[j] : 1) : 0;
+                        for (int dd = 32; dd > 0; dd >>= 1) part += __shfl_xor(part, dd, 64);
+                        if (lane == t) pre += part;
+                    }
+                } else if (contended) {
                     if (vwgt) {
 #pragma unroll 8
                         for (int j = 0; j < len; ++j) pre += (s_kv[j] >= lo && s_kv[j] <= hi) ? s_w[j] : 0;
