@@ -67,6 +67,119 @@ __global__ void k_local_ids(const uint32_t* __restrict__ verts, const int32_t* _
     local[v] = (int32_t)i - bstart[part[v]];
 }
 
+// Extraction over the whole device (levels whose blocks have long rows): the
+// rows of the vertices of the blocks to split, in block order (position p of
+// the block-sorted vertices), are cut into chunks of kExtChunk entries; one
+// wavefront per chunk counts the entries whose neighbour lies in the same
+// block, an exclusive scan of the chunk counts numbers the internal entries in
+// position order, and a second pass writes them as (local neighbour, weight),
+// in row order.  The greedy growing then reads each block's internal rows
+// instead of walking its full rows in one workgroup.
+constexpr int32_t kExtChunk = 1024;
+
+// chunks per position (0 for the vertices of blocks that are not split)
+__global__ void k_ext_plan(const uint32_t* __restrict__ verts, const int32_t* __restrict__ part,
+                           const int32_t* __restrict__ xadj, const uint8_t* __restrict__ split, int32_t n,
+                           int32_t* __restrict__ nch)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int32_t v = (int32_t)verts[p];
+    const int32_t d = xadj[v + 1] - xadj[v];
+    nch[p] = split[part[v]] ? (d + kExtChunk - 1) / kExtChunk : 0;
+}
+
+// the position whose chunks include chunk ch: the last p with cplan[p] <= ch
+__device__ inline int32_t ext_row_of(const int32_t* cplan, int32_t n, int32_t ch)
+{
+    int32_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (cplan[mid] <= ch) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct ExtArgs {
+    const uint32_t* verts;
+    const int32_t* part;
+    const int32_t* xadj;
+    const int32_t* adjncy;
+    const int32_t* adjwgt;
+    const int32_t* local;
+    const int32_t* cplan;  // [n + 1] first chunk of each position; cplan[n] = chunks
+    int32_t n;
+    int32_t* ccnt;  // [chunks] internal entries per chunk (count pass)
+    const int32_t* cpre;  // [chunks + 1] their exclusive prefix (write pass)
+    int32_t* iw;    // [n] weighted internal degree per position (count pass; zero before)
+    int32_t* bint;  // [blocks] internal entries per block (count pass; zero before)
+    int2* ied;      // internal entries (write pass)
+};
+
+// One wavefront per chunk: WRITE = false counts, true writes in row order.
+template <bool WRITE>
+__global__ __launch_bounds__(kBlock) void k_ext_chunks(ExtArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t total = a.cplan[a.n];
+    for (int64_t ch = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); ch < total;
+         ch += (int64_t)gridDim.x * (kBlock / 64)) {
+        const int32_t p = ext_row_of(a.cplan, a.n, (int32_t)ch);
+        const int32_t v = (int32_t)a.verts[p];
+        const int32_t b = a.part[v];
+        const int32_t r0 = a.xadj[v], r1 = a.xadj[v + 1];
+        const int32_t c0 = r0 + ((int32_t)ch - a.cplan[p]) * kExtChunk;
+        const int32_t c1 = c0 + kExtChunk < r1 ? c0 + kExtChunk : r1;
+        int32_t cnt = 0, ws = 0;
+        int32_t pos = WRITE ? a.cpre[ch] : 0;
+        constexpr int U = 4;
+        for (int32_t e0 = c0; e0 < c1; e0 += U * 64) {
+            int32_t u[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int32_t e = e0 + q * 64 + lane;
+                u[q] = e < c1 ? a.adjncy[e] : -1;
+            }
+            bool in[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) in[q] = u[q] >= 0 && a.part[u[q]] == b;
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int32_t e = e0 + q * 64 + lane;
+                const int32_t w = in[q] ? (a.adjwgt ? a.adjwgt[e] : 1) : 0;
+                if (WRITE) {
+                    const uint64_t m = __ballot(in[q]);
+                    if (in[q]) a.ied[pos + __popcll(m & ((1ull << lane) - 1))] = make_int2(a.local[u[q]], w);
+                    pos += __popcll(m);
+                } else {
+                    cnt += in[q] ? 1 : 0;
+                    ws += w;
+                }
+            }
+        }
+        if (!WRITE) {
+            for (int dd = 32; dd > 0; dd >>= 1) {
+                cnt += __shfl_xor(cnt, dd, 64);
+                ws += __shfl_xor(ws, dd, 64);
+            }
+            if (lane == 0) {
+                a.ccnt[ch] = cnt;
+                if (ws) atomicAdd(&a.iw[p], ws);
+                if (cnt) atomicAdd(&a.bint[b], cnt);
+            }
+        }
+    }
+}
+
+// internal entry offset of every position: ioff[p] = cpre[cplan[p]] (p <= n)
+__global__ void k_ext_offsets(const int32_t* __restrict__ cplan, const int32_t* __restrict__ cpre, int32_t n,
+                              int32_t* __restrict__ ioff)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p <= n) ioff[p] = cpre[cplan[p]];
+}
+
 // ---------------------------------------------------------------- GGG
 constexpr int GGG_THREADS = 64 * kSeeds;
 
@@ -105,6 +218,13 @@ struct GGGArgs {
     int32_t algs;
     uint8_t* side_alg;
     int64_t* res;  // [job][family][2]
+    // the block's internal rows from the extraction over the whole device (NULL: the
+    // workgroup extracts them itself): by position of the block-sorted vertices, the
+    // first internal entry ioff[p] (ioff[n] = all), the weighted internal degree iw[p],
+    // and the entries ied (local neighbour, weight)
+    const int32_t* ioff = nullptr;
+    const int32_t* iw = nullptr;
+    const int2* ied = nullptr;
 };
 
 // A growth keeps one 64-bit key per node, so that finding the next node is one
@@ -489,143 +609,168 @@ __global__ __launch_bounds__(GGG_THREADS) void k_ggg(GGGArgs a)
 
     int32_t* wdeg = sw_all + (a.fm_passes > 0 ? (int64_t)kSeeds * nvp : 0);  // internal weighted degrees
     constexpr int kWaves = GGG_THREADS / 64;
-    // ---- internal degrees (in nd[i + 1].x), internal weighted degrees and node weights.  A row
-    // of the level graph can hold 10^5 entries, most of them outside the block: rows of up to
-    // kGggLightRow entries are walked by one thread each (loads in groups of 8), longer ones are
-    // listed (in the key array, which the growths initialise later) and walked by a whole
-    // wavefront each, four 64-entry chunks in flight
-    int32_t* heavy = reinterpret_cast<int32_t*>(key_all);
-    if (tid == 0) s_nheavy = 0;
-    __syncthreads();
-    int64_t cacc = 0;
-    for (int32_t i = tid; i < nv; i += GGG_THREADS) {
-        const int32_t v = (int32_t)vlist[i];
-        const int32_t e1 = a.xadj[v + 1];
-        const int32_t c = a.vwgt ? a.vwgt[v] : 1;
-        nd[i].y = c;
-        cacc += c;
-        if (e1 - a.xadj[v] > kGggLightRow) {
-            heavy[atomicAdd(&s_nheavy, 1)] = i;
-            continue;
-        }
-        int32_t cnt = 0, ws = 0;
-        for (int32_t e0 = a.xadj[v]; e0 < e1; e0 += 8) {
-            int32_t u[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) u[q] = e0 + q < e1 ? a.adjncy[e0 + q] : -1;
-#pragma unroll
-            for (int q = 0; q < 8; ++q)
-                if (u[q] >= 0 && a.part[u[q]] == b) {
-                    ++cnt;
-                    ws += a.adjwgt ? a.adjwgt[e0 + q] : 1;
-                }
-        }
-        nd[i + 1].x = cnt;
-        wdeg[i] = ws;
-    }
-    __syncthreads();
-    const int32_t nheavy = s_nheavy;
-    for (int32_t h = wv; h < nheavy; h += kWaves) {
-        const int32_t i = heavy[h];
-        const int32_t v = (int32_t)vlist[i];
-        const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
-        uint32_t cnt = 0, ws = 0;
-        for (int32_t base = e0; base < e1; base += 256) {
-            int32_t u[4];
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t e = base + q * 64 + lane;
-                u[q] = e < e1 ? a.adjncy[e] : -1;
-            }
-#pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int32_t e = base + q * 64 + lane;
-                if (u[q] >= 0 && a.part[u[q]] == b) {
-                    ++cnt;
-                    ws += a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
-                }
-            }
-        }
-        cnt = group_sum_u32<64>(cnt);
-        ws = group_sum_u32<64>(ws);
-        if (lane == 0) {
-            nd[i + 1].x = (int32_t)cnt;
-            wdeg[i] = (int32_t)ws;
-        }
-    }
-    for (int d = 32; d > 0; d >>= 1) cacc += __shfl_xor(cacc, d, 64);
-    if (lane == 0) s_red[wv] = cacc;
-    if (tid == 0) {
-        nd[0].x = 0;
-        nd[nv].y = 0;
-        s_carry = 0;
-    }
-    __syncthreads();
     int64_t cB = 0;
-    for (int q = 0; q < GGG_THREADS / 64; ++q) cB += s_red[q];
-    // ---- prefix sum of internal degrees (chunks of GGG_THREADS, carry in LDS)
-    for (int32_t c0 = 0; c0 < nv; c0 += GGG_THREADS) {
-        const int32_t i = c0 + tid;
-        int32_t x = i < nv ? nd[i + 1].x : 0;
-        // inclusive scan in the wave
-        for (int d = 1; d < 64; d <<= 1) {
-            int32_t y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
+    if (a.ied) {
+        // ---- the block's internal rows from the extraction over the whole device
+        const int32_t p0 = a.bstart[b];
+        const int32_t eb = a.ioff[p0];
+        int64_t cacc = 0;
+        for (int32_t i = tid; i < nv; i += GGG_THREADS) {
+            const int32_t v = (int32_t)vlist[i];
+            const int32_t c = a.vwgt ? a.vwgt[v] : 1;
+            nd[i] = make_int2(a.ioff[p0 + i] - eb, c);
+            wdeg[i] = a.iw[p0 + i];
+            cacc += c;
+        }
+        for (int d = 32; d > 0; d >>= 1) cacc += __shfl_xor(cacc, d, 64);
+        if (lane == 0) s_red[wv] = cacc;
+        const int32_t E = a.ioff[p0 + nv] - eb;
+        if (tid == 0) nd[nv] = make_int2(E, 0);
+        if (MODE == GGG_HYBRID) {
+            ed = const_cast<int2*>(a.ied) + eb;  // read in place
+        } else {
+            for (int32_t e = tid; e < E; e += GGG_THREADS) ed[e] = a.ied[eb + e];
         }
         __syncthreads();
-        if (lane == 63) s_red[wv] = x;
+        for (int q = 0; q < GGG_THREADS / 64; ++q) cB += s_red[q];
+    } else {
+        // ---- internal degrees (in nd[i + 1].x), internal weighted degrees and node weights.  A row
+        // of the level graph can hold 10^5 entries, most of them outside the block: rows of up to
+        // kGggLightRow entries are walked by one thread each (loads in groups of 8), longer ones are
+        // listed (in the key array, which the growths initialise later) and walked by a whole
+        // wavefront each, four 64-entry chunks in flight
+        int32_t* heavy = reinterpret_cast<int32_t*>(key_all);
+        if (tid == 0) s_nheavy = 0;
         __syncthreads();
-        int32_t pre = s_carry;
-        for (int q = 0; q < wv; ++q) pre += (int32_t)s_red[q];
-        if (i < nv) nd[i + 1].x = pre + x;
-        __syncthreads();
-        if (tid == GGG_THREADS - 1) s_carry = pre + x;
-        __syncthreads();
-    }
-    // ---- local adjacency (ascending node id => ascending local id): short rows by one thread
-    // each, the listed long rows by a wavefront each (the internal entries of a chunk keep their
-    // order: ballot, then the count of lower lanes)
-    for (int32_t i = tid; i < nv; i += GGG_THREADS) {
-        const int32_t v = (int32_t)vlist[i];
-        const int32_t e1 = a.xadj[v + 1];
-        if (e1 - a.xadj[v] > kGggLightRow) continue;
-        int32_t pos = nd[i].x;
-        for (int32_t e0 = a.xadj[v]; e0 < e1; e0 += 8) {
-            int32_t u[8], p[8], lu[8], w[8];
-#pragma unroll
-            for (int q = 0; q < 8; ++q) u[q] = e0 + q < e1 ? a.adjncy[e0 + q] : -1;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                p[q] = u[q] >= 0 ? a.part[u[q]] : -1;
-                lu[q] = u[q] >= 0 ? a.local[u[q]] : 0;
-                w[q] = u[q] >= 0 ? (a.adjwgt ? a.adjwgt[e0 + q] : 1) : 0;
+        int64_t cacc = 0;
+        for (int32_t i = tid; i < nv; i += GGG_THREADS) {
+            const int32_t v = (int32_t)vlist[i];
+            const int32_t e1 = a.xadj[v + 1];
+            const int32_t c = a.vwgt ? a.vwgt[v] : 1;
+            nd[i].y = c;
+            cacc += c;
+            if (e1 - a.xadj[v] > kGggLightRow) {
+                heavy[atomicAdd(&s_nheavy, 1)] = i;
+                continue;
             }
-#pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                if (p[q] != b) continue;
-                ed[pos] = make_int2(lu[q], w[q]);
-                ++pos;
+            int32_t cnt = 0, ws = 0;
+            for (int32_t e0 = a.xadj[v]; e0 < e1; e0 += 8) {
+                int32_t u[8];
+    #pragma unroll
+                for (int q = 0; q < 8; ++q) u[q] = e0 + q < e1 ? a.adjncy[e0 + q] : -1;
+    #pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    if (u[q] >= 0 && a.part[u[q]] == b) {
+                        ++cnt;
+                        ws += a.adjwgt ? a.adjwgt[e0 + q] : 1;
+                    }
+            }
+            nd[i + 1].x = cnt;
+            wdeg[i] = ws;
+        }
+        __syncthreads();
+        const int32_t nheavy = s_nheavy;
+        for (int32_t h = wv; h < nheavy; h += kWaves) {
+            const int32_t i = heavy[h];
+            const int32_t v = (int32_t)vlist[i];
+            const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
+            uint32_t cnt = 0, ws = 0;
+            for (int32_t base = e0; base < e1; base += 256) {
+                int32_t u[4];
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t e = base + q * 64 + lane;
+                    u[q] = e < e1 ? a.adjncy[e] : -1;
+                }
+    #pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int32_t e = base + q * 64 + lane;
+                    if (u[q] >= 0 && a.part[u[q]] == b) {
+                        ++cnt;
+                        ws += a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u;
+                    }
+                }
+            }
+            cnt = group_sum_u32<64>(cnt);
+            ws = group_sum_u32<64>(ws);
+            if (lane == 0) {
+                nd[i + 1].x = (int32_t)cnt;
+                wdeg[i] = (int32_t)ws;
             }
         }
-    }
-    for (int32_t h = wv; h < nheavy; h += kWaves) {
-        const int32_t i = heavy[h];
-        const int32_t v = (int32_t)vlist[i];
-        const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
-        int32_t pos = nd[i].x;
-        for (int32_t base = e0; base < e1; base += 64) {
-            const int32_t e = base + lane;
-            const int32_t u = e < e1 ? a.adjncy[e] : -1;
-            const bool in = u >= 0 && a.part[u] == b;
-            int2 val = make_int2(0, 0);
-            if (in) val = make_int2(a.local[u], a.adjwgt ? a.adjwgt[e] : 1);
-            const uint64_t m = __ballot(in);
-            if (in) ed[pos + __popcll(m & ((1ull << lane) - 1))] = val;
-            pos += __popcll(m);
+        for (int d = 32; d > 0; d >>= 1) cacc += __shfl_xor(cacc, d, 64);
+        if (lane == 0) s_red[wv] = cacc;
+        if (tid == 0) {
+            nd[0].x = 0;
+            nd[nv].y = 0;
+            s_carry = 0;
         }
-    }
-    __syncthreads();
+        __syncthreads();
+        for (int q = 0; q < GGG_THREADS / 64; ++q) cB += s_red[q];
+        // ---- prefix sum of internal degrees (chunks of GGG_THREADS, carry in LDS)
+        for (int32_t c0 = 0; c0 < nv; c0 += GGG_THREADS) {
+            const int32_t i = c0 + tid;
+            int32_t x = i < nv ? nd[i + 1].x : 0;
+            // inclusive scan in the wave
+            for (int d = 1; d < 64; d <<= 1) {
+                int32_t y = __shfl_up(x, d, 64);
+                if (lane >= d) x += y;
+            }
+            __syncthreads();
+            if (lane == 63) s_red[wv] = x;
+            __syncthreads();
+            int32_t pre = s_carry;
+            for (int q = 0; q < wv; ++q) pre += (int32_t)s_red[q];
+            if (i < nv) nd[i + 1].x = pre + x;
+            __syncthreads();
+            if (tid == GGG_THREADS - 1) s_carry = pre + x;
+            __syncthreads();
+        }
+        // ---- local adjacency (ascending node id => ascending local id): short rows by one thread
+        // each, the listed long rows by a wavefront each (the internal entries of a chunk keep their
+        // order: ballot, then the count of lower lanes)
+        for (int32_t i = tid; i < nv; i += GGG_THREADS) {
+            const int32_t v = (int32_t)vlist[i];
+            const int32_t e1 = a.xadj[v + 1];
+            if (e1 - a.xadj[v] > kGggLightRow) continue;
+            int32_t pos = nd[i].x;
+            for (int32_t e0 = a.xadj[v]; e0 < e1; e0 += 8) {
+                int32_t u[8], p[8], lu[8], w[8];
+    #pragma unroll
+                for (int q = 0; q < 8; ++q) u[q] = e0 + q < e1 ? a.adjncy[e0 + q] : -1;
+    #pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    p[q] = u[q] >= 0 ? a.part[u[q]] : -1;
+                    lu[q] = u[q] >= 0 ? a.local[u[q]] : 0;
+                    w[q] = u[q] >= 0 ? (a.adjwgt ? a.adjwgt[e0 + q] : 1) : 0;
+                }
+    #pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    if (p[q] != b) continue;
+                    ed[pos] = make_int2(lu[q], w[q]);
+                    ++pos;
+                }
+            }
+        }
+        for (int32_t h = wv; h < nheavy; h += kWaves) {
+            const int32_t i = heavy[h];
+            const int32_t v = (int32_t)vlist[i];
+            const int32_t e0 = a.xadj[v], e1 = a.xadj[v + 1];
+            int32_t pos = nd[i].x;
+            for (int32_t base = e0; base < e1; base += 64) {
+                const int32_t e = base + lane;
+                const int32_t u = e < e1 ? a.adjncy[e] : -1;
+                const bool in = u >= 0 && a.part[u] == b;
+                int2 val = make_int2(0, 0);
+                if (in) val = make_int2(a.local[u], a.adjwgt ? a.adjwgt[e] : 1);
+                const uint64_t m = __ballot(in);
+                if (in) ed[pos + __popcll(m & ((1ull << lane) - 1))] = val;
+                pos += __popcll(m);
+            }
+        }
+        __syncthreads();
 
+    }
     // ---- the key width: 32 bits when every gain fits (largest weighted degree)
     if (tid == 0) s_wmax = 0;
     __syncthreads();
@@ -1013,8 +1158,10 @@ void launch_ggg_jobs(Ctx& c, GGGArgs a, const std::vector<GGGJob>& jobs_in)
             lds_jobs[q].push_back(jb);
             lds_max[q] = std::max(lds_max[q], bytes);
         } else if (hbytes <= kLdsBudget) {
+            // the internal entries in global memory: the device-wide extraction's, read in
+            // place, or a copy in the scratch
             jb.scratch = scratch_total;
-            jb.sstride = ((int64_t)jb.dsum * 8 + 255) & ~(int64_t)255;
+            jb.sstride = a.ied ? 0 : ((int64_t)jb.dsum * 8 + 255) & ~(int64_t)255;
             scratch_total += a.algs * jb.sstride;
             hyb_jobs.push_back(jb);
             hyb_max = std::max(hyb_max, hbytes);
@@ -1445,6 +1592,9 @@ void ml_bipartition_blocks(Ctx& c, const DGraph& g, int32_t level, const GGGArgs
             jobs.push_back(jb);
         }
         GGGArgs a = ga;
+        a.ioff = nullptr;  // subgraph rows of their own
+        a.iw = nullptr;
+        a.ied = nullptr;
         a.xadj = Li.g.xadj;
         a.adjncy = Li.g.adjncy;
         a.vwgt = Li.g.vwgt;
@@ -1482,6 +1632,9 @@ void ml_bipartition_blocks(Ctx& c, const DGraph& g, int32_t level, const GGGArgs
             jobs.push_back(jb);
         }
         GGGArgs a = ga;
+        a.ioff = nullptr;  // subgraph rows of their own
+        a.iw = nullptr;
+        a.ied = nullptr;
         a.xadj = Li.g.xadj;
         a.adjncy = Li.g.adjncy;
         a.vwgt = Li.g.vwgt;
@@ -1541,6 +1694,69 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         }
         const int32_t* hb = hbd.data();
         const int32_t* hd = hbd.data() + nb + 1;
+        // Levels where a block to split has rows too long to hold in LDS (its degree sum bounds
+        // its internal entries) take the extraction over the whole device: the greedy growing
+        // then reads the exact internal rows, and blocks whose internal entries fit LDS run
+        // there.  Other levels extract inside the growth launch.
+        bool ext = false;
+        int64_t sdeg = 0;
+        for (int32_t bb = 0; bb < nb && !c.ip_multilevel; ++bb) {
+            if (!split[bb]) continue;
+            sdeg += hd[bb];
+            if (ggg_bytes(hb[bb + 1] - hb[bb], hd[bb], c.fm_passes > 0) > kLdsBudget) ext = true;
+        }
+        std::vector<int32_t> hint;  // internal entries per block (extraction over the device)
+        DBuf<int32_t> ioff, iw;
+        DBuf<int2> ied;
+        if (ext) {
+            // timed with the growth launches (class ggg): the extraction is a step of the
+            // initial bipartitioning
+            auto scope = std::make_unique<ProfScope>(c, KMP_PROF_GGG);
+            DBuf<uint8_t> dsplit(c, (size_t)nb);
+            c.write(dsplit.p, split.data(), (size_t)nb);
+            DBuf<int32_t> nch(c, (size_t)n), cplan(c, (size_t)n + 1);
+            hipLaunchKernelGGL(k_ext_plan, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, vsorted, part, g.xadj,
+                               dsplit.p, n, nch.p);
+            KMP_LAUNCH_CHECK();
+            scan_excl_i32(c, nch.p, cplan.p, n, cplan.p + n);
+            // a row of d entries has at most d / kExtChunk + 1 chunks
+            const int64_t ubt = sdeg / kExtChunk + n;
+            DBuf<int32_t> ccnt(c, (size_t)ubt), cpre(c, (size_t)ubt + 1), bint(c, (size_t)nb);
+            iw = DBuf<int32_t>(c, (size_t)n);
+            ioff = DBuf<int32_t>(c, (size_t)n + 1);
+            fill_bytes_many(c, {{ccnt.p, 4 * ubt, 0}, {iw.p, 4 * (int64_t)n, 0}, {bint.p, 4 * (int64_t)nb, 0}});
+            ExtArgs ea;
+            ea.verts = vsorted;
+            ea.part = part;
+            ea.xadj = g.xadj;
+            ea.adjncy = g.adjncy;
+            ea.adjwgt = g.adjwgt;
+            ea.local = local.p;
+            ea.cplan = cplan.p;
+            ea.n = n;
+            ea.ccnt = ccnt.p;
+            ea.cpre = cpre.p;
+            ea.iw = iw.p;
+            ea.bint = bint.p;
+            ea.ied = nullptr;
+            const dim3 cgrid(grid_for(ubt, kBlock / 64, 65536));
+            hipLaunchKernelGGL(k_ext_chunks<false>, cgrid, dim3(kBlock), 0, c.stream, ea);
+            KMP_LAUNCH_CHECK();
+            scan_excl_i32(c, ccnt.p, cpre.p, ubt, cpre.p + ubt);
+            hipLaunchKernelGGL(k_ext_offsets, dim3(grid_for((int64_t)n + 1)), dim3(kBlock), 0, c.stream, cplan.p,
+                               cpre.p, n, ioff.p);
+            KMP_LAUNCH_CHECK();
+            scope.reset();
+            hint.resize(nb);
+            c.read(hint.data(), bint.p, sizeof(int32_t) * nb);
+            int64_t tot = 0;
+            for (int32_t bb = 0; bb < nb; ++bb) tot += hint[bb];
+            ied = DBuf<int2>(c, (size_t)std::max<int64_t>(tot, 1));
+            ea.ied = ied.p;
+            ProfScope ps(c, KMP_PROF_GGG);
+            hipLaunchKernelGGL(k_ext_chunks<true>, cgrid, dim3(kBlock), 0, c.stream, ea);
+            KMP_LAUNCH_CHECK();
+        }
         std::vector<GGGJob> gjobs;
         for (int32_t bb = 0; bb < nb; ++bb) {
             if (!split[bb]) continue;
@@ -1550,7 +1766,7 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             jb.first = bt.first[bb];
             jb.f = bt.f[bb];
             jb.nverts = hb[bb + 1] - hb[bb];
-            jb.dsum = hd[bb];
+            jb.dsum = ext ? hint[bb] : hd[bb];
             jb.hpre = hash_step(hash_step(hseed[jb_job], TAG_GGG, 1), (uint32_t)level, 2);
             jb.hpre_bfs = hash_step(hash_step(hseed[jb_job], TAG_BFS, 1), (uint32_t)level, 2);
             jb.hpre_rnd = hash_step(hash_step(hseed[jb_job], TAG_RND, 1), (uint32_t)level, 2);
@@ -1576,6 +1792,9 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
         a.fm_passes = c.fm_passes;
         a.pool = c.ip_pool ? 1 : 0;
         a.given = nullptr;
+        a.ioff = ext ? ioff.p : nullptr;
+        a.iw = ext ? iw.p : nullptr;
+        a.ied = ext ? ied.p : nullptr;
         if (c.ip_multilevel) {
             std::vector<uint64_t> jseed(gjobs.size());
             for (size_t q = 0; q < gjobs.size(); ++q) {

@@ -398,20 +398,66 @@ __device__ inline int write_result(const RateArgs& a, int32_t v, uint32_t own, c
     return 0;
 }
 
-// Evaluate one aggregated (label, rating) entry for the lane-local bests.
-__device__ inline void consider(const RateArgs& a, const NodeKey& nk, uint32_t key, uint32_t val, uint32_t own,
-                                int64_t cv, Key3& fav, Key3& adm, uint32_t& rown)
+// Rates a thread's slots of a node's label table, slot(j, K, V) giving the
+// (label, rating) of slot j (K = EMPTY for none) for j = j0, j0 + step, ... <
+// end: the own rating and the favoured label directly, the best admissible
+// label with the weights (and caps, overload flags) of B slots gathered at
+// once.  A label is weighed if it beats the admissible label found before its
+// batch and taken if it is admissible and still beats it, so the result is
+// that of weighing every label in slot order.  The gathers are unconditional
+// (a slot that needs none reads the own label's weight), so the B loads of a
+// batch are in flight together instead of one after another.
+template <int B, bool CAPV, bool BAL, class Slot>
+__device__ inline void rate_slots_t(const RateArgs& a, const NodeKey& nk, uint32_t own, int64_t cv, int64_t j0,
+                                    int64_t end, int64_t step, Slot&& slot, Key3& fav, Key3& adm, uint32_t& rown)
 {
-    if (key == EMPTY) return;
-    if (key == own) {
-        rown = val;
-        return;
+    for (; j0 < end; j0 += B * step) {
+        uint32_t K[B], V[B], Hs[B];
+        bool need[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const int64_t j = j0 + q * step;
+            K[q] = EMPTY;
+            V[q] = 0;
+            slot(j < end ? j : end - 1, K[q], V[q]);
+            if (j >= end) K[q] = EMPTY;
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const bool cand = K[q] != EMPTY && K[q] != own;
+            if (K[q] == own) rown = V[q];
+            Hs[q] = hash_step(nk.hp, K[q] - nk.lo, 4);
+            const Key3 c{V[q], Hs[q], K[q]};
+            if (cand && better(c, fav)) fav = c;
+            need[q] = cand && better(c, adm);
+        }
+        int64_t w[B], cap[B];
+        bool ov[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const uint32_t l = need[q] ? K[q] : own;
+            w[q] = a.wt[l];
+            cap[q] = CAPV ? a.cap_vec[l] : nk.cap;
+            ov[q] = BAL ? a.over[l] != 0 : false;
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            const Key3 c{V[q], Hs[q], K[q]};
+            if (need[q] && better(c, adm) && w[q] + cv <= cap[q] && !ov[q]) adm = c;
+        }
     }
-    Key3 c{val, hash_step(nk.hp, key - nk.lo, 4), key};
-    if (better(c, fav)) fav = c;
-    if (better(c, adm)) {
-        const int64_t cap = a.cap_vec ? a.cap_vec[key] : nk.cap;
-        if (a.wt[key] + cv <= cap && !(a.over && a.over[key])) adm = c;
+}
+
+template <int B, class Slot>
+__device__ inline void rate_slots(const RateArgs& a, const NodeKey& nk, uint32_t own, int64_t cv, int64_t j0,
+                                  int64_t end, int64_t step, Slot&& slot, Key3& fav, Key3& adm, uint32_t& rown)
+{
+    if (a.cap_vec) {
+        if (a.over) rate_slots_t<B, true, true>(a, nk, own, cv, j0, end, step, slot, fav, adm, rown);
+        else rate_slots_t<B, true, false>(a, nk, own, cv, j0, end, step, slot, fav, adm, rown);
+    } else {
+        if (a.over) rate_slots_t<B, false, true>(a, nk, own, cv, j0, end, step, slot, fav, adm, rown);
+        else rate_slots_t<B, false, false>(a, nk, own, cv, j0, end, step, slot, fav, adm, rown);
     }
 }
 
@@ -827,7 +873,12 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             own = (uint32_t)a.label[v];
             const NodeKey nk = node_key(a, v);
             cv = a.vwgt ? a.vwgt[v] : 1;
-            for (int j = gl; j < hsn; j += G) consider(a, nk, keys[j], vals[j], own, cv, fav, adm, rown);
+            rate_slots<4>(a, nk, own, cv, gl, hsn, G,
+                          [&](int64_t j, uint32_t& K, uint32_t& V) {
+                              K = keys[j];
+                              V = vals[j];
+                          },
+                          fav, adm, rown);
         }
         if constexpr (G <= 64) {
             fav = group_best<G>(fav);
@@ -1168,7 +1219,12 @@ __global__ __launch_bounds__(kBlock) void k_hub_agg(RateArgs a)
             __syncthreads();
             in_lds = s_full == 0;
             if (in_lds)
-                for (int q = tid; q < ls; q += kBlock) consider(a, nk, s_key[q], s_val[q], own, cv, fav, adm, rown);
+                rate_slots<4>(a, nk, own, cv, tid, ls, kBlock,
+                              [&](int64_t q, uint32_t& K, uint32_t& V) {
+                                  K = s_key[q];
+                                  V = s_val[q];
+                              },
+                              fav, adm, rown);
         }
         if (E > 0 && !in_lds) {
             // overflow table of 2^b >= 2 E slots at slot d + 4 * before (2^b < 4 E and the
@@ -1194,10 +1250,15 @@ __global__ __launch_bounds__(kBlock) void k_hub_agg(RateArgs a)
                 }
             });
             __syncthreads();
-            for (int64_t q = tid; q < gs; q += kBlock) {
-                const uint64_t x = tab[q];
-                if (x != kEmptySlot) consider(a, nk, (uint32_t)(x >> 32), (uint32_t)x, own, cv, fav, adm, rown);
-            }
+            rate_slots<4>(a, nk, own, cv, tid, gs, kBlock,
+                          [&](int64_t q, uint32_t& K, uint32_t& V) {
+                              const uint64_t x = tab[q];
+                              if (x != kEmptySlot) {
+                                  K = (uint32_t)(x >> 32);
+                                  V = (uint32_t)x;
+                              }
+                          },
+                          fav, adm, rown);
         }
         fav = group_best<64>(fav);
         adm = group_best<64>(adm);
