@@ -68,38 +68,17 @@ __global__ void k_local_ids(const uint32_t* __restrict__ verts, const int32_t* _
 }
 
 // Extraction over the whole device (levels whose blocks have long rows): the
-// rows of the vertices of the blocks to split, in block order (position p of
-// the block-sorted vertices), are cut into chunks of kExtChunk entries; one
-// wavefront per chunk counts the entries whose neighbour lies in the same
-// block, an exclusive scan of the chunk counts numbers the internal entries in
-// position order, and a second pass writes them as (local neighbour, weight),
-// in row order.  The greedy growing then reads each block's internal rows
-// instead of walking its full rows in one workgroup.
+// internal entries (neighbour in the same block) of the vertices of the blocks
+// to split, in block order (position p of the block-sorted vertices), are
+// counted, numbered by an exclusive scan over the positions, and written as
+// (local neighbour, weight) in row order.  A row of at most kExtLight entries
+// is walked by one thread; a longer one is cut into chunks of kExtChunk
+// entries, one wavefront each, whose counts are scanned as well so that each
+// chunk knows where its entries start within the row.  The greedy growing then
+// reads each block's internal rows instead of walking its full rows in one
+// workgroup.
 constexpr int32_t kExtChunk = 1024;
-
-// chunks per position (0 for the vertices of blocks that are not split)
-__global__ void k_ext_plan(const uint32_t* __restrict__ verts, const int32_t* __restrict__ part,
-                           const int32_t* __restrict__ xadj, const uint8_t* __restrict__ split, int32_t n,
-                           int32_t* __restrict__ nch)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t v = (int32_t)verts[p];
-    const int32_t d = xadj[v + 1] - xadj[v];
-    nch[p] = split[part[v]] ? (d + kExtChunk - 1) / kExtChunk : 0;
-}
-
-// the position whose chunks include chunk ch: the last p with cplan[p] <= ch
-__device__ inline int32_t ext_row_of(const int32_t* cplan, int32_t n, int32_t ch)
-{
-    int32_t lo = 0, hi = n - 1;
-    while (lo < hi) {
-        const int32_t mid = (lo + hi + 1) >> 1;
-        if (cplan[mid] <= ch) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
+constexpr int32_t kExtLight = 64;
 
 struct ExtArgs {
     const uint32_t* verts;
@@ -108,16 +87,77 @@ struct ExtArgs {
     const int32_t* adjncy;
     const int32_t* adjwgt;
     const int32_t* local;
-    const int32_t* cplan;  // [n + 1] first chunk of each position; cplan[n] = chunks
+    const uint8_t* split;  // [blocks] the block is split at this level
     int32_t n;
-    int32_t* ccnt;  // [chunks] internal entries per chunk (count pass)
-    const int32_t* cpre;  // [chunks + 1] their exclusive prefix (write pass)
-    int32_t* iw;    // [n] weighted internal degree per position (count pass; zero before)
-    int32_t* bint;  // [blocks] internal entries per block (count pass; zero before)
-    int2* ied;      // internal entries (write pass)
+    int32_t* nch;          // [n] chunks of a long row (0 for short rows and other blocks)
+    const int32_t* cplan;  // [n + 1] first chunk of each position; cplan[n] = chunks
+    const int32_t* crow;   // [chunks] position of each chunk
+    int32_t* pc;           // [n] internal entries per position (count pass; zero before)
+    int32_t* ccnt;         // [chunks] internal entries per chunk (count pass)
+    const int32_t* ioff;   // [n + 1] exclusive prefix of pc (write pass)
+    const int32_t* cpre;   // [chunks + 1] exclusive prefix of ccnt (write pass)
+    int32_t* iw;           // [n] weighted internal degree per position (count pass; zero before)
+    int32_t* bint;         // [blocks] internal entries per block (count pass; zero before)
+    int2* ied;             // internal entries (write pass)
 };
 
-// One wavefront per chunk: WRITE = false counts, true writes in row order.
+// chunks per position of a long row in a block to split
+__global__ void k_ext_plan(ExtArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int32_t v = (int32_t)a.verts[p];
+    const int32_t d = a.xadj[v + 1] - a.xadj[v];
+    a.nch[p] = a.split[a.part[v]] && d > kExtLight ? (d + kExtChunk - 1) / kExtChunk : 0;
+}
+
+// the position of every chunk: crow[c] = p for the chunks c of position p
+__global__ void k_ext_rows(const int32_t* __restrict__ cplan, int32_t n, int32_t* __restrict__ crow)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    for (int32_t c = cplan[p]; c < cplan[p + 1]; ++c) crow[c] = (int32_t)p;
+}
+
+// Short rows, one thread each (eight entries in flight): WRITE = false counts,
+// true writes at ioff[p] in row order.
+template <bool WRITE>
+__global__ void k_ext_light(ExtArgs a)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const int32_t v = (int32_t)a.verts[p];
+    const int32_t b = a.part[v];
+    const int32_t r0 = a.xadj[v], r1 = a.xadj[v + 1];
+    if (!a.split[b] || r1 - r0 > kExtLight || r1 == r0) return;
+    int32_t cnt = 0, ws = 0;
+    int32_t pos = WRITE ? a.ioff[p] : 0;
+    for (int32_t e0 = r0; e0 < r1; e0 += 8) {
+        int32_t u[8], pu[8], wq[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) u[q] = a.adjncy[e0 + q < r1 ? e0 + q : r1 - 1];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            pu[q] = a.part[u[q]];
+            wq[q] = a.adjwgt ? a.adjwgt[e0 + q < r1 ? e0 + q : r1 - 1] : 1;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (e0 + q >= r1 || pu[q] != b) continue;
+            if (WRITE) a.ied[pos++] = make_int2(a.local[u[q]], wq[q]);
+            ++cnt;
+            ws += wq[q];
+        }
+    }
+    if (!WRITE) {
+        a.pc[p] = cnt;
+        a.iw[p] = ws;
+        if (cnt) atomicAdd(&a.bint[b], cnt);
+    }
+}
+
+// Long rows, one wavefront per chunk: WRITE = false counts, true writes in row
+// order from ioff[p] + (entries of the row's earlier chunks).
 template <bool WRITE>
 __global__ __launch_bounds__(kBlock) void k_ext_chunks(ExtArgs a)
 {
@@ -125,37 +165,40 @@ __global__ __launch_bounds__(kBlock) void k_ext_chunks(ExtArgs a)
     const int32_t total = a.cplan[a.n];
     for (int64_t ch = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6); ch < total;
          ch += (int64_t)gridDim.x * (kBlock / 64)) {
-        const int32_t p = ext_row_of(a.cplan, a.n, (int32_t)ch);
+        const int32_t p = a.crow[ch];
         const int32_t v = (int32_t)a.verts[p];
         const int32_t b = a.part[v];
         const int32_t r0 = a.xadj[v], r1 = a.xadj[v + 1];
         const int32_t c0 = r0 + ((int32_t)ch - a.cplan[p]) * kExtChunk;
         const int32_t c1 = c0 + kExtChunk < r1 ? c0 + kExtChunk : r1;
         int32_t cnt = 0, ws = 0;
-        int32_t pos = WRITE ? a.cpre[ch] : 0;
-        constexpr int U = 4;
-        for (int32_t e0 = c0; e0 < c1; e0 += U * 64) {
-            int32_t u[U];
+        int32_t pos = WRITE ? a.ioff[p] + a.cpre[ch] - a.cpre[a.cplan[p]] : 0;
+        constexpr int U = kExtChunk / 64;  // the whole chunk in flight
+        // every load unconditional (indices clamped into the chunk), so all are in flight
+        int32_t u[U];
 #pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int32_t e = e0 + q * 64 + lane;
-                u[q] = e < c1 ? a.adjncy[e] : -1;
-            }
-            bool in[U];
+        for (int q = 0; q < U; ++q) {
+            const int32_t e = c0 + q * 64 + lane;
+            u[q] = a.adjncy[e < c1 ? e : c1 - 1];
+        }
+        int32_t pu[U], wq[U];
 #pragma unroll
-            for (int q = 0; q < U; ++q) in[q] = u[q] >= 0 && a.part[u[q]] == b;
+        for (int q = 0; q < U; ++q) {
+            const int32_t e = c0 + q * 64 + lane;
+            pu[q] = a.part[u[q]];
+            wq[q] = a.adjwgt ? a.adjwgt[e < c1 ? e : c1 - 1] : 1;
+        }
 #pragma unroll
-            for (int q = 0; q < U; ++q) {
-                const int32_t e = e0 + q * 64 + lane;
-                const int32_t w = in[q] ? (a.adjwgt ? a.adjwgt[e] : 1) : 0;
-                if (WRITE) {
-                    const uint64_t m = __ballot(in[q]);
-                    if (in[q]) a.ied[pos + __popcll(m & ((1ull << lane) - 1))] = make_int2(a.local[u[q]], w);
-                    pos += __popcll(m);
-                } else {
-                    cnt += in[q] ? 1 : 0;
-                    ws += w;
-                }
+        for (int q = 0; q < U; ++q) {
+            const bool in = c0 + q * 64 + lane < c1 && pu[q] == b;
+            const int32_t w = in ? wq[q] : 0;
+            if (WRITE) {
+                const uint64_t m = __ballot(in);
+                if (in) a.ied[pos + __popcll(m & ((1ull << lane) - 1))] = make_int2(a.local[u[q]], w);
+                pos += __popcll(m);
+            } else {
+                cnt += in ? 1 : 0;
+                ws += w;
             }
         }
         if (!WRITE) {
@@ -165,19 +208,14 @@ __global__ __launch_bounds__(kBlock) void k_ext_chunks(ExtArgs a)
             }
             if (lane == 0) {
                 a.ccnt[ch] = cnt;
+                if (cnt) {
+                    atomicAdd(&a.pc[p], cnt);
+                    atomicAdd(&a.bint[b], cnt);
+                }
                 if (ws) atomicAdd(&a.iw[p], ws);
-                if (cnt) atomicAdd(&a.bint[b], cnt);
             }
         }
     }
-}
-
-// internal entry offset of every position: ioff[p] = cpre[cplan[p]] (p <= n)
-__global__ void k_ext_offsets(const int32_t* __restrict__ cplan, const int32_t* __restrict__ cpre, int32_t n,
-                              int32_t* __restrict__ ioff)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p <= n) ioff[p] = cpre[cplan[p]];
 }
 
 // ---------------------------------------------------------------- GGG
@@ -1714,17 +1752,16 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             auto scope = std::make_unique<ProfScope>(c, KMP_PROF_GGG);
             DBuf<uint8_t> dsplit(c, (size_t)nb);
             c.write(dsplit.p, split.data(), (size_t)nb);
-            DBuf<int32_t> nch(c, (size_t)n), cplan(c, (size_t)n + 1);
-            hipLaunchKernelGGL(k_ext_plan, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, vsorted, part, g.xadj,
-                               dsplit.p, n, nch.p);
-            KMP_LAUNCH_CHECK();
-            scan_excl_i32(c, nch.p, cplan.p, n, cplan.p + n);
-            // a row of d entries has at most d / kExtChunk + 1 chunks
-            const int64_t ubt = sdeg / kExtChunk + n;
+            // a long row of d > kExtLight entries has at most d / kExtChunk + 1 chunks
+            const int64_t ubt = sdeg / kExtChunk + sdeg / (kExtLight + 1) + 1;
+            DBuf<int32_t> nch(c, (size_t)n), cplan(c, (size_t)n + 1), crow(c, (size_t)ubt), pc(c, (size_t)n);
             DBuf<int32_t> ccnt(c, (size_t)ubt), cpre(c, (size_t)ubt + 1), bint(c, (size_t)nb);
             iw = DBuf<int32_t>(c, (size_t)n);
             ioff = DBuf<int32_t>(c, (size_t)n + 1);
-            fill_bytes_many(c, {{ccnt.p, 4 * ubt, 0}, {iw.p, 4 * (int64_t)n, 0}, {bint.p, 4 * (int64_t)nb, 0}});
+            fill_bytes_many(c, {{ccnt.p, 4 * ubt, 0},
+                                {pc.p, 4 * (int64_t)n, 0},
+                                {iw.p, 4 * (int64_t)n, 0},
+                                {bint.p, 4 * (int64_t)nb, 0}});
             ExtArgs ea;
             ea.verts = vsorted;
             ea.part = part;
@@ -1732,20 +1769,30 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             ea.adjncy = g.adjncy;
             ea.adjwgt = g.adjwgt;
             ea.local = local.p;
-            ea.cplan = cplan.p;
+            ea.split = dsplit.p;
             ea.n = n;
+            ea.nch = nch.p;
+            ea.cplan = cplan.p;
+            ea.crow = crow.p;
+            ea.pc = pc.p;
             ea.ccnt = ccnt.p;
+            ea.ioff = ioff.p;
             ea.cpre = cpre.p;
             ea.iw = iw.p;
             ea.bint = bint.p;
             ea.ied = nullptr;
+            hipLaunchKernelGGL(k_ext_plan, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, ea);
+            KMP_LAUNCH_CHECK();
+            scan_excl_i32(c, nch.p, cplan.p, n, cplan.p + n);
+            hipLaunchKernelGGL(k_ext_rows, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, cplan.p, n, crow.p);
+            KMP_LAUNCH_CHECK();
             const dim3 cgrid(grid_for(ubt, kBlock / 64, 65536));
+            hipLaunchKernelGGL(k_ext_light<false>, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, ea);
+            KMP_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_ext_chunks<false>, cgrid, dim3(kBlock), 0, c.stream, ea);
             KMP_LAUNCH_CHECK();
+            scan_excl_i32(c, pc.p, ioff.p, n, ioff.p + n);
             scan_excl_i32(c, ccnt.p, cpre.p, ubt, cpre.p + ubt);
-            hipLaunchKernelGGL(k_ext_offsets, dim3(grid_for((int64_t)n + 1)), dim3(kBlock), 0, c.stream, cplan.p,
-                               cpre.p, n, ioff.p);
-            KMP_LAUNCH_CHECK();
             scope.reset();
             hint.resize(nb);
             c.read(hint.data(), bint.p, sizeof(int32_t) * nb);
@@ -1754,6 +1801,8 @@ int32_t bipartition_round(Ctx& c, const DGraph& g, int32_t level, int32_t* part,
             ied = DBuf<int2>(c, (size_t)std::max<int64_t>(tot, 1));
             ea.ied = ied.p;
             ProfScope ps(c, KMP_PROF_GGG);
+            hipLaunchKernelGGL(k_ext_light<true>, dim3(grid_for(n)), dim3(kBlock), 0, c.stream, ea);
+            KMP_LAUNCH_CHECK();
             hipLaunchKernelGGL(k_ext_chunks<true>, cgrid, dim3(kBlock), 0, c.stream, ea);
             KMP_LAUNCH_CHECK();
         }

@@ -1667,7 +1667,15 @@ __global__ __launch_bounds__(kBlock) void k_push_active(const int64_t* __restric
         const int32_t v = list[off + i];
         if (mflag[v] != stamp) continue;
         const int32_t e1 = xadj[v + 1];
-        for (int32_t e = xadj[v] + gl; e < e1; e += W) active[adjncy[e]] = mark;
+        // eight neighbour ids per lane in flight (indices clamped into the row: a repeated last
+        // neighbour is marked twice)
+        for (int32_t e0 = xadj[v] + gl; e0 < e1; e0 += 8 * W) {
+            int32_t u[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) u[q] = adjncy[e0 + q * W < e1 ? e0 + q * W : e1 - 1];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) active[u[q]] = mark;
+        }
     }
 }
 
