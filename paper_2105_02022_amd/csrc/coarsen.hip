@@ -440,15 +440,47 @@ __global__ void k_copy_rows(const int32_t* __restrict__ cxadj, const int32_t* __
                             const int32_t* __restrict__ tmp_adj, const int32_t* __restrict__ tmp_w,
                             int32_t* __restrict__ cadj, int32_t* __restrict__ cw)
 {
-    // 16 lanes per row
+    // 16 lanes per row; rows of more than R_T2 fine entries are left to k_copy_heavy
     const int gl = threadIdx.x & 15;
     int64_t r = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 4;
     const int64_t stride = ((int64_t)gridDim.x * blockDim.x) >> 4;
     for (; r < nc; r += stride) {
-        const int32_t o = cxadj[r], len = cxadj[r + 1] - o, s = dstart[r];
+        const int32_t s = dstart[r];
+        if (dstart[r + 1] - s > R_T2) continue;
+        const int32_t o = cxadj[r], len = cxadj[r + 1] - o;
         for (int32_t j = gl; j < len; j += 16) {
             cadj[o + j] = tmp_adj[s + j];
             cw[o + j] = tmp_w[s + j];
+        }
+    }
+}
+
+// The rows of more than R_T2 fine entries (the heavy path's; up to 10^5 coarse
+// entries on power-law graphs), one workgroup each, eight entries per thread in
+// flight (indices clamped into the row: the last entry is copied again).
+__global__ __launch_bounds__(kBlock) void k_copy_heavy(const int32_t* __restrict__ hrows,
+                                                       const int32_t* __restrict__ cxadj,
+                                                       const int32_t* __restrict__ dstart,
+                                                       const int32_t* __restrict__ tmp_adj,
+                                                       const int32_t* __restrict__ tmp_w, int32_t* __restrict__ cadj,
+                                                       int32_t* __restrict__ cw)
+{
+    const int32_t r = hrows[blockIdx.x];
+    const int32_t o = cxadj[r], len = cxadj[r + 1] - o, s = dstart[r];
+    if (len <= 0) return;
+    for (int32_t j0 = threadIdx.x; j0 < len; j0 += 8 * kBlock) {
+        int32_t x[8], w[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int32_t j = j0 + q * kBlock < len ? j0 + q * kBlock : len - 1;
+            x[q] = tmp_adj[s + j];
+            w[q] = tmp_w[s + j];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int32_t j = j0 + q * kBlock < len ? j0 + q * kBlock : len - 1;
+            cadj[o + j] = x[q];
+            cw[o + j] = w[q];
         }
     }
 }
@@ -633,6 +665,7 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
         KMP_LAUNCH_TIMED(c, KMP_PROF_CONTRACT_ROWS, (k_contract_rows<256, 13>), dim3(grid_for(tc[2], 1, 65536)),
                          dim3(kBlock), 0, a, rows + off, tc[2]);
     off += tc[2];
+    const int32_t* heavy_rows = rows + off;  // the rows of more than R_T2 fine entries (tc[3] of them)
     if (tc[3] > 0) {
         const int32_t nh = tc[3];
         const int32_t* hrows = rows + off;
@@ -691,6 +724,11 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
         hipLaunchKernelGGL(k_copy_rows, dim3(grid_for((int64_t)nc * 16, kBlock, 16384)), dim3(kBlock), 0, c.stream,
                            out.xadj.p, dstart.p, nc, tmp_adj.p, tmp_w.p, out.adjncy.p, out.adjwgt.p);
         KMP_LAUNCH_CHECK();
+        if (tc[3] > 0) {
+            hipLaunchKernelGGL(k_copy_heavy, dim3((unsigned)tc[3]), dim3(kBlock), 0, c.stream, heavy_rows, out.xadj.p,
+                               dstart.p, tmp_adj.p, tmp_w.p, out.adjncy.p, out.adjwgt.p);
+            KMP_LAUNCH_CHECK();
+        }
     }
 }
 
