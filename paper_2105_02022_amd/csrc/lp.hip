@@ -1031,13 +1031,29 @@ __global__ __launch_bounds__(kBlock) void k_hub_split(RateArgs a)
         uint32_t* ptot = reinterpret_cast<uint32_t*>(reg + 5 * d) + hub_runs(d) * (P + 1);
         for (int q = tid; q < P; q += kBlock) s_cnt[q] = 0;
         __syncthreads();
+        // every load unconditional (indices clamped into the run), so all are in flight
         uint32_t K[PER], W[PER], pp[PER];
+        int32_t u[PER];
 #pragma unroll
         for (int t = 0; t < PER; ++t) {
             const int64_t e = c0 + (int64_t)t * kBlock + tid;
-            const bool in = e < c1;
-            K[t] = in ? (uint32_t)a.label[a.adjncy[e]] : 0u;
-            W[t] = in ? (a.adjwgt ? (uint32_t)a.adjwgt[e] : 1u) : 0u;
+            u[t] = a.adjncy[e < c1 ? e : c1 - 1];
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) K[t] = (uint32_t)a.label[u[t]];
+        if (a.adjwgt) {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int64_t e = c0 + (int64_t)t * kBlock + tid;
+                W[t] = (uint32_t)a.adjwgt[e < c1 ? e : c1 - 1];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) W[t] = 1u;
+        }
+#pragma unroll
+        for (int t = 0; t < PER; ++t) {
+            const bool in = c0 + (int64_t)t * kBlock + tid < c1;
             pp[t] = in ? hub_part_of(K[t], P) : 0xFFFFFFFFu;
         }
 #pragma unroll
