@@ -254,15 +254,20 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
                 const int32_t v = a.members[mi];
                 const int32_t e1 = a.xadj[v + 1];
                 for (int32_t e = a.xadj[v] + sl; e < e1; e += U * sw) {
+                    // every load unconditional (indices clamped into the row), so all are in flight
                     int32_t u[U], cu[U];
+                    uint32_t wq[U];
 #pragma unroll
-                    for (int q = 0; q < U; ++q) u[q] = e + q * sw < e1 ? a.adjncy[e + q * sw] : -1;
-#pragma unroll
-                    for (int q = 0; q < U; ++q) cu[q] = u[q] >= 0 ? a.map[u[q]] : row;
+                    for (int q = 0; q < U; ++q) u[q] = a.adjncy[e + q * sw < e1 ? e + q * sw : e1 - 1];
 #pragma unroll
                     for (int q = 0; q < U; ++q) {
-                        if (cu[q] == row) continue;
-                        const uint32_t w = a.adjwgt ? (uint32_t)a.adjwgt[e + q * sw] : 1u;
+                        cu[q] = a.map[u[q]];
+                        wq[q] = a.adjwgt ? (uint32_t)a.adjwgt[e + q * sw < e1 ? e + q * sw : e1 - 1] : 1u;
+                    }
+#pragma unroll
+                    for (int q = 0; q < U; ++q) {
+                        if (e + q * sw >= e1 || cu[q] == row) continue;
+                        const uint32_t w = wq[q];
                         // at most f distinct ids in at least 2 f slots: one sweep finds a slot
                         uint32_t h = slot_of((uint32_t)cu[q], bits);
                         for (uint32_t t = 0; t <= mask; ++t) {

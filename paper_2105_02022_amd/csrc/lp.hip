@@ -845,20 +845,26 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
         if (v >= 0) {
             // at most d distinct labels in at least 2 d slots: every insert finds its
             // slot within one sweep of the table
-            constexpr int U = 4;
+            // a lane's whole share of the row (the tier's largest degree / G entries) in one
+            // batch, every load unconditional (indices clamped into the row)
+            constexpr int U = (1 << (HB - 1)) / G;
             for (int32_t e = e0 + gl; e < e1; e += U * G) {
                 int32_t u[U];
                 uint32_t K[U], w[U];
 #pragma unroll
-                for (int q = 0; q < U; ++q) u[q] = e + q * G < e1 ? a.adjncy[e + q * G] : -1;
+                for (int q = 0; q < U; ++q) u[q] = a.adjncy[e + q * G < e1 ? e + q * G : e1 - 1];
 #pragma unroll
-                for (int q = 0; q < U; ++q) {
-                    K[q] = u[q] >= 0 ? (uint32_t)a.label[u[q]] : EMPTY;
-                    w[q] = a.adjwgt && u[q] >= 0 ? (uint32_t)a.adjwgt[e + q * G] : 1u;
+                for (int q = 0; q < U; ++q) K[q] = (uint32_t)a.label[u[q]];
+                if (a.adjwgt) {
+#pragma unroll
+                    for (int q = 0; q < U; ++q) w[q] = (uint32_t)a.adjwgt[e + q * G < e1 ? e + q * G : e1 - 1];
+                } else {
+#pragma unroll
+                    for (int q = 0; q < U; ++q) w[q] = 1u;
                 }
 #pragma unroll
                 for (int q = 0; q < U; ++q)
-                    if (K[q] != EMPTY) lds_try_insert(keys, vals, bits, K[q], w[q]);
+                    if (e + q * G < e1) lds_try_insert(keys, vals, bits, K[q], w[q]);
             }
             if (gl == 0) {
                 edges += e1 - e0;
