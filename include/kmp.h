@@ -340,8 +340,10 @@ int kmp_server_set_options(kmp_server* server, const kmp_options* opt);
  * rating tiers follow the degree ranges of the rating kernels: degree <=
  * tier0_deg one lane per node; <= tier1_deg 16 lanes with a 128-slot LDS
  * table; <= tier2_deg a wavefront with a 1024-slot table; <= tier3_deg a
- * workgroup with an 8192-slot table; above, a workgroup with a global table
- * (each table has at least twice as many slots as the largest degree it may
+ * workgroup with an 8192-slot table; above, the
+ * hub tier: the row in runs of 4096 entries, split by label partition, each
+ * partition summed in an LDS table of hub_lds_slots slots (each LDS table of
+ * tiers 1-3 has at least twice as many slots as the largest degree it may
  * hold, which bounds the ranges).
  * ------------------------------------------------------------------------ */
 typedef struct kmp_tuning {
