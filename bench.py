@@ -67,7 +67,7 @@ def parse():
     ap.add_argument("--serving-loads", type=str, default="0.25,0.5,0.7,0.9",
                     help="offered loads as fractions of the measured capacity, comma separated")
     ap.add_argument("--serving-workers", type=int, default=4)
-    ap.add_argument("--serving-budget-gib", type=float, default=64.0)
+    ap.add_argument("--serving-budget-gib", type=float, default=224.0)
     ap.add_argument("--fm-passes", type=int, default=0,
                     help="2-way FM passes after every greedy growth in the timed steps (0: none, the default)")
     ap.add_argument("--ip-pool", action="store_true",

@@ -812,6 +812,11 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
     __shared__ uint32_t s_vals[GPB * HS];
     __shared__ Key3 s_red[2][4];
     __shared__ uint32_t s_rown[4];
+    // a workgroup per node: the occupied slots of its table are listed before they are
+    // weighed (at most 2^(HB-1) labels), so the weighing visits labels, not slots
+    constexpr bool kList = G == kBlock;
+    __shared__ uint16_t s_occ[kList ? HS / 2 : 1];
+    __shared__ int32_t s_nocc;
     if (aborted(a)) return;
     const int32_t off = a.segtab[a.seg], count = a.segtab[kSegs + a.seg];
     const int tid = threadIdx.x;
@@ -841,6 +846,7 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             keys[j] = EMPTY;
             vals[j] = 0;
         }
+        if (kList && tid == 0) s_nocc = 0;
         group_sync<G>();
         if (v >= 0) {
             // at most d distinct labels in at least 2 d slots: every insert finds its
@@ -872,6 +878,13 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             }
         }
         group_sync<G>();
+        int32_t nocc = 0;
+        if constexpr (kList) {
+            for (int j = gl; j < hsn; j += G)
+                if (keys[j] != EMPTY) s_occ[atomicAdd(&s_nocc, 1)] = (uint16_t)j;
+            __syncthreads();
+            nocc = s_nocc;
+        }
         Key3 fav{0, 0, 0}, adm{0, 0, 0};
         uint32_t rown = 0, own = 0;
         int64_t cv = 0;
@@ -879,12 +892,21 @@ __global__ __launch_bounds__(kBlock) void k_rate_lds(RateArgs a)
             own = (uint32_t)a.label[v];
             const NodeKey nk = node_key(a, v);
             cv = a.vwgt ? a.vwgt[v] : 1;
-            rate_slots<4>(a, nk, own, cv, gl, hsn, G,
-                          [&](int64_t j, uint32_t& K, uint32_t& V) {
-                              K = keys[j];
-                              V = vals[j];
-                          },
-                          fav, adm, rown);
+            if constexpr (kList)
+                rate_slots<4>(a, nk, own, cv, gl, nocc, G,
+                              [&](int64_t q, uint32_t& K, uint32_t& V) {
+                                  const int j = s_occ[q];
+                                  K = keys[j];
+                                  V = vals[j];
+                              },
+                              fav, adm, rown);
+            else
+                rate_slots<4>(a, nk, own, cv, gl, hsn, G,
+                              [&](int64_t j, uint32_t& K, uint32_t& V) {
+                                  K = keys[j];
+                                  V = vals[j];
+                              },
+                              fav, adm, rown);
         }
         if constexpr (G <= 64) {
             fav = group_best<G>(fav);
