@@ -5,14 +5,17 @@
 // its estimated device footprint fits the free part of the HBM budget (or
 // nothing else runs), and adds later waiting jobs of the same size class
 // (n + m within a factor of four of the first job's) and the same
-// initial-bipartitioning options whose footprints still fit (at most
-// kMaxBatchJobs); the others keep their place in the queue.  The batch is
+// initial-bipartitioning options whose footprints still fit, at most the
+// waiting jobs per worker, between kMinBatchJobs and kMaxBatchJobs (a long
+// queue forms large batches for throughput, a short one small batches that
+// finish soon); the others keep their place in the queue.  The batch is
 // partitioned in one level-by-level union pass (as kmp_partition_batch).
 // Jobs that arrive while other batches run are admitted by the next free
 // worker, so their work overlaps on the device with the batches already
 // running, and small jobs are not held behind a large one of the same
 // batch.  Every job's result is the one kmp_partition gives for it alone
 // with the options that were current when it was submitted.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <list>
@@ -37,6 +40,7 @@ struct kmp_server {
     int device = 0;
     size_t budget = 0, in_use = 0;
     std::vector<std::thread> workers;
+    int nworkers = 1;  // set before the workers start
     std::vector<hipStream_t> streams;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -53,6 +57,7 @@ namespace kmp {
 namespace {
 
 constexpr int kMaxBatchJobs = 256;
+constexpr int kMinBatchJobs = 64;
 
 // Device bytes a job may hold at its peak: the union copy of its CSR, LP and
 // contraction work arrays, and the coarse levels (which can stay close to the
@@ -104,7 +109,9 @@ void worker_main(kmp_server* s, int w)
             opt = head.opt;
             // batch entries and nodes stay below 2^30 each (the union's indices are int32)
             int64_t sum_n = 0, sum_m = 0;
-            for (auto it = s->queue.begin(); it != s->queue.end() && (int)ids.size() < kMaxBatchJobs;) {
+            const int share = (int)(s->queue.size() / (size_t)s->nworkers);
+            const int limit = std::min(kMaxBatchJobs, std::max(kMinBatchJobs, share));
+            for (auto it = s->queue.begin(); it != s->queue.end() && (int)ids.size() < limit;) {
                 kmp_server::Job& jb = s->jobs[*it];
                 const bool first = ids.empty();
                 bool take = first;
@@ -188,6 +195,7 @@ kmp_server* kmp_server_create(size_t hbm_budget_bytes, int32_t workers)
     if (!s) return nullptr;
     bool ok = hipGetDevice(&s->device) == hipSuccess;
     s->budget = hbm_budget_bytes;
+    s->nworkers = workers;
     for (int w = 0; ok && w < workers; ++w) {
         hipStream_t st = nullptr;
         ok = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess;
