@@ -353,8 +353,9 @@ __global__ __launch_bounds__(kBlock) void k_contract_rows(RowArgs a, const int32
 __global__ __launch_bounds__(kBlock) void k_heavy_expand(RowArgs a, const int32_t* __restrict__ rows, int32_t nrows,
                                                          const int32_t* __restrict__ eoff, uint32_t nc,
                                                          uint32_t* __restrict__ nbr, uint32_t* __restrict__ rowq,
-                                                         int32_t* __restrict__ w)
+                                                         int32_t* __restrict__ w, int nbbits)
 {
+    // nbbits >= 0: one packed key (row << nbbits | neighbour) per entry in nbr, rowq unused
     for (int32_t q = blockIdx.x; q < nrows; q += gridDim.x) {
         const int32_t row = rows[q];
         int32_t pos = eoff[q];
@@ -364,8 +365,13 @@ __global__ __launch_bounds__(kBlock) void k_heavy_expand(RowArgs a, const int32_
             for (int32_t e = e0 + threadIdx.x; e < e1; e += kBlock) {
                 const int32_t cu = a.map[a.adjncy[e]];
                 const int32_t p = pos + (e - e0);
-                nbr[p] = cu == row ? nc : (uint32_t)cu;  // intra entries sort last in the row
-                rowq[p] = (uint32_t)q;
+                const uint32_t nb = cu == row ? nc : (uint32_t)cu;  // intra entries sort last in the row
+                if (nbbits >= 0) {
+                    nbr[p] = ((uint32_t)q << nbbits) | nb;
+                } else {
+                    nbr[p] = nb;
+                    rowq[p] = (uint32_t)q;
+                }
                 w[p] = a.adjwgt ? a.adjwgt[e] : 1;
             }
             pos += e1 - e0;
@@ -385,6 +391,17 @@ __global__ void k_gather_u32(const uint32_t* __restrict__ src, const uint32_t* _
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = src[idx[i]];
+}
+
+__global__ void k_heavy_unpack(const uint32_t* __restrict__ key, int64_t n, int nbbits, uint32_t* __restrict__ rq,
+                               uint32_t* __restrict__ nb)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const uint32_t k = key[i];
+        rq[i] = nbbits < 32 ? k >> nbbits : 0u;
+        nb[i] = k & (uint32_t)((1ull << nbbits) - 1);
+    }
 }
 
 __global__ void k_heavy_heads(const uint32_t* __restrict__ rq, const uint32_t* __restrict__ nb,
@@ -679,27 +696,41 @@ void contract(Ctx& c, const DGraph& g, const int32_t* label, const int64_t* cw, 
         KMP_LAUNCH_CHECK();
         scan_excl_i32(c, eoff.p, eoff.p, nh, eoff.p + nh);
         const int64_t ne = c.read1(eoff.p + nh);
-        DBuf<uint32_t> nb(c, ne), rq(c, ne), perm(c, ne), t1(c, ne), t2(c, ne);
+        // (row, neighbour) fits one 32-bit key on most levels: one stable sort of
+        // the packed key orders entries by (row, neighbour, entry id), as the two
+        // stable sorts below do
+        const int nbbits = bits_for((uint64_t)nc), rqbits = bits_for((uint64_t)(nh - 1));
+        const bool packed = nbbits + rqbits <= 32;
+        DBuf<uint32_t> nb(c, ne), rq(c, packed ? 1 : ne), perm(c, ne), t1(c, ne), t2(c, ne);
         DBuf<int32_t> w(c, ne);
         hipLaunchKernelGGL(k_heavy_expand, dim3(grid_for(nh, 1, 4096)), dim3(kBlock), 0, c.stream, a, hrows, nh,
-                           eoff.p, (uint32_t)nc, nb.p, rq.p, w.p);
+                           eoff.p, (uint32_t)nc, nb.p, rq.p, w.p, packed ? nbbits : -1);
         KMP_LAUNCH_CHECK();
-        // sort entry ids by neighbour, then stably by row
+        DBuf<uint32_t> rqs(c, ne), nbs(c, ne), perm2;
         iota_i32(c, reinterpret_cast<int32_t*>(perm.p), ne);
-        radix_sort_pairs(c, nb.p, perm.p, t1.p, t2.p, ne, bits_for((uint64_t)nc));
-        DBuf<uint32_t> rqs(c, ne);
-        hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, rq.p, perm.p, ne, rqs.p);
-        KMP_LAUNCH_CHECK();
-        // carry the neighbour along: sort (row, position) and gather both
-        DBuf<uint32_t> pos(c, ne);
-        iota_i32(c, reinterpret_cast<int32_t*>(pos.p), ne);
-        radix_sort_pairs(c, rqs.p, pos.p, t1.p, t2.p, ne, bits_for((uint64_t)(nh - 1)));
-        // final order: entry = perm[pos[i]]
-        DBuf<uint32_t> perm2(c, ne), nbs(c, ne);
-        hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, perm.p, pos.p, ne, perm2.p);
-        KMP_LAUNCH_CHECK();
-        hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, nb.p, pos.p, ne, nbs.p);
-        KMP_LAUNCH_CHECK();
+        if (packed) {
+            radix_sort_pairs(c, nb.p, perm.p, t1.p, t2.p, ne, nbbits + rqbits);
+            hipLaunchKernelGGL(k_heavy_unpack, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, nb.p, ne, nbbits, rqs.p,
+                               nbs.p);
+            KMP_LAUNCH_CHECK();
+            perm2 = std::move(perm);
+        } else {
+            // sort entry ids by neighbour, then stably by row
+            radix_sort_pairs(c, nb.p, perm.p, t1.p, t2.p, ne, nbbits);
+            hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, rq.p, perm.p, ne, rqs.p);
+            KMP_LAUNCH_CHECK();
+            // carry the neighbour along: sort (row, position) and gather both
+            DBuf<uint32_t> pos(c, ne);
+            iota_i32(c, reinterpret_cast<int32_t*>(pos.p), ne);
+            radix_sort_pairs(c, rqs.p, pos.p, t1.p, t2.p, ne, rqbits);
+            // final order: entry = perm[pos[i]]
+            perm2 = DBuf<uint32_t>(c, ne);
+            hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, perm.p, pos.p, ne,
+                               perm2.p);
+            KMP_LAUNCH_CHECK();
+            hipLaunchKernelGGL(k_gather_u32, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, nb.p, pos.p, ne, nbs.p);
+            KMP_LAUNCH_CHECK();
+        }
         DBuf<int32_t> head(c, (size_t)ne + 1), hexcl(c, (size_t)ne + 1), runstart(c, (size_t)ne + 1);
         DBuf<int64_t> ws(c, ne), wpre(c, ne);
         hipLaunchKernelGGL(k_heavy_heads, dim3(grid_for(ne)), dim3(kBlock), 0, c.stream, rqs.p, nbs.p, perm2.p, w.p,
