@@ -718,14 +718,24 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t* __restric
     s_off[tid] = (uint32_t)offs[(int64_t)tid * nblk + blockIdx.x];
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
     const uint64_t lanes_below = (1ull << lane) - 1ull;
+    // the tile's pairs loaded up front, indices clamped to the last pair so
+    // that every load is issued together (invalid ones are never written)
+    uint32_t kt[RS_IT], vt[RS_IT];
+#pragma unroll
+    for (int j = 0; j < RS_IT; ++j) {
+        const int64_t idx = base + (int64_t)j * kBlock + tid;
+        const int64_t ci = idx < n ? idx : n - 1;
+        kt[j] = kin[ci];
+        vt[j] = vin[ci];
+    }
+#pragma unroll
     for (int j = 0; j < RS_IT; ++j) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) s_cnt[i][tid] = 0;
         __syncthreads();
         const int64_t idx = base + (int64_t)j * kBlock + tid;
         const bool valid = idx < n;
-        uint32_t k = valid ? kin[idx] : 0u;
-        uint32_t v = valid ? vin[idx] : 0u;
+        const uint32_t k = kt[j], v = vt[j];
         uint32_t d = (k >> shift) & 255u;
         uint64_t peers = ballot64(valid);
 #pragma unroll
