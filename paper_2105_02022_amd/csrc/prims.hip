@@ -697,11 +697,16 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t* __restrict__
     cnt[threadIdx.x] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+    // every load issued together (indices clamped to the last key), then counted
+    uint32_t kt[RS_IT];
 #pragma unroll
     for (int j = 0; j < RS_IT; ++j) {
-        int64_t idx = base + (int64_t)j * kBlock + threadIdx.x;
-        if (idx < n) atomicAdd(&cnt[(keys[idx] >> shift) & 255u], 1u);
+        const int64_t idx = base + (int64_t)j * kBlock + threadIdx.x;
+        kt[j] = keys[idx < n ? idx : n - 1];
     }
+#pragma unroll
+    for (int j = 0; j < RS_IT; ++j)
+        if (base + (int64_t)j * kBlock + threadIdx.x < n) atomicAdd(&cnt[(kt[j] >> shift) & 255u], 1u);
     __syncthreads();
     hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = (int32_t)cnt[threadIdx.x];
 }
